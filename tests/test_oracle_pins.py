@@ -323,3 +323,33 @@ def test_preprocess_box_contains_footprint(oracle_mod):
         x0, x1, y0, y1 = pre["aabb"][:, i]
         assert xs.min() >= x0 - 1e-9 and xs.max() <= x1 + 1e-9
         assert ys.min() >= y0 - 1e-9 and ys.max() <= y1 + 1e-9
+
+
+def test_finite_differences_clamped_opacity(oracle_mod):
+    """Near-opaque surfels (o G > 0.99 around their centres): the clamp has zero derivative."""
+    for seed in range(300, 500):
+        s = synth.tiny_scene(seed, n=3)
+        s.params[11, :] = np.float32(1.0)
+        o = oracle_mod.render(s.params, s.camera, s.pose)
+        if o["gmargin"].min() > 1e-3 and o["alpha"].max() >= 0.99:
+            break
+    else:
+        raise RuntimeError("no clean clamped scene")
+    H, W = s.camera.height, s.camera.width
+    g = np.random.default_rng(seed)
+    w = {"rgb": g.normal(size=(3, H, W)), "depth": g.normal(size=(H, W)),
+         "normal": g.normal(size=(3, H, W)), "alpha": g.normal(size=(H, W))}
+    an = oracle_mod.backward(s.params, s.camera, s.pose, d_rgb=w["rgb"], d_depth=w["depth"],
+                             d_normal=w["normal"], d_alpha=w["alpha"])
+    p0 = s.params.astype(np.float64)
+    fd = np.zeros((4, s.n))
+    for j, r in enumerate((0, 2, 9, 11)):
+        for i in range(s.n):
+            h = 1e-6 * max(1.0, abs(p0[r, i]))
+            pp, pm = p0.copy(), p0.copy()
+            pp[r, i] += h
+            pm[r, i] -= h
+            fd[j, i] = (_linear_loss(oracle_mod.render(pp, s.camera, s.pose), w)
+                        - _linear_loss(oracle_mod.render(pm, s.camera, s.pose), w)) / (2 * h)
+    got = an["d_params"][[0, 2, 9, 11]]
+    np.testing.assert_allclose(got, fd, rtol=1e-6, atol=1e-7 * np.abs(fd).max())
