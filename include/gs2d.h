@@ -1,0 +1,190 @@
+/*
+ * gs2d: differentiable 2D Gaussian surfel rasterizer for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libgs2d.so.  The rasterizer renders colour, depth, normal and opacity
+ * images from 2D Gaussian surfels seen by a pinhole camera, and returns gradients
+ * to every surfel parameter and to the camera pose as an se(3) 6-vector.  The
+ * method is the one of "Globally Consistent RGB-D SLAM with 2D Gaussian
+ * Splatting" (Zhong et al., 2025): Sec. "2D Gaussian Splatting" (eq:Puv, eq:hc,
+ * eq:homo, eq:wth, eq:alpha_blending) for the forward pass, Sec. "Camera Pose
+ * Optimization" (eq:derivatives) for the pose gradient, and Sec. "Tracking and
+ * Keyframe Selection" (eq:LD, eq:normal_mask, eq:opacity_mask, eq:tracking_loss)
+ * for the tracking loss.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Surfels   float32 structure-of-arrays [15][n], row-major, rows:
+ *           mu.xyz (0-2), t_u.xyz (3-5), t_v.xyz (6-8), s_u (9), s_v (10),
+ *           opacity (11), r g b (12-14).  Scales and opacity are used as given
+ *           (post-activation); colour is a plain RGB triple (no spherical
+ *           harmonics).  The surfel normal is t_u x t_v (not re-normalised).
+ * Pose      float32 [12], row-major 3x4 [R | t] mapping world points into the
+ *           camera frame (x right, y down, z forward).  Pose gradients are with
+ *           respect to a left perturbation Exp(tau) T, tau = (rho, phi):
+ *           translation first, rotation vector second.
+ * Camera    pinhole (fx, fy, cx, cy); pixel (x, y) is sampled at the integer
+ *           image coordinates x, y.
+ * Images    float32 planar, row-major: rgb [3][H][W], depth [H][W],
+ *           normal [3][H][W], alpha [H][W].  Depth is the blended camera z of
+ *           each ray-splat intersection (not divided by alpha); background is 0.
+ * Rules     a (pixel, surfel) pair is composited when min(u^2+v^2, 2|p-c|^2)
+ *           <= 9 (c: projected centre, the second term a low-pass filter that
+ *           the options can turn off), its depth is >= z_near and
+ *           alpha = min(0.99, o G) >= 1/255; compositing stops before the
+ *           surfel that would drop transmittance below 1e-4; surfels are
+ *           ordered by float32 camera depth of their centre, ties by index.
+ *
+ * Memory: every array argument is a device pointer owned by the caller unless
+ * marked "host".  Inputs are only read.  The library allocates only context
+ * workspace, never while the stream is being captured into a graph.  Calls on
+ * one context must be serialised by the caller (one context per stream).
+ *
+ * Errors: every int-returning call returns GS2D_OK (0) or a negative code; see
+ * gs2d_error_string.  After GS2D_ERR_HIP the underlying hipError_t is kept in
+ * the context (gs2d_last_hip_error).
+ */
+#ifndef GS2D_H
+#define GS2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS2D_API __attribute__((visibility("default")))
+
+#define GS2D_OK 0
+#define GS2D_ERR_INVALID_ARG (-1)
+#define GS2D_ERR_OOM (-2)
+#define GS2D_ERR_HIP (-3)
+#define GS2D_ERR_CAPACITY (-4)   /* tile-pair capacity exceeded on the device */
+#define GS2D_ERR_STATE (-5)      /* backward called without a matching forward */
+#define GS2D_ERR_UNSUPPORTED (-6)
+
+/* Flags for gs2d_render_backward. */
+#define GS2D_ACCUMULATE 1        /* add into d_params / d_pose instead of overwriting */
+
+typedef struct gs2d_ctx gs2d_ctx;
+
+typedef struct gs2d_camera {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+} gs2d_camera;
+
+typedef struct gs2d_options {
+  int32_t tile_w, tile_h;    /* screen tile: 8x8, 16x8, 16x16 (default) or 32x16 */
+  int32_t batch;             /* surfels staged per LDS batch: 32, 64, 128 or 256 (default) */
+  int32_t filter;            /* 1 (default): low-pass filter branch; 0: plain 3-sigma footprint */
+  float z_near;              /* default 0.2: centre cull and per-pixel depth cut */
+  int64_t pair_capacity;     /* tile-pair capacity; 0 (default): grow on demand */
+  int32_t keep_unsorted;     /* 1: keep a copy of the pairs before the tile sort (tests) */
+} gs2d_options;
+
+/* Counters of the last forward pass (gs2d_get_counts synchronises the stream). */
+typedef struct gs2d_counts {
+  int64_t n_surfels;         /* surfels given to the last render */
+  int64_t n_visible;         /* surfels that touch at least one tile */
+  int64_t n_pairs;           /* (tile, surfel) pairs after duplication */
+  int64_t pair_capacity;     /* current pair capacity */
+  int32_t overflow;          /* 1: the last render exceeded the capacity (outputs invalid) */
+  int32_t n_tiles;
+} gs2d_counts;
+
+/* Arguments of gs2d_track: n_iters tracking iterations, each a forward render at the
+ * current pose, the tracking loss against (tgt_rgb, tgt_depth), a pose-only backward
+ * and one AdamW step on tau followed by T <- Exp(tau) T (tau reset to 0, moments kept). */
+typedef struct gs2d_track_args {
+  const float* params;       /* [15][n] */
+  int64_t n;
+  gs2d_camera camera;
+  float* pose;               /* [12] in: start pose, out: final pose */
+  const float* tgt_rgb;      /* [3][H][W] */
+  const float* tgt_depth;    /* [H][W] */
+  float lambda_d;            /* depth weight of the tracking loss */
+  int32_t use_masks;         /* 1: normal and opacity masks of the tracking loss */
+  int32_t n_iters;
+  float lr[6];               /* per-component learning rates (rho then phi) */
+  float beta1, beta2, eps, weight_decay;
+  int32_t use_graph;         /* 1: capture one iteration into a HIP graph and replay it */
+  float* pose_history;       /* [n_iters][12] pose after each step, or NULL */
+  float* loss_history;       /* [n_iters] loss before each step, or NULL */
+} gs2d_track_args;
+
+/* Fill *opt with the defaults listed above. */
+GS2D_API int gs2d_default_options(gs2d_options* opt);
+
+/* Create a context on HIP device `device` (opt may be NULL for defaults).  The
+ * context owns all workspace.  Returns INVALID_ARG for an unsupported tile or batch. */
+GS2D_API int gs2d_create(gs2d_ctx** ctx, int device, const gs2d_options* opt);
+
+/* Free the context and its workspace (never caller memory).  NULL is accepted. */
+GS2D_API int gs2d_destroy(gs2d_ctx* ctx);
+
+/* Forward render (Sec. "2D Gaussian Splatting": eq:homo for the ray-splat
+ * intersection, eq:alpha_blending for compositing).  params [15][n], pose [12]
+ * (device); camera by value from the host.  Overwrites rgb [3][H][W],
+ * depth [H][W], normal [3][H][W], alpha [H][W]; any of them may be NULL.
+ * Saves the forward state in the context and returns its generation number in
+ * *generation (host, may be NULL).  n == 0 renders a blank image. */
+GS2D_API int gs2d_render(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera,
+                         const float* pose, float* rgb, float* depth, float* normal, float* alpha,
+                         uint32_t* generation, hipStream_t stream);
+
+/* Reverse mode of the render with generation `generation` (else GS2D_ERR_STATE)
+ * for the given image gradients (any may be NULL, meaning zero).
+ * d_params [15][n] receives dL/d(surfel parameters) in the world frame; NULL
+ * selects the pose-only mode, in which no per-surfel gradient is formed.
+ * d_pose [6] receives dL/dtau for a left perturbation of the pose, the paper's
+ * eq:derivatives (dL/dmu_c [I, -mu_c^x] plus dL/dR_c against [0, -R_c[:,k]^x]).
+ * flags: GS2D_ACCUMULATE adds to d_params and d_pose instead of overwriting. */
+GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float* d_depth,
+                                  const float* d_normal, const float* d_alpha, float* d_params,
+                                  float* d_pose, uint32_t generation, int32_t flags,
+                                  hipStream_t stream);
+
+/* Tracking loss of Sec. "Tracking and Keyframe Selection" (eq:tracking_loss):
+ * L = (1/HW) sum_p M_n M_o (|rgb - tgt_rgb|_1 + lambda_d |depth - tgt_depth|),
+ * M_n = [normal . ray > 0] (eq:normal_mask), M_o = [alpha > 0.95]
+ * (eq:opacity_mask); use_masks = 0 drops both masks.  Inputs are images of
+ * `camera`'s size.  Writes the loss to *loss (device scalar) and its gradients,
+ * masks held constant and d|x|/dx = 0 at 0, to d_rgb [3][H][W] and d_depth [H][W]. */
+GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const float* rgb,
+                                const float* depth, const float* normal, const float* alpha,
+                                const float* tgt_rgb, const float* tgt_depth, float lambda_d,
+                                int32_t use_masks, float* loss, float* d_rgb, float* d_depth,
+                                hipStream_t stream);
+
+/* Run the tracking loop described at gs2d_track_args (the pose update of Sec.
+ * "Tracking and Keyframe Selection": AdamW on the pose, surfels frozen). */
+GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* args, hipStream_t stream);
+
+/* Counters of the last render; synchronises `stream`. */
+GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream);
+
+/* Copy an internal buffer of the last render to host memory (diagnostics and tests).
+ * which: 0 sorted tile keys (uint32 [n_pairs]), 1 sorted surfel ids (uint32 [n_pairs]),
+ * 2 tile ranges (uint32 [n_tiles][2]), 3 depth-sorted surfel keys (uint32 [n], ascending;
+ * float32 camera depth bits, 0xFFFFFFFF for surfels that touch no tile; ids in 9),
+ * 4 per-surfel tile rect (uint16 [n][4]: x0, x1, y0, y1, inclusive; empty: x0 > x1),
+ * 5 per-pixel final transmittance (float [H][W]), 6 per-pixel list length (uint32 [H][W]),
+ * 7 unsorted tile keys, 8 unsorted surfel ids (uint32 [n_pairs], before the tile sort;
+ * only with options.keep_unsorted = 1), 9 depth-sorted surfel ids (uint32 [n]).
+ * *bytes (host) is the buffer size in; the bytes copied out.  Synchronises `stream`. */
+GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes,
+                             hipStream_t stream);
+
+/* Last hipError_t recorded by the context (0 if none). */
+GS2D_API int gs2d_last_hip_error(gs2d_ctx* ctx);
+
+/* Static description of an error code. */
+GS2D_API const char* gs2d_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS2D_H */

@@ -282,12 +282,21 @@ void composite_pixel(const Scene& sc, int x, int y, double out[8], double& t_fin
     double m_t = rel(Tn, sc.k.t_min);
     fm = std::min(fm, m_t);
     gm = std::min(gm, m_t);
-    if (!std::isnan(prev_z)) {
-      double m_o = rel(s.mu_c[2], prev_z);
+    // Order is decided on float32(mu_c.z) (ties by index).  A depth computed in
+    // double lands on a different float32 key only if it sits on a float32
+    // rounding boundary, so the order margin is the relative distance to the
+    // nearest such boundary, scaled by 1e8 to share the 1e-5 exclusion threshold
+    // (1e-13 relative is far above double rounding noise).
+    {
+      const double z = s.mu_c[2];
+      const float f = (float)z;
+      const double up = (double)std::nextafter(f, INFINITY), dn = (double)std::nextafter(f, -INFINITY);
+      const double b1 = 0.5 * ((double)f + up), b0 = 0.5 * ((double)f + dn);
+      const double m_o = 1e8 * std::min(std::fabs(z - b1), std::fabs(z - b0)) / std::fabs(z);
       fm = std::min(fm, m_o);
       gm = std::min(gm, m_o);
     }
-    prev_z = s.mu_c[2];
+    (void)prev_z;
     if (Tn < sc.k.t_min) break;
     double w = h.alpha * T;
     for (int c = 0; c < 3; ++c) out[c] += w * s.rgb[c];

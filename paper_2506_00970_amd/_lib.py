@@ -1,0 +1,111 @@
+"""ctypes declarations of the libgs2d.so C ABI (include/gs2d.h).
+
+This module only loads the library and marshals arguments.  There is no
+fallback: if the library has not been built, loading raises ``ImportError``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgs2d.so")
+HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "gs2d.h")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_OOM = -2
+ERR_HIP = -3
+ERR_CAPACITY = -4
+ERR_STATE = -5
+ERR_UNSUPPORTED = -6
+ACCUMULATE = 1
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("filter", ctypes.c_int32), ("z_near", ctypes.c_float), ("pair_capacity", ctypes.c_int64),
+                ("keep_unsorted", ctypes.c_int32)]
+
+
+class Counts(ctypes.Structure):
+    _fields_ = [("n_surfels", ctypes.c_int64), ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
+                ("pair_capacity", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
+
+
+class TrackArgs(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera),
+                ("pose", ctypes.c_void_p), ("tgt_rgb", ctypes.c_void_p), ("tgt_depth", ctypes.c_void_p),
+                ("lambda_d", ctypes.c_float), ("use_masks", ctypes.c_int32), ("n_iters", ctypes.c_int32),
+                ("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("use_graph", ctypes.c_int32),
+                ("pose_history", ctypes.c_void_p), ("loss_history", ctypes.c_void_p)]
+
+
+class Gs2dError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"gs2d error {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "gs2d_default_options": ([ctypes.POINTER(Options)], ctypes.c_int),
+    "gs2d_create": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(Options)], ctypes.c_int),
+    "gs2d_destroy": ([_P], ctypes.c_int),
+    "gs2d_render": ([_P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, _P, _P, _P, _P,
+                     ctypes.POINTER(ctypes.c_uint32), _P], ctypes.c_int),
+    "gs2d_render_backward": ([_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, ctypes.c_int32, _P], ctypes.c_int),
+    "gs2d_tracking_loss": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
+                            _P, _P, _P, _P], ctypes.c_int),
+    "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
+    "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
+    "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),
+    "gs2d_last_hip_error": ([_P], ctypes.c_int),
+    "gs2d_error_string": ([ctypes.c_int], ctypes.c_char_p),
+}
+
+
+def load():
+    """Load libgs2d.so (built in-tree) and declare every exported function."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2506_00970_amd.build` "
+                              "(the rasterizer has no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return load().gs2d_error_string(int(code)).decode()
+
+
+def check(code: int, ctx=None) -> None:
+    if code != OK:
+        msg = error_string(code)
+        if ctx is not None and code == ERR_HIP:
+            msg += f" (hipError_t {load().gs2d_last_hip_error(ctx)})"
+        raise Gs2dError(code, msg)
+
+
+def declared_functions() -> list:
+    """Names of the functions declared with GS2D_API in include/gs2d.h."""
+    import re
+
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    return re.findall(r"GS2D_API\s+[\w\s\*]+?\b(gs2d_\w+)\s*\(", text)

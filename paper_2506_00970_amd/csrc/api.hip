@@ -1,0 +1,553 @@
+// C ABI of libgs2d.so: context and workspace management, render, backward,
+// tracking loss, the graph-captured tracking loop and diagnostics.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gs2d_internal.h"
+
+using namespace gs2d;
+
+namespace {
+
+int fail_hip(gs2d_ctx* ctx, hipError_t e) {
+  ctx->last_hip_error = (int)e;
+  (void)hipGetLastError();  // clear the sticky launch error, if any
+  return e == hipErrorOutOfMemory ? GS2D_ERR_OOM : GS2D_ERR_HIP;
+}
+
+#define GS2D_HIP(ctx, expr)                    \
+  do {                                         \
+    hipError_t e_ = (expr);                    \
+    if (e_ != hipSuccess) return fail_hip((ctx), e_); \
+  } while (0)
+
+#define GS2D_TRY(expr)            \
+  do {                            \
+    int r_ = (expr);              \
+    if (r_ != GS2D_OK) return r_; \
+  } while (0)
+
+template <class T>
+int realloc_dev(gs2d_ctx* ctx, T** p, int64_t count) {
+  if (*p) {
+    (void)hipFree(*p);
+    *p = nullptr;
+  }
+  if (count <= 0) return GS2D_OK;
+  hipError_t e = hipMalloc((void**)p, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail_hip(ctx, e);
+  }
+  return GS2D_OK;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int stream_capturing(hipStream_t s, bool* cap) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &st);
+  if (e != hipSuccess) return (int)e;
+  *cap = st == hipStreamCaptureStatusActive;
+  return 0;
+}
+
+int ensure_hist(gs2d_ctx* ctx) {
+  const int64_t items = ctx->n_cap > ctx->p_cap ? ctx->n_cap : ctx->p_cap;
+  const int64_t need = (items + kScanItems - 1) / kScanItems * 256;
+  if (need <= ctx->hist_cap) return GS2D_OK;
+  GS2D_TRY(realloc_dev(ctx, &ctx->hist, need));
+  ctx->hist_cap = need;
+  return GS2D_OK;
+}
+
+int ensure_surfels(gs2d_ctx* ctx, int64_t n) {
+  if (n <= ctx->n_cap) return GS2D_OK;
+  const int64_t cap = round_up(n, kScanItems);
+  GS2D_TRY(realloc_dev(ctx, &ctx->rec, cap * kRecF4));
+  GS2D_TRY(realloc_dev(ctx, &ctx->rect, cap));
+  GS2D_TRY(realloc_dev(ctx, &ctx->count, cap));
+  for (int k = 0; k < 2; ++k) {
+    GS2D_TRY(realloc_dev(ctx, &ctx->dkey[k], cap));
+    GS2D_TRY(realloc_dev(ctx, &ctx->dval[k], cap));
+  }
+  GS2D_TRY(realloc_dev(ctx, &ctx->offs, cap));
+  GS2D_TRY(realloc_dev(ctx, &ctx->block_sums, cap / kScanItems + 1));
+  ctx->n_cap = cap;
+  return ensure_hist(ctx);
+}
+
+int ensure_pairs(gs2d_ctx* ctx, int64_t p) {
+  if (p <= ctx->p_cap) return GS2D_OK;
+  const int64_t cap = round_up(p, kScanItems);
+  for (int k = 0; k < 2; ++k) {
+    GS2D_TRY(realloc_dev(ctx, &ctx->pkey[k], cap));
+    GS2D_TRY(realloc_dev(ctx, &ctx->pval[k], cap));
+  }
+  if (ctx->opt.keep_unsorted) {
+    GS2D_TRY(realloc_dev(ctx, &ctx->pkey_keep, cap));
+    GS2D_TRY(realloc_dev(ctx, &ctx->pval_keep, cap));
+  }
+  ctx->p_cap = cap;
+  return ensure_hist(ctx);
+}
+
+int ensure_pixels(gs2d_ctx* ctx, int64_t hw) {
+  if (hw <= ctx->hw_cap) return GS2D_OK;
+  GS2D_TRY(realloc_dev(ctx, &ctx->t_final, hw));
+  GS2D_TRY(realloc_dev(ctx, &ctx->last, hw));
+  GS2D_TRY(realloc_dev(ctx, &ctx->lpart, (int64_t)loss_blocks((int)hw) + 1));
+  if (ctx->lgrad) GS2D_TRY(realloc_dev(ctx, &ctx->lgrad, 4 * hw));
+  if (ctx->limg) GS2D_TRY(realloc_dev(ctx, &ctx->limg, 8 * hw));
+  ctx->hw_cap = hw;
+  return GS2D_OK;
+}
+
+int ensure_tiles(gs2d_ctx* ctx, int64_t tiles) {
+  if (tiles <= ctx->tile_cap) return GS2D_OK;
+  GS2D_TRY(realloc_dev(ctx, &ctx->ranges, tiles));
+  ctx->tile_cap = tiles;
+  return GS2D_OK;
+}
+
+int ensure_parts(gs2d_ctx* ctx, int64_t rows) {
+  if (rows <= ctx->part_cap) return GS2D_OK;
+  GS2D_TRY(realloc_dev(ctx, &ctx->part, rows * 8));
+  ctx->part_cap = rows;
+  return GS2D_OK;
+}
+
+int ensure_gacc(gs2d_ctx* ctx, int64_t n) {
+  if (n <= ctx->gacc_cap) return GS2D_OK;
+  const int64_t cap = round_up(n, kScanItems);
+  GS2D_TRY(realloc_dev(ctx, &ctx->gacc, cap * 16));
+  ctx->gacc_cap = cap;
+  return GS2D_OK;
+}
+
+int tile_bits(int n_tiles) {
+  int b = 1;
+  while ((1 << b) < n_tiles) ++b;
+  return b;
+}
+
+bool valid_tile(int tw, int th) {
+  return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 16);
+}
+
+bool valid_batch(int b) { return b == 32 || b == 64 || b == 128 || b == 256; }
+
+CamF camf(const gs2d_camera& c) { return CamF{c.width, c.height, c.fx, c.fy, c.cx, c.cy}; }
+
+bool valid_camera(const gs2d_camera* c) {
+  return c && c->width > 0 && c->height > 0 && c->width <= 16384 && c->height <= 16384 &&
+         std::isfinite(c->fx) && std::isfinite(c->fy) && c->fx > 0.f && c->fy > 0.f &&
+         std::isfinite(c->cx) && std::isfinite(c->cy);
+}
+
+// Forward pass.  With allow_sync the pair count is read back after the scan and
+// the pair buffers grow to fit; without it (graph capture, tracking loop) an
+// overflow only raises the device flag.
+int render_impl(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera& cam, const float* pose,
+                float* rgb, float* depth, float* normal, float* alpha, hipStream_t s, bool allow_sync) {
+  const int W = cam.width, H = cam.height;
+  const int64_t HW = (int64_t)W * H;
+  const int tw = ctx->opt.tile_w, th = ctx->opt.tile_h;
+  const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
+  const int n_tiles = tiles_x * tiles_y;
+  if (n > 0x7FFFFFFF || n_tiles > 65535 * 64) return GS2D_ERR_UNSUPPORTED;
+  bool capturing = false;
+  if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+  const bool grow_ok = !capturing;
+  if ((n > ctx->n_cap || HW > ctx->hw_cap || n_tiles > ctx->tile_cap) && !grow_ok) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_surfels(ctx, n > 0 ? n : 1));
+  GS2D_TRY(ensure_pixels(ctx, HW));
+  GS2D_TRY(ensure_tiles(ctx, n_tiles));
+  const int64_t rows = n_tiles > (n + 255) / 256 ? n_tiles : (n + 255) / 256;
+  if (rows > ctx->part_cap && !grow_ok) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_parts(ctx, rows));
+  if (ctx->p_cap == 0) {
+    if (!grow_ok) return GS2D_ERR_CAPACITY;
+    GS2D_TRY(ensure_pairs(ctx, ctx->opt.pair_capacity > 0 ? ctx->opt.pair_capacity : 4 * (n > 0 ? n : 1)));
+  }
+  ctx->tiles_x = tiles_x;
+  ctx->tiles_y = tiles_y;
+  ctx->n_tiles = n_tiles;
+  const CamF cf = camf(cam);
+  int pbuf = 0;
+  if (n == 0) {
+    if (rgb) launch_fill_f32(rgb, 0.f, 3 * HW, s);
+    if (depth) launch_fill_f32(depth, 0.f, HW, s);
+    if (normal) launch_fill_f32(normal, 0.f, 3 * HW, s);
+    if (alpha) launch_fill_f32(alpha, 0.f, HW, s);
+    launch_fill_f32(ctx->t_final, 1.f, HW, s);
+    launch_fill_u32(ctx->last, 0u, HW, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ranges), 0u, 2 * (int64_t)n_tiles, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ctrl), 0u, 3, s);
+  } else {
+    launch_preprocess(params, (int)n, pose, cf, ctx->opt.z_near, ctx->opt.filter, tw, th, tiles_x, tiles_y,
+                      ctx->rec, ctx->rect, ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, s);
+    const int dbuf = radix_sort(ctx->dkey, ctx->dval, n, n, nullptr, 32, ctx->hist, s);
+    if (dbuf != 0) return GS2D_ERR_HIP;  // four 8-bit passes end in buffer 0
+    launch_scan_counts(ctx->count, ctx->dval[0], (int)n, ctx->offs, ctx->block_sums, ctx->ctrl, s);
+    if (allow_sync && !capturing && !ctx->pair_fixed) {
+      GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+      GS2D_HIP(ctx, hipStreamSynchronize(s));
+      const int64_t np = ctx->host_ctrl->n_pairs;
+      if (np > ctx->p_cap) GS2D_TRY(ensure_pairs(ctx, np + np / 4));
+    }
+    launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, (int)n, tiles_x, ctx->p_cap, ctx->pkey[0],
+                     ctx->pval[0], ctx->ctrl, s);
+    if (ctx->opt.keep_unsorted && ctx->pkey_keep) {
+      launch_copy_u32(ctx->pkey[0], ctx->pkey_keep, ctx->p_cap, s);
+      launch_copy_u32(ctx->pval[0], ctx->pval_keep, ctx->p_cap, s);
+    }
+    pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits(n_tiles), ctx->hist, s);
+    launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, n_tiles, s);
+    BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, cf, ctx->opt.z_near, ctx->opt.filter, tiles_x, n_tiles,
+                 ctx->opt.batch};
+    launch_blend_fwd(ba, tw, th, rgb, depth, normal, alpha, ctx->t_final, ctx->last, s);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  ctx->generation += 1;
+  ctx->last_n = n;
+  ctx->last_cam = cam;
+  ctx->last_params = params;
+  ctx->pair_buf = pbuf;
+  ctx->have_forward = true;
+  ctx->last_blank = n == 0;
+  return GS2D_OK;
+}
+
+BlendArgs blend_args(gs2d_ctx* ctx) {
+  return BlendArgs{ctx->ranges, ctx->pval[ctx->pair_buf], ctx->rec, camf(ctx->last_cam), ctx->opt.z_near,
+                   ctx->opt.filter, ctx->tiles_x, ctx->n_tiles, ctx->opt.batch};
+}
+
+int set_device(gs2d_ctx* ctx) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) GS2D_HIP(ctx, hipSetDevice(ctx->device));
+  return GS2D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+GS2D_API int gs2d_default_options(gs2d_options* opt) {
+  if (!opt) return GS2D_ERR_INVALID_ARG;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->tile_w = 16;
+  opt->tile_h = 16;
+  opt->batch = 256;
+  opt->filter = 1;
+  opt->z_near = 0.2f;
+  opt->pair_capacity = 0;
+  opt->keep_unsorted = 0;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_create(gs2d_ctx** out, int device, const gs2d_options* opt) {
+  if (!out) return GS2D_ERR_INVALID_ARG;
+  *out = nullptr;
+  gs2d_options o;
+  gs2d_default_options(&o);
+  if (opt) o = *opt;
+  if (!valid_tile(o.tile_w, o.tile_h) || !valid_batch(o.batch) || !(o.z_near > 0.f) ||
+      !std::isfinite(o.z_near) || o.pair_capacity < 0 || (o.filter != 0 && o.filter != 1))
+    return GS2D_ERR_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return GS2D_ERR_INVALID_ARG;
+  }
+  gs2d_ctx* ctx = new (std::nothrow) gs2d_ctx();
+  if (!ctx) return GS2D_ERR_OOM;
+  ctx->device = device;
+  ctx->opt = o;
+  int r = set_device(ctx);
+  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->ctrl, 1);
+  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->saved_pose, 12);
+  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->pose0, 12);
+  if (r == GS2D_OK) {
+    hipError_t e = hipHostMalloc((void**)&ctx->host_ctrl, sizeof(Ctrl), hipHostMallocDefault);
+    if (e != hipSuccess) r = fail_hip(ctx, e);
+  }
+  if (r == GS2D_OK && o.pair_capacity > 0) {
+    r = ensure_pairs(ctx, o.pair_capacity);
+    ctx->pair_fixed = true;
+  }
+  if (r == GS2D_OK) {
+    hipError_t e = hipMemset(ctx->ctrl, 0, sizeof(Ctrl));
+    if (e != hipSuccess) r = fail_hip(ctx, e);
+  }
+  if (r != GS2D_OK) {
+    gs2d_destroy(ctx);
+    return r;
+  }
+  *out = ctx;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
+  if (!ctx) return GS2D_OK;
+  (void)set_device(ctx);
+  void* bufs[] = {ctx->rec,     ctx->rect,     ctx->count,   ctx->dkey[0],   ctx->dkey[1],   ctx->dval[0],
+                  ctx->dval[1], ctx->offs,     ctx->block_sums, ctx->hist,  ctx->gacc,      ctx->pkey[0],
+                  ctx->pkey[1], ctx->pval[0],  ctx->pval[1],  ctx->pkey_keep, ctx->pval_keep, ctx->ranges,
+                  ctx->t_final, ctx->last,     ctx->lgrad,    ctx->limg,      ctx->part,      ctx->lpart,
+                  ctx->pose0,   ctx->saved_pose, ctx->ctrl};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);
+  if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+  delete ctx;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_render(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera,
+                         const float* pose, float* rgb, float* depth, float* normal, float* alpha,
+                         uint32_t* generation, hipStream_t stream) {
+  if (!ctx || !valid_camera(camera) || n < 0 || (n > 0 && !params) || !pose) return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  GS2D_TRY(render_impl(ctx, params, n, *camera, pose, rgb, depth, normal, alpha, stream, true));
+  if (generation) *generation = ctx->generation;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float* d_depth,
+                                  const float* d_normal, const float* d_alpha, float* d_params,
+                                  float* d_pose, uint32_t generation, int32_t flags, hipStream_t stream) {
+  if (!ctx) return GS2D_ERR_INVALID_ARG;
+  if ((flags & ~GS2D_ACCUMULATE) != 0) return GS2D_ERR_INVALID_ARG;
+  if (!ctx->have_forward || generation != ctx->generation) return GS2D_ERR_STATE;
+  GS2D_TRY(set_device(ctx));
+  const int acc = (flags & GS2D_ACCUMULATE) ? 1 : 0;
+  const int64_t n = ctx->last_n;
+  const hipStream_t s = stream;
+  if (n == 0) {
+    if (!acc && d_pose) launch_fill_f32(d_pose, 0.f, 6, s);
+    GS2D_HIP(ctx, hipGetLastError());
+    return GS2D_OK;
+  }
+  const BlendArgs ba = blend_args(ctx);
+  if (!d_params) {
+    launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
+                     d_alpha, nullptr, ctx->part, s);
+    if (d_pose) launch_reduce_pose(ctx->part, ctx->n_tiles, d_pose, acc, s);
+  } else {
+    bool capturing = false;
+    if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+    if (n > ctx->gacc_cap && capturing) return GS2D_ERR_CAPACITY;
+    GS2D_TRY(ensure_gacc(ctx, n));
+    launch_fill_f32(ctx->gacc, 0.f, n * 16, s);
+    launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
+                     d_alpha, ctx->gacc, ctx->part, s);
+    launch_preprocess_bwd(ctx->last_params, (int)n, ctx->saved_pose, ctx->gacc, d_params, acc, ctx->part, s);
+    if (d_pose) launch_reduce_pose(ctx->part, (int)((n + 255) / 256), d_pose, acc, s);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const float* rgb, const float* depth,
+                                const float* normal, const float* alpha, const float* tgt_rgb,
+                                const float* tgt_depth, float lambda_d, int32_t use_masks, float* loss,
+                                float* d_rgb, float* d_depth, hipStream_t stream) {
+  if (!ctx || !valid_camera(camera) || !rgb || !depth || !tgt_rgb || !tgt_depth || !loss || !d_rgb || !d_depth)
+    return GS2D_ERR_INVALID_ARG;
+  if (use_masks && (!normal || !alpha)) return GS2D_ERR_INVALID_ARG;
+  if (!std::isfinite(lambda_d)) return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  const int64_t HW = (int64_t)camera->width * camera->height;
+  bool capturing = false;
+  if (stream_capturing(stream, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+  if (HW > ctx->hw_cap && capturing) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_pixels(ctx, HW));
+  int nparts = 0;
+  launch_tracking_loss(camf(*camera), rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks, d_rgb,
+                       d_depth, ctx->lpart, &nparts, stream);
+  launch_reduce_loss(ctx->lpart, nparts, 1.0f / (float)HW, loss, nullptr, stream);
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* a, hipStream_t caller_stream) {
+  if (!ctx || !a || !valid_camera(&a->camera) || a->n < 0 || (a->n > 0 && !a->params) || !a->pose ||
+      !a->tgt_rgb || !a->tgt_depth || a->n_iters < 0)
+    return GS2D_ERR_INVALID_ARG;
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.f) return GS2D_ERR_INVALID_ARG;
+  if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f))
+    return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  bool capturing = false;
+  if (stream_capturing(caller_stream, &capturing) != 0 || capturing) return GS2D_ERR_INVALID_ARG;
+  // The loop runs on the caller's stream, or, to be captured into a graph, on a
+  // stream of the context (the legacy null stream cannot be captured); the call
+  // returns after the work has completed either way.
+  hipStream_t s = caller_stream;
+  if (a->use_graph) {
+    if (!ctx->graph_stream) GS2D_HIP(ctx, hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
+    GS2D_HIP(ctx, hipStreamSynchronize(caller_stream));
+    s = ctx->graph_stream;
+  }
+  const gs2d_camera cam = a->camera;
+  const int64_t HW = (int64_t)cam.width * cam.height;
+  GS2D_TRY(ensure_pixels(ctx, HW));
+  if (!ctx->lgrad) GS2D_TRY(realloc_dev(ctx, &ctx->lgrad, 4 * ctx->hw_cap));
+  if (!ctx->limg) GS2D_TRY(realloc_dev(ctx, &ctx->limg, 8 * ctx->hw_cap));
+  float* img = ctx->limg;
+  float *rgb = img, *depth = img + 3 * HW, *normal = img + 4 * HW, *alpha = img + 7 * HW;
+  float *g_rgb = ctx->lgrad, *g_depth = ctx->lgrad + 3 * HW;
+  GS2D_HIP(ctx, hipMemcpyAsync(ctx->pose0, a->pose, 12 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  AdamArgs adam;
+  for (int k = 0; k < 6; ++k) adam.lr[k] = a->lr[k];
+  adam.beta1 = a->beta1;
+  adam.beta2 = a->beta2;
+  adam.eps = a->eps;
+  adam.weight_decay = a->weight_decay;
+  const float inv_hw = 1.0f / (float)HW;
+
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if (attempt > 0)
+      GS2D_HIP(ctx, hipMemcpyAsync(a->pose, ctx->pose0, 12 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // size the pair buffers on the start pose with headroom, then run without readbacks
+    const bool was_fixed = ctx->pair_fixed;
+    ctx->pair_fixed = false;
+    int r = render_impl(ctx, a->params, a->n, cam, a->pose, rgb, depth, normal, alpha, s, true);
+    if (r != GS2D_OK) {
+      ctx->pair_fixed = was_fixed;
+      return r;
+    }
+    const int64_t np = ctx->host_ctrl->n_pairs;
+    r = ensure_pairs(ctx, (np + np / 2 + 1024) << attempt);
+    ctx->pair_fixed = true;
+    if (r != GS2D_OK) {
+      ctx->pair_fixed = was_fixed;
+      return r;
+    }
+    launch_track_init(a->pose, ctx->ctrl, s);
+    auto iteration = [&]() -> int {
+      GS2D_TRY(render_impl(ctx, a->params, a->n, cam, a->pose, rgb, depth, normal, alpha, s, false));
+      int nparts = 0;
+      launch_tracking_loss(camf(cam), rgb, depth, normal, alpha, a->tgt_rgb, a->tgt_depth, a->lambda_d,
+                           a->use_masks, g_rgb, g_depth, ctx->lpart, &nparts, s);
+      if (a->n > 0)
+        launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, g_rgb,
+                         g_depth, nullptr, nullptr, nullptr, ctx->part, s);
+      else
+        launch_fill_f32(ctx->part, 0.f, 8, s);
+      launch_pose_step(ctx->part, a->n > 0 ? ctx->n_tiles : 1, ctx->lpart, nparts, inv_hw, adam, a->pose,
+                       ctx->ctrl, a->pose_history, a->loss_history, a->n_iters, s);
+      return GS2D_OK;
+    };
+    if (a->use_graph && a->n_iters > 0) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      GS2D_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      int ri = iteration();
+      hipError_t ec = hipStreamEndCapture(s, &graph);
+      if (ri != GS2D_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->pair_fixed = was_fixed;
+        return ri;
+      }
+      if (ec != hipSuccess) {
+        ctx->pair_fixed = was_fixed;
+        return fail_hip(ctx, ec);
+      }
+      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        ctx->pair_fixed = was_fixed;
+        return fail_hip(ctx, ei);
+      }
+      hipError_t el = hipSuccess;
+      for (int it = 0; it < a->n_iters && el == hipSuccess; ++it) el = hipGraphLaunch(exec, s);
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      if (el != hipSuccess) {
+        ctx->pair_fixed = was_fixed;
+        return fail_hip(ctx, el);
+      }
+    } else {
+      for (int it = 0; it < a->n_iters; ++it) {
+        int ri = iteration();
+        if (ri != GS2D_OK) {
+          ctx->pair_fixed = was_fixed;
+          return ri;
+        }
+      }
+    }
+    ctx->pair_fixed = was_fixed;
+    GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    GS2D_HIP(ctx, hipStreamSynchronize(s));
+    if (!ctx->host_ctrl->overflow) return GS2D_OK;
+  }
+  return GS2D_ERR_CAPACITY;
+}
+
+GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream) {
+  if (!ctx || !out) return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+  GS2D_HIP(ctx, hipStreamSynchronize(stream));
+  out->n_surfels = ctx->last_n;
+  out->n_visible = ctx->last_blank ? 0 : ctx->host_ctrl->n_visible;
+  out->n_pairs = ctx->last_blank ? 0 : ctx->host_ctrl->n_pairs;
+  out->pair_capacity = ctx->p_cap;
+  out->overflow = ctx->host_ctrl->overflow ? 1 : 0;
+  out->n_tiles = ctx->n_tiles;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes, hipStream_t stream) {
+  if (!ctx || !bytes || (!host_dst && *bytes > 0)) return GS2D_ERR_INVALID_ARG;
+  if (!ctx->have_forward) return GS2D_ERR_STATE;
+  gs2d_counts c;
+  GS2D_TRY(gs2d_get_counts(ctx, &c, stream));
+  const int64_t HW = (int64_t)ctx->last_cam.width * ctx->last_cam.height;
+  const void* src = nullptr;
+  size_t need = 0;
+  const int64_t np = c.n_pairs < ctx->p_cap ? c.n_pairs : ctx->p_cap;
+  switch (which) {
+    case 0: src = ctx->pkey[ctx->pair_buf]; need = (size_t)np * 4; break;
+    case 1: src = ctx->pval[ctx->pair_buf]; need = (size_t)np * 4; break;
+    case 2: src = ctx->ranges; need = (size_t)ctx->n_tiles * 8; break;
+    case 3: src = ctx->dkey[0]; need = (size_t)ctx->last_n * 4; break;
+    case 4: src = ctx->rect; need = (size_t)ctx->last_n * 8; break;
+    case 5: src = ctx->t_final; need = (size_t)HW * 4; break;
+    case 6: src = ctx->last; need = (size_t)HW * 4; break;
+    case 7: src = ctx->pkey_keep; need = (size_t)np * 4; break;
+    case 8: src = ctx->pval_keep; need = (size_t)np * 4; break;
+    case 9: src = ctx->dval[0]; need = (size_t)ctx->last_n * 4; break;
+    default: return GS2D_ERR_INVALID_ARG;
+  }
+  if (!src) return GS2D_ERR_UNSUPPORTED;
+  if (*bytes < need) {
+    *bytes = need;
+    return GS2D_ERR_INVALID_ARG;
+  }
+  if (need > 0) GS2D_HIP(ctx, hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_last_hip_error(gs2d_ctx* ctx) { return ctx ? ctx->last_hip_error : 0; }
+
+GS2D_API const char* gs2d_error_string(int code) {
+  switch (code) {
+    case GS2D_OK: return "ok";
+    case GS2D_ERR_INVALID_ARG: return "invalid argument";
+    case GS2D_ERR_OOM: return "out of device memory";
+    case GS2D_ERR_HIP: return "HIP runtime error (see gs2d_last_hip_error)";
+    case GS2D_ERR_CAPACITY: return "tile-pair capacity exceeded; outputs of the last render are invalid";
+    case GS2D_ERR_STATE: return "backward without a matching forward (generation mismatch)";
+    case GS2D_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error code";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,436 @@
+// Per-tile front-to-back blending (forward) and its reverse mode (backward).
+//
+// Forward (Sec. "2D Gaussian Splatting", eq:alpha_blending): one workgroup per
+// screen tile, one lane per pixel, each wave owning an 8x8 block of the tile.
+// The tile's depth-ordered surfel list is staged through LDS in batches of
+// 96-byte records; every wave tests each record's footprint box against its own
+// 8x8 block (a scalar, wave-uniform branch) before any lane evaluates it.  Per
+// (pixel, surfel) pair the ray-splat intersection is solved in the surfel's uv
+// frame from the centre-relative homography rows (see gs2d_internal.h), the
+// Gaussian G = exp(-(u^2+v^2)/2) (or the low-pass filter term) gives
+// alpha = min(0.99, o G), and colour, depth, normal and opacity are composited
+// until the transmittance would fall below 1e-4.
+//
+// Backward (Sec. "Camera Pose Optimization"): the same lists walked back to front
+// from each pixel's last composited entry.  The transmittance in front of each
+// surfel is recovered by division, T_i = T_{i+1} / (1 - alpha_i), starting from
+// the stored final transmittance, and the colour/depth/normal/opacity behind it
+// by B_{i-1} = alpha_i v_i + (1 - alpha_i) B_i, so dL/dalpha_i =
+// T_i sum_ch g_ch (v_i,ch - B_i,ch) needs no per-surfel blend state.  For every
+// pair the gradient to the camera-frame surfel frame H_c (columns a = s_u t_uc,
+// b = s_v t_vc, mu_c) is rank one, V (u, v, 1)^T, where V = K^T V' collects the
+// image-space gradient of the pair (the paper's W^T dL/dT); the filter branch
+// has (u, v) = (0, 0).  Hence the pose gradient of eq:derivatives is, pair by
+// pair, rho += V and phi += X x V (+ n x g_n) with X = mu_c + u a + v b the
+// intersection point.  Pose-only mode accumulates those six numbers in
+// registers and reduces them once per workgroup (no per-surfel atomics); the
+// full mode reduces the 16 per-surfel terms over each wave and adds them
+// atomically.
+#include "gs2d_internal.h"
+
+namespace gs2d {
+namespace {
+
+struct Hit {
+  float alpha, G, d, u, v, rq, dx, dy;
+  bool b3d, clamped;
+};
+
+// One (pixel, surfel) evaluation; the forward and backward kernels call this same
+// function so that every decision is reproduced bit for bit.
+__device__ __forceinline__ bool evaluate(float px, float py, const float4 g1, const float4 g2,
+                                         const float4 g3, float o, float z_near, int filter, Hit& h) {
+  const float cx = g1.x, cy = g1.y, Dt = g1.z, k0 = g1.w;
+  const float k1 = g2.x, P0 = g2.y, P1 = g2.z, Q0 = g2.w;
+  const float Q1 = g3.x, m0 = g3.y, m1 = g3.z, m2 = g3.w;
+  h.dx = px - cx;
+  h.dy = py - cy;
+  const float q2 = fmaf(-h.dy, k1, fmaf(-h.dx, k0, Dt));
+  const float e0 = fmaf(Q1, h.dx, -(P1 * h.dy));
+  const float e1 = fmaf(P0, h.dy, -(Q0 * h.dx));
+  h.rq = __builtin_amdgcn_rcpf(q2);
+  const float sc = m2 * h.rq;
+  h.u = e0 * sc;
+  h.v = e1 * sc;
+  const float rho3 = fmaf(h.u, h.u, h.v * h.v);
+  const float rho2 = filter ? kFilterScale * fmaf(h.dx, h.dx, h.dy * h.dy) : __builtin_inff();
+  h.b3d = rho3 <= rho2;  // NaN (q2 = 0) selects the filter branch
+  const float rho = h.b3d ? rho3 : rho2;
+  h.d = h.b3d ? fmaf(m0, h.u, fmaf(m1, h.v, m2)) : m2;
+  if (!(rho <= kRhoCutoff) || !(h.d >= z_near)) return false;
+  h.G = __builtin_amdgcn_exp2f(rho * -0.72134752044448170368f);  // exp(-rho / 2)
+  const float og = o * h.G;
+  h.clamped = og > kAlphaMax;
+  h.alpha = h.clamped ? kAlphaMax : og;
+  return h.alpha >= kAlphaMin;
+}
+
+__device__ __forceinline__ float uniformf(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous band
+// of tiles so that neighbouring tiles, which share surfel records, share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  const int q = G / 8, r = G % 8, x = b % 8, k = b / 8;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v = max(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ rgb,
+                                                           float* __restrict__ depth,
+                                                           float* __restrict__ normal,
+                                                           float* __restrict__ alpha,
+                                                           float* __restrict__ t_final,
+                                                           uint32_t* __restrict__ last_out) {
+  constexpr int NT = TW * TH, WX = TW / 8;
+  extern __shared__ float4 srec[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wx0 = tx * TW + (wave % WX) * 8, wy0 = ty * TH + (wave / WX) * 8;
+  const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+  const bool inside = px < a.cam.width && py < a.cam.height;
+  const float fpx = (float)px, fpy = (float)py;
+  const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
+  const uint2 rg = a.ranges[tile];
+  const int start = (int)rg.x, end = (int)rg.y;
+  float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f, co = 0.f;
+  int lastj = 0;
+  bool done = !inside;
+  for (int b0 = start; b0 < end; b0 += a.batch) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int nb = min(a.batch, end - b0);
+    for (int k = t; k < nb * kRecF4; k += NT) {
+      const int j = k / kRecF4, f = k - j * kRecF4;
+      srec[k] = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      if (__ballot(!done) == 0ull) break;
+      const float4 bb = srec[j * kRecF4];
+      if (uniformf(bb.y) < bx0 || uniformf(bb.x) > bx1 || uniformf(bb.w) < by0 || uniformf(bb.z) > by1)
+        continue;
+      if (!done) {
+        const float4 c4 = srec[j * kRecF4 + 4];
+        Hit h;
+        if (evaluate(fpx, fpy, srec[j * kRecF4 + 1], srec[j * kRecF4 + 2], srec[j * kRecF4 + 3], c4.x,
+                     a.z_near, a.filter, h)) {
+          const float Tn = T * (1.0f - h.alpha);
+          if (Tn < kTMin) {
+            done = true;
+          } else {
+            const float w = h.alpha * T;
+            const float4 nv = srec[j * kRecF4 + 5];
+            cr = fmaf(w, c4.y, cr);
+            cg = fmaf(w, c4.z, cg);
+            cb = fmaf(w, c4.w, cb);
+            cd = fmaf(w, h.d, cd);
+            n0 = fmaf(w, nv.x, n0);
+            n1 = fmaf(w, nv.y, n1);
+            n2 = fmaf(w, nv.z, n2);
+            co += w;
+            T = Tn;
+            lastj = b0 - start + j + 1;
+          }
+        }
+      }
+    }
+  }
+  if (!inside) return;
+  const int HW = a.cam.width * a.cam.height;
+  const int p = py * a.cam.width + px;
+  if (rgb) {
+    rgb[p] = cr;
+    rgb[HW + p] = cg;
+    rgb[2 * HW + p] = cb;
+  }
+  if (depth) depth[p] = cd;
+  if (normal) {
+    normal[p] = n0;
+    normal[HW + p] = n1;
+    normal[2 * HW + p] = n2;
+  }
+  if (alpha) alpha[p] = co;
+  t_final[p] = T;
+  last_out[p] = (uint32_t)lastj;
+}
+
+template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O>
+__global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
+    BlendArgs a, const float* __restrict__ t_final, const uint32_t* __restrict__ last_in,
+    const float* __restrict__ g_rgb, const float* __restrict__ g_depth, const float* __restrict__ g_normal,
+    const float* __restrict__ g_alpha, float* __restrict__ gacc, float* __restrict__ part) {
+  constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
+  extern __shared__ float4 srec[];
+  uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * kRecF4);
+  __shared__ int s_wmax[NW];
+  __shared__ float s_red[NW][6];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wx0 = tx * TW + (wave % WX) * 8, wy0 = ty * TH + (wave / WX) * 8;
+  const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+  const bool inside = px < a.cam.width && py < a.cam.height;
+  const float fpx = (float)px, fpy = (float)py;
+  const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
+  const int HW = a.cam.width * a.cam.height;
+  const int p = py * a.cam.width + px;
+  int my_last = 0;
+  float T = 1.0f;
+  float gr = 0.f, gg = 0.f, gbl = 0.f, gd = 0.f, gn0 = 0.f, gn1 = 0.f, gn2 = 0.f, go = 0.f;
+  if (inside) {
+    my_last = (int)last_in[p];
+    T = t_final[p];
+    if (g_rgb) {
+      gr = g_rgb[p];
+      gg = g_rgb[HW + p];
+      gbl = g_rgb[2 * HW + p];
+    }
+    if (g_depth) gd = g_depth[p];
+    if (HAS_N) {
+      gn0 = g_normal[p];
+      gn1 = g_normal[HW + p];
+      gn2 = g_normal[2 * HW + p];
+    }
+    if (HAS_O) go = g_alpha[p];
+  }
+  const float xh = (fpx - a.cam.cx) / a.cam.fx, yh = (fpy - a.cam.cy) / a.cam.fy;
+  float Br = 0.f, Bg = 0.f, Bb = 0.f, Bd = 0.f, Bn0 = 0.f, Bn1 = 0.f, Bn2 = 0.f, Bo = 0.f;
+  float pr0 = 0.f, pr1 = 0.f, pr2 = 0.f, pp0 = 0.f, pp1 = 0.f, pp2 = 0.f;
+  const uint2 rg = a.ranges[tile];
+  const int start = (int)rg.x;
+
+  const int wlast = wave_max(my_last);
+  if (lane == 0) s_wmax[wave] = wlast;
+  __syncthreads();
+  int blast = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) blast = max(blast, s_wmax[w]);
+
+  for (int bend = blast; bend > 0; bend -= a.batch) {
+    const int bstart = max(0, bend - a.batch);
+    const int nb = bend - bstart;
+    __syncthreads();
+    for (int k = t; k < nb * kRecF4; k += NT) {
+      const int j = k / kRecF4, f = k - j * kRecF4;
+      const uint32_t id = a.pval[start + bstart + j];
+      srec[k] = a.rec[(size_t)id * kRecF4 + f];
+      if (f == 0) sid[j] = id;
+    }
+    __syncthreads();
+    for (int jj = nb - 1; jj >= 0; --jj) {
+      const int j = bstart + jj;
+      if (j >= wlast) continue;
+      const float4 bb = srec[jj * kRecF4];
+      if (uniformf(bb.y) < bx0 || uniformf(bb.x) > bx1 || uniformf(bb.w) < by0 || uniformf(bb.z) > by1)
+        continue;
+      float acc[16];
+      if (!POSE_ONLY) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+      }
+      bool contrib = false;
+      if (j < my_last) {
+        const float4 g1 = srec[jj * kRecF4 + 1], g2 = srec[jj * kRecF4 + 2], g3 = srec[jj * kRecF4 + 3];
+        const float4 c4 = srec[jj * kRecF4 + 4];
+        Hit h;
+        if (evaluate(fpx, fpy, g1, g2, g3, c4.x, a.z_near, a.filter, h)) {
+          contrib = true;
+          const float4 nv = srec[jj * kRecF4 + 5];
+          const float al = h.alpha;
+          const float Tj = T * __builtin_amdgcn_rcpf(1.0f - al);
+          const float w = al * Tj;
+          float dLda = gr * (c4.y - Br) + gg * (c4.z - Bg) + gbl * (c4.w - Bb) + gd * (h.d - Bd);
+          if (HAS_N) dLda += gn0 * (nv.x - Bn0) + gn1 * (nv.y - Bn1) + gn2 * (nv.z - Bn2);
+          if (HAS_O) dLda += go * (1.0f - Bo);
+          dLda *= Tj;
+          Br = fmaf(al, c4.y - Br, Br);
+          Bg = fmaf(al, c4.z - Bg, Bg);
+          Bb = fmaf(al, c4.w - Bb, Bb);
+          Bd = fmaf(al, h.d - Bd, Bd);
+          if (HAS_N) {
+            Bn0 = fmaf(al, nv.x - Bn0, Bn0);
+            Bn1 = fmaf(al, nv.y - Bn1, Bn1);
+            Bn2 = fmaf(al, nv.z - Bn2, Bn2);
+          }
+          if (HAS_O) Bo = fmaf(al, 1.0f - Bo, Bo);
+          T = Tj;
+          const float g_d = w * gd;
+          float g_o = 0.f, dLdG = 0.f;
+          if (!h.clamped) {
+            g_o = h.G * dLda;
+            dLdG = c4.x * dLda;
+          }
+          const float dLdrho = -0.5f * h.G * dLdG;
+          const float m0 = g3.y, m1 = g3.z, m2 = g3.w;
+          float Vx, Vy, Vz, ue, ve, Xx, Xy, Xz;
+          if (h.b3d) {
+            // u = q0/q2, v = q1/q2; depth d = m . (u, v, 1)
+            const float gu = fmaf(2.0f * h.u, dLdrho, m0 * g_d);
+            const float gv = fmaf(2.0f * h.v, dLdrho, m1 * g_d);
+            const float gq0 = gu * h.rq, gq1 = gv * h.rq;
+            // h_u = P - dx m, h_v = Q - dy m (third entries -dx m2, -dy m2)
+            const float hu0 = fmaf(-h.dx, m0, g2.y), hu1 = fmaf(-h.dx, m1, g2.z);
+            const float hv0 = fmaf(-h.dy, m0, g2.w), hv1 = fmaf(-h.dy, m1, g3.x);
+            const float V0 = hv0 * gq1 - hv1 * gq0;  // (h_v x g_q)_z
+            const float V1 = gq0 * hu1 - gq1 * hu0;  // (g_q x h_u)_z
+            Vx = a.cam.fx * V0;
+            Vy = a.cam.fy * V1;
+            Vz = g_d - xh * Vx - yh * Vy;
+            ue = h.u;
+            ve = h.v;
+            Xx = h.d * xh;
+            Xy = h.d * yh;
+            Xz = h.d;
+          } else {
+            // rho = 2 |p - c|^2 with c = (M02, M12) / m2; depth = m2
+            const float gcx = -2.0f * kFilterScale * h.dx * dLdrho;
+            const float gcy = -2.0f * kFilterScale * h.dy * dLdrho;
+            const float im2 = 1.0f / m2;
+            Vx = a.cam.fx * gcx * im2;
+            Vy = a.cam.fy * gcy * im2;
+            const float xc = (g1.x - a.cam.cx) / a.cam.fx, yc = (g1.y - a.cam.cy) / a.cam.fy;
+            Vz = g_d - xc * Vx - yc * Vy;
+            ue = 0.f;
+            ve = 0.f;
+            Xx = m2 * xc;
+            Xy = m2 * yc;
+            Xz = m2;
+          }
+          if (POSE_ONLY) {
+            pr0 += Vx;
+            pr1 += Vy;
+            pr2 += Vz;
+            pp0 += Xy * Vz - Xz * Vy;
+            pp1 += Xz * Vx - Xx * Vz;
+            pp2 += Xx * Vy - Xy * Vx;
+            if (HAS_N) {
+              const float w0 = w * gn0, w1 = w * gn1, w2 = w * gn2;
+              pp0 += nv.y * w2 - nv.z * w1;
+              pp1 += nv.z * w0 - nv.x * w2;
+              pp2 += nv.x * w1 - nv.y * w0;
+            }
+          } else {
+            acc[0] = Vx;
+            acc[1] = Vy;
+            acc[2] = Vz;
+            acc[3] = ue * Vx;
+            acc[4] = ue * Vy;
+            acc[5] = ue * Vz;
+            acc[6] = ve * Vx;
+            acc[7] = ve * Vy;
+            acc[8] = ve * Vz;
+            acc[9] = w * gn0;
+            acc[10] = w * gn1;
+            acc[11] = w * gn2;
+            acc[12] = w * gr;
+            acc[13] = w * gg;
+            acc[14] = w * gbl;
+            acc[15] = g_o;
+          }
+        }
+      }
+      if (!POSE_ONLY) {
+        if (__ballot(contrib) != 0ull) {
+          const uint32_t id = sid[jj];
+          float* dst = gacc + (size_t)id * 16;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const float v = wave_sum(acc[k]);
+            if (lane == 0) atomicAdd(dst + k, v);
+          }
+        }
+      }
+    }
+  }
+  if (POSE_ONLY) {
+    float v[6] = {pr0, pr1, pr2, pp0, pp1, pp2};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float s = wave_sum(v[k]);
+      if (lane == 0) s_red[wave][k] = s;
+    }
+    __syncthreads();
+    if (t < 8) {
+      float s = 0.f;
+      if (t < 6)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += s_red[w][t];
+      part[(size_t)blockIdx.x * 8 + t] = s;
+    }
+  }
+}
+
+template <int TW, int TH>
+void fwd_shape(const BlendArgs& a, float* rgb, float* depth, float* normal, float* alpha, float* t_final,
+               uint32_t* last, hipStream_t s) {
+  const size_t lds = (size_t)a.batch * kRecF4 * sizeof(float4);
+  blend_fwd_kernel<TW, TH><<<a.n_tiles, TW * TH, lds, s>>>(a, rgb, depth, normal, alpha, t_final, last);
+}
+
+template <int TW, int TH, bool PO, bool HN, bool HO>
+void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, const float* g_rgb,
+                 const float* g_depth, const float* g_normal, const float* g_alpha, float* gacc, float* part,
+                 hipStream_t s) {
+  const size_t lds = (size_t)a.batch * (kRecF4 * sizeof(float4) + sizeof(uint32_t));
+  blend_bwd_kernel<TW, TH, PO, HN, HO><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, g_rgb, g_depth,
+                                                                       g_normal, g_alpha, gacc, part);
+}
+
+template <int TW, int TH>
+void bwd_shape(const BlendArgs& a, const float* t_final, const uint32_t* last, const float* g_rgb,
+               const float* g_depth, const float* g_normal, const float* g_alpha, float* gacc, float* part,
+               hipStream_t s) {
+  const bool po = gacc == nullptr, hn = g_normal != nullptr, ho = g_alpha != nullptr;
+#define GS2D_BWD(PO, HN, HO) \
+  bwd_variant<TW, TH, PO, HN, HO>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s)
+  if (po) {
+    if (hn && ho) GS2D_BWD(true, true, true);
+    else if (hn) GS2D_BWD(true, true, false);
+    else if (ho) GS2D_BWD(true, false, true);
+    else GS2D_BWD(true, false, false);
+  } else {
+    if (hn && ho) GS2D_BWD(false, true, true);
+    else if (hn) GS2D_BWD(false, true, false);
+    else if (ho) GS2D_BWD(false, false, true);
+    else GS2D_BWD(false, false, false);
+  }
+#undef GS2D_BWD
+}
+
+}  // namespace
+
+void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* rgb, float* depth, float* normal,
+                      float* alpha, float* t_final, uint32_t* last, hipStream_t s) {
+  if (tile_w == 8 && tile_h == 8) fwd_shape<8, 8>(a, rgb, depth, normal, alpha, t_final, last, s);
+  else if (tile_w == 16 && tile_h == 8) fwd_shape<16, 8>(a, rgb, depth, normal, alpha, t_final, last, s);
+  else if (tile_w == 32 && tile_h == 16) fwd_shape<32, 16>(a, rgb, depth, normal, alpha, t_final, last, s);
+  else fwd_shape<16, 16>(a, rgb, depth, normal, alpha, t_final, last, s);
+}
+
+void launch_blend_bwd(const BlendArgs& a, int tile_w, int tile_h, const float* t_final, const uint32_t* last,
+                      const float* g_rgb, const float* g_depth, const float* g_normal, const float* g_alpha,
+                      float* gacc, float* part, hipStream_t s) {
+  if (tile_w == 8 && tile_h == 8)
+    bwd_shape<8, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+  else if (tile_w == 16 && tile_h == 8)
+    bwd_shape<16, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+  else if (tile_w == 32 && tile_h == 16)
+    bwd_shape<32, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+  else
+    bwd_shape<16, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+}
+
+}  // namespace gs2d

@@ -1,0 +1,223 @@
+// Tracking loss with its image gradients, partial-sum reductions, and the pose step.
+//
+// Tracking loss (Sec. "Tracking and Keyframe Selection", eq:LD, eq:normal_mask,
+// eq:opacity_mask, eq:tracking_loss), one lane per pixel:
+//   L = (1/HW) sum_p M_n M_o (|rgb - I|_1 + lambda_d |D - D_obs|),
+//   M_n = [N . r > 0] (the sign does not depend on normalising the ray, so the
+//   ray (x - cx)/fx, (y - cy)/fy, 1 is used), M_o = [O > 0.95].
+// Gradients hold the masks fixed and take d|x|/dx = sign(x) (0 at 0).  Each
+// workgroup writes one partial sum; a single workgroup adds them in a fixed order.
+//
+// Pose step (Sec. "Tracking and Keyframe Selection": AdamW on the camera pose with
+// the surfels frozen).  The step variable is the left-perturbation twist tau,
+// which is zero before every step, so decoupled weight decay has no effect:
+//   m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+//   tau = -lr m/(1-b1^t) / (sqrt(v/(1-b2^t)) + eps),  T <- Exp(tau) T.
+// Exp on SE(3) is the closed form R = I + sin(th)/th K + (1-cos th)/th^2 K^2,
+// t = J rho with J = I + (1-cos th)/th^2 K + (th - sin th)/th^3 K^2 (Barfoot,
+// "State Estimation for Robotics", Sec. 7.1), evaluated in FP64 on a master copy
+// of the pose so that repeated steps do not drift off SO(3).
+#include "gs2d_internal.h"
+
+namespace gs2d {
+namespace {
+
+constexpr int kLossThreads = 256;
+
+__global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(
+    CamF cam, const float* __restrict__ rgb, const float* __restrict__ depth,
+    const float* __restrict__ normal, const float* __restrict__ alpha, const float* __restrict__ tgt_rgb,
+    const float* __restrict__ tgt_depth, float lambda_d, int use_masks, float* __restrict__ d_rgb,
+    float* __restrict__ d_depth, float* __restrict__ part) {
+  const int HW = cam.width * cam.height;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.f;
+  if (p < HW) {
+    const int y = p / cam.width, x = p - y * cam.width;
+    bool m = true;
+    if (use_masks) {
+      const float xh = ((float)x - cam.cx) / cam.fx, yh = ((float)y - cam.cy) / cam.fy;
+      const float ndr = fmaf(normal[p], xh, fmaf(normal[HW + p], yh, normal[2 * HW + p]));
+      m = (ndr > 0.0f) && (alpha[p] > kOpacityMask);
+    }
+    const float inv = 1.0f / (float)HW;
+    const float d0 = rgb[p] - tgt_rgb[p];
+    const float d1 = rgb[HW + p] - tgt_rgb[HW + p];
+    const float d2 = rgb[2 * HW + p] - tgt_rgb[2 * HW + p];
+    const float dd = depth[p] - tgt_depth[p];
+    auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
+    if (m) {
+      l = fabsf(d0) + fabsf(d1) + fabsf(d2) + lambda_d * fabsf(dd);
+      d_rgb[p] = sgn(d0) * inv;
+      d_rgb[HW + p] = sgn(d1) * inv;
+      d_rgb[2 * HW + p] = sgn(d2) * inv;
+      d_depth[p] = lambda_d * sgn(dd) * inv;
+    } else {
+      d_rgb[p] = 0.f;
+      d_rgb[HW + p] = 0.f;
+      d_rgb[2 * HW + p] = 0.f;
+      d_depth[p] = 0.f;
+    }
+  }
+  __shared__ float red[kLossThreads];
+  red[threadIdx.x] = l;
+  __syncthreads();
+  for (int s = kLossThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Sum n rows of `stride` floats, column k, in a fixed order (64 lanes, then a
+// butterfly): deterministic for a given n.
+__device__ inline double sum_parts(const float* part, int n, int stride, int k) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) s += (double)part[(size_t)i * stride + k];
+  return wave_sum_d(s);
+}
+
+__global__ void reduce_loss_kernel(const float* __restrict__ part, int n, float inv_hw, float* __restrict__ loss,
+                                   Ctrl* __restrict__ ctrl) {
+  const double s = sum_parts(part, n, 1, 0) * (double)inv_hw;
+  if (threadIdx.x == 0) {
+    if (loss) *loss = (float)s;
+    if (ctrl) ctrl->loss = s;
+  }
+}
+
+__global__ void reduce_pose_kernel(const float* __restrict__ part, int n, float* __restrict__ d_pose,
+                                   int accumulate) {
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = sum_parts(part, n, 8, k);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d_pose[k] = accumulate ? d_pose[k] + (float)g[k] : (float)g[k];
+  }
+}
+
+__global__ void track_init_kernel(const float* __restrict__ pose, Ctrl* __restrict__ ctrl) {
+  const int t = threadIdx.x;
+  if (t < 12) ctrl->master_pose[t] = (double)pose[t];
+  if (t < 6) {
+    ctrl->adam_m[t] = 0.0;
+    ctrl->adam_v[t] = 0.0;
+  }
+  if (t == 0) {
+    ctrl->iter = 0;
+    ctrl->loss = 0.0;
+  }
+}
+
+__device__ void se3_exp(const double tau[6], double R[9], double tt[3]) {
+  const double px = tau[3], py = tau[4], pz = tau[5];
+  const double th2 = px * px + py * py + pz * pz;
+  const double th = sqrt(th2);
+  double A, B, C;  // R = I + A K + B K^2,  J = I + B K + C K^2
+  if (th < 1e-6) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = sin(th) / th;
+    B = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double K[9] = {0.0, -pz, py, pz, 0.0, -px, -py, px, 0.0};
+  double K2[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      K2[r * 3 + c] = K[r * 3 + 0] * K[0 * 3 + c] + K[r * 3 + 1] * K[1 * 3 + c] + K[r * 3 + 2] * K[2 * 3 + c];
+  double J[9];
+  for (int k = 0; k < 9; ++k) {
+    const double I = (k % 4 == 0) ? 1.0 : 0.0;
+    R[k] = I + A * K[k] + B * K2[k];
+    J[k] = I + B * K[k] + C * K2[k];
+  }
+  for (int r = 0; r < 3; ++r) tt[r] = J[r * 3 + 0] * tau[0] + J[r * 3 + 1] * tau[1] + J[r * 3 + 2] * tau[2];
+}
+
+__global__ void pose_step_kernel(const float* __restrict__ pose_part, int n_pose_parts,
+                                 const float* __restrict__ loss_part, int n_loss_parts, float inv_hw,
+                                 AdamArgs adam, float* __restrict__ pose, Ctrl* __restrict__ ctrl,
+                                 float* __restrict__ pose_history, float* __restrict__ loss_history,
+                                 int max_hist) {
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = sum_parts(pose_part, n_pose_parts, 8, k);
+  const double loss = loss_part ? sum_parts(loss_part, n_loss_parts, 1, 0) * (double)inv_hw : 0.0;
+  if (threadIdx.x != 0) return;
+  const uint32_t it = ctrl->iter;
+  ctrl->loss = loss;
+  if (loss_history && (int)it < max_hist) loss_history[it] = (float)loss;
+  const double t = (double)it + 1.0;
+  const double b1 = adam.beta1, b2 = adam.beta2;
+  const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+  double tau[6];
+  for (int k = 0; k < 6; ++k) {
+    const double m = b1 * ctrl->adam_m[k] + (1.0 - b1) * g[k];
+    const double v = b2 * ctrl->adam_v[k] + (1.0 - b2) * g[k] * g[k];
+    ctrl->adam_m[k] = m;
+    ctrl->adam_v[k] = v;
+    tau[k] = -(double)adam.lr[k] * (m / c1) / (sqrt(v / c2) + (double)adam.eps);
+  }
+  double Re[9], te[3];
+  se3_exp(tau, Re, te);
+  double* T = ctrl->master_pose;
+  double Tn[12];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 4; ++c) {
+      double s = Re[r * 3 + 0] * T[0 * 4 + c] + Re[r * 3 + 1] * T[1 * 4 + c] + Re[r * 3 + 2] * T[2 * 4 + c];
+      if (c == 3) s += te[r];
+      Tn[r * 4 + c] = s;
+    }
+  }
+  for (int k = 0; k < 12; ++k) {
+    T[k] = Tn[k];
+    pose[k] = (float)Tn[k];
+    if (pose_history && (int)it < max_hist) pose_history[(size_t)it * 12 + k] = (float)Tn[k];
+  }
+  ctrl->iter = it + 1;
+}
+
+}  // namespace
+
+int loss_blocks(int hw) { return (hw + kLossThreads - 1) / kLossThreads; }
+
+void launch_tracking_loss(CamF cam, const float* rgb, const float* depth, const float* normal,
+                          const float* alpha, const float* tgt_rgb, const float* tgt_depth, float lambda_d,
+                          int use_masks, float* d_rgb, float* d_depth, float* part, int* n_parts,
+                          hipStream_t s) {
+  const int nb = loss_blocks(cam.width * cam.height);
+  tracking_loss_kernel<<<nb, kLossThreads, 0, s>>>(cam, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d,
+                                                   use_masks, d_rgb, d_depth, part);
+  if (n_parts) *n_parts = nb;
+}
+
+void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, Ctrl* ctrl, hipStream_t s) {
+  reduce_loss_kernel<<<1, 64, 0, s>>>(part, n_parts, inv_hw, loss, ctrl);
+}
+
+void launch_reduce_pose(const float* part, int n_parts, float* d_pose, int accumulate, hipStream_t s) {
+  reduce_pose_kernel<<<1, 64, 0, s>>>(part, n_parts, d_pose, accumulate);
+}
+
+void launch_track_init(const float* pose, Ctrl* ctrl, hipStream_t s) {
+  track_init_kernel<<<1, 64, 0, s>>>(pose, ctrl);
+}
+
+void launch_pose_step(const float* pose_part, int n_pose_parts, const float* loss_part, int n_loss_parts,
+                      float inv_hw, AdamArgs adam, float* pose, Ctrl* ctrl, float* pose_history,
+                      float* loss_history, int max_hist, hipStream_t s) {
+  pose_step_kernel<<<1, 64, 0, s>>>(pose_part, n_pose_parts, loss_part, n_loss_parts, inv_hw, adam, pose, ctrl,
+                                    pose_history, loss_history, max_hist);
+}
+
+}  // namespace gs2d

@@ -1,0 +1,252 @@
+// Per-surfel preprocessing (forward) and its reverse mode with the pose reduction.
+//
+// Forward, one thread per surfel (Sec. "2D Gaussian Splatting", eq:hc and eq:wth):
+// camera-frame centre and tangents, the homography M = K [s_u t_uc | s_v t_vc | mu_c],
+// culling, the screen box of the 3-sigma ellipse (dual conic M diag(9,9,-1) M^T)
+// united with the low-pass disc, its tile rectangle, the float32 depth key, and the
+// 96-byte blend record.  The kernel is bound by HBM traffic (60 B in, about 110 B
+// out per surfel), so it computes in FP64 at no cost and rounds once at the end:
+// the depth keys then agree bit for bit with a double-precision reference.
+//
+// Reverse, one thread per surfel (Sec. "Camera Pose Optimization"): the blend
+// backward leaves per surfel the camera-frame gradients g_mu_c, g_a, g_b
+// (a = s_u t_uc, b = s_v t_vc), g_n (normal), g_rgb and g_o.  From them:
+// dL/dt_uc = s_u g_a + t_vc x g_n, dL/dt_vc = s_v g_b + g_n x t_uc,
+// dL/ds_u = t_uc . g_a, dL/ds_v = t_vc . g_b; world-frame gradients are R^T of the
+// camera-frame ones.  The pose gradient is eq:derivatives:
+// rho += g_mu_c, phi += mu_c x g_mu_c + t_uc x (s_u g_a) + t_vc x (s_v g_b) + n x g_n,
+// reduced per block into partial sums.
+#include "gs2d_internal.h"
+
+namespace gs2d {
+namespace {
+
+__global__ __launch_bounds__(256) void preprocess_kernel(
+    const float* __restrict__ P, int n, const float* __restrict__ pose, CamF cam, float z_near,
+    int filter, int tile_w, int tile_h, float4* __restrict__ rec,
+    uint2* __restrict__ rect, uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
+    uint32_t* __restrict__ dval, float* __restrict__ saved_pose) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 12 && saved_pose) saved_pose[i] = pose[i];
+  if (i >= n) return;
+  double R[9], t[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    R[r * 3 + 0] = pose[r * 4 + 0];
+    R[r * 3 + 1] = pose[r * 4 + 1];
+    R[r * 3 + 2] = pose[r * 4 + 2];
+    t[r] = pose[r * 4 + 3];
+  }
+  double mu[3], tu[3], tv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = P[(size_t)(0 + c) * n + i];
+    tu[c] = P[(size_t)(3 + c) * n + i];
+    tv[c] = P[(size_t)(6 + c) * n + i];
+  }
+  const double su = P[(size_t)9 * n + i], sv = P[(size_t)10 * n + i];
+  double mc[3], uc[3], vc[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    mc[r] = R[r * 3 + 0] * mu[0] + R[r * 3 + 1] * mu[1] + R[r * 3 + 2] * mu[2] + t[r];
+    uc[r] = R[r * 3 + 0] * tu[0] + R[r * 3 + 1] * tu[1] + R[r * 3 + 2] * tu[2];
+    vc[r] = R[r * 3 + 0] * tv[0] + R[r * 3 + 1] * tv[1] + R[r * 3 + 2] * tv[2];
+  }
+  dval[i] = (uint32_t)i;
+  const double a[3] = {su * uc[0], su * uc[1], su * uc[2]};
+  const double b[3] = {sv * vc[0], sv * vc[1], sv * vc[2]};
+  // homography rows: M0 = fx col.x + cx col.z, M1 = fy col.y + cy col.z, M2 = col.z
+  const double* col[3] = {a, b, mc};
+  double M0[3], M1[3], m[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    M0[j] = (double)cam.fx * col[j][0] + (double)cam.cx * col[j][2];
+    M1[j] = (double)cam.fy * col[j][1] + (double)cam.cy * col[j][2];
+    m[j] = col[j][2];
+  }
+  bool vis = mc[2] > (double)z_near;
+  // C*_22 = 9 (m0^2 + m1^2) - m2^2 < 0  <=>  the 3-sigma disk is wholly in front of z = 0
+  const double c22 = 9.0 * (m[0] * m[0] + m[1] * m[1]) - m[2] * m[2];
+  vis = vis && (c22 < 0.0);
+  uint32_t cnt = 0;
+  uint2 rc = make_uint2(1u, 0u);
+  double bx0 = 0, bx1 = -1, by0 = 0, by1 = -1;
+  if (vis) {
+    // dual conic entries needed for the box: C00, C11, C02, C12 (and C22)
+    const double c00 = 9.0 * (M0[0] * M0[0] + M0[1] * M0[1]) - M0[2] * M0[2];
+    const double c11 = 9.0 * (M1[0] * M1[0] + M1[1] * M1[1]) - M1[2] * M1[2];
+    const double c02 = 9.0 * (M0[0] * m[0] + M0[1] * m[1]) - M0[2] * m[2];
+    const double c12 = 9.0 * (M1[0] * m[0] + M1[1] * m[1]) - M1[2] * m[2];
+    const double ex = c02 / c22, ey = c12 / c22;
+    const double hx = sqrt(fmax(0.0, ex * ex - c00 / c22));
+    const double hy = sqrt(fmax(0.0, ey * ey - c11 / c22));
+    double x0 = ex - hx, x1 = ex + hx, y0 = ey - hy, y1 = ey + hy;
+    if (filter) {
+      const double pcx = M0[2] / m[2], pcy = M1[2] / m[2];
+      const double rr = sqrt((double)kRhoCutoff / (double)kFilterScale);
+      x0 = fmin(x0, pcx - rr);
+      x1 = fmax(x1, pcx + rr);
+      y0 = fmin(y0, pcy - rr);
+      y1 = fmax(y1, pcy + rr);
+    }
+    // one pixel of slack, clipped to the image
+    bx0 = fmax(floor(x0 - 1.0), 0.0);
+    bx1 = fmin(ceil(x1 + 1.0), (double)(cam.width - 1));
+    by0 = fmax(floor(y0 - 1.0), 0.0);
+    by1 = fmin(ceil(y1 + 1.0), (double)(cam.height - 1));
+    if (bx0 <= bx1 && by0 <= by1) {
+      const int tx0 = (int)bx0 / tile_w, tx1 = (int)bx1 / tile_w;
+      const int ty0 = (int)by0 / tile_h, ty1 = (int)by1 / tile_h;
+      cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+      rc = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+    }
+  }
+  count[i] = cnt;
+  if (cnt == 0) {
+    rect[i] = make_uint2(1u, 0u);  // x0 = 1 > x1 = 0: empty
+    dkey[i] = 0xFFFFFFFFu;
+    return;
+  }
+  rect[i] = rc;
+  dkey[i] = __float_as_uint((float)mc[2]);
+  // centre-relative homography rows (see gs2d_internal.h)
+  const double pcx = M0[2] / m[2], pcy = M1[2] / m[2];
+  const double P0 = M0[0] - pcx * m[0], P1 = M0[1] - pcx * m[1];
+  const double Q0 = M1[0] - pcy * m[0], Q1 = M1[1] - pcy * m[1];
+  const double Dt = P0 * Q1 - P1 * Q0;
+  const double k0 = m[0] * Q1 - m[1] * Q0;
+  const double k1 = P0 * m[1] - P1 * m[0];
+  const double nn[3] = {uc[1] * vc[2] - uc[2] * vc[1], uc[2] * vc[0] - uc[0] * vc[2],
+                        uc[0] * vc[1] - uc[1] * vc[0]};
+  float4* r = rec + (size_t)i * kRecF4;
+  r[0] = make_float4((float)bx0, (float)bx1, (float)by0, (float)by1);
+  r[1] = make_float4((float)pcx, (float)pcy, (float)Dt, (float)k0);
+  r[2] = make_float4((float)k1, (float)P0, (float)P1, (float)Q0);
+  r[3] = make_float4((float)Q1, (float)m[0], (float)m[1], (float)m[2]);
+  r[4] = make_float4(P[(size_t)11 * n + i], P[(size_t)12 * n + i], P[(size_t)13 * n + i],
+                     P[(size_t)14 * n + i]);
+  r[5] = make_float4((float)nn[0], (float)nn[1], (float)nn[2], 0.0f);
+}
+
+__device__ inline void cross3(const float* a, const float* b, float* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__global__ __launch_bounds__(256) void preprocess_bwd_kernel(
+    const float* __restrict__ P, int n, const float* __restrict__ pose,
+    const float* __restrict__ gacc, float* __restrict__ d_params, int accumulate,
+    float* __restrict__ part) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float pr[6] = {0, 0, 0, 0, 0, 0};
+  if (i < n) {
+    float R[9], t[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      R[r * 3 + 0] = pose[r * 4 + 0];
+      R[r * 3 + 1] = pose[r * 4 + 1];
+      R[r * 3 + 2] = pose[r * 4 + 2];
+      t[r] = pose[r * 4 + 3];
+    }
+    float mu[3], tu[3], tv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      mu[c] = P[(size_t)(0 + c) * n + i];
+      tu[c] = P[(size_t)(3 + c) * n + i];
+      tv[c] = P[(size_t)(6 + c) * n + i];
+    }
+    const float su = P[(size_t)9 * n + i], sv = P[(size_t)10 * n + i];
+    float mc[3], uc[3], vc[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      mc[r] = R[r * 3 + 0] * mu[0] + R[r * 3 + 1] * mu[1] + R[r * 3 + 2] * mu[2] + t[r];
+      uc[r] = R[r * 3 + 0] * tu[0] + R[r * 3 + 1] * tu[1] + R[r * 3 + 2] * tu[2];
+      vc[r] = R[r * 3 + 0] * tv[0] + R[r * 3 + 1] * tv[1] + R[r * 3 + 2] * tv[2];
+    }
+    const float4* g4 = reinterpret_cast<const float4*>(gacc + (size_t)i * 16);
+    const float4 A = g4[0], B = g4[1], C = g4[2], D = g4[3];
+    const float gmu[3] = {A.x, A.y, A.z};
+    const float ga[3] = {A.w, B.x, B.y};
+    const float gb[3] = {B.z, B.w, C.x};
+    const float gn[3] = {C.y, C.z, C.w};
+    const float grgb[3] = {D.x, D.y, D.z};
+    const float go = D.w;
+    float tmp[3], gtu[3], gtv[3];
+    cross3(vc, gn, tmp);
+    for (int c = 0; c < 3; ++c) gtu[c] = su * ga[c] + tmp[c];
+    cross3(gn, uc, tmp);
+    for (int c = 0; c < 3; ++c) gtv[c] = sv * gb[c] + tmp[c];
+    const float gsu = uc[0] * ga[0] + uc[1] * ga[1] + uc[2] * ga[2];
+    const float gsv = vc[0] * gb[0] + vc[1] * gb[1] + vc[2] * gb[2];
+    float out[15];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      out[0 + c] = R[0 * 3 + c] * gmu[0] + R[1 * 3 + c] * gmu[1] + R[2 * 3 + c] * gmu[2];
+      out[3 + c] = R[0 * 3 + c] * gtu[0] + R[1 * 3 + c] * gtu[1] + R[2 * 3 + c] * gtu[2];
+      out[6 + c] = R[0 * 3 + c] * gtv[0] + R[1 * 3 + c] * gtv[1] + R[2 * 3 + c] * gtv[2];
+      out[12 + c] = grgb[c];
+    }
+    out[9] = gsu;
+    out[10] = gsv;
+    out[11] = go;
+    if (d_params) {
+#pragma unroll
+      for (int k = 0; k < 15; ++k) {
+        float* dst = d_params + (size_t)k * n + i;
+        *dst = accumulate ? *dst + out[k] : out[k];
+      }
+    }
+    // eq:derivatives, left perturbation: [I, -mu_c^x] and [0, -R_c[:,k]^x]
+    float gcu[3], gcv[3], c1[3], c2[3], c3[3], c4[3];
+    for (int c = 0; c < 3; ++c) {
+      gcu[c] = su * ga[c];
+      gcv[c] = sv * gb[c];
+    }
+    const float nn[3] = {uc[1] * vc[2] - uc[2] * vc[1], uc[2] * vc[0] - uc[0] * vc[2],
+                         uc[0] * vc[1] - uc[1] * vc[0]};
+    cross3(mc, gmu, c1);
+    cross3(uc, gcu, c2);
+    cross3(vc, gcv, c3);
+    cross3(nn, gn, c4);
+    for (int c = 0; c < 3; ++c) {
+      pr[c] = gmu[c];
+      pr[3 + c] = c1[c] + c2[c] + c3[c] + c4[c];
+    }
+  }
+  // block reduction of the six pose terms (fixed order: deterministic)
+  __shared__ float red[256][6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[threadIdx.x][k] = pr[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) red[threadIdx.x][k] += red[threadIdx.x + s][k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[(size_t)blockIdx.x * 8 + threadIdx.x] = red[0][threadIdx.x];
+  if (threadIdx.x == 6 || threadIdx.x == 7) part[(size_t)blockIdx.x * 8 + threadIdx.x] = 0.0f;
+}
+
+}  // namespace
+
+void launch_preprocess(const float* params, int n, const float* pose, CamF cam, float z_near, int filter,
+                       int tile_w, int tile_h, int tiles_x, int tiles_y, float4* rec, uint2* rect,
+                       uint32_t* count, uint32_t* dkey, uint32_t* dval, float* saved_pose,
+                       hipStream_t s) {
+  const int grid = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
+  (void)tiles_x;
+  (void)tiles_y;
+  preprocess_kernel<<<grid, 256, 0, s>>>(params, n, pose, cam, z_near, filter, tile_w, tile_h, rec, rect,
+                                         count, dkey, dval, saved_pose);
+}
+
+void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc,
+                           float* d_params, int accumulate, float* part, hipStream_t s) {
+  const int grid = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
+  preprocess_bwd_kernel<<<grid, 256, 0, s>>>(params, n, pose, gacc, d_params, accumulate, part);
+}
+
+}  // namespace gs2d

@@ -1,0 +1,323 @@
+// Scans, the stable LSD radix sort, pair duplication and tile ranges.
+//
+// The paper composites surfels "sorted by depth" per pixel (Sec. "2D Gaussian
+// Splatting", eq:alpha_blending).  The tile rasterizer realises that order with
+// two stable sorts: surfels by float32 camera depth (ties keep the index order),
+// then the (tile, surfel) pairs, emitted in that depth order, stably by tile.
+// Each tile's list is therefore ascending (depth, index), the order of the
+// per-pixel definition.
+//
+// Radix pass = three kernels over blocks of kScanItems keys:
+//   hist    per-block digit histogram (LDS atomics, one sub-histogram per wave)
+//   offsets one block, one thread per digit: exclusive prefix over blocks, then
+//           over digits, giving every (block, digit) its global output offset
+//   scatter per block, 8 rounds of 256 keys: a wave-level multi-split (ballots
+//           over the digit bits give each lane the mask of lanes holding the
+//           same digit), a per-digit prefix over the 4 waves in LDS, and the
+//           running per-digit offset across rounds keep the pass stable.
+// Kernels whose item count lives on the device read it and exit early, so a
+// capacity-sized launch can be captured in a graph.
+#include "gs2d_internal.h"
+
+namespace gs2d {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRounds = kScanItems / kThreads;  // 8
+constexpr int kDigits = 256;
+constexpr int kWaves = kThreads / 64;
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void fill_f32_kernel(float* p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void copy_u32_kernel(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // Hillis-Steele over 256 threads in LDS; sh has 256 entries.
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    uint32_t x = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  if (total) *total = sh[kThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__device__ inline uint32_t load_count(const uint32_t* count, const uint32_t* perm, int i, int n) {
+  if (i >= n) return 0u;
+  return perm ? count[perm[i]] : count[i];
+}
+
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ count,
+                                                               const uint32_t* __restrict__ perm, int n,
+                                                               uint32_t* __restrict__ block_sums) {
+  __shared__ uint32_t sh[kThreads];
+  const int base = blockIdx.x * kScanItems + threadIdx.x * kRounds;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k) s += load_count(count, perm, base + k, n);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint32_t* __restrict__ block_sums, int nb,
+                                                               Ctrl* __restrict__ ctrl) {
+  // one block: exclusive scan of nb block sums, in chunks of 256
+  __shared__ uint32_t sh[kThreads];
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += kThreads) {
+    const int i = c0 + threadIdx.x;
+    const uint32_t v = i < nb ? block_sums[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(v, sh, &tot);
+    if (i < nb) block_sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ctrl->n_pairs = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_final_kernel(const uint32_t* __restrict__ count,
+                                                              const uint32_t* __restrict__ perm, int n,
+                                                              const uint32_t* __restrict__ block_sums,
+                                                              uint32_t* __restrict__ offs) {
+  __shared__ uint32_t sh[kThreads];
+  const int base = blockIdx.x * kScanItems + threadIdx.x * kRounds;
+  uint32_t v[kRounds];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k) {
+    v[k] = load_count(count, perm, base + k, n);
+    s += v[k];
+  }
+  uint32_t run = block_sums[blockIdx.x] + block_exclusive_scan(s, sh, nullptr);
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k) {
+    if (base + k < n) offs[base + k] = run;
+    run += v[k];
+  }
+}
+
+// Item count of a radix pass: the device count clamped to the buffer capacity
+// (`limit`), or `limit` itself when there is no device count.
+__device__ inline int64_t item_count(const uint32_t* n_dev, int64_t limit) {
+  if (!n_dev) return limit;
+  const int64_t n = (int64_t)(*n_dev);
+  return n < limit ? n : limit;
+}
+
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
+                                                              const uint32_t* __restrict__ n_dev,
+                                                              int64_t n_host, int shift, int bits,
+                                                              uint32_t* __restrict__ hist) {
+  const int64_t n = item_count(n_dev, n_host);
+  const int64_t base = (int64_t)blockIdx.x * kScanItems;
+  if (base >= n) return;
+  __shared__ uint32_t h[kWaves][kDigits];
+  const int wave = threadIdx.x / 64;
+  const uint32_t dmask = (1u << bits) - 1u;
+  for (int k = threadIdx.x; k < kWaves * kDigits; k += kThreads) (&h[0][0])[k] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = base + r * kThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & dmask], 1u);
+  }
+  __syncthreads();
+  const int d = threadIdx.x;
+  uint32_t s = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) s += h[w][d];
+  hist[(size_t)blockIdx.x * kDigits + d] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist,
+                                                                 const uint32_t* __restrict__ n_dev,
+                                                                 int64_t n_host) {
+  const int64_t n = item_count(n_dev, n_host);
+  const int nb = (int)((n + kScanItems - 1) / kScanItems);
+  __shared__ uint32_t sh[kThreads];
+  const int d = threadIdx.x;
+  uint32_t run = 0;
+  for (int b = 0; b < nb; ++b) {
+    const uint32_t c = hist[(size_t)b * kDigits + d];
+    hist[(size_t)b * kDigits + d] = run;
+    run += c;
+  }
+  const uint32_t base = block_exclusive_scan(run, sh, nullptr);
+  for (int b = 0; b < nb; ++b) hist[(size_t)b * kDigits + d] += base;
+}
+
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int shift,
+    int bits, const uint32_t* __restrict__ hist) {
+  const int64_t n = item_count(n_dev, n_host);
+  const int64_t base = (int64_t)blockIdx.x * kScanItems;
+  if (base >= n) return;
+  __shared__ uint32_t doff[kDigits];
+  __shared__ uint32_t wcnt[kWaves][kDigits];
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  doff[t] = hist[(size_t)blockIdx.x * kDigits + t];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRounds; ++r) {
+    for (int k = t; k < kWaves * kDigits; k += kThreads) (&wcnt[0][0])[k] = 0u;
+    __syncthreads();
+    const int64_t i = base + r * kThreads + t;
+    const bool valid = i < n;
+    uint32_t key = 0, val = 0, digit = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+      digit = (key >> shift) & ((1u << bits) - 1u);
+    }
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      const bool set = (digit >> b) & 1u;
+      const uint64_t bal = __ballot(valid && set);
+      peers &= set ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    {
+      uint32_t run = doff[t];
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w][t];
+        wcnt[w][t] = run;
+        run += c;
+      }
+      doff[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wcnt[wave][digit] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void duplicate_kernel(
+    const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ count,
+    const uint32_t* __restrict__ offs, const uint2* __restrict__ rect, int n, int tiles_x,
+    int64_t p_cap, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, Ctrl* __restrict__ ctrl) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t id = j < n ? sorted_ids[j] : 0u;
+  const uint32_t c = j < n ? count[id] : 0u;
+  // one atomic per wave for the visible-surfel counter
+  const uint64_t vis = __ballot(c > 0);
+  if (vis != 0ull && (threadIdx.x % 64) == (unsigned)(__ffsll((long long)vis) - 1))
+    atomicAdd(&ctrl->n_visible, (uint32_t)__popcll(vis));
+  if (c == 0) return;
+  uint32_t off = offs[j];
+  if ((int64_t)off + c > p_cap) {
+    ctrl->overflow = 1u;
+    return;
+  }
+  const uint2 rc = rect[id];
+  const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
+  for (uint32_t ty = ty0; ty <= ty1; ++ty)
+    for (uint32_t tx = tx0; tx <= tx1; ++tx) {
+      pkey[off] = ty * (uint32_t)tiles_x + tx;
+      pval[off] = id;
+      ++off;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ skey,
+                                                          const Ctrl* __restrict__ ctrl, int64_t p_cap,
+                                                          uint2* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t np = ctrl->n_pairs;
+  if (ctrl->overflow) np = 0;
+  if (np > p_cap) np = p_cap;
+  if (i >= np) return;
+  const uint32_t t = skey[i];
+  if (i == 0 || skey[i - 1] != t) ranges[t].x = (uint32_t)i;
+  if (i == np - 1 || skey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+__global__ void clear_ctrl_kernel(Ctrl* ctrl) {
+  if (threadIdx.x == 0) {
+    ctrl->n_visible = 0;
+    ctrl->overflow = 0;
+  }
+}
+
+inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per) > 0 ? (int)((n + per - 1) / per) : 1; }
+
+}  // namespace
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  fill_u32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(p, v, n);
+}
+void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  fill_f32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(p, v, n);
+}
+void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  copy_u32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(src, dst, n);
+}
+
+void launch_scan_counts(const uint32_t* count, const uint32_t* perm, int n, uint32_t* offs,
+                        uint32_t* block_sums, Ctrl* ctrl, hipStream_t s) {
+  const int nb = blocks_for(n, kScanItems);
+  clear_ctrl_kernel<<<1, 64, 0, s>>>(ctrl);
+  scan_reduce_kernel<<<nb, kThreads, 0, s>>>(count, perm, n, block_sums);
+  scan_blocks_kernel<<<1, kThreads, 0, s>>>(block_sums, nb, ctrl);
+  scan_final_kernel<<<nb, kThreads, 0, s>>>(count, perm, n, block_sums, offs);
+}
+
+int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host, const uint32_t* n_dev,
+               int bits, uint32_t* hist, hipStream_t s) {
+  const int nb = blocks_for(cap, kScanItems);
+  const int64_t limit = n_dev ? cap : n_host;
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    const int pb = (bits - shift) < 8 ? (bits - shift) : 8;
+    radix_hist_kernel<<<nb, kThreads, 0, s>>>(keys[cur], n_dev, limit, shift, pb, hist);
+    radix_offsets_kernel<<<1, kThreads, 0, s>>>(hist, n_dev, limit);
+    radix_scatter_kernel<<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev,
+                                                 limit, shift, pb, hist);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
+                      const uint2* rect, int n, int tiles_x, int64_t p_cap, uint32_t* pkey,
+                      uint32_t* pval, Ctrl* ctrl, hipStream_t s) {
+  duplicate_kernel<<<blocks_for(n, 256), 256, 0, s>>>(sorted_ids, count, offs, rect, n, tiles_x, p_cap, pkey,
+                                                      pval, ctrl);
+}
+
+void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
+                   hipStream_t s) {
+  launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)n_tiles, s);
+  ranges_kernel<<<blocks_for(p_cap, 256), 256, 0, s>>>(skey, ctrl, p_cap, ranges);
+}
+
+}  // namespace gs2d

@@ -1,0 +1,220 @@
+"""PyTorch-facing binding of the gfx950 rasterizer.
+
+PyTorch provides device memory and the stream; every step of the computation
+runs in libgs2d.so.  Argument checks here only guard the C ABI (shapes, dtype,
+device, contiguity).
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _camera(cam) -> _lib.Camera:
+    t = cam.as_tuple() if hasattr(cam, "as_tuple") else tuple(cam)
+    W, H, fx, fy, cx, cy = t
+    return _lib.Camera(int(W), int(H), float(fx), float(fy), float(cx), float(cy))
+
+
+def _dev_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, name, shape, device):
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+@dataclass
+class RenderOut:
+    rgb: torch.Tensor
+    depth: torch.Tensor
+    normal: torch.Tensor
+    alpha: torch.Tensor
+    generation: int
+
+
+class Rasterizer:
+    """One libgs2d context on one device (one context per stream; not thread safe)."""
+
+    def __init__(self, device: int | str | torch.device = 0, tile=(16, 16), batch: int = 256,
+                 filter: bool = True, z_near: float = 0.2, pair_capacity: int = 0,
+                 keep_unsorted: bool = False):
+        lib = _lib.load()
+        if isinstance(device, int):
+            idx = device
+        else:
+            idx = torch.device(device).index or 0
+        self.device = torch.device("cuda", idx)
+        opt = _lib.Options()
+        _lib.check(lib.gs2d_default_options(ctypes.byref(opt)))
+        opt.tile_w, opt.tile_h = int(tile[0]), int(tile[1])
+        opt.batch = int(batch)
+        opt.filter = 1 if filter else 0
+        opt.z_near = float(z_near)
+        opt.pair_capacity = int(pair_capacity)
+        opt.keep_unsorted = 1 if keep_unsorted else 0
+        self.options = opt
+        ctx = ctypes.c_void_p()
+        _lib.check(lib.gs2d_create(ctypes.byref(ctx), self.device.index, ctypes.byref(opt)))
+        self._ctx = ctx
+        self._lib = lib
+        self._last = None
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.gs2d_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    # ------------------------------------------------------------------ forward
+    def render(self, params: torch.Tensor, camera, pose: torch.Tensor, want=("rgb", "depth", "normal", "alpha")
+               ) -> RenderOut:
+        """Render [15, N] surfels at pose [12] (or [3, 4]); returns planar float32 images."""
+        cam = _camera(camera)
+        n = int(params.shape[1]) if params.ndim == 2 else -1
+        _check_tensor(params, "params", (15, n), self.device)
+        pose = pose.reshape(12) if pose.numel() == 12 else pose
+        _check_tensor(pose, "pose", (12,), self.device)
+        H, W = cam.height, cam.width
+        mk = lambda c: torch.empty((c, H, W) if c > 1 else (H, W), dtype=torch.float32, device=self.device)
+        rgb = mk(3) if "rgb" in want else None
+        depth = mk(1) if "depth" in want else None
+        normal = mk(3) if "normal" in want else None
+        alpha = mk(1) if "alpha" in want else None
+        gen = ctypes.c_uint32(0)
+        _lib.check(self._lib.gs2d_render(self._ctx, _dev_ptr(params), n, ctypes.byref(cam), _dev_ptr(pose),
+                                         _dev_ptr(rgb), _dev_ptr(depth), _dev_ptr(normal), _dev_ptr(alpha),
+                                         ctypes.byref(gen), self._stream()), self._ctx)
+        self._last = (params, pose, cam)  # keep the inputs alive until the backward
+        return RenderOut(rgb, depth, normal, alpha, int(gen.value))
+
+    # ----------------------------------------------------------------- backward
+    def backward(self, generation: int, d_rgb=None, d_depth=None, d_normal=None, d_alpha=None,
+                 params_grad: bool = True, d_params: torch.Tensor | None = None,
+                 d_pose: torch.Tensor | None = None, accumulate: bool = False):
+        """Reverse mode of the render with ``generation``; returns (d_params or None, d_pose [6])."""
+        if self._last is None:
+            raise _lib.Gs2dError(_lib.ERR_STATE, "no forward pass")
+        params, _, cam = self._last
+        H, W = cam.height, cam.width
+        _check_tensor(d_rgb, "d_rgb", (3, H, W), self.device)
+        _check_tensor(d_depth, "d_depth", (H, W), self.device)
+        _check_tensor(d_normal, "d_normal", (3, H, W), self.device)
+        _check_tensor(d_alpha, "d_alpha", (H, W), self.device)
+        if params_grad and d_params is None:
+            d_params = torch.empty_like(params)
+        if not params_grad:
+            d_params = None
+        _check_tensor(d_params, "d_params", tuple(params.shape), self.device)
+        if d_pose is None:
+            d_pose = torch.empty(6, dtype=torch.float32, device=self.device)
+        _check_tensor(d_pose, "d_pose", (6,), self.device)
+        flags = _lib.ACCUMULATE if accumulate else 0
+        _lib.check(self._lib.gs2d_render_backward(self._ctx, _dev_ptr(d_rgb), _dev_ptr(d_depth), _dev_ptr(d_normal),
+                                                  _dev_ptr(d_alpha), _dev_ptr(d_params), _dev_ptr(d_pose),
+                                                  ctypes.c_uint32(generation), flags, self._stream()), self._ctx)
+        return d_params, d_pose
+
+    # --------------------------------------------------------------------- loss
+    def tracking_loss(self, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d: float = 1.0,
+                      use_masks: bool = True):
+        """Returns (loss scalar tensor, d_rgb [3,H,W], d_depth [H,W])."""
+        cam = _camera(camera)
+        H, W = cam.height, cam.width
+        for t, nm, shp in ((rgb, "rgb", (3, H, W)), (depth, "depth", (H, W)), (tgt_rgb, "tgt_rgb", (3, H, W)),
+                           (tgt_depth, "tgt_depth", (H, W))):
+            _check_tensor(t, nm, shp, self.device)
+        if use_masks:
+            _check_tensor(normal, "normal", (3, H, W), self.device)
+            _check_tensor(alpha, "alpha", (H, W), self.device)
+        loss = torch.empty((), dtype=torch.float32, device=self.device)
+        d_rgb = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
+        d_depth = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        _lib.check(self._lib.gs2d_tracking_loss(self._ctx, ctypes.byref(cam), _dev_ptr(rgb), _dev_ptr(depth),
+                                                _dev_ptr(normal), _dev_ptr(alpha), _dev_ptr(tgt_rgb),
+                                                _dev_ptr(tgt_depth), float(lambda_d), 1 if use_masks else 0,
+                                                _dev_ptr(loss), _dev_ptr(d_rgb), _dev_ptr(d_depth),
+                                                self._stream()), self._ctx)
+        return loss, d_rgb, d_depth
+
+    # ----------------------------------------------------------------- tracking
+    def track(self, params, camera, pose, tgt_rgb, tgt_depth, n_iters: int, lr=(1e-3,) * 3 + (3e-3,) * 3,
+              lambda_d: float = 1.0, use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8,
+              weight_decay: float = 0.0, use_graph: bool = True, history: bool = True):
+        """Run ``n_iters`` tracking iterations in place on ``pose`` [12]; returns (pose, pose_hist, loss_hist)."""
+        cam = _camera(camera)
+        H, W = cam.height, cam.width
+        n = int(params.shape[1])
+        _check_tensor(params, "params", (15, n), self.device)
+        _check_tensor(pose, "pose", (12,), self.device)
+        _check_tensor(tgt_rgb, "tgt_rgb", (3, H, W), self.device)
+        _check_tensor(tgt_depth, "tgt_depth", (H, W), self.device)
+        ph = torch.zeros((max(n_iters, 1), 12), dtype=torch.float32, device=self.device) if history else None
+        lh = torch.zeros((max(n_iters, 1),), dtype=torch.float32, device=self.device) if history else None
+        a = _lib.TrackArgs()
+        a.params = params.data_ptr()
+        a.n = n
+        a.camera = cam
+        a.pose = pose.data_ptr()
+        a.tgt_rgb = tgt_rgb.data_ptr()
+        a.tgt_depth = tgt_depth.data_ptr()
+        a.lambda_d = float(lambda_d)
+        a.use_masks = 1 if use_masks else 0
+        a.n_iters = int(n_iters)
+        for k in range(6):
+            a.lr[k] = float(lr[k])
+        a.beta1, a.beta2 = float(betas[0]), float(betas[1])
+        a.eps = float(eps)
+        a.weight_decay = float(weight_decay)
+        a.use_graph = 1 if use_graph else 0
+        a.pose_history = ph.data_ptr() if ph is not None else None
+        a.loss_history = lh.data_ptr() if lh is not None else None
+        _lib.check(self._lib.gs2d_track(self._ctx, ctypes.byref(a), self._stream()), self._ctx)
+        return pose, ph, lh
+
+    # -------------------------------------------------------------- diagnostics
+    def counts(self) -> dict:
+        c = _lib.Counts()
+        _lib.check(self._lib.gs2d_get_counts(self._ctx, ctypes.byref(c), self._stream()), self._ctx)
+        return {k: getattr(c, k) for k, _ in _lib.Counts._fields_}
+
+    _DEBUG = {"tile_keys": (0, np.uint32), "tile_ids": (1, np.uint32), "ranges": (2, np.uint32),
+              "depth_keys": (3, np.uint32), "rect": (4, np.uint16), "t_final": (5, np.float32),
+              "last": (6, np.uint32), "unsorted_keys": (7, np.uint32), "unsorted_ids": (8, np.uint32),
+              "depth_ids": (9, np.uint32)}
+
+    def debug(self, what: str) -> np.ndarray:
+        which, dt = self._DEBUG[what]
+        size = ctypes.c_size_t(0)
+        r = self._lib.gs2d_debug_copy(self._ctx, which, None, ctypes.byref(size), self._stream())
+        if r not in (_lib.OK, _lib.ERR_INVALID_ARG):
+            _lib.check(r, self._ctx)
+        buf = np.empty(size.value // np.dtype(dt).itemsize, dtype=dt)
+        _lib.check(self._lib.gs2d_debug_copy(self._ctx, which, buf.ctypes.data_as(ctypes.c_void_p),
+                                             ctypes.byref(size), self._stream()), self._ctx)
+        return buf

@@ -1,0 +1,83 @@
+"""Shared helpers of the GPU parity tests: inputs, tolerances and exclusion masks."""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import synth
+
+ROOM_CAM = synth.Camera(640, 480, 525.0, 525.0, 320.0, 240.0)
+MARGIN = 1e-5            # pixels closer than this (relative) to a decision are excluded
+MAX_EXCLUDED = 1e-3      # ... and may be at most 0.1 % of the image
+
+
+def dev(a, device="cuda:0"):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32))).to(device)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def room_scene(n=300_000, seed=0, cam_seed=0):
+    room = synth.make_room(n, seed=seed)
+    pose = synth.room_camera(room, seed=cam_seed)
+    return room, pose
+
+
+def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth", "normal", "alpha")):
+    """Parity of planar images with the tolerances of the method's parity bar.
+
+    colour and opacity: |d| <= 1e-4 absolute; depth: |d| <= 1e-4 max(|ref|, 1e-3);
+    normal (blended, unnormalised): |d| <= 1e-4 max(|ref|, 1e-3 O) component-wise,
+    where O is the pixel's opacity (a normal blended from unit vectors of
+    different directions cancels, so its error is relative to O, not to itself).
+    Pixels with a decision margin below MARGIN are excluded and counted.
+    """
+    keep = margin >= MARGIN
+    frac = 1.0 - keep.mean()
+    assert frac <= MAX_EXCLUDED, f"{frac:.4%} of pixels excluded by margin"
+    report = {"excluded_frac": float(frac)}
+    for k in what:
+        g, r = gpu[k], ref[k]
+        if k in ("rgb", "alpha"):
+            tol = 1e-4 + 0 * r
+        elif k == "depth":
+            tol = 1e-4 * np.maximum(np.abs(r), 1e-3)
+        else:
+            tol = 1e-4 * np.maximum(np.abs(r), 1e-3 * np.maximum(ref["alpha"][None], 1e-3))
+        err = np.abs(g - r)
+        bad = (err > tol) & (keep if err.ndim == 2 else keep[None])
+        report[k] = float(err[..., keep].max()) if keep.any() else 0.0
+        assert not bad.any(), f"{k}: {int(bad.sum())} values out of tolerance, worst {err[bad].max():.3g}"
+    return report
+
+
+GROUPS = {"mu": slice(0, 3), "t_u": slice(3, 6), "t_v": slice(6, 9), "s": slice(9, 11), "o": slice(11, 12),
+          "rgb": slice(12, 15)}
+
+
+def check_grads(gpu: np.ndarray, ref: np.ndarray, skip: np.ndarray | None = None, rel=1e-3, floor=1e-6):
+    """|d| <= rel |ref| + floor ||group||_inf per parameter group (surfels in `skip` excluded)."""
+    report = {}
+    keep = np.ones(ref.shape[1], dtype=bool) if skip is None else ~skip
+    for name, sl in GROUPS.items():
+        g, r = gpu[sl][:, keep], ref[sl][:, keep]
+        scale = np.abs(r).max() if r.size else 0.0
+        tol = rel * np.abs(r) + floor * scale
+        err = np.abs(g - r)
+        bad = err > tol
+        report[name] = float((err / np.maximum(np.abs(r), 1e-30)).max()) if r.size else 0.0
+        assert not bad.any(), (f"{name}: {int(bad.sum())}/{bad.size} out of tolerance; "
+                               f"worst abs {err[bad].max():.3g} at ref {r[bad][np.argmax(err[bad])]:.3g}, "
+                               f"scale {scale:.3g}")
+    return report
+
+
+def check_pose(gpu, ref, rel=1e-3, floor=1e-6):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    for sl in (slice(0, 3), slice(3, 6)):
+        g, r = gpu[sl], ref[sl]
+        tol = rel * np.abs(r) + floor * np.abs(r).max()
+        assert np.all(np.abs(g - r) <= tol), (g, r)

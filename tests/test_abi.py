@@ -1,0 +1,79 @@
+"""The C ABI library loads and exports every symbol include/gs2d.h declares (no GPU needed)."""
+
+import ctypes
+
+import pytest
+
+from paper_2506_00970_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _lib.declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_error_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert len(_lib.error_string(code)) >= 2
+    assert _lib.error_string(-99) == "unknown error code"
+
+
+def test_default_options(lib):
+    o = _lib.Options()
+    assert lib.gs2d_default_options(ctypes.byref(o)) == 0
+    assert (o.tile_w, o.tile_h, o.batch, o.filter) == (16, 16, 256, 1)
+    assert o.z_near == pytest.approx(0.2)
+    assert lib.gs2d_default_options(None) == _lib.ERR_INVALID_ARG
+
+
+def test_invalid_arguments_rejected_before_any_device_call(lib):
+    cam = _lib.Camera(64, 48, 60.0, 60.0, 32.0, 24.0)
+    assert lib.gs2d_create(None, 0, None) == _lib.ERR_INVALID_ARG
+    assert lib.gs2d_render(None, None, 0, ctypes.byref(cam), None, None, None, None, None, None, None) \
+        == _lib.ERR_INVALID_ARG
+    assert lib.gs2d_render_backward(None, None, None, None, None, None, None, 0, 0, None) == _lib.ERR_INVALID_ARG
+    assert lib.gs2d_track(None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.gs2d_get_counts(None, None, None) == _lib.ERR_INVALID_ARG
+    assert lib.gs2d_destroy(None) == 0
+    bad = _lib.Options()
+    lib.gs2d_default_options(ctypes.byref(bad))
+    bad.tile_w = 12
+    out = ctypes.c_void_p()
+    assert lib.gs2d_create(ctypes.byref(out), 0, ctypes.byref(bad)) == _lib.ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof and field offsets of the ctypes mirrors equal the C compiler's view of gs2d.h."""
+    import os
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gs2d_camera": _lib.Camera, "gs2d_options": _lib.Options, "gs2d_counts": _lib.Counts,
+               "gs2d_track_args": _lib.TrackArgs}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs2d.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    inc = os.path.dirname(_lib.HEADER_PATH)
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-D__HIP_PLATFORM_AMD__", "-I", inc, "-I", "/opt/rocm/include", str(src), "-o",
+                           str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
