@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: graph-captured 2DGS tracking iterations at 640x480 with 300k surfels on one MI355X.
+
+One step is one tracking iteration of the whole hot path: per-surfel preprocessing,
+the depth sort, scan and pair duplication, the tile sort and ranges, the forward
+blend of colour/depth/normal/opacity, the tracking loss with its masks, the
+pose-only backward blend with the se(3) pose reduction, and the AdamW + Exp pose
+step.  Inputs (a seeded synthetic 6x5x3 m room with 20 boxes, 300,000 surfels,
+the target RGB-D frame rendered at the ground-truth pose, a start pose 5 cm / 3 deg
+away) are resident in HBM before timing starts.
+
+Printed (one JSON line): iterations/s over the timed steps, ms to converge to
+1 cm / 0.5 deg from the same start, the roofline of the dominant kernel (timed
+with HIP events in an eager profiled pass of the same loop), and the FP64 CPU
+oracle's iterations/s on the host cores over a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd 2DGS iters/s @640x480, 300k surfels; ms to 1cm/0.5deg pose converge"
+LR = (1e-3, 1e-3, 1e-3, 3e-3, 3e-3, 3e-3)
+HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per
+# lane per clock; transcendental ops occupy 4 issue slots).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic VALU lane-ops per (pixel, surfel) pair inside the footprint, reached
+# before termination: forward intersection + Gaussian + opacity + 8-channel blend;
+# backward recompute + blend reverse + intersection reverse + pose terms.
+OPS_FWD_PAIR = 44
+OPS_BWD_PAIR = 110
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(room_params, cam, start, tgt_rgb, tgt_depth, budget_s=20.0):
+    """The FP64 oracle on the host: tracking iterations (render, loss, pose-only backward, step)."""
+    import numpy as np
+
+    import oracle
+    from oracle import loss as oloss
+
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    pose = start.astype(np.float64)
+    st = oloss.AdamState()
+    t0 = time.perf_counter()
+    iters = 0
+    while True:
+        o = oracle.render(room_params, cam, pose, nthreads=threads)
+        _, d_rgb, d_depth, _ = oloss.tracking_loss(o["rgb"], o["depth"], o["normal"], o["alpha"], tgt_rgb,
+                                                   tgt_depth, cam)
+        g = oracle.backward(room_params, cam, pose, d_rgb=d_rgb, d_depth=d_depth, nthreads=threads)
+        pose, _ = oloss.adamw_pose_step(pose, g["pose_paper"], st, LR)
+        iters += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or iters >= 50:
+            break
+    return {"value": iters / el, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"{iters} FP64 tracking iterations (render + loss + pose-only backward + AdamW step) "
+                      f"of the same 640x480 / 300k workload in {el:.1f} s on {threads} threads of "
+                      f"'{cpu_model()}' ({os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=300_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path: "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_00970_amd import Rasterizer
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    cam = synth.Camera(640, 480, 525.0, 525.0, 320.0, 240.0)
+    log("building the synthetic room")
+    room = synth.make_room(args.n, seed=args.seed)
+    pose_gt = synth.room_camera(room, seed=args.seed)
+    start = synth.perturb_pose(pose_gt, 0.05, 3.0, seed=args.seed + 1)
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+    r = Rasterizer(device=0, profile=True)
+    P = to_dev(room.params)
+    gt = to_dev(pose_gt.reshape(12))
+    tgt = r.render(P, cam, gt)
+    tgt_rgb, tgt_depth = tgt.rgb.clone(), tgt.depth.clone()
+    pose = to_dev(start.reshape(12))
+    start_dev = pose.clone()
+    torch.cuda.synchronize()
+
+    # convergence: 100 iterations from the start pose, pose history on the device
+    log("convergence run")
+    pose.copy_(start_dev)
+    _, ph, lh = r.track(P, cam, pose, tgt_rgb, tgt_depth, n_iters=100, lr=LR, use_graph=True)
+    torch.cuda.synchronize()
+    hist = ph.cpu().numpy().astype(np.float64)
+    conv_iter = None
+    errs = []
+    for i in range(hist.shape[0]):
+        e_t, e_r = synth.pose_error(hist[i].reshape(3, 4), pose_gt)
+        errs.append((e_t, e_r))
+        if conv_iter is None and e_t < 0.01 and e_r < 0.5:
+            conv_iter = i + 1
+
+    # warm-up and timed graph replays
+    log("warm-up")
+    pose.copy_(start_dev)
+    r.track(P, cam, pose, tgt_rgb, tgt_depth, n_iters=args.warmup, lr=LR, use_graph=True, history=False)
+    pose.copy_(start_dev)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    r.track(P, cam, pose, tgt_rgb, tgt_depth, n_iters=args.steps, lr=LR, use_graph=True, history=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_step = 1e3 * el / args.steps
+    value = args.steps / el
+
+    # eager profiled pass of the same loop: per-kernel HIP event times and work counters
+    log("profiled eager pass")
+    pose.copy_(start_dev)
+    torch.cuda.synchronize()
+    r.profile(reset=True)
+    r.track(P, cam, pose, tgt_rgb, tgt_depth, n_iters=args.profile_steps, lr=LR, use_graph=False, history=False)
+    prof = r.profile(reset=True)
+    counts = r.counts()
+    fam = prof["families"]
+    per_launch = {k: (v["ms"] / v["launches"] if v["launches"] else 0.0) for k, v in fam.items()}
+    dom = max(("blend_fwd", "blend_bwd"), key=lambda k: per_launch[k])
+    n_fwd = fam["blend_fwd"]["launches"]
+    n_bwd = fam["blend_bwd"]["launches"]
+    if dom == "blend_bwd":
+        units = prof["bwd_covering"] / max(n_bwd, 1)
+        ops = units * OPS_BWD_PAIR
+    else:
+        units = prof["fwd_covering"] / max(n_fwd, 1)
+        ops = units * OPS_FWD_PAIR
+    achieved = ops / (per_launch[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "units_per_launch": units, "ops_per_unit": OPS_BWD_PAIR if dom == "blend_bwd" else OPS_FWD_PAIR,
+                "avg_launch_ms": per_launch[dom]}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "tracking iteration (fwd + tracking loss + pose-only bwd + AdamW/Exp step), "
+                               "640x480 f=525, 300k-surfel synthetic room (6x5x3 m, 20 boxes), start 5 cm / 3 deg",
+                   "n_surfels": args.n, "width": 640, "height": 480, "tile": [16, 16], "graph": True,
+                   "room_seed": args.seed},
+        "ms_to_converge": (conv_iter * ms_step) if conv_iter else None,
+        "iters_to_converge": conv_iter,
+        "final_error_cm_deg": [100 * errs[-1][0], errs[-1][1]],
+        "roofline": roofline,
+        "kernels_ms_per_launch": per_launch,
+        "work": {"fwd_evaluated": prof["fwd_evaluated"] / max(n_fwd, 1),
+                 "fwd_covering": prof["fwd_covering"] / max(n_fwd, 1),
+                 "bwd_evaluated": prof["bwd_evaluated"] / max(n_bwd, 1),
+                 "bwd_covering": prof["bwd_covering"] / max(n_bwd, 1),
+                 "n_visible": counts["n_visible"], "n_pairs": counts["n_pairs"]},
+    }
+    if not args.no_cpu_baseline:
+        log("CPU baseline (FP64 oracle)")
+        out["cpu_baseline"] = cpu_baseline(room.params, cam, start, tgt_rgb.cpu().numpy().astype(np.float64),
+                                           tgt_depth.cpu().numpy().astype(np.float64))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,6 +82,8 @@ typedef struct gs2d_options {
   float z_near;              /* default 0.2: centre cull and per-pixel depth cut */
   int64_t pair_capacity;     /* tile-pair capacity; 0 (default): grow on demand */
   int32_t keep_unsorted;     /* 1: keep a copy of the pairs before the tile sort (tests) */
+  int32_t profile;           /* 1: time kernel families with HIP events and count blend work
+                                (calls outside graph capture only); see gs2d_get_profile */
 } gs2d_options;
 
 /* Counters of the last forward pass (gs2d_get_counts synchronises the stream). */
@@ -93,6 +95,17 @@ typedef struct gs2d_counts {
   int32_t overflow;          /* 1: the last render exceeded the capacity (outputs invalid) */
   int32_t n_tiles;
 } gs2d_counts;
+
+/* Kernel-family timings and blend work counters (options.profile = 1). */
+#define GS2D_PROFILE_FAMILIES 12
+typedef struct gs2d_profile {
+  double ms[GS2D_PROFILE_FAMILIES];          /* summed event time per family since the last reset */
+  int64_t launches[GS2D_PROFILE_FAMILIES];   /* timed calls per family */
+  int64_t fwd_evaluated;     /* (pixel, surfel) evaluations performed by the forward blend */
+  int64_t fwd_covering;      /* ... of which inside the footprint (rho <= 9, depth >= z_near) */
+  int64_t bwd_evaluated;     /* the same for the backward blend */
+  int64_t bwd_covering;
+} gs2d_profile;
 
 /* Arguments of gs2d_track: n_iters tracking iterations, each a forward render at the
  * current pose, the tracking loss against (tgt_rgb, tgt_depth), a pose-only backward
@@ -159,8 +172,25 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
                                 hipStream_t stream);
 
 /* Run the tracking loop described at gs2d_track_args (the pose update of Sec.
- * "Tracking and Keyframe Selection": AdamW on the pose, surfels frozen). */
+ * "Tracking and Keyframe Selection": AdamW on the pose, surfels frozen).  The
+ * first call sizes the pair buffers on the start pose (one synchronising render).
+ * With use_graph the iteration is captured once on a stream of the context and
+ * replayed; the instantiated graph is kept and reused by later calls with the same
+ * buffers and hyper-parameters.  Returns after the work has completed (the call
+ * synchronises).  On a pair overflow the loop restarts from the start pose with
+ * larger buffers (up to 3 attempts, then GS2D_ERR_CAPACITY). */
 GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* args, hipStream_t stream);
+
+/* pose_out = Exp(tau) pose_in for tau = (rho, phi) [6] and 3x4 poses [12] (device;
+ * pose_out may alias pose_in).  The left perturbation of the paper's manifold
+ * derivative (Sec. "Camera Pose Optimization"); Exp in closed form, FP64 inside. */
+GS2D_API int gs2d_pose_exp(gs2d_ctx* ctx, const float* tau, const float* pose_in, float* pose_out,
+                           hipStream_t stream);
+
+/* d_tau = J_l(tau)^T d_pose (device [6] each): pulls the left-perturbation gradient
+ * at Exp(tau) T back to tau, J_l the SE(3) left Jacobian (identity at tau = 0). */
+GS2D_API int gs2d_pose_tau_grad(gs2d_ctx* ctx, const float* tau, const float* d_pose, float* d_tau,
+                                hipStream_t stream);
 
 /* Counters of the last render; synchronises `stream`. */
 GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream);
@@ -176,6 +206,13 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
  * *bytes (host) is the buffer size in; the bytes copied out.  Synchronises `stream`. */
 GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes,
                              hipStream_t stream);
+
+/* Name of profile family i (0 <= i < GS2D_PROFILE_FAMILIES), NULL otherwise. */
+GS2D_API const char* gs2d_profile_family(int i);
+
+/* Collect the profile since the last reset (synchronises `stream`); reset != 0
+ * clears it afterwards.  GS2D_ERR_UNSUPPORTED unless options.profile = 1. */
+GS2D_API int gs2d_get_profile(gs2d_ctx* ctx, gs2d_profile* out, int32_t reset, hipStream_t stream);
 
 /* Last hipError_t recorded by the context (0 if none). */
 GS2D_API int gs2d_last_hip_error(gs2d_ctx* ctx);

@@ -31,12 +31,21 @@ class Camera(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("z_near", ctypes.c_float), ("pair_capacity", ctypes.c_int64),
-                ("keep_unsorted", ctypes.c_int32)]
+                ("keep_unsorted", ctypes.c_int32), ("profile", ctypes.c_int32)]
 
 
 class Counts(ctypes.Structure):
     _fields_ = [("n_surfels", ctypes.c_int64), ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("pair_capacity", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
+
+
+PROFILE_FAMILIES = 12
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * PROFILE_FAMILIES), ("launches", ctypes.c_int64 * PROFILE_FAMILIES),
+                ("fwd_evaluated", ctypes.c_int64), ("fwd_covering", ctypes.c_int64),
+                ("bwd_evaluated", ctypes.c_int64), ("bwd_covering", ctypes.c_int64)]
 
 
 class TrackArgs(ctypes.Structure):
@@ -69,6 +78,10 @@ _SIGS = {
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),
+    "gs2d_pose_exp": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "gs2d_pose_tau_grad": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "gs2d_profile_family": ([ctypes.c_int], ctypes.c_char_p),
+    "gs2d_get_profile": ([_P, ctypes.POINTER(Profile), ctypes.c_int32, _P], ctypes.c_int),
     "gs2d_last_hip_error": ([_P], ctypes.c_int),
     "gs2d_error_string": ([ctypes.c_int], ctypes.c_char_p),
 }

@@ -28,8 +28,19 @@ int fail_hip(gs2d_ctx* ctx, hipError_t e) {
     if (r_ != GS2D_OK) return r_; \
   } while (0)
 
+void invalidate_graph(gs2d_ctx* ctx) {
+  if (ctx->track_exec) (void)hipGraphExecDestroy(ctx->track_exec);
+  if (ctx->track_graph) (void)hipGraphDestroy(ctx->track_graph);
+  ctx->track_exec = nullptr;
+  ctx->track_graph = nullptr;
+  ctx->track_valid = false;
+}
+
+// Every workspace (re)allocation moves a buffer, so it also drops the cached
+// tracking graph, whose kernels hold the old addresses.
 template <class T>
 int realloc_dev(gs2d_ctx* ctx, T** p, int64_t count) {
+  invalidate_graph(ctx);
   if (*p) {
     (void)hipFree(*p);
     *p = nullptr;
@@ -44,6 +55,55 @@ int realloc_dev(gs2d_ctx* ctx, T** p, int64_t count) {
 }
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+const char* kFamilyNames[kNumFamilies] = {"preprocess", "depth_sort", "scan",     "duplicate",
+                                          "tile_sort",  "ranges",     "blend_fwd", "loss",
+                                          "blend_bwd",  "preprocess_bwd", "pose_step", "reduce"};
+
+// Records a HIP event pair around a kernel family on the launch stream when the
+// context profiles and the stream is not being captured.
+struct ProfScope {
+  gs2d_ctx* ctx = nullptr;
+  hipStream_t s = nullptr;
+  int idx = -1;
+  ProfScope(gs2d_ctx* c, int fam, hipStream_t st) {
+    if (!c->opt.profile) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    if (c->ev_used == c->ev_cap) {
+      const int cap = c->ev_cap ? 2 * c->ev_cap : 64;
+      auto* nev = new (std::nothrow) gs2d_ctx::EvPair[cap];
+      if (!nev) return;
+      for (int i = 0; i < c->ev_cap; ++i) nev[i] = c->ev[i];
+      for (int i = c->ev_cap; i < cap; ++i) {
+        nev[i].a = nev[i].b = nullptr;
+        if (hipEventCreate(&nev[i].a) != hipSuccess || hipEventCreate(&nev[i].b) != hipSuccess) {
+          (void)hipGetLastError();
+          delete[] nev;
+          return;
+        }
+      }
+      delete[] c->ev;
+      c->ev = nev;
+      c->ev_cap = cap;
+    }
+    idx = c->ev_used++;
+    c->ev[idx].fam = fam;
+    ctx = c;
+    s = st;
+    (void)hipEventRecord(c->ev[idx].a, st);
+  }
+  ~ProfScope() {
+    if (ctx) (void)hipEventRecord(ctx->ev[idx].b, s);
+  }
+};
+
+unsigned long long* work_ptr(gs2d_ctx* ctx, hipStream_t s) {
+  if (!ctx->opt.profile) return nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  return ctx->ctrl->work;
+}
 
 int stream_capturing(hipStream_t s, bool* cap) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -186,28 +246,51 @@ int render_impl(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ranges), 0u, 2 * (int64_t)n_tiles, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ctrl), 0u, 3, s);
   } else {
-    launch_preprocess(params, (int)n, pose, cf, ctx->opt.z_near, ctx->opt.filter, tw, th, tiles_x, tiles_y,
-                      ctx->rec, ctx->rect, ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, s);
-    const int dbuf = radix_sort(ctx->dkey, ctx->dval, n, n, nullptr, 32, ctx->hist, s);
+    {
+      ProfScope ps(ctx, kPre, s);
+      launch_preprocess(params, (int)n, pose, cf, ctx->opt.z_near, ctx->opt.filter, tw, th, tiles_x, tiles_y,
+                        ctx->rec, ctx->rect, ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, s);
+    }
+    int dbuf;
+    {
+      ProfScope ps(ctx, kDepthSort, s);
+      dbuf = radix_sort(ctx->dkey, ctx->dval, n, n, nullptr, 32, ctx->hist, s);
+    }
     if (dbuf != 0) return GS2D_ERR_HIP;  // four 8-bit passes end in buffer 0
-    launch_scan_counts(ctx->count, ctx->dval[0], (int)n, ctx->offs, ctx->block_sums, ctx->ctrl, s);
+    {
+      ProfScope ps(ctx, kScan, s);
+      launch_scan_counts(ctx->count, ctx->dval[0], (int)n, ctx->offs, ctx->block_sums, ctx->ctrl, s);
+    }
     if (allow_sync && !capturing && !ctx->pair_fixed) {
       GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
       GS2D_HIP(ctx, hipStreamSynchronize(s));
       const int64_t np = ctx->host_ctrl->n_pairs;
       if (np > ctx->p_cap) GS2D_TRY(ensure_pairs(ctx, np + np / 4));
     }
-    launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, (int)n, tiles_x, ctx->p_cap, ctx->pkey[0],
-                     ctx->pval[0], ctx->ctrl, s);
+    {
+      ProfScope ps(ctx, kDup, s);
+      launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, (int)n, tiles_x, ctx->p_cap, ctx->pkey[0],
+                       ctx->pval[0], ctx->ctrl, s);
+    }
     if (ctx->opt.keep_unsorted && ctx->pkey_keep) {
       launch_copy_u32(ctx->pkey[0], ctx->pkey_keep, ctx->p_cap, s);
       launch_copy_u32(ctx->pval[0], ctx->pval_keep, ctx->p_cap, s);
     }
-    pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits(n_tiles), ctx->hist, s);
-    launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, n_tiles, s);
+    {
+      ProfScope ps(ctx, kTileSort, s);
+      pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits(n_tiles), ctx->hist,
+                        s);
+    }
+    {
+      ProfScope ps(ctx, kRanges, s);
+      launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, n_tiles, s);
+    }
     BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, cf, ctx->opt.z_near, ctx->opt.filter, tiles_x, n_tiles,
                  ctx->opt.batch};
-    launch_blend_fwd(ba, tw, th, rgb, depth, normal, alpha, ctx->t_final, ctx->last, s);
+    {
+      ProfScope ps(ctx, kBlendFwd, s);
+      launch_blend_fwd(ba, tw, th, rgb, depth, normal, alpha, ctx->t_final, ctx->last, work_ptr(ctx, s), s);
+    }
   }
   GS2D_HIP(ctx, hipGetLastError());
   ctx->generation += 1;
@@ -245,6 +328,7 @@ GS2D_API int gs2d_default_options(gs2d_options* opt) {
   opt->z_near = 0.2f;
   opt->pair_capacity = 0;
   opt->keep_unsorted = 0;
+  opt->profile = 0;
   return GS2D_OK;
 }
 
@@ -255,7 +339,8 @@ GS2D_API int gs2d_create(gs2d_ctx** out, int device, const gs2d_options* opt) {
   gs2d_default_options(&o);
   if (opt) o = *opt;
   if (!valid_tile(o.tile_w, o.tile_h) || !valid_batch(o.batch) || !(o.z_near > 0.f) ||
-      !std::isfinite(o.z_near) || o.pair_capacity < 0 || (o.filter != 0 && o.filter != 1))
+      !std::isfinite(o.z_near) || o.pair_capacity < 0 || (o.filter != 0 && o.filter != 1) ||
+      (o.profile != 0 && o.profile != 1))
     return GS2D_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -301,7 +386,13 @@ GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);
+  invalidate_graph(ctx);
   if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
+  for (int i = 0; i < ctx->ev_cap; ++i) {
+    (void)hipEventDestroy(ctx->ev[i].a);
+    (void)hipEventDestroy(ctx->ev[i].b);
+  }
+  delete[] ctx->ev;
   delete ctx;
   return GS2D_OK;
 }
@@ -333,19 +424,34 @@ GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float
   }
   const BlendArgs ba = blend_args(ctx);
   if (!d_params) {
-    launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
-                     d_alpha, nullptr, ctx->part, s);
-    if (d_pose) launch_reduce_pose(ctx->part, ctx->n_tiles, d_pose, acc, s);
+    {
+      ProfScope ps(ctx, kBlendBwd, s);
+      launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
+                       d_alpha, nullptr, ctx->part, work_ptr(ctx, s), s);
+    }
+    if (d_pose) {
+      ProfScope ps(ctx, kReduce, s);
+      launch_reduce_pose(ctx->part, ctx->n_tiles, d_pose, acc, s);
+    }
   } else {
     bool capturing = false;
     if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
     if (n > ctx->gacc_cap && capturing) return GS2D_ERR_CAPACITY;
     GS2D_TRY(ensure_gacc(ctx, n));
     launch_fill_f32(ctx->gacc, 0.f, n * 16, s);
-    launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
-                     d_alpha, ctx->gacc, ctx->part, s);
-    launch_preprocess_bwd(ctx->last_params, (int)n, ctx->saved_pose, ctx->gacc, d_params, acc, ctx->part, s);
-    if (d_pose) launch_reduce_pose(ctx->part, (int)((n + 255) / 256), d_pose, acc, s);
+    {
+      ProfScope ps(ctx, kBlendBwd, s);
+      launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
+                       d_alpha, ctx->gacc, ctx->part, work_ptr(ctx, s), s);
+    }
+    {
+      ProfScope ps(ctx, kPreBwd, s);
+      launch_preprocess_bwd(ctx->last_params, (int)n, ctx->saved_pose, ctx->gacc, d_params, acc, ctx->part, s);
+    }
+    if (d_pose) {
+      ProfScope ps(ctx, kReduce, s);
+      launch_reduce_pose(ctx->part, (int)((n + 255) / 256), d_pose, acc, s);
+    }
   }
   GS2D_HIP(ctx, hipGetLastError());
   return GS2D_OK;
@@ -366,12 +472,92 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
   if (HW > ctx->hw_cap && capturing) return GS2D_ERR_CAPACITY;
   GS2D_TRY(ensure_pixels(ctx, HW));
   int nparts = 0;
-  launch_tracking_loss(camf(*camera), rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks, d_rgb,
-                       d_depth, ctx->lpart, &nparts, stream);
-  launch_reduce_loss(ctx->lpart, nparts, 1.0f / (float)HW, loss, nullptr, stream);
+  {
+    ProfScope ps(ctx, kLoss, stream);
+    launch_tracking_loss(camf(*camera), rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks, d_rgb,
+                         d_depth, ctx->lpart, &nparts, stream);
+  }
+  {
+    ProfScope ps(ctx, kReduce, stream);
+    launch_reduce_loss(ctx->lpart, nparts, 1.0f / (float)HW, loss, nullptr, stream);
+  }
   GS2D_HIP(ctx, hipGetLastError());
   return GS2D_OK;
 }
+
+namespace {
+// Everything the captured tracking iteration bakes into its kernel arguments.
+struct TrackKey {
+  const float* params;
+  int64_t n;
+  gs2d_camera cam;
+  float* pose;
+  const float* tgt_rgb;
+  const float* tgt_depth;
+  float lambda_d;
+  int32_t use_masks;
+  float lr[6];
+  float beta1, beta2, eps, weight_decay;
+  int64_t p_cap;
+};
+static_assert(sizeof(TrackKey) <= sizeof(((gs2d_ctx*)nullptr)->track_key), "track key size");
+
+TrackKey make_key(gs2d_ctx* ctx, const gs2d_track_args* a) {
+  TrackKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.params = a->params;
+  k.n = a->n;
+  k.cam = a->camera;
+  k.pose = a->pose;
+  k.tgt_rgb = a->tgt_rgb;
+  k.tgt_depth = a->tgt_depth;
+  k.lambda_d = a->lambda_d;
+  k.use_masks = a->use_masks;
+  for (int i = 0; i < 6; ++i) k.lr[i] = a->lr[i];
+  k.beta1 = a->beta1;
+  k.beta2 = a->beta2;
+  k.eps = a->eps;
+  k.weight_decay = a->weight_decay;
+  k.p_cap = ctx->p_cap;
+  return k;
+}
+
+// One tracking iteration: render at the current pose, tracking loss, pose-only
+// backward, AdamW + Exp step.  No allocation and no synchronisation (capturable).
+int track_iteration(gs2d_ctx* ctx, const gs2d_track_args* a, float* img, float* grad, hipStream_t s) {
+  const gs2d_camera cam = a->camera;
+  const int64_t HW = (int64_t)cam.width * cam.height;
+  float *rgb = img, *depth = img + 3 * HW, *normal = img + 4 * HW, *alpha = img + 7 * HW;
+  float *g_rgb = grad, *g_depth = grad + 3 * HW;
+  AdamArgs adam;
+  for (int k = 0; k < 6; ++k) adam.lr[k] = a->lr[k];
+  adam.beta1 = a->beta1;
+  adam.beta2 = a->beta2;
+  adam.eps = a->eps;
+  adam.weight_decay = a->weight_decay;
+  GS2D_TRY(render_impl(ctx, a->params, a->n, cam, a->pose, rgb, depth, normal, alpha, s, false));
+  int nparts = 0;
+  {
+    ProfScope ps(ctx, kLoss, s);
+    launch_tracking_loss(camf(cam), rgb, depth, normal, alpha, a->tgt_rgb, a->tgt_depth, a->lambda_d, a->use_masks,
+                         g_rgb, g_depth, ctx->lpart, &nparts, s);
+  }
+  if (a->n > 0) {
+    ProfScope ps(ctx, kBlendBwd, s);
+    launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, g_rgb, g_depth,
+                     nullptr, nullptr, nullptr, ctx->part, work_ptr(ctx, s), s);
+  } else {
+    launch_fill_f32(ctx->part, 0.f, 8, s);
+  }
+  {
+    ProfScope ps(ctx, kPose, s);
+    launch_pose_step(ctx->part, a->n > 0 ? ctx->n_tiles : 1, ctx->lpart, nparts, 1.0f / (float)HW, adam, a->pose,
+                     ctx->ctrl, s);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+}  // namespace
 
 GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* a, hipStream_t caller_stream) {
   if (!ctx || !a || !valid_camera(&a->camera) || a->n < 0 || (a->n > 0 && !a->params) || !a->pose ||
@@ -379,114 +565,100 @@ GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* a, hipStream_t cal
     return GS2D_ERR_INVALID_ARG;
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.f) return GS2D_ERR_INVALID_ARG;
-  if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f))
+  if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f) ||
+      !std::isfinite(a->lambda_d))
     return GS2D_ERR_INVALID_ARG;
   GS2D_TRY(set_device(ctx));
   bool capturing = false;
   if (stream_capturing(caller_stream, &capturing) != 0 || capturing) return GS2D_ERR_INVALID_ARG;
   // The loop runs on the caller's stream, or, to be captured into a graph, on a
-  // stream of the context (the legacy null stream cannot be captured); the call
-  // returns after the work has completed either way.
+  // stream of the context (the legacy null stream cannot be captured).
   hipStream_t s = caller_stream;
   if (a->use_graph) {
     if (!ctx->graph_stream) GS2D_HIP(ctx, hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
     GS2D_HIP(ctx, hipStreamSynchronize(caller_stream));
     s = ctx->graph_stream;
   }
-  const gs2d_camera cam = a->camera;
-  const int64_t HW = (int64_t)cam.width * cam.height;
+  const int64_t HW = (int64_t)a->camera.width * a->camera.height;
   GS2D_TRY(ensure_pixels(ctx, HW));
   if (!ctx->lgrad) GS2D_TRY(realloc_dev(ctx, &ctx->lgrad, 4 * ctx->hw_cap));
   if (!ctx->limg) GS2D_TRY(realloc_dev(ctx, &ctx->limg, 8 * ctx->hw_cap));
-  float* img = ctx->limg;
-  float *rgb = img, *depth = img + 3 * HW, *normal = img + 4 * HW, *alpha = img + 7 * HW;
-  float *g_rgb = ctx->lgrad, *g_depth = ctx->lgrad + 3 * HW;
   GS2D_HIP(ctx, hipMemcpyAsync(ctx->pose0, a->pose, 12 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  AdamArgs adam;
-  for (int k = 0; k < 6; ++k) adam.lr[k] = a->lr[k];
-  adam.beta1 = a->beta1;
-  adam.beta2 = a->beta2;
-  adam.eps = a->eps;
-  adam.weight_decay = a->weight_decay;
-  const float inv_hw = 1.0f / (float)HW;
-
+  const bool was_fixed = ctx->pair_fixed;
+  int result = GS2D_ERR_CAPACITY;
   for (int attempt = 0; attempt < 3; ++attempt) {
     if (attempt > 0)
       GS2D_HIP(ctx, hipMemcpyAsync(a->pose, ctx->pose0, 12 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    // size the pair buffers on the start pose with headroom, then run without readbacks
-    const bool was_fixed = ctx->pair_fixed;
-    ctx->pair_fixed = false;
-    int r = render_impl(ctx, a->params, a->n, cam, a->pose, rgb, depth, normal, alpha, s, true);
-    if (r != GS2D_OK) {
-      ctx->pair_fixed = was_fixed;
-      return r;
+    TrackKey key = make_key(ctx, a);
+    const bool reuse = a->use_graph && attempt == 0 && ctx->track_valid &&
+                       std::memcmp(ctx->track_key, &key, sizeof(key)) == 0;
+    if (!reuse) {
+      // size the pair buffers on the start pose, with headroom for the moving pose
+      ctx->pair_fixed = false;
+      int r = render_impl(ctx, a->params, a->n, a->camera, a->pose, ctx->limg, ctx->limg + 3 * HW,
+                          ctx->limg + 4 * HW, ctx->limg + 7 * HW, s, true);
+      if (r == GS2D_OK) {
+        const int64_t np = ctx->host_ctrl->n_pairs;
+        r = ensure_pairs(ctx, (np + np / 2 + 1024) << attempt);
+      }
+      if (r != GS2D_OK) {
+        ctx->pair_fixed = was_fixed;
+        return r;
+      }
     }
-    const int64_t np = ctx->host_ctrl->n_pairs;
-    r = ensure_pairs(ctx, (np + np / 2 + 1024) << attempt);
     ctx->pair_fixed = true;
-    if (r != GS2D_OK) {
-      ctx->pair_fixed = was_fixed;
-      return r;
-    }
-    launch_track_init(a->pose, ctx->ctrl, s);
-    auto iteration = [&]() -> int {
-      GS2D_TRY(render_impl(ctx, a->params, a->n, cam, a->pose, rgb, depth, normal, alpha, s, false));
-      int nparts = 0;
-      launch_tracking_loss(camf(cam), rgb, depth, normal, alpha, a->tgt_rgb, a->tgt_depth, a->lambda_d,
-                           a->use_masks, g_rgb, g_depth, ctx->lpart, &nparts, s);
-      if (a->n > 0)
-        launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, g_rgb,
-                         g_depth, nullptr, nullptr, nullptr, ctx->part, s);
-      else
-        launch_fill_f32(ctx->part, 0.f, 8, s);
-      launch_pose_step(ctx->part, a->n > 0 ? ctx->n_tiles : 1, ctx->lpart, nparts, inv_hw, adam, a->pose,
-                       ctx->ctrl, a->pose_history, a->loss_history, a->n_iters, s);
-      return GS2D_OK;
-    };
+    launch_track_init(a->pose, ctx->ctrl, a->pose_history, a->loss_history, a->n_iters, s);
+    int r = GS2D_OK;
     if (a->use_graph && a->n_iters > 0) {
-      hipGraph_t graph = nullptr;
-      hipGraphExec_t exec = nullptr;
-      GS2D_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      int ri = iteration();
-      hipError_t ec = hipStreamEndCapture(s, &graph);
-      if (ri != GS2D_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        ctx->pair_fixed = was_fixed;
-        return ri;
-      }
-      if (ec != hipSuccess) {
-        ctx->pair_fixed = was_fixed;
-        return fail_hip(ctx, ec);
-      }
-      hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (ei != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        ctx->pair_fixed = was_fixed;
-        return fail_hip(ctx, ei);
-      }
-      hipError_t el = hipSuccess;
-      for (int it = 0; it < a->n_iters && el == hipSuccess; ++it) el = hipGraphLaunch(exec, s);
-      (void)hipGraphExecDestroy(exec);
-      (void)hipGraphDestroy(graph);
-      if (el != hipSuccess) {
-        ctx->pair_fixed = was_fixed;
-        return fail_hip(ctx, el);
-      }
-    } else {
-      for (int it = 0; it < a->n_iters; ++it) {
-        int ri = iteration();
-        if (ri != GS2D_OK) {
+      if (!reuse) {
+        invalidate_graph(ctx);
+        GS2D_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int ri = track_iteration(ctx, a, ctx->limg, ctx->lgrad, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (ri != GS2D_OK || ec != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
           ctx->pair_fixed = was_fixed;
-          return ri;
+          return ri != GS2D_OK ? ri : fail_hip(ctx, ec);
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          (void)hipGraphDestroy(graph);
+          ctx->pair_fixed = was_fixed;
+          return fail_hip(ctx, ei);
+        }
+        ctx->track_graph = graph;
+        ctx->track_exec = exec;
+        key = make_key(ctx, a);
+        std::memcpy(ctx->track_key, &key, sizeof(key));
+        ctx->track_valid = true;
+      }
+      for (int it = 0; it < a->n_iters; ++it) {
+        const hipError_t el = hipGraphLaunch(ctx->track_exec, s);
+        if (el != hipSuccess) {
+          ctx->pair_fixed = was_fixed;
+          return fail_hip(ctx, el);
         }
       }
+    } else {
+      for (int it = 0; it < a->n_iters && r == GS2D_OK; ++it) r = track_iteration(ctx, a, ctx->limg, ctx->lgrad, s);
     }
-    ctx->pair_fixed = was_fixed;
+    if (r != GS2D_OK) {
+      ctx->pair_fixed = was_fixed;
+      return r;
+    }
     GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     GS2D_HIP(ctx, hipStreamSynchronize(s));
-    if (!ctx->host_ctrl->overflow) return GS2D_OK;
+    if (!ctx->host_ctrl->overflow) {
+      result = GS2D_OK;
+      break;
+    }
+    invalidate_graph(ctx);
   }
-  return GS2D_ERR_CAPACITY;
+  ctx->pair_fixed = was_fixed;
+  ctx->have_forward = false;  // the loop's internal render state is not a public forward
+  return result;
 }
 
 GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream) {
@@ -532,6 +704,63 @@ GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_
   }
   if (need > 0) GS2D_HIP(ctx, hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost));
   *bytes = need;
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_pose_exp(gs2d_ctx* ctx, const float* tau, const float* pose_in, float* pose_out,
+                           hipStream_t stream) {
+  if (!ctx || !tau || !pose_in || !pose_out) return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  launch_pose_exp(tau, pose_in, pose_out, stream);
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_pose_tau_grad(gs2d_ctx* ctx, const float* tau, const float* d_pose, float* d_tau,
+                                hipStream_t stream) {
+  if (!ctx || !tau || !d_pose || !d_tau) return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  launch_pose_tau_grad(tau, d_pose, d_tau, stream);
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API const char* gs2d_profile_family(int i) {
+  return (i >= 0 && i < kNumFamilies) ? kFamilyNames[i] : nullptr;
+}
+
+GS2D_API int gs2d_get_profile(gs2d_ctx* ctx, gs2d_profile* out, int32_t reset, hipStream_t stream) {
+  if (!ctx || !out) return GS2D_ERR_INVALID_ARG;
+  if (!ctx->opt.profile) return GS2D_ERR_UNSUPPORTED;
+  GS2D_TRY(set_device(ctx));
+  GS2D_HIP(ctx, hipStreamSynchronize(stream));
+  if (ctx->graph_stream) GS2D_HIP(ctx, hipStreamSynchronize(ctx->graph_stream));
+  for (int i = 0; i < ctx->ev_used; ++i) {
+    float ms = 0.f;
+    GS2D_HIP(ctx, hipEventSynchronize(ctx->ev[i].b));
+    GS2D_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[i].a, ctx->ev[i].b));
+    ctx->prof_ms[ctx->ev[i].fam] += ms;
+    ctx->prof_launches[ctx->ev[i].fam] += 1;
+  }
+  ctx->ev_used = 0;
+  GS2D_HIP(ctx, hipMemcpy(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  for (int f = 0; f < kNumFamilies; ++f) {
+    out->ms[f] = ctx->prof_ms[f];
+    out->launches[f] = ctx->prof_launches[f];
+  }
+  out->fwd_evaluated = (int64_t)ctx->host_ctrl->work[0];
+  out->fwd_covering = (int64_t)ctx->host_ctrl->work[1];
+  out->bwd_evaluated = (int64_t)ctx->host_ctrl->work[2];
+  out->bwd_covering = (int64_t)ctx->host_ctrl->work[3];
+  if (reset) {
+    for (int f = 0; f < kNumFamilies; ++f) {
+      ctx->prof_ms[f] = 0.0;
+      ctx->prof_launches[f] = 0;
+    }
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ctrl->work), 0u, 8, stream);
+    GS2D_HIP(ctx, hipStreamSynchronize(stream));
+  }
   return GS2D_OK;
 }
 

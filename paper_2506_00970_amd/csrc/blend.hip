@@ -37,9 +37,11 @@ struct Hit {
 };
 
 // One (pixel, surfel) evaluation; the forward and backward kernels call this same
-// function so that every decision is reproduced bit for bit.
-__device__ __forceinline__ bool evaluate(float px, float py, const float4 g1, const float4 g2,
-                                         const float4 g3, float o, float z_near, int filter, Hit& h) {
+// function so that every decision is reproduced bit for bit.  Returns 0 outside
+// the footprint (rho > 9 or depth < z_near), 1 inside it but below the opacity
+// threshold, 2 when the pair is composited.
+__device__ __forceinline__ int evaluate(float px, float py, const float4 g1, const float4 g2,
+                                        const float4 g3, float o, float z_near, int filter, Hit& h) {
   const float cx = g1.x, cy = g1.y, Dt = g1.z, k0 = g1.w;
   const float k1 = g2.x, P0 = g2.y, P1 = g2.z, Q0 = g2.w;
   const float Q1 = g3.x, m0 = g3.y, m1 = g3.z, m2 = g3.w;
@@ -57,12 +59,24 @@ __device__ __forceinline__ bool evaluate(float px, float py, const float4 g1, co
   h.b3d = rho3 <= rho2;  // NaN (q2 = 0) selects the filter branch
   const float rho = h.b3d ? rho3 : rho2;
   h.d = h.b3d ? fmaf(m0, h.u, fmaf(m1, h.v, m2)) : m2;
-  if (!(rho <= kRhoCutoff) || !(h.d >= z_near)) return false;
+  if (!(rho <= kRhoCutoff) || !(h.d >= z_near)) return 0;
   h.G = __builtin_amdgcn_exp2f(rho * -0.72134752044448170368f);  // exp(-rho / 2)
   const float og = o * h.G;
   h.clamped = og > kAlphaMax;
   h.alpha = h.clamped ? kAlphaMax : og;
-  return h.alpha >= kAlphaMin;
+  return h.alpha >= kAlphaMin ? 2 : 1;
+}
+
+__device__ __forceinline__ void add_work(unsigned long long* work, int lane, int a, int b) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    a += __shfl_xor(a, m, 64);
+    b += __shfl_xor(b, m, 64);
+  }
+  if (lane == 0) {
+    atomicAdd(work, (unsigned long long)a);
+    atomicAdd(work + 1, (unsigned long long)b);
+  }
 }
 
 __device__ __forceinline__ float uniformf(float x) {
@@ -87,13 +101,14 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool PROF>
 __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ rgb,
                                                            float* __restrict__ depth,
                                                            float* __restrict__ normal,
                                                            float* __restrict__ alpha,
                                                            float* __restrict__ t_final,
-                                                           uint32_t* __restrict__ last_out) {
+                                                           uint32_t* __restrict__ last_out,
+                                                           unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8;
   extern __shared__ float4 srec[];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -108,6 +123,7 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   const int start = (int)rg.x, end = (int)rg.y;
   float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f, co = 0.f;
   int lastj = 0;
+  int n_eval = 0, n_cov = 0;
   bool done = !inside;
   for (int b0 = start; b0 < end; b0 += a.batch) {
     if (__syncthreads_count(!done) == 0) break;
@@ -125,8 +141,13 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
       if (!done) {
         const float4 c4 = srec[j * kRecF4 + 4];
         Hit h;
-        if (evaluate(fpx, fpy, srec[j * kRecF4 + 1], srec[j * kRecF4 + 2], srec[j * kRecF4 + 3], c4.x,
-                     a.z_near, a.filter, h)) {
+        const int code = evaluate(fpx, fpy, srec[j * kRecF4 + 1], srec[j * kRecF4 + 2], srec[j * kRecF4 + 3],
+                                  c4.x, a.z_near, a.filter, h);
+        if (PROF) {
+          n_eval += 1;
+          n_cov += code > 0;
+        }
+        if (code == 2) {
           const float Tn = T * (1.0f - h.alpha);
           if (Tn < kTMin) {
             done = true;
@@ -148,6 +169,7 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
       }
     }
   }
+  if (PROF) add_work(work, lane, n_eval, n_cov);
   if (!inside) return;
   const int HW = a.cam.width * a.cam.height;
   const int p = py * a.cam.width + px;
@@ -167,11 +189,12 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   last_out[p] = (uint32_t)lastj;
 }
 
-template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O>
+template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>
 __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
     BlendArgs a, const float* __restrict__ t_final, const uint32_t* __restrict__ last_in,
     const float* __restrict__ g_rgb, const float* __restrict__ g_depth, const float* __restrict__ g_normal,
-    const float* __restrict__ g_alpha, float* __restrict__ gacc, float* __restrict__ part) {
+    const float* __restrict__ g_alpha, float* __restrict__ gacc, float* __restrict__ part,
+    unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
   extern __shared__ float4 srec[];
   uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * kRecF4);
@@ -209,6 +232,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
   const float xh = (fpx - a.cam.cx) / a.cam.fx, yh = (fpy - a.cam.cy) / a.cam.fy;
   float Br = 0.f, Bg = 0.f, Bb = 0.f, Bd = 0.f, Bn0 = 0.f, Bn1 = 0.f, Bn2 = 0.f, Bo = 0.f;
   float pr0 = 0.f, pr1 = 0.f, pr2 = 0.f, pp0 = 0.f, pp1 = 0.f, pp2 = 0.f;
+  int n_eval = 0, n_cov = 0;
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x;
 
@@ -246,7 +270,12 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
         const float4 g1 = srec[jj * kRecF4 + 1], g2 = srec[jj * kRecF4 + 2], g3 = srec[jj * kRecF4 + 3];
         const float4 c4 = srec[jj * kRecF4 + 4];
         Hit h;
-        if (evaluate(fpx, fpy, g1, g2, g3, c4.x, a.z_near, a.filter, h)) {
+        const int code = evaluate(fpx, fpy, g1, g2, g3, c4.x, a.z_near, a.filter, h);
+        if (PROF) {
+          n_eval += 1;
+          n_cov += code > 0;
+        }
+        if (code == 2) {
           contrib = true;
           const float4 nv = srec[jj * kRecF4 + 5];
           const float al = h.alpha;
@@ -355,6 +384,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
       }
     }
   }
+  if (PROF) add_work(work + 2, lane, n_eval, n_cov);
   if (POSE_ONLY) {
     float v[6] = {pr0, pr1, pr2, pp0, pp1, pp2};
 #pragma unroll
@@ -375,27 +405,36 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
 
 template <int TW, int TH>
 void fwd_shape(const BlendArgs& a, float* rgb, float* depth, float* normal, float* alpha, float* t_final,
-               uint32_t* last, hipStream_t s) {
+               uint32_t* last, unsigned long long* work, hipStream_t s) {
   const size_t lds = (size_t)a.batch * kRecF4 * sizeof(float4);
-  blend_fwd_kernel<TW, TH><<<a.n_tiles, TW * TH, lds, s>>>(a, rgb, depth, normal, alpha, t_final, last);
+  if (work)
+    blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, rgb, depth, normal, alpha, t_final, last,
+                                                                    work);
+  else
+    blend_fwd_kernel<TW, TH, false><<<a.n_tiles, TW * TH, lds, s>>>(a, rgb, depth, normal, alpha, t_final, last,
+                                                                     work);
 }
 
 template <int TW, int TH, bool PO, bool HN, bool HO>
 void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, const float* g_rgb,
                  const float* g_depth, const float* g_normal, const float* g_alpha, float* gacc, float* part,
-                 hipStream_t s) {
+                 unsigned long long* work, hipStream_t s) {
   const size_t lds = (size_t)a.batch * (kRecF4 * sizeof(float4) + sizeof(uint32_t));
-  blend_bwd_kernel<TW, TH, PO, HN, HO><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, g_rgb, g_depth,
-                                                                       g_normal, g_alpha, gacc, part);
+  if (work)
+    blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(
+        a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work);
+  else
+    blend_bwd_kernel<TW, TH, PO, HN, HO, false><<<a.n_tiles, TW * TH, lds, s>>>(
+        a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work);
 }
 
 template <int TW, int TH>
 void bwd_shape(const BlendArgs& a, const float* t_final, const uint32_t* last, const float* g_rgb,
                const float* g_depth, const float* g_normal, const float* g_alpha, float* gacc, float* part,
-               hipStream_t s) {
+               unsigned long long* work, hipStream_t s) {
   const bool po = gacc == nullptr, hn = g_normal != nullptr, ho = g_alpha != nullptr;
 #define GS2D_BWD(PO, HN, HO) \
-  bwd_variant<TW, TH, PO, HN, HO>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s)
+  bwd_variant<TW, TH, PO, HN, HO>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s)
   if (po) {
     if (hn && ho) GS2D_BWD(true, true, true);
     else if (hn) GS2D_BWD(true, true, false);
@@ -413,24 +452,24 @@ void bwd_shape(const BlendArgs& a, const float* t_final, const uint32_t* last, c
 }  // namespace
 
 void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* rgb, float* depth, float* normal,
-                      float* alpha, float* t_final, uint32_t* last, hipStream_t s) {
-  if (tile_w == 8 && tile_h == 8) fwd_shape<8, 8>(a, rgb, depth, normal, alpha, t_final, last, s);
-  else if (tile_w == 16 && tile_h == 8) fwd_shape<16, 8>(a, rgb, depth, normal, alpha, t_final, last, s);
-  else if (tile_w == 32 && tile_h == 16) fwd_shape<32, 16>(a, rgb, depth, normal, alpha, t_final, last, s);
-  else fwd_shape<16, 16>(a, rgb, depth, normal, alpha, t_final, last, s);
+                      float* alpha, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
+  if (tile_w == 8 && tile_h == 8) fwd_shape<8, 8>(a, rgb, depth, normal, alpha, t_final, last, work, s);
+  else if (tile_w == 16 && tile_h == 8) fwd_shape<16, 8>(a, rgb, depth, normal, alpha, t_final, last, work, s);
+  else if (tile_w == 32 && tile_h == 16) fwd_shape<32, 16>(a, rgb, depth, normal, alpha, t_final, last, work, s);
+  else fwd_shape<16, 16>(a, rgb, depth, normal, alpha, t_final, last, work, s);
 }
 
 void launch_blend_bwd(const BlendArgs& a, int tile_w, int tile_h, const float* t_final, const uint32_t* last,
                       const float* g_rgb, const float* g_depth, const float* g_normal, const float* g_alpha,
-                      float* gacc, float* part, hipStream_t s) {
+                      float* gacc, float* part, unsigned long long* work, hipStream_t s) {
   if (tile_w == 8 && tile_h == 8)
-    bwd_shape<8, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+    bwd_shape<8, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
   else if (tile_w == 16 && tile_h == 8)
-    bwd_shape<16, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+    bwd_shape<16, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
   else if (tile_w == 32 && tile_h == 16)
-    bwd_shape<32, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+    bwd_shape<32, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
   else
-    bwd_shape<16, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, s);
+    bwd_shape<16, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
 }
 
 }  // namespace gs2d

@@ -44,7 +44,16 @@ struct Ctrl {            // device-resident counters
   double adam_v[6];
   double master_pose[12];
   double loss;
+  float* pose_history;   // set per gs2d_track call, read by the pose step
+  float* loss_history;
+  int32_t max_hist;
+  int32_t pad;
+  unsigned long long work[4];  // profile counters: fwd evaluated, fwd covering, bwd evaluated, bwd covering
 };
+
+// Kernel families timed by the profiler.
+enum Family { kPre, kDepthSort, kScan, kDup, kTileSort, kRanges, kBlendFwd, kLoss, kBlendBwd, kPreBwd, kPose,
+              kReduce, kNumFamilies };
 
 }  // namespace gs2d
 
@@ -88,6 +97,20 @@ struct gs2d_ctx {
   gs2d::Ctrl* ctrl = nullptr;
   gs2d::Ctrl* host_ctrl = nullptr;  // pinned mirror for readbacks
   hipStream_t graph_stream = nullptr;  // capture stream of gs2d_track (default priority)
+
+  // cached tracking graph (invalidated whenever a workspace buffer moves)
+  hipGraphExec_t track_exec = nullptr;
+  hipGraph_t track_graph = nullptr;
+  unsigned char track_key[256] = {0};
+  bool track_valid = false;
+
+  // profiling: HIP events around kernel families (eager calls only)
+  struct EvPair { hipEvent_t a, b; int fam; };
+  EvPair* ev = nullptr;
+  int ev_used = 0, ev_cap = 0;
+  double prof_ms[gs2d::kNumFamilies] = {0};
+  long long prof_launches[gs2d::kNumFamilies] = {0};
+  long long prof_renders = 0;
 
   // state of the last render
   uint32_t generation = 0;
@@ -138,12 +161,14 @@ struct BlendArgs {
   int filter;
   int tiles_x, n_tiles, batch;
 };
+// work (may be null): profile counters, see Ctrl::work
 void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* rgb, float* depth,
-                      float* normal, float* alpha, float* t_final, uint32_t* last, hipStream_t s);
+                      float* normal, float* alpha, float* t_final, uint32_t* last,
+                      unsigned long long* work, hipStream_t s);
 void launch_blend_bwd(const BlendArgs& a, int tile_w, int tile_h, const float* t_final,
                       const uint32_t* last, const float* g_rgb, const float* g_depth,
                       const float* g_normal, const float* g_alpha, float* gacc, float* part,
-                      hipStream_t s);
+                      unsigned long long* work, hipStream_t s);
 
 // loss_pose.hip
 void launch_tracking_loss(CamF cam, const float* rgb, const float* depth, const float* normal,
@@ -159,9 +184,12 @@ struct AdamArgs {
   float lr[6];
   float beta1, beta2, eps, weight_decay;
 };
-void launch_track_init(const float* pose, Ctrl* ctrl, hipStream_t s);
+void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
+void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
+void launch_track_init(const float* pose, Ctrl* ctrl, float* pose_history, float* loss_history,
+                       int max_hist, hipStream_t s);
 void launch_pose_step(const float* pose_part, int n_pose_parts, const float* loss_part,
                       int n_loss_parts, float inv_hw, AdamArgs adam, float* pose, Ctrl* ctrl,
-                      float* pose_history, float* loss_history, int max_hist, hipStream_t s);
+                      hipStream_t s);
 
 }  // namespace gs2d

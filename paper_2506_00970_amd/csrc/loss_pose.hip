@@ -103,7 +103,8 @@ __global__ void reduce_pose_kernel(const float* __restrict__ part, int n, float*
   }
 }
 
-__global__ void track_init_kernel(const float* __restrict__ pose, Ctrl* __restrict__ ctrl) {
+__global__ void track_init_kernel(const float* __restrict__ pose, Ctrl* __restrict__ ctrl,
+                                  float* pose_history, float* loss_history, int max_hist) {
   const int t = threadIdx.x;
   if (t < 12) ctrl->master_pose[t] = (double)pose[t];
   if (t < 6) {
@@ -113,6 +114,9 @@ __global__ void track_init_kernel(const float* __restrict__ pose, Ctrl* __restri
   if (t == 0) {
     ctrl->iter = 0;
     ctrl->loss = 0.0;
+    ctrl->pose_history = pose_history;
+    ctrl->loss_history = loss_history;
+    ctrl->max_hist = max_hist;
   }
 }
 
@@ -146,15 +150,16 @@ __device__ void se3_exp(const double tau[6], double R[9], double tt[3]) {
 
 __global__ void pose_step_kernel(const float* __restrict__ pose_part, int n_pose_parts,
                                  const float* __restrict__ loss_part, int n_loss_parts, float inv_hw,
-                                 AdamArgs adam, float* __restrict__ pose, Ctrl* __restrict__ ctrl,
-                                 float* __restrict__ pose_history, float* __restrict__ loss_history,
-                                 int max_hist) {
+                                 AdamArgs adam, float* __restrict__ pose, Ctrl* __restrict__ ctrl) {
   double g[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = sum_parts(pose_part, n_pose_parts, 8, k);
   const double loss = loss_part ? sum_parts(loss_part, n_loss_parts, 1, 0) * (double)inv_hw : 0.0;
   if (threadIdx.x != 0) return;
   const uint32_t it = ctrl->iter;
+  float* pose_history = ctrl->pose_history;
+  float* loss_history = ctrl->loss_history;
+  const int max_hist = ctrl->max_hist;
   ctrl->loss = loss;
   if (loss_history && (int)it < max_hist) loss_history[it] = (float)loss;
   const double t = (double)it + 1.0;
@@ -187,7 +192,100 @@ __global__ void pose_step_kernel(const float* __restrict__ pose_part, int n_pose
   ctrl->iter = it + 1;
 }
 
+// Left Jacobian of SE(3) for tau = (rho, phi) (Barfoot, "State Estimation for
+// Robotics", Sec. 7.1.5): J = [[J_so3, Q], [0, J_so3]] with
+// Q = 1/2 R + c2 (F R + R F + F R F) + c3 (F F R + R F F - 3 F R F)
+//     + c4 (F R F F + F F R F),  F = phi^, R = rho^,
+// c2 = (th - sin th)/th^3, c3 = (th^2 + 2 cos th - 2)/(2 th^4),
+// c4 = (2 th - 3 sin th + th cos th)/(2 th^5)  (series below 1e-3 rad).
+__device__ void mat3_mul(const double* A, const double* B, double* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      C[r * 3 + c] = A[r * 3 + 0] * B[0 * 3 + c] + A[r * 3 + 1] * B[1 * 3 + c] + A[r * 3 + 2] * B[2 * 3 + c];
+}
+
+__device__ void se3_left_jacobian(const double tau[6], double Jl[36]) {
+  const double px = tau[3], py = tau[4], pz = tau[5];
+  const double th2 = px * px + py * py + pz * pz, th = sqrt(th2);
+  double b, c, c2, c3, c4;  // J_so3 = I + b F + c F^2
+  if (th < 1e-3) {
+    b = 0.5 - th2 / 24.0;
+    c = 1.0 / 6.0 - th2 / 120.0;
+    c2 = 1.0 / 6.0 - th2 / 120.0;
+    c3 = 1.0 / 24.0 - th2 / 720.0;
+    c4 = 1.0 / 120.0 - th2 / 2520.0;
+  } else {
+    const double s = sin(th), co = cos(th);
+    b = (1.0 - co) / th2;
+    c = (th - s) / (th2 * th);
+    c2 = c;
+    c3 = (th2 + 2.0 * co - 2.0) / (2.0 * th2 * th2);
+    c4 = (2.0 * th - 3.0 * s + th * co) / (2.0 * th2 * th2 * th);
+  }
+  const double F[9] = {0.0, -pz, py, pz, 0.0, -px, -py, px, 0.0};
+  const double R[9] = {0.0, -tau[2], tau[1], tau[2], 0.0, -tau[0], -tau[1], tau[0], 0.0};
+  double FF[9], FR[9], RF[9], FRF[9], FFR[9], RFF[9], FRFF[9], FFRF[9];
+  mat3_mul(F, F, FF);
+  mat3_mul(F, R, FR);
+  mat3_mul(R, F, RF);
+  mat3_mul(FR, F, FRF);
+  mat3_mul(FF, R, FFR);
+  mat3_mul(RF, F, RFF);
+  mat3_mul(FRF, F, FRFF);
+  mat3_mul(FF, RF, FFRF);
+  double J3[9], Q[9];
+  for (int k = 0; k < 9; ++k) {
+    J3[k] = ((k % 4 == 0) ? 1.0 : 0.0) + b * F[k] + c * FF[k];
+    Q[k] = 0.5 * R[k] + c2 * (FR[k] + RF[k] + FRF[k]) + c3 * (FFR[k] + RFF[k] - 3.0 * FRF[k]) +
+           c4 * (FRFF[k] + FFRF[k]);
+  }
+  for (int k = 0; k < 36; ++k) Jl[k] = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int cc = 0; cc < 3; ++cc) {
+      Jl[r * 6 + cc] = J3[r * 3 + cc];
+      Jl[r * 6 + 3 + cc] = Q[r * 3 + cc];
+      Jl[(r + 3) * 6 + 3 + cc] = J3[r * 3 + cc];
+    }
+}
+
+__global__ void pose_exp_kernel(const float* __restrict__ tau, const float* __restrict__ pin,
+                                float* __restrict__ pout) {
+  if (threadIdx.x != 0) return;
+  double t[6], Re[9], te[3];
+  for (int k = 0; k < 6; ++k) t[k] = tau[k];
+  se3_exp(t, Re, te);
+  double T[12];
+  for (int k = 0; k < 12; ++k) T[k] = pin[k];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 4; ++c) {
+      double s = Re[r * 3 + 0] * T[0 * 4 + c] + Re[r * 3 + 1] * T[1 * 4 + c] + Re[r * 3 + 2] * T[2 * 4 + c];
+      if (c == 3) s += te[r];
+      pout[r * 4 + c] = (float)s;
+    }
+}
+
+__global__ void pose_tau_grad_kernel(const float* __restrict__ tau, const float* __restrict__ g,
+                                     float* __restrict__ d_tau) {
+  if (threadIdx.x != 0) return;
+  double t[6], J[36];
+  for (int k = 0; k < 6; ++k) t[k] = tau[k];
+  se3_left_jacobian(t, J);
+  for (int c = 0; c < 6; ++c) {
+    double s = 0.0;
+    for (int r = 0; r < 6; ++r) s += J[r * 6 + c] * (double)g[r];
+    d_tau[c] = (float)s;
+  }
+}
+
 }  // namespace
+
+void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s) {
+  pose_exp_kernel<<<1, 64, 0, s>>>(tau, pose_in, pose_out);
+}
+
+void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s) {
+  pose_tau_grad_kernel<<<1, 64, 0, s>>>(tau, d_pose, d_tau);
+}
 
 int loss_blocks(int hw) { return (hw + kLossThreads - 1) / kLossThreads; }
 
@@ -209,15 +307,14 @@ void launch_reduce_pose(const float* part, int n_parts, float* d_pose, int accum
   reduce_pose_kernel<<<1, 64, 0, s>>>(part, n_parts, d_pose, accumulate);
 }
 
-void launch_track_init(const float* pose, Ctrl* ctrl, hipStream_t s) {
-  track_init_kernel<<<1, 64, 0, s>>>(pose, ctrl);
+void launch_track_init(const float* pose, Ctrl* ctrl, float* pose_history, float* loss_history, int max_hist,
+                       hipStream_t s) {
+  track_init_kernel<<<1, 64, 0, s>>>(pose, ctrl, pose_history, loss_history, max_hist);
 }
 
 void launch_pose_step(const float* pose_part, int n_pose_parts, const float* loss_part, int n_loss_parts,
-                      float inv_hw, AdamArgs adam, float* pose, Ctrl* ctrl, float* pose_history,
-                      float* loss_history, int max_hist, hipStream_t s) {
-  pose_step_kernel<<<1, 64, 0, s>>>(pose_part, n_pose_parts, loss_part, n_loss_parts, inv_hw, adam, pose, ctrl,
-                                    pose_history, loss_history, max_hist);
+                      float inv_hw, AdamArgs adam, float* pose, Ctrl* ctrl, hipStream_t s) {
+  pose_step_kernel<<<1, 64, 0, s>>>(pose_part, n_pose_parts, loss_part, n_loss_parts, inv_hw, adam, pose, ctrl);
 }
 
 }  // namespace gs2d

@@ -55,7 +55,7 @@ class Rasterizer:
 
     def __init__(self, device: int | str | torch.device = 0, tile=(16, 16), batch: int = 256,
                  filter: bool = True, z_near: float = 0.2, pair_capacity: int = 0,
-                 keep_unsorted: bool = False):
+                 keep_unsorted: bool = False, profile: bool = False):
         lib = _lib.load()
         if isinstance(device, int):
             idx = device
@@ -70,6 +70,7 @@ class Rasterizer:
         opt.z_near = float(z_near)
         opt.pair_capacity = int(pair_capacity)
         opt.keep_unsorted = 1 if keep_unsorted else 0
+        opt.profile = 1 if profile else 0
         self.options = opt
         ctx = ctypes.c_void_p()
         _lib.check(lib.gs2d_create(ctypes.byref(ctx), self.device.index, ctypes.byref(opt)))
@@ -140,6 +141,28 @@ class Rasterizer:
                                                   ctypes.c_uint32(generation), flags, self._stream()), self._ctx)
         return d_params, d_pose
 
+    # --------------------------------------------------------------------- pose
+    def pose_exp(self, tau: torch.Tensor, pose_in: torch.Tensor, pose_out: torch.Tensor | None = None):
+        """Exp(tau) pose_in as a [12] tensor (left perturbation; computed by the library)."""
+        _check_tensor(tau, "tau", (6,), self.device)
+        pose_in = pose_in.reshape(12)
+        _check_tensor(pose_in, "pose_in", (12,), self.device)
+        if pose_out is None:
+            pose_out = torch.empty(12, dtype=torch.float32, device=self.device)
+        _check_tensor(pose_out, "pose_out", (12,), self.device)
+        _lib.check(self._lib.gs2d_pose_exp(self._ctx, _dev_ptr(tau), _dev_ptr(pose_in), _dev_ptr(pose_out),
+                                           self._stream()), self._ctx)
+        return pose_out
+
+    def pose_tau_grad(self, tau: torch.Tensor, d_pose: torch.Tensor):
+        """J_l(tau)^T d_pose: the gradient to tau of a loss whose pose is Exp(tau) T."""
+        _check_tensor(tau, "tau", (6,), self.device)
+        _check_tensor(d_pose, "d_pose", (6,), self.device)
+        d_tau = torch.empty(6, dtype=torch.float32, device=self.device)
+        _lib.check(self._lib.gs2d_pose_tau_grad(self._ctx, _dev_ptr(tau), _dev_ptr(d_pose), _dev_ptr(d_tau),
+                                                self._stream()), self._ctx)
+        return d_tau
+
     # --------------------------------------------------------------------- loss
     def tracking_loss(self, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d: float = 1.0,
                       use_masks: bool = True):
@@ -202,6 +225,17 @@ class Rasterizer:
         c = _lib.Counts()
         _lib.check(self._lib.gs2d_get_counts(self._ctx, ctypes.byref(c), self._stream()), self._ctx)
         return {k: getattr(c, k) for k, _ in _lib.Counts._fields_}
+
+    def profile(self, reset: bool = False) -> dict:
+        """Per-family kernel time (ms, summed) and launches, plus blend work counters."""
+        p = _lib.Profile()
+        _lib.check(self._lib.gs2d_get_profile(self._ctx, ctypes.byref(p), 1 if reset else 0, self._stream()),
+                   self._ctx)
+        fams = {}
+        for i in range(_lib.PROFILE_FAMILIES):
+            fams[self._lib.gs2d_profile_family(i).decode()] = {"ms": p.ms[i], "launches": p.launches[i]}
+        return {"families": fams, "fwd_evaluated": p.fwd_evaluated, "fwd_covering": p.fwd_covering,
+                "bwd_evaluated": p.bwd_evaluated, "bwd_covering": p.bwd_covering}
 
     _DEBUG = {"tile_keys": (0, np.uint32), "tile_ids": (1, np.uint32), "ranges": (2, np.uint32),
               "depth_keys": (3, np.uint32), "rect": (4, np.uint16), "t_final": (5, np.float32),
