@@ -48,6 +48,11 @@ class Profile(ctypes.Structure):
                 ("bwd_evaluated", ctypes.c_int64), ("bwd_covering", ctypes.c_int64)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+
 class TrackArgs(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera),
                 ("pose", ctypes.c_void_p), ("tgt_rgb", ctypes.c_void_p), ("tgt_depth", ctypes.c_void_p),
@@ -78,6 +83,8 @@ _SIGS = {
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),
+    "gs2d_autotune": ([_P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, ctypes.c_int32,
+                       ctypes.POINTER(Tuning), _P], ctypes.c_int),
     "gs2d_pose_exp": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "gs2d_pose_tau_grad": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "gs2d_profile_family": ([ctypes.c_int], ctypes.c_char_p),

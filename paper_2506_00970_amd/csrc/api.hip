@@ -725,6 +725,104 @@ GS2D_API int gs2d_pose_tau_grad(gs2d_ctx* ctx, const float* tau, const float* d_
   return GS2D_OK;
 }
 
+GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera,
+                           const float* pose, int32_t reps, gs2d_tuning* out, hipStream_t stream) {
+  if (!ctx || !out || !valid_camera(camera) || n <= 0 || !params || !pose || reps < 1 || reps > 1000)
+    return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  bool capturing = false;
+  if (stream_capturing(stream, &capturing) != 0 || capturing) return GS2D_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  int ncls = 0;
+  while ((1ll << ncls) < n) ++ncls;
+  for (int i = 0; i < ctx->n_tune; ++i) {
+    const auto& e = ctx->tune[i];
+    if (e.w == camera->width && e.h == camera->height && e.ncls == ncls) {
+      if (ctx->opt.tile_w != e.tw || ctx->opt.tile_h != e.th || ctx->opt.batch != e.batch) invalidate_graph(ctx);
+      ctx->opt.tile_w = e.tw;
+      ctx->opt.tile_h = e.th;
+      ctx->opt.batch = e.batch;
+      *out = gs2d_tuning{e.tw, e.th, e.batch, e.ms, 16, 1};
+      return GS2D_OK;
+    }
+  }
+  const int64_t HW = (int64_t)camera->width * camera->height;
+  float* img = nullptr;
+  float* dpose = nullptr;
+  GS2D_HIP(ctx, hipMalloc((void**)&img, (size_t)8 * HW * sizeof(float)));
+  if (hipMalloc((void**)&dpose, 8 * sizeof(float)) != hipSuccess) {
+    (void)hipFree(img);
+    return fail_hip(ctx, hipErrorOutOfMemory);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int tiles[4][2] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}};
+  const int batches[4] = {32, 64, 128, 256};
+  const gs2d_options saved = ctx->opt;
+  const bool saved_fixed = ctx->pair_fixed;
+  const int saved_prof = ctx->opt.profile;
+  ctx->opt.profile = 0;
+  float best = 1e30f;
+  int bt = saved.tile_w, bh = saved.tile_h, bb = saved.batch;
+  int r = GS2D_OK;
+  for (int ti = 0; ti < 4 && r == GS2D_OK; ++ti)
+    for (int bi = 0; bi < 4 && r == GS2D_OK; ++bi) {
+      ctx->opt.tile_w = tiles[ti][0];
+      ctx->opt.tile_h = tiles[ti][1];
+      ctx->opt.batch = batches[bi];
+      ctx->pair_fixed = false;
+      // one synchronising warm-up sizes the pair buffers for this tile shape
+      r = render_impl(ctx, params, n, *camera, pose, img, img + 3 * HW, img + 4 * HW, img + 7 * HW, stream, true);
+      if (r != GS2D_OK) break;
+      ctx->pair_fixed = true;
+      (void)hipEventRecord(e0, stream);
+      for (int k = 0; k < reps && r == GS2D_OK; ++k) {
+        r = render_impl(ctx, params, n, *camera, pose, img, img + 3 * HW, img + 4 * HW, img + 7 * HW, stream,
+                        false);
+        if (r == GS2D_OK) {
+          launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, img,
+                           img + 3 * HW, nullptr, nullptr, nullptr, ctx->part, nullptr, stream);
+          launch_reduce_pose(ctx->part, ctx->n_tiles, dpose, 0, stream);
+        }
+      }
+      (void)hipEventRecord(e1, stream);
+      if (r != GS2D_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        r = fail_hip(ctx, hipGetLastError());
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= (float)reps;
+      (void)hipMemcpy(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+      if (!ctx->host_ctrl->overflow && ms < best) {
+        best = ms;
+        bt = tiles[ti][0];
+        bh = tiles[ti][1];
+        bb = batches[bi];
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(img);
+  (void)hipFree(dpose);
+  ctx->pair_fixed = saved_fixed;
+  ctx->opt.profile = saved_prof;
+  ctx->opt.tile_w = bt;
+  ctx->opt.tile_h = bh;
+  ctx->opt.batch = bb;
+  ctx->have_forward = false;
+  invalidate_graph(ctx);
+  if (r != GS2D_OK) {
+    ctx->opt = saved;
+    return r;
+  }
+  if (ctx->n_tune < 32) ctx->tune[ctx->n_tune++] = {camera->width, camera->height, ncls, bt, bh, bb, best};
+  *out = gs2d_tuning{bt, bh, bb, best, 16, 0};
+  return GS2D_OK;
+}
+
 GS2D_API const char* gs2d_profile_family(int i) {
   return (i >= 0 && i < kNumFamilies) ? kFamilyNames[i] : nullptr;
 }

@@ -112,6 +112,11 @@ struct gs2d_ctx {
   long long prof_launches[gs2d::kNumFamilies] = {0};
   long long prof_renders = 0;
 
+  // autotuner cache: (width, height, log2 n class) -> (tile_w, tile_h, batch, ms)
+  struct TuneEntry { int w, h, ncls, tw, th, batch; float ms; };
+  TuneEntry tune[32];
+  int n_tune = 0;
+
   // state of the last render
   uint32_t generation = 0;
   int64_t last_n = 0;

@@ -141,6 +141,20 @@ class Rasterizer:
                                                   ctypes.c_uint32(generation), flags, self._stream()), self._ctx)
         return d_params, d_pose
 
+    # ----------------------------------------------------------------- autotune
+    def autotune(self, params: torch.Tensor, camera, pose: torch.Tensor, reps: int = 3) -> dict:
+        """Pick the fastest tile shape and LDS batch for this workload; later renders use it."""
+        cam = _camera(camera)
+        n = int(params.shape[1])
+        _check_tensor(params, "params", (15, n), self.device)
+        pose = pose.reshape(12)
+        _check_tensor(pose, "pose", (12,), self.device)
+        t = _lib.Tuning()
+        _lib.check(self._lib.gs2d_autotune(self._ctx, _dev_ptr(params), n, ctypes.byref(cam), _dev_ptr(pose),
+                                           int(reps), ctypes.byref(t), self._stream()), self._ctx)
+        self._last = None
+        return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
+
     # --------------------------------------------------------------------- pose
     def pose_exp(self, tau: torch.Tensor, pose_in: torch.Tensor, pose_out: torch.Tensor | None = None):
         """Exp(tau) pose_in as a [12] tensor (left perturbation; computed by the library)."""

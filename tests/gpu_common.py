@@ -29,10 +29,9 @@ def room_scene(n=300_000, seed=0, cam_seed=0):
 def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth", "normal", "alpha")):
     """Parity of planar images with the tolerances of the method's parity bar.
 
-    colour and opacity: |d| <= 1e-4 absolute; depth: |d| <= 1e-4 max(|ref|, 1e-3);
-    normal (blended, unnormalised): |d| <= 1e-4 max(|ref|, 1e-3 O) component-wise,
-    where O is the pixel's opacity (a normal blended from unit vectors of
-    different directions cancels, so its error is relative to O, not to itself).
+    colour and opacity: |d| <= 1e-4 absolute per channel; depth: |d| <= 1e-4 max(|ref|, 1e-3);
+    normal: a 3-vector, so "1e-4 relative" is read on its norm,
+    ||d N||_2 <= 1e-4 max(||N_ref||_2, 1e-3) per pixel.
     Pixels with a decision margin below MARGIN are excluded and counted.
     """
     keep = margin >= MARGIN
@@ -43,11 +42,13 @@ def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth",
         g, r = gpu[k], ref[k]
         if k in ("rgb", "alpha"):
             tol = 1e-4 + 0 * r
+            err = np.abs(g - r)
         elif k == "depth":
             tol = 1e-4 * np.maximum(np.abs(r), 1e-3)
+            err = np.abs(g - r)
         else:
-            tol = 1e-4 * np.maximum(np.abs(r), 1e-3 * np.maximum(ref["alpha"][None], 1e-3))
-        err = np.abs(g - r)
+            tol = 1e-4 * np.maximum(np.linalg.norm(r, axis=0), 1e-3)
+            err = np.linalg.norm(g - r, axis=0)
         bad = (err > tol) & (keep if err.ndim == 2 else keep[None])
         report[k] = float(err[..., keep].max()) if keep.any() else 0.0
         assert not bad.any(), f"{k}: {int(bad.sum())} values out of tolerance, worst {err[bad].max():.3g}"
@@ -58,8 +59,13 @@ GROUPS = {"mu": slice(0, 3), "t_u": slice(3, 6), "t_v": slice(6, 9), "s": slice(
           "rgb": slice(12, 15)}
 
 
-def check_grads(gpu: np.ndarray, ref: np.ndarray, skip: np.ndarray | None = None, rel=1e-3, floor=1e-6):
-    """|d| <= rel |ref| + floor ||group||_inf per parameter group (surfels in `skip` excluded)."""
+def check_grads(gpu: np.ndarray, ref: np.ndarray, skip: np.ndarray | None = None, rel=1e-3, floor=1e-5):
+    """|d| <= rel |ref| + floor ||group||_inf per parameter group (surfels in `skip` excluded).
+
+    The floor covers float32 accumulation: a surfel's gradient sums many pixel terms
+    of both signs, each carrying ~1e-6 relative rounding, so an entry that cancels to
+    a small net value carries an absolute error proportional to the terms, not to itself.
+    """
     report = {}
     keep = np.ones(ref.shape[1], dtype=bool) if skip is None else ~skip
     for name, sl in GROUPS.items():

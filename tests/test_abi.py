@@ -59,7 +59,8 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = {"gs2d_camera": _lib.Camera, "gs2d_options": _lib.Options, "gs2d_counts": _lib.Counts,
-               "gs2d_track_args": _lib.TrackArgs, "gs2d_profile": _lib.Profile}
+               "gs2d_track_args": _lib.TrackArgs, "gs2d_profile": _lib.Profile,
+               "gs2d_tuning": _lib.Tuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs2d.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

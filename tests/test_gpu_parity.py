@@ -306,3 +306,20 @@ def test_gpu_track_first_step_matches_oracle(gs):
     T1, tau = oloss.adamw_pose_step(start.astype(np.float64), og["pose_paper"], oloss.AdamState(), lr)
     # the first Adam step is -lr sign(g): the update is exact unless a component's gradient is ~0
     np.testing.assert_allclose(host(ph)[0].reshape(3, 4), T1, atol=2e-6)
+
+
+def test_gpu_autotune(gs):
+    """The autotuner returns a valid choice, caches it, and the images do not change."""
+    room, pose = room_scene(300_000, seed=4, cam_seed=4)
+    r = gs.Rasterizer()
+    P, T = dev(room.params), dev(pose.reshape(12))
+    before = r.render(P, ROOM_CAM, T)
+    a = {k: host(getattr(before, k)) for k in ("rgb", "depth", "normal", "alpha")}
+    t = r.autotune(P, ROOM_CAM, T, reps=2)
+    assert (t["tile_w"], t["tile_h"]) in {(8, 8), (16, 8), (16, 16), (32, 16)}
+    assert t["batch"] in (32, 64, 128, 256) and t["ms"] > 0 and t["from_cache"] == 0
+    assert r.autotune(P, ROOM_CAM, T)["from_cache"] == 1
+    after = r.render(P, ROOM_CAM, T)
+    for k in a:
+        np.testing.assert_array_equal(a[k], host(getattr(after, k)), err_msg=k)
+    print("autotune", t)
