@@ -65,6 +65,9 @@ extern "C" {
 #define GS2D_ERR_STATE (-5)      /* backward called without a matching forward */
 #define GS2D_ERR_UNSUPPORTED (-6)
 
+/* Most views (or tracking problems) one batched call may take. */
+#define GS2D_MAX_VIEWS 32
+
 /* Flags for gs2d_render_backward. */
 #define GS2D_ACCUMULATE 1        /* add into d_params / d_pose instead of overwriting */
 
@@ -95,6 +98,41 @@ typedef struct gs2d_counts {
   int32_t overflow;          /* 1: the last render exceeded the capacity (outputs invalid) */
   int32_t n_tiles;
 } gs2d_counts;
+
+/* One view of a batched render: its surfels [15][n], camera, pose [12] and outputs
+ * (planar images of the view's size; any may be NULL).  Views may share a surfel
+ * buffer (a window of keyframes over one map) or not (independent problems). */
+typedef struct gs2d_view {
+  const float* params;
+  int64_t n;
+  gs2d_camera camera;
+  const float* pose;
+  float* rgb;
+  float* depth;
+  float* normal;
+  float* alpha;
+} gs2d_view;
+
+/* Gradients of one view for gs2d_render_backward_batch: image gradients in (any may
+ * be NULL, meaning zero), d_params [15][n] and d_pose [6] out (NULL: not wanted). */
+typedef struct gs2d_view_grad {
+  const float* d_rgb;
+  const float* d_depth;
+  const float* d_normal;
+  const float* d_alpha;
+  float* d_params;
+  float* d_pose;
+} gs2d_view_grad;
+
+/* One independent tracking problem of gs2d_track_batch. */
+typedef struct gs2d_track_problem {
+  const float* params;       /* [15][n] */
+  int64_t n;
+  gs2d_camera camera;
+  float* pose;               /* [12] in: start pose, out: final pose */
+  const float* tgt_rgb;      /* [3][H][W] */
+  const float* tgt_depth;    /* [H][W] */
+} gs2d_track_problem;
 
 /* Kernel-family timings and blend work counters (options.profile = 1). */
 #define GS2D_PROFILE_FAMILIES 12
@@ -159,6 +197,20 @@ GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float
                                   float* d_pose, uint32_t generation, int32_t flags,
                                   hipStream_t stream);
 
+/* Batched forward render of n_views (1..GS2D_MAX_VIEWS) views in one launch per
+ * kernel: one depth sort over every (view, surfel) item, pairs keyed by a global
+ * tile index that places each view's tiles after the previous view's, one tile
+ * sort, and one blend grid over all tiles of all views.  Each view's images equal
+ * what gs2d_render gives for that view alone, bit for bit. */
+GS2D_API int gs2d_render_batch(gs2d_ctx* ctx, const gs2d_view* views, int32_t n_views, uint32_t* generation,
+                               hipStream_t stream);
+
+/* Reverse mode of the batched render `generation`; grads has one entry per view.
+ * Views that share a d_params buffer accumulate into it (the first overwrites unless
+ * GS2D_ACCUMULATE).  Each view's d_pose is its own left-perturbation gradient. */
+GS2D_API int gs2d_render_backward_batch(gs2d_ctx* ctx, const gs2d_view_grad* grads, int32_t n_views,
+                                        uint32_t generation, int32_t flags, hipStream_t stream);
+
 /* Tracking loss of Sec. "Tracking and Keyframe Selection" (eq:tracking_loss):
  * L = (1/HW) sum_p M_n M_o (|rgb - tgt_rgb|_1 + lambda_d |depth - tgt_depth|),
  * M_n = [normal . ray > 0] (eq:normal_mask), M_o = [alpha > 0.95]
@@ -180,6 +232,16 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
  * synchronises).  On a pair overflow the loop restarts from the start pose with
  * larger buffers (up to 3 attempts, then GS2D_ERR_CAPACITY). */
 GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* args, hipStream_t stream);
+
+/* n_problems (1..GS2D_MAX_VIEWS) independent tracking problems stepped together:
+ * every iteration renders all of them in one batched launch per kernel, computes
+ * each one's tracking loss, runs one batched pose-only backward and one AdamW + Exp
+ * step per problem.  `common` supplies lambda_d, use_masks, n_iters, the optimizer
+ * constants and use_graph (its params/n/camera/pose/target fields are ignored);
+ * its pose_history is [n_iters][n_problems][12] and loss_history [n_iters][n_problems].
+ * Same graph caching, synchronisation and restart rules as gs2d_track. */
+GS2D_API int gs2d_track_batch(gs2d_ctx* ctx, const gs2d_track_problem* problems, int32_t n_problems,
+                              const gs2d_track_args* common, hipStream_t stream);
 
 /* pose_out = Exp(tau) pose_in for tau = (rho, phi) [6] and 3x4 poses [12] (device;
  * pose_out may alias pose_in).  The left perturbation of the paper's manifold

@@ -53,6 +53,25 @@ class Tuning(ctypes.Structure):
                 ("ms", ctypes.c_float), ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
+MAX_VIEWS = 32
+
+
+class View(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
+                ("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
+                ("alpha", ctypes.c_void_p)]
+
+
+class ViewGrad(ctypes.Structure):
+    _fields_ = [("d_rgb", ctypes.c_void_p), ("d_depth", ctypes.c_void_p), ("d_normal", ctypes.c_void_p),
+                ("d_alpha", ctypes.c_void_p), ("d_params", ctypes.c_void_p), ("d_pose", ctypes.c_void_p)]
+
+
+class TrackProblem(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
+                ("tgt_rgb", ctypes.c_void_p), ("tgt_depth", ctypes.c_void_p)]
+
+
 class TrackArgs(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera),
                 ("pose", ctypes.c_void_p), ("tgt_rgb", ctypes.c_void_p), ("tgt_depth", ctypes.c_void_p),
@@ -78,6 +97,12 @@ _SIGS = {
     "gs2d_render": ([_P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, _P, _P, _P, _P,
                      ctypes.POINTER(ctypes.c_uint32), _P], ctypes.c_int),
     "gs2d_render_backward": ([_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, ctypes.c_int32, _P], ctypes.c_int),
+    "gs2d_render_batch": ([_P, ctypes.POINTER(View), ctypes.c_int32, ctypes.POINTER(ctypes.c_uint32), _P],
+                          ctypes.c_int),
+    "gs2d_render_backward_batch": ([_P, ctypes.POINTER(ViewGrad), ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
+                                    _P], ctypes.c_int),
+    "gs2d_track_batch": ([_P, ctypes.POINTER(TrackProblem), ctypes.c_int32, ctypes.POINTER(TrackArgs), _P],
+                         ctypes.c_int),
     "gs2d_tracking_loss": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
                             _P, _P, _P, _P], ctypes.c_int),
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),

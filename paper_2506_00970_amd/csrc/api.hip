@@ -157,9 +157,6 @@ int ensure_pixels(gs2d_ctx* ctx, int64_t hw) {
   if (hw <= ctx->hw_cap) return GS2D_OK;
   GS2D_TRY(realloc_dev(ctx, &ctx->t_final, hw));
   GS2D_TRY(realloc_dev(ctx, &ctx->last, hw));
-  GS2D_TRY(realloc_dev(ctx, &ctx->lpart, (int64_t)loss_blocks((int)hw) + 1));
-  if (ctx->lgrad) GS2D_TRY(realloc_dev(ctx, &ctx->lgrad, 4 * hw));
-  if (ctx->limg) GS2D_TRY(realloc_dev(ctx, &ctx->limg, 8 * hw));
   ctx->hw_cap = hw;
   return GS2D_OK;
 }
@@ -206,60 +203,106 @@ bool valid_camera(const gs2d_camera* c) {
          std::isfinite(c->cx) && std::isfinite(c->cy);
 }
 
-// Forward pass.  With allow_sync the pair count is read back after the scan and
-// the pair buffers grow to fit; without it (graph capture, tracking loop) an
-// overflow only raises the device flag.
-int render_impl(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera& cam, const float* pose,
-                float* rgb, float* depth, float* normal, float* alpha, hipStream_t s, bool allow_sync) {
-  const int W = cam.width, H = cam.height;
-  const int64_t HW = (int64_t)W * H;
+
+int ensure_lpart(gs2d_ctx* ctx, int64_t n) {
+  if (n <= ctx->lpart_cap) return GS2D_OK;
+  GS2D_TRY(realloc_dev(ctx, &ctx->lpart, n));
+  ctx->lpart_cap = n;
+  return GS2D_OK;
+}
+
+// Lays out a view table: items, tiles and pixels of view v follow those of view v - 1.
+int build_views(gs2d_ctx* ctx, const gs2d_view* in, int nv, ViewSet& vs) {
+  if (!in || nv < 1 || nv > kMaxViews) return GS2D_ERR_INVALID_ARG;
   const int tw = ctx->opt.tile_w, th = ctx->opt.tile_h;
-  const int tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
-  const int n_tiles = tiles_x * tiles_y;
-  if (n > 0x7FFFFFFF || n_tiles > 65535 * 64) return GS2D_ERR_UNSUPPORTED;
+  vs = ViewSet();
+  vs.n_views = nv;
+  for (int k = 0; k < nv; ++k) {
+    const gs2d_view& g = in[k];
+    if (!valid_camera(&g.camera) || g.n < 0 || (g.n > 0 && !g.params) || !g.pose) return GS2D_ERR_INVALID_ARG;
+    ViewDesc& d = vs.v[k];
+    std::memset(&d, 0, sizeof(d));
+    d.params = g.params;
+    d.pose = const_cast<float*>(g.pose);
+    d.rgb = g.rgb;
+    d.depth = g.depth;
+    d.normal = g.normal;
+    d.alpha = g.alpha;
+    d.cam = camf(g.camera);
+    d.n = (int)g.n;
+    d.tiles_x = (g.camera.width + tw - 1) / tw;
+    d.tiles_y = (g.camera.height + th - 1) / th;
+    d.item_base = (int)vs.items;
+    d.tile_base = (int)vs.tiles;
+    d.pix_base = (int)vs.pixels;
+    const int hw = g.camera.width * g.camera.height;
+    vs.max_hw = hw > vs.max_hw ? hw : vs.max_hw;
+    vs.items += g.n;
+    vs.tiles += (int64_t)d.tiles_x * d.tiles_y;
+    vs.pixels += hw;
+    if (vs.items > 0x7FFFFFFF || vs.pixels > 0x7FFFFFFF) return GS2D_ERR_UNSUPPORTED;
+  }
+  if (vs.tiles > (1 << 24)) return GS2D_ERR_UNSUPPORTED;
+  return GS2D_OK;
+}
+
+BlendArgs blend_args(gs2d_ctx* ctx) {
+  return BlendArgs{ctx->ranges, ctx->pval[ctx->pair_buf], ctx->rec, ctx->views, ctx->last_views.n_views,
+                   (int)ctx->last_views.tiles, ctx->opt.z_near, ctx->opt.filter, ctx->opt.batch};
+}
+
+// Forward pass of a view set.  With allow_sync the pair count is read back after the
+// scan and the pair buffers grow to fit; without it (graph capture, tracking loop) an
+// overflow only raises the device flag.
+int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync) {
+  const int64_t items = vs.items;
+  const int nv = vs.n_views;
   bool capturing = false;
   if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
   const bool grow_ok = !capturing;
-  if ((n > ctx->n_cap || HW > ctx->hw_cap || n_tiles > ctx->tile_cap) && !grow_ok) return GS2D_ERR_CAPACITY;
-  GS2D_TRY(ensure_surfels(ctx, n > 0 ? n : 1));
-  GS2D_TRY(ensure_pixels(ctx, HW));
-  GS2D_TRY(ensure_tiles(ctx, n_tiles));
-  const int64_t rows = n_tiles > (n + 255) / 256 ? n_tiles : (n + 255) / 256;
-  if (rows > ctx->part_cap && !grow_ok) return GS2D_ERR_CAPACITY;
+  int64_t rows = vs.tiles;
+  for (int k = 0; k < nv; ++k) rows = (vs.v[k].n + 255) / 256 > rows ? (vs.v[k].n + 255) / 256 : rows;
+  if ((items > ctx->n_cap || vs.pixels > ctx->hw_cap || vs.tiles > ctx->tile_cap || rows > ctx->part_cap ||
+       ctx->p_cap == 0) &&
+      !grow_ok)
+    return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_surfels(ctx, items > 0 ? items : 1));
+  GS2D_TRY(ensure_pixels(ctx, vs.pixels));
+  GS2D_TRY(ensure_tiles(ctx, vs.tiles));
   GS2D_TRY(ensure_parts(ctx, rows));
-  if (ctx->p_cap == 0) {
-    if (!grow_ok) return GS2D_ERR_CAPACITY;
-    GS2D_TRY(ensure_pairs(ctx, ctx->opt.pair_capacity > 0 ? ctx->opt.pair_capacity : 4 * (n > 0 ? n : 1)));
-  }
-  ctx->tiles_x = tiles_x;
-  ctx->tiles_y = tiles_y;
-  ctx->n_tiles = n_tiles;
-  const CamF cf = camf(cam);
+  if (ctx->p_cap == 0)
+    GS2D_TRY(ensure_pairs(ctx, ctx->opt.pair_capacity > 0 ? ctx->opt.pair_capacity : 4 * (items > 0 ? items : 1)));
+  launch_upload_views(vs, ctx->views, s);
+  const int tw = ctx->opt.tile_w, th = ctx->opt.tile_h;
   int pbuf = 0;
-  if (n == 0) {
-    if (rgb) launch_fill_f32(rgb, 0.f, 3 * HW, s);
-    if (depth) launch_fill_f32(depth, 0.f, HW, s);
-    if (normal) launch_fill_f32(normal, 0.f, 3 * HW, s);
-    if (alpha) launch_fill_f32(alpha, 0.f, HW, s);
-    launch_fill_f32(ctx->t_final, 1.f, HW, s);
-    launch_fill_u32(ctx->last, 0u, HW, s);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ranges), 0u, 2 * (int64_t)n_tiles, s);
+  if (items == 0) {
+    for (int k = 0; k < nv; ++k) {
+      const ViewDesc& d = vs.v[k];
+      const int64_t hw = (int64_t)d.cam.width * d.cam.height;
+      if (d.rgb) launch_fill_f32(d.rgb, 0.f, 3 * hw, s);
+      if (d.depth) launch_fill_f32(d.depth, 0.f, hw, s);
+      if (d.normal) launch_fill_f32(d.normal, 0.f, 3 * hw, s);
+      if (d.alpha) launch_fill_f32(d.alpha, 0.f, hw, s);
+    }
+    launch_fill_f32(ctx->t_final, 1.f, vs.pixels, s);
+    launch_fill_u32(ctx->last, 0u, vs.pixels, s);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ranges), 0u, 2 * vs.tiles, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ctrl), 0u, 3, s);
   } else {
     {
       ProfScope ps(ctx, kPre, s);
-      launch_preprocess(params, (int)n, pose, cf, ctx->opt.z_near, ctx->opt.filter, tw, th, tiles_x, tiles_y,
-                        ctx->rec, ctx->rect, ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, s);
+      launch_preprocess(ctx->views, nv, items, ctx->opt.z_near, ctx->opt.filter, tw, th, ctx->rec, ctx->rect,
+                        ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, s);
     }
     int dbuf;
     {
       ProfScope ps(ctx, kDepthSort, s);
-      dbuf = radix_sort(ctx->dkey, ctx->dval, n, n, nullptr, 32, ctx->hist, s);
+      dbuf = radix_sort(ctx->dkey, ctx->dval, items, items, nullptr, 32, ctx->hist, s);
     }
     if (dbuf != 0) return GS2D_ERR_HIP;  // four 8-bit passes end in buffer 0
     {
       ProfScope ps(ctx, kScan, s);
-      launch_scan_counts(ctx->count, ctx->dval[0], (int)n, ctx->offs, ctx->block_sums, ctx->ctrl, s);
+      launch_scan_counts(ctx->count, ctx->dval[0], (int)items, ctx->offs, ctx->block_sums, ctx->ctrl, s);
     }
     if (allow_sync && !capturing && !ctx->pair_fixed) {
       GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -269,8 +312,8 @@ int render_impl(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera
     }
     {
       ProfScope ps(ctx, kDup, s);
-      launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, (int)n, tiles_x, ctx->p_cap, ctx->pkey[0],
-                       ctx->pval[0], ctx->ctrl, s);
+      launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, ctx->views, nv, (int)items, ctx->p_cap,
+                       ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
     }
     if (ctx->opt.keep_unsorted && ctx->pkey_keep) {
       launch_copy_u32(ctx->pkey[0], ctx->pkey_keep, ctx->p_cap, s);
@@ -278,40 +321,324 @@ int render_impl(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera
     }
     {
       ProfScope ps(ctx, kTileSort, s);
-      pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits(n_tiles), ctx->hist,
-                        s);
+      pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits((int)vs.tiles),
+                        ctx->hist, s);
     }
     {
       ProfScope ps(ctx, kRanges, s);
-      launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, n_tiles, s);
+      launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, (int)vs.tiles, s);
     }
-    BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, cf, ctx->opt.z_near, ctx->opt.filter, tiles_x, n_tiles,
-                 ctx->opt.batch};
+    BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, ctx->views, nv, (int)vs.tiles, ctx->opt.z_near,
+                 ctx->opt.filter, ctx->opt.batch};
     {
       ProfScope ps(ctx, kBlendFwd, s);
-      launch_blend_fwd(ba, tw, th, rgb, depth, normal, alpha, ctx->t_final, ctx->last, work_ptr(ctx, s), s);
+      launch_blend_fwd(ba, tw, th, ctx->t_final, ctx->last, work_ptr(ctx, s), s);
     }
   }
   GS2D_HIP(ctx, hipGetLastError());
   ctx->generation += 1;
-  ctx->last_n = n;
-  ctx->last_cam = cam;
-  ctx->last_params = params;
+  ctx->last_views = vs;
   ctx->pair_buf = pbuf;
   ctx->have_forward = true;
-  ctx->last_blank = n == 0;
   return GS2D_OK;
 }
 
-BlendArgs blend_args(gs2d_ctx* ctx) {
-  return BlendArgs{ctx->ranges, ctx->pval[ctx->pair_buf], ctx->rec, camf(ctx->last_cam), ctx->opt.z_near,
-                   ctx->opt.filter, ctx->tiles_x, ctx->n_tiles, ctx->opt.batch};
+// Reverse mode of the last render for per-view gradients.
+int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, hipStream_t s) {
+  ViewSet vs = ctx->last_views;
+  if (nv != vs.n_views) return GS2D_ERR_INVALID_ARG;
+  bool full = false, hn = false, ho = false;
+  for (int k = 0; k < nv; ++k) {
+    ViewDesc& d = vs.v[k];
+    d.g_rgb = const_cast<float*>(grads[k].d_rgb);
+    d.g_depth = const_cast<float*>(grads[k].d_depth);
+    d.g_normal = grads[k].d_normal;
+    d.g_alpha = grads[k].d_alpha;
+    d.d_pose = grads[k].d_pose;
+    full = full || grads[k].d_params != nullptr;
+    hn = hn || grads[k].d_normal != nullptr;
+    ho = ho || grads[k].d_alpha != nullptr;
+  }
+  if (vs.items == 0) {
+    if (!acc)
+      for (int k = 0; k < nv; ++k)
+        if (grads[k].d_pose) launch_fill_f32(grads[k].d_pose, 0.f, 6, s);
+    GS2D_HIP(ctx, hipGetLastError());
+    return GS2D_OK;
+  }
+  bool capturing = false;
+  if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+  if (full) {
+    if (vs.items > ctx->gacc_cap && capturing) return GS2D_ERR_CAPACITY;
+    GS2D_TRY(ensure_gacc(ctx, vs.items));
+  }
+  launch_upload_views(vs, ctx->views, s);
+  const BlendArgs ba = blend_args(ctx);
+  if (!full) {
+    {
+      ProfScope ps(ctx, kBlendBwd, s);
+      launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, hn, ho, nullptr, ctx->part,
+                       work_ptr(ctx, s), s);
+    }
+    ProfScope ps(ctx, kReduce, s);
+    launch_reduce_pose_views(ctx->views, nv, ctx->part, acc, s);
+  } else {
+    launch_fill_f32(ctx->gacc, 0.f, vs.items * 16, s);
+    {
+      ProfScope ps(ctx, kBlendBwd, s);
+      launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, hn, ho, ctx->gacc,
+                       ctx->part, work_ptr(ctx, s), s);
+    }
+    for (int k = 0; k < nv; ++k) {
+      const ViewDesc& d = vs.v[k];
+      if (d.n == 0) {
+        if (!acc && grads[k].d_pose) launch_fill_f32(grads[k].d_pose, 0.f, 6, s);
+        continue;
+      }
+      // views that share a d_params buffer add into it after the first
+      int acc_k = acc;
+      for (int j = 0; j < k && grads[k].d_params; ++j)
+        if (grads[j].d_params == grads[k].d_params && vs.v[j].n > 0) acc_k = 1;
+      {
+        ProfScope ps(ctx, kPreBwd, s);
+        launch_preprocess_bwd(d.params, d.n, ctx->saved_pose + 12 * k, ctx->gacc + (size_t)16 * d.item_base,
+                              grads[k].d_params, acc_k, ctx->part, s);
+      }
+      if (grads[k].d_pose) {
+        ProfScope ps(ctx, kReduce, s);
+        launch_reduce_pose(ctx->part, 0, (d.n + 255) / 256, grads[k].d_pose, acc, s);
+      }
+    }
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
 }
 
 int set_device(gs2d_ctx* ctx) {
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) GS2D_HIP(ctx, hipSetDevice(ctx->device));
   return GS2D_OK;
+}
+
+// Everything a captured tracking iteration bakes into its kernel arguments.
+struct TrackKeyHead {
+  int32_t n_problems;
+  float lambda_d;
+  int32_t use_masks;
+  float lr[6];
+  float beta1, beta2, eps, weight_decay;
+  int64_t p_cap;
+  int32_t tile_w, tile_h, batch, pad;
+};
+
+std::vector<unsigned char> make_key(gs2d_ctx* ctx, const gs2d_track_problem* p, int np, const gs2d_track_args* a) {
+  TrackKeyHead h;
+  std::memset(&h, 0, sizeof(h));
+  h.n_problems = np;
+  h.lambda_d = a->lambda_d;
+  h.use_masks = a->use_masks;
+  for (int i = 0; i < 6; ++i) h.lr[i] = a->lr[i];
+  h.beta1 = a->beta1;
+  h.beta2 = a->beta2;
+  h.eps = a->eps;
+  h.weight_decay = a->weight_decay;
+  h.p_cap = ctx->p_cap;
+  h.tile_w = ctx->opt.tile_w;
+  h.tile_h = ctx->opt.tile_h;
+  h.batch = ctx->opt.batch;
+  std::vector<unsigned char> key(sizeof(h) + (size_t)np * sizeof(gs2d_track_problem));
+  std::memcpy(key.data(), &h, sizeof(h));
+  for (int k = 0; k < np; ++k) {
+    gs2d_track_problem q;
+    std::memset(&q, 0, sizeof(q));
+    q.params = p[k].params;
+    q.n = p[k].n;
+    q.camera = p[k].camera;
+    q.pose = p[k].pose;
+    q.tgt_rgb = p[k].tgt_rgb;
+    q.tgt_depth = p[k].tgt_depth;
+    std::memcpy(key.data() + sizeof(h) + (size_t)k * sizeof(q), &q, sizeof(q));
+  }
+  return key;
+}
+
+// The view set of a tracking batch: images and gradients in the context's buffers.
+int track_views(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, ViewSet& vs) {
+  gs2d_view in[kMaxViews];
+  for (int k = 0; k < np; ++k) {
+    std::memset(&in[k], 0, sizeof(in[k]));
+    in[k].params = probs[k].params;
+    in[k].n = probs[k].n;
+    in[k].camera = probs[k].camera;
+    in[k].pose = probs[k].pose;
+  }
+  GS2D_TRY(build_views(ctx, in, np, vs));
+  for (int k = 0; k < np; ++k) {
+    ViewDesc& d = vs.v[k];
+    const int64_t hw = (int64_t)d.cam.width * d.cam.height;
+    float* img = ctx->limg + (size_t)8 * d.pix_base;
+    float* grad = ctx->lgrad + (size_t)4 * d.pix_base;
+    d.rgb = img;
+    d.depth = img + 3 * hw;
+    d.normal = img + 4 * hw;
+    d.alpha = img + 7 * hw;
+    d.g_rgb = grad;
+    d.g_depth = grad + 3 * hw;
+    d.tgt_rgb = probs[k].tgt_rgb;
+    d.tgt_depth = probs[k].tgt_depth;
+  }
+  return GS2D_OK;
+}
+
+// One tracking iteration of every problem: batched render, tracking losses, batched
+// pose-only backward, one AdamW + Exp step per problem.  No allocation and no
+// synchronisation (capturable).
+int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, hipStream_t s) {
+  AdamArgs adam;
+  for (int k = 0; k < 6; ++k) adam.lr[k] = a->lr[k];
+  adam.beta1 = a->beta1;
+  adam.beta2 = a->beta2;
+  adam.eps = a->eps;
+  adam.weight_decay = a->weight_decay;
+  GS2D_TRY(render_views(ctx, vs, s, false));
+  const int stride = loss_blocks(vs.max_hw);
+  {
+    ProfScope ps(ctx, kLoss, s);
+    launch_tracking_loss(ctx->views, vs.n_views, vs.max_hw, a->lambda_d, a->use_masks, ctx->lpart, stride, s);
+  }
+  if (vs.items > 0) {
+    ProfScope ps(ctx, kBlendBwd, s);
+    launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, false, false,
+                     nullptr, ctx->part, work_ptr(ctx, s), s);
+  } else {
+    launch_fill_f32(ctx->part, 0.f, 8 * vs.tiles, s);
+  }
+  {
+    ProfScope ps(ctx, kPose, s);
+    launch_pose_step(ctx->views, vs.n_views, ctx->part, ctx->lpart, stride, adam, ctx->ctrl, s);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2d_track_args* a,
+               hipStream_t caller_stream) {
+  if (!ctx || !probs || !a || np < 1 || np > kMaxViews || a->n_iters < 0) return GS2D_ERR_INVALID_ARG;
+  for (int k = 0; k < np; ++k)
+    if (!valid_camera(&probs[k].camera) || probs[k].n < 0 || (probs[k].n > 0 && !probs[k].params) ||
+        !probs[k].pose || !probs[k].tgt_rgb || !probs[k].tgt_depth)
+      return GS2D_ERR_INVALID_ARG;
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.f) return GS2D_ERR_INVALID_ARG;
+  if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f) ||
+      !std::isfinite(a->lambda_d))
+    return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  bool capturing = false;
+  if (stream_capturing(caller_stream, &capturing) != 0 || capturing) return GS2D_ERR_INVALID_ARG;
+  // The loop runs on the caller's stream, or, to be captured into a graph, on a
+  // stream of the context (the legacy null stream cannot be captured).
+  hipStream_t s = caller_stream;
+  if (a->use_graph) {
+    if (!ctx->graph_stream) GS2D_HIP(ctx, hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
+    GS2D_HIP(ctx, hipStreamSynchronize(caller_stream));
+    s = ctx->graph_stream;
+  }
+  // pixel layout first (buffers for the loop's images and gradients)
+  int64_t pixels = 0, max_hw = 0;
+  for (int k = 0; k < np; ++k) {
+    const int64_t hw = (int64_t)probs[k].camera.width * probs[k].camera.height;
+    pixels += hw;
+    max_hw = hw > max_hw ? hw : max_hw;
+  }
+  GS2D_TRY(ensure_pixels(ctx, pixels));
+  if (ctx->img_cap < ctx->hw_cap || !ctx->limg || !ctx->lgrad) {
+    GS2D_TRY(realloc_dev(ctx, &ctx->limg, 8 * ctx->hw_cap));
+    GS2D_TRY(realloc_dev(ctx, &ctx->lgrad, 4 * ctx->hw_cap));
+    ctx->img_cap = ctx->hw_cap;
+  }
+  GS2D_TRY(ensure_lpart(ctx, (int64_t)np * loss_blocks((int)max_hw)));
+  ViewSet vs;
+  GS2D_TRY(track_views(ctx, probs, np, vs));
+  for (int k = 0; k < np; ++k)
+    GS2D_HIP(ctx, hipMemcpyAsync(ctx->pose0 + 12 * k, probs[k].pose, 12 * sizeof(float), hipMemcpyDeviceToDevice,
+                                 s));
+  const bool was_fixed = ctx->pair_fixed;
+  int result = GS2D_ERR_CAPACITY;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if (attempt > 0)
+      for (int k = 0; k < np; ++k)
+        GS2D_HIP(ctx, hipMemcpyAsync(probs[k].pose, ctx->pose0 + 12 * k, 12 * sizeof(float),
+                                     hipMemcpyDeviceToDevice, s));
+    std::vector<unsigned char> key = make_key(ctx, probs, np, a);
+    const bool reuse = a->use_graph && attempt == 0 && ctx->track_valid && ctx->track_key == key;
+    if (!reuse) {
+      // size the pair buffers on the start poses, with headroom for the moving poses
+      ctx->pair_fixed = false;
+      int r = render_views(ctx, vs, s, true);
+      if (r == GS2D_OK) {
+        const int64_t npairs = ctx->host_ctrl->n_pairs;
+        r = ensure_pairs(ctx, (npairs + npairs / 2 + 1024) << attempt);
+      }
+      if (r == GS2D_OK) r = ensure_lpart(ctx, (int64_t)np * loss_blocks((int)max_hw));
+      if (r != GS2D_OK) {
+        ctx->pair_fixed = was_fixed;
+        return r;
+      }
+    }
+    ctx->pair_fixed = true;
+    launch_upload_views(vs, ctx->views, s);
+    launch_track_init(ctx->views, np, ctx->ctrl, a->pose_history, a->loss_history, a->n_iters, s);
+    int r = GS2D_OK;
+    if (a->use_graph && a->n_iters > 0) {
+      if (!reuse) {
+        invalidate_graph(ctx);
+        GS2D_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int ri = track_iteration(ctx, vs, a, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (ri != GS2D_OK || ec != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          ctx->pair_fixed = was_fixed;
+          return ri != GS2D_OK ? ri : fail_hip(ctx, ec);
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          (void)hipGraphDestroy(graph);
+          ctx->pair_fixed = was_fixed;
+          return fail_hip(ctx, ei);
+        }
+        ctx->track_graph = graph;
+        ctx->track_exec = exec;
+        ctx->track_key = make_key(ctx, probs, np, a);
+        ctx->track_valid = true;
+      }
+      for (int it = 0; it < a->n_iters; ++it) {
+        const hipError_t el = hipGraphLaunch(ctx->track_exec, s);
+        if (el != hipSuccess) {
+          ctx->pair_fixed = was_fixed;
+          return fail_hip(ctx, el);
+        }
+      }
+    } else {
+      for (int it = 0; it < a->n_iters && r == GS2D_OK; ++it) r = track_iteration(ctx, vs, a, s);
+    }
+    if (r != GS2D_OK) {
+      ctx->pair_fixed = was_fixed;
+      return r;
+    }
+    GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    GS2D_HIP(ctx, hipStreamSynchronize(s));
+    if (!ctx->host_ctrl->overflow) {
+      result = GS2D_OK;
+      break;
+    }
+    invalidate_graph(ctx);
+  }
+  ctx->pair_fixed = was_fixed;
+  ctx->have_forward = false;  // the loop's internal render state is not a public forward
+  return result;
 }
 
 }  // namespace
@@ -353,8 +680,9 @@ GS2D_API int gs2d_create(gs2d_ctx** out, int device, const gs2d_options* opt) {
   ctx->opt = o;
   int r = set_device(ctx);
   if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->ctrl, 1);
-  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->saved_pose, 12);
-  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->pose0, 12);
+  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->saved_pose, 12 * kMaxViews);
+  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->pose0, 12 * kMaxViews);
+  if (r == GS2D_OK) r = realloc_dev(ctx, &ctx->views, kMaxViews);
   if (r == GS2D_OK) {
     hipError_t e = hipHostMalloc((void**)&ctx->host_ctrl, sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) r = fail_hip(ctx, e);
@@ -378,15 +706,15 @@ GS2D_API int gs2d_create(gs2d_ctx** out, int device, const gs2d_options* opt) {
 GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
   if (!ctx) return GS2D_OK;
   (void)set_device(ctx);
-  void* bufs[] = {ctx->rec,     ctx->rect,     ctx->count,   ctx->dkey[0],   ctx->dkey[1],   ctx->dval[0],
-                  ctx->dval[1], ctx->offs,     ctx->block_sums, ctx->hist,  ctx->gacc,      ctx->pkey[0],
-                  ctx->pkey[1], ctx->pval[0],  ctx->pval[1],  ctx->pkey_keep, ctx->pval_keep, ctx->ranges,
-                  ctx->t_final, ctx->last,     ctx->lgrad,    ctx->limg,      ctx->part,      ctx->lpart,
-                  ctx->pose0,   ctx->saved_pose, ctx->ctrl};
+  invalidate_graph(ctx);
+  void* bufs[] = {ctx->rec,       ctx->rect,     ctx->count,      ctx->dkey[0],   ctx->dkey[1],    ctx->dval[0],
+                  ctx->dval[1],   ctx->offs,     ctx->block_sums, ctx->hist,      ctx->gacc,       ctx->pkey[0],
+                  ctx->pkey[1],   ctx->pval[0],  ctx->pval[1],    ctx->pkey_keep, ctx->pval_keep,  ctx->ranges,
+                  ctx->t_final,   ctx->last,     ctx->lgrad,      ctx->limg,      ctx->part,       ctx->lpart,
+                  ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);
-  invalidate_graph(ctx);
   if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
   for (int i = 0; i < ctx->ev_cap; ++i) {
     (void)hipEventDestroy(ctx->ev[i].a);
@@ -401,8 +729,17 @@ GS2D_API int gs2d_render(gs2d_ctx* ctx, const float* params, int64_t n, const gs
                          const float* pose, float* rgb, float* depth, float* normal, float* alpha,
                          uint32_t* generation, hipStream_t stream) {
   if (!ctx || !valid_camera(camera) || n < 0 || (n > 0 && !params) || !pose) return GS2D_ERR_INVALID_ARG;
+  gs2d_view v{params, n, *camera, pose, rgb, depth, normal, alpha};
+  return gs2d_render_batch(ctx, &v, 1, generation, stream);
+}
+
+GS2D_API int gs2d_render_batch(gs2d_ctx* ctx, const gs2d_view* views, int32_t n_views, uint32_t* generation,
+                               hipStream_t stream) {
+  if (!ctx) return GS2D_ERR_INVALID_ARG;
+  ViewSet vs;
+  GS2D_TRY(build_views(ctx, views, n_views, vs));
   GS2D_TRY(set_device(ctx));
-  GS2D_TRY(render_impl(ctx, params, n, *camera, pose, rgb, depth, normal, alpha, stream, true));
+  GS2D_TRY(render_views(ctx, vs, stream, true));
   if (generation) *generation = ctx->generation;
   return GS2D_OK;
 }
@@ -411,50 +748,18 @@ GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float
                                   const float* d_normal, const float* d_alpha, float* d_params,
                                   float* d_pose, uint32_t generation, int32_t flags, hipStream_t stream) {
   if (!ctx) return GS2D_ERR_INVALID_ARG;
+  gs2d_view_grad g{d_rgb, d_depth, d_normal, d_alpha, d_params, d_pose};
+  return gs2d_render_backward_batch(ctx, &g, 1, generation, flags, stream);
+}
+
+GS2D_API int gs2d_render_backward_batch(gs2d_ctx* ctx, const gs2d_view_grad* grads, int32_t n_views,
+                                        uint32_t generation, int32_t flags, hipStream_t stream) {
+  if (!ctx || !grads || n_views < 1 || n_views > kMaxViews) return GS2D_ERR_INVALID_ARG;
   if ((flags & ~GS2D_ACCUMULATE) != 0) return GS2D_ERR_INVALID_ARG;
   if (!ctx->have_forward || generation != ctx->generation) return GS2D_ERR_STATE;
+  if (n_views != ctx->last_views.n_views) return GS2D_ERR_INVALID_ARG;
   GS2D_TRY(set_device(ctx));
-  const int acc = (flags & GS2D_ACCUMULATE) ? 1 : 0;
-  const int64_t n = ctx->last_n;
-  const hipStream_t s = stream;
-  if (n == 0) {
-    if (!acc && d_pose) launch_fill_f32(d_pose, 0.f, 6, s);
-    GS2D_HIP(ctx, hipGetLastError());
-    return GS2D_OK;
-  }
-  const BlendArgs ba = blend_args(ctx);
-  if (!d_params) {
-    {
-      ProfScope ps(ctx, kBlendBwd, s);
-      launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
-                       d_alpha, nullptr, ctx->part, work_ptr(ctx, s), s);
-    }
-    if (d_pose) {
-      ProfScope ps(ctx, kReduce, s);
-      launch_reduce_pose(ctx->part, ctx->n_tiles, d_pose, acc, s);
-    }
-  } else {
-    bool capturing = false;
-    if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
-    if (n > ctx->gacc_cap && capturing) return GS2D_ERR_CAPACITY;
-    GS2D_TRY(ensure_gacc(ctx, n));
-    launch_fill_f32(ctx->gacc, 0.f, n * 16, s);
-    {
-      ProfScope ps(ctx, kBlendBwd, s);
-      launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, d_rgb, d_depth, d_normal,
-                       d_alpha, ctx->gacc, ctx->part, work_ptr(ctx, s), s);
-    }
-    {
-      ProfScope ps(ctx, kPreBwd, s);
-      launch_preprocess_bwd(ctx->last_params, (int)n, ctx->saved_pose, ctx->gacc, d_params, acc, ctx->part, s);
-    }
-    if (d_pose) {
-      ProfScope ps(ctx, kReduce, s);
-      launch_reduce_pose(ctx->part, (int)((n + 255) / 256), d_pose, acc, s);
-    }
-  }
-  GS2D_HIP(ctx, hipGetLastError());
-  return GS2D_OK;
+  return backward_views(ctx, grads, n_views, (flags & GS2D_ACCUMULATE) ? 1 : 0, stream);
 }
 
 GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const float* rgb, const float* depth,
@@ -466,199 +771,46 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
   if (use_masks && (!normal || !alpha)) return GS2D_ERR_INVALID_ARG;
   if (!std::isfinite(lambda_d)) return GS2D_ERR_INVALID_ARG;
   GS2D_TRY(set_device(ctx));
-  const int64_t HW = (int64_t)camera->width * camera->height;
+  const int hw = camera->width * camera->height;
   bool capturing = false;
   if (stream_capturing(stream, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
-  if (HW > ctx->hw_cap && capturing) return GS2D_ERR_CAPACITY;
-  GS2D_TRY(ensure_pixels(ctx, HW));
-  int nparts = 0;
+  if (loss_blocks(hw) > ctx->lpart_cap && capturing) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_lpart(ctx, loss_blocks(hw)));
+  ViewSet vs;
+  vs.n_views = 1;
+  ViewDesc& d = vs.v[0];
+  std::memset(&d, 0, sizeof(d));
+  d.cam = camf(*camera);
+  d.rgb = const_cast<float*>(rgb);
+  d.depth = const_cast<float*>(depth);
+  d.normal = const_cast<float*>(normal);
+  d.alpha = const_cast<float*>(alpha);
+  d.tgt_rgb = tgt_rgb;
+  d.tgt_depth = tgt_depth;
+  d.g_rgb = d_rgb;
+  d.g_depth = d_depth;
+  launch_upload_views(vs, ctx->views, stream);
   {
     ProfScope ps(ctx, kLoss, stream);
-    launch_tracking_loss(camf(*camera), rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks, d_rgb,
-                         d_depth, ctx->lpart, &nparts, stream);
+    launch_tracking_loss(ctx->views, 1, hw, lambda_d, use_masks, ctx->lpart, loss_blocks(hw), stream);
   }
   {
     ProfScope ps(ctx, kReduce, stream);
-    launch_reduce_loss(ctx->lpart, nparts, 1.0f / (float)HW, loss, nullptr, stream);
+    launch_reduce_loss(ctx->lpart, loss_blocks(hw), 1.0f / (float)hw, loss, stream);
   }
   GS2D_HIP(ctx, hipGetLastError());
   return GS2D_OK;
 }
-
-namespace {
-// Everything the captured tracking iteration bakes into its kernel arguments.
-struct TrackKey {
-  const float* params;
-  int64_t n;
-  gs2d_camera cam;
-  float* pose;
-  const float* tgt_rgb;
-  const float* tgt_depth;
-  float lambda_d;
-  int32_t use_masks;
-  float lr[6];
-  float beta1, beta2, eps, weight_decay;
-  int64_t p_cap;
-};
-static_assert(sizeof(TrackKey) <= sizeof(((gs2d_ctx*)nullptr)->track_key), "track key size");
-
-TrackKey make_key(gs2d_ctx* ctx, const gs2d_track_args* a) {
-  TrackKey k;
-  std::memset(&k, 0, sizeof(k));
-  k.params = a->params;
-  k.n = a->n;
-  k.cam = a->camera;
-  k.pose = a->pose;
-  k.tgt_rgb = a->tgt_rgb;
-  k.tgt_depth = a->tgt_depth;
-  k.lambda_d = a->lambda_d;
-  k.use_masks = a->use_masks;
-  for (int i = 0; i < 6; ++i) k.lr[i] = a->lr[i];
-  k.beta1 = a->beta1;
-  k.beta2 = a->beta2;
-  k.eps = a->eps;
-  k.weight_decay = a->weight_decay;
-  k.p_cap = ctx->p_cap;
-  return k;
-}
-
-// One tracking iteration: render at the current pose, tracking loss, pose-only
-// backward, AdamW + Exp step.  No allocation and no synchronisation (capturable).
-int track_iteration(gs2d_ctx* ctx, const gs2d_track_args* a, float* img, float* grad, hipStream_t s) {
-  const gs2d_camera cam = a->camera;
-  const int64_t HW = (int64_t)cam.width * cam.height;
-  float *rgb = img, *depth = img + 3 * HW, *normal = img + 4 * HW, *alpha = img + 7 * HW;
-  float *g_rgb = grad, *g_depth = grad + 3 * HW;
-  AdamArgs adam;
-  for (int k = 0; k < 6; ++k) adam.lr[k] = a->lr[k];
-  adam.beta1 = a->beta1;
-  adam.beta2 = a->beta2;
-  adam.eps = a->eps;
-  adam.weight_decay = a->weight_decay;
-  GS2D_TRY(render_impl(ctx, a->params, a->n, cam, a->pose, rgb, depth, normal, alpha, s, false));
-  int nparts = 0;
-  {
-    ProfScope ps(ctx, kLoss, s);
-    launch_tracking_loss(camf(cam), rgb, depth, normal, alpha, a->tgt_rgb, a->tgt_depth, a->lambda_d, a->use_masks,
-                         g_rgb, g_depth, ctx->lpart, &nparts, s);
-  }
-  if (a->n > 0) {
-    ProfScope ps(ctx, kBlendBwd, s);
-    launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, g_rgb, g_depth,
-                     nullptr, nullptr, nullptr, ctx->part, work_ptr(ctx, s), s);
-  } else {
-    launch_fill_f32(ctx->part, 0.f, 8, s);
-  }
-  {
-    ProfScope ps(ctx, kPose, s);
-    launch_pose_step(ctx->part, a->n > 0 ? ctx->n_tiles : 1, ctx->lpart, nparts, 1.0f / (float)HW, adam, a->pose,
-                     ctx->ctrl, s);
-  }
-  GS2D_HIP(ctx, hipGetLastError());
-  return GS2D_OK;
-}
-}  // namespace
 
 GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* a, hipStream_t caller_stream) {
-  if (!ctx || !a || !valid_camera(&a->camera) || a->n < 0 || (a->n > 0 && !a->params) || !a->pose ||
-      !a->tgt_rgb || !a->tgt_depth || a->n_iters < 0)
-    return GS2D_ERR_INVALID_ARG;
-  for (int k = 0; k < 6; ++k)
-    if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.f) return GS2D_ERR_INVALID_ARG;
-  if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f) ||
-      !std::isfinite(a->lambda_d))
-    return GS2D_ERR_INVALID_ARG;
-  GS2D_TRY(set_device(ctx));
-  bool capturing = false;
-  if (stream_capturing(caller_stream, &capturing) != 0 || capturing) return GS2D_ERR_INVALID_ARG;
-  // The loop runs on the caller's stream, or, to be captured into a graph, on a
-  // stream of the context (the legacy null stream cannot be captured).
-  hipStream_t s = caller_stream;
-  if (a->use_graph) {
-    if (!ctx->graph_stream) GS2D_HIP(ctx, hipStreamCreateWithFlags(&ctx->graph_stream, hipStreamNonBlocking));
-    GS2D_HIP(ctx, hipStreamSynchronize(caller_stream));
-    s = ctx->graph_stream;
-  }
-  const int64_t HW = (int64_t)a->camera.width * a->camera.height;
-  GS2D_TRY(ensure_pixels(ctx, HW));
-  if (!ctx->lgrad) GS2D_TRY(realloc_dev(ctx, &ctx->lgrad, 4 * ctx->hw_cap));
-  if (!ctx->limg) GS2D_TRY(realloc_dev(ctx, &ctx->limg, 8 * ctx->hw_cap));
-  GS2D_HIP(ctx, hipMemcpyAsync(ctx->pose0, a->pose, 12 * sizeof(float), hipMemcpyDeviceToDevice, s));
-  const bool was_fixed = ctx->pair_fixed;
-  int result = GS2D_ERR_CAPACITY;
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    if (attempt > 0)
-      GS2D_HIP(ctx, hipMemcpyAsync(a->pose, ctx->pose0, 12 * sizeof(float), hipMemcpyDeviceToDevice, s));
-    TrackKey key = make_key(ctx, a);
-    const bool reuse = a->use_graph && attempt == 0 && ctx->track_valid &&
-                       std::memcmp(ctx->track_key, &key, sizeof(key)) == 0;
-    if (!reuse) {
-      // size the pair buffers on the start pose, with headroom for the moving pose
-      ctx->pair_fixed = false;
-      int r = render_impl(ctx, a->params, a->n, a->camera, a->pose, ctx->limg, ctx->limg + 3 * HW,
-                          ctx->limg + 4 * HW, ctx->limg + 7 * HW, s, true);
-      if (r == GS2D_OK) {
-        const int64_t np = ctx->host_ctrl->n_pairs;
-        r = ensure_pairs(ctx, (np + np / 2 + 1024) << attempt);
-      }
-      if (r != GS2D_OK) {
-        ctx->pair_fixed = was_fixed;
-        return r;
-      }
-    }
-    ctx->pair_fixed = true;
-    launch_track_init(a->pose, ctx->ctrl, a->pose_history, a->loss_history, a->n_iters, s);
-    int r = GS2D_OK;
-    if (a->use_graph && a->n_iters > 0) {
-      if (!reuse) {
-        invalidate_graph(ctx);
-        GS2D_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const int ri = track_iteration(ctx, a, ctx->limg, ctx->lgrad, s);
-        hipGraph_t graph = nullptr;
-        const hipError_t ec = hipStreamEndCapture(s, &graph);
-        if (ri != GS2D_OK || ec != hipSuccess) {
-          if (graph) (void)hipGraphDestroy(graph);
-          ctx->pair_fixed = was_fixed;
-          return ri != GS2D_OK ? ri : fail_hip(ctx, ec);
-        }
-        hipGraphExec_t exec = nullptr;
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ei != hipSuccess) {
-          (void)hipGraphDestroy(graph);
-          ctx->pair_fixed = was_fixed;
-          return fail_hip(ctx, ei);
-        }
-        ctx->track_graph = graph;
-        ctx->track_exec = exec;
-        key = make_key(ctx, a);
-        std::memcpy(ctx->track_key, &key, sizeof(key));
-        ctx->track_valid = true;
-      }
-      for (int it = 0; it < a->n_iters; ++it) {
-        const hipError_t el = hipGraphLaunch(ctx->track_exec, s);
-        if (el != hipSuccess) {
-          ctx->pair_fixed = was_fixed;
-          return fail_hip(ctx, el);
-        }
-      }
-    } else {
-      for (int it = 0; it < a->n_iters && r == GS2D_OK; ++it) r = track_iteration(ctx, a, ctx->limg, ctx->lgrad, s);
-    }
-    if (r != GS2D_OK) {
-      ctx->pair_fixed = was_fixed;
-      return r;
-    }
-    GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    GS2D_HIP(ctx, hipStreamSynchronize(s));
-    if (!ctx->host_ctrl->overflow) {
-      result = GS2D_OK;
-      break;
-    }
-    invalidate_graph(ctx);
-  }
-  ctx->pair_fixed = was_fixed;
-  ctx->have_forward = false;  // the loop's internal render state is not a public forward
-  return result;
+  if (!ctx || !a) return GS2D_ERR_INVALID_ARG;
+  gs2d_track_problem p{a->params, a->n, a->camera, a->pose, a->tgt_rgb, a->tgt_depth};
+  return track_impl(ctx, &p, 1, a, caller_stream);
+}
+
+GS2D_API int gs2d_track_batch(gs2d_ctx* ctx, const gs2d_track_problem* problems, int32_t n_problems,
+                              const gs2d_track_args* common, hipStream_t stream) {
+  return track_impl(ctx, problems, n_problems, common, stream);
 }
 
 GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream) {
@@ -666,12 +818,13 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
   GS2D_TRY(set_device(ctx));
   GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
   GS2D_HIP(ctx, hipStreamSynchronize(stream));
-  out->n_surfels = ctx->last_n;
-  out->n_visible = ctx->last_blank ? 0 : ctx->host_ctrl->n_visible;
-  out->n_pairs = ctx->last_blank ? 0 : ctx->host_ctrl->n_pairs;
+  const bool blank = ctx->last_views.items == 0;
+  out->n_surfels = ctx->last_views.items;
+  out->n_visible = blank ? 0 : ctx->host_ctrl->n_visible;
+  out->n_pairs = blank ? 0 : ctx->host_ctrl->n_pairs;
   out->pair_capacity = ctx->p_cap;
   out->overflow = ctx->host_ctrl->overflow ? 1 : 0;
-  out->n_tiles = ctx->n_tiles;
+  out->n_tiles = (int32_t)ctx->last_views.tiles;
   return GS2D_OK;
 }
 
@@ -680,21 +833,21 @@ GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_
   if (!ctx->have_forward) return GS2D_ERR_STATE;
   gs2d_counts c;
   GS2D_TRY(gs2d_get_counts(ctx, &c, stream));
-  const int64_t HW = (int64_t)ctx->last_cam.width * ctx->last_cam.height;
+  const int64_t items = ctx->last_views.items, pixels = ctx->last_views.pixels;
   const void* src = nullptr;
   size_t need = 0;
   const int64_t np = c.n_pairs < ctx->p_cap ? c.n_pairs : ctx->p_cap;
   switch (which) {
     case 0: src = ctx->pkey[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 1: src = ctx->pval[ctx->pair_buf]; need = (size_t)np * 4; break;
-    case 2: src = ctx->ranges; need = (size_t)ctx->n_tiles * 8; break;
-    case 3: src = ctx->dkey[0]; need = (size_t)ctx->last_n * 4; break;
-    case 4: src = ctx->rect; need = (size_t)ctx->last_n * 8; break;
-    case 5: src = ctx->t_final; need = (size_t)HW * 4; break;
-    case 6: src = ctx->last; need = (size_t)HW * 4; break;
+    case 2: src = ctx->ranges; need = (size_t)ctx->last_views.tiles * 8; break;
+    case 3: src = ctx->dkey[0]; need = (size_t)items * 4; break;
+    case 4: src = ctx->rect; need = (size_t)items * 8; break;
+    case 5: src = ctx->t_final; need = (size_t)pixels * 4; break;
+    case 6: src = ctx->last; need = (size_t)pixels * 4; break;
     case 7: src = ctx->pkey_keep; need = (size_t)np * 4; break;
     case 8: src = ctx->pval_keep; need = (size_t)np * 4; break;
-    case 9: src = ctx->dval[0]; need = (size_t)ctx->last_n * 4; break;
+    case 9: src = ctx->dval[0]; need = (size_t)items * 4; break;
     default: return GS2D_ERR_INVALID_ARG;
   }
   if (!src) return GS2D_ERR_UNSUPPORTED;
@@ -748,12 +901,7 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
   }
   const int64_t HW = (int64_t)camera->width * camera->height;
   float* img = nullptr;
-  float* dpose = nullptr;
-  GS2D_HIP(ctx, hipMalloc((void**)&img, (size_t)8 * HW * sizeof(float)));
-  if (hipMalloc((void**)&dpose, 8 * sizeof(float)) != hipSuccess) {
-    (void)hipFree(img);
-    return fail_hip(ctx, hipErrorOutOfMemory);
-  }
+  GS2D_HIP(ctx, hipMalloc((void**)&img, (size_t)(8 * HW + 8) * sizeof(float)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -761,29 +909,35 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
   const int batches[4] = {32, 64, 128, 256};
   const gs2d_options saved = ctx->opt;
   const bool saved_fixed = ctx->pair_fixed;
-  const int saved_prof = ctx->opt.profile;
   ctx->opt.profile = 0;
   float best = 1e30f;
   int bt = saved.tile_w, bh = saved.tile_h, bb = saved.batch;
   int r = GS2D_OK;
+  gs2d_view v{params, n, *camera, pose, img, img + 3 * HW, img + 4 * HW, img + 7 * HW};
   for (int ti = 0; ti < 4 && r == GS2D_OK; ++ti)
     for (int bi = 0; bi < 4 && r == GS2D_OK; ++bi) {
       ctx->opt.tile_w = tiles[ti][0];
       ctx->opt.tile_h = tiles[ti][1];
       ctx->opt.batch = batches[bi];
+      ViewSet vs;
+      r = build_views(ctx, &v, 1, vs);
+      if (r != GS2D_OK) break;
+      // the image buffer doubles as the image gradient of the timed backward
+      vs.v[0].g_rgb = img;
+      vs.v[0].g_depth = img + 3 * HW;
+      vs.v[0].d_pose = img + 8 * HW;
       ctx->pair_fixed = false;
       // one synchronising warm-up sizes the pair buffers for this tile shape
-      r = render_impl(ctx, params, n, *camera, pose, img, img + 3 * HW, img + 4 * HW, img + 7 * HW, stream, true);
+      r = render_views(ctx, vs, stream, true);
       if (r != GS2D_OK) break;
       ctx->pair_fixed = true;
       (void)hipEventRecord(e0, stream);
       for (int k = 0; k < reps && r == GS2D_OK; ++k) {
-        r = render_impl(ctx, params, n, *camera, pose, img, img + 3 * HW, img + 4 * HW, img + 7 * HW, stream,
-                        false);
+        r = render_views(ctx, vs, stream, false);
         if (r == GS2D_OK) {
-          launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, img,
-                           img + 3 * HW, nullptr, nullptr, nullptr, ctx->part, nullptr, stream);
-          launch_reduce_pose(ctx->part, ctx->n_tiles, dpose, 0, stream);
+          launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, false, false,
+                           nullptr, ctx->part, nullptr, stream);
+          launch_reduce_pose_views(ctx->views, 1, ctx->part, 0, stream);
         }
       }
       (void)hipEventRecord(e1, stream);
@@ -805,10 +959,10 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(stream);
   (void)hipFree(img);
-  (void)hipFree(dpose);
   ctx->pair_fixed = saved_fixed;
-  ctx->opt.profile = saved_prof;
+  ctx->opt.profile = saved.profile;
   ctx->opt.tile_w = bt;
   ctx->opt.tile_h = bh;
   ctx->opt.batch = bb;

@@ -40,13 +40,14 @@ struct Hit {
 // function so that every decision is reproduced bit for bit.  Returns 0 outside
 // the footprint (rho > 9 or depth < z_near), 1 inside it but below the opacity
 // threshold, 2 when the pair is composited.
-__device__ __forceinline__ int evaluate(float px, float py, const float4 g1, const float4 g2,
+__device__ __forceinline__ int evaluate(float px, float py, float ox, float oy, const float4 g1, const float4 g2,
                                         const float4 g3, float o, float z_near, int filter, Hit& h) {
-  const float cx = g1.x, cy = g1.y, Dt = g1.z, k0 = g1.w;
+  // (ox, oy): the integer box corner; g1.xy: the projected centre relative to it
+  const float cxr = g1.x, cyr = g1.y, Dt = g1.z, k0 = g1.w;
   const float k1 = g2.x, P0 = g2.y, P1 = g2.z, Q0 = g2.w;
   const float Q1 = g3.x, m0 = g3.y, m1 = g3.z, m2 = g3.w;
-  h.dx = px - cx;
-  h.dy = py - cy;
+  h.dx = (px - ox) - cxr;  // px - ox is exact (integers below 2^24)
+  h.dy = (py - oy) - cyr;
   const float q2 = fmaf(-h.dy, k1, fmaf(-h.dx, k0, Dt));
   const float e0 = fmaf(Q1, h.dx, -(P1 * h.dy));
   const float e1 = fmaf(P0, h.dy, -(Q0 * h.dx));
@@ -102,21 +103,19 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 template <int TW, int TH, bool PROF>
-__global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ rgb,
-                                                           float* __restrict__ depth,
-                                                           float* __restrict__ normal,
-                                                           float* __restrict__ alpha,
-                                                           float* __restrict__ t_final,
+__global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ t_final,
                                                            uint32_t* __restrict__ last_out,
                                                            unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8;
   extern __shared__ float4 srec[];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // global tile over all views
+  const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int wx0 = tx * TW + (wave % WX) * 8, wy0 = ty * TH + (wave / WX) * 8;
   const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
-  const bool inside = px < a.cam.width && py < a.cam.height;
+  const bool inside = px < V.cam.width && py < V.cam.height;
   const float fpx = (float)px, fpy = (float)py;
   const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
   const uint2 rg = a.ranges[tile];
@@ -141,8 +140,8 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
       if (!done) {
         const float4 c4 = srec[j * kRecF4 + 4];
         Hit h;
-        const int code = evaluate(fpx, fpy, srec[j * kRecF4 + 1], srec[j * kRecF4 + 2], srec[j * kRecF4 + 3],
-                                  c4.x, a.z_near, a.filter, h);
+        const int code = evaluate(fpx, fpy, bb.x, bb.z, srec[j * kRecF4 + 1], srec[j * kRecF4 + 2],
+                                  srec[j * kRecF4 + 3], c4.x, a.z_near, a.filter, h);
         if (PROF) {
           n_eval += 1;
           n_cov += code > 0;
@@ -171,65 +170,67 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   }
   if (PROF) add_work(work, lane, n_eval, n_cov);
   if (!inside) return;
-  const int HW = a.cam.width * a.cam.height;
-  const int p = py * a.cam.width + px;
-  if (rgb) {
-    rgb[p] = cr;
-    rgb[HW + p] = cg;
-    rgb[2 * HW + p] = cb;
+  const int HW = V.cam.width * V.cam.height;
+  const int p = py * V.cam.width + px;
+  if (V.rgb) {
+    V.rgb[p] = cr;
+    V.rgb[HW + p] = cg;
+    V.rgb[2 * HW + p] = cb;
   }
-  if (depth) depth[p] = cd;
-  if (normal) {
-    normal[p] = n0;
-    normal[HW + p] = n1;
-    normal[2 * HW + p] = n2;
+  if (V.depth) V.depth[p] = cd;
+  if (V.normal) {
+    V.normal[p] = n0;
+    V.normal[HW + p] = n1;
+    V.normal[2 * HW + p] = n2;
   }
-  if (alpha) alpha[p] = co;
-  t_final[p] = T;
-  last_out[p] = (uint32_t)lastj;
+  if (V.alpha) V.alpha[p] = co;
+  t_final[V.pix_base + p] = T;
+  last_out[V.pix_base + p] = (uint32_t)lastj;
 }
 
 template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>
-__global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
-    BlendArgs a, const float* __restrict__ t_final, const uint32_t* __restrict__ last_in,
-    const float* __restrict__ g_rgb, const float* __restrict__ g_depth, const float* __restrict__ g_normal,
-    const float* __restrict__ g_alpha, float* __restrict__ gacc, float* __restrict__ part,
-    unsigned long long* __restrict__ work) {
+__global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const float* __restrict__ t_final,
+                                                           const uint32_t* __restrict__ last_in,
+                                                           float* __restrict__ gacc, float* __restrict__ part,
+                                                           unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
   extern __shared__ float4 srec[];
   uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * kRecF4);
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // global tile over all views
+  const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
+  const CamF cam = V.cam;
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int wx0 = tx * TW + (wave % WX) * 8, wy0 = ty * TH + (wave / WX) * 8;
   const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
-  const bool inside = px < a.cam.width && py < a.cam.height;
+  const bool inside = px < cam.width && py < cam.height;
   const float fpx = (float)px, fpy = (float)py;
   const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
-  const int HW = a.cam.width * a.cam.height;
-  const int p = py * a.cam.width + px;
+  const int HW = cam.width * cam.height;
+  const int p = py * cam.width + px;
   int my_last = 0;
   float T = 1.0f;
   float gr = 0.f, gg = 0.f, gbl = 0.f, gd = 0.f, gn0 = 0.f, gn1 = 0.f, gn2 = 0.f, go = 0.f;
   if (inside) {
-    my_last = (int)last_in[p];
-    T = t_final[p];
-    if (g_rgb) {
-      gr = g_rgb[p];
-      gg = g_rgb[HW + p];
-      gbl = g_rgb[2 * HW + p];
+    my_last = (int)last_in[V.pix_base + p];
+    T = t_final[V.pix_base + p];
+    if (V.g_rgb) {
+      gr = V.g_rgb[p];
+      gg = V.g_rgb[HW + p];
+      gbl = V.g_rgb[2 * HW + p];
     }
-    if (g_depth) gd = g_depth[p];
-    if (HAS_N) {
-      gn0 = g_normal[p];
-      gn1 = g_normal[HW + p];
-      gn2 = g_normal[2 * HW + p];
+    if (V.g_depth) gd = V.g_depth[p];
+    if (HAS_N && V.g_normal) {
+      gn0 = V.g_normal[p];
+      gn1 = V.g_normal[HW + p];
+      gn2 = V.g_normal[2 * HW + p];
     }
-    if (HAS_O) go = g_alpha[p];
+    if (HAS_O && V.g_alpha) go = V.g_alpha[p];
   }
-  const float xh = (fpx - a.cam.cx) / a.cam.fx, yh = (fpy - a.cam.cy) / a.cam.fy;
+  const float xh = (fpx - cam.cx) / cam.fx, yh = (fpy - cam.cy) / cam.fy;
   float Br = 0.f, Bg = 0.f, Bb = 0.f, Bd = 0.f, Bn0 = 0.f, Bn1 = 0.f, Bn2 = 0.f, Bo = 0.f;
   float pr0 = 0.f, pr1 = 0.f, pr2 = 0.f, pp0 = 0.f, pp1 = 0.f, pp2 = 0.f;
   int n_eval = 0, n_cov = 0;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
         const float4 g1 = srec[jj * kRecF4 + 1], g2 = srec[jj * kRecF4 + 2], g3 = srec[jj * kRecF4 + 3];
         const float4 c4 = srec[jj * kRecF4 + 4];
         Hit h;
-        const int code = evaluate(fpx, fpy, g1, g2, g3, c4.x, a.z_near, a.filter, h);
+        const int code = evaluate(fpx, fpy, bb.x, bb.z, g1, g2, g3, c4.x, a.z_near, a.filter, h);
         if (PROF) {
           n_eval += 1;
           n_cov += code > 0;
@@ -315,8 +316,8 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
             const float hv0 = fmaf(-h.dy, m0, g2.w), hv1 = fmaf(-h.dy, m1, g3.x);
             const float V0 = hv0 * gq1 - hv1 * gq0;  // (h_v x g_q)_z
             const float V1 = gq0 * hu1 - gq1 * hu0;  // (g_q x h_u)_z
-            Vx = a.cam.fx * V0;
-            Vy = a.cam.fy * V1;
+            Vx = cam.fx * V0;
+            Vy = cam.fy * V1;
             Vz = g_d - xh * Vx - yh * Vy;
             ue = h.u;
             ve = h.v;
@@ -328,9 +329,9 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
             const float gcx = -2.0f * kFilterScale * h.dx * dLdrho;
             const float gcy = -2.0f * kFilterScale * h.dy * dLdrho;
             const float im2 = 1.0f / m2;
-            Vx = a.cam.fx * gcx * im2;
-            Vy = a.cam.fy * gcy * im2;
-            const float xc = (g1.x - a.cam.cx) / a.cam.fx, yc = (g1.y - a.cam.cy) / a.cam.fy;
+            Vx = cam.fx * gcx * im2;
+            Vy = cam.fy * gcy * im2;
+            const float xc = ((bb.x + g1.x) - cam.cx) / cam.fx, yc = ((bb.z + g1.y) - cam.cy) / cam.fy;
             Vz = g_d - xc * Vx - yc * Vy;
             ue = 0.f;
             ve = 0.f;
@@ -398,43 +399,36 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(
       if (t < 6)
 #pragma unroll
         for (int w = 0; w < NW; ++w) s += s_red[w][t];
-      part[(size_t)blockIdx.x * 8 + t] = s;
+      part[(size_t)tile * 8 + t] = s;
     }
   }
 }
 
 template <int TW, int TH>
-void fwd_shape(const BlendArgs& a, float* rgb, float* depth, float* normal, float* alpha, float* t_final,
-               uint32_t* last, unsigned long long* work, hipStream_t s) {
+void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
   const size_t lds = (size_t)a.batch * kRecF4 * sizeof(float4);
   if (work)
-    blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, rgb, depth, normal, alpha, t_final, last,
-                                                                    work);
+    blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
   else
-    blend_fwd_kernel<TW, TH, false><<<a.n_tiles, TW * TH, lds, s>>>(a, rgb, depth, normal, alpha, t_final, last,
-                                                                     work);
+    blend_fwd_kernel<TW, TH, false><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
 }
 
 template <int TW, int TH, bool PO, bool HN, bool HO>
-void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, const float* g_rgb,
-                 const float* g_depth, const float* g_normal, const float* g_alpha, float* gacc, float* part,
+void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, float* gacc, float* part,
                  unsigned long long* work, hipStream_t s) {
   const size_t lds = (size_t)a.batch * (kRecF4 * sizeof(float4) + sizeof(uint32_t));
   if (work)
-    blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(
-        a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work);
+    blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
   else
-    blend_bwd_kernel<TW, TH, PO, HN, HO, false><<<a.n_tiles, TW * TH, lds, s>>>(
-        a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work);
+    blend_bwd_kernel<TW, TH, PO, HN, HO, false><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part,
+                                                                               work);
 }
 
 template <int TW, int TH>
-void bwd_shape(const BlendArgs& a, const float* t_final, const uint32_t* last, const float* g_rgb,
-               const float* g_depth, const float* g_normal, const float* g_alpha, float* gacc, float* part,
-               unsigned long long* work, hipStream_t s) {
-  const bool po = gacc == nullptr, hn = g_normal != nullptr, ho = g_alpha != nullptr;
-#define GS2D_BWD(PO, HN, HO) \
-  bwd_variant<TW, TH, PO, HN, HO>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s)
+void bwd_shape(const BlendArgs& a, const float* t_final, const uint32_t* last, bool hn, bool ho, float* gacc,
+               float* part, unsigned long long* work, hipStream_t s) {
+  const bool po = gacc == nullptr;
+#define GS2D_BWD(PO, HN, HO) bwd_variant<TW, TH, PO, HN, HO>(a, t_final, last, gacc, part, work, s)
   if (po) {
     if (hn && ho) GS2D_BWD(true, true, true);
     else if (hn) GS2D_BWD(true, true, false);
@@ -451,25 +445,24 @@ void bwd_shape(const BlendArgs& a, const float* t_final, const uint32_t* last, c
 
 }  // namespace
 
-void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* rgb, float* depth, float* normal,
-                      float* alpha, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
-  if (tile_w == 8 && tile_h == 8) fwd_shape<8, 8>(a, rgb, depth, normal, alpha, t_final, last, work, s);
-  else if (tile_w == 16 && tile_h == 8) fwd_shape<16, 8>(a, rgb, depth, normal, alpha, t_final, last, work, s);
-  else if (tile_w == 32 && tile_h == 16) fwd_shape<32, 16>(a, rgb, depth, normal, alpha, t_final, last, work, s);
-  else fwd_shape<16, 16>(a, rgb, depth, normal, alpha, t_final, last, work, s);
+void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* t_final, uint32_t* last,
+                      unsigned long long* work, hipStream_t s) {
+  if (tile_w == 8 && tile_h == 8) fwd_shape<8, 8>(a, t_final, last, work, s);
+  else if (tile_w == 16 && tile_h == 8) fwd_shape<16, 8>(a, t_final, last, work, s);
+  else if (tile_w == 32 && tile_h == 16) fwd_shape<32, 16>(a, t_final, last, work, s);
+  else fwd_shape<16, 16>(a, t_final, last, work, s);
 }
 
 void launch_blend_bwd(const BlendArgs& a, int tile_w, int tile_h, const float* t_final, const uint32_t* last,
-                      const float* g_rgb, const float* g_depth, const float* g_normal, const float* g_alpha,
-                      float* gacc, float* part, unsigned long long* work, hipStream_t s) {
-  if (tile_w == 8 && tile_h == 8)
-    bwd_shape<8, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
+                      bool has_normal, bool has_alpha, float* gacc, float* part, unsigned long long* work,
+                      hipStream_t s) {
+  if (tile_w == 8 && tile_h == 8) bwd_shape<8, 8>(a, t_final, last, has_normal, has_alpha, gacc, part, work, s);
   else if (tile_w == 16 && tile_h == 8)
-    bwd_shape<16, 8>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
+    bwd_shape<16, 8>(a, t_final, last, has_normal, has_alpha, gacc, part, work, s);
   else if (tile_w == 32 && tile_h == 16)
-    bwd_shape<32, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
+    bwd_shape<32, 16>(a, t_final, last, has_normal, has_alpha, gacc, part, work, s);
   else
-    bwd_shape<16, 16>(a, t_final, last, g_rgb, g_depth, g_normal, g_alpha, gacc, part, work, s);
+    bwd_shape<16, 16>(a, t_final, last, has_normal, has_alpha, gacc, part, work, s);
 }
 
 }  // namespace gs2d

@@ -24,28 +24,33 @@ namespace {
 
 constexpr int kLossThreads = 256;
 
-__global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(
-    CamF cam, const float* __restrict__ rgb, const float* __restrict__ depth,
-    const float* __restrict__ normal, const float* __restrict__ alpha, const float* __restrict__ tgt_rgb,
-    const float* __restrict__ tgt_depth, float lambda_d, int use_masks, float* __restrict__ d_rgb,
-    float* __restrict__ d_depth, float* __restrict__ part) {
+__global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(const ViewDesc* __restrict__ views,
+                                                                     float lambda_d, int use_masks,
+                                                                     float* __restrict__ part, int part_stride) {
+  const ViewDesc& V = views[blockIdx.y];
+  const CamF cam = V.cam;
   const int HW = cam.width * cam.height;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   float l = 0.f;
   if (p < HW) {
+    const float* rgb = V.rgb;
+    const float* tgt_rgb = V.tgt_rgb;
     const int y = p / cam.width, x = p - y * cam.width;
     bool m = true;
     if (use_masks) {
+      const float* normal = V.normal;
       const float xh = ((float)x - cam.cx) / cam.fx, yh = ((float)y - cam.cy) / cam.fy;
       const float ndr = fmaf(normal[p], xh, fmaf(normal[HW + p], yh, normal[2 * HW + p]));
-      m = (ndr > 0.0f) && (alpha[p] > kOpacityMask);
+      m = (ndr > 0.0f) && (V.alpha[p] > kOpacityMask);
     }
     const float inv = 1.0f / (float)HW;
     const float d0 = rgb[p] - tgt_rgb[p];
     const float d1 = rgb[HW + p] - tgt_rgb[HW + p];
     const float d2 = rgb[2 * HW + p] - tgt_rgb[2 * HW + p];
-    const float dd = depth[p] - tgt_depth[p];
+    const float dd = V.depth[p] - V.tgt_depth[p];
     auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
+    float* d_rgb = V.g_rgb;
+    float* d_depth = V.g_depth;
     if (m) {
       l = fabsf(d0) + fabsf(d1) + fabsf(d2) + lambda_d * fabsf(dd);
       d_rgb[p] = sgn(d0) * inv;
@@ -66,7 +71,7 @@ __global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * part_stride + blockIdx.x] = red[0];
 }
 
 __device__ inline double wave_sum_d(double v) {
@@ -82,41 +87,58 @@ __device__ inline double sum_parts(const float* part, int n, int stride, int k) 
   for (int i = threadIdx.x; i < n; i += 64) s += (double)part[(size_t)i * stride + k];
   return wave_sum_d(s);
 }
+__device__ inline int loss_blocks_dev(int hw) { return (hw + kLossThreads - 1) / kLossThreads; }
 
-__global__ void reduce_loss_kernel(const float* __restrict__ part, int n, float inv_hw, float* __restrict__ loss,
-                                   Ctrl* __restrict__ ctrl) {
+__global__ void reduce_loss_kernel(const float* __restrict__ part, int n, float inv_hw, float* __restrict__ loss) {
   const double s = sum_parts(part, n, 1, 0) * (double)inv_hw;
-  if (threadIdx.x == 0) {
-    if (loss) *loss = (float)s;
-    if (ctrl) ctrl->loss = s;
-  }
+  if (threadIdx.x == 0) *loss = (float)s;
 }
 
-__global__ void reduce_pose_kernel(const float* __restrict__ part, int n, float* __restrict__ d_pose,
+__global__ void reduce_pose_kernel(const float* __restrict__ part, int row0, int rows, float* __restrict__ d_pose,
                                    int accumulate) {
   double g[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = sum_parts(part, n, 8, k);
+  for (int k = 0; k < 6; ++k) g[k] = sum_parts(part + (size_t)row0 * 8, rows, 8, k);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) d_pose[k] = accumulate ? d_pose[k] + (float)g[k] : (float)g[k];
   }
 }
 
-__global__ void track_init_kernel(const float* __restrict__ pose, Ctrl* __restrict__ ctrl,
+// one wave per view: d_pose of view blockIdx.x = sum of the rows of its tiles
+__global__ void reduce_pose_views_kernel(const ViewDesc* __restrict__ views, const float* __restrict__ part,
+                                         int accumulate) {
+  const ViewDesc& V = views[blockIdx.x];
+  float* d_pose = V.d_pose;
+  if (!d_pose) return;
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = sum_parts(part + (size_t)V.tile_base * 8, V.tiles_x * V.tiles_y, 8, k);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d_pose[k] = accumulate ? d_pose[k] + (float)g[k] : (float)g[k];
+  }
+}
+
+__global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_views, Ctrl* __restrict__ ctrl,
                                   float* pose_history, float* loss_history, int max_hist) {
   const int t = threadIdx.x;
-  if (t < 12) ctrl->master_pose[t] = (double)pose[t];
-  if (t < 6) {
-    ctrl->adam_m[t] = 0.0;
-    ctrl->adam_v[t] = 0.0;
+  for (int k = t; k < n_views * 12; k += blockDim.x)
+    ctrl->master_pose[k / 12][k % 12] = (double)views[k / 12].pose[k % 12];
+  for (int k = t; k < n_views * 6; k += blockDim.x) {
+    ctrl->adam_m[k / 6][k % 6] = 0.0;
+    ctrl->adam_v[k / 6][k % 6] = 0.0;
+  }
+  for (int k = t; k < n_views; k += blockDim.x) {
+    ctrl->loss[k] = 0.0;
+    ctrl->iter_v[k] = 0;
   }
   if (t == 0) {
     ctrl->iter = 0;
-    ctrl->loss = 0.0;
     ctrl->pose_history = pose_history;
     ctrl->loss_history = loss_history;
     ctrl->max_hist = max_hist;
+    ctrl->n_views = n_views;
   }
 }
 
@@ -148,34 +170,61 @@ __device__ void se3_exp(const double tau[6], double R[9], double tt[3]) {
   for (int r = 0; r < 3; ++r) tt[r] = J[r * 3 + 0] * tau[0] + J[r * 3 + 1] * tau[1] + J[r * 3 + 2] * tau[2];
 }
 
-__global__ void pose_step_kernel(const float* __restrict__ pose_part, int n_pose_parts,
-                                 const float* __restrict__ loss_part, int n_loss_parts, float inv_hw,
-                                 AdamArgs adam, float* __restrict__ pose, Ctrl* __restrict__ ctrl) {
+// One workgroup of 256 threads per view: a fixed-order (deterministic) reduction of
+// the view's pose and loss partials, then the AdamW + Exp step on one thread.
+__device__ inline double block_sum_d(double v, double* sh) {
+  v = wave_sum_d(v);
+  const int w = threadIdx.x / 64;
+  __syncthreads();
+  if (threadIdx.x % 64 == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < (int)blockDim.x / 64; ++k) s += sh[k];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void pose_step_kernel(const ViewDesc* __restrict__ views,
+                                                        const float* __restrict__ pose_part,
+                                                        const float* __restrict__ loss_part, int part_stride,
+                                                        AdamArgs adam, Ctrl* __restrict__ ctrl) {
+  __shared__ double sh[4];
+  const int v = blockIdx.x;
+  const int n_views = gridDim.x;
+  const ViewDesc& V = views[v];
+  const int HW = V.cam.width * V.cam.height;
+  const int rows = V.tiles_x * V.tiles_y;
+  const float* pp = pose_part + (size_t)V.tile_base * 8;
   double g[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = sum_parts(pose_part, n_pose_parts, 8, k);
-  const double loss = loss_part ? sum_parts(loss_part, n_loss_parts, 1, 0) * (double)inv_hw : 0.0;
+  for (int k = 0; k < 6; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) s += (double)pp[(size_t)i * 8 + k];
+    g[k] = block_sum_d(s, sh);
+  }
+  double sl = 0.0;
+  const int nl = loss_blocks_dev(HW);
+  for (int i = threadIdx.x; i < nl; i += blockDim.x) sl += (double)loss_part[(size_t)v * part_stride + i];
+  const double loss = block_sum_d(sl, sh) / (double)HW;
   if (threadIdx.x != 0) return;
-  const uint32_t it = ctrl->iter;
+  const uint32_t it = ctrl->iter_v[v];
   float* pose_history = ctrl->pose_history;
   float* loss_history = ctrl->loss_history;
   const int max_hist = ctrl->max_hist;
-  ctrl->loss = loss;
-  if (loss_history && (int)it < max_hist) loss_history[it] = (float)loss;
+  ctrl->loss[v] = loss;
+  if (loss_history && (int)it < max_hist) loss_history[(size_t)it * n_views + v] = (float)loss;
   const double t = (double)it + 1.0;
   const double b1 = adam.beta1, b2 = adam.beta2;
   const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
   double tau[6];
   for (int k = 0; k < 6; ++k) {
-    const double m = b1 * ctrl->adam_m[k] + (1.0 - b1) * g[k];
-    const double v = b2 * ctrl->adam_v[k] + (1.0 - b2) * g[k] * g[k];
-    ctrl->adam_m[k] = m;
-    ctrl->adam_v[k] = v;
-    tau[k] = -(double)adam.lr[k] * (m / c1) / (sqrt(v / c2) + (double)adam.eps);
+    const double m = b1 * ctrl->adam_m[v][k] + (1.0 - b1) * g[k];
+    const double vv = b2 * ctrl->adam_v[v][k] + (1.0 - b2) * g[k] * g[k];
+    ctrl->adam_m[v][k] = m;
+    ctrl->adam_v[v][k] = vv;
+    tau[k] = -(double)adam.lr[k] * (m / c1) / (sqrt(vv / c2) + (double)adam.eps);
   }
   double Re[9], te[3];
   se3_exp(tau, Re, te);
-  double* T = ctrl->master_pose;
+  double* T = ctrl->master_pose[v];
   double Tn[12];
   for (int r = 0; r < 3; ++r) {
     for (int c = 0; c < 4; ++c) {
@@ -186,10 +235,10 @@ __global__ void pose_step_kernel(const float* __restrict__ pose_part, int n_pose
   }
   for (int k = 0; k < 12; ++k) {
     T[k] = Tn[k];
-    pose[k] = (float)Tn[k];
-    if (pose_history && (int)it < max_hist) pose_history[(size_t)it * 12 + k] = (float)Tn[k];
+    V.pose[k] = (float)Tn[k];
+    if (pose_history && (int)it < max_hist) pose_history[((size_t)it * n_views + v) * 12 + k] = (float)Tn[k];
   }
-  ctrl->iter = it + 1;
+  ctrl->iter_v[v] = it + 1;
 }
 
 // Left Jacobian of SE(3) for tau = (rho, phi) (Barfoot, "State Estimation for
@@ -289,32 +338,33 @@ void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, h
 
 int loss_blocks(int hw) { return (hw + kLossThreads - 1) / kLossThreads; }
 
-void launch_tracking_loss(CamF cam, const float* rgb, const float* depth, const float* normal,
-                          const float* alpha, const float* tgt_rgb, const float* tgt_depth, float lambda_d,
-                          int use_masks, float* d_rgb, float* d_depth, float* part, int* n_parts,
-                          hipStream_t s) {
-  const int nb = loss_blocks(cam.width * cam.height);
-  tracking_loss_kernel<<<nb, kLossThreads, 0, s>>>(cam, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d,
-                                                   use_masks, d_rgb, d_depth, part);
-  if (n_parts) *n_parts = nb;
+void launch_tracking_loss(const ViewDesc* views, int n_views, int max_hw, float lambda_d, int use_masks,
+                          float* part, int part_stride, hipStream_t s) {
+  const dim3 grid(loss_blocks(max_hw), n_views);
+  tracking_loss_kernel<<<grid, kLossThreads, 0, s>>>(views, lambda_d, use_masks, part, part_stride);
 }
 
-void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, Ctrl* ctrl, hipStream_t s) {
-  reduce_loss_kernel<<<1, 64, 0, s>>>(part, n_parts, inv_hw, loss, ctrl);
+void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, hipStream_t s) {
+  reduce_loss_kernel<<<1, 64, 0, s>>>(part, n_parts, inv_hw, loss);
 }
 
-void launch_reduce_pose(const float* part, int n_parts, float* d_pose, int accumulate, hipStream_t s) {
-  reduce_pose_kernel<<<1, 64, 0, s>>>(part, n_parts, d_pose, accumulate);
+void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, int accumulate, hipStream_t s) {
+  reduce_pose_kernel<<<1, 64, 0, s>>>(part, row0, rows, d_pose, accumulate);
 }
 
-void launch_track_init(const float* pose, Ctrl* ctrl, float* pose_history, float* loss_history, int max_hist,
-                       hipStream_t s) {
-  track_init_kernel<<<1, 64, 0, s>>>(pose, ctrl, pose_history, loss_history, max_hist);
+void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,
+                              hipStream_t s) {
+  reduce_pose_views_kernel<<<n_views, 64, 0, s>>>(views, part, accumulate);
 }
 
-void launch_pose_step(const float* pose_part, int n_pose_parts, const float* loss_part, int n_loss_parts,
-                      float inv_hw, AdamArgs adam, float* pose, Ctrl* ctrl, hipStream_t s) {
-  pose_step_kernel<<<1, 64, 0, s>>>(pose_part, n_pose_parts, loss_part, n_loss_parts, inv_hw, adam, pose, ctrl);
+void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
+                       int max_hist, hipStream_t s) {
+  track_init_kernel<<<1, 256, 0, s>>>(views, n_views, ctrl, pose_history, loss_history, max_hist);
+}
+
+void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, const float* loss_part,
+                      int part_stride, AdamArgs adam, Ctrl* ctrl, hipStream_t s) {
+  pose_step_kernel<<<n_views, 256, 0, s>>>(views, pose_part, loss_part, part_stride, adam, ctrl);
 }
 
 }  // namespace gs2d

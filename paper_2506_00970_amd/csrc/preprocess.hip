@@ -21,14 +21,33 @@
 namespace gs2d {
 namespace {
 
+// Copies up to 8 view descriptors (kernel arguments) into the device view table, so
+// that the table is part of the launch sequence (and of a captured graph).
+struct ViewChunk {
+  ViewDesc v[8];
+  int first, count;
+};
+
+__global__ void upload_views_kernel(ViewChunk c, ViewDesc* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < c.count) dst[c.first + i] = c.v[i];
+}
+
 __global__ __launch_bounds__(256) void preprocess_kernel(
-    const float* __restrict__ P, int n, const float* __restrict__ pose, CamF cam, float z_near,
-    int filter, int tile_w, int tile_h, float4* __restrict__ rec,
-    uint2* __restrict__ rect, uint32_t* __restrict__ count, uint32_t* __restrict__ dkey,
-    uint32_t* __restrict__ dval, float* __restrict__ saved_pose) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 12 && saved_pose) saved_pose[i] = pose[i];
-  if (i >= n) return;
+    const ViewDesc* __restrict__ views, int n_views, int64_t items, float z_near, int filter, int tile_w,
+    int tile_h, float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ count,
+    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, float* __restrict__ saved_pose) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= items) return;
+  const int item = (int)gi;
+  const int v = view_of_item(views, n_views, item);
+  const ViewDesc& V = views[v];
+  const float* __restrict__ P = V.params;
+  const float* __restrict__ pose = V.pose;
+  const CamF cam = V.cam;
+  const int n = V.n;
+  const int i = item - V.item_base;  // surfel index within the view
+  if (i < 12 && saved_pose) saved_pose[v * 12 + i] = pose[i];
   double R[9], t[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -52,7 +71,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
     uc[r] = R[r * 3 + 0] * tu[0] + R[r * 3 + 1] * tu[1] + R[r * 3 + 2] * tu[2];
     vc[r] = R[r * 3 + 0] * tv[0] + R[r * 3 + 1] * tv[1] + R[r * 3 + 2] * tv[2];
   }
-  dval[i] = (uint32_t)i;
+  dval[item] = (uint32_t)item;
   const double a[3] = {su * uc[0], su * uc[1], su * uc[2]};
   const double b[3] = {sv * vc[0], sv * vc[1], sv * vc[2]};
   // homography rows: M0 = fx col.x + cx col.z, M1 = fy col.y + cy col.z, M2 = col.z
@@ -70,7 +89,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
   vis = vis && (c22 < 0.0);
   uint32_t cnt = 0;
   uint2 rc = make_uint2(1u, 0u);
-  double bx0 = 0, bx1 = -1, by0 = 0, by1 = -1;
+  double bx0 = 0, bx1 = -1, by0 = 0, by1 = -1, ux0 = 0, ux1 = -1, uy0 = 0, uy1 = -1;
   if (vis) {
     // dual conic entries needed for the box: C00, C11, C02, C12 (and C22)
     const double c00 = 9.0 * (M0[0] * M0[0] + M0[1] * M0[1]) - M0[2] * M0[2];
@@ -89,11 +108,16 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       y0 = fmin(y0, pcy - rr);
       y1 = fmax(y1, pcy + rr);
     }
-    // one pixel of slack, clipped to the image
-    bx0 = fmax(floor(x0 - 1.0), 0.0);
-    bx1 = fmin(ceil(x1 + 1.0), (double)(cam.width - 1));
-    by0 = fmax(floor(y0 - 1.0), 0.0);
-    by1 = fmin(ceil(y1 + 1.0), (double)(cam.height - 1));
+    // one pixel of slack; the record keeps the unclipped box (integer-valued, within
+    // +-2^23 so that it is exact in float32), the tile rectangle the clipped one
+    ux0 = fmin(fmax(floor(x0 - 1.0), -8388608.0), 8388608.0);
+    ux1 = fmin(fmax(ceil(x1 + 1.0), -8388608.0), 8388608.0);
+    uy0 = fmin(fmax(floor(y0 - 1.0), -8388608.0), 8388608.0);
+    uy1 = fmin(fmax(ceil(y1 + 1.0), -8388608.0), 8388608.0);
+    bx0 = fmax(ux0, 0.0);
+    bx1 = fmin(ux1, (double)(cam.width - 1));
+    by0 = fmax(uy0, 0.0);
+    by1 = fmin(uy1, (double)(cam.height - 1));
     if (bx0 <= bx1 && by0 <= by1) {
       const int tx0 = (int)bx0 / tile_w, tx1 = (int)bx1 / tile_w;
       const int ty0 = (int)by0 / tile_h, ty1 = (int)by1 / tile_h;
@@ -101,14 +125,14 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       rc = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
     }
   }
-  count[i] = cnt;
+  count[item] = cnt;
   if (cnt == 0) {
-    rect[i] = make_uint2(1u, 0u);  // x0 = 1 > x1 = 0: empty
-    dkey[i] = 0xFFFFFFFFu;
+    rect[item] = make_uint2(1u, 0u);  // x0 = 1 > x1 = 0: empty
+    dkey[item] = 0xFFFFFFFFu;
     return;
   }
-  rect[i] = rc;
-  dkey[i] = __float_as_uint((float)mc[2]);
+  rect[item] = rc;
+  dkey[item] = __float_as_uint((float)mc[2]);
   // centre-relative homography rows (see gs2d_internal.h)
   const double pcx = M0[2] / m[2], pcy = M1[2] / m[2];
   const double P0 = M0[0] - pcx * m[0], P1 = M0[1] - pcx * m[1];
@@ -118,9 +142,11 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
   const double k1 = P0 * m[1] - P1 * m[0];
   const double nn[3] = {uc[1] * vc[2] - uc[2] * vc[1], uc[2] * vc[0] - uc[0] * vc[2],
                         uc[0] * vc[1] - uc[1] * vc[0]};
-  float4* r = rec + (size_t)i * kRecF4;
-  r[0] = make_float4((float)bx0, (float)bx1, (float)by0, (float)by1);
-  r[1] = make_float4((float)pcx, (float)pcy, (float)Dt, (float)k0);
+  float4* r = rec + (size_t)item * kRecF4;
+  // the projected centre is stored relative to the box corner (ux0, uy0), so that a
+  // pixel's offset (x - ux0) - (cx - ux0) loses no precision at large x
+  r[0] = make_float4((float)ux0, (float)ux1, (float)uy0, (float)uy1);
+  r[1] = make_float4((float)(pcx - ux0), (float)(pcy - uy0), (float)Dt, (float)k0);
   r[2] = make_float4((float)k1, (float)P0, (float)P1, (float)Q0);
   r[3] = make_float4((float)Q1, (float)m[0], (float)m[1], (float)m[2]);
   r[4] = make_float4(P[(size_t)11 * n + i], P[(size_t)12 * n + i], P[(size_t)13 * n + i],
@@ -232,15 +258,22 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
 
 }  // namespace
 
-void launch_preprocess(const float* params, int n, const float* pose, CamF cam, float z_near, int filter,
-                       int tile_w, int tile_h, int tiles_x, int tiles_y, float4* rec, uint2* rect,
-                       uint32_t* count, uint32_t* dkey, uint32_t* dval, float* saved_pose,
-                       hipStream_t s) {
-  const int grid = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
-  (void)tiles_x;
-  (void)tiles_y;
-  preprocess_kernel<<<grid, 256, 0, s>>>(params, n, pose, cam, z_near, filter, tile_w, tile_h, rec, rect,
-                                         count, dkey, dval, saved_pose);
+void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s) {
+  for (int f = 0; f < vs.n_views; f += 8) {
+    ViewChunk c;
+    c.first = f;
+    c.count = vs.n_views - f < 8 ? vs.n_views - f : 8;
+    for (int k = 0; k < c.count; ++k) c.v[k] = vs.v[f + k];
+    upload_views_kernel<<<1, 64, 0, s>>>(c, dst);
+  }
+}
+
+void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
+                       int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, uint32_t* dval,
+                       float* saved_pose, hipStream_t s) {
+  const int grid = items > 0 ? (int)((items + 255) / 256) : 1;
+  preprocess_kernel<<<grid, 256, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec, rect, count,
+                                         dkey, dval, saved_pose);
 }
 
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc,

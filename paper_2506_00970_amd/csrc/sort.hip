@@ -2,15 +2,16 @@
 //
 // The paper composites surfels "sorted by depth" per pixel (Sec. "2D Gaussian
 // Splatting", eq:alpha_blending).  The tile rasterizer realises that order with
-// two stable sorts: surfels by float32 camera depth (ties keep the index order),
-// then the (tile, surfel) pairs, emitted in that depth order, stably by tile.
-// Each tile's list is therefore ascending (depth, index), the order of the
-// per-pixel definition.
+// two stable sorts: (view, surfel) items by float32 camera depth (ties keep the
+// item order, i.e. the surfel index within a view), then the (tile, item) pairs,
+// emitted in that depth order and keyed by a global tile index (each view's tiles
+// follow the previous view's), stably by tile.  Each tile's list is therefore
+// ascending (depth, index), the order of the per-pixel definition.
 //
 // Radix pass = three kernels over blocks of kScanItems keys:
 //   hist    per-block digit histogram (LDS atomics, one sub-histogram per wave)
-//   offsets one block, one thread per digit: exclusive prefix over blocks, then
-//           over digits, giving every (block, digit) its global output offset
+//   offsets one workgroup: exclusive scan of the digit-major histograms, giving
+//           every (block, digit) its global output offset
 //   scatter per block, 8 rounds of 256 keys: a wave-level multi-split (ballots
 //           over the digit bits give each lane the mask of lanes holding the
 //           same digit), a per-digit prefix over the 4 waves in LDS, and the
@@ -92,7 +93,11 @@ __global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint32_t* __restr
     if (i < nb) block_sums[i] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) ctrl->n_pairs = carry;
+  if (threadIdx.x == 0) {
+    ctrl->n_pairs = carry;
+    ctrl->n_visible = 0;  // counted by the duplicate kernel that follows
+    ctrl->overflow = 0;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void scan_final_kernel(const uint32_t* __restrict__ count,
@@ -146,24 +151,43 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
   uint32_t s = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s += h[w][d];
-  hist[(size_t)blockIdx.x * kDigits + d] = s;
+  // digit-major: an exclusive scan of hist[d * nb + b] gives every (block, digit)
+  // its global output offset
+  hist[(size_t)d * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist,
-                                                                 const uint32_t* __restrict__ n_dev,
-                                                                 int64_t n_host) {
+// One workgroup of 1024 threads: exclusive scan of the digit-major histogram of the
+// active blocks (256 x nb entries, each thread a contiguous chunk).  The grid's
+// block count is the row stride; only the first nb_active blocks of each row count.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist, int nb_grid,
+                                                                     const uint32_t* __restrict__ n_dev,
+                                                                     int64_t n_host) {
   const int64_t n = item_count(n_dev, n_host);
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
-  __shared__ uint32_t sh[kThreads];
-  const int d = threadIdx.x;
-  uint32_t run = 0;
-  for (int b = 0; b < nb; ++b) {
-    const uint32_t c = hist[(size_t)b * kDigits + d];
-    hist[(size_t)b * kDigits + d] = run;
+  const int total = kDigits * nb;
+  const int chunk = (total + kScanThreads - 1) / kScanThreads;
+  const int t = threadIdx.x;
+  const int e0 = t * chunk, e1 = min(total, e0 + chunk);
+  // entry e = digit * nb + block maps to hist[digit * nb_grid + block]
+  uint32_t s = 0;
+  for (int e = e0; e < e1; ++e) s += hist[(size_t)(e / nb) * nb_grid + (e % nb)];
+  __shared__ uint32_t sh[kScanThreads];
+  sh[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t x = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  uint32_t run = sh[t] - s;
+  for (int e = e0; e < e1; ++e) {
+    uint32_t* p = hist + (size_t)(e / nb) * nb_grid + (e % nb);
+    const uint32_t c = *p;
+    *p = run;
     run += c;
   }
-  const uint32_t base = block_exclusive_scan(run, sh, nullptr);
-  for (int b = 0; b < nb; ++b) hist[(size_t)b * kDigits + d] += base;
 }
 
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
@@ -176,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
   __shared__ uint32_t doff[kDigits];
   __shared__ uint32_t wcnt[kWaves][kDigits];
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
-  doff[t] = hist[(size_t)blockIdx.x * kDigits + t];
+  doff[t] = hist[(size_t)t * gridDim.x + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kRounds; ++r) {
     for (int k = t; k < kWaves * kDigits; k += kThreads) (&wcnt[0][0])[k] = 0u;
@@ -220,12 +244,15 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
 
 __global__ __launch_bounds__(kThreads) void duplicate_kernel(
     const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ count,
-    const uint32_t* __restrict__ offs, const uint2* __restrict__ rect, int n, int tiles_x,
-    int64_t p_cap, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, Ctrl* __restrict__ ctrl) {
+    const uint32_t* __restrict__ offs, const uint2* __restrict__ rect, const ViewDesc* __restrict__ views,
+    int n_views, int n, int64_t p_cap, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval,
+    Ctrl* __restrict__ ctrl, uint2* __restrict__ ranges, int n_tiles) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  // clear the tile ranges for the ranges kernel (which runs after the tile sort)
+  for (int k = j; k < n_tiles; k += gridDim.x * blockDim.x) ranges[k] = make_uint2(0u, 0u);
   const uint32_t id = j < n ? sorted_ids[j] : 0u;
   const uint32_t c = j < n ? count[id] : 0u;
-  // one atomic per wave for the visible-surfel counter
+  // one atomic per wave for the visible-item counter
   const uint64_t vis = __ballot(c > 0);
   if (vis != 0ull && (threadIdx.x % 64) == (unsigned)(__ffsll((long long)vis) - 1))
     atomicAdd(&ctrl->n_visible, (uint32_t)__popcll(vis));
@@ -235,11 +262,14 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(
     ctrl->overflow = 1u;
     return;
   }
+  // key = the view's first global tile + the tile's index within the view
+  const ViewDesc& V = views[view_of_item(views, n_views, (int)id)];
+  const uint32_t base = (uint32_t)V.tile_base, tiles_x = (uint32_t)V.tiles_x;
   const uint2 rc = rect[id];
   const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
   for (uint32_t ty = ty0; ty <= ty1; ++ty)
     for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-      pkey[off] = ty * (uint32_t)tiles_x + tx;
+      pkey[off] = base + ty * tiles_x + tx;
       pval[off] = id;
       ++off;
     }
@@ -256,13 +286,6 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __rest
   const uint32_t t = skey[i];
   if (i == 0 || skey[i - 1] != t) ranges[t].x = (uint32_t)i;
   if (i == np - 1 || skey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
-}
-
-__global__ void clear_ctrl_kernel(Ctrl* ctrl) {
-  if (threadIdx.x == 0) {
-    ctrl->n_visible = 0;
-    ctrl->overflow = 0;
-  }
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per) > 0 ? (int)((n + per - 1) / per) : 1; }
@@ -285,7 +308,6 @@ void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t 
 void launch_scan_counts(const uint32_t* count, const uint32_t* perm, int n, uint32_t* offs,
                         uint32_t* block_sums, Ctrl* ctrl, hipStream_t s) {
   const int nb = blocks_for(n, kScanItems);
-  clear_ctrl_kernel<<<1, 64, 0, s>>>(ctrl);
   scan_reduce_kernel<<<nb, kThreads, 0, s>>>(count, perm, n, block_sums);
   scan_blocks_kernel<<<1, kThreads, 0, s>>>(block_sums, nb, ctrl);
   scan_final_kernel<<<nb, kThreads, 0, s>>>(count, perm, n, block_sums, offs);
@@ -299,7 +321,7 @@ int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host
   for (int shift = 0; shift < bits; shift += 8) {
     const int pb = (bits - shift) < 8 ? (bits - shift) : 8;
     radix_hist_kernel<<<nb, kThreads, 0, s>>>(keys[cur], n_dev, limit, shift, pb, hist);
-    radix_offsets_kernel<<<1, kThreads, 0, s>>>(hist, n_dev, limit);
+    radix_offsets_kernel<<<1, kScanThreads, 0, s>>>(hist, nb, n_dev, limit);
     radix_scatter_kernel<<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev,
                                                  limit, shift, pb, hist);
     cur ^= 1;
@@ -308,15 +330,15 @@ int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host
 }
 
 void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
-                      const uint2* rect, int n, int tiles_x, int64_t p_cap, uint32_t* pkey,
-                      uint32_t* pval, Ctrl* ctrl, hipStream_t s) {
-  duplicate_kernel<<<blocks_for(n, 256), 256, 0, s>>>(sorted_ids, count, offs, rect, n, tiles_x, p_cap, pkey,
-                                                      pval, ctrl);
+                      const uint2* rect, const ViewDesc* views, int n_views, int n, int64_t p_cap,
+                      uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles, hipStream_t s) {
+  duplicate_kernel<<<blocks_for(n, 256), 256, 0, s>>>(sorted_ids, count, offs, rect, views, n_views, n, p_cap, pkey,
+                                                      pval, ctrl, ranges, n_tiles);
 }
 
 void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s) {
-  launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, 2 * (int64_t)n_tiles, s);
+  (void)n_tiles;  // cleared by the duplicate kernel
   ranges_kernel<<<blocks_for(p_cap, 256), 256, 0, s>>>(skey, ctrl, p_cap, ranges);
 }
 

@@ -114,6 +114,72 @@ class Rasterizer:
         self._last = (params, pose, cam)  # keep the inputs alive until the backward
         return RenderOut(rgb, depth, normal, alpha, int(gen.value))
 
+    def render_batch(self, views) -> list:
+        """Render several views in one batched launch.
+
+        ``views``: sequence of (params [15, N], camera, pose [12]); views may share a
+        params tensor.  Returns one RenderOut per view (all with the same generation).
+        """
+        views = list(views)
+        if not 1 <= len(views) <= _lib.MAX_VIEWS:
+            raise ValueError(f"1..{_lib.MAX_VIEWS} views")
+        arr = (_lib.View * len(views))()
+        outs, keep = [], []
+        for k, (params, camera, pose) in enumerate(views):
+            cam = _camera(camera)
+            n = int(params.shape[1])
+            _check_tensor(params, f"params[{k}]", (15, n), self.device)
+            pose = pose.reshape(12)
+            _check_tensor(pose, f"pose[{k}]", (12,), self.device)
+            H, W = cam.height, cam.width
+            o = [torch.empty((3, H, W), dtype=torch.float32, device=self.device),
+                 torch.empty((H, W), dtype=torch.float32, device=self.device),
+                 torch.empty((3, H, W), dtype=torch.float32, device=self.device),
+                 torch.empty((H, W), dtype=torch.float32, device=self.device)]
+            arr[k] = _lib.View(params.data_ptr(), n, cam, pose.data_ptr(), o[0].data_ptr(), o[1].data_ptr(),
+                               o[2].data_ptr(), o[3].data_ptr())
+            outs.append(o)
+            keep.append((params, pose, cam))
+        gen = ctypes.c_uint32(0)
+        _lib.check(self._lib.gs2d_render_batch(self._ctx, arr, len(views), ctypes.byref(gen), self._stream()),
+                   self._ctx)
+        self._last = keep
+        return [RenderOut(o[0], o[1], o[2], o[3], int(gen.value)) for o in outs]
+
+    def backward_batch(self, generation: int, grads, params_grad=True, accumulate: bool = False):
+        """Reverse mode of a batched render.
+
+        ``grads``: one dict per view with optional 'd_rgb', 'd_depth', 'd_normal', 'd_alpha'.
+        ``params_grad``: bool or per-view bools.  Views that share a params tensor share
+        (and accumulate into) one gradient tensor.  Returns a list of (d_params or None, d_pose).
+        """
+        last = self._last if isinstance(self._last, list) else None
+        if last is None or len(last) != len(grads):
+            raise _lib.Gs2dError(_lib.ERR_STATE, "no matching batched forward")
+        flags = [params_grad] * len(grads) if isinstance(params_grad, bool) else list(params_grad)
+        arr = (_lib.ViewGrad * len(grads))()
+        shared = {}
+        res = []
+        for k, (g, (params, _, cam)) in enumerate(zip(grads, last)):
+            H, W = cam.height, cam.width
+            for nm, shp in (("d_rgb", (3, H, W)), ("d_depth", (H, W)), ("d_normal", (3, H, W)), ("d_alpha", (H, W))):
+                _check_tensor(g.get(nm), nm, shp, self.device)
+            dp = None
+            if flags[k]:
+                key = params.data_ptr()
+                if key not in shared:
+                    shared[key] = torch.empty_like(params)
+                dp = shared[key]
+            dpose = torch.empty(6, dtype=torch.float32, device=self.device)
+            ptr = lambda t: None if t is None else t.data_ptr()
+            arr[k] = _lib.ViewGrad(ptr(g.get("d_rgb")), ptr(g.get("d_depth")), ptr(g.get("d_normal")),
+                                   ptr(g.get("d_alpha")), ptr(dp), dpose.data_ptr())
+            res.append((dp, dpose))
+        _lib.check(self._lib.gs2d_render_backward_batch(self._ctx, arr, len(grads), ctypes.c_uint32(generation),
+                                                        _lib.ACCUMULATE if accumulate else 0, self._stream()),
+                   self._ctx)
+        return res
+
     # ----------------------------------------------------------------- backward
     def backward(self, generation: int, d_rgb=None, d_depth=None, d_normal=None, d_alpha=None,
                  params_grad: bool = True, d_params: torch.Tensor | None = None,
@@ -233,6 +299,45 @@ class Rasterizer:
         a.loss_history = lh.data_ptr() if lh is not None else None
         _lib.check(self._lib.gs2d_track(self._ctx, ctypes.byref(a), self._stream()), self._ctx)
         return pose, ph, lh
+
+    def track_batch(self, problems, n_iters: int, lr=(1e-3,) * 3 + (3e-3,) * 3, lambda_d: float = 1.0,
+                    use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8, weight_decay: float = 0.0,
+                    use_graph: bool = True, history: bool = True):
+        """Independent tracking problems stepped together in batched launches.
+
+        ``problems``: sequence of (params, camera, pose [12] (updated in place), tgt_rgb, tgt_depth).
+        Returns (pose_history [n_iters, P, 12], loss_history [n_iters, P]) or (None, None).
+        """
+        problems = list(problems)
+        P = len(problems)
+        if not 1 <= P <= _lib.MAX_VIEWS:
+            raise ValueError(f"1..{_lib.MAX_VIEWS} problems")
+        arr = (_lib.TrackProblem * P)()
+        for k, (params, camera, pose, tgt_rgb, tgt_depth) in enumerate(problems):
+            cam = _camera(camera)
+            n = int(params.shape[1])
+            _check_tensor(params, "params", (15, n), self.device)
+            _check_tensor(pose, "pose", (12,), self.device)
+            _check_tensor(tgt_rgb, "tgt_rgb", (3, cam.height, cam.width), self.device)
+            _check_tensor(tgt_depth, "tgt_depth", (cam.height, cam.width), self.device)
+            arr[k] = _lib.TrackProblem(params.data_ptr(), n, cam, pose.data_ptr(), tgt_rgb.data_ptr(),
+                                       tgt_depth.data_ptr())
+        ph = torch.zeros((max(n_iters, 1), P, 12), dtype=torch.float32, device=self.device) if history else None
+        lh = torch.zeros((max(n_iters, 1), P), dtype=torch.float32, device=self.device) if history else None
+        a = _lib.TrackArgs()
+        a.lambda_d = float(lambda_d)
+        a.use_masks = 1 if use_masks else 0
+        a.n_iters = int(n_iters)
+        for k in range(6):
+            a.lr[k] = float(lr[k])
+        a.beta1, a.beta2 = float(betas[0]), float(betas[1])
+        a.eps = float(eps)
+        a.weight_decay = float(weight_decay)
+        a.use_graph = 1 if use_graph else 0
+        a.pose_history = ph.data_ptr() if ph is not None else None
+        a.loss_history = lh.data_ptr() if lh is not None else None
+        _lib.check(self._lib.gs2d_track_batch(self._ctx, arr, P, ctypes.byref(a), self._stream()), self._ctx)
+        return ph, lh
 
     # -------------------------------------------------------------- diagnostics
     def counts(self) -> dict:

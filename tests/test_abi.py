@@ -14,7 +14,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     names = _lib.declared_functions()
-    assert len(names) >= 13
+    assert len(names) >= 19
     for n in names:
         assert hasattr(lib, n), n
 
@@ -60,7 +60,8 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"gs2d_camera": _lib.Camera, "gs2d_options": _lib.Options, "gs2d_counts": _lib.Counts,
                "gs2d_track_args": _lib.TrackArgs, "gs2d_profile": _lib.Profile,
-               "gs2d_tuning": _lib.Tuning}
+               "gs2d_tuning": _lib.Tuning, "gs2d_view": _lib.View, "gs2d_view_grad": _lib.ViewGrad,
+               "gs2d_track_problem": _lib.TrackProblem}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs2d.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -1,0 +1,124 @@
+"""GPU: batched views and batched tracking against single-view calls and the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_common import check_grads, check_images, dev, host, room_scene
+
+pytestmark = pytest.mark.gpu
+
+CAMS = [synth.Camera(640, 480, 525.0, 525.0, 320.0, 240.0), synth.Camera(320, 240, 262.5, 262.5, 160.0, 120.0),
+        synth.Camera(1200, 680, 600.0, 600.0, 600.0, 340.0), synth.Camera(848, 480, 696.0, 696.0, 424.0, 240.0)]
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2506_00970_amd as p
+
+    return p
+
+
+def _scene():
+    room, pose = room_scene(300_000, seed=7, cam_seed=7)
+    poses = [pose] + [synth.room_camera(room, seed=70 + k) for k in range(3)]
+    return room, poses
+
+
+def test_batch_render_equals_single_views(pkg):
+    """A batched render of mixed resolutions equals rendering each view alone, bit for bit."""
+    room, poses = _scene()
+    r = pkg.Rasterizer()
+    P = dev(room.params)
+    Q = dev(synth.make_room(50_000, seed=8).params)  # a second surfel set: views need not share
+    views = [(P, CAMS[0], dev(poses[0].reshape(12))), (Q, CAMS[1], dev(poses[1].reshape(12))),
+             (P, CAMS[2], dev(poses[2].reshape(12))), (P, CAMS[3], dev(poses[3].reshape(12)))]
+    outs = r.render_batch(views)
+    torch.cuda.synchronize()
+    for k, (params, cam, pose) in enumerate(views):
+        single = r.render(params, cam, pose)
+        torch.cuda.synchronize()
+        for name in ("rgb", "depth", "normal", "alpha"):
+            np.testing.assert_array_equal(host(getattr(outs[k], name)), host(getattr(single, name)),
+                                          err_msg=f"view {k} {name}")
+    # one view against the oracle (the 1200x680 one)
+    ref = oracle.render(room.params, CAMS[2], poses[2])
+    img = {k: host(getattr(outs[2], k)) for k in ("rgb", "depth", "normal", "alpha")}
+    check_images(img, ref, ref["fmargin"])
+
+
+def test_batch_backward_shared_params(pkg):
+    """Views sharing one surfel buffer: d_params is the sum of the per-view gradients; poses per view."""
+    room, poses = _scene()
+    r = pkg.Rasterizer()
+    P = dev(room.params)
+    cams = [CAMS[1], CAMS[0], CAMS[1]]
+    views = [(P, cams[k], dev(poses[k].reshape(12))) for k in range(3)]
+    outs = r.render_batch(views)
+    g = np.random.default_rng(0)
+    grads = []
+    for cam in cams:
+        H, W = cam.height, cam.width
+        grads.append({"d_rgb": dev(g.normal(size=(3, H, W)) / (H * W)),
+                      "d_depth": dev(g.normal(size=(H, W)) / (H * W))})
+    res = r.backward_batch(outs[0].generation, grads, params_grad=True)
+    torch.cuda.synchronize()
+    dp_batch = host(res[0][0])
+    assert res[1][0] is res[0][0]
+    total = np.zeros_like(dp_batch)
+    for k in range(3):
+        out = r.render(P, cams[k], views[k][2])
+        d_params, d_pose = r.backward(out.generation, grads[k]["d_rgb"], grads[k]["d_depth"], None, None)
+        torch.cuda.synchronize()
+        total += host(d_params)
+        np.testing.assert_allclose(host(res[k][1]), host(d_pose), rtol=1e-4, atol=1e-6 * np.abs(host(d_pose)).max())
+    check_grads(dp_batch, total, rel=1e-4, floor=1e-5)
+    # and against the oracle's summed gradient
+    ref = sum(oracle.backward(room.params, cams[k], poses[k], d_rgb=host(grads[k]["d_rgb"]),
+                              d_depth=host(grads[k]["d_depth"]))["d_params"] for k in range(3))
+    check_grads(dp_batch, ref)
+
+
+def test_batch_pose_only_matches_single(pkg):
+    room, poses = _scene()
+    r = pkg.Rasterizer()
+    P = dev(room.params)
+    views = [(P, CAMS[k % 2], dev(poses[k].reshape(12))) for k in range(4)]
+    outs = r.render_batch(views)
+    g = np.random.default_rng(1)
+    grads = [{"d_rgb": dev(g.normal(size=(3, c.height, c.width))), "d_depth": dev(g.normal(size=(c.height, c.width)))}
+             for c in (CAMS[k % 2] for k in range(4))]
+    res = r.backward_batch(outs[0].generation, grads, params_grad=False)
+    torch.cuda.synchronize()
+    for k in range(4):
+        out = r.render(*views[k])
+        _, d_pose = r.backward(out.generation, grads[k]["d_rgb"], grads[k]["d_depth"], None, None,
+                               params_grad=False)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(res[k][1]), host(d_pose))
+
+
+def test_batch_tracking_equals_single(pkg):
+    """Three problems tracked together give each problem's single-problem history, bit for bit."""
+    problems, singles = [], []
+    r = pkg.Rasterizer()
+    for k in range(3):
+        room, pose = room_scene(100_000 * (k + 1), seed=20 + k, cam_seed=20 + k)
+        start = synth.perturb_pose(pose, 0.05, 3.0, seed=30 + k)
+        cam = CAMS[k % 2]
+        P = dev(room.params)
+        tgt = r.render(P, cam, dev(pose.reshape(12)))
+        problems.append((P, cam, dev(start.reshape(12)), tgt.rgb.clone(), tgt.depth.clone()))
+        singles.append(start)
+    torch.cuda.synchronize()
+    ph, lh = r.track_batch(problems, n_iters=15)
+    torch.cuda.synchronize()
+    for k, (P, cam, _, trgb, tdep) in enumerate(problems):
+        p = dev(singles[k].reshape(12))
+        _, sph, slh = r.track(P, cam, p, trgb, tdep, n_iters=15)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(ph[:, k]), host(sph))
+        np.testing.assert_array_equal(host(lh[:, k]), host(slh))
+        assert host(lh[-1, k]) < host(lh[0, k])
