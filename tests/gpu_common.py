@@ -31,7 +31,13 @@ def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth",
 
     colour and opacity: |d| <= 1e-4 absolute per channel; depth: |d| <= 1e-4 max(|ref|, 1e-3);
     normal: a 3-vector, so "1e-4 relative" is read on its norm,
-    ||d N||_2 <= 1e-4 max(||N_ref||_2, 1e-3) per pixel.
+    ||d N||_2 <= 1e-4 max(||N_ref||_2, 1e-3) per pixel, with one allowance: N is a sum of unit
+    normals weighted by w_i, and where they cancel (||N|| << sum_i w_i = O) the sum is
+    ill-conditioned.  FP32 rounding of a k-term blend is then bounded relative to the scale of
+    its terms, not of its result: each weight carries the rounding of the k transmittance
+    factors in front of it and the sum that of its own k additions, so
+    ||d N|| <= (2 k + 8) 2^-24 O (k = the pixel's composited count).  The bar is the larger of
+    the two; wherever ||N|| is not cancelled the first one is the binding one.
     Pixels with a decision margin below MARGIN are excluded and counted.
     """
     keep = margin >= MARGIN
@@ -48,6 +54,7 @@ def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth",
             err = np.abs(g - r)
         else:
             tol = 1e-4 * np.maximum(np.linalg.norm(r, axis=0), 1e-3)
+            tol = np.maximum(tol, (2.0 * ref["count"] + 8.0) * 2.0**-24 * ref["alpha"])
             err = np.linalg.norm(g - r, axis=0)
         bad = (err > tol) & (keep if err.ndim == 2 else keep[None])
         report[k] = float(err[..., keep].max()) if keep.any() else 0.0
