@@ -85,8 +85,10 @@ typedef struct gs2d_options {
   float z_near;              /* default 0.2: centre cull and per-pixel depth cut */
   int64_t pair_capacity;     /* tile-pair capacity; 0 (default): grow on demand */
   int32_t keep_unsorted;     /* 1: keep a copy of the pairs before the tile sort (tests) */
-  int32_t profile;           /* 1: time kernel families with HIP events and count blend work
-                                (calls outside graph capture only); see gs2d_get_profile */
+  int32_t profile;           /* 1: time kernel families with HIP events and count blend work;
+                                2: time them only (the blend kernels then run the same code as
+                                without profiling); calls outside graph capture only; see
+                                gs2d_get_profile */
 } gs2d_options;
 
 /* Counters of the last forward pass (gs2d_get_counts synchronises the stream). */
@@ -134,7 +136,7 @@ typedef struct gs2d_track_problem {
   const float* tgt_depth;    /* [H][W] */
 } gs2d_track_problem;
 
-/* Kernel-family timings and blend work counters (options.profile = 1). */
+/* Kernel-family timings (options.profile = 1 or 2) and blend work counters (profile = 1). */
 #define GS2D_PROFILE_FAMILIES 12
 typedef struct gs2d_profile {
   double ms[GS2D_PROFILE_FAMILIES];          /* summed event time per family since the last reset */
@@ -275,12 +277,12 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
 
 /* Copy an internal buffer of the last render to host memory (diagnostics and tests).
  * which: 0 sorted tile keys (uint32 [n_pairs]), 1 sorted surfel ids (uint32 [n_pairs]),
- * 2 tile ranges (uint32 [n_tiles][2]), 3 depth-sorted surfel keys (uint32 [n], ascending;
- * float32 camera depth bits, 0xFFFFFFFF for surfels that touch no tile; ids in 9),
+ * 2 tile ranges (uint32 [n_tiles][2]), 3 depth-sorted keys of the surfels that touch a
+ * tile (uint32 [n_visible], ascending float32 camera depth bits; ids in 9),
  * 4 per-surfel tile rect (uint16 [n][4]: x0, x1, y0, y1, inclusive; empty: x0 > x1),
  * 5 per-pixel final transmittance (float [H][W]), 6 per-pixel list length (uint32 [H][W]),
  * 7 unsorted tile keys, 8 unsorted surfel ids (uint32 [n_pairs], before the tile sort;
- * only with options.keep_unsorted = 1), 9 depth-sorted surfel ids (uint32 [n]).
+ * only with options.keep_unsorted = 1), 9 depth-sorted surfel ids (uint32 [n_visible]).
  * *bytes (host) is the buffer size in; the bytes copied out.  Synchronises `stream`. */
 GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes,
                              hipStream_t stream);
@@ -289,7 +291,7 @@ GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_
 GS2D_API const char* gs2d_profile_family(int i);
 
 /* Collect the profile since the last reset (synchronises `stream`); reset != 0
- * clears it afterwards.  GS2D_ERR_UNSUPPORTED unless options.profile = 1. */
+ * clears it afterwards.  GS2D_ERR_UNSUPPORTED when options.profile = 0. */
 GS2D_API int gs2d_get_profile(gs2d_ctx* ctx, gs2d_profile* out, int32_t reset, hipStream_t stream);
 
 /* Last hipError_t recorded by the context (0 if none). */

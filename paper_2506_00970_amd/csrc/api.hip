@@ -99,7 +99,7 @@ struct ProfScope {
 };
 
 unsigned long long* work_ptr(gs2d_ctx* ctx, hipStream_t s) {
-  if (!ctx->opt.profile) return nullptr;
+  if (ctx->opt.profile != 1) return nullptr;  // level 2 times the kernels without counting
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
   return ctx->ctrl->work;
@@ -115,7 +115,8 @@ int stream_capturing(hipStream_t s, bool* cap) {
 
 int ensure_hist(gs2d_ctx* ctx) {
   const int64_t items = ctx->n_cap > ctx->p_cap ? ctx->n_cap : ctx->p_cap;
-  const int64_t need = (items + kScanItems - 1) / kScanItems * 256;
+  // digit-major rows of every block plus the 256 row totals
+  const int64_t need = ((items + kScanItems - 1) / kScanItems + 1) * 256;
   if (need <= ctx->hist_cap) return GS2D_OK;
   GS2D_TRY(realloc_dev(ctx, &ctx->hist, need));
   ctx->hist_cap = need;
@@ -292,17 +293,19 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     {
       ProfScope ps(ctx, kPre, s);
       launch_preprocess(ctx->views, nv, items, ctx->opt.z_near, ctx->opt.filter, tw, th, ctx->rec, ctx->rect,
-                        ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, s);
+                        ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, ctx->ctrl, s);
     }
     int dbuf;
     {
       ProfScope ps(ctx, kDepthSort, s);
-      dbuf = radix_sort(ctx->dkey, ctx->dval, items, items, nullptr, 32, ctx->hist, s);
+      // the first pass keeps only the surfels that touch a tile
+      dbuf = radix_sort(ctx->dkey, ctx->dval, items, items, nullptr, 32, ctx->hist, &ctx->ctrl->n_visible, s);
     }
     if (dbuf != 0) return GS2D_ERR_HIP;  // four 8-bit passes end in buffer 0
     {
       ProfScope ps(ctx, kScan, s);
-      launch_scan_counts(ctx->count, ctx->dval[0], (int)items, ctx->offs, ctx->block_sums, ctx->ctrl, s);
+      launch_scan_counts(ctx->count, ctx->dval[0], &ctx->ctrl->n_visible, (int)items, ctx->offs, ctx->block_sums,
+                         ctx->ctrl, s);
     }
     if (allow_sync && !capturing && !ctx->pair_fixed) {
       GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -312,8 +315,8 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     }
     {
       ProfScope ps(ctx, kDup, s);
-      launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, ctx->views, nv, (int)items, ctx->p_cap,
-                       ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
+      launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, ctx->views, nv, &ctx->ctrl->n_visible,
+                       (int)items, ctx->p_cap, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
     }
     if (ctx->opt.keep_unsorted && ctx->pkey_keep) {
       launch_copy_u32(ctx->pkey[0], ctx->pkey_keep, ctx->p_cap, s);
@@ -322,7 +325,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     {
       ProfScope ps(ctx, kTileSort, s);
       pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits((int)vs.tiles),
-                        ctx->hist, s);
+                        ctx->hist, nullptr, s);
     }
     {
       ProfScope ps(ctx, kRanges, s);
@@ -667,7 +670,7 @@ GS2D_API int gs2d_create(gs2d_ctx** out, int device, const gs2d_options* opt) {
   if (opt) o = *opt;
   if (!valid_tile(o.tile_w, o.tile_h) || !valid_batch(o.batch) || !(o.z_near > 0.f) ||
       !std::isfinite(o.z_near) || o.pair_capacity < 0 || (o.filter != 0 && o.filter != 1) ||
-      (o.profile != 0 && o.profile != 1))
+      o.profile < 0 || o.profile > 2)
     return GS2D_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -841,13 +844,13 @@ GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_
     case 0: src = ctx->pkey[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 1: src = ctx->pval[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 2: src = ctx->ranges; need = (size_t)ctx->last_views.tiles * 8; break;
-    case 3: src = ctx->dkey[0]; need = (size_t)items * 4; break;
+    case 3: src = ctx->dkey[0]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
     case 4: src = ctx->rect; need = (size_t)items * 8; break;
     case 5: src = ctx->t_final; need = (size_t)pixels * 4; break;
     case 6: src = ctx->last; need = (size_t)pixels * 4; break;
     case 7: src = ctx->pkey_keep; need = (size_t)np * 4; break;
     case 8: src = ctx->pval_keep; need = (size_t)np * 4; break;
-    case 9: src = ctx->dval[0]; need = (size_t)items * 4; break;
+    case 9: src = ctx->dval[0]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
     default: return GS2D_ERR_INVALID_ARG;
   }
   if (!src) return GS2D_ERR_UNSUPPORTED;

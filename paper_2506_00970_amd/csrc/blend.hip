@@ -102,12 +102,72 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Entries [c0, c0 + 64) of a staged batch of nb: the mask of those whose footprint
+// box overlaps the wave's 8x8 block [bx0, bx1] x [by0, by1] (lane k tests entry
+// c0 + k) and whose list position is below `limit`.  The mask is wave-uniform.
+__device__ __forceinline__ uint64_t overlap_mask(const float4* sbox, int c0, int nb, int lane, float bx0,
+                                                 float bx1, float by0, float by1, int pos0, int limit) {
+  const int j = c0 + lane;
+  bool hit = false;
+  if (j < nb && pos0 + j < limit) {
+    const float4 bb = sbox[j];
+    hit = !(bb.y < bx0 || bb.x > bx1 || bb.w < by0 || bb.z > by1);
+  }
+  return __ballot(hit);
+}
+
+// A staged record: box corner (x0, y0), rows g1..g3, (o, rgb), normal.
+struct Rec {
+  float ox, oy;
+  float4 g1, g2, g3, c4, nv;
+};
+__device__ __forceinline__ Rec load_rec(const float4* srec, int j) {
+  Rec r;
+  const float4 bb = srec[j * kRecF4];
+  r.ox = bb.x;
+  r.oy = bb.z;
+  r.g1 = srec[j * kRecF4 + 1];
+  r.g2 = srec[j * kRecF4 + 2];
+  r.g3 = srec[j * kRecF4 + 3];
+  r.c4 = srec[j * kRecF4 + 4];
+  r.nv = srec[j * kRecF4 + 5];
+  return r;
+}
+
+struct FwdPix {
+  float T, cr, cg, cb, cd, n0, n1, n2, co;
+  int lastj;
+  bool done;
+};
+
+// Front-to-back compositing of one evaluated entry (list position pos).
+__device__ __forceinline__ void composite(FwdPix& s, int code, const Hit& h, const Rec& r, int pos) {
+  if (s.done || code != 2) return;
+  const float Tn = s.T * (1.0f - h.alpha);
+  if (Tn < kTMin) {
+    s.done = true;
+    return;
+  }
+  const float w = h.alpha * s.T;
+  s.cr = fmaf(w, r.c4.y, s.cr);
+  s.cg = fmaf(w, r.c4.z, s.cg);
+  s.cb = fmaf(w, r.c4.w, s.cb);
+  s.cd = fmaf(w, h.d, s.cd);
+  s.n0 = fmaf(w, r.nv.x, s.n0);
+  s.n1 = fmaf(w, r.nv.y, s.n1);
+  s.n2 = fmaf(w, r.nv.z, s.n2);
+  s.co += w;
+  s.T = Tn;
+  s.lastj = pos + 1;
+}
+
 template <int TW, int TH, bool PROF>
 __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ t_final,
                                                            uint32_t* __restrict__ last_out,
                                                            unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8;
   extern __shared__ float4 srec[];
+  float4* sbox = srec + (size_t)a.batch * kRecF4;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);  // global tile over all views
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const int lt = tile - V.tile_base;
@@ -120,51 +180,49 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x, end = (int)rg.y;
-  float T = 1.0f, cr = 0.f, cg = 0.f, cb = 0.f, cd = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f, co = 0.f;
-  int lastj = 0;
+  FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
   int n_eval = 0, n_cov = 0;
-  bool done = !inside;
   for (int b0 = start; b0 < end; b0 += a.batch) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(!s.done) == 0) break;
     const int nb = min(a.batch, end - b0);
     for (int k = t; k < nb * kRecF4; k += NT) {
       const int j = k / kRecF4, f = k - j * kRecF4;
-      srec[k] = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
+      const float4 v = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
+      srec[k] = v;
+      if (f == 0) sbox[j] = v;
     }
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      if (__ballot(!done) == 0ull) break;
-      const float4 bb = srec[j * kRecF4];
-      if (uniformf(bb.y) < bx0 || uniformf(bb.x) > bx1 || uniformf(bb.w) < by0 || uniformf(bb.z) > by1)
-        continue;
-      if (!done) {
-        const float4 c4 = srec[j * kRecF4 + 4];
-        Hit h;
-        const int code = evaluate(fpx, fpy, bb.x, bb.z, srec[j * kRecF4 + 1], srec[j * kRecF4 + 2],
-                                  srec[j * kRecF4 + 3], c4.x, a.z_near, a.filter, h);
-        if (PROF) {
-          n_eval += 1;
-          n_cov += code > 0;
-        }
-        if (code == 2) {
-          const float Tn = T * (1.0f - h.alpha);
-          if (Tn < kTMin) {
-            done = true;
-          } else {
-            const float w = h.alpha * T;
-            const float4 nv = srec[j * kRecF4 + 5];
-            cr = fmaf(w, c4.y, cr);
-            cg = fmaf(w, c4.z, cg);
-            cb = fmaf(w, c4.w, cb);
-            cd = fmaf(w, h.d, cd);
-            n0 = fmaf(w, nv.x, n0);
-            n1 = fmaf(w, nv.y, n1);
-            n2 = fmaf(w, nv.z, n2);
-            co += w;
-            T = Tn;
-            lastj = b0 - start + j + 1;
+    const int pos0 = b0 - start;
+    for (int c0 = 0; c0 < nb; c0 += 64) {
+      if (__ballot(!s.done) == 0ull) break;
+      uint64_t m = overlap_mask(sbox, c0, nb, lane, bx0, bx1, by0, by1, 0, nb);
+      // two overlapping entries per step: their evaluations are independent, the
+      // compositing stays in list order
+      while (m != 0ull) {
+        const int j1 = c0 + __builtin_ctzll(m);
+        m &= m - 1ull;
+        const bool two = m != 0ull;
+        const int j2 = two ? c0 + __builtin_ctzll(m) : j1;
+        if (two) m &= m - 1ull;
+        if (!s.done) {
+          const Rec r1 = load_rec(srec, j1), r2 = load_rec(srec, j2);
+          Hit h1, h2;
+          const int k1 = evaluate(fpx, fpy, r1.ox, r1.oy, r1.g1, r1.g2, r1.g3, r1.c4.x, a.z_near, a.filter, h1);
+          const int k2 = evaluate(fpx, fpy, r2.ox, r2.oy, r2.g1, r2.g2, r2.g3, r2.c4.x, a.z_near, a.filter, h2);
+          if (PROF) {
+            n_eval += 1;
+            n_cov += k1 > 0;
+          }
+          composite(s, k1, h1, r1, pos0 + j1);
+          if (two && !s.done) {
+            if (PROF) {
+              n_eval += 1;
+              n_cov += k2 > 0;
+            }
+            composite(s, k2, h2, r2, pos0 + j2);
           }
         }
+        if (__ballot(!s.done) == 0ull) break;
       }
     }
   }
@@ -173,19 +231,138 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   const int HW = V.cam.width * V.cam.height;
   const int p = py * V.cam.width + px;
   if (V.rgb) {
-    V.rgb[p] = cr;
-    V.rgb[HW + p] = cg;
-    V.rgb[2 * HW + p] = cb;
+    V.rgb[p] = s.cr;
+    V.rgb[HW + p] = s.cg;
+    V.rgb[2 * HW + p] = s.cb;
   }
-  if (V.depth) V.depth[p] = cd;
+  if (V.depth) V.depth[p] = s.cd;
   if (V.normal) {
-    V.normal[p] = n0;
-    V.normal[HW + p] = n1;
-    V.normal[2 * HW + p] = n2;
+    V.normal[p] = s.n0;
+    V.normal[HW + p] = s.n1;
+    V.normal[2 * HW + p] = s.n2;
   }
-  if (V.alpha) V.alpha[p] = co;
-  t_final[V.pix_base + p] = T;
-  last_out[V.pix_base + p] = (uint32_t)lastj;
+  if (V.alpha) V.alpha[p] = s.co;
+  t_final[V.pix_base + p] = s.T;
+  last_out[V.pix_base + p] = (uint32_t)s.lastj;
+}
+
+// Per-pixel state of the backward walk.
+struct BwdPix {
+  float T;                                   // transmittance in front of the next entry
+  float gr, gg, gb, gd, gn0, gn1, gn2, go;   // image-space gradients of the pixel
+  float Br, Bg, Bb, Bd, Bn0, Bn1, Bn2, Bo;   // blended values behind the next entry
+  float pr0, pr1, pr2, pp0, pp1, pp2;        // pose gradient (pose-only mode)
+};
+
+// Reverse mode of one composited entry: updates the walk state and either the
+// pose sums (pose-only) or the entry's 16 per-surfel terms acc.
+template <bool POSE_ONLY, bool HAS_N, bool HAS_O>
+__device__ __forceinline__ void reverse_entry(BwdPix& s, const Hit& h, const Rec& r, const CamF& cam, float xh,
+                                              float yh, float* acc) {
+  const float4 c4 = r.c4, nv = r.nv;
+  const float al = h.alpha;
+  const float Tj = s.T * __builtin_amdgcn_rcpf(1.0f - al);
+  const float w = al * Tj;
+  float dLda = s.gr * (c4.y - s.Br) + s.gg * (c4.z - s.Bg) + s.gb * (c4.w - s.Bb) + s.gd * (h.d - s.Bd);
+  if (HAS_N) dLda += s.gn0 * (nv.x - s.Bn0) + s.gn1 * (nv.y - s.Bn1) + s.gn2 * (nv.z - s.Bn2);
+  if (HAS_O) dLda += s.go * (1.0f - s.Bo);
+  dLda *= Tj;
+  s.Br = fmaf(al, c4.y - s.Br, s.Br);
+  s.Bg = fmaf(al, c4.z - s.Bg, s.Bg);
+  s.Bb = fmaf(al, c4.w - s.Bb, s.Bb);
+  s.Bd = fmaf(al, h.d - s.Bd, s.Bd);
+  if (HAS_N) {
+    s.Bn0 = fmaf(al, nv.x - s.Bn0, s.Bn0);
+    s.Bn1 = fmaf(al, nv.y - s.Bn1, s.Bn1);
+    s.Bn2 = fmaf(al, nv.z - s.Bn2, s.Bn2);
+  }
+  if (HAS_O) s.Bo = fmaf(al, 1.0f - s.Bo, s.Bo);
+  s.T = Tj;
+  const float g_d = w * s.gd;
+  float g_o = 0.f, dLdG = 0.f;
+  if (!h.clamped) {
+    g_o = h.G * dLda;
+    dLdG = c4.x * dLda;
+  }
+  const float dLdrho = -0.5f * h.G * dLdG;
+  const float m0 = r.g3.y, m1 = r.g3.z, m2 = r.g3.w;
+  float Vx, Vy, Vz, ue, ve, Xx, Xy, Xz;
+  if (h.b3d) {
+    // u = q0/q2, v = q1/q2; depth d = m . (u, v, 1)
+    const float gu = fmaf(2.0f * h.u, dLdrho, m0 * g_d);
+    const float gv = fmaf(2.0f * h.v, dLdrho, m1 * g_d);
+    const float gq0 = gu * h.rq, gq1 = gv * h.rq;
+    // h_u = P - dx m, h_v = Q - dy m (third entries -dx m2, -dy m2)
+    const float hu0 = fmaf(-h.dx, m0, r.g2.y), hu1 = fmaf(-h.dx, m1, r.g2.z);
+    const float hv0 = fmaf(-h.dy, m0, r.g2.w), hv1 = fmaf(-h.dy, m1, r.g3.x);
+    const float V0 = hv0 * gq1 - hv1 * gq0;  // (h_v x g_q)_z
+    const float V1 = gq0 * hu1 - gq1 * hu0;  // (g_q x h_u)_z
+    Vx = cam.fx * V0;
+    Vy = cam.fy * V1;
+    Vz = g_d - xh * Vx - yh * Vy;
+    ue = h.u;
+    ve = h.v;
+    Xx = h.d * xh;
+    Xy = h.d * yh;
+    Xz = h.d;
+  } else {
+    // rho = 2 |p - c|^2 with c = (M02, M12) / m2; depth = m2
+    const float gcx = -2.0f * kFilterScale * h.dx * dLdrho;
+    const float gcy = -2.0f * kFilterScale * h.dy * dLdrho;
+    const float im2 = 1.0f / m2;
+    Vx = cam.fx * gcx * im2;
+    Vy = cam.fy * gcy * im2;
+    const float xc = ((r.ox + r.g1.x) - cam.cx) / cam.fx, yc = ((r.oy + r.g1.y) - cam.cy) / cam.fy;
+    Vz = g_d - xc * Vx - yc * Vy;
+    ue = 0.f;
+    ve = 0.f;
+    Xx = m2 * xc;
+    Xy = m2 * yc;
+    Xz = m2;
+  }
+  if (POSE_ONLY) {
+    s.pr0 += Vx;
+    s.pr1 += Vy;
+    s.pr2 += Vz;
+    s.pp0 += Xy * Vz - Xz * Vy;
+    s.pp1 += Xz * Vx - Xx * Vz;
+    s.pp2 += Xx * Vy - Xy * Vx;
+    if (HAS_N) {
+      const float w0 = w * s.gn0, w1 = w * s.gn1, w2 = w * s.gn2;
+      s.pp0 += nv.y * w2 - nv.z * w1;
+      s.pp1 += nv.z * w0 - nv.x * w2;
+      s.pp2 += nv.x * w1 - nv.y * w0;
+    }
+  } else {
+    acc[0] = Vx;
+    acc[1] = Vy;
+    acc[2] = Vz;
+    acc[3] = ue * Vx;
+    acc[4] = ue * Vy;
+    acc[5] = ue * Vz;
+    acc[6] = ve * Vx;
+    acc[7] = ve * Vy;
+    acc[8] = ve * Vz;
+    acc[9] = w * s.gn0;
+    acc[10] = w * s.gn1;
+    acc[11] = w * s.gn2;
+    acc[12] = w * s.gr;
+    acc[13] = w * s.gg;
+    acc[14] = w * s.gb;
+    acc[15] = g_o;
+  }
+}
+
+// Full mode: the wave's sum of one entry's 16 terms, added to the surfel's row.
+__device__ __forceinline__ void flush_entry(const float* acc, bool contrib, float* __restrict__ gacc, uint32_t id,
+                                            int lane) {
+  if (__ballot(contrib) == 0ull) return;
+  float* dst = gacc + (size_t)id * 16;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float v = wave_sum(contrib ? acc[k] : 0.f);
+    if (lane == 0) atomicAdd(dst + k, v);
+  }
 }
 
 template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>
@@ -195,7 +372,8 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
                                                            unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
   extern __shared__ float4 srec[];
-  uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * kRecF4);
+  float4* sbox = srec + (size_t)a.batch * kRecF4;
+  uint32_t* sid = reinterpret_cast<uint32_t*>(sbox + a.batch);
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);  // global tile over all views
@@ -212,27 +390,25 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   const int HW = cam.width * cam.height;
   const int p = py * cam.width + px;
   int my_last = 0;
-  float T = 1.0f;
-  float gr = 0.f, gg = 0.f, gbl = 0.f, gd = 0.f, gn0 = 0.f, gn1 = 0.f, gn2 = 0.f, go = 0.f;
+  BwdPix s{};
+  s.T = 1.0f;
   if (inside) {
     my_last = (int)last_in[V.pix_base + p];
-    T = t_final[V.pix_base + p];
+    s.T = t_final[V.pix_base + p];
     if (V.g_rgb) {
-      gr = V.g_rgb[p];
-      gg = V.g_rgb[HW + p];
-      gbl = V.g_rgb[2 * HW + p];
+      s.gr = V.g_rgb[p];
+      s.gg = V.g_rgb[HW + p];
+      s.gb = V.g_rgb[2 * HW + p];
     }
-    if (V.g_depth) gd = V.g_depth[p];
+    if (V.g_depth) s.gd = V.g_depth[p];
     if (HAS_N && V.g_normal) {
-      gn0 = V.g_normal[p];
-      gn1 = V.g_normal[HW + p];
-      gn2 = V.g_normal[2 * HW + p];
+      s.gn0 = V.g_normal[p];
+      s.gn1 = V.g_normal[HW + p];
+      s.gn2 = V.g_normal[2 * HW + p];
     }
-    if (HAS_O && V.g_alpha) go = V.g_alpha[p];
+    if (HAS_O && V.g_alpha) s.go = V.g_alpha[p];
   }
   const float xh = (fpx - cam.cx) / cam.fx, yh = (fpy - cam.cy) / cam.fy;
-  float Br = 0.f, Bg = 0.f, Bb = 0.f, Bd = 0.f, Bn0 = 0.f, Bn1 = 0.f, Bn2 = 0.f, Bo = 0.f;
-  float pr0 = 0.f, pr1 = 0.f, pr2 = 0.f, pp0 = 0.f, pp1 = 0.f, pp2 = 0.f;
   int n_eval = 0, n_cov = 0;
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x;
@@ -251,162 +427,66 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
     for (int k = t; k < nb * kRecF4; k += NT) {
       const int j = k / kRecF4, f = k - j * kRecF4;
       const uint32_t id = a.pval[start + bstart + j];
-      srec[k] = a.rec[(size_t)id * kRecF4 + f];
-      if (f == 0) sid[j] = id;
+      const float4 v = a.rec[(size_t)id * kRecF4 + f];
+      srec[k] = v;
+      if (f == 0) {
+        sbox[j] = v;
+        sid[j] = id;
+      }
     }
     __syncthreads();
-    for (int jj = nb - 1; jj >= 0; --jj) {
-      const int j = bstart + jj;
-      if (j >= wlast) continue;
-      const float4 bb = srec[jj * kRecF4];
-      if (uniformf(bb.y) < bx0 || uniformf(bb.x) > bx1 || uniformf(bb.w) < by0 || uniformf(bb.z) > by1)
-        continue;
-      float acc[16];
-      if (!POSE_ONLY) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-      }
-      bool contrib = false;
-      if (j < my_last) {
-        const float4 g1 = srec[jj * kRecF4 + 1], g2 = srec[jj * kRecF4 + 2], g3 = srec[jj * kRecF4 + 3];
-        const float4 c4 = srec[jj * kRecF4 + 4];
-        Hit h;
-        const int code = evaluate(fpx, fpy, bb.x, bb.z, g1, g2, g3, c4.x, a.z_near, a.filter, h);
+    // chunks of 64 from the back; within a chunk the overlapping entries below the
+    // wave's last position, highest first, two per step
+    for (int c1 = nb; c1 > 0; c1 -= 64) {
+      const int c0 = max(0, c1 - 64);
+      uint64_t m = overlap_mask(sbox, c0, c1, lane, bx0, bx1, by0, by1, bstart, wlast);
+      while (m != 0ull) {
+        const int b1 = 63 - __builtin_clzll(m);
+        m &= ~(1ull << b1);
+        const bool two = m != 0ull;
+        const int b2 = two ? 63 - __builtin_clzll(m) : b1;
+        if (two) m &= ~(1ull << b2);
+        const int j1 = c0 + b1, j2 = c0 + b2;
+        const Rec r1 = load_rec(srec, j1), r2 = load_rec(srec, j2);
+        const bool live1 = bstart + j1 < my_last, live2 = two && bstart + j2 < my_last;
+        Hit h1, h2;
+        const int k1 = evaluate(fpx, fpy, r1.ox, r1.oy, r1.g1, r1.g2, r1.g3, r1.c4.x, a.z_near, a.filter, h1);
+        const int k2 = evaluate(fpx, fpy, r2.ox, r2.oy, r2.g1, r2.g2, r2.g3, r2.c4.x, a.z_near, a.filter, h2);
         if (PROF) {
-          n_eval += 1;
-          n_cov += code > 0;
+          n_eval += (int)live1 + (int)live2;
+          n_cov += (int)(live1 && k1 > 0) + (int)(live2 && k2 > 0);
         }
-        if (code == 2) {
-          contrib = true;
-          const float4 nv = srec[jj * kRecF4 + 5];
-          const float al = h.alpha;
-          const float Tj = T * __builtin_amdgcn_rcpf(1.0f - al);
-          const float w = al * Tj;
-          float dLda = gr * (c4.y - Br) + gg * (c4.z - Bg) + gbl * (c4.w - Bb) + gd * (h.d - Bd);
-          if (HAS_N) dLda += gn0 * (nv.x - Bn0) + gn1 * (nv.y - Bn1) + gn2 * (nv.z - Bn2);
-          if (HAS_O) dLda += go * (1.0f - Bo);
-          dLda *= Tj;
-          Br = fmaf(al, c4.y - Br, Br);
-          Bg = fmaf(al, c4.z - Bg, Bg);
-          Bb = fmaf(al, c4.w - Bb, Bb);
-          Bd = fmaf(al, h.d - Bd, Bd);
-          if (HAS_N) {
-            Bn0 = fmaf(al, nv.x - Bn0, Bn0);
-            Bn1 = fmaf(al, nv.y - Bn1, Bn1);
-            Bn2 = fmaf(al, nv.z - Bn2, Bn2);
-          }
-          if (HAS_O) Bo = fmaf(al, 1.0f - Bo, Bo);
-          T = Tj;
-          const float g_d = w * gd;
-          float g_o = 0.f, dLdG = 0.f;
-          if (!h.clamped) {
-            g_o = h.G * dLda;
-            dLdG = c4.x * dLda;
-          }
-          const float dLdrho = -0.5f * h.G * dLdG;
-          const float m0 = g3.y, m1 = g3.z, m2 = g3.w;
-          float Vx, Vy, Vz, ue, ve, Xx, Xy, Xz;
-          if (h.b3d) {
-            // u = q0/q2, v = q1/q2; depth d = m . (u, v, 1)
-            const float gu = fmaf(2.0f * h.u, dLdrho, m0 * g_d);
-            const float gv = fmaf(2.0f * h.v, dLdrho, m1 * g_d);
-            const float gq0 = gu * h.rq, gq1 = gv * h.rq;
-            // h_u = P - dx m, h_v = Q - dy m (third entries -dx m2, -dy m2)
-            const float hu0 = fmaf(-h.dx, m0, g2.y), hu1 = fmaf(-h.dx, m1, g2.z);
-            const float hv0 = fmaf(-h.dy, m0, g2.w), hv1 = fmaf(-h.dy, m1, g3.x);
-            const float V0 = hv0 * gq1 - hv1 * gq0;  // (h_v x g_q)_z
-            const float V1 = gq0 * hu1 - gq1 * hu0;  // (g_q x h_u)_z
-            Vx = cam.fx * V0;
-            Vy = cam.fy * V1;
-            Vz = g_d - xh * Vx - yh * Vy;
-            ue = h.u;
-            ve = h.v;
-            Xx = h.d * xh;
-            Xy = h.d * yh;
-            Xz = h.d;
-          } else {
-            // rho = 2 |p - c|^2 with c = (M02, M12) / m2; depth = m2
-            const float gcx = -2.0f * kFilterScale * h.dx * dLdrho;
-            const float gcy = -2.0f * kFilterScale * h.dy * dLdrho;
-            const float im2 = 1.0f / m2;
-            Vx = cam.fx * gcx * im2;
-            Vy = cam.fy * gcy * im2;
-            const float xc = ((bb.x + g1.x) - cam.cx) / cam.fx, yc = ((bb.z + g1.y) - cam.cy) / cam.fy;
-            Vz = g_d - xc * Vx - yc * Vy;
-            ue = 0.f;
-            ve = 0.f;
-            Xx = m2 * xc;
-            Xy = m2 * yc;
-            Xz = m2;
-          }
-          if (POSE_ONLY) {
-            pr0 += Vx;
-            pr1 += Vy;
-            pr2 += Vz;
-            pp0 += Xy * Vz - Xz * Vy;
-            pp1 += Xz * Vx - Xx * Vz;
-            pp2 += Xx * Vy - Xy * Vx;
-            if (HAS_N) {
-              const float w0 = w * gn0, w1 = w * gn1, w2 = w * gn2;
-              pp0 += nv.y * w2 - nv.z * w1;
-              pp1 += nv.z * w0 - nv.x * w2;
-              pp2 += nv.x * w1 - nv.y * w0;
-            }
-          } else {
-            acc[0] = Vx;
-            acc[1] = Vy;
-            acc[2] = Vz;
-            acc[3] = ue * Vx;
-            acc[4] = ue * Vy;
-            acc[5] = ue * Vz;
-            acc[6] = ve * Vx;
-            acc[7] = ve * Vy;
-            acc[8] = ve * Vz;
-            acc[9] = w * gn0;
-            acc[10] = w * gn1;
-            acc[11] = w * gn2;
-            acc[12] = w * gr;
-            acc[13] = w * gg;
-            acc[14] = w * gbl;
-            acc[15] = g_o;
-          }
-        }
-      }
-      if (!POSE_ONLY) {
-        if (__ballot(contrib) != 0ull) {
-          const uint32_t id = sid[jj];
-          float* dst = gacc + (size_t)id * 16;
-#pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            const float v = wave_sum(acc[k]);
-            if (lane == 0) atomicAdd(dst + k, v);
-          }
-        }
+        float acc1[16], acc2[16];
+        const bool c1on = live1 && k1 == 2, c2on = live2 && k2 == 2;
+        if (c1on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h1, r1, cam, xh, yh, acc1);
+        if (!POSE_ONLY) flush_entry(acc1, c1on, gacc, sid[j1], lane);
+        if (c2on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h2, r2, cam, xh, yh, acc2);
+        if (!POSE_ONLY && two) flush_entry(acc2, c2on, gacc, sid[j2], lane);
       }
     }
   }
   if (PROF) add_work(work + 2, lane, n_eval, n_cov);
   if (POSE_ONLY) {
-    float v[6] = {pr0, pr1, pr2, pp0, pp1, pp2};
+    float v[6] = {s.pr0, s.pr1, s.pr2, s.pp0, s.pp1, s.pp2};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const float s = wave_sum(v[k]);
-      if (lane == 0) s_red[wave][k] = s;
+      const float sum = wave_sum(v[k]);
+      if (lane == 0) s_red[wave][k] = sum;
     }
     __syncthreads();
     if (t < 8) {
-      float s = 0.f;
+      float sum = 0.f;
       if (t < 6)
 #pragma unroll
-        for (int w = 0; w < NW; ++w) s += s_red[w][t];
-      part[(size_t)tile * 8 + t] = s;
+        for (int w = 0; w < NW; ++w) sum += s_red[w][t];
+      part[(size_t)tile * 8 + t] = sum;
     }
   }
 }
 
 template <int TW, int TH>
 void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * kRecF4 * sizeof(float4);
+  const size_t lds = (size_t)a.batch * (kRecF4 + 1) * sizeof(float4);
   if (work)
     blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
   else
@@ -416,7 +496,7 @@ void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long
 template <int TW, int TH, bool PO, bool HN, bool HO>
 void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, float* gacc, float* part,
                  unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * (kRecF4 * sizeof(float4) + sizeof(uint32_t));
+  const size_t lds = (size_t)a.batch * ((kRecF4 + 1) * sizeof(float4) + sizeof(uint32_t));
   if (work)
     blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
   else

@@ -184,7 +184,7 @@ namespace gs2d {
 void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s);
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
                        int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, uint32_t* dval,
-                       float* saved_pose, hipStream_t s);
+                       float* saved_pose, Ctrl* ctrl, hipStream_t s);
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc, float* d_params,
                            int accumulate, float* part, hipStream_t s);
 
@@ -192,16 +192,23 @@ void launch_preprocess_bwd(const float* params, int n, const float* pose, const 
 constexpr int kScanItems = 2048;   // items per block of the scans and radix passes
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
-void launch_scan_counts(const uint32_t* count, const uint32_t* perm, int n, uint32_t* offs,
-                        uint32_t* block_sums, Ctrl* ctrl, hipStream_t s);
+// Exclusive scan of count[perm[j]] over j < n into offs, the total into ctrl->n_pairs
+// (and ctrl->overflow cleared); n = *n_dev clamped to limit, or limit without n_dev.
+void launch_scan_counts(const uint32_t* count, const uint32_t* perm, const uint32_t* n_dev, int limit,
+                        uint32_t* offs, uint32_t* block_sums, Ctrl* ctrl, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [0, bits).  n is taken from
 // *n_dev (clamped to cap) when n_dev is non-null (capacity-sized grid), else n_host.
+// With n_kept (zero on entry) the first pass drops keys equal to 0xFFFFFFFF and counts
+// the others into *n_kept, which is the item count of the later passes: the result
+// then holds the kept pairs only, in front.  hist holds 256 (blocks(cap) + 1) words.
 // Returns the index (0 or 1) of the buffer holding the result.
 int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host,
-               const uint32_t* n_dev, int bits, uint32_t* hist, hipStream_t s);
+               const uint32_t* n_dev, int bits, uint32_t* hist, uint32_t* n_kept, hipStream_t s);
+// Pairs of the first n depth-sorted items (n = *n_dev clamped to limit).
 void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
-                      const uint2* rect, const ViewDesc* views, int n_views, int n, int64_t p_cap,
-                      uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles, hipStream_t s);
+                      const uint2* rect, const ViewDesc* views, int n_views, const uint32_t* n_dev, int limit,
+                      int64_t p_cap, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles,
+                      hipStream_t s);
 void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s);
 void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s);

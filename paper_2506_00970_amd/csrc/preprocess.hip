@@ -36,8 +36,10 @@ __global__ void upload_views_kernel(ViewChunk c, ViewDesc* __restrict__ dst) {
 __global__ __launch_bounds__(256) void preprocess_kernel(
     const ViewDesc* __restrict__ views, int n_views, int64_t items, float z_near, int filter, int tile_w,
     int tile_h, float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ count,
-    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, float* __restrict__ saved_pose) {
+    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, float* __restrict__ saved_pose,
+    Ctrl* __restrict__ ctrl) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi == 0) ctrl->n_visible = 0;  // counted by the depth sort's first pass
   if (gi >= items) return;
   const int item = (int)gi;
   const int v = view_of_item(views, n_views, item);
@@ -270,10 +272,10 @@ void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s) {
 
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
                        int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, uint32_t* dval,
-                       float* saved_pose, hipStream_t s) {
+                       float* saved_pose, Ctrl* ctrl, hipStream_t s) {
   const int grid = items > 0 ? (int)((items + 255) / 256) : 1;
   preprocess_kernel<<<grid, 256, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec, rect, count,
-                                         dkey, dval, saved_pose);
+                                         dkey, dval, saved_pose, ctrl);
 }
 
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc,

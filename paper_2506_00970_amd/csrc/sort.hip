@@ -9,13 +9,20 @@
 // ascending (depth, index), the order of the per-pixel definition.
 //
 // Radix pass = three kernels over blocks of kScanItems keys:
-//   hist    per-block digit histogram (LDS atomics, one sub-histogram per wave)
-//   offsets one workgroup: exclusive scan of the digit-major histograms, giving
-//           every (block, digit) its global output offset
-//   scatter per block, 8 rounds of 256 keys: a wave-level multi-split (ballots
-//           over the digit bits give each lane the mask of lanes holding the
-//           same digit), a per-digit prefix over the 4 waves in LDS, and the
-//           running per-digit offset across rounds keep the pass stable.
+//   hist    per-block digit histogram (LDS atomics, one sub-histogram per wave),
+//           stored digit-major: row d holds digit d's count in every block
+//   offsets one workgroup per digit: exclusive scan of that digit's row (its
+//           offset within the digit) and the row total
+//   scatter per block: the digit bases (an LDS scan of the 256 row totals) plus
+//           the row prefix give each digit's first output slot; then 8 rounds of
+//           256 keys: a wave-level multi-split (ballots over the digit bits give
+//           each lane the mask of lanes holding the same digit), a per-digit
+//           prefix over the 4 waves in LDS, and the running per-digit offset
+//           across rounds keep the pass stable.
+// The depth sort's first pass also compacts: items whose key is kDropKey (surfels
+// that touch no tile) are left out of the histogram and the scatter, so the pass
+// writes only the visible items, in stable order, and counts them on the device;
+// the remaining passes and everything after them run over that count.
 // Kernels whose item count lives on the device read it and exit early, so a
 // capacity-sized launch can be captured in a graph.
 #include "gs2d_internal.h"
@@ -27,6 +34,7 @@ constexpr int kThreads = 256;
 constexpr int kRounds = kScanItems / kThreads;  // 8
 constexpr int kDigits = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,9 +71,20 @@ __device__ inline uint32_t load_count(const uint32_t* count, const uint32_t* per
   return perm ? count[perm[i]] : count[i];
 }
 
+// Item count of a pass: the device count clamped to the buffer capacity
+// (`limit`), or `limit` itself when there is no device count.
+__device__ inline int64_t item_count(const uint32_t* n_dev, int64_t limit) {
+  if (!n_dev) return limit;
+  const int64_t n = (int64_t)(*n_dev);
+  return n < limit ? n : limit;
+}
+
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ count,
-                                                               const uint32_t* __restrict__ perm, int n,
+                                                               const uint32_t* __restrict__ perm,
+                                                               const uint32_t* __restrict__ n_dev, int limit,
                                                                uint32_t* __restrict__ block_sums) {
+  const int n = (int)item_count(n_dev, limit);
+  if ((int64_t)blockIdx.x * kScanItems >= n) return;
   __shared__ uint32_t sh[kThreads];
   const int base = blockIdx.x * kScanItems + threadIdx.x * kRounds;
   uint32_t s = 0;
@@ -80,9 +99,12 @@ __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* _
   if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint32_t* __restrict__ block_sums, int nb,
+__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint32_t* __restrict__ block_sums,
+                                                               const uint32_t* __restrict__ n_dev, int limit,
                                                                Ctrl* __restrict__ ctrl) {
-  // one block: exclusive scan of nb block sums, in chunks of 256
+  // one block: exclusive scan of the active blocks' sums, in chunks of 256
+  const int n = (int)item_count(n_dev, limit);
+  const int nb = (n + kScanItems - 1) / kScanItems;
   __shared__ uint32_t sh[kThreads];
   uint32_t carry = 0;
   for (int c0 = 0; c0 < nb; c0 += kThreads) {
@@ -95,15 +117,17 @@ __global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint32_t* __restr
   }
   if (threadIdx.x == 0) {
     ctrl->n_pairs = carry;
-    ctrl->n_visible = 0;  // counted by the duplicate kernel that follows
     ctrl->overflow = 0;
   }
 }
 
 __global__ __launch_bounds__(kThreads) void scan_final_kernel(const uint32_t* __restrict__ count,
-                                                              const uint32_t* __restrict__ perm, int n,
+                                                              const uint32_t* __restrict__ perm,
+                                                              const uint32_t* __restrict__ n_dev, int limit,
                                                               const uint32_t* __restrict__ block_sums,
                                                               uint32_t* __restrict__ offs) {
+  const int n = (int)item_count(n_dev, limit);
+  if ((int64_t)blockIdx.x * kScanItems >= n) return;
   __shared__ uint32_t sh[kThreads];
   const int base = blockIdx.x * kScanItems + threadIdx.x * kRounds;
   uint32_t v[kRounds];
@@ -121,18 +145,12 @@ __global__ __launch_bounds__(kThreads) void scan_final_kernel(const uint32_t* __
   }
 }
 
-// Item count of a radix pass: the device count clamped to the buffer capacity
-// (`limit`), or `limit` itself when there is no device count.
-__device__ inline int64_t item_count(const uint32_t* n_dev, int64_t limit) {
-  if (!n_dev) return limit;
-  const int64_t n = (int64_t)(*n_dev);
-  return n < limit ? n : limit;
-}
-
+// drop: leave kDropKey keys out and add the kept count to *n_kept (zero beforehand).
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
-                                                              int64_t n_host, int shift, int bits,
-                                                              uint32_t* __restrict__ hist) {
+                                                              int64_t n_host, int shift, int bits, int drop,
+                                                              uint32_t* __restrict__ hist,
+                                                              uint32_t* __restrict__ n_kept) {
   const int64_t n = item_count(n_dev, n_host);
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   if (base >= n) return;
@@ -144,74 +162,84 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t i = base + r * kThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & dmask], 1u);
+    if (i < n) {
+      const uint32_t k = keys[i];
+      if (!(drop && k == kDropKey)) atomicAdd(&h[wave][(k >> shift) & dmask], 1u);
+    }
   }
   __syncthreads();
   const int d = threadIdx.x;
   uint32_t s = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) s += h[w][d];
-  // digit-major: an exclusive scan of hist[d * nb + b] gives every (block, digit)
-  // its global output offset
   hist[(size_t)d * gridDim.x + blockIdx.x] = s;
+  if (drop) {
+    uint32_t w = s;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) w += __shfl_xor(w, m, 64);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(n_kept, w);
+  }
 }
 
-// One workgroup of 1024 threads: exclusive scan of the digit-major histogram of the
-// active blocks (256 x nb entries, each thread a contiguous chunk).  The grid's
-// block count is the row stride; only the first nb_active blocks of each row count.
-constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist, int nb_grid,
-                                                                     const uint32_t* __restrict__ n_dev,
-                                                                     int64_t n_host) {
+// One workgroup per digit d (grid = 256): exclusive scan, in place, of row d of the
+// digit-major histogram over the active blocks (each thread four consecutive
+// entries per chunk of 1024), and the row total into dtot[d].  The grid's block
+// count is the row stride.
+__global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist, int nb_grid,
+                                                                 const uint32_t* __restrict__ n_dev,
+                                                                 int64_t n_host, uint32_t* __restrict__ dtot) {
   const int64_t n = item_count(n_dev, n_host);
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
-  const int total = kDigits * nb;
-  const int chunk = (total + kScanThreads - 1) / kScanThreads;
+  uint32_t* __restrict__ row = hist + (size_t)blockIdx.x * nb_grid;
+  __shared__ uint32_t sh[kThreads];
   const int t = threadIdx.x;
-  const int e0 = t * chunk, e1 = min(total, e0 + chunk);
-  // entry e = digit * nb + block maps to hist[digit * nb_grid + block]
-  uint32_t s = 0;
-  for (int e = e0; e < e1; ++e) s += hist[(size_t)(e / nb) * nb_grid + (e % nb)];
-  __shared__ uint32_t sh[kScanThreads];
-  sh[t] = s;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t x = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += 4 * kThreads) {
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = c0 + 4 * t + k;
+      v[k] = e < nb ? row[e] : 0u;
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_exclusive_scan(v[0] + v[1] + v[2] + v[3], sh, &tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = c0 + 4 * t + k;
+      if (e < nb) row[e] = run;
+      run += v[k];
+    }
+    carry += tot;
   }
-  uint32_t run = sh[t] - s;
-  for (int e = e0; e < e1; ++e) {
-    uint32_t* p = hist + (size_t)(e / nb) * nb_grid + (e % nb);
-    const uint32_t c = *p;
-    *p = run;
-    run += c;
-  }
+  if (t == 0) dtot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int shift,
-    int bits, const uint32_t* __restrict__ hist) {
+    int bits, int drop, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot) {
   const int64_t n = item_count(n_dev, n_host);
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   if (base >= n) return;
   __shared__ uint32_t doff[kDigits];
   __shared__ uint32_t wcnt[kWaves][kDigits];
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
-  doff[t] = hist[(size_t)t * gridDim.x + blockIdx.x];
+  // first slot of digit t: the keys of all smaller digits, then this digit's keys
+  // in the blocks before this one
+  const uint32_t dbase = block_exclusive_scan(dtot[t], doff, nullptr);
+  doff[t] = dbase + hist[(size_t)t * gridDim.x + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kRounds; ++r) {
     for (int k = t; k < kWaves * kDigits; k += kThreads) (&wcnt[0][0])[k] = 0u;
     __syncthreads();
     const int64_t i = base + r * kThreads + t;
-    const bool valid = i < n;
     uint32_t key = 0, val = 0, digit = 0;
+    bool valid = i < n;
     if (valid) {
       key = kin[i];
       val = vin[i];
       digit = (key >> shift) & ((1u << bits) - 1u);
+      valid = !(drop && key == kDropKey);
     }
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -245,17 +273,14 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
 __global__ __launch_bounds__(kThreads) void duplicate_kernel(
     const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ count,
     const uint32_t* __restrict__ offs, const uint2* __restrict__ rect, const ViewDesc* __restrict__ views,
-    int n_views, int n, int64_t p_cap, uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval,
-    Ctrl* __restrict__ ctrl, uint2* __restrict__ ranges, int n_tiles) {
+    int n_views, const uint32_t* __restrict__ n_dev, int limit, int64_t p_cap, uint32_t* __restrict__ pkey,
+    uint32_t* __restrict__ pval, Ctrl* __restrict__ ctrl, uint2* __restrict__ ranges, int n_tiles) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   // clear the tile ranges for the ranges kernel (which runs after the tile sort)
   for (int k = j; k < n_tiles; k += gridDim.x * blockDim.x) ranges[k] = make_uint2(0u, 0u);
+  const int n = (int)item_count(n_dev, limit);
   const uint32_t id = j < n ? sorted_ids[j] : 0u;
   const uint32_t c = j < n ? count[id] : 0u;
-  // one atomic per wave for the visible-item counter
-  const uint64_t vis = __ballot(c > 0);
-  if (vis != 0ull && (threadIdx.x % 64) == (unsigned)(__ffsll((long long)vis) - 1))
-    atomicAdd(&ctrl->n_visible, (uint32_t)__popcll(vis));
   if (c == 0) return;
   uint32_t off = offs[j];
   if ((int64_t)off + c > p_cap) {
@@ -305,35 +330,41 @@ void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t 
   copy_u32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(src, dst, n);
 }
 
-void launch_scan_counts(const uint32_t* count, const uint32_t* perm, int n, uint32_t* offs,
-                        uint32_t* block_sums, Ctrl* ctrl, hipStream_t s) {
-  const int nb = blocks_for(n, kScanItems);
-  scan_reduce_kernel<<<nb, kThreads, 0, s>>>(count, perm, n, block_sums);
-  scan_blocks_kernel<<<1, kThreads, 0, s>>>(block_sums, nb, ctrl);
-  scan_final_kernel<<<nb, kThreads, 0, s>>>(count, perm, n, block_sums, offs);
+void launch_scan_counts(const uint32_t* count, const uint32_t* perm, const uint32_t* n_dev, int limit,
+                        uint32_t* offs, uint32_t* block_sums, Ctrl* ctrl, hipStream_t s) {
+  const int nb = blocks_for(limit, kScanItems);
+  scan_reduce_kernel<<<nb, kThreads, 0, s>>>(count, perm, n_dev, limit, block_sums);
+  scan_blocks_kernel<<<1, kThreads, 0, s>>>(block_sums, n_dev, limit, ctrl);
+  scan_final_kernel<<<nb, kThreads, 0, s>>>(count, perm, n_dev, limit, block_sums, offs);
 }
 
 int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host, const uint32_t* n_dev,
-               int bits, uint32_t* hist, hipStream_t s) {
+               int bits, uint32_t* hist, uint32_t* n_kept, hipStream_t s) {
   const int nb = blocks_for(cap, kScanItems);
   const int64_t limit = n_dev ? cap : n_host;
+  uint32_t* dtot = hist + (size_t)kDigits * nb;
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     const int pb = (bits - shift) < 8 ? (bits - shift) : 8;
-    radix_hist_kernel<<<nb, kThreads, 0, s>>>(keys[cur], n_dev, limit, shift, pb, hist);
-    radix_offsets_kernel<<<1, kScanThreads, 0, s>>>(hist, nb, n_dev, limit);
-    radix_scatter_kernel<<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev,
-                                                 limit, shift, pb, hist);
+    const int drop = (n_kept && shift == 0) ? 1 : 0;
+    // after a dropping first pass the kept count is the item count
+    const uint32_t* nd = (n_kept && shift > 0) ? n_kept : n_dev;
+    const int64_t lim = (n_kept && shift > 0) ? cap : limit;
+    radix_hist_kernel<<<nb, kThreads, 0, s>>>(keys[cur], nd, lim, shift, pb, drop, hist, n_kept);
+    radix_offsets_kernel<<<kDigits, kThreads, 0, s>>>(hist, nb, nd, lim, dtot);
+    radix_scatter_kernel<<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], nd, lim,
+                                                 shift, pb, drop, hist, dtot);
     cur ^= 1;
   }
   return cur;
 }
 
 void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
-                      const uint2* rect, const ViewDesc* views, int n_views, int n, int64_t p_cap,
-                      uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles, hipStream_t s) {
-  duplicate_kernel<<<blocks_for(n, 256), 256, 0, s>>>(sorted_ids, count, offs, rect, views, n_views, n, p_cap, pkey,
-                                                      pval, ctrl, ranges, n_tiles);
+                      const uint2* rect, const ViewDesc* views, int n_views, const uint32_t* n_dev, int limit,
+                      int64_t p_cap, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles,
+                      hipStream_t s) {
+  duplicate_kernel<<<blocks_for(limit, 256), 256, 0, s>>>(sorted_ids, count, offs, rect, views, n_views, n_dev,
+                                                          limit, p_cap, pkey, pval, ctrl, ranges, n_tiles);
 }
 
 void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,

@@ -55,7 +55,7 @@ class Rasterizer:
 
     def __init__(self, device: int | str | torch.device = 0, tile=(16, 16), batch: int = 256,
                  filter: bool = True, z_near: float = 0.2, pair_capacity: int = 0,
-                 keep_unsorted: bool = False, profile: bool = False):
+                 keep_unsorted: bool = False, profile: int | bool = False):
         lib = _lib.load()
         if isinstance(device, int):
             idx = device
@@ -70,7 +70,8 @@ class Rasterizer:
         opt.z_near = float(z_near)
         opt.pair_capacity = int(pair_capacity)
         opt.keep_unsorted = 1 if keep_unsorted else 0
-        opt.profile = 1 if profile else 0
+        # 1 (or True): kernel-family event times and blend work counters; 2: times only
+        opt.profile = int(profile)
         self.options = opt
         ctx = ctypes.c_void_p()
         _lib.check(lib.gs2d_create(ctypes.byref(ctx), self.device.index, ctypes.byref(opt)))

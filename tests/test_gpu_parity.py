@@ -173,13 +173,20 @@ def test_gpu_sort_bit_exact(gs):
     order = np.argsort(ukeys, kind="stable")
     np.testing.assert_array_equal(keys, ukeys[order])
     np.testing.assert_array_equal(ids, uids[order])
-    # per-surfel depth keys from the depth-sorted list
+    # the depth-sorted list holds exactly the surfels that touch a tile, ascending
+    # (depth key, id)
     dk, di = r.debug("depth_keys"), r.debug("depth_ids")
-    assert np.all(np.diff(dk.astype(np.int64)) >= 0)
-    per = np.empty(room.n, dtype=np.uint32)
+    assert len(di) == c["n_visible"] and len(np.unique(di)) == len(di)
+    kk = dk.astype(np.int64) * (1 << 32) + di
+    assert np.all(np.diff(kk) > 0)
+    rect = r.debug("rect").reshape(-1, 4)
+    touches = (rect[:, 0] <= rect[:, 1]) & (rect[:, 2] <= rect[:, 3])
+    assert np.array_equal(np.sort(di), np.flatnonzero(touches))
+    per = np.full(room.n, 0xFFFFFFFF, dtype=np.uint32)
     per[di] = dk
     pre = oracle.preprocess(room.params, ROOM_CAM, pose)
     vis = per != 0xFFFFFFFF
+    assert vis.sum() == len(di)
     okey = pre["key"].view(np.uint32)
     assert np.array_equal(per[vis], okey[vis]), int((per[vis] != okey[vis]).sum())
     assert not np.any(pre["culled"][vis])
