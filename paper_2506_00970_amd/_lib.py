@@ -1,4 +1,4 @@
-"""ctypes declarations of the libgs2d.so C ABI (include/gs2d.h).
+"""ctypes declarations of the libgs2d.so C ABI (include/gs2d.h, include/gs2d_warm.h).
 
 This module only loads the library and marshals arguments.  There is no
 fallback: if the library has not been built, loading raises ``ImportError``.
@@ -11,7 +11,9 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs2d.so")
-HEADER_PATH = os.path.join(os.path.dirname(HERE), "include", "gs2d.h")
+INCLUDE_DIR = os.path.join(os.path.dirname(HERE), "include")
+HEADER_PATH = os.path.join(INCLUDE_DIR, "gs2d.h")
+HEADERS = [os.path.join(INCLUDE_DIR, h) for h in ("gs2d.h", "gs2d_warm.h")]
 
 OK = 0
 ERR_INVALID_ARG = -1
@@ -54,6 +56,11 @@ class Tuning(ctypes.Structure):
 
 
 MAX_VIEWS = 32
+
+
+class WsAdamW(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("weight_decay", ctypes.c_float)]
 
 
 class View(ctypes.Structure):
@@ -116,6 +123,18 @@ _SIGS = {
     "gs2d_get_profile": ([_P, ctypes.POINTER(Profile), ctypes.c_int32, _P], ctypes.c_int),
     "gs2d_last_hip_error": ([_P], ctypes.c_int),
     "gs2d_error_string": ([ctypes.c_int], ctypes.c_char_p),
+    # learned warm start (gs2d_warm.h)
+    "gs2d_ws_param_count": ([], ctypes.c_int64),
+    "gs2d_ws_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int32], ctypes.c_int),
+    "gs2d_ws_destroy": ([_P], ctypes.c_int),
+    "gs2d_ws_set_params": ([_P, _P, _P], ctypes.c_int),
+    "gs2d_ws_get_params": ([_P, _P, _P], ctypes.c_int),
+    "gs2d_ws_residual": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "gs2d_ws_forward": ([_P, _P, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "gs2d_ws_gradient": ([_P, _P, _P, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
+    "gs2d_ws_adamw_step": ([_P, ctypes.POINTER(WsAdamW), _P], ctypes.c_int),
+    "gs2d_warm_start": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, _P, _P, ctypes.c_float,
+                         ctypes.c_int32, _P, _P, _P], ctypes.c_int),
 }
 
 
@@ -148,9 +167,11 @@ def check(code: int, ctx=None) -> None:
 
 
 def declared_functions() -> list:
-    """Names of the functions declared with GS2D_API in include/gs2d.h."""
+    """Names of the functions declared with GS2D_API in the public headers."""
     import re
 
-    with open(HEADER_PATH) as f:
-        text = f.read()
-    return re.findall(r"GS2D_API\s+[\w\s\*]+?\b(gs2d_\w+)\s*\(", text)
+    names = []
+    for h in HEADERS:
+        with open(h) as f:
+            names += re.findall(r"GS2D_API\s+[\w\s\*]+?\b(gs2d_\w+)\s*\(", f.read())
+    return names

@@ -1,4 +1,4 @@
-"""The C ABI library loads and exports every symbol include/gs2d.h declares (no GPU needed)."""
+"""The C ABI library loads and exports every symbol include/*.h declares (no GPU needed)."""
 
 import ctypes
 
@@ -61,8 +61,9 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"gs2d_camera": _lib.Camera, "gs2d_options": _lib.Options, "gs2d_counts": _lib.Counts,
                "gs2d_track_args": _lib.TrackArgs, "gs2d_profile": _lib.Profile,
                "gs2d_tuning": _lib.Tuning, "gs2d_view": _lib.View, "gs2d_view_grad": _lib.ViewGrad,
-               "gs2d_track_problem": _lib.TrackProblem}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs2d.h"', "int main(void) {"]
+               "gs2d_track_problem": _lib.TrackProblem, "gs2d_ws_adamw": _lib.WsAdamW}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs2d.h"', '#include "gs2d_warm.h"',
+             "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
@@ -79,3 +80,10 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_warm_start_parameter_count(lib):
+    """The network's parameter count (a host-side constant of the library) is the architecture's."""
+    from oracle import warmstart
+
+    assert lib.gs2d_ws_param_count() == warmstart.param_count() == 900_326

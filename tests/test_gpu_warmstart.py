@@ -1,0 +1,192 @@
+"""GPU: the warm-start network (residual, forward, gradient, AdamW) against the FP64 oracle,
+and the warm start's choice between T_0 and the start pose.
+
+Parity has two regimes.
+
+* Exact arithmetic (the parity bar): inputs, biases and targets are multiples of 0.25
+  and the weights sparse +-1 (synth.exact_params), so every forward sum and every
+  activation-gradient sum is exact in FP32 whatever its order.  Both sides then round
+  identical values to bfloat16: the output must match bit for bit, and the weight
+  gradients -- FP32 sums of exact products over the batch and the pixels -- to the
+  gradient bar, |d g| <= 1e-3 |g_ref| + 1e-6 max_layer |g_ref|.
+* Random data (BF16 noise): with dense random weights an activation whose FP32 and
+  exact sums straddle a bfloat16 rounding boundary rounds one unit in the last place
+  (2^-8) apart, and such flips propagate through the later layers.  Outputs:
+  |d out| <= 1e-2 max|out_ref| per sample; gradients: per layer,
+  |d g| <= 1e-2 max_layer |g_ref| (2.5 bfloat16 units of the layer's scale).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import warmstart as ows
+from tests.gpu_common import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wsmod():
+    from paper_2506_00970_amd import warmstart
+
+    return warmstart
+
+
+def _layer_slices():
+    out, o = [], 0
+    for ws_, bs in ows.param_shapes():
+        n = int(np.prod(ws_)) + int(np.prod(bs))
+        out.append(slice(o, o + n))
+        o += n
+    return out
+
+
+def test_ws_residual_parity(wsmod):
+    g = np.random.default_rng(0)
+    B, H, W = 2, 480, 640
+    rgb, trgb = g.uniform(size=(B, 3, H, W)).astype(np.float32), g.uniform(size=(B, 3, H, W)).astype(np.float32)
+    d, td = g.uniform(1, 4, size=(B, H, W)).astype(np.float32), g.uniform(1, 4, size=(B, H, W)).astype(np.float32)
+    net = wsmod.WarmStartNet(max_batch=4)
+    got = host(net.residual(dev(rgb), dev(d), dev(trgb), dev(td)))
+    for b in range(B):
+        ref = ows.residual_input(rgb[b], d[b], trgb[b], td[b])
+        np.testing.assert_allclose(got[b], ref, rtol=0, atol=2e-6)
+    # 1200 x 680 is not 15 x (80 x 60) in both axes: refused
+    with pytest.raises(Exception):
+        net.residual(dev(np.zeros((1, 3, 680, 1200), np.float32)), dev(np.zeros((1, 680, 1200), np.float32)),
+                     dev(np.zeros((1, 3, 680, 1200), np.float32)), dev(np.zeros((1, 680, 1200), np.float32)))
+
+
+def _oracle_grad(theta, x, tgt):
+    t64 = theta.astype(np.float64)
+    ref_out, acts = ows.forward(t64, x.astype(np.float64))
+    ref_loss, dout = ows.loss_and_grad(ref_out, tgt)
+    return ref_out, ref_loss, ows.backward(t64, acts, dout)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ws_forward_exact(wsmod, seed):
+    theta = synth.exact_params(seed)
+    x = synth.exact_inputs(5, seed=20 + seed)
+    net = wsmod.WarmStartNet(max_batch=8)
+    net.set_params(dev(theta))
+    out = host(net.forward(dev(x)))
+    ref, _ = ows.forward(theta.astype(np.float64), x.astype(np.float64))
+    np.testing.assert_array_equal(out, ref)
+    np.testing.assert_array_equal(host(net.params()), theta)
+
+
+@pytest.mark.parametrize("batch", [4, 37])
+def test_ws_gradient_exact(wsmod, batch):
+    """Batch 37 spans several split-K slices and ragged GEMM tiles."""
+    theta = synth.exact_params(2)
+    x = synth.exact_inputs(batch, seed=22)
+    tgt = synth.exact_targets(batch, seed=23)
+    net = wsmod.WarmStartNet(max_batch=64)
+    net.set_params(dev(theta))
+    loss, out, grad = net.gradient(dev(x), dev(tgt))
+    loss, out, grad = float(host(loss)[0]), host(out), host(grad)
+    ref_out, ref_loss, ref_grad = _oracle_grad(theta, x, tgt)
+    np.testing.assert_array_equal(out, ref_out)
+    assert abs(loss - ref_loss) <= 1e-6 * ref_loss, (loss, ref_loss)
+    for li, sl in enumerate(_layer_slices()):
+        g, r = grad[sl], ref_grad[sl]
+        err = np.abs(g - r)
+        tol = 1e-3 * np.abs(r) + 1e-6 * np.abs(r).max()
+        print(f"layer {li}: max |d g| / layer max = {err.max() / np.abs(r).max():.3g}")
+        assert np.all(err <= tol), (li, int((err > tol).sum()), float((err / tol).max()))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_ws_forward_bf16_noise(wsmod, seed):
+    theta = synth.init_params(seed, bias_std=0.05)
+    x = synth.random_inputs(3, seed=10 + seed)
+    net = wsmod.WarmStartNet(max_batch=8)
+    net.set_params(dev(theta))
+    out = host(net.forward(dev(x)))
+    ref, _ = ows.forward(theta.astype(np.float64), x.astype(np.float64))
+    err = np.abs(out - ref).max(axis=1)
+    scale = np.abs(ref).max(axis=1)
+    print("forward rel err per sample", err / scale)
+    assert np.all(err <= 1e-2 * scale), (err, scale)
+
+
+def test_ws_gradient_bf16_noise(wsmod):
+    theta = synth.init_params(3, bias_std=0.05)
+    x = synth.random_inputs(4, seed=13)
+    tgt = np.random.default_rng(14).normal(size=(4, 6)).astype(np.float32)
+    net = wsmod.WarmStartNet(max_batch=8)
+    net.set_params(dev(theta))
+    loss, out, grad = net.gradient(dev(x), dev(tgt))
+    loss, grad = float(host(loss)[0]), host(grad)
+    _, ref_loss, ref_grad = _oracle_grad(theta, x, tgt)
+    assert abs(loss - ref_loss) <= 1e-2 * ref_loss, (loss, ref_loss)
+    for li, sl in enumerate(_layer_slices()):
+        g, r = grad[sl], ref_grad[sl]
+        err = np.abs(g - r).max() / np.abs(r).max()
+        print(f"layer {li}: max |d g| / layer max = {err:.3g}")
+        assert err <= 1e-2, (li, err)
+
+
+def test_ws_adamw_step(wsmod):
+    """One AdamW step after the gradient equals the oracle's step on the oracle's gradient
+    wherever the first-step update (lr g / (|g| + eps), a sign step) is decided clearly."""
+    theta = synth.exact_params(5)
+    x = synth.exact_inputs(2, seed=15)
+    tgt = synth.exact_targets(2, seed=16)
+    net = wsmod.WarmStartNet(max_batch=4)
+    net.set_params(dev(theta))
+    net.gradient(dev(x), dev(tgt), want_grad=False)
+    lr, wd = 1e-3, 0.01
+    net.adamw_step(lr=lr, weight_decay=wd)
+    got = host(net.params()).astype(np.float64)
+    t64 = theta.astype(np.float64)
+    _, _, ref_grad = _oracle_grad(theta, x, tgt)
+    ref = ows.adamw_step(t64, ref_grad, ows.AdamWState(t64.size), lr=lr, weight_decay=wd)
+    clear = np.abs(ref_grad) >= 1e-2 * np.abs(ref_grad).max()
+    assert clear.sum() > 1000
+    np.testing.assert_allclose(got[clear], ref[clear], rtol=0, atol=1e-6)
+    # everywhere: at most one sign step apart
+    assert np.abs(got - ref).max() <= 2 * lr + 1e-6
+
+
+def test_ws_training_fits_a_fixed_batch(wsmod):
+    theta = synth.init_params(7)
+    x = synth.random_inputs(32, seed=17)
+    tgt = np.random.default_rng(18).normal(size=(32, 6)).astype(np.float32)
+    net = wsmod.WarmStartNet(max_batch=32)
+    net.set_params(dev(theta))
+    X, T = dev(x), dev(tgt)
+    losses = [float(host(net.train_step(X, T, lr=1e-3))[0]) for _ in range(200)]
+    print("loss", losses[0], losses[-1])
+    assert losses[-1] < 0.05 * losses[0]
+
+
+def test_warm_start_choice(wsmod):
+    """Zero weights propose tau = 0 (T_0 = T_start, kept); wild weights propose a pose
+    whose loss is worse, and the start pose is returned unchanged."""
+    from paper_2506_00970_amd import Rasterizer
+    from tests.gpu_common import ROOM_CAM, room_scene
+
+    room, pose = room_scene(100_000, seed=3, cam_seed=3)
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=4)
+    r = Rasterizer()
+    P = dev(room.params)
+    tgt = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = tgt.rgb.clone(), tgt.depth.clone()
+    net = wsmod.WarmStartNet(max_batch=1)
+    net.set_params(torch.zeros(wsmod.PARAMS, device="cuda"))
+    ps = dev(start.reshape(12))
+    chosen, info = net.warm_start(r, P, ROOM_CAM, ps, trgb, tdep)
+    info = host(info)
+    np.testing.assert_array_equal(host(chosen), start.reshape(12))
+    assert info[2] == 1.0 and info[0] == info[1]
+    # large weights: a far-off proposal (metres, radians) is rejected on the unmasked loss
+    net.set_params(dev(synth.init_params(9, bias_std=50.0) * 50.0))
+    chosen, info = net.warm_start(r, P, ROOM_CAM, ps, trgb, tdep)
+    info = host(info)
+    print("wild proposal losses", info)
+    assert info[1] > info[0] and info[2] == 0.0
+    np.testing.assert_array_equal(host(chosen), start.reshape(12))
