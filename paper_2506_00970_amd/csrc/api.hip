@@ -115,8 +115,8 @@ int stream_capturing(hipStream_t s, bool* cap) {
 
 int ensure_hist(gs2d_ctx* ctx) {
   const int64_t items = ctx->n_cap > ctx->p_cap ? ctx->n_cap : ctx->p_cap;
-  // digit-major rows of every block plus the 256 row totals
-  const int64_t need = ((items + kScanItems - 1) / kScanItems + 1) * 256;
+  // digit-major rows of every block plus the row totals, for up to 2048 digits
+  const int64_t need = ((items + kScanItems - 1) / kScanItems + 1) * (1 << kMaxDigitBits);
   if (need <= ctx->hist_cap) return GS2D_OK;
   GS2D_TRY(realloc_dev(ctx, &ctx->hist, need));
   ctx->hist_cap = need;
@@ -299,12 +299,13 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     {
       ProfScope ps(ctx, kDepthSort, s);
       // the first pass keeps only the surfels that touch a tile
-      dbuf = radix_sort(ctx->dkey, ctx->dval, items, items, nullptr, 32, ctx->hist, &ctx->ctrl->n_visible, s);
+      dbuf = radix_sort(ctx->dkey, ctx->dval, items, items, nullptr, 32, ctx->hist, &ctx->ctrl->n_visible, nullptr,
+                        0, nullptr, s);
     }
-    if (dbuf != 0) return GS2D_ERR_HIP;  // four 8-bit passes end in buffer 0
+    ctx->depth_buf = dbuf;
     {
       ProfScope ps(ctx, kScan, s);
-      launch_scan_counts(ctx->count, ctx->dval[0], &ctx->ctrl->n_visible, (int)items, ctx->offs, ctx->block_sums,
+      launch_scan_counts(ctx->count, ctx->dval[dbuf], &ctx->ctrl->n_visible, (int)items, ctx->offs, ctx->block_sums,
                          ctx->ctrl, s);
     }
     if (allow_sync && !capturing && !ctx->pair_fixed) {
@@ -315,19 +316,22 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     }
     {
       ProfScope ps(ctx, kDup, s);
-      launch_duplicate(ctx->dval[0], ctx->count, ctx->offs, ctx->rect, ctx->views, nv, &ctx->ctrl->n_visible,
+      launch_duplicate(ctx->dval[dbuf], ctx->count, ctx->offs, ctx->rect, ctx->views, nv, &ctx->ctrl->n_visible,
                        (int)items, ctx->p_cap, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
     }
     if (ctx->opt.keep_unsorted && ctx->pkey_keep) {
       launch_copy_u32(ctx->pkey[0], ctx->pkey_keep, ctx->p_cap, s);
       launch_copy_u32(ctx->pval[0], ctx->pval_keep, ctx->p_cap, s);
     }
+    // a tile sort of one pass (up to 2048 tiles) writes the tile ranges itself
+    const int tbits = tile_bits((int)vs.tiles);
+    const bool fused_ranges = tbits <= kMaxDigitBits;
     {
       ProfScope ps(ctx, kTileSort, s);
-      pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tile_bits((int)vs.tiles),
-                        ctx->hist, nullptr, s);
+      pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tbits, ctx->hist, nullptr,
+                        fused_ranges ? ctx->ranges : nullptr, (int)vs.tiles, &ctx->ctrl->overflow, s);
     }
-    {
+    if (!fused_ranges) {
       ProfScope ps(ctx, kRanges, s);
       launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, (int)vs.tiles, s);
     }
@@ -844,13 +848,13 @@ GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_
     case 0: src = ctx->pkey[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 1: src = ctx->pval[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 2: src = ctx->ranges; need = (size_t)ctx->last_views.tiles * 8; break;
-    case 3: src = ctx->dkey[0]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
+    case 3: src = ctx->dkey[ctx->depth_buf]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
     case 4: src = ctx->rect; need = (size_t)items * 8; break;
     case 5: src = ctx->t_final; need = (size_t)pixels * 4; break;
     case 6: src = ctx->last; need = (size_t)pixels * 4; break;
     case 7: src = ctx->pkey_keep; need = (size_t)np * 4; break;
     case 8: src = ctx->pval_keep; need = (size_t)np * 4; break;
-    case 9: src = ctx->dval[0]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
+    case 9: src = ctx->dval[ctx->depth_buf]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
     default: return GS2D_ERR_INVALID_ARG;
   }
   if (!src) return GS2D_ERR_UNSUPPORTED;

@@ -175,6 +175,7 @@ struct gs2d_ctx {
   uint32_t generation = 0;
   gs2d::ViewSet last_views;    // views of the last render (host copy)
   int pair_buf = 0;            // which pkey/pval holds the sorted pairs
+  int depth_buf = 0;           // which dkey/dval holds the depth-sorted visible items
   bool have_forward = false;
 };
 
@@ -190,20 +191,25 @@ void launch_preprocess_bwd(const float* params, int n, const float* pose, const 
 
 // sort.hip
 constexpr int kScanItems = 2048;   // items per block of the scans and radix passes
+constexpr int kMaxDigitBits = 11;  // widest radix digit (2048 bins)
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
 // Exclusive scan of count[perm[j]] over j < n into offs, the total into ctrl->n_pairs
 // (and ctrl->overflow cleared); n = *n_dev clamped to limit, or limit without n_dev.
 void launch_scan_counts(const uint32_t* count, const uint32_t* perm, const uint32_t* n_dev, int limit,
                         uint32_t* offs, uint32_t* block_sums, Ctrl* ctrl, hipStream_t s);
-// Stable LSD radix sort of (key, value) u32 pairs over bits [0, bits).  n is taken from
-// *n_dev (clamped to cap) when n_dev is non-null (capacity-sized grid), else n_host.
-// With n_kept (zero on entry) the first pass drops keys equal to 0xFFFFFFFF and counts
-// the others into *n_kept, which is the item count of the later passes: the result
-// then holds the kept pairs only, in front.  hist holds 256 (blocks(cap) + 1) words.
-// Returns the index (0 or 1) of the buffer holding the result.
+// Stable LSD radix sort of (key, value) u32 pairs over bits [0, bits) in
+// ceil(bits / 11) passes of at most 11 bits.  n is taken from *n_dev (clamped to cap)
+// when n_dev is non-null (capacity-sized grid), else n_host.  With n_kept (zero on
+// entry) the first pass drops keys equal to 0xFFFFFFFF and counts the others into
+// *n_kept, which is the item count of the later passes: the result then holds the
+// kept pairs only, in front.  With `ranges` and a single pass, the pass also writes
+// [start, end) of every key value below n_tiles (empty ranges when *overflow != 0).
+// hist holds 2048 (blocks(cap) + 1) words.  Returns the index (0 or 1) of the buffer
+// holding the result.
 int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host,
-               const uint32_t* n_dev, int bits, uint32_t* hist, uint32_t* n_kept, hipStream_t s);
+               const uint32_t* n_dev, int bits, uint32_t* hist, uint32_t* n_kept, uint2* ranges,
+               int n_tiles, const uint32_t* overflow, hipStream_t s);
 // Pairs of the first n depth-sorted items (n = *n_dev clamped to limit).
 void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
                       const uint2* rect, const ViewDesc* views, int n_views, const uint32_t* n_dev, int limit,

@@ -8,17 +8,21 @@
 // follow the previous view's), stably by tile.  Each tile's list is therefore
 // ascending (depth, index), the order of the per-pixel definition.
 //
-// Radix pass = three kernels over blocks of kScanItems keys:
+// Radix pass (digits of up to 11 bits: 256 or 2048 bins) = three kernels over blocks
+// of kScanItems keys:
 //   hist    per-block digit histogram (LDS atomics, one sub-histogram per wave),
 //           stored digit-major: row d holds digit d's count in every block
 //   offsets one workgroup per digit: exclusive scan of that digit's row (its
 //           offset within the digit) and the row total
-//   scatter per block: the digit bases (an LDS scan of the 256 row totals) plus
-//           the row prefix give each digit's first output slot; then 8 rounds of
-//           256 keys: a wave-level multi-split (ballots over the digit bits give
-//           each lane the mask of lanes holding the same digit), a per-digit
-//           prefix over the 4 waves in LDS, and the running per-digit offset
-//           across rounds keep the pass stable.
+//   scatter per block: the digit bases (an LDS scan of the row totals) plus the
+//           row prefix give each digit's first output slot; then 8 rounds of 256
+//           keys: a wave-level multi-split (ballots over the digit bits give each
+//           lane the mask of lanes holding the same digit), the same digit's keys
+//           in the lower waves of the round (per-wave counts in LDS, stamped with
+//           the round so that they need no clearing), and the running per-digit
+//           offset across rounds keep the pass stable.
+// 32-bit depth keys take 3 passes (11, 11, 10 bits); tile keys of up to 2048 tiles
+// take one, whose digit bases and totals are the tile ranges.
 // The depth sort's first pass also compacts: items whose key is kDropKey (surfels
 // that touch no tile) are left out of the histogram and the scatter, so the pass
 // writes only the visible items, in stable order, and counts them on the device;
@@ -32,7 +36,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kRounds = kScanItems / kThreads;  // 8
-constexpr int kDigits = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kDropKey = 0xFFFFFFFFu;
 
@@ -145,19 +148,25 @@ __global__ __launch_bounds__(kThreads) void scan_final_kernel(const uint32_t* __
   }
 }
 
+// Radix passes take up to 11 bits: R = 256 or 2048 bins (kDigits8, kDigits11).
+constexpr int kDigits8 = 256, kDigits11 = 2048;
+
+// Per-block digit histogram, digit-major (row d = digit d's count in every block).
 // drop: leave kDropKey keys out and add the kept count to *n_kept (zero beforehand).
+template <int R>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
                                                               int64_t n_host, int shift, int bits, int drop,
                                                               uint32_t* __restrict__ hist,
                                                               uint32_t* __restrict__ n_kept) {
+  constexpr int PER = R / kThreads;  // digits per thread
   const int64_t n = item_count(n_dev, n_host);
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   if (base >= n) return;
-  __shared__ uint32_t h[kWaves][kDigits];
+  __shared__ uint32_t h[kWaves][R];
   const int wave = threadIdx.x / 64;
   const uint32_t dmask = (1u << bits) - 1u;
-  for (int k = threadIdx.x; k < kWaves * kDigits; k += kThreads) (&h[0][0])[k] = 0u;
+  for (int k = threadIdx.x; k < kWaves * R; k += kThreads) (&h[0][0])[k] = 0u;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -168,20 +177,24 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __
     }
   }
   __syncthreads();
-  const int d = threadIdx.x;
-  uint32_t s = 0;
+  uint32_t kept = 0;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) s += h[w][d];
-  hist[(size_t)d * gridDim.x + blockIdx.x] = s;
+  for (int q = 0; q < PER; ++q) {
+    const int d = q * kThreads + threadIdx.x;
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s += h[w][d];
+    hist[(size_t)d * gridDim.x + blockIdx.x] = s;
+    kept += s;
+  }
   if (drop) {
-    uint32_t w = s;
 #pragma unroll
-    for (int m = 32; m > 0; m >>= 1) w += __shfl_xor(w, m, 64);
-    if ((threadIdx.x & 63) == 0 && w) atomicAdd(n_kept, w);
+    for (int m = 32; m > 0; m >>= 1) kept += __shfl_xor(kept, m, 64);
+    if ((threadIdx.x & 63) == 0 && kept) atomicAdd(n_kept, kept);
   }
 }
 
-// One workgroup per digit d (grid = 256): exclusive scan, in place, of row d of the
+// One workgroup per digit d (grid = R): exclusive scan, in place, of row d of the
 // digit-major histogram over the active blocks (each thread four consecutive
 // entries per chunk of 1024), and the row total into dtot[d].  The grid's block
 // count is the row stride.
@@ -214,24 +227,46 @@ __global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __res
   if (t == 0) dtot[blockIdx.x] = carry;
 }
 
+// Scatter of one pass.  With `ranges` (a pass over every tile bit of the pair keys),
+// block 0 also writes each tile's [start, end) -- the digit bases and totals -- for
+// tiles < n_tiles (empty ranges after a pair overflow).
+template <int R>
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int shift,
-    int bits, int drop, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot) {
+    int bits, int drop, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
+    uint2* __restrict__ ranges, int n_tiles, const uint32_t* __restrict__ overflow) {
+  constexpr int PER = R / kThreads;
   const int64_t n = item_count(n_dev, n_host);
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   if (base >= n) return;
-  __shared__ uint32_t doff[kDigits];
-  __shared__ uint32_t wcnt[kWaves][kDigits];
+  __shared__ uint32_t doff[R];
+  __shared__ uint32_t wcnt[kWaves][R];  // (round stamp << 16) | count of the wave's keys of a digit
+  __shared__ uint32_t sh[kThreads];
   const int t = threadIdx.x, wave = t / 64, lane = t % 64;
-  // first slot of digit t: the keys of all smaller digits, then this digit's keys
-  // in the blocks before this one
-  const uint32_t dbase = block_exclusive_scan(dtot[t], doff, nullptr);
-  doff[t] = dbase + hist[(size_t)t * gridDim.x + blockIdx.x];
+  for (int k = t; k < kWaves * R; k += kThreads) (&wcnt[0][0])[k] = 0u;
+  // first slot of digit d: the keys of all smaller digits, then this digit's keys in
+  // the blocks before this one (thread t holds digits PER t .. PER t + PER - 1)
+  uint32_t tot[PER], pre = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    tot[q] = dtot[PER * t + q];
+    pre += tot[q];
+  }
+  uint32_t run = block_exclusive_scan(pre, sh, nullptr);
+  const bool write_ranges = ranges && blockIdx.x == 0;
+  const bool empty = write_ranges && *overflow != 0u;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int d = PER * t + q;
+    doff[d] = run + hist[(size_t)d * gridDim.x + blockIdx.x];
+    if (write_ranges && d < n_tiles) ranges[d] = empty ? make_uint2(0u, 0u) : make_uint2(run, run + tot[q]);
+    run += tot[q];
+  }
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kRounds; ++r) {
-    for (int k = t; k < kWaves * kDigits; k += kThreads) (&wcnt[0][0])[k] = 0u;
-    __syncthreads();
+    const uint32_t stamp = (uint32_t)(r + 1) << 16;
     const int64_t i = base + r * kThreads + t;
     uint32_t key = 0, val = 0, digit = 0;
     bool valid = i < n;
@@ -248,25 +283,29 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
       peers &= set ? bal : ~bal;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[wave][digit] = (uint32_t)__popcll(peers);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    const bool leader = valid && rank == 0;
+    if (leader) wcnt[wave][digit] = stamp | cnt;
     __syncthreads();
-    {
-      uint32_t run = doff[t];
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = wcnt[w][t];
-        wcnt[w][t] = run;
-        run += c;
+    // the group's first slot: the digit's running offset plus the same digit's keys
+    // in the lower waves of this round
+    uint32_t pb = 0;
+    if (leader) {
+      pb = doff[digit];
+      for (int w = 0; w < wave; ++w) {
+        const uint32_t e = wcnt[w][digit];
+        if ((e & 0xFFFF0000u) == stamp) pb += e & 0xFFFFu;
       }
-      doff[t] = run;
     }
     __syncthreads();
+    if (leader) atomicAdd(&doff[digit], cnt);
+    const int src = peers ? (int)__ffsll((long long)peers) - 1 : lane;
+    const uint32_t gb = (uint32_t)__shfl((int)pb, src, 64);
     if (valid) {
-      const uint32_t pos = wcnt[wave][digit] + rank;
+      const uint32_t pos = gb + rank;
       kout[pos] = key;
       vout[pos] = val;
     }
-    __syncthreads();
   }
 }
 
@@ -339,22 +378,35 @@ void launch_scan_counts(const uint32_t* count, const uint32_t* perm, const uint3
 }
 
 int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host, const uint32_t* n_dev,
-               int bits, uint32_t* hist, uint32_t* n_kept, hipStream_t s) {
+               int bits, uint32_t* hist, uint32_t* n_kept, uint2* ranges, int n_tiles, const uint32_t* overflow,
+               hipStream_t s) {
   const int nb = blocks_for(cap, kScanItems);
   const int64_t limit = n_dev ? cap : n_host;
-  uint32_t* dtot = hist + (size_t)kDigits * nb;
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    const int pb = (bits - shift) < 8 ? (bits - shift) : 8;
-    const int drop = (n_kept && shift == 0) ? 1 : 0;
+  uint32_t* dtot = hist + (size_t)kDigits11 * nb;
+  const int passes = (bits + 10) / 11;
+  int cur = 0, shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    const int pb = (bits - shift + (passes - p) - 1) / (passes - p);  // split the bits evenly
+    const int drop = (n_kept && p == 0) ? 1 : 0;
     // after a dropping first pass the kept count is the item count
-    const uint32_t* nd = (n_kept && shift > 0) ? n_kept : n_dev;
-    const int64_t lim = (n_kept && shift > 0) ? cap : limit;
-    radix_hist_kernel<<<nb, kThreads, 0, s>>>(keys[cur], nd, lim, shift, pb, drop, hist, n_kept);
-    radix_offsets_kernel<<<kDigits, kThreads, 0, s>>>(hist, nb, nd, lim, dtot);
-    radix_scatter_kernel<<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], nd, lim,
-                                                 shift, pb, drop, hist, dtot);
+    const uint32_t* nd = (n_kept && p > 0) ? n_kept : n_dev;
+    const int64_t lim = (n_kept && p > 0) ? cap : limit;
+    uint2* rg = (ranges && passes == 1) ? ranges : nullptr;
+    if (pb <= 8) {
+      radix_hist_kernel<kDigits8><<<nb, kThreads, 0, s>>>(keys[cur], nd, lim, shift, pb, drop, hist, n_kept);
+      radix_offsets_kernel<<<kDigits8, kThreads, 0, s>>>(hist, nb, nd, lim, dtot);
+      radix_scatter_kernel<kDigits8><<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
+                                                             nd, lim, shift, pb, drop, hist, dtot, rg, n_tiles,
+                                                             overflow);
+    } else {
+      radix_hist_kernel<kDigits11><<<nb, kThreads, 0, s>>>(keys[cur], nd, lim, shift, pb, drop, hist, n_kept);
+      radix_offsets_kernel<<<kDigits11, kThreads, 0, s>>>(hist, nb, nd, lim, dtot);
+      radix_scatter_kernel<kDigits11><<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
+                                                              nd, lim, shift, pb, drop, hist, dtot, rg, n_tiles,
+                                                              overflow);
+    }
     cur ^= 1;
+    shift += pb;
   }
   return cur;
 }
