@@ -1,0 +1,159 @@
+"""GPU: the batched workloads at their full sizes.
+
+* Mapping window: 8 keyframes (4 at 640 x 480, 4 at 1200 x 680) over one 1M-surfel
+  room, rendered and differentiated to all 15 surfel parameters and the 8 poses in
+  one launch per kernel; checked against the oracle (images of one view of each
+  resolution, every view's pose gradient, the surfel gradient summed over the 8
+  views), and captured into a HIP graph whose replays equal the eager pass.
+* Batched tracking: 32 independent problems (resolutions 320 x 240 .. 1200 x 680,
+  50k .. 1M surfels, 2-8 cm / 1-5 deg starts), 50 iterations in one launch per
+  kernel per iteration; every problem's pose and loss history equals the same
+  problem tracked alone, bit for bit.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_common import check_grads, check_images, check_pose, dev, host
+
+pytestmark = pytest.mark.gpu
+
+CAM_S = synth.Camera(640, 480, 525.0, 525.0, 320.0, 240.0)
+CAM_L = synth.Camera(1200, 680, 600.0, 600.0, 600.0, 340.0)
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2506_00970_amd as p
+
+    return p
+
+
+@pytest.fixture(scope="module")
+def window():
+    """The 1M-surfel room, its 8 keyframe cameras and poses, and seeded image gradients."""
+    room = synth.make_room(1_000_000, seed=100)
+    cams = [CAM_S] * 4 + [CAM_L] * 4
+    poses = [synth.room_camera(room, seed=100 + k) for k in range(8)]
+    g = np.random.default_rng(101)
+    grads = [{"d_rgb": g.normal(size=(3, c.height, c.width)).astype(np.float32) / (c.height * c.width),
+              "d_depth": g.normal(size=(c.height, c.width)).astype(np.float32) / (c.height * c.width)} for c in cams]
+    return room, cams, poses, grads
+
+
+def test_mapping_window_against_oracle(pkg, window):
+    room, cams, poses, grads = window
+    r = pkg.Rasterizer()
+    P = dev(room.params)
+    views = [(P, cams[k], dev(poses[k].reshape(12))) for k in range(8)]
+    outs = r.render_batch(views)
+    dg = [{k: dev(v) for k, v in gr.items()} for gr in grads]
+    res = r.backward_batch(outs[0].generation, dg, params_grad=True)
+    torch.cuda.synchronize()
+    c = r.counts()
+    print("mapping window counts", c)
+    assert c["overflow"] == 0 and c["n_tiles"] == 4 * 1200 + 4 * 75 * 43
+    d_params = host(res[0][0])
+    total = np.zeros_like(d_params, dtype=np.float64)
+    touched = np.zeros(room.n, dtype=bool)
+    for k in range(8):
+        ref = oracle.render(room.params, cams[k], poses[k])
+        ob = oracle.backward(room.params, cams[k], poses[k], d_rgb=grads[k]["d_rgb"].astype(np.float64),
+                             d_depth=grads[k]["d_depth"].astype(np.float64), watch=ref["gmargin"] < 1e-5)
+        total += ob["d_params"]
+        touched |= ob["touched"].astype(bool)
+        # pixels near a decision change a few pair terms of the summed pose gradient
+        check_pose(host(res[k][1]), ob["pose_paper"], rel=1e-3, floor=1e-4)
+        if k in (0, 4):
+            img = {n: host(getattr(outs[k], n)) for n in ("rgb", "depth", "normal", "alpha")}
+            print("view", k, check_images(img, ref, ref["fmargin"]))
+    print("surfel grads", check_grads(d_params, total, skip=touched), "skipped", int(touched.sum()))
+
+
+def test_mapping_window_graph_replays(pkg, window):
+    """The batched forward + full backward captured into one graph; every replay, with
+    unrelated eager work and synchronisations between replays, equals the eager pass
+    (images bit for bit; gradients, which add float atomics, to the gradient bar)."""
+    room, cams, poses, grads = window
+    r = pkg.Rasterizer()
+    other = pkg.Rasterizer()  # eager work between replays on its own context
+    small = synth.random_surfels(2000, seed=3)
+    P = dev(room.params)
+    pose_t = [dev(poses[k].reshape(12)) for k in range(8)]
+    views = [(P, cams[k], pose_t[k]) for k in range(8)]
+    dg = [{k: dev(v) for k, v in gr.items()} for gr in grads]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        outs = r.render_batch(views)  # sizes the buffers
+        res = r.backward_batch(outs[0].generation, dg, params_grad=True)
+    s.synchronize()
+    ref_img = [host(o.rgb) for o in outs]
+    ref_d = host(res[0][0])
+    ref_pose = [host(x[1]) for x in res]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        g_outs = r.render_batch(views)
+        g_res = r.backward_batch(g_outs[0].generation, dg, params_grad=True)
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in range(8):
+            np.testing.assert_array_equal(host(g_outs[k].rgb), ref_img[k], err_msg=f"replay {rep} view {k}")
+            check_pose(host(g_res[k][1]), ref_pose[k].astype(np.float64))
+        check_grads(host(g_res[0][0]), ref_d.astype(np.float64), rel=1e-3)
+        other.render(dev(small.params), small.camera, dev(small.pose.reshape(12)))
+        torch.cuda.synchronize()
+
+
+def _config4_problems(count=32):
+    res = [(320, 240), (640, 480), (848, 480), (1200, 680)]
+    out = []
+    for j in range(count):
+        g = np.random.default_rng(1000 + j)
+        W, H = res[g.integers(0, 4)]
+        f = 525.0 * W / 640.0
+        cam = synth.Camera(W, H, f, f, W / 2.0, H / 2.0)
+        n = int(round(np.exp(g.uniform(np.log(5e4), np.log(1e6)))))
+        room = synth.make_room(n, seed=1000 + j)
+        gt = synth.room_camera(room, seed=1000 + j)
+        start = synth.perturb_pose(gt, g.uniform(0.02, 0.08), g.uniform(1.0, 5.0), seed=2000 + j)
+        out.append((room, cam, gt, start))
+    return out
+
+
+def test_batched_tracking_32_problems(pkg):
+    import time
+
+    probs = _config4_problems()
+    r = pkg.Rasterizer()
+    batch, singles = [], []
+    for room, cam, gt, start in probs:
+        P = dev(room.params)
+        tgt = r.render(P, cam, dev(gt.reshape(12)))
+        batch.append((P, cam, dev(start.reshape(12)), tgt.rgb.clone(), tgt.depth.clone()))
+        singles.append(start)
+    torch.cuda.synchronize()
+    print("surfels", sum(p[0].shape[1] for p in batch), "pixels", sum(c.width * c.height for _, c, _, _ in probs))
+    ph, lh = r.track_batch(batch, n_iters=50)
+    torch.cuda.synchronize()
+    # timed: the same 32 x 50 iterations again from the start poses (graph reused)
+    for k, (_, _, pose, _, _) in enumerate(batch):
+        pose.copy_(dev(singles[k].reshape(12)))
+    t0 = time.perf_counter()
+    r.track_batch(batch, n_iters=50, history=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(f"32 problems x 50 iterations: {1e3 * el:.1f} ms, aggregate {32 * 50 / el:.0f} iters/s")
+    conv = 0
+    for k, (P, cam, _, trgb, tdep) in enumerate(batch):
+        p = dev(singles[k].reshape(12))
+        _, sph, slh = r.track(P, cam, p, trgb, tdep, n_iters=50)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(ph[:, k]), host(sph), err_msg=f"problem {k}")
+        np.testing.assert_array_equal(host(lh[:, k]), host(slh), err_msg=f"problem {k}")
+        e = synth.pose_error(host(ph[-1, k]).reshape(3, 4), probs[k][2])
+        conv += e[0] < 0.01 and e[1] < 0.5
+    print(f"{conv}/32 within 1 cm / 0.5 deg after 50 iterations")
