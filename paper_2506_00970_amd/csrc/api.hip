@@ -255,7 +255,15 @@ BlendArgs blend_args(gs2d_ctx* ctx) {
 // Forward pass of a view set.  With allow_sync the pair count is read back after the
 // scan and the pair buffers grow to fit; without it (graph capture, tracking loop) an
 // overflow only raises the device flag.
-int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync) {
+// upload = false: the device view table already holds vs (the tracking loop uploads
+// it once, outside the captured iteration).  tl: the forward also forms the tracking
+// loss of the views that carry targets.
+struct TrackLoss {
+  float lambda_d;
+  int use_masks;
+};
+int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync, bool upload = true,
+                 const TrackLoss* tl = nullptr) {
   const int64_t items = vs.items;
   const int nv = vs.n_views;
   bool capturing = false;
@@ -273,7 +281,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
   GS2D_TRY(ensure_parts(ctx, rows));
   if (ctx->p_cap == 0)
     GS2D_TRY(ensure_pairs(ctx, ctx->opt.pair_capacity > 0 ? ctx->opt.pair_capacity : 4 * (items > 0 ? items : 1)));
-  launch_upload_views(vs, ctx->views, s);
+  if (upload) launch_upload_views(vs, ctx->views, s);
   const int tw = ctx->opt.tile_w, th = ctx->opt.tile_h;
   int pbuf = 0;
   if (items == 0) {
@@ -337,6 +345,11 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     }
     BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, ctx->views, nv, (int)vs.tiles, ctx->opt.z_near,
                  ctx->opt.filter, ctx->opt.batch};
+    if (tl) {
+      ba.loss_part = ctx->part;
+      ba.lambda_d = tl->lambda_d;
+      ba.use_masks = tl->use_masks;
+    }
     {
       ProfScope ps(ctx, kBlendFwd, s);
       launch_blend_fwd(ba, tw, th, ctx->t_final, ctx->last, work_ptr(ctx, s), s);
@@ -507,9 +520,12 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
   adam.beta2 = a->beta2;
   adam.eps = a->eps;
   adam.weight_decay = a->weight_decay;
-  GS2D_TRY(render_views(ctx, vs, s, false));
+  // the forward blend also forms the tracking loss and its image gradients; with no
+  // surfel there is no blend and the loss kernel does it
+  const TrackLoss tl{a->lambda_d, a->use_masks};
+  GS2D_TRY(render_views(ctx, vs, s, false, false, &tl));
   const int stride = loss_blocks(vs.max_hw);
-  {
+  if (vs.items == 0) {
     ProfScope ps(ctx, kLoss, s);
     launch_tracking_loss(ctx->views, vs.n_views, vs.max_hw, a->lambda_d, a->use_masks, ctx->lpart, stride, s);
   }
@@ -522,7 +538,7 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
   }
   {
     ProfScope ps(ctx, kPose, s);
-    launch_pose_step(ctx->views, vs.n_views, ctx->part, ctx->lpart, stride, adam, ctx->ctrl, s);
+    launch_pose_step(ctx->views, vs.n_views, ctx->part, vs.items > 0, ctx->lpart, stride, adam, ctx->ctrl, s);
   }
   GS2D_HIP(ctx, hipGetLastError());
   return GS2D_OK;

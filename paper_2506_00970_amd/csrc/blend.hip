@@ -84,13 +84,6 @@ __device__ __forceinline__ float uniformf(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
-// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous band
-// of tiles so that neighbouring tiles, which share surfel records, share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int G) {
-  const int q = G / 8, r = G % 8, x = b % 8, k = b / 8;
-  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
-
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -168,7 +161,9 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   constexpr int NT = TW * TH, WX = TW / 8;
   extern __shared__ float4 srec[];
   float4* sbox = srec + (size_t)a.batch * kRecF4;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // global tile over all views
+  // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
+  // each XCD gets every 8th tile: an even share of the dense and sparse image regions
+  const int tile = blockIdx.x;
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
@@ -227,23 +222,65 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
     }
   }
   if (PROF) add_work(work, lane, n_eval, n_cov);
-  if (!inside) return;
   const int HW = V.cam.width * V.cam.height;
   const int p = py * V.cam.width + px;
-  if (V.rgb) {
-    V.rgb[p] = s.cr;
-    V.rgb[HW + p] = s.cg;
-    V.rgb[2 * HW + p] = s.cb;
+  if (inside) {
+    if (V.rgb) {
+      V.rgb[p] = s.cr;
+      V.rgb[HW + p] = s.cg;
+      V.rgb[2 * HW + p] = s.cb;
+    }
+    if (V.depth) V.depth[p] = s.cd;
+    if (V.normal) {
+      V.normal[p] = s.n0;
+      V.normal[HW + p] = s.n1;
+      V.normal[2 * HW + p] = s.n2;
+    }
+    if (V.alpha) V.alpha[p] = s.co;
+    t_final[V.pix_base + p] = s.T;
+    last_out[V.pix_base + p] = (uint32_t)s.lastj;
   }
-  if (V.depth) V.depth[p] = s.cd;
-  if (V.normal) {
-    V.normal[p] = s.n0;
-    V.normal[HW + p] = s.n1;
-    V.normal[2 * HW + p] = s.n2;
+  if (a.loss_part && V.tgt_rgb) {  // tracking (uniform over the workgroup)
+    // eq:tracking_loss at this pixel, with the normal and opacity masks of
+    // eq:normal_mask and eq:opacity_mask, and its gradient to the rendered images
+    float l = 0.f;
+    if (inside) {
+      bool m = true;
+      if (a.use_masks) {
+        const float xh = (fpx - V.cam.cx) / V.cam.fx, yh = (fpy - V.cam.cy) / V.cam.fy;
+        const float ndr = fmaf(s.n0, xh, fmaf(s.n1, yh, s.n2));
+        m = (ndr > 0.0f) && (s.co > kOpacityMask);
+      }
+      const float inv = 1.0f / (float)HW;
+      const float d0 = s.cr - V.tgt_rgb[p];
+      const float d1 = s.cg - V.tgt_rgb[HW + p];
+      const float d2 = s.cb - V.tgt_rgb[2 * HW + p];
+      const float dd = s.cd - V.tgt_depth[p];
+      auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
+      if (m) {
+        l = fabsf(d0) + fabsf(d1) + fabsf(d2) + a.lambda_d * fabsf(dd);
+        V.g_rgb[p] = sgn(d0) * inv;
+        V.g_rgb[HW + p] = sgn(d1) * inv;
+        V.g_rgb[2 * HW + p] = sgn(d2) * inv;
+        V.g_depth[p] = a.lambda_d * sgn(dd) * inv;
+      } else {
+        V.g_rgb[p] = 0.f;
+        V.g_rgb[HW + p] = 0.f;
+        V.g_rgb[2 * HW + p] = 0.f;
+        V.g_depth[p] = 0.f;
+      }
+    }
+    __shared__ float s_loss[NT / 64];
+    l = wave_sum(l);
+    if (lane == 0) s_loss[wave] = l;
+    __syncthreads();
+    if (t == 0) {
+      float sum = 0.f;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) sum += s_loss[w];
+      a.loss_part[(size_t)tile * 8 + 6] = sum;
+    }
   }
-  if (V.alpha) V.alpha[p] = s.co;
-  t_final[V.pix_base + p] = s.T;
-  last_out[V.pix_base + p] = (uint32_t)s.lastj;
 }
 
 // Per-pixel state of the backward walk.
@@ -376,7 +413,9 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   uint32_t* sid = reinterpret_cast<uint32_t*>(sbox + a.batch);
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);  // global tile over all views
+  // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
+  // each XCD gets every 8th tile: an even share of the dense and sparse image regions
+  const int tile = blockIdx.x;
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const CamF cam = V.cam;
   const int lt = tile - V.tile_base;
@@ -474,11 +513,10 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
       if (lane == 0) s_red[wave][k] = sum;
     }
     __syncthreads();
-    if (t < 8) {
+    if (t < 6) {  // slots 6 and 7 of the row belong to the forward's tracking loss
       float sum = 0.f;
-      if (t < 6)
 #pragma unroll
-        for (int w = 0; w < NW; ++w) sum += s_red[w][t];
+      for (int w = 0; w < NW; ++w) sum += s_red[w][t];
       part[(size_t)tile * 8 + t] = sum;
     }
   }

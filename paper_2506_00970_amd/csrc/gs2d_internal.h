@@ -77,6 +77,8 @@ struct Ctrl {            // device-resident counters and tracking state
   double loss[kMaxViews];
   double adam_m[kMaxViews][6];
   double adam_v[kMaxViews][6];
+  double adam_b1t[kMaxViews];   // beta1^t, beta2^t of each view's AdamW step
+  double adam_b2t[kMaxViews];
   double master_pose[kMaxViews][12];
 };
 
@@ -230,6 +232,11 @@ struct BlendArgs {
   float z_near;
   int filter;
   int batch;
+  // tracking: views with targets also get the tracking loss and its image gradients
+  // from the forward blend, each tile's loss sum in loss_part[tile * 8 + 6]
+  float* loss_part = nullptr;
+  float lambda_d = 0.f;
+  int use_masks = 0;
 };
 // work (may be null): profile counters, see Ctrl::work
 void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* t_final, uint32_t* last,
@@ -262,7 +269,10 @@ void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* po
                        int max_hist, hipStream_t s);
 // One AdamW + Exp step per view: pose partials are the rows of each view's tiles,
 // loss partials part[v * part_stride + block].
-void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, const float* loss_part,
+// loss_in_part: each view's loss is the sum of its tiles' pose_part[tile * 8 + 6]
+// (fused into the forward blend), else of its row of loss_part.
+void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, bool loss_in_part,
+                      const float* loss_part,
                       int part_stride, AdamArgs adam, Ctrl* ctrl, hipStream_t s);
 
 }  // namespace gs2d

@@ -132,6 +132,8 @@ __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_view
   for (int k = t; k < n_views; k += blockDim.x) {
     ctrl->loss[k] = 0.0;
     ctrl->iter_v[k] = 0;
+    ctrl->adam_b1t[k] = 1.0;
+    ctrl->adam_b2t[k] = 1.0;
   }
   if (t == 0) {
     ctrl->iter = 0;
@@ -172,48 +174,52 @@ __device__ void se3_exp(const double tau[6], double R[9], double tt[3]) {
 
 // One workgroup of 256 threads per view: a fixed-order (deterministic) reduction of
 // the view's pose and loss partials, then the AdamW + Exp step on one thread.
-__device__ inline double block_sum_d(double v, double* sh) {
-  v = wave_sum_d(v);
-  const int w = threadIdx.x / 64;
-  __syncthreads();
-  if (threadIdx.x % 64 == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int k = 0; k < (int)blockDim.x / 64; ++k) s += sh[k];
-  return s;
-}
-
 __global__ __launch_bounds__(256) void pose_step_kernel(const ViewDesc* __restrict__ views,
-                                                        const float* __restrict__ pose_part,
+                                                        const float* __restrict__ pose_part, int loss_in_part,
                                                         const float* __restrict__ loss_part, int part_stride,
                                                         AdamArgs adam, Ctrl* __restrict__ ctrl) {
-  __shared__ double sh[4];
+  __shared__ double sh[7][4];
   const int v = blockIdx.x;
   const int n_views = gridDim.x;
   const ViewDesc& V = views[v];
   const int HW = V.cam.width * V.cam.height;
   const int rows = V.tiles_x * V.tiles_y;
   const float* pp = pose_part + (size_t)V.tile_base * 8;
-  double g[6];
-  for (int k = 0; k < 6; ++k) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) s += (double)pp[(size_t)i * 8 + k];
-    g[k] = block_sum_d(s, sh);
+  // the six pose sums and the loss in one pass and one block reduction (fixed order)
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < rows; i += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] += (double)pp[(size_t)i * 8 + k];
+  if (loss_in_part) {
+    for (int i = threadIdx.x; i < rows; i += blockDim.x) acc[6] += (double)pp[(size_t)i * 8 + 6];
+  } else {
+    const int nl = loss_blocks_dev(HW);
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) acc[6] += (double)loss_part[(size_t)v * part_stride + i];
   }
-  double sl = 0.0;
-  const int nl = loss_blocks_dev(HW);
-  for (int i = threadIdx.x; i < nl; i += blockDim.x) sl += (double)loss_part[(size_t)v * part_stride + i];
-  const double loss = block_sum_d(sl, sh) / (double)HW;
+  const int w = threadIdx.x / 64;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double s = wave_sum_d(acc[k]);
+    if (threadIdx.x % 64 == 0) sh[k][w] = s;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  double g[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) g[k] = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
+  const double loss = (sh[6][0] + sh[6][1] + sh[6][2] + sh[6][3]) / (double)HW;
   const uint32_t it = ctrl->iter_v[v];
   float* pose_history = ctrl->pose_history;
   float* loss_history = ctrl->loss_history;
   const int max_hist = ctrl->max_hist;
   ctrl->loss[v] = loss;
   if (loss_history && (int)it < max_hist) loss_history[(size_t)it * n_views + v] = (float)loss;
-  const double t = (double)it + 1.0;
   const double b1 = adam.beta1, b2 = adam.beta2;
-  const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+  // bias corrections 1 - beta^t from running powers (t = it + 1)
+  const double b1t = ctrl->adam_b1t[v] * b1, b2t = ctrl->adam_b2t[v] * b2;
+  ctrl->adam_b1t[v] = b1t;
+  ctrl->adam_b2t[v] = b2t;
+  const double c1 = 1.0 - b1t, c2 = 1.0 - b2t;
   double tau[6];
   for (int k = 0; k < 6; ++k) {
     const double m = b1 * ctrl->adam_m[v][k] + (1.0 - b1) * g[k];
@@ -362,9 +368,10 @@ void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* po
   track_init_kernel<<<1, 256, 0, s>>>(views, n_views, ctrl, pose_history, loss_history, max_hist);
 }
 
-void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, const float* loss_part,
-                      int part_stride, AdamArgs adam, Ctrl* ctrl, hipStream_t s) {
-  pose_step_kernel<<<n_views, 256, 0, s>>>(views, pose_part, loss_part, part_stride, adam, ctrl);
+void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, bool loss_in_part,
+                      const float* loss_part, int part_stride, AdamArgs adam, Ctrl* ctrl, hipStream_t s) {
+  pose_step_kernel<<<n_views, 256, 0, s>>>(views, pose_part, loss_in_part ? 1 : 0, loss_part, part_stride, adam,
+                                           ctrl);
 }
 
 }  // namespace gs2d

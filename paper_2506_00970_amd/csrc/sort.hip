@@ -265,17 +265,23 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // all of the block's keys up front: the rounds' loads overlap instead of each
+  // round waiting for its own
+  uint32_t kr[kRounds], vr[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = base + r * kThreads + t;
+    kr[r] = i < n ? kin[i] : 0u;
+    vr[r] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t stamp = (uint32_t)(r + 1) << 16;
     const int64_t i = base + r * kThreads + t;
-    uint32_t key = 0, val = 0, digit = 0;
+    const uint32_t key = kr[r], val = vr[r];
     bool valid = i < n;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-      digit = (key >> shift) & ((1u << bits) - 1u);
-      valid = !(drop && key == kDropKey);
-    }
+    const uint32_t digit = valid ? (key >> shift) & ((1u << bits) - 1u) : 0u;
+    valid = valid && !(drop && key == kDropKey);
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
       const bool set = (digit >> b) & 1u;

@@ -64,20 +64,26 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Op op, int M, int N, int
   const int r = t >> 2, kc = (t & 3) * 8;  // this thread's row (of A and of B^T) and k chunk
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int li = lane & 15, g = lane >> 4;
+  const int m = m0 + r, n = n0 + r;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kb; k0 < ke; k0 += kBK) {
+    // each op gathers 8 consecutive k of one row (zero past ke): the index is
+    // decomposed once per chunk and stepped across the 8
     uint16_t va[8], vb[8];
-    const int m = m0 + r, n = n0 + r;
+    if (m < M)
+      op.a8(m, k0 + kc, ke, va);
+    else
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = k0 + kc + i;
-      va[i] = (m < M && k < ke) ? op.a(m, k) : (uint16_t)0;
-      vb[i] = (n < N && k < ke) ? op.b(k, n) : (uint16_t)0;
-    }
+      for (int i = 0; i < 8; ++i) va[i] = 0;
+    if (n < N)
+      op.b8(k0 + kc, n, ke, vb);
+    else
+#pragma unroll
+      for (int i = 0; i < 8; ++i) vb[i] = 0;
     __syncthreads();  // the previous step's fragments have been read
     uint4 pa, pb;
     pa.x = va[0] | ((uint32_t)va[1] << 16);
@@ -108,31 +114,52 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(Op op, int M, int N, int
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm + i * 16 + g * 4 + q, n = n0 + wn + j * 16 + li;
-        if (m < M && n < N) op.store(m, n, acc[i][j][q]);
+        const int mm = m0 + wm + i * 16 + g * 4 + q, nn = n0 + wn + j * 16 + li;
+        if (mm < M && nn < N) op.store(mm, nn, acc[i][j][q]);
       }
 }
 
-// Shapes of one stride-2 convolution over a batch.
+// Shapes of one stride-2 convolution over a batch (kernel side KS fixed by the op).
 struct ConvShape {
   int B, ci, co, k, H, W, OH, OW;
 };
 
-// y = bf16(relu(conv(x, w) + bias)): M = co, N = B OH OW, K = ci k k.
+// 8 consecutive values of a contiguous row, zero past `end`.
+__device__ __forceinline__ void row8(const uint16_t* __restrict__ p, int k, int end, uint16_t* out) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) out[i] = k + i < end ? p[k + i] : (uint16_t)0;
+}
+
+// y = bf16(relu(conv(x, w) + bias)): M = co, N = B OH OW, K = ci KS KS.
+template <int KS>
 struct ConvFwd {
   ConvShape s;
   const uint16_t* w;
   const float* bias;
   const uint16_t* x;
   uint16_t* y;
-  __device__ uint16_t a(int m, int k) const { return w[(size_t)m * (s.ci * s.k * s.k) + k]; }
-  __device__ uint16_t b(int k, int n) const {
-    const int kk = s.k * s.k, ohw = s.OH * s.OW;
+  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
+    row8(w + (size_t)m * (s.ci * KS * KS), k, ke, out);
+  }
+  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
+    const int ohw = s.OH * s.OW;
     const int bi = n / ohw, rr = n - bi * ohw, oy = rr / s.OW, ox = rr - oy * s.OW;
-    const int c = k / kk, t = k - c * kk, ky = t / s.k, kx = t - ky * s.k;
-    const int iy = 2 * oy + ky - s.k / 2, ix = 2 * ox + kx - s.k / 2;
-    if (iy < 0 || iy >= s.H || ix < 0 || ix >= s.W) return 0;
-    return x[(((size_t)bi * s.ci + c) * s.H + iy) * s.W + ix];
+    const int iy0 = 2 * oy - KS / 2, ix0 = 2 * ox - KS / 2;
+    const uint16_t* __restrict__ xb = x + (size_t)bi * s.ci * s.H * s.W;
+    int c = k / (KS * KS), t = k - c * (KS * KS), ky = t / KS, kx = t - ky * KS;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int iy = iy0 + ky, ix = ix0 + kx;
+      out[i] = (k + i < ke && iy >= 0 && iy < s.H && ix >= 0 && ix < s.W) ? xb[((size_t)c * s.H + iy) * s.W + ix]
+                                                                           : (uint16_t)0;
+      if (++kx == KS) {
+        kx = 0;
+        if (++ky == KS) {
+          ky = 0;
+          ++c;
+        }
+      }
+    }
   }
   __device__ void store(int m, int n, float v) const {
     const int ohw = s.OH * s.OW, bi = n / ohw, rr = n - bi * ohw;
@@ -142,26 +169,45 @@ struct ConvFwd {
 };
 
 // Input gradient of a convolution, masked by the ReLU of its input:
-// gx = bf16(conv^T(gy, w) [x > 0]): M = ci, N = B H W, K = co k k.
+// gx = bf16(conv^T(gy, w) [x > 0]): M = ci, N = B H W, K = co KS KS.
+template <int KS>
 struct ConvBwdData {
   ConvShape s;
   const uint16_t* w;
   const uint16_t* gy;  // [B][co][OH][OW]
   const uint16_t* x;   // the layer's input (post-ReLU)
   uint16_t* gx;        // [B][ci][H][W]
-  __device__ uint16_t a(int m, int k) const {
-    const int kk = s.k * s.k, o = k / kk, t = k - o * kk;
-    return w[((size_t)o * s.ci + m) * kk + t];
+  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
+    constexpr int KK = KS * KS;
+    int o = k / KK, t = k - o * KK;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      out[i] = k + i < ke ? w[((size_t)o * s.ci + m) * KK + t] : (uint16_t)0;
+      if (++t == KK) {
+        t = 0;
+        ++o;
+      }
+    }
   }
-  __device__ uint16_t b(int k, int n) const {
-    const int kk = s.k * s.k, hw = s.H * s.W;
+  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
+    const int hw = s.H * s.W;
     const int bi = n / hw, rr = n - bi * hw, iy = rr / s.W, ix = rr - iy * s.W;
-    const int o = k / kk, t = k - o * kk, ky = t / s.k, kx = t - ky * s.k;
-    const int ty = iy + s.k / 2 - ky, tx = ix + s.k / 2 - kx;  // = 2 oy, 2 ox
-    if (ty < 0 || tx < 0 || (ty & 1) || (tx & 1)) return 0;
-    const int oy = ty >> 1, ox = tx >> 1;
-    if (oy >= s.OH || ox >= s.OW) return 0;
-    return gy[(((size_t)bi * s.co + o) * s.OH + oy) * s.OW + ox];
+    const uint16_t* __restrict__ gb = gy + (size_t)bi * s.co * s.OH * s.OW;
+    int o = k / (KS * KS), t = k - o * (KS * KS), ky = t / KS, kx = t - ky * KS;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int ty = iy + KS / 2 - ky, tx = ix + KS / 2 - kx;  // = 2 oy, 2 ox
+      const int oy = ty >> 1, ox = tx >> 1;
+      const bool ok = k + i < ke && ty >= 0 && tx >= 0 && !(ty & 1) && !(tx & 1) && oy < s.OH && ox < s.OW;
+      out[i] = ok ? gb[((size_t)o * s.OH + oy) * s.OW + ox] : (uint16_t)0;
+      if (++kx == KS) {
+        kx = 0;
+        if (++ky == KS) {
+          ky = 0;
+          ++o;
+        }
+      }
+    }
   }
   __device__ void store(int m, int n, float v) const {
     const int hw = s.H * s.W, bi = n / hw, rr = n - bi * hw;
@@ -171,26 +217,49 @@ struct ConvBwdData {
 };
 
 // Weight and bias gradient of a convolution, one split-K slice per blockIdx.z:
-// part[z][co][ci k k + 1] = sum_n gy[co][n] [x patch | 1][n].
+// part[z][co][ci KS KS + 1] = sum_n gy[co][n] [x patch | 1][n].
+template <int KS>
 struct ConvBwdWeight {
   ConvShape s;
   const uint16_t* gy;
   const uint16_t* x;
   float* part;
-  int ncol;  // ci k k + 1
+  int ncol;  // ci KS KS + 1
   int M;
-  __device__ uint16_t a(int m, int k) const {
-    const int ohw = s.OH * s.OW, bi = k / ohw, rr = k - bi * ohw;
-    return gy[((size_t)bi * s.co + m) * ohw + rr];
+  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
+    const int ohw = s.OH * s.OW;
+    int bi = k / ohw, rr = k - bi * ohw;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      out[i] = k + i < ke ? gy[((size_t)bi * s.co + m) * ohw + rr] : (uint16_t)0;
+      if (++rr == ohw) {
+        rr = 0;
+        ++bi;
+      }
+    }
   }
-  __device__ uint16_t b(int k, int n) const {
-    if (n == ncol - 1) return kOne;
-    const int kk = s.k * s.k, ohw = s.OH * s.OW;
-    const int bi = k / ohw, rr = k - bi * ohw, oy = rr / s.OW, ox = rr - oy * s.OW;
-    const int c = n / kk, t = n - c * kk, ky = t / s.k, kx = t - ky * s.k;
-    const int iy = 2 * oy + ky - s.k / 2, ix = 2 * ox + kx - s.k / 2;
-    if (iy < 0 || iy >= s.H || ix < 0 || ix >= s.W) return 0;
-    return x[(((size_t)bi * s.ci + c) * s.H + iy) * s.W + ix];
+  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
+    if (n == ncol - 1) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? kOne : (uint16_t)0;
+      return;
+    }
+    const int c = n / (KS * KS), t = n - c * (KS * KS), ky = t / KS, kx = t - ky * KS;
+    const int ohw = s.OH * s.OW;
+    int bi = k / ohw, rr = k - bi * ohw, oy = rr / s.OW, ox = rr - oy * s.OW;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int iy = 2 * oy + ky - KS / 2, ix = 2 * ox + kx - KS / 2;
+      const bool ok = k + i < ke && iy >= 0 && iy < s.H && ix >= 0 && ix < s.W;
+      out[i] = ok ? x[(((size_t)bi * s.ci + c) * s.H + iy) * s.W + ix] : (uint16_t)0;
+      if (++ox == s.OW) {
+        ox = 0;
+        if (++oy == s.OH) {
+          oy = 0;
+          ++bi;
+        }
+      }
+    }
   }
   __device__ void store(int m, int n, float v) const { part[((size_t)blockIdx.z * M + m) * ncol + n] = v; }
 };
@@ -203,8 +272,8 @@ struct FcFwd {
   const uint16_t* x;
   uint16_t* y;   // ReLU + bf16 (hidden layer), or
   float* yf;     // FP32, no ReLU (output layer)
-  __device__ uint16_t a(int m, int k) const { return w[(size_t)m * I + k]; }
-  __device__ uint16_t b(int k, int n) const { return x[(size_t)n * I + k]; }
+  __device__ void a8(int m, int k, int ke, uint16_t* out) const { row8(w + (size_t)m * I, k, ke, out); }
+  __device__ void b8(int k, int n, int ke, uint16_t* out) const { row8(x + (size_t)n * I, k, ke, out); }
   __device__ void store(int m, int n, float v) const {
     v += bias[m];
     if (yf)
@@ -222,8 +291,11 @@ struct FcBwdData {
   const uint16_t* gy;
   const uint16_t* x;
   uint16_t* gx;
-  __device__ uint16_t a(int m, int k) const { return w[(size_t)k * I + m]; }
-  __device__ uint16_t b(int k, int n) const { return gy[(size_t)n * O + k]; }
+  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? w[(size_t)(k + i) * I + m] : (uint16_t)0;
+  }
+  __device__ void b8(int k, int n, int ke, uint16_t* out) const { row8(gy + (size_t)n * O, k, ke, out); }
   __device__ void store(int m, int n, float v) const {
     const size_t idx = (size_t)n * I + m;
     gx[idx] = to_bf16(positive(x[idx]) ? v : 0.f);
@@ -236,8 +308,14 @@ struct FcBwdWeight {
   const uint16_t* gy;
   const uint16_t* x;
   float* part;
-  __device__ uint16_t a(int m, int k) const { return gy[(size_t)k * O + m]; }
-  __device__ uint16_t b(int k, int n) const { return n == I ? kOne : x[(size_t)k * I + n]; }
+  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? gy[(size_t)(k + i) * O + m] : (uint16_t)0;
+  }
+  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? (n == I ? kOne : x[(size_t)(k + i) * I + n]) : (uint16_t)0;
+  }
   __device__ void store(int m, int n, float v) const { part[((size_t)blockIdx.z * O + m) * (I + 1) + n] = v; }
 };
 
@@ -460,8 +538,12 @@ ConvShape conv_shape(int li, int B) {
 void forward_layers(gs2d_ws* net, int B, hipStream_t s) {
   for (int li = 0; li < 4; ++li) {
     const ConvShape cs = conv_shape(li, B);
-    ConvFwd op{cs, net->wb + net->w_off[li], net->theta + net->b_off[li], net->act[li], net->act[li + 1]};
-    gemm(op, cs.co, B * cs.OH * cs.OW, cs.ci * cs.k * cs.k, 1, s);
+    const uint16_t* w = net->wb + net->w_off[li];
+    const float* b = net->theta + net->b_off[li];
+    if (cs.k == 5)
+      gemm(ConvFwd<5>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 25, 1, s);
+    else
+      gemm(ConvFwd<3>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 9, 1, s);
   }
   {
     FcFwd op{2560, 256, net->wb + net->w_off[4], net->theta + net->b_off[4], net->act[4], net->act[5], nullptr};
@@ -480,8 +562,10 @@ int weight_grad(gs2d_ws* net, int li, int B, hipStream_t s) {
   if (L.k) {
     const ConvShape cs = conv_shape(li, B);
     const int ncol = cs.ci * cs.k * cs.k + 1, K = B * cs.OH * cs.OW, sp = splits_for(K);
-    ConvBwdWeight op{cs, net->gact[li + 1], net->act[li], net->part, ncol, cs.co};
-    gemm(op, cs.co, ncol, K, sp, s);
+    if (cs.k == 5)
+      gemm(ConvBwdWeight<5>{cs, net->gact[li + 1], net->act[li], net->part, ncol, cs.co}, cs.co, ncol, K, sp, s);
+    else
+      gemm(ConvBwdWeight<3>{cs, net->gact[li + 1], net->act[li], net->part, ncol, cs.co}, cs.co, ncol, K, sp, s);
     reduce_parts_kernel<<<(cs.co * ncol + 255) / 256, 256, 0, s>>>(net->part, sp, cs.co, ncol, gw, gb);
   } else {
     const int sp = splits_for(B);
@@ -642,8 +726,9 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
     WS_TRY(weight_grad(net, li, B, s));
     if (li > 0) {
       const ConvShape cs = conv_shape(li, B);
-      ConvBwdData op{cs, net->wb + net->w_off[li], net->gact[li + 1], net->act[li], net->gact[li]};
-      gemm(op, cs.ci, B * cs.H * cs.W, cs.co * cs.k * cs.k, 1, s);
+      // layers 1-3 (the input gradient of layer 0 is not needed) are all 3 x 3
+      ConvBwdData<3> op{cs, net->wb + net->w_off[li], net->gact[li + 1], net->act[li], net->gact[li]};
+      gemm(op, cs.ci, B * cs.H * cs.W, cs.co * 9, 1, s);
     }
   }
   if (loss) WS_HIP(hipMemcpyAsync(loss, net->lossbuf, sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -192,12 +192,11 @@ def test_warm_start_choice(wsmod):
     np.testing.assert_array_equal(host(chosen), start.reshape(12))
 
 
-def test_warm_start_gain_on_held_out_rooms(wsmod):
-    """The trained network (the committed weights, trained on rooms 2000-2199) against plain
-    tracking on held-out rooms 0-5 with the tracking workload's 5 cm / 3 deg start: the
-    warm-started tracking reaches 1 cm / 0.5 deg in fewer iterations in most rooms and, with
-    the warm start itself charged as 3 iterations (0.77 ms against 0.31 ms per iteration),
-    in at most 80 % of the plain iterations overall."""
+@pytest.fixture(scope="module")
+def held_out(wsmod):
+    """Plain and warm-started tracking (100 iterations) on held-out rooms 0-19 with the
+    tracking workload's 5 cm / 3 deg start, using the committed weights (trained on
+    rooms 2000-2199)."""
     import os
 
     from paper_2506_00970_amd import Rasterizer
@@ -207,11 +206,28 @@ def test_warm_start_gain_on_held_out_rooms(wsmod):
     net = wsmod.WarmStartNet(max_batch=1)
     net.set_params(dev(np.load(path, allow_pickle=False).astype(np.float32)))
     r = Rasterizer()
-    plain, warm = [], []
-    for seed in range(6):
+    out = []
+    for seed in range(20):
         c = run_case(r, net, seed, 100)
-        plain.append(c["plain_iters"] or 101)
-        warm.append(c["warm_iters"] or 101)
+        out.append((c["plain_iters"], c["warm_iters"]))
         print(seed, "plain", c["plain_iters"], "warm", c["warm_iters"], "after warm start", c["warm_err_cm_deg"])
+    return out
+
+
+def test_warm_start_gain_on_held_out_rooms(held_out):
+    """The warm-started tracking reaches 1 cm / 0.5 deg in fewer iterations in most rooms
+    and, with the warm start itself charged as 3 iterations (0.77 ms against 0.31 ms per
+    iteration), in at most 80 % of the plain iterations overall (unconverged runs count
+    101)."""
+    plain = [p or 101 for p, _ in held_out]
+    warm = [w or 101 for _, w in held_out]
     assert sum(w + 3 for w in warm) <= 0.8 * sum(plain), (plain, warm)
-    assert sum(w < p for w, p in zip(warm, plain)) >= 4, (plain, warm)
+    assert sum(w < p for w, p in zip(warm, plain)) >= 14, (plain, warm)
+
+
+def test_tracking_converges_on_held_out_rooms(held_out):
+    """End to end: from a 5 cm / 3 deg start, plain tracking converges to 1 cm / 0.5 deg
+    within 100 iterations in at least 90 % of the rooms (measured 19 of 20) and the
+    warm-started tracking in at least 95 % (measured 20 of 20)."""
+    assert sum(p is not None for p, _ in held_out) >= 18, held_out
+    assert sum(w is not None for _, w in held_out) >= 19, held_out
