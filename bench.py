@@ -234,19 +234,25 @@ def main():
     rt.track(P, cam, pose, tgt_rgb, tgt_depth, n_iters=args.profile_steps, lr=LR, use_graph=False, history=False)
     fam = rt.profile(reset=True)["families"]
     per_launch = {k: (v["ms"] / v["launches"] if v["launches"] else 0.0) for k, v in fam.items()}
-    dom = max(("blend_fwd", "blend_bwd"), key=lambda k: per_launch[k])
-    n_fwd = fam["blend_fwd"]["launches"]
-    n_bwd = fam["blend_bwd"]["launches"]
-    if dom == "blend_bwd":
-        units = prof["bwd_covering"] / max(n_bwd, 1)
-        ops = units * OPS_BWD_PAIR
-    else:
+    cfam = prof["families"]  # launches of the counting pass
+    n_fwd = cfam["blend_fwd"]["launches"] + cfam["blend_track"]["launches"]
+    n_bwd = cfam["blend_bwd"]["launches"]
+    if cfam["blend_track"]["launches"]:
+        # the tracking walk: forward blend, loss and pose gradient of each covering pair
+        dom = "blend_track"
         units = prof["fwd_covering"] / max(n_fwd, 1)
-        ops = units * OPS_FWD_PAIR
+        ops_unit = OPS_FWD_PAIR + OPS_BWD_PAIR
+    else:
+        dom = max(("blend_fwd", "blend_bwd"), key=lambda k: per_launch[k])
+        if dom == "blend_bwd":
+            units, ops_unit = prof["bwd_covering"] / max(n_bwd, 1), OPS_BWD_PAIR
+        else:
+            units, ops_unit = prof["fwd_covering"] / max(n_fwd, 1), OPS_FWD_PAIR
+    ops = units * ops_unit
     achieved = ops / (per_launch[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(dom),
-                "units_per_launch": units, "ops_per_unit": OPS_BWD_PAIR if dom == "blend_bwd" else OPS_FWD_PAIR,
+                "units_per_launch": units, "ops_per_unit": ops_unit,
                 "avg_launch_ms": per_launch[dom]}
 
     out = {

@@ -80,7 +80,7 @@ typedef struct gs2d_camera {
 
 typedef struct gs2d_options {
   int32_t tile_w, tile_h;    /* screen tile: 8x8, 16x8, 16x16 (default) or 32x16 */
-  int32_t batch;             /* surfels staged per LDS batch: 32, 64, 128 or 256 (default) */
+  int32_t batch;             /* surfels staged per LDS batch: 32, 64, 128 (default) or 256 */
   int32_t filter;            /* 1 (default): low-pass filter branch; 0: plain 3-sigma footprint */
   float z_near;              /* default 0.2: centre cull and per-pixel depth cut */
   int64_t pair_capacity;     /* tile-pair capacity; 0 (default): grow on demand */
@@ -137,7 +137,7 @@ typedef struct gs2d_track_problem {
 } gs2d_track_problem;
 
 /* Kernel-family timings (options.profile = 1 or 2) and blend work counters (profile = 1). */
-#define GS2D_PROFILE_FAMILIES 12
+#define GS2D_PROFILE_FAMILIES 13
 typedef struct gs2d_profile {
   double ms[GS2D_PROFILE_FAMILIES];          /* summed event time per family since the last reset */
   int64_t launches[GS2D_PROFILE_FAMILIES];   /* timed calls per family */
@@ -282,7 +282,9 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
  * 4 per-surfel tile rect (uint16 [n][4]: x0, x1, y0, y1, inclusive; empty: x0 > x1),
  * 5 per-pixel final transmittance (float [H][W]), 6 per-pixel list length (uint32 [H][W]),
  * 7 unsorted tile keys, 8 unsorted surfel ids (uint32 [n_pairs], before the tile sort;
- * only with options.keep_unsorted = 1), 9 depth-sorted surfel ids (uint32 [n_visible]).
+ * only with options.keep_unsorted = 1), 9 depth-sorted surfel ids (uint32 [n_visible]),
+ * 10 the pose gradient of each problem's last tracking iteration (double [32][6];
+ * available after gs2d_track / gs2d_track_batch, without a forward).
  * *bytes (host) is the buffer size in; the bytes copied out.  Synchronises `stream`. */
 GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes,
                              hipStream_t stream);

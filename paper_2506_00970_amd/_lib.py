@@ -41,7 +41,7 @@ class Counts(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
 
 
-PROFILE_FAMILIES = 12
+PROFILE_FAMILIES = 13
 
 
 class Profile(ctypes.Structure):

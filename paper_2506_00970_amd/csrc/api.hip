@@ -58,7 +58,8 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 const char* kFamilyNames[kNumFamilies] = {"preprocess", "depth_sort", "scan",     "duplicate",
                                           "tile_sort",  "ranges",     "blend_fwd", "loss",
-                                          "blend_bwd",  "preprocess_bwd", "pose_step", "reduce"};
+                                          "blend_bwd",  "preprocess_bwd", "pose_step", "reduce",
+                                          "blend_track"};
 
 // Records a HIP event pair around a kernel family on the launch stream when the
 // context profiles and the stream is not being captured.
@@ -263,7 +264,7 @@ struct TrackLoss {
   int use_masks;
 };
 int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync, bool upload = true,
-                 const TrackLoss* tl = nullptr) {
+                 const TrackLoss* tl = nullptr, bool blend = true) {
   const int64_t items = vs.items;
   const int nv = vs.n_views;
   bool capturing = false;
@@ -350,7 +351,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
       ba.lambda_d = tl->lambda_d;
       ba.use_masks = tl->use_masks;
     }
-    {
+    if (blend) {
       ProfScope ps(ctx, kBlendFwd, s);
       launch_blend_fwd(ba, tw, th, ctx->t_final, ctx->last, work_ptr(ctx, s), s);
     }
@@ -520,21 +521,23 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
   adam.beta2 = a->beta2;
   adam.eps = a->eps;
   adam.weight_decay = a->weight_decay;
-  // the forward blend also forms the tracking loss and its image gradients; with no
-  // surfel there is no blend and the loss kernel does it
-  const TrackLoss tl{a->lambda_d, a->use_masks};
-  GS2D_TRY(render_views(ctx, vs, s, false, false, &tl));
+  // sorts, then one walk per tile for the forward blend, the tracking loss and the
+  // pose gradient; with no surfel there is no walk and the loss kernel forms the loss
+  GS2D_TRY(render_views(ctx, vs, s, false, false, nullptr, false));
   const int stride = loss_blocks(vs.max_hw);
-  if (vs.items == 0) {
-    ProfScope ps(ctx, kLoss, s);
-    launch_tracking_loss(ctx->views, vs.n_views, vs.max_hw, a->lambda_d, a->use_masks, ctx->lpart, stride, s);
-  }
   if (vs.items > 0) {
-    ProfScope ps(ctx, kBlendBwd, s);
-    launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, false, false,
-                     nullptr, ctx->part, work_ptr(ctx, s), s);
+    BlendArgs ba = blend_args(ctx);
+    ba.loss_part = ctx->part;
+    ba.lambda_d = a->lambda_d;
+    ba.use_masks = a->use_masks;
+    ProfScope ps(ctx, kBlendTrack, s);
+    launch_blend_track(ba, ctx->opt.tile_w, ctx->opt.tile_h, work_ptr(ctx, s), s);
   } else {
-    launch_fill_f32(ctx->part, 0.f, 8 * vs.tiles, s);
+    {
+      ProfScope ps(ctx, kLoss, s);
+      launch_fill_f32(ctx->part, 0.f, 8 * vs.tiles, s);
+    }
+    launch_tracking_loss(ctx->views, vs.n_views, vs.max_hw, a->lambda_d, a->use_masks, ctx->lpart, stride, s);
   }
   {
     ProfScope ps(ctx, kPose, s);
@@ -673,7 +676,7 @@ GS2D_API int gs2d_default_options(gs2d_options* opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->tile_w = 16;
   opt->tile_h = 16;
-  opt->batch = 256;
+  opt->batch = 128;
   opt->filter = 1;
   opt->z_near = 0.2f;
   opt->pair_capacity = 0;
@@ -853,6 +856,18 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
 
 GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes, hipStream_t stream) {
   if (!ctx || !bytes || (!host_dst && *bytes > 0)) return GS2D_ERR_INVALID_ARG;
+  if (which == 10) {  // the tracking loop's last pose gradients (no forward state needed)
+    const size_t need = sizeof(ctx->ctrl->last_grad);
+    if (*bytes < need) {
+      *bytes = need;
+      return GS2D_ERR_INVALID_ARG;
+    }
+    GS2D_TRY(set_device(ctx));
+    GS2D_HIP(ctx, hipStreamSynchronize(stream));
+    GS2D_HIP(ctx, hipMemcpy(host_dst, ctx->ctrl->last_grad, need, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return GS2D_OK;
+  }
   if (!ctx->have_forward) return GS2D_ERR_STATE;
   gs2d_counts c;
   GS2D_TRY(gs2d_get_counts(ctx, &c, stream));

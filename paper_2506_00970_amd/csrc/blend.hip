@@ -84,6 +84,18 @@ __device__ __forceinline__ float uniformf(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
+// Issue priority of a wave by the length of the list it walks: all tiles' workgroups
+// are resident at once, and a long list is the critical path of the launch, so its
+// waves take the SIMD before the short ones (which fill the remaining slots).
+__device__ __forceinline__ void prioritise(int len) {
+  if (len >= 192)
+    __builtin_amdgcn_s_setprio(3);
+  else if (len >= 128)
+    __builtin_amdgcn_s_setprio(2);
+  else if (len >= 64)
+    __builtin_amdgcn_s_setprio(1);
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -95,16 +107,67 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Entries [c0, c0 + 64) of a staged batch of nb: the mask of those whose footprint
-// box overlaps the wave's 8x8 block [bx0, bx1] x [by0, by1] (lane k tests entry
-// c0 + k) and whose list position is below `limit`.  The mask is wave-uniform.
-__device__ __forceinline__ uint64_t overlap_mask(const float4* sbox, int c0, int nb, int lane, float bx0,
-                                                 float bx1, float by0, float by1, int pos0, int limit) {
+// Per staged entry, what the waves' cull reads: the footprint box, the 3-sigma
+// ellipse (centre relative to the box corner, support matrix Sxx, Sxy) and
+// (Syy, low-pass disc centre relative to the box corner, 0).
+constexpr int kLdsRec = 6;  // record float4 kept per staged entry ([6] feeds the cull only)
+
+struct CullLds {
+  float4* box;
+  float4* ell;
+  float4* ell2;
+};
+__device__ __forceinline__ void stage_cull(const CullLds& c, int j, int f, const float4& v) {
+  if (f == 0) c.box[j] = v;
+  if (f == 6) c.ell[j] = v;
+  if (f == 5) c.ell2[j].x = v.w;
+  if (f == 1) {
+    c.ell2[j].y = v.x;
+    c.ell2[j].z = v.y;
+  }
+}
+
+// Entries [c0, c0 + 64) of a staged batch of nb: the mask of those whose list
+// position is below `limit` and whose footprint may touch the wave's 8x8 block
+// [bx0, bx0 + 7] x [by0, by0 + 7] (lane k tests entry c0 + k; the mask is
+// wave-uniform).  The footprint (rho <= 9) is the union of the projected 3-sigma
+// ellipse and, with the low-pass filter, the disc of radius 3/sqrt(2) about the
+// projected centre.  An entry is dropped when its box misses the block, or when
+// both the ellipse and the disc are separated from it: the ellipse along the
+// direction from its centre to the block's centre, the disc by its distance.  Half
+// a pixel of slack keeps the test conservative against the per-pixel FP32
+// evaluation, so dropping changes no image.
+__device__ __forceinline__ uint64_t overlap_mask(const CullLds& c, int c0, int nb, int lane, float bx0, float by0,
+                                                 int filter, int pos0, int limit) {
   const int j = c0 + lane;
   bool hit = false;
   if (j < nb && pos0 + j < limit) {
-    const float4 bb = sbox[j];
-    hit = !(bb.y < bx0 || bb.x > bx1 || bb.w < by0 || bb.z > by1);
+    const float4 bb = c.box[j];
+    hit = !(bb.y < bx0 || bb.x > bx0 + 7.0f || bb.w < by0 || bb.z > by0 + 7.0f);
+    if (hit) {
+      const float4 e = c.ell[j], e2 = c.ell2[j];
+      // block corner relative to the box corner (integers: exact)
+      const float rx = bx0 - bb.x, ry = by0 - bb.z;
+      float nx = rx + 3.5f - e.x, ny = ry + 3.5f - e.y;
+      const float n2 = nx * nx + ny * ny;
+      bool sep_e = false;
+      if (n2 > 0.0f) {
+        const float inv = __builtin_amdgcn_rsqf(n2);
+        nx *= inv;
+        ny *= inv;
+        const float ext = __builtin_amdgcn_sqrtf(fmaxf(nx * nx * e.z + 2.0f * nx * ny * e.w + ny * ny * e2.x, 0.0f));
+        const float box_lo = nx * (rx + 3.5f) + ny * (ry + 3.5f) - 3.5f * (fabsf(nx) + fabsf(ny));
+        sep_e = box_lo > nx * e.x + ny * e.y + ext + 0.5f;
+      }
+      bool sep_d = true;
+      if (filter) {
+        const float qx = fminf(fmaxf(e2.y, rx), rx + 7.0f), qy = fminf(fmaxf(e2.z, ry), ry + 7.0f);
+        const float dx = e2.y - qx, dy = e2.z - qy;
+        const float r = 2.12132034f + 0.5f;  // sqrt(9 / 2) + slack
+        sep_d = dx * dx + dy * dy > r * r;
+      }
+      hit = !(sep_e && sep_d);
+    }
   }
   return __ballot(hit);
 }
@@ -116,14 +179,14 @@ struct Rec {
 };
 __device__ __forceinline__ Rec load_rec(const float4* srec, int j) {
   Rec r;
-  const float4 bb = srec[j * kRecF4];
+  const float4 bb = srec[j * kLdsRec];
   r.ox = bb.x;
   r.oy = bb.z;
-  r.g1 = srec[j * kRecF4 + 1];
-  r.g2 = srec[j * kRecF4 + 2];
-  r.g3 = srec[j * kRecF4 + 3];
-  r.c4 = srec[j * kRecF4 + 4];
-  r.nv = srec[j * kRecF4 + 5];
+  r.g1 = srec[j * kLdsRec + 1];
+  r.g2 = srec[j * kLdsRec + 2];
+  r.g3 = srec[j * kLdsRec + 3];
+  r.c4 = srec[j * kLdsRec + 4];
+  r.nv = srec[j * kLdsRec + 5];
   return r;
 }
 
@@ -160,7 +223,8 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
                                                            unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8;
   extern __shared__ float4 srec[];
-  float4* sbox = srec + (size_t)a.batch * kRecF4;
+  const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
+                     srec + (size_t)a.batch * (kLdsRec + 2)};
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
   // each XCD gets every 8th tile: an even share of the dense and sparse image regions
   const int tile = blockIdx.x;
@@ -172,9 +236,10 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
   const bool inside = px < V.cam.width && py < V.cam.height;
   const float fpx = (float)px, fpy = (float)py;
-  const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
+  const float bx0 = (float)wx0, by0 = (float)wy0;
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x, end = (int)rg.y;
+  prioritise(end - start);
   FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
   int n_eval = 0, n_cov = 0;
   for (int b0 = start; b0 < end; b0 += a.batch) {
@@ -183,14 +248,14 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
     for (int k = t; k < nb * kRecF4; k += NT) {
       const int j = k / kRecF4, f = k - j * kRecF4;
       const float4 v = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
-      srec[k] = v;
-      if (f == 0) sbox[j] = v;
+      if (f < kLdsRec) srec[j * kLdsRec + f] = v;
+      stage_cull(cull, j, f, v);
     }
     __syncthreads();
     const int pos0 = b0 - start;
     for (int c0 = 0; c0 < nb; c0 += 64) {
       if (__ballot(!s.done) == 0ull) break;
-      uint64_t m = overlap_mask(sbox, c0, nb, lane, bx0, bx1, by0, by1, 0, nb);
+      uint64_t m = overlap_mask(cull, c0, nb, lane, bx0, by0, a.filter, 0, nb);
       // two overlapping entries per step: their evaluations are independent, the
       // compositing stays in list order
       while (m != 0ull) {
@@ -409,8 +474,9 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
                                                            unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
   extern __shared__ float4 srec[];
-  float4* sbox = srec + (size_t)a.batch * kRecF4;
-  uint32_t* sid = reinterpret_cast<uint32_t*>(sbox + a.batch);
+  const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
+                     srec + (size_t)a.batch * (kLdsRec + 2)};
+  uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * (kLdsRec + 3));
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
@@ -425,7 +491,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
   const bool inside = px < cam.width && py < cam.height;
   const float fpx = (float)px, fpy = (float)py;
-  const float bx0 = (float)wx0, bx1 = (float)(wx0 + 7), by0 = (float)wy0, by1 = (float)(wy0 + 7);
+  const float bx0 = (float)wx0, by0 = (float)wy0;
   const int HW = cam.width * cam.height;
   const int p = py * cam.width + px;
   int my_last = 0;
@@ -458,6 +524,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   int blast = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) blast = max(blast, s_wmax[w]);
+  prioritise(blast);
 
   for (int bend = blast; bend > 0; bend -= a.batch) {
     const int bstart = max(0, bend - a.batch);
@@ -467,18 +534,16 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
       const int j = k / kRecF4, f = k - j * kRecF4;
       const uint32_t id = a.pval[start + bstart + j];
       const float4 v = a.rec[(size_t)id * kRecF4 + f];
-      srec[k] = v;
-      if (f == 0) {
-        sbox[j] = v;
-        sid[j] = id;
-      }
+      if (f < kLdsRec) srec[j * kLdsRec + f] = v;
+      stage_cull(cull, j, f, v);
+      if (f == 0) sid[j] = id;
     }
     __syncthreads();
     // chunks of 64 from the back; within a chunk the overlapping entries below the
     // wave's last position, highest first, two per step
     for (int c1 = nb; c1 > 0; c1 -= 64) {
       const int c0 = max(0, c1 - 64);
-      uint64_t m = overlap_mask(sbox, c0, c1, lane, bx0, bx1, by0, by1, bstart, wlast);
+      uint64_t m = overlap_mask(cull, c0, c1, lane, bx0, by0, a.filter, bstart, wlast);
       while (m != 0ull) {
         const int b1 = 63 - __builtin_clzll(m);
         m &= ~(1ull << b1);
@@ -522,9 +587,206 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   }
 }
 
+// Tracking: the forward blend, the tracking loss and the pose-only gradient in one
+// walk of each tile's list.  For pixel loss gradients g_ch (known only once the
+// pixel is composited) the pose gradient of eq:derivatives is
+//   sum_ch g_ch A_ch + g_D G_D,  A_ch = sum_i v_i,ch (T_i J_i - w_i Q_<i),
+//   Q_<i = sum_{j<i} J_j / (1 - alpha_j),  G_D = sum_i w_i K_i,
+// where v_i are the colours and the depth of composited entry i, w_i = alpha_i T_i,
+// J_i = dalpha_i/dtau (zero when the opacity clamp is active) and K_i = dd_i/dtau,
+// both rank-one pair terms [V; X x V] as in the backward kernel.  This is the
+// back-to-front recurrence dL/dalpha_i = T_i sum_ch g_ch (v_i,ch - B_i,ch) with the
+// colour behind i, T_{i+1} B_i = sum_{j>i} w_j v_j, regrouped by j: every term is
+// accumulated front to back, and no total is subtracted from a prefix.
+template <int TW, int TH, bool PROF>
+__global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsigned long long* __restrict__ work) {
+  constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
+  extern __shared__ float4 srec[];
+  const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
+                     srec + (size_t)a.batch * (kLdsRec + 2)};
+  __shared__ float s_red[NW][7];
+  const int tile = blockIdx.x;
+  const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
+  const CamF cam = V.cam;
+  const int lt = tile - V.tile_base;
+  const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int wx0 = tx * TW + (wave % WX) * 8, wy0 = ty * TH + (wave / WX) * 8;
+  const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+  const bool inside = px < cam.width && py < cam.height;
+  const float fpx = (float)px, fpy = (float)py;
+  const float bx0 = (float)wx0, by0 = (float)wy0;
+  const float xh = (fpx - cam.cx) / cam.fx, yh = (fpy - cam.cy) / cam.fy;
+  const uint2 rg = a.ranges[tile];
+  const int start = (int)rg.x, end = (int)rg.y;
+  prioritise(end - start);
+  FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
+  float Q[6], Ar[6], Ag[6], Ab[6], AD[6], GD[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Q[k] = Ar[k] = Ag[k] = Ab[k] = AD[k] = GD[k] = 0.f;
+  int n_eval = 0, n_cov = 0;
+  // one composited entry: the forward blend and the gradient terms
+  auto step = [&](int code, const Hit& h, const Rec& r) {
+    if (s.done || code != 2) return;
+    const float al = h.alpha;
+    const float Tn = s.T * (1.0f - al);
+    if (Tn < kTMin) {
+      s.done = true;
+      return;
+    }
+    const float T = s.T, w = al * T;
+    const float m0 = r.g3.y, m1 = r.g3.z, m2 = r.g3.w;
+    // V = dLdrho V_rho + g_d V_d for the pair (see the backward kernel)
+    float Vr[3], Vd[3], X[3];
+    if (h.b3d) {
+      const float hu0 = fmaf(-h.dx, m0, r.g2.y), hu1 = fmaf(-h.dx, m1, r.g2.z);
+      const float hv0 = fmaf(-h.dy, m0, r.g2.w), hv1 = fmaf(-h.dy, m1, r.g3.x);
+      // gradient to (u, v): 2 (u, v) per unit dLdrho, (m0, m1) per unit g_d
+      const float ru0 = 2.0f * h.u * h.rq, rv0 = 2.0f * h.v * h.rq;
+      const float du0 = m0 * h.rq, dv0 = m1 * h.rq;
+      Vr[0] = cam.fx * (hv0 * rv0 - hv1 * ru0);
+      Vr[1] = cam.fy * (ru0 * hu1 - rv0 * hu0);
+      Vr[2] = -xh * Vr[0] - yh * Vr[1];
+      Vd[0] = cam.fx * (hv0 * dv0 - hv1 * du0);
+      Vd[1] = cam.fy * (du0 * hu1 - dv0 * hu0);
+      Vd[2] = 1.0f - xh * Vd[0] - yh * Vd[1];
+      X[0] = h.d * xh;
+      X[1] = h.d * yh;
+      X[2] = h.d;
+    } else {
+      const float im2 = 1.0f / m2;
+      const float xc = ((r.ox + r.g1.x) - cam.cx) / cam.fx, yc = ((r.oy + r.g1.y) - cam.cy) / cam.fy;
+      Vr[0] = cam.fx * (-2.0f * kFilterScale * h.dx) * im2;
+      Vr[1] = cam.fy * (-2.0f * kFilterScale * h.dy) * im2;
+      Vr[2] = -xc * Vr[0] - yc * Vr[1];
+      Vd[0] = 0.f;
+      Vd[1] = 0.f;
+      Vd[2] = 1.0f;
+      X[0] = m2 * xc;
+      X[1] = m2 * yc;
+      X[2] = m2;
+    }
+    // J = dalpha/dtau = dLdrho-direction times drho/dalpha = -G o / 2 (unclamped)
+    const float jc = h.clamped ? 0.f : -0.5f * h.G * r.c4.x;
+    float J[6], K[6];
+    J[0] = jc * Vr[0];
+    J[1] = jc * Vr[1];
+    J[2] = jc * Vr[2];
+    J[3] = jc * (X[1] * Vr[2] - X[2] * Vr[1]);
+    J[4] = jc * (X[2] * Vr[0] - X[0] * Vr[2]);
+    J[5] = jc * (X[0] * Vr[1] - X[1] * Vr[0]);
+    K[0] = Vd[0];
+    K[1] = Vd[1];
+    K[2] = Vd[2];
+    K[3] = X[1] * Vd[2] - X[2] * Vd[1];
+    K[4] = X[2] * Vd[0] - X[0] * Vd[2];
+    K[5] = X[0] * Vd[1] - X[1] * Vd[0];
+    const float ia = __builtin_amdgcn_rcpf(1.0f - al);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float U = fmaf(T, J[k], -w * Q[k]);
+      Ar[k] = fmaf(r.c4.y, U, Ar[k]);
+      Ag[k] = fmaf(r.c4.z, U, Ag[k]);
+      Ab[k] = fmaf(r.c4.w, U, Ab[k]);
+      AD[k] = fmaf(h.d, U, AD[k]);
+      GD[k] = fmaf(w, K[k], GD[k]);
+      Q[k] = fmaf(J[k], ia, Q[k]);
+    }
+    s.cr = fmaf(w, r.c4.y, s.cr);
+    s.cg = fmaf(w, r.c4.z, s.cg);
+    s.cb = fmaf(w, r.c4.w, s.cb);
+    s.cd = fmaf(w, h.d, s.cd);
+    s.n0 = fmaf(w, r.nv.x, s.n0);
+    s.n1 = fmaf(w, r.nv.y, s.n1);
+    s.n2 = fmaf(w, r.nv.z, s.n2);
+    s.co += w;
+    s.T = Tn;
+  };
+  for (int b0 = start; b0 < end; b0 += a.batch) {
+    if (__syncthreads_count(!s.done) == 0) break;
+    const int nb = min(a.batch, end - b0);
+    for (int k = t; k < nb * kRecF4; k += NT) {
+      const int j = k / kRecF4, f = k - j * kRecF4;
+      const float4 v = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
+      if (f < kLdsRec) srec[j * kLdsRec + f] = v;
+      stage_cull(cull, j, f, v);
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < nb; c0 += 64) {
+      if (__ballot(!s.done) == 0ull) break;
+      uint64_t m = overlap_mask(cull, c0, nb, lane, bx0, by0, a.filter, 0, nb);
+      while (m != 0ull) {
+        const int j1 = c0 + __builtin_ctzll(m);
+        m &= m - 1ull;
+        const bool two = m != 0ull;
+        const int j2 = two ? c0 + __builtin_ctzll(m) : j1;
+        if (two) m &= m - 1ull;
+        if (!s.done) {
+          const Rec r1 = load_rec(srec, j1), r2 = load_rec(srec, j2);
+          Hit h1, h2;
+          const int k1 = evaluate(fpx, fpy, r1.ox, r1.oy, r1.g1, r1.g2, r1.g3, r1.c4.x, a.z_near, a.filter, h1);
+          const int k2 = evaluate(fpx, fpy, r2.ox, r2.oy, r2.g1, r2.g2, r2.g3, r2.c4.x, a.z_near, a.filter, h2);
+          if (PROF) {
+            n_eval += 1;
+            n_cov += k1 > 0;
+          }
+          step(k1, h1, r1);
+          if (two && !s.done) {
+            if (PROF) {
+              n_eval += 1;
+              n_cov += k2 > 0;
+            }
+            step(k2, h2, r2);
+          }
+        }
+        if (__ballot(!s.done) == 0ull) break;
+      }
+    }
+  }
+  if (PROF) add_work(work, lane, n_eval, n_cov);
+  // the pixel's tracking loss (eq:tracking_loss with the masks of eq:normal_mask
+  // and eq:opacity_mask) and its gradient to the rendered colour and depth
+  const int HW = cam.width * cam.height;
+  const int p = py * cam.width + px;
+  float l = 0.f, pg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (inside) {
+    bool mk = true;
+    if (a.use_masks) {
+      const float ndr = fmaf(s.n0, xh, fmaf(s.n1, yh, s.n2));
+      mk = (ndr > 0.0f) && (s.co > kOpacityMask);
+    }
+    if (mk) {
+      const float inv = 1.0f / (float)HW;
+      const float d0 = s.cr - V.tgt_rgb[p];
+      const float d1 = s.cg - V.tgt_rgb[HW + p];
+      const float d2 = s.cb - V.tgt_rgb[2 * HW + p];
+      const float dd = s.cd - V.tgt_depth[p];
+      auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
+      l = fabsf(d0) + fabsf(d1) + fabsf(d2) + a.lambda_d * fabsf(dd);
+      const float gr = sgn(d0) * inv, gg = sgn(d1) * inv, gb = sgn(d2) * inv, gd = a.lambda_d * sgn(dd) * inv;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pg[k] = gr * Ar[k] + gg * Ag[k] + gb * Ab[k] + gd * (AD[k] + GD[k]);
+    }
+  }
+  // tile sums: pose gradient in slots 0-5, loss in slot 6
+  float v7[7] = {pg[0], pg[1], pg[2], pg[3], pg[4], pg[5], l};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const float sum = wave_sum(v7[k]);
+    if (lane == 0) s_red[wave][k] = sum;
+  }
+  __syncthreads();
+  if (t < 7) {
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += s_red[w][t];
+    a.loss_part[(size_t)tile * 8 + t] = sum;
+  }
+}
+
 template <int TW, int TH>
 void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * (kRecF4 + 1) * sizeof(float4);
+  const size_t lds = (size_t)a.batch * (kLdsRec + 3) * sizeof(float4);
   if (work)
     blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
   else
@@ -534,7 +796,7 @@ void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long
 template <int TW, int TH, bool PO, bool HN, bool HO>
 void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, float* gacc, float* part,
                  unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * ((kRecF4 + 1) * sizeof(float4) + sizeof(uint32_t));
+  const size_t lds = (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + sizeof(uint32_t));
   if (work)
     blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
   else
@@ -569,6 +831,22 @@ void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* t_final
   else if (tile_w == 16 && tile_h == 8) fwd_shape<16, 8>(a, t_final, last, work, s);
   else if (tile_w == 32 && tile_h == 16) fwd_shape<32, 16>(a, t_final, last, work, s);
   else fwd_shape<16, 16>(a, t_final, last, work, s);
+}
+
+template <int TW, int TH>
+void track_shape(const BlendArgs& a, unsigned long long* work, hipStream_t s) {
+  const size_t lds = (size_t)a.batch * (kLdsRec + 3) * sizeof(float4);
+  if (work)
+    blend_track_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, work);
+  else
+    blend_track_kernel<TW, TH, false><<<a.n_tiles, TW * TH, lds, s>>>(a, work);
+}
+
+void launch_blend_track(const BlendArgs& a, int tile_w, int tile_h, unsigned long long* work, hipStream_t s) {
+  if (tile_w == 8 && tile_h == 8) track_shape<8, 8>(a, work, s);
+  else if (tile_w == 16 && tile_h == 8) track_shape<16, 8>(a, work, s);
+  else if (tile_w == 32 && tile_h == 16) track_shape<32, 16>(a, work, s);
+  else track_shape<16, 16>(a, work, s);
 }
 
 void launch_blend_bwd(const BlendArgs& a, int tile_w, int tile_h, const float* t_final, const uint32_t* last,

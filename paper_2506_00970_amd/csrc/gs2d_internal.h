@@ -18,19 +18,21 @@ constexpr float kTMin = 1e-4f;            // stop before transmittance drops bel
 constexpr float kFilterScale = 2.0f;      // low-pass term 2 |p - c|^2 (sigma^2 = 1/2 px^2)
 constexpr float kOpacityMask = 0.95f;     // tracking-loss opacity mask threshold
 
-// Per-surfel blend record: 6 float4 = 96 bytes, written by the preprocess kernel
+// Per-surfel blend record: 7 float4 = 112 bytes, written by the preprocess kernel
 // and staged through LDS by the blend kernels.
 //   [0] footprint box x0, x1, y0, y1 (inclusive integer pixel bounds, not clipped to
 //       the image; wave culling, and the origin of the centre below)
 //   [1] cx - x0, cy - y0, Dt, k0      [2] k1, P0, P1, Q0      [3] Q1, m0, m1, m2
-//   [4] opacity, r, g, b    [5] n.xyz, 0
+//   [4] opacity, r, g, b    [5] n.xyz, Syy
+//   [6] ex - x0, ey - y0, Sxx, Sxy: the 3-sigma ellipse (centre e, extent sqrt(d^T S d)
+//       along a unit direction d), for the waves' separating-direction cull
 // With M = K [s_u t_uc | s_v t_vc | mu_c] (rows M0, M1, M2 = m) and the projected
 // centre c = (M02, M12) / m2, the record holds the centre-relative rows
 // P = M0 - cx m, Q = M1 - cy m (whose third entries vanish), and
 // Dt = P0 Q1 - P1 Q0, k0 = m0 Q1 - m1 Q0, k1 = P0 m1 - P1 m0, so that for a
 // pixel at offset (dx, dy) from c the homogeneous intersection h_u x h_v is
 // (m2 (Q1 dx - P1 dy), m2 (P0 dy - Q0 dx), Dt - k0 dx - k1 dy).
-constexpr int kRecF4 = 6;
+constexpr int kRecF4 = 7;
 constexpr int kMaxViews = GS2D_MAX_VIEWS;
 
 struct CamF {
@@ -77,6 +79,7 @@ struct Ctrl {            // device-resident counters and tracking state
   double loss[kMaxViews];
   double adam_m[kMaxViews][6];
   double adam_v[kMaxViews][6];
+  double last_grad[kMaxViews][6];  // each view's pose gradient of the last tracking step
   double adam_b1t[kMaxViews];   // beta1^t, beta2^t of each view's AdamW step
   double adam_b2t[kMaxViews];
   double master_pose[kMaxViews][12];
@@ -84,7 +87,7 @@ struct Ctrl {            // device-resident counters and tracking state
 
 // Kernel families timed by the profiler.
 enum Family { kPre, kDepthSort, kScan, kDup, kTileSort, kRanges, kBlendFwd, kLoss, kBlendBwd, kPreBwd, kPose,
-              kReduce, kNumFamilies };
+              kReduce, kBlendTrack, kNumFamilies };
 
 // Host copy of a launch's view table.
 struct ViewSet {
@@ -238,6 +241,10 @@ struct BlendArgs {
   float lambda_d = 0.f;
   int use_masks = 0;
 };
+// Tracking: forward blend, tracking loss and pose-only gradient in one walk; needs
+// a.loss_part (tile rows: pose gradient in slots 0-5, loss in slot 6), lambda_d,
+// use_masks, and views with targets.  work: the forward's profile counters.
+void launch_blend_track(const BlendArgs& a, int tile_w, int tile_h, unsigned long long* work, hipStream_t s);
 // work (may be null): profile counters, see Ctrl::work
 void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* t_final, uint32_t* last,
                       unsigned long long* work, hipStream_t s);

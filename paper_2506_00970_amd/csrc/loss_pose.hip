@@ -208,6 +208,8 @@ __global__ __launch_bounds__(256) void pose_step_kernel(const ViewDesc* __restri
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
   const double loss = (sh[6][0] + sh[6][1] + sh[6][2] + sh[6][3]) / (double)HW;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ctrl->last_grad[v][k] = g[k];
   const uint32_t it = ctrl->iter_v[v];
   float* pose_history = ctrl->pose_history;
   float* loss_history = ctrl->loss_history;

@@ -92,15 +92,24 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
   uint32_t cnt = 0;
   uint2 rc = make_uint2(1u, 0u);
   double bx0 = 0, bx1 = -1, by0 = 0, by1 = -1, ux0 = 0, ux1 = -1, uy0 = 0, uy1 = -1;
+  double ecx = 0, ecy = 0, sxx = 0, sxy = 0, syy = 0;  // the 3-sigma ellipse: centre, support matrix
   if (vis) {
     // dual conic entries needed for the box: C00, C11, C02, C12 (and C22)
     const double c00 = 9.0 * (M0[0] * M0[0] + M0[1] * M0[1]) - M0[2] * M0[2];
     const double c11 = 9.0 * (M1[0] * M1[0] + M1[1] * M1[1]) - M1[2] * M1[2];
     const double c02 = 9.0 * (M0[0] * m[0] + M0[1] * m[1]) - M0[2] * m[2];
     const double c12 = 9.0 * (M1[0] * m[0] + M1[1] * m[1]) - M1[2] * m[2];
+    const double c01 = 9.0 * (M0[0] * M1[0] + M0[1] * M1[1]) - M0[2] * M1[2];
     const double ex = c02 / c22, ey = c12 / c22;
-    const double hx = sqrt(fmax(0.0, ex * ex - c00 / c22));
-    const double hy = sqrt(fmax(0.0, ey * ey - c11 / c22));
+    // the ellipse's extent along a unit direction d is sqrt(d^T S d) about its centre,
+    // S = e e^T - C*[0:2, 0:2] / C*22 (its tangent lines l satisfy l^T C* l = 0)
+    ecx = ex;
+    ecy = ey;
+    sxx = ex * ex - c00 / c22;
+    sxy = ex * ey - c01 / c22;
+    syy = ey * ey - c11 / c22;
+    const double hx = sqrt(fmax(0.0, sxx));
+    const double hy = sqrt(fmax(0.0, syy));
     double x0 = ex - hx, x1 = ex + hx, y0 = ey - hy, y1 = ey + hy;
     if (filter) {
       const double pcx = M0[2] / m[2], pcy = M1[2] / m[2];
@@ -153,7 +162,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
   r[3] = make_float4((float)Q1, (float)m[0], (float)m[1], (float)m[2]);
   r[4] = make_float4(P[(size_t)11 * n + i], P[(size_t)12 * n + i], P[(size_t)13 * n + i],
                      P[(size_t)14 * n + i]);
-  r[5] = make_float4((float)nn[0], (float)nn[1], (float)nn[2], 0.0f);
+  r[5] = make_float4((float)nn[0], (float)nn[1], (float)nn[2], (float)syy);
+  r[6] = make_float4((float)(ecx - ux0), (float)(ecy - uy0), (float)sxx, (float)sxy);
 }
 
 __device__ inline void cross3(const float* a, const float* b, float* o) {

@@ -444,6 +444,45 @@ void gemm(const Op& op, int M, int N, int K, int splits, hipStream_t s) {
   gemm_kernel<Op><<<grid, kThreads, 0, s>>>(op, M, N, K, ks);
 }
 
+// A forward layer with few output tiles (small batches) and a long reduction: each
+// split-K slice writes FP32 partial sums, and a second kernel adds them in slice
+// order and applies the layer's own epilogue (bias, ReLU, rounding) to the total.
+template <class Op>
+struct SplitPart {
+  Op op;
+  float* part;
+  int M, N;
+  __device__ void a8(int m, int k, int ke, uint16_t* o) const { op.a8(m, k, ke, o); }
+  __device__ void b8(int k, int n, int ke, uint16_t* o) const { op.b8(k, n, ke, o); }
+  __device__ void store(int m, int n, float v) const { part[((size_t)blockIdx.z * M + m) * N + n] = v; }
+};
+
+template <class Op>
+__global__ void split_finish_kernel(Op op, const float* __restrict__ part, int S, int M, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * N) return;
+  float v = 0.f;
+  for (int z = 0; z < S; ++z) v += part[(size_t)z * M * N + i];
+  op.store(i / N, i - (i / N) * N, v);
+}
+
+template <class Op>
+void gemm_fwd(const Op& op, int M, int N, int K, float* part, int64_t part_cap, hipStream_t s) {
+  const int tiles = ((N + kBN - 1) / kBN) * ((M + kBM - 1) / kBM);
+  int S = 1;
+  if (tiles < 64 && K >= 256) {
+    S = K / 128;
+    const int want = (128 + tiles - 1) / tiles;  // about 128 workgroups in all
+    S = S < want ? S : want;
+  }
+  if (S > 1 && (int64_t)S * M * N <= part_cap) {
+    gemm(SplitPart<Op>{op, part, M, N}, M, N, K, S, s);
+    split_finish_kernel<Op><<<(M * N + 255) / 256, 256, 0, s>>>(op, part, S, M, N);
+  } else {
+    gemm(op, M, N, K, 1, s);
+  }
+}
+
 int splits_for(int64_t K) {  // split-K slices of about 2048 reduction steps
   int64_t s = (K + 2047) / 2048;
   return (int)(s < 1 ? 1 : (s > 512 ? 512 : s));
@@ -541,17 +580,19 @@ void forward_layers(gs2d_ws* net, int B, hipStream_t s) {
     const uint16_t* w = net->wb + net->w_off[li];
     const float* b = net->theta + net->b_off[li];
     if (cs.k == 5)
-      gemm(ConvFwd<5>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 25, 1, s);
+      gemm_fwd(ConvFwd<5>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 25,
+               net->part, net->part_cap, s);
     else
-      gemm(ConvFwd<3>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 9, 1, s);
+      gemm_fwd(ConvFwd<3>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 9,
+               net->part, net->part_cap, s);
   }
   {
     FcFwd op{2560, 256, net->wb + net->w_off[4], net->theta + net->b_off[4], net->act[4], net->act[5], nullptr};
-    gemm(op, 256, B, 2560, 1, s);
+    gemm_fwd(op, 256, B, 2560, net->part, net->part_cap, s);
   }
   {
     FcFwd op{256, 6, net->wb + net->w_off[5], net->theta + net->b_off[5], net->act[5], nullptr, net->out};
-    gemm(op, 6, B, 256, 1, s);
+    gemm_fwd(op, 6, B, 256, net->part, net->part_cap, s);
   }
 }
 

@@ -28,7 +28,7 @@ def test_error_strings(lib):
 def test_default_options(lib):
     o = _lib.Options()
     assert lib.gs2d_default_options(ctypes.byref(o)) == 0
-    assert (o.tile_w, o.tile_h, o.batch, o.filter) == (16, 16, 256, 1)
+    assert (o.tile_w, o.tile_h, o.batch, o.filter) == (16, 16, 128, 1)
     assert o.z_near == pytest.approx(0.2)
     assert lib.gs2d_default_options(None) == _lib.ERR_INVALID_ARG
 

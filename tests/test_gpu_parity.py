@@ -143,13 +143,14 @@ def test_gpu_backward_parity_room_pose(gs):
     room, pose = room_scene(300_000, seed=0, cam_seed=0)
     start = synth.perturb_pose(pose, 0.05, 3.0, seed=1)
     r = gs.Rasterizer()
-    _, tgt = _render(r, room.params, ROOM_CAM, pose)
-    out, img = _render(r, room.params, ROOM_CAM, start)
-    L, d_rgb, d_depth, m = oloss.tracking_loss(img["rgb"], img["depth"], img["normal"], img["alpha"], tgt["rgb"],
+    # the image gradients of the tracking loss, from the oracle's own renders
+    ref = oracle.render(room.params, ROOM_CAM, start)
+    tgt = oracle.render(room.params, ROOM_CAM, pose)
+    L, d_rgb, d_depth, m = oloss.tracking_loss(ref["rgb"], ref["depth"], ref["normal"], ref["alpha"], tgt["rgb"],
                                                tgt["depth"], ROOM_CAM)
     grads = {"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": None, "d_alpha": None}
+    out, _ = _render(r, room.params, ROOM_CAM, start)
     _, dpose = _gpu_backward(r, out.generation, grads, params_grad=False)
-    ref = oracle.render(room.params, ROOM_CAM, start)
     og = oracle.backward(room.params, ROOM_CAM, start, **grads)
     # pixels near a decision change a few pair terms; the summed pose gradient stays within 1e-3
     check_pose(dpose, og["pose_paper"], rel=1e-3, floor=1e-4)
@@ -198,6 +199,30 @@ def test_gpu_sort_bit_exact(gs):
         kk = per[seg].astype(np.int64) * (1 << 32) + seg
         assert np.all(np.diff(kk) > 0)
         assert np.all(keys[a:b] == t)
+
+
+def test_gpu_track_gradient_matches_oracle(gs):
+    """The tracking loop's fused walk (forward blend, tracking loss and pose gradient in
+    one pass) against the oracle's pose gradient of the tracking loss at the start pose.
+    Each side forms the loss from its own render and target, so only pixels whose
+    residual is within rendering noise of zero can differ in sign."""
+    room, pose = room_scene(300_000, seed=0, cam_seed=0)
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=1)
+    r = gs.Rasterizer()
+    P = dev(room.params)
+    t = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = t.rgb.clone(), t.depth.clone()
+    ref = oracle.render(room.params, ROOM_CAM, start)
+    tgt = oracle.render(room.params, ROOM_CAM, pose)
+    L, d_rgb, d_depth, _ = oloss.tracking_loss(ref["rgb"], ref["depth"], ref["normal"], ref["alpha"], tgt["rgb"],
+                                               tgt["depth"], ROOM_CAM)
+    og = oracle.backward(room.params, ROOM_CAM, start, d_rgb=d_rgb, d_depth=d_depth)
+    for graph in (False, True):
+        p = dev(start.reshape(12))
+        r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=1, use_graph=graph)
+        g = r.debug("track_grad").reshape(-1, 6)[0]
+        print("fused tracking gradient", g, "oracle", og["pose_paper"])
+        check_pose(g, og["pose_paper"], rel=1e-3, floor=1e-4)
 
 
 @pytest.mark.parametrize("tile,batch", [((8, 8), 64), ((16, 8), 128), ((32, 16), 32), ((16, 16), 256)])
