@@ -200,9 +200,9 @@ GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float
                                   hipStream_t stream);
 
 /* Batched forward render of n_views (1..GS2D_MAX_VIEWS) views in one launch per
- * kernel: one depth sort over every (view, surfel) item, pairs keyed by a global
- * tile index that places each view's tiles after the previous view's, one tile
- * sort, and one blend grid over all tiles of all views.  Each view's images equal
+ * kernel: pairs of every (view, surfel) item keyed by a global tile index that
+ * places each view's tiles after the previous view's, one tile sort, one depth
+ * order of every tile's list, and one blend grid over all tiles of all views.  Each view's images equal
  * what gs2d_render gives for that view alone, bit for bit. */
 GS2D_API int gs2d_render_batch(gs2d_ctx* ctx, const gs2d_view* views, int32_t n_views, uint32_t* generation,
                                hipStream_t stream);
@@ -276,14 +276,14 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
 GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream);
 
 /* Copy an internal buffer of the last render to host memory (diagnostics and tests).
- * which: 0 sorted tile keys (uint32 [n_pairs]), 1 sorted surfel ids (uint32 [n_pairs]),
- * 2 tile ranges (uint32 [n_tiles][2]), 3 depth-sorted keys of the surfels that touch a
- * tile (uint32 [n_visible], ascending float32 camera depth bits; ids in 9),
- * 4 per-surfel tile rect (uint16 [n][4]: x0, x1, y0, y1, inclusive; empty: x0 > x1),
- * 5 per-pixel final transmittance (float [H][W]), 6 per-pixel list length (uint32 [H][W]),
- * 7 unsorted tile keys, 8 unsorted surfel ids (uint32 [n_pairs], before the tile sort;
- * only with options.keep_unsorted = 1), 9 depth-sorted surfel ids (uint32 [n_visible]),
- * 10 the pose gradient of each problem's last tracking iteration (double [32][6];
+ * which: 0 sorted tile keys (uint32 [n_pairs]), 1 the tiles' surfel ids (uint32 [n_pairs];
+ * within each tile ascending in (depth key, id)), 2 tile ranges (uint32 [n_tiles][2]),
+ * 3 per-surfel depth keys (uint32 [n]: float32 camera depth bits, 0xFFFFFFFF for
+ * surfels that touch no tile), 4 per-surfel tile rect (uint16 [n][4]: x0, x1, y0, y1,
+ * inclusive; empty: x0 > x1), 5 per-pixel final transmittance (float [H][W]),
+ * 6 per-pixel list length (uint32 [H][W]), 7 unsorted tile keys, 8 unsorted surfel ids
+ * (uint32 [n_pairs], emitted in surfel order before the tile sort; only with
+ * options.keep_unsorted = 1), 10 the pose gradient of each problem's last tracking iteration (double [32][6];
  * available after gs2d_track / gs2d_track_batch, without a forward).
  * *bytes (host) is the buffer size in; the bytes copied out.  Synchronises `stream`. */
 GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes,

@@ -56,7 +56,7 @@ int realloc_dev(gs2d_ctx* ctx, T** p, int64_t count) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-const char* kFamilyNames[kNumFamilies] = {"preprocess", "depth_sort", "scan",     "duplicate",
+const char* kFamilyNames[kNumFamilies] = {"preprocess", "depth_order", "count_scan", "duplicate",
                                           "tile_sort",  "ranges",     "blend_fwd", "loss",
                                           "blend_bwd",  "preprocess_bwd", "pose_step", "reduce",
                                           "blend_track"};
@@ -116,12 +116,27 @@ int stream_capturing(hipStream_t s, bool* cap) {
 
 int ensure_hist(gs2d_ctx* ctx) {
   const int64_t items = ctx->n_cap > ctx->p_cap ? ctx->n_cap : ctx->p_cap;
-  // digit-major rows of every block plus the row totals, for up to 2048 digits
-  const int64_t need = ((items + kScanItems - 1) / kScanItems + 1) * (1 << kMaxDigitBits);
-  if (need <= ctx->hist_cap) return GS2D_OK;
+  // two planes of 2048 digit rows by one column per block, plus the row totals
+  const int64_t stride = (items + kScanItems - 1) / kScanItems > 0 ? (items + kScanItems - 1) / kScanItems : 1;
+  if (stride <= ctx->hist_stride) return GS2D_OK;
+  const int64_t need = 2 * stride * (1 << kMaxDigitBits) + (1 << kMaxDigitBits);
   GS2D_TRY(realloc_dev(ctx, &ctx->hist, need));
   ctx->hist_cap = need;
+  ctx->hist_stride = (int)stride;
+  ctx->hist_fresh = true;  // cleared on the stream before its first use
   return GS2D_OK;
+}
+
+SortPlanes sort_planes(gs2d_ctx* ctx) {
+  const size_t plane = (size_t)ctx->hist_stride << kMaxDigitBits;
+  return SortPlanes{{ctx->hist, ctx->hist + plane}, ctx->hist_stride, ctx->hist + 2 * plane};
+}
+
+// The sort planes must be all zero before a render; fresh allocations are cleared here.
+void clear_fresh_hist(gs2d_ctx* ctx, hipStream_t s) {
+  if (!ctx->hist_fresh) return;
+  launch_fill_u32(ctx->hist, 0u, ctx->hist_cap, s);
+  ctx->hist_fresh = false;
 }
 
 int ensure_surfels(gs2d_ctx* ctx, int64_t n) {
@@ -130,12 +145,8 @@ int ensure_surfels(gs2d_ctx* ctx, int64_t n) {
   GS2D_TRY(realloc_dev(ctx, &ctx->rec, cap * kRecF4));
   GS2D_TRY(realloc_dev(ctx, &ctx->rect, cap));
   GS2D_TRY(realloc_dev(ctx, &ctx->count, cap));
-  for (int k = 0; k < 2; ++k) {
-    GS2D_TRY(realloc_dev(ctx, &ctx->dkey[k], cap));
-    GS2D_TRY(realloc_dev(ctx, &ctx->dval[k], cap));
-  }
-  GS2D_TRY(realloc_dev(ctx, &ctx->offs, cap));
-  GS2D_TRY(realloc_dev(ctx, &ctx->block_sums, cap / kScanItems + 1));
+  GS2D_TRY(realloc_dev(ctx, &ctx->dkey, cap));
+  GS2D_TRY(realloc_dev(ctx, &ctx->parts, 2 * (cap / kPartItems + 1)));
   ctx->n_cap = cap;
   return ensure_hist(ctx);
 }
@@ -299,50 +310,64 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ranges), 0u, 2 * vs.tiles, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ctrl), 0u, 3, s);
   } else {
+    clear_fresh_hist(ctx, s);
+    SortPlanes ws = sort_planes(ctx);
+    uint32_t* part_pairs = ctx->parts;
+    uint32_t* part_vis = ctx->parts + ctx->n_cap / kPartItems + 1;
     {
       ProfScope ps(ctx, kPre, s);
       launch_preprocess(ctx->views, nv, items, ctx->opt.z_near, ctx->opt.filter, tw, th, ctx->rec, ctx->rect,
-                        ctx->count, ctx->dkey[0], ctx->dval[0], ctx->saved_pose, ctx->ctrl, s);
+                        ctx->count, ctx->dkey, ctx->saved_pose, part_pairs, part_vis, ctx->ctrl, s);
     }
-    int dbuf;
-    {
-      ProfScope ps(ctx, kDepthSort, s);
-      // the first pass keeps only the surfels that touch a tile
-      dbuf = radix_sort(ctx->dkey, ctx->dval, items, items, nullptr, 32, ctx->hist, &ctx->ctrl->n_visible, nullptr,
-                        0, nullptr, s);
-    }
-    ctx->depth_buf = dbuf;
-    {
+    const bool scanned = part_scan_needed(items);
+    if (scanned) {
       ProfScope ps(ctx, kScan, s);
-      launch_scan_counts(ctx->count, ctx->dval[dbuf], &ctx->ctrl->n_visible, (int)items, ctx->offs, ctx->block_sums,
-                         ctx->ctrl, s);
+      launch_part_scan(part_pairs, part_vis, items, ctx->ctrl, s);
     }
+    // pairs in item order; a tile sort of one pass (up to 2048 tiles) writes the tile
+    // ranges itself
+    const int tbits = tile_bits((int)vs.tiles);
+    const bool fused_ranges = tbits <= kMaxDigitBits;
+    auto duplicate = [&]() {
+      ProfScope ps(ctx, kDup, s);
+      launch_duplicate(ws, ctx->count, part_pairs, part_vis, scanned, ctx->rect, ctx->views, nv, items, ctx->p_cap,
+                       tbits, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
+    };
+    duplicate();
     if (allow_sync && !capturing && !ctx->pair_fixed) {
       GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
       GS2D_HIP(ctx, hipStreamSynchronize(s));
       const int64_t np = ctx->host_ctrl->n_pairs;
-      if (np > ctx->p_cap) GS2D_TRY(ensure_pairs(ctx, np + np / 4));
-    }
-    {
-      ProfScope ps(ctx, kDup, s);
-      launch_duplicate(ctx->dval[dbuf], ctx->count, ctx->offs, ctx->rect, ctx->views, nv, &ctx->ctrl->n_visible,
-                       (int)items, ctx->p_cap, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
+      if (np > ctx->p_cap) {
+        // grow and duplicate again (the first pass counted part of its pairs into plane 1)
+        GS2D_TRY(ensure_pairs(ctx, np + np / 4));
+        if (ctx->hist_fresh) {
+          clear_fresh_hist(ctx, s);
+        } else {
+          launch_fill_u32(ctx->hist + ((size_t)ctx->hist_stride << kMaxDigitBits), 0u,
+                          (int64_t)ctx->hist_stride << kMaxDigitBits, s);
+        }
+        ws = sort_planes(ctx);
+        launch_fill_u32(&ctx->ctrl->overflow, 0u, 1, s);  // set by the first pass
+        duplicate();
+      }
     }
     if (ctx->opt.keep_unsorted && ctx->pkey_keep) {
       launch_copy_u32(ctx->pkey[0], ctx->pkey_keep, ctx->p_cap, s);
       launch_copy_u32(ctx->pval[0], ctx->pval_keep, ctx->p_cap, s);
     }
-    // a tile sort of one pass (up to 2048 tiles) writes the tile ranges itself
-    const int tbits = tile_bits((int)vs.tiles);
-    const bool fused_ranges = tbits <= kMaxDigitBits;
     {
       ProfScope ps(ctx, kTileSort, s);
-      pbuf = radix_sort(ctx->pkey, ctx->pval, ctx->p_cap, 0, &ctx->ctrl->n_pairs, tbits, ctx->hist, nullptr,
-                        fused_ranges ? ctx->ranges : nullptr, (int)vs.tiles, &ctx->ctrl->overflow, s);
+      pbuf = tile_sort(ws, ctx->pkey, ctx->pval, ctx->p_cap, tbits, ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
     }
     if (!fused_ranges) {
       ProfScope ps(ctx, kRanges, s);
       launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, (int)vs.tiles, s);
+    }
+    {
+      // each tile's items, ascending on entry, stably into depth order
+      ProfScope ps(ctx, kDepthSort, s);
+      launch_tile_order(ctx->ranges, (int)vs.tiles, ctx->pval[pbuf], ctx->pval[pbuf ^ 1], ctx->dkey, s);
     }
     BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, ctx->views, nv, (int)vs.tiles, ctx->opt.z_near,
                  ctx->opt.filter, ctx->opt.batch};
@@ -533,10 +558,8 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
     ProfScope ps(ctx, kBlendTrack, s);
     launch_blend_track(ba, ctx->opt.tile_w, ctx->opt.tile_h, work_ptr(ctx, s), s);
   } else {
-    {
-      ProfScope ps(ctx, kLoss, s);
-      launch_fill_f32(ctx->part, 0.f, 8 * vs.tiles, s);
-    }
+    ProfScope ps(ctx, kLoss, s);
+    launch_fill_f32(ctx->part, 0.f, 8 * vs.tiles, s);
     launch_tracking_loss(ctx->views, vs.n_views, vs.max_hw, a->lambda_d, a->use_masks, ctx->lpart, stride, s);
   }
   {
@@ -733,9 +756,8 @@ GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
   if (!ctx) return GS2D_OK;
   (void)set_device(ctx);
   invalidate_graph(ctx);
-  void* bufs[] = {ctx->rec,       ctx->rect,     ctx->count,      ctx->dkey[0],   ctx->dkey[1],    ctx->dval[0],
-                  ctx->dval[1],   ctx->offs,     ctx->block_sums, ctx->hist,      ctx->gacc,       ctx->pkey[0],
-                  ctx->pkey[1],   ctx->pval[0],  ctx->pval[1],    ctx->pkey_keep, ctx->pval_keep,  ctx->ranges,
+  void* bufs[] = {ctx->rec,       ctx->rect,     ctx->count,      ctx->dkey,      ctx->parts,      ctx->hist,
+                  ctx->gacc,      ctx->pkey[0],  ctx->pkey[1],   ctx->pval[0],  ctx->pval[1],    ctx->pkey_keep, ctx->pval_keep,  ctx->ranges,
                   ctx->t_final,   ctx->last,     ctx->lgrad,      ctx->limg,      ctx->part,       ctx->lpart,
                   ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl};
   for (void* b : bufs)
@@ -879,13 +901,12 @@ GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_
     case 0: src = ctx->pkey[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 1: src = ctx->pval[ctx->pair_buf]; need = (size_t)np * 4; break;
     case 2: src = ctx->ranges; need = (size_t)ctx->last_views.tiles * 8; break;
-    case 3: src = ctx->dkey[ctx->depth_buf]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
+    case 3: src = ctx->dkey; need = (size_t)items * 4; break;
     case 4: src = ctx->rect; need = (size_t)items * 8; break;
     case 5: src = ctx->t_final; need = (size_t)pixels * 4; break;
     case 6: src = ctx->last; need = (size_t)pixels * 4; break;
     case 7: src = ctx->pkey_keep; need = (size_t)np * 4; break;
     case 8: src = ctx->pval_keep; need = (size_t)np * 4; break;
-    case 9: src = ctx->dval[ctx->depth_buf]; need = (size_t)(c.n_visible < items ? c.n_visible : items) * 4; break;
     default: return GS2D_ERR_INVALID_ARG;
   }
   if (!src) return GS2D_ERR_UNSUPPORTED;

@@ -128,12 +128,12 @@ struct gs2d_ctx {
   float4* rec = nullptr;
   uint2* rect = nullptr;
   uint32_t* count = nullptr;
-  uint32_t* dkey[2] = {nullptr, nullptr};
-  uint32_t* dval[2] = {nullptr, nullptr};
-  uint32_t* offs = nullptr;
-  uint32_t* block_sums = nullptr;
-  uint32_t* hist = nullptr;
+  uint32_t* dkey = nullptr;     // per-item depth keys
+  uint32_t* parts = nullptr;   // per-block pair and visible counts of preprocessing
+  uint32_t* hist = nullptr;    // the sort planes and row totals (gs2d::SortPlanes)
   int64_t hist_cap = 0;
+  int hist_stride = 0;
+  bool hist_fresh = false;     // allocated but not yet cleared on the stream
   float* gacc = nullptr;       // [items][16]
 
   // pairs [p_cap]
@@ -180,7 +180,6 @@ struct gs2d_ctx {
   uint32_t generation = 0;
   gs2d::ViewSet last_views;    // views of the last render (host copy)
   int pair_buf = 0;            // which pkey/pval holds the sorted pairs
-  int depth_buf = 0;           // which dkey/dval holds the depth-sorted visible items
   bool have_forward = false;
 };
 
@@ -188,9 +187,13 @@ namespace gs2d {
 
 // preprocess.hip
 void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s);
+constexpr int kPartItems = 256;  // items per preprocessing block (per-block pair counts)
+// Per item: record, tile rectangle, tile count and depth key (0xFFFFFFFF for items
+// that touch no tile); per block of kPartItems items: the pair count and the count of
+// items that touch a tile.  Clears ctrl->overflow.
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
-                       int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, uint32_t* dval,
-                       float* saved_pose, Ctrl* ctrl, hipStream_t s);
+                       int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, float* saved_pose,
+                       uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s);
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc, float* d_params,
                            int accumulate, float* part, hipStream_t s);
 
@@ -199,30 +202,46 @@ constexpr int kScanItems = 2048;   // items per block of the scans and radix pas
 constexpr int kMaxDigitBits = 11;  // widest radix digit (2048 bins)
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
-// Exclusive scan of count[perm[j]] over j < n into offs, the total into ctrl->n_pairs
-// (and ctrl->overflow cleared); n = *n_dev clamped to limit, or limit without n_dev.
-void launch_scan_counts(const uint32_t* count, const uint32_t* perm, const uint32_t* n_dev, int limit,
-                        uint32_t* offs, uint32_t* block_sums, Ctrl* ctrl, hipStream_t s);
-// Stable LSD radix sort of (key, value) u32 pairs over bits [0, bits) in
-// ceil(bits / 11) passes of at most 11 bits.  n is taken from *n_dev (clamped to cap)
-// when n_dev is non-null (capacity-sized grid), else n_host.  With n_kept (zero on
-// entry) the first pass drops keys equal to 0xFFFFFFFF and counts the others into
-// *n_kept, which is the item count of the later passes: the result then holds the
-// kept pairs only, in front.  With `ranges` and a single pass, the pass also writes
-// [start, end) of every key value below n_tiles (empty ranges when *overflow != 0).
-// hist holds 2048 (blocks(cap) + 1) words.  Returns the index (0 or 1) of the buffer
-// holding the result.
-int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host,
-               const uint32_t* n_dev, int bits, uint32_t* hist, uint32_t* n_kept, uint2* ranges,
-               int n_tiles, const uint32_t* overflow, hipStream_t s);
-// Pairs of the first n depth-sorted items (n = *n_dev clamped to limit).
-void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
-                      const uint2* rect, const ViewDesc* views, int n_views, const uint32_t* n_dev, int limit,
-                      int64_t p_cap, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles,
-                      hipStream_t s);
+// Digit histograms of the tile sort's passes: two digit-major planes of 2048 rows by
+// `stride` columns (one per block of kScanItems pairs) and the row totals.  Between
+// renders both planes are all zero.
+struct SortPlanes {
+  uint32_t* plane[2];
+  int stride;
+  uint32_t* dtot;
+};
+// Bits of pass p of a stable LSD sort over `bits` key bits in passes of at most 11.
+int radix_pass_bits(int bits, int p);
+// Whether `items` take the scan below (many preprocessing blocks); otherwise the
+// duplication sums the per-block counts itself.
+bool part_scan_needed(int64_t items);
+// Exclusive scan of the per-block pair counts in place, and ctrl->n_pairs / n_visible.
+void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t items, Ctrl* ctrl, hipStream_t s);
+// The (tile, item) pairs of every item, in item order, placed by the per-block pair
+// counts of preprocessing (an exclusive prefix when `scanned`; otherwise the kernel
+// also stores ctrl->n_pairs and ctrl->n_visible); sets ctrl->overflow when the pairs
+// exceed p_cap.  Fills plane 1 with the first tile pass's histogram.
+void launch_duplicate(const SortPlanes& ws, const uint32_t* count, const uint32_t* part_pairs,
+                      const uint32_t* part_vis, bool scanned, const uint2* rect, const ViewDesc* views, int n_views,
+                      int64_t items, int64_t p_cap, int tile_bits, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl,
+                      uint2* ranges, int n_tiles, hipStream_t s);
+// Stable sort of the min(n_pairs, p_cap) pairs by tile key over `bits` bits.  A single
+// pass also writes the tile ranges (empty after an overflow).  Returns the buffer index.
+int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_t p_cap, int bits, Ctrl* ctrl,
+              uint2* ranges, int n_tiles, hipStream_t s);
+// Orders every tile's items (ids[ranges[t].x .. ranges[t].y), ascending on entry) by
+// depth key, stably: each list then ascends in (depth key, item).  scratch: a buffer
+// of the same size as ids for lists longer than one workgroup's LDS.
+void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* dkey,
+                       hipStream_t s);
 void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s);
 void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s);
+
+struct AdamArgs {  // the tracking pose step's AdamW settings
+  float lr[6];
+  float beta1, beta2, eps, weight_decay;
+};
 
 // blend.hip
 struct BlendArgs {
@@ -266,10 +285,6 @@ void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, in
 // Per view: d_pose (from the view table) = sum of the rows of the view's tiles.
 void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,
                               hipStream_t s);
-struct AdamArgs {
-  float lr[6];
-  float beta1, beta2, eps, weight_decay;
-};
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,

@@ -4,7 +4,7 @@
 // camera-frame centre and tangents, the homography M = K [s_u t_uc | s_v t_vc | mu_c],
 // culling, the screen box of the 3-sigma ellipse (dual conic M diag(9,9,-1) M^T)
 // united with the low-pass disc, its tile rectangle, the float32 depth key, and the
-// 96-byte blend record.  The kernel is bound by HBM traffic (60 B in, about 110 B
+// blend record.  The kernel is bound by HBM traffic (60 B in, about 110 B
 // out per surfel), so it computes in FP64 at no cost and rounds once at the end:
 // the depth keys then agree bit for bit with a double-precision reference.
 //
@@ -33,15 +33,11 @@ __global__ void upload_views_kernel(ViewChunk c, ViewDesc* __restrict__ dst) {
   if (i < c.count) dst[c.first + i] = c.v[i];
 }
 
-__global__ __launch_bounds__(256) void preprocess_kernel(
-    const ViewDesc* __restrict__ views, int n_views, int64_t items, float z_near, int filter, int tile_w,
-    int tile_h, float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ count,
-    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval, float* __restrict__ saved_pose,
-    Ctrl* __restrict__ ctrl) {
-  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gi == 0) ctrl->n_visible = 0;  // counted by the depth sort's first pass
-  if (gi >= items) return;
-  const int item = (int)gi;
+// One item (view, surfel); returns its tile count.
+__device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, int n_views, int item, float z_near,
+                                           int filter, int tile_w, int tile_h, float4* __restrict__ rec,
+                                           uint2* __restrict__ rect, uint32_t* __restrict__ count,
+                                           uint32_t* __restrict__ dkey, float* __restrict__ saved_pose) {
   const int v = view_of_item(views, n_views, item);
   const ViewDesc& V = views[v];
   const float* __restrict__ P = V.params;
@@ -73,7 +69,6 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
     uc[r] = R[r * 3 + 0] * tu[0] + R[r * 3 + 1] * tu[1] + R[r * 3 + 2] * tu[2];
     vc[r] = R[r * 3 + 0] * tv[0] + R[r * 3 + 1] * tv[1] + R[r * 3 + 2] * tv[2];
   }
-  dval[item] = (uint32_t)item;
   const double a[3] = {su * uc[0], su * uc[1], su * uc[2]};
   const double b[3] = {sv * vc[0], sv * vc[1], sv * vc[2]};
   // homography rows: M0 = fx col.x + cx col.z, M1 = fy col.y + cy col.z, M2 = col.z
@@ -140,7 +135,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
   if (cnt == 0) {
     rect[item] = make_uint2(1u, 0u);  // x0 = 1 > x1 = 0: empty
     dkey[item] = 0xFFFFFFFFu;
-    return;
+    return 0u;
   }
   rect[item] = rc;
   dkey[item] = __float_as_uint((float)mc[2]);
@@ -164,6 +159,45 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
                      P[(size_t)14 * n + i]);
   r[5] = make_float4((float)nn[0], (float)nn[1], (float)nn[2], (float)syy);
   r[6] = make_float4((float)(ecx - ux0), (float)(ecy - uy0), (float)sxx, (float)sxy);
+  return cnt;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += (uint32_t)__shfl_xor((int)v, m, 64);
+  return v;
+}
+
+// One thread per item, kPartItems items per block; each block also stores its pair
+// count and visible-item count (the pair duplication places pairs from them).
+__global__ __launch_bounds__(kPartItems) void preprocess_kernel(
+    const ViewDesc* __restrict__ views, int n_views, int64_t items, float z_near, int filter, int tile_w,
+    int tile_h, float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ count,
+    uint32_t* __restrict__ dkey, float* __restrict__ saved_pose, uint32_t* __restrict__ part_pairs,
+    uint32_t* __restrict__ part_vis, Ctrl* __restrict__ ctrl) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t cnt = gi < items ? preprocess_item(views, n_views, (int)gi, z_near, filter, tile_w, tile_h, rec,
+                                                    rect, count, dkey, saved_pose)
+                                  : 0u;
+  __shared__ uint32_t sp[kPartItems / 64], sv[kPartItems / 64];
+  const uint32_t wp = wave_sum_u32(cnt), wv = wave_sum_u32(cnt != 0u ? 1u : 0u);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sp[wave] = wp;
+    sv[wave] = wv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t bp = 0, bv = 0;
+#pragma unroll
+    for (int w = 0; w < kPartItems / 64; ++w) {
+      bp += sp[w];
+      bv += sv[w];
+    }
+    part_pairs[blockIdx.x] = bp;
+    part_vis[blockIdx.x] = bv;
+    if (blockIdx.x == 0) ctrl->overflow = 0u;
+  }
 }
 
 __device__ inline void cross3(const float* a, const float* b, float* o) {
@@ -281,11 +315,11 @@ void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s) {
 }
 
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
-                       int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, uint32_t* dval,
-                       float* saved_pose, Ctrl* ctrl, hipStream_t s) {
-  const int grid = items > 0 ? (int)((items + 255) / 256) : 1;
-  preprocess_kernel<<<grid, 256, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec, rect, count,
-                                         dkey, dval, saved_pose, ctrl);
+                       int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, float* saved_pose,
+                       uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s) {
+  const int grid = items > 0 ? (int)((items + kPartItems - 1) / kPartItems) : 1;
+  preprocess_kernel<<<grid, kPartItems, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec, rect,
+                                                count, dkey, saved_pose, part_pairs, part_vis, ctrl);
 }
 
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc,

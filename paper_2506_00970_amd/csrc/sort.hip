@@ -1,32 +1,36 @@
-// Scans, the stable LSD radix sort, pair duplication and tile ranges.
+// Pair duplication, the tile sort, the per-tile depth order and the tile ranges.
 //
 // The paper composites surfels "sorted by depth" per pixel (Sec. "2D Gaussian
-// Splatting", eq:alpha_blending).  The tile rasterizer realises that order with
-// two stable sorts: (view, surfel) items by float32 camera depth (ties keep the
-// item order, i.e. the surfel index within a view), then the (tile, item) pairs,
-// emitted in that depth order and keyed by a global tile index (each view's tiles
-// follow the previous view's), stably by tile.  Each tile's list is therefore
-// ascending (depth, index), the order of the per-pixel definition.
+// Splatting", eq:alpha_blending).  Here every tile's list ends up ascending in
+// (float32 camera depth, item), the order of the per-pixel definition, in three steps:
+//   1. duplication  each item (view, surfel) that touches a tile emits one (tile,
+//                   item) pair per tile of its rectangle, in item order: its first
+//                   slot is the pair count of all earlier items (per-block counts
+//                   from preprocessing, plus a block scan);
+//   2. tile sort    a stable LSD radix sort of the pairs by the global tile index (each
+//                   view's tiles follow the previous view's), so that each tile's
+//                   items stay in ascending item order;
+//   3. depth order  one workgroup per tile stably sorts the tile's items by depth key;
+//                   with the items ascending on entry, ties keep item order.
+// Lists are short (a tile holds a few hundred items), so step 3 runs in LDS; longer
+// lists take the same passes through global memory.
 //
-// Radix pass (digits of up to 11 bits: 256 or 2048 bins) = three kernels over blocks
-// of kScanItems keys:
-//   hist    per-block digit histogram (LDS atomics, one sub-histogram per wave),
-//           stored digit-major: row d holds digit d's count in every block
-//   offsets one workgroup per digit: exclusive scan of that digit's row (its
-//           offset within the digit) and the row total
+// Radix pass of the tile sort (digits of up to 11 bits: 256 or 2048 bins) over blocks
+// of kScanItems keys, with a digit-major histogram plane: cell (d, b) = the keys of
+// digit d in block b.  The duplication fills the first pass's plane (and a two-pass
+// sort's first scatter fills the second's), with atomics at each key's block.  The
+// pass itself is two kernels:
+//   offsets one workgroup per digit: exclusive scan of row d over the active blocks,
+//           in place, and the row total
 //   scatter per block: the digit bases (an LDS scan of the row totals) plus the
-//           row prefix give each digit's first output slot; then 8 rounds of 256
-//           keys: a wave-level multi-split (ballots over the digit bits give each
-//           lane the mask of lanes holding the same digit), the same digit's keys
-//           in the lower waves of the round (per-wave counts in LDS, stamped with
-//           the round so that they need no clearing), and the running per-digit
-//           offset across rounds keep the pass stable.
-// 32-bit depth keys take 3 passes (11, 11, 10 bits); tile keys of up to 2048 tiles
-// take one, whose digit bases and totals are the tile ranges.
-// The depth sort's first pass also compacts: items whose key is kDropKey (surfels
-// that touch no tile) are left out of the histogram and the scatter, so the pass
-// writes only the visible items, in stable order, and counts them on the device;
-// the remaining passes and everything after them run over that count.
+//           block's column give each digit's first output slot, and the block then
+//           clears its column, so that a plane is all zero again once its pass is
+//           done; then 8 rounds of 256 keys: a wave-level multi-split (ballots over
+//           the digit bits give each lane the mask of lanes holding the same digit),
+//           the same digit's keys in the lower waves of the round (per-wave counts in
+//           LDS, stamped with the round so that they need no clearing), and the
+//           running per-digit offset across rounds keep the pass stable.
+// Up to 2048 tiles take one pass, whose digit bases and totals are the tile ranges.
 // Kernels whose item count lives on the device read it and exit early, so a
 // capacity-sized launch can be captured in a graph.
 #include "gs2d_internal.h"
@@ -37,7 +41,12 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRounds = kScanItems / kThreads;  // 8
 constexpr int kWaves = kThreads / 64;
-constexpr uint32_t kDropKey = 0xFFFFFFFFu;
+constexpr int kBlockShift = 11;  // log2(kScanItems)
+static_assert(kScanItems == 1 << kBlockShift, "block shift");
+static_assert(kPartItems == kThreads, "duplication blocks are preprocessing blocks");
+constexpr int kDirectParts = 4096;  // up to this many item blocks, each block sums the counts before it
+constexpr int kOrderMax = kScanItems;  // tile lists up to this length are ordered in LDS
+constexpr int kOrderBits = 8;          // digit of the depth order: 4 passes over 32-bit keys
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,26 +61,29 @@ __global__ void copy_u32_kernel(const uint32_t* __restrict__ src, uint32_t* __re
   if (i < n) dst[i] = src[i];
 }
 
+// Exclusive scan over the 256 threads of a block: a scan within each wave, then the
+// totals of the lower waves (sh: kWaves words of LDS).  *total = the block's sum.
+// Every thread of the block must call it.
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  // Hillis-Steele over 256 threads in LDS; sh has 256 entries.
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    uint32_t x = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
   }
-  const uint32_t incl = sh[t];
-  if (total) *total = sh[kThreads - 1];
+  if (lane == 63) sh[wave] = x;
   __syncthreads();
-  return incl - v;
-}
-
-__device__ inline uint32_t load_count(const uint32_t* count, const uint32_t* perm, int i, int n) {
-  if (i >= n) return 0u;
-  return perm ? count[perm[i]] : count[i];
+  uint32_t below = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t sw = sh[w];
+    below += w < wave ? sw : 0u;
+    all += sw;
+  }
+  __syncthreads();
+  if (total) *total = all;
+  return below + x - v;
 }
 
 // Item count of a pass: the device count clamped to the buffer capacity
@@ -82,129 +94,52 @@ __device__ inline int64_t item_count(const uint32_t* n_dev, int64_t limit) {
   return n < limit ? n : limit;
 }
 
-__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ count,
-                                                               const uint32_t* __restrict__ perm,
-                                                               const uint32_t* __restrict__ n_dev, int limit,
-                                                               uint32_t* __restrict__ block_sums) {
-  const int n = (int)item_count(n_dev, limit);
-  if ((int64_t)blockIdx.x * kScanItems >= n) return;
-  __shared__ uint32_t sh[kThreads];
-  const int base = blockIdx.x * kScanItems + threadIdx.x * kRounds;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kRounds; ++k) s += load_count(count, perm, base + k, n);
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0];
-}
-
-__global__ __launch_bounds__(kThreads) void scan_blocks_kernel(uint32_t* __restrict__ block_sums,
-                                                               const uint32_t* __restrict__ n_dev, int limit,
-                                                               Ctrl* __restrict__ ctrl) {
-  // one block: exclusive scan of the active blocks' sums, in chunks of 256
-  const int n = (int)item_count(n_dev, limit);
-  const int nb = (n + kScanItems - 1) / kScanItems;
-  __shared__ uint32_t sh[kThreads];
-  uint32_t carry = 0;
-  for (int c0 = 0; c0 < nb; c0 += kThreads) {
-    const int i = c0 + threadIdx.x;
-    const uint32_t v = i < nb ? block_sums[i] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(v, sh, &tot);
-    if (i < nb) block_sums[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    ctrl->n_pairs = carry;
-    ctrl->overflow = 0;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void scan_final_kernel(const uint32_t* __restrict__ count,
-                                                              const uint32_t* __restrict__ perm,
-                                                              const uint32_t* __restrict__ n_dev, int limit,
-                                                              const uint32_t* __restrict__ block_sums,
-                                                              uint32_t* __restrict__ offs) {
-  const int n = (int)item_count(n_dev, limit);
-  if ((int64_t)blockIdx.x * kScanItems >= n) return;
-  __shared__ uint32_t sh[kThreads];
-  const int base = blockIdx.x * kScanItems + threadIdx.x * kRounds;
-  uint32_t v[kRounds];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kRounds; ++k) {
-    v[k] = load_count(count, perm, base + k, n);
-    s += v[k];
-  }
-  uint32_t run = block_sums[blockIdx.x] + block_exclusive_scan(s, sh, nullptr);
-#pragma unroll
-  for (int k = 0; k < kRounds; ++k) {
-    if (base + k < n) offs[base + k] = run;
-    run += v[k];
-  }
-}
-
-// Radix passes take up to 11 bits: R = 256 or 2048 bins (kDigits8, kDigits11).
-constexpr int kDigits8 = 256, kDigits11 = 2048;
-
-// Per-block digit histogram, digit-major (row d = digit d's count in every block).
-// drop: leave kDropKey keys out and add the kept count to *n_kept (zero beforehand).
+// Rank of one round of up to 256 keys in a stable counting pass (every thread of the
+// block calls it).  digit: the key's digit; valid: the lane holds a key; doff[d]: the
+// next free slot of digit d (advanced here); wcnt: per-wave digit counts, stamped.
+// Returns the key's slot.
 template <int R>
-__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const uint32_t* __restrict__ keys,
-                                                              const uint32_t* __restrict__ n_dev,
-                                                              int64_t n_host, int shift, int bits, int drop,
-                                                              uint32_t* __restrict__ hist,
-                                                              uint32_t* __restrict__ n_kept) {
-  constexpr int PER = R / kThreads;  // digits per thread
-  const int64_t n = item_count(n_dev, n_host);
-  const int64_t base = (int64_t)blockIdx.x * kScanItems;
-  if (base >= n) return;
-  __shared__ uint32_t h[kWaves][R];
-  const int wave = threadIdx.x / 64;
-  const uint32_t dmask = (1u << bits) - 1u;
-  for (int k = threadIdx.x; k < kWaves * R; k += kThreads) (&h[0][0])[k] = 0u;
+__device__ inline uint32_t rank_round(uint32_t digit, bool valid, int bits, uint32_t stamp,
+                                      uint32_t (*wcnt)[R], uint32_t* doff) {
+  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < bits; ++b) {
+    const bool set = (digit >> b) & 1u;
+    const uint64_t bal = __ballot(valid && set);
+    peers &= set ? bal : ~bal;
+  }
+  const uint32_t rank = (uint32_t)__popcll(peers & lt);
+  const uint32_t cnt = (uint32_t)__popcll(peers);
+  const bool leader = valid && rank == 0;
+  if (leader) wcnt[wave][digit] = stamp | cnt;
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t i = base + r * kThreads + threadIdx.x;
-    if (i < n) {
-      const uint32_t k = keys[i];
-      if (!(drop && k == kDropKey)) atomicAdd(&h[wave][(k >> shift) & dmask], 1u);
+  // the group's first slot: the digit's running offset plus the same digit's keys
+  // in the lower waves of this round
+  uint32_t pb = 0;
+  if (leader) {
+    pb = doff[digit];
+    for (int w = 0; w < wave; ++w) {
+      const uint32_t e = wcnt[w][digit];
+      if ((e & 0xFFFF0000u) == stamp) pb += e & 0xFFFFu;
     }
   }
   __syncthreads();
-  uint32_t kept = 0;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int d = q * kThreads + threadIdx.x;
-    uint32_t s = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += h[w][d];
-    hist[(size_t)d * gridDim.x + blockIdx.x] = s;
-    kept += s;
-  }
-  if (drop) {
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) kept += __shfl_xor(kept, m, 64);
-    if ((threadIdx.x & 63) == 0 && kept) atomicAdd(n_kept, kept);
-  }
+  if (leader) atomicAdd(&doff[digit], cnt);
+  const int src = peers ? (int)__ffsll((long long)peers) - 1 : lane;
+  return (uint32_t)__shfl((int)pb, src, 64) + rank;
 }
 
-// One workgroup per digit d (grid = R): exclusive scan, in place, of row d of the
-// digit-major histogram over the active blocks (each thread four consecutive
-// entries per chunk of 1024), and the row total into dtot[d].  The grid's block
-// count is the row stride.
-__global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist, int nb_grid,
+// One workgroup per digit d (grid = the pass's bins): exclusive scan, in place, of
+// row d of the plane over the active blocks (each thread four consecutive entries
+// per chunk of 1024), and the row total into dtot[d].
+__global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __restrict__ hist, int stride,
                                                                  const uint32_t* __restrict__ n_dev,
                                                                  int64_t n_host, uint32_t* __restrict__ dtot) {
   const int64_t n = item_count(n_dev, n_host);
   const int nb = (int)((n + kScanItems - 1) / kScanItems);
-  uint32_t* __restrict__ row = hist + (size_t)blockIdx.x * nb_grid;
-  __shared__ uint32_t sh[kThreads];
+  uint32_t* __restrict__ row = hist + (size_t)blockIdx.x * stride;
+  __shared__ uint32_t sh[kWaves];
   const int t = threadIdx.x;
   uint32_t carry = 0;
   for (int c0 = 0; c0 < nb; c0 += 4 * kThreads) {
@@ -227,120 +162,192 @@ __global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __res
   if (t == 0) dtot[blockIdx.x] = carry;
 }
 
-// Scatter of one pass.  With `ranges` (a pass over every tile bit of the pair keys),
-// block 0 also writes each tile's [start, end) -- the digit bases and totals -- for
-// tiles < n_tiles (empty ranges after a pair overflow).
+// One radix pass's scatter (see the top of the file).
+struct PassArgs {
+  const uint32_t* kin;
+  const uint32_t* vin;
+  uint32_t* kout;
+  uint32_t* vout;
+  const uint32_t* n_dev;  // item count on the device (clamped to n_host), or null: n_host
+  int64_t n_host;
+  int shift, bits;        // digit = (key >> shift) mod 2^bits
+  uint32_t* hist;         // this pass's plane: offsets in, cleared out
+  int stride;             // row stride of the planes
+  const uint32_t* dtot;   // row totals
+  uint32_t* hnext;        // the next pass's plane, or null
+  int nshift, nbits;      // the next pass's digit
+  uint2* ranges;          // a pass over every tile bit: block 0 writes each tile's [start, end)
+  int n_tiles;            //   for tiles < n_tiles (empty ranges when *overflow != 0)
+  const uint32_t* overflow;
+};
+
 template <int R>
-__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int64_t n_host, int shift,
-    int bits, int drop, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
-    uint2* __restrict__ ranges, int n_tiles, const uint32_t* __restrict__ overflow) {
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
   constexpr int PER = R / kThreads;
-  const int64_t n = item_count(n_dev, n_host);
+  const int64_t n = item_count(a.n_dev, a.n_host);
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   if (base >= n) return;
   __shared__ uint32_t doff[R];
   __shared__ uint32_t wcnt[kWaves][R];  // (round stamp << 16) | count of the wave's keys of a digit
-  __shared__ uint32_t sh[kThreads];
-  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
+  __shared__ uint32_t sh[kWaves];
+  const int t = threadIdx.x;
   for (int k = t; k < kWaves * R; k += kThreads) (&wcnt[0][0])[k] = 0u;
   // first slot of digit d: the keys of all smaller digits, then this digit's keys in
   // the blocks before this one (thread t holds digits PER t .. PER t + PER - 1)
   uint32_t tot[PER], pre = 0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    tot[q] = dtot[PER * t + q];
+    tot[q] = a.dtot[PER * t + q];
     pre += tot[q];
   }
   uint32_t run = block_exclusive_scan(pre, sh, nullptr);
-  const bool write_ranges = ranges && blockIdx.x == 0;
-  const bool empty = write_ranges && *overflow != 0u;
+  const bool write_ranges = a.ranges && blockIdx.x == 0;
+  const bool empty = write_ranges && *a.overflow != 0u;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int d = PER * t + q;
-    doff[d] = run + hist[(size_t)d * gridDim.x + blockIdx.x];
-    if (write_ranges && d < n_tiles) ranges[d] = empty ? make_uint2(0u, 0u) : make_uint2(run, run + tot[q]);
+    uint32_t* cell = a.hist + (size_t)d * a.stride + blockIdx.x;
+    const uint32_t c = *cell;
+    if (c) *cell = 0u;  // only this block reads this column
+    doff[d] = run + c;
+    if (write_ranges && d < a.n_tiles) a.ranges[d] = empty ? make_uint2(0u, 0u) : make_uint2(run, run + tot[q]);
     run += tot[q];
   }
   __syncthreads();
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t nmask = (1u << a.nbits) - 1u;
   // all of the block's keys up front: the rounds' loads overlap instead of each
   // round waiting for its own
   uint32_t kr[kRounds], vr[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t i = base + r * kThreads + t;
-    kr[r] = i < n ? kin[i] : 0u;
-    vr[r] = i < n ? vin[i] : 0u;
+    kr[r] = i < n ? a.kin[i] : 0u;
+    vr[r] = i < n ? a.vin[i] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    const uint32_t stamp = (uint32_t)(r + 1) << 16;
-    const int64_t i = base + r * kThreads + t;
-    const uint32_t key = kr[r], val = vr[r];
-    bool valid = i < n;
-    const uint32_t digit = valid ? (key >> shift) & ((1u << bits) - 1u) : 0u;
-    valid = valid && !(drop && key == kDropKey);
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      const bool set = (digit >> b) & 1u;
-      const uint64_t bal = __ballot(valid && set);
-      peers &= set ? bal : ~bal;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    const bool leader = valid && rank == 0;
-    if (leader) wcnt[wave][digit] = stamp | cnt;
-    __syncthreads();
-    // the group's first slot: the digit's running offset plus the same digit's keys
-    // in the lower waves of this round
-    uint32_t pb = 0;
-    if (leader) {
-      pb = doff[digit];
-      for (int w = 0; w < wave; ++w) {
-        const uint32_t e = wcnt[w][digit];
-        if ((e & 0xFFFF0000u) == stamp) pb += e & 0xFFFFu;
-      }
-    }
-    __syncthreads();
-    if (leader) atomicAdd(&doff[digit], cnt);
-    const int src = peers ? (int)__ffsll((long long)peers) - 1 : lane;
-    const uint32_t gb = (uint32_t)__shfl((int)pb, src, 64);
+    const bool valid = base + r * kThreads + t < n;
+    const uint32_t key = kr[r];
+    const uint32_t digit = valid ? (key >> a.shift) & ((1u << a.bits) - 1u) : 0u;
+    const uint32_t pos = rank_round<R>(digit, valid, a.bits, (uint32_t)(r + 1) << 16, wcnt, doff);
     if (valid) {
-      const uint32_t pos = gb + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+      a.kout[pos] = key;
+      a.vout[pos] = vr[r];
+      if (a.hnext)
+        atomicAdd(&a.hnext[(size_t)((key >> a.nshift) & nmask) * a.stride + (pos >> kBlockShift)], 1u);
     }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void duplicate_kernel(
-    const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ count,
-    const uint32_t* __restrict__ offs, const uint2* __restrict__ rect, const ViewDesc* __restrict__ views,
-    int n_views, const uint32_t* __restrict__ n_dev, int limit, int64_t p_cap, uint32_t* __restrict__ pkey,
-    uint32_t* __restrict__ pval, Ctrl* __restrict__ ctrl, uint2* __restrict__ ranges, int n_tiles) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  // clear the tile ranges for the ranges kernel (which runs after the tile sort)
-  for (int k = j; k < n_tiles; k += gridDim.x * blockDim.x) ranges[k] = make_uint2(0u, 0u);
-  const int n = (int)item_count(n_dev, limit);
-  const uint32_t id = j < n ? sorted_ids[j] : 0u;
-  const uint32_t c = j < n ? count[id] : 0u;
+// With more item blocks than kDirectParts: exclusive scan, in place, of the per-block
+// pair counts (one workgroup, chunks of 2048), and the totals.
+__global__ __launch_bounds__(kThreads) void scan_parts_kernel(uint32_t* __restrict__ part_pairs,
+                                                              const uint32_t* __restrict__ part_vis, int n_parts,
+                                                              Ctrl* __restrict__ ctrl) {
+  __shared__ uint32_t sh[kWaves];
+  const int t = threadIdx.x;
+  uint32_t carry = 0, vis = 0;
+  for (int c0 = 0; c0 < n_parts; c0 += kScanItems) {
+    uint32_t v[kRounds], s = 0;
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+      const int e = c0 + kRounds * t + k;
+      v[k] = e < n_parts ? part_pairs[e] : 0u;
+      vis += e < n_parts ? part_vis[e] : 0u;
+      s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_exclusive_scan(s, sh, &tot);
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+      const int e = c0 + kRounds * t + k;
+      if (e < n_parts) part_pairs[e] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  uint32_t vt;
+  (void)block_exclusive_scan(vis, sh, &vt);
+  if (t == 0) {
+    ctrl->n_pairs = carry;
+    ctrl->n_visible = vt;
+  }
+}
+
+// The pairs of every item, in item order (one thread per item, the blocks of
+// preprocessing).  Item j's first slot is the pair count of the items before it: the
+// earlier blocks' counts (summed here, or scanned beforehand for many blocks) plus a
+// block scan.  Each pair also counts into the first tile pass's plane at its output
+// block.
+struct DupArgs {
+  const uint32_t* count;       // tile count per item
+  const uint32_t* part_pairs;  // per-block pair counts (exclusive prefix when scanned)
+  const uint32_t* part_vis;    // per-block visible-item counts
+  int n_parts;
+  int scanned;
+  const uint2* rect;
+  const ViewDesc* views;
+  int n_views;
+  int64_t items;
+  int64_t p_cap;
+  uint32_t* pkey;
+  uint32_t* pval;
+  Ctrl* ctrl;
+  uint2* ranges;  // cleared here for the ranges kernel (multi-pass tile sorts)
+  int n_tiles;
+  uint32_t* hist;  // the first tile pass's plane
+  int stride;
+  int bits;        // the first tile pass's digit: key mod 2^bits
+};
+
+__global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
+  const int t = threadIdx.x;
+  const int g = blockIdx.x;
+  const int64_t j = (int64_t)g * kThreads + t;
+  for (int64_t k = j; k < a.n_tiles; k += (int64_t)gridDim.x * kThreads) a.ranges[k] = make_uint2(0u, 0u);
+  __shared__ uint32_t sh[kWaves];
+  uint32_t before;
+  if (a.scanned) {
+    before = a.part_pairs[g];
+  } else {
+    uint32_t s = 0;
+    for (int k = t; k < g; k += kThreads) s += a.part_pairs[k];
+    (void)block_exclusive_scan(s, sh, &before);
+    if (g == 0) {
+      uint32_t sp = 0, sv = 0;
+      for (int k = t; k < a.n_parts; k += kThreads) {
+        sp += a.part_pairs[k];
+        sv += a.part_vis[k];
+      }
+      uint32_t tp, tv;
+      (void)block_exclusive_scan(sp, sh, &tp);
+      (void)block_exclusive_scan(sv, sh, &tv);
+      if (t == 0) {
+        a.ctrl->n_pairs = tp;
+        a.ctrl->n_visible = tv;
+      }
+    }
+  }
+  const uint32_t c = j < a.items ? a.count[j] : 0u;
+  uint32_t off = before + block_exclusive_scan(c, sh, nullptr);
   if (c == 0) return;
-  uint32_t off = offs[j];
-  if ((int64_t)off + c > p_cap) {
-    ctrl->overflow = 1u;
+  if ((int64_t)off + c > a.p_cap) {
+    a.ctrl->overflow = 1u;
     return;
   }
   // key = the view's first global tile + the tile's index within the view
-  const ViewDesc& V = views[view_of_item(views, n_views, (int)id)];
-  const uint32_t base = (uint32_t)V.tile_base, tiles_x = (uint32_t)V.tiles_x;
-  const uint2 rc = rect[id];
+  const int item = (int)j;
+  const ViewDesc& V = a.views[view_of_item(a.views, a.n_views, item)];
+  const uint32_t tbase = (uint32_t)V.tile_base, tiles_x = (uint32_t)V.tiles_x;
+  const uint2 rc = a.rect[item];
   const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
+  const uint32_t dmask = (1u << a.bits) - 1u;
   for (uint32_t ty = ty0; ty <= ty1; ++ty)
     for (uint32_t tx = tx0; tx <= tx1; ++tx) {
-      pkey[off] = base + ty * tiles_x + tx;
-      pval[off] = id;
+      const uint32_t key = tbase + ty * tiles_x + tx;
+      a.pkey[off] = key;
+      a.pval[off] = (uint32_t)item;
+      atomicAdd(&a.hist[(size_t)(key & dmask) * a.stride + (off >> kBlockShift)], 1u);
       ++off;
     }
 }
@@ -358,9 +365,163 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __rest
   if (i == np - 1 || skey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
+// Depth order of one tile's list (one workgroup per tile), stable in the list order.
+// Up to 256 entries (the common case): each entry's slot is counted directly against
+// the others in LDS.  Longer lists: a stable LSD radix sort by the 32-bit depth keys,
+// four passes of 8 bits, each a counting pass (histogram, digit bases, ranked rounds
+// of 256); up to kOrderMax entries stay in LDS and registers (8 per thread) and skip
+// passes whose digit is the same for every entry; longer lists alternate between
+// `ids` and `scratch` in global memory, which after four passes leaves them in `ids`.
+__global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
+                                                              uint32_t* __restrict__ ids,
+                                                              uint32_t* __restrict__ scratch,
+                                                              const uint32_t* __restrict__ dkey) {
+  constexpr int RB = 1 << kOrderBits;
+  const uint2 rg = ranges[blockIdx.x];
+  const int64_t start = rg.x, L = (int64_t)rg.y - (int64_t)rg.x;
+  if (L <= 1) return;
+  __shared__ uint32_t wcnt[kWaves][RB];
+  __shared__ uint32_t doff[RB];
+  __shared__ uint32_t hcnt[RB];
+  __shared__ uint32_t sh[kWaves];
+  __shared__ __align__(16) uint32_t skey[kOrderMax];
+  __shared__ uint32_t sid[kOrderMax];
+  const int t = threadIdx.x;
+  if (L <= kThreads) {
+    // one entry per thread, ranked by counting: the entries with a smaller key, and
+    // those with the same key earlier in the list (keys past the end read as 2^32 - 1,
+    // above every depth key)
+    const bool valid = t < L;
+    const uint32_t id = valid ? ids[start + t] : 0u;
+    const uint32_t key = valid ? dkey[id] : 0xFFFFFFFFu;
+    skey[t] = key;
+    __syncthreads();
+    const int n4 = (int)((L + 3) & ~3);
+    uint32_t rank = 0;
+    for (int j = 0; j < n4; j += 4) {
+      const uint4 k4 = *reinterpret_cast<const uint4*>(&skey[j]);
+      rank += (k4.x < key) + (k4.x == key && j < t);
+      rank += (k4.y < key) + (k4.y == key && j + 1 < t);
+      rank += (k4.z < key) + (k4.z == key && j + 2 < t);
+      rank += (k4.w < key) + (k4.w == key && j + 3 < t);
+    }
+    if (valid) ids[start + rank] = id;
+    return;
+  }
+  for (int k = t; k < kWaves * RB; k += kThreads) (&wcnt[0][0])[k] = 0u;
+  uint32_t stamp = 0;  // round counter across the whole sort: stamps never repeat
+  if (L <= kOrderMax) {
+    const int nr = (int)((L + kThreads - 1) / kThreads);
+    uint32_t key[kRounds], id[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int e = r * kThreads + t;
+      id[r] = e < L ? ids[start + e] : 0u;
+      key[r] = e < L ? dkey[id[r]] : 0u;
+    }
+    for (int p = 0; p < 32 / kOrderBits; ++p) {
+      const int shift = p * kOrderBits;
+      hcnt[t] = 0u;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r)
+        if (r * kThreads + t < L) atomicAdd(&hcnt[(key[r] >> shift) & (RB - 1)], 1u);
+      __syncthreads();
+      const uint32_t h = hcnt[t];
+      // a digit that every entry shares leaves the order as it is
+      const bool uniform = __syncthreads_or(h == (uint32_t)L) != 0;
+      if (uniform) continue;
+      doff[t] = block_exclusive_scan(h, sh, nullptr);
+      __syncthreads();
+      uint32_t pos[kRounds];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        if (r < nr) {
+          const bool valid = r * kThreads + t < L;
+          const uint32_t digit = valid ? (key[r] >> shift) & (RB - 1) : 0u;
+          stamp += 1u << 16;
+          pos[r] = rank_round<RB>(digit, valid, kOrderBits, stamp, wcnt, doff);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        if (r * kThreads + t < L) {
+          skey[pos[r]] = key[r];
+          sid[pos[r]] = id[r];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int e = r * kThreads + t;
+        if (e < L) {
+          key[r] = skey[e];
+          id[r] = sid[e];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int e = r * kThreads + t;
+      if (e < L) ids[start + e] = id[r];
+    }
+    return;
+  }
+  // long lists: the same passes through global memory, chunk by chunk
+  for (int p = 0; p < 32 / kOrderBits; ++p) {
+    const int shift = p * kOrderBits;
+    const uint32_t* __restrict__ src = (p & 1) ? scratch : ids;
+    uint32_t* __restrict__ dst = (p & 1) ? ids : scratch;
+    hcnt[t] = 0u;
+    __syncthreads();
+    for (int64_t e = t; e < L; e += kThreads) atomicAdd(&hcnt[(dkey[src[start + e]] >> shift) & (RB - 1)], 1u);
+    __syncthreads();
+    doff[t] = block_exclusive_scan(hcnt[t], sh, nullptr);
+    __syncthreads();
+    for (int64_t e0 = 0; e0 < L; e0 += kThreads) {
+      if ((stamp >> 16) == 0xFFFFu) {  // stamps used up: clear the counts and start again
+        __syncthreads();
+        for (int k = t; k < kWaves * RB; k += kThreads) (&wcnt[0][0])[k] = 0u;
+        __syncthreads();
+        stamp = 0;
+      }
+      const int64_t e = e0 + t;
+      const bool valid = e < L;
+      const uint32_t v = valid ? src[start + e] : 0u;
+      const uint32_t digit = valid ? (dkey[v] >> shift) & (RB - 1) : 0u;
+      stamp += 1u << 16;
+      const uint32_t pos = rank_round<RB>(digit, valid, kOrderBits, stamp, wcnt, doff);
+      if (valid) dst[start + pos] = v;
+    }
+    __syncthreads();
+  }
+}
+
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per) > 0 ? (int)((n + per - 1) / per) : 1; }
 
+void launch_pass(const PassArgs& a, int grid, hipStream_t s) {
+  if (a.bits <= 8) {
+    radix_offsets_kernel<<<256, kThreads, 0, s>>>(a.hist, a.stride, a.n_dev, a.n_host, const_cast<uint32_t*>(a.dtot));
+    radix_scatter_kernel<256><<<grid, kThreads, 0, s>>>(a);
+  } else {
+    radix_offsets_kernel<<<2048, kThreads, 0, s>>>(a.hist, a.stride, a.n_dev, a.n_host,
+                                                   const_cast<uint32_t*>(a.dtot));
+    radix_scatter_kernel<2048><<<grid, kThreads, 0, s>>>(a);
+  }
+}
+
 }  // namespace
+
+int radix_pass_bits(int bits, int p) {
+  const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+  int shift = 0, pb = 0;
+  for (int k = 0; k <= p; ++k) {
+    pb = (bits - shift + (passes - k) - 1) / (passes - k);  // split the bits evenly
+    shift += pb;
+  }
+  return pb;
+}
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
@@ -375,60 +536,69 @@ void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t 
   copy_u32_kernel<<<blocks_for(n, 256), 256, 0, s>>>(src, dst, n);
 }
 
-void launch_scan_counts(const uint32_t* count, const uint32_t* perm, const uint32_t* n_dev, int limit,
-                        uint32_t* offs, uint32_t* block_sums, Ctrl* ctrl, hipStream_t s) {
-  const int nb = blocks_for(limit, kScanItems);
-  scan_reduce_kernel<<<nb, kThreads, 0, s>>>(count, perm, n_dev, limit, block_sums);
-  scan_blocks_kernel<<<1, kThreads, 0, s>>>(block_sums, n_dev, limit, ctrl);
-  scan_final_kernel<<<nb, kThreads, 0, s>>>(count, perm, n_dev, limit, block_sums, offs);
+bool part_scan_needed(int64_t items) { return blocks_for(items, kPartItems) > kDirectParts; }
+
+void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t items, Ctrl* ctrl, hipStream_t s) {
+  scan_parts_kernel<<<1, kThreads, 0, s>>>(part_pairs, part_vis, blocks_for(items, kPartItems), ctrl);
 }
 
-int radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, int64_t n_host, const uint32_t* n_dev,
-               int bits, uint32_t* hist, uint32_t* n_kept, uint2* ranges, int n_tiles, const uint32_t* overflow,
-               hipStream_t s) {
-  const int nb = blocks_for(cap, kScanItems);
-  const int64_t limit = n_dev ? cap : n_host;
-  uint32_t* dtot = hist + (size_t)kDigits11 * nb;
-  const int passes = (bits + 10) / 11;
+void launch_duplicate(const SortPlanes& ws, const uint32_t* count, const uint32_t* part_pairs,
+                      const uint32_t* part_vis, bool scanned, const uint2* rect, const ViewDesc* views, int n_views,
+                      int64_t items, int64_t p_cap, int tile_bits, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl,
+                      uint2* ranges, int n_tiles, hipStream_t s) {
+  const int n_parts = blocks_for(items, kPartItems);
+  DupArgs a{count,  part_pairs, part_vis, n_parts, scanned ? 1 : 0, rect,   views,   n_views,
+            items,  p_cap,      pkey,     pval,    ctrl,            ranges, n_tiles, ws.plane[1],
+            ws.stride, radix_pass_bits(tile_bits, 0)};
+  duplicate_kernel<<<n_parts, kThreads, 0, s>>>(a);
+}
+
+int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_t p_cap, int bits, Ctrl* ctrl,
+              uint2* ranges, int n_tiles, hipStream_t s) {
+  const int grid = blocks_for(p_cap, kScanItems);
+  const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
   int cur = 0, shift = 0;
   for (int p = 0; p < passes; ++p) {
-    const int pb = (bits - shift + (passes - p) - 1) / (passes - p);  // split the bits evenly
-    const int drop = (n_kept && p == 0) ? 1 : 0;
-    // after a dropping first pass the kept count is the item count
-    const uint32_t* nd = (n_kept && p > 0) ? n_kept : n_dev;
-    const int64_t lim = (n_kept && p > 0) ? cap : limit;
-    uint2* rg = (ranges && passes == 1) ? ranges : nullptr;
-    if (pb <= 8) {
-      radix_hist_kernel<kDigits8><<<nb, kThreads, 0, s>>>(keys[cur], nd, lim, shift, pb, drop, hist, n_kept);
-      radix_offsets_kernel<<<kDigits8, kThreads, 0, s>>>(hist, nb, nd, lim, dtot);
-      radix_scatter_kernel<kDigits8><<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
-                                                             nd, lim, shift, pb, drop, hist, dtot, rg, n_tiles,
-                                                             overflow);
-    } else {
-      radix_hist_kernel<kDigits11><<<nb, kThreads, 0, s>>>(keys[cur], nd, lim, shift, pb, drop, hist, n_kept);
-      radix_offsets_kernel<<<kDigits11, kThreads, 0, s>>>(hist, nb, nd, lim, dtot);
-      radix_scatter_kernel<kDigits11><<<nb, kThreads, 0, s>>>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1],
-                                                              nd, lim, shift, pb, drop, hist, dtot, rg, n_tiles,
-                                                              overflow);
+    const int pb = radix_pass_bits(bits, p);
+    PassArgs a{};
+    a.kin = keys[cur];
+    a.vin = vals[cur];
+    a.kout = keys[cur ^ 1];
+    a.vout = vals[cur ^ 1];
+    a.n_dev = &ctrl->n_pairs;
+    a.n_host = p_cap;
+    a.shift = shift;
+    a.bits = pb;
+    a.hist = ws.plane[(p + 1) & 1];  // the duplication fills plane 1
+    a.stride = ws.stride;
+    a.dtot = ws.dtot;
+    if (p + 1 < passes) {
+      a.hnext = ws.plane[p & 1];
+      a.nshift = shift + pb;
+      a.nbits = radix_pass_bits(bits, p + 1);
     }
+    if (passes == 1) {
+      a.ranges = ranges;
+      a.n_tiles = n_tiles;
+      a.overflow = &ctrl->overflow;
+    }
+    launch_pass(a, grid, s);
     cur ^= 1;
     shift += pb;
   }
   return cur;
 }
 
-void launch_duplicate(const uint32_t* sorted_ids, const uint32_t* count, const uint32_t* offs,
-                      const uint2* rect, const ViewDesc* views, int n_views, const uint32_t* n_dev, int limit,
-                      int64_t p_cap, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl, uint2* ranges, int n_tiles,
-                      hipStream_t s) {
-  duplicate_kernel<<<blocks_for(limit, 256), 256, 0, s>>>(sorted_ids, count, offs, rect, views, n_views, n_dev,
-                                                          limit, p_cap, pkey, pval, ctrl, ranges, n_tiles);
-}
-
 void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s) {
   (void)n_tiles;  // cleared by the duplicate kernel
   ranges_kernel<<<blocks_for(p_cap, 256), 256, 0, s>>>(skey, ctrl, p_cap, ranges);
+}
+
+void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* dkey,
+                       hipStream_t s) {
+  if (n_tiles <= 0) return;
+  tile_order_kernel<<<n_tiles, kThreads, 0, s>>>(ranges, ids, scratch, dkey);
 }
 
 }  // namespace gs2d

@@ -360,7 +360,7 @@ class Rasterizer:
     _DEBUG = {"tile_keys": (0, np.uint32), "tile_ids": (1, np.uint32), "ranges": (2, np.uint32),
               "depth_keys": (3, np.uint32), "rect": (4, np.uint16), "t_final": (5, np.float32),
               "last": (6, np.uint32), "unsorted_keys": (7, np.uint32), "unsorted_ids": (8, np.uint32),
-              "depth_ids": (9, np.uint32), "track_grad": (10, np.float64)}
+              "track_grad": (10, np.float64)}
 
     def debug(self, what: str) -> np.ndarray:
         which, dt = self._DEBUG[what]

@@ -26,7 +26,8 @@ def room_scene(n=300_000, seed=0, cam_seed=0):
     return room, pose
 
 
-def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth", "normal", "alpha")):
+def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth", "normal", "alpha"),
+                 max_excluded=MAX_EXCLUDED):
     """Parity of planar images with the tolerances of the method's parity bar.
 
     colour and opacity: |d| <= 1e-4 absolute per channel; depth: |d| <= 1e-4 max(|ref|, 1e-3);
@@ -38,11 +39,12 @@ def check_images(gpu: dict, ref: dict, margin: np.ndarray, what=("rgb", "depth",
     factors in front of it and the sum that of its own k additions, so
     ||d N|| <= (2 k + 8) 2^-24 O (k = the pixel's composited count).  The bar is the larger of
     the two; wherever ||N|| is not cancelled the first one is the binding one.
-    Pixels with a decision margin below MARGIN are excluded and counted.
+    Pixels with a decision margin below MARGIN are excluded and counted (at most
+    max_excluded of the image).
     """
     keep = margin >= MARGIN
     frac = 1.0 - keep.mean()
-    assert frac <= MAX_EXCLUDED, f"{frac:.4%} of pixels excluded by margin"
+    assert frac <= max_excluded, f"{frac:.4%} of pixels excluded by margin"
     report = {"excluded_frac": float(frac)}
     for k in what:
         g, r = gpu[k], ref[k]

@@ -162,43 +162,126 @@ def test_gpu_backward_parity_room_pose(gs):
     print("room grads", rep, "loss", L)
 
 
+def _expected_order(ukeys, uids, dkey):
+    """Pairs ordered by (tile, depth key, surfel id): the order of the per-pixel lists."""
+    order = np.lexsort((uids, dkey[uids], ukeys))
+    return ukeys[order], uids[order]
+
+
 def test_gpu_sort_bit_exact(gs):
-    """Tile sort = stable sort of the GPU's own pairs; depth keys = the oracle's float32 keys."""
+    """Pairs = every visible surfel's tiles in surfel order; sorted lists = (tile, depth
+    key, id) order; depth keys = the oracle's float32 keys."""
     room, pose = room_scene(300_000, seed=1, cam_seed=1)
     r = gs.Rasterizer(keep_unsorted=True)
     _render(r, room.params, ROOM_CAM, pose)
     c = r.counts()
     keys, ids = r.debug("tile_keys"), r.debug("tile_ids")
     ukeys, uids = r.debug("unsorted_keys"), r.debug("unsorted_ids")
-    assert len(keys) == c["n_pairs"] and len(ukeys) == c["n_pairs"]
-    order = np.argsort(ukeys, kind="stable")
-    np.testing.assert_array_equal(keys, ukeys[order])
-    np.testing.assert_array_equal(ids, uids[order])
-    # the depth-sorted list holds exactly the surfels that touch a tile, ascending
-    # (depth key, id)
-    dk, di = r.debug("depth_keys"), r.debug("depth_ids")
-    assert len(di) == c["n_visible"] and len(np.unique(di)) == len(di)
-    kk = dk.astype(np.int64) * (1 << 32) + di
-    assert np.all(np.diff(kk) > 0)
-    rect = r.debug("rect").reshape(-1, 4)
+    dk = r.debug("depth_keys")
+    assert len(keys) == c["n_pairs"] and len(ukeys) == c["n_pairs"] and len(dk) == room.n
+    ek, ei = _expected_order(ukeys, uids, dk)
+    np.testing.assert_array_equal(keys, ek)
+    np.testing.assert_array_equal(ids, ei)
+    # pairs are emitted surfel by surfel, each surfel's tiles row by row
+    rect = r.debug("rect").reshape(-1, 4).astype(np.int64)
     touches = (rect[:, 0] <= rect[:, 1]) & (rect[:, 2] <= rect[:, 3])
-    assert np.array_equal(np.sort(di), np.flatnonzero(touches))
-    per = np.full(room.n, 0xFFFFFFFF, dtype=np.uint32)
-    per[di] = dk
+    assert c["n_visible"] == touches.sum()
+    assert np.all(np.diff(uids.astype(np.int64)) >= 0)
+    assert np.array_equal(np.unique(uids), np.flatnonzero(touches))
+    tx = ROOM_CAM.width // 16 + (ROOM_CAM.width % 16 > 0)
+    for i in np.random.default_rng(0).choice(np.flatnonzero(touches), 200, replace=False):
+        x0, x1, y0, y1 = rect[i]
+        want = [(y * tx + x) for y in range(y0, y1 + 1) for x in range(x0, x1 + 1)]
+        np.testing.assert_array_equal(ukeys[uids == i], want)
+    # the depth keys of the surfels that touch a tile are the oracle's
     pre = oracle.preprocess(room.params, ROOM_CAM, pose)
-    vis = per != 0xFFFFFFFF
-    assert vis.sum() == len(di)
     okey = pre["key"].view(np.uint32)
-    assert np.array_equal(per[vis], okey[vis]), int((per[vis] != okey[vis]).sum())
-    assert not np.any(pre["culled"][vis])
-    # within each tile, ids ascend in (depth key, id)
+    assert np.array_equal(dk[touches], okey[touches]), int((dk[touches] != okey[touches]).sum())
+    assert np.all(dk[~touches] == 0xFFFFFFFF)
+    assert not np.any(pre["culled"][touches])
+    # the ranges cover each tile's run of the sorted pairs
     rng = r.debug("ranges").reshape(-1, 2)
     for t in np.random.default_rng(0).choice(len(rng), 50, replace=False):
         a, b = rng[t]
-        seg = ids[a:b]
-        kk = per[seg].astype(np.int64) * (1 << 32) + seg
-        assert np.all(np.diff(kk) > 0)
         assert np.all(keys[a:b] == t)
+
+
+def _sort_state(r):
+    """The sort's outputs after a render, checked for consistency: the sorted pairs are
+    the emitted pairs in (tile, depth key, id) order and the ranges cover the sorted
+    pairs tile by tile."""
+    c = r.counts()
+    out = {k: r.debug(k).copy() for k in ("tile_keys", "tile_ids", "unsorted_keys", "unsorted_ids", "ranges",
+                                          "depth_keys")}
+    keys = out["tile_keys"]
+    assert len(keys) == c["n_pairs"] and c["overflow"] == 0
+    ek, ei = _expected_order(out["unsorted_keys"], out["unsorted_ids"], out["depth_keys"])
+    np.testing.assert_array_equal(keys, ek)
+    np.testing.assert_array_equal(out["tile_ids"], ei)
+    rng = out["ranges"].reshape(-1, 2)
+    assert rng.shape[0] == c["n_tiles"]
+    counts = np.bincount(keys, minlength=c["n_tiles"])
+    nz = counts > 0
+    np.testing.assert_array_equal(rng[nz, 1] - rng[nz, 0], counts[nz])
+    np.testing.assert_array_equal(keys[rng[nz, 0]], np.flatnonzero(nz))
+    return out
+
+
+def test_gpu_sort_state_across_calls(gs):
+    """The sort keeps no state between renders: the same render before and after others
+    (smaller, larger, with a two-pass tile sort) gives the same sorted pairs bit for bit,
+    and each render's sort is consistent."""
+    room, pose = room_scene(300_000, seed=1, cam_seed=1)
+    small = synth.random_surfels(2000, seed=5)
+    big_cam = synth.Camera(1200, 680, 600.0, 600.0, 600.0, 340.0)  # 75 x 43 tiles: two tile passes
+    r = gs.Rasterizer(keep_unsorted=True)
+    seq = [("A", room.params, ROOM_CAM, pose), ("B", small.params, small.camera, small.pose),
+           ("C", room.params, big_cam, pose), ("A", room.params, ROOM_CAM, pose),
+           ("B", small.params, small.camera, small.pose), ("C", room.params, big_cam, pose)]
+    first = {}
+    for name, params, cam, p in seq:
+        _render(r, params, cam, p)
+        st = _sort_state(r)
+        if name in first:
+            for k, v in first[name].items():
+                np.testing.assert_array_equal(st[k], v, err_msg=f"{name} {k}")
+        else:
+            first[name] = st
+    # the first render's depth keys are the oracle's
+    pre = oracle.preprocess(room.params, ROOM_CAM, pose)
+    dk = first["A"]["depth_keys"]
+    vis = dk != 0xFFFFFFFF
+    np.testing.assert_array_equal(dk[vis], pre["key"].view(np.uint32)[vis])
+
+
+def test_gpu_long_tile_lists(gs):
+    """Tiles whose lists exceed one workgroup's LDS take the depth order through global
+    memory: 3000 surfels stacked over one tile, in shuffled depth, with repeated depths
+    (ties keep the surfel order), render as the oracle does and order as defined.  Their
+    pairs also outgrow the default pair capacity, so the render grows it."""
+    s = synth.stacked_surfels(opacity=0.02)
+    base = s.params[:, :1]
+    n = 3000
+    g = np.random.default_rng(11)
+    P = np.repeat(base, n, axis=1).copy()
+    z = g.choice(np.linspace(1.0, 3.0, 1000), n)  # about three surfels per depth
+    P[2] = z
+    P[12] = g.uniform(0, 1, n)
+    cam = s.camera
+    r = gs.Rasterizer(keep_unsorted=True)
+    out, img = _render(r, P.astype(np.float32), cam, s.pose)
+    c = r.counts()
+    # more pairs than the default capacity: the render grew the pair buffers and ran again
+    assert c["overflow"] == 0 and c["n_pairs"] > 4 * n
+    rng = r.debug("ranges").reshape(-1, 2)
+    assert (rng[:, 1] - rng[:, 0]).max() > 2048
+    keys, ids = r.debug("tile_keys"), r.debug("tile_ids")
+    ek, ei = _expected_order(r.debug("unsorted_keys"), r.debug("unsorted_ids"), r.debug("depth_keys"))
+    np.testing.assert_array_equal(keys, ek)
+    np.testing.assert_array_equal(ids, ei)
+    ref = oracle.render(P.astype(np.float32), cam, s.pose)
+    # 3000 coincident footprints put many pixels near a cutoff decision of some pair
+    print("long lists", c, check_images(img, ref, ref["fmargin"], max_excluded=1e-2))
 
 
 def test_gpu_track_gradient_matches_oracle(gs):
