@@ -3,7 +3,7 @@
 // Forward (Sec. "2D Gaussian Splatting", eq:alpha_blending): one workgroup per
 // screen tile, one lane per pixel, each wave owning an 8x8 block of the tile.
 // The tile's depth-ordered surfel list is staged through LDS in batches of
-// 96-byte records; every wave tests each record's footprint box against its own
+// records; every wave tests each record's footprint box against its own
 // 8x8 block (a scalar, wave-uniform branch) before any lane evaluates it.  Per
 // (pixel, surfel) pair the ray-splat intersection is solved in the surfel's uv
 // frame from the centre-relative homography rows (see gs2d_internal.h), the
@@ -597,7 +597,10 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
 // both rank-one pair terms [V; X x V] as in the backward kernel.  This is the
 // back-to-front recurrence dL/dalpha_i = T_i sum_ch g_ch (v_i,ch - B_i,ch) with the
 // colour behind i, T_{i+1} B_i = sum_{j>i} w_j v_j, regrouped by j: every term is
-// accumulated front to back, and no total is subtracted from a prefix.
+// accumulated front to back, and no total is subtracted from a prefix.  A_D and G_D
+// share one accumulator (both take g_D).  Entries are walked one per step: the
+// walk's registers then allow five waves per SIMD, which hides more latency than
+// two independent evaluations per step at four.
 template <int TW, int TH, bool PROF>
 __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
@@ -621,9 +624,9 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
   FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
-  float Q[6], Ar[6], Ag[6], Ab[6], AD[6], GD[6];
+  float Q[6], Ar[6], Ag[6], Ab[6], AD[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) Q[k] = Ar[k] = Ag[k] = Ab[k] = AD[k] = GD[k] = 0.f;
+  for (int k = 0; k < 6; ++k) Q[k] = Ar[k] = Ag[k] = Ab[k] = AD[k] = 0.f;
   int n_eval = 0, n_cov = 0;
   // one composited entry: the forward blend and the gradient terms
   auto step = [&](int code, const Hit& h, const Rec& r) {
@@ -688,8 +691,7 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
       Ar[k] = fmaf(r.c4.y, U, Ar[k]);
       Ag[k] = fmaf(r.c4.z, U, Ag[k]);
       Ab[k] = fmaf(r.c4.w, U, Ab[k]);
-      AD[k] = fmaf(h.d, U, AD[k]);
-      GD[k] = fmaf(w, K[k], GD[k]);
+      AD[k] = fmaf(h.d, U, fmaf(w, K[k], AD[k]));
       Q[k] = fmaf(J[k], ia, Q[k]);
     }
     s.cr = fmaf(w, r.c4.y, s.cr);
@@ -718,26 +720,15 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
       while (m != 0ull) {
         const int j1 = c0 + __builtin_ctzll(m);
         m &= m - 1ull;
-        const bool two = m != 0ull;
-        const int j2 = two ? c0 + __builtin_ctzll(m) : j1;
-        if (two) m &= m - 1ull;
         if (!s.done) {
-          const Rec r1 = load_rec(srec, j1), r2 = load_rec(srec, j2);
-          Hit h1, h2;
+          const Rec r1 = load_rec(srec, j1);
+          Hit h1;
           const int k1 = evaluate(fpx, fpy, r1.ox, r1.oy, r1.g1, r1.g2, r1.g3, r1.c4.x, a.z_near, a.filter, h1);
-          const int k2 = evaluate(fpx, fpy, r2.ox, r2.oy, r2.g1, r2.g2, r2.g3, r2.c4.x, a.z_near, a.filter, h2);
           if (PROF) {
             n_eval += 1;
             n_cov += k1 > 0;
           }
           step(k1, h1, r1);
-          if (two && !s.done) {
-            if (PROF) {
-              n_eval += 1;
-              n_cov += k2 > 0;
-            }
-            step(k2, h2, r2);
-          }
         }
         if (__ballot(!s.done) == 0ull) break;
       }
@@ -765,7 +756,7 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
       l = fabsf(d0) + fabsf(d1) + fabsf(d2) + a.lambda_d * fabsf(dd);
       const float gr = sgn(d0) * inv, gg = sgn(d1) * inv, gb = sgn(d2) * inv, gd = a.lambda_d * sgn(dd) * inv;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) pg[k] = gr * Ar[k] + gg * Ag[k] + gb * Ab[k] + gd * (AD[k] + GD[k]);
+      for (int k = 0; k < 6; ++k) pg[k] = gr * Ar[k] + gg * Ag[k] + gb * Ab[k] + gd * AD[k];
     }
   }
   // tile sums: pose gradient in slots 0-5, loss in slot 6
