@@ -283,8 +283,9 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
  * inclusive; empty: x0 > x1), 5 per-pixel final transmittance (float [H][W]),
  * 6 per-pixel list length (uint32 [H][W]), 7 unsorted tile keys, 8 unsorted surfel ids
  * (uint32 [n_pairs], emitted in surfel order before the tile sort; only with
- * options.keep_unsorted = 1), 10 the pose gradient of each problem's last tracking iteration (double [32][6];
- * available after gs2d_track / gs2d_track_batch, without a forward).
+ * options.keep_unsorted = 1), 10 the pose gradient of each problem's last tracking
+ * iteration (double [32][6]; available after gs2d_track / gs2d_track_batch, without a
+ * forward).
  * *bytes (host) is the buffer size in; the bytes copied out.  Synchronises `stream`. */
 GS2D_API int gs2d_debug_copy(gs2d_ctx* ctx, int32_t which, void* host_dst, size_t* bytes,
                              hipStream_t stream);

@@ -275,7 +275,7 @@ struct TrackLoss {
   int use_masks;
 };
 int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync, bool upload = true,
-                 const TrackLoss* tl = nullptr, bool blend = true) {
+                 const TrackLoss* tl = nullptr, bool blend = true, bool order = true) {
   const int64_t items = vs.items;
   const int nv = vs.n_views;
   bool capturing = false;
@@ -364,7 +364,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
       ProfScope ps(ctx, kRanges, s);
       launch_ranges(ctx->pkey[pbuf], ctx->ctrl, ctx->p_cap, ctx->ranges, (int)vs.tiles, s);
     }
-    {
+    if (order) {
       // each tile's items, ascending on entry, stably into depth order
       ProfScope ps(ctx, kDepthSort, s);
       launch_tile_order(ctx->ranges, (int)vs.tiles, ctx->pval[pbuf], ctx->pval[pbuf ^ 1], ctx->dkey, s);
@@ -548,13 +548,20 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
   adam.weight_decay = a->weight_decay;
   // sorts, then one walk per tile for the forward blend, the tracking loss and the
   // pose gradient; with no surfel there is no walk and the loss kernel forms the loss
-  GS2D_TRY(render_views(ctx, vs, s, false, false, nullptr, false));
+  // with 256-pixel tiles each workgroup of the walk orders its own tile's list
+  const bool walk_orders = ctx->opt.tile_w * ctx->opt.tile_h == 256;
+  GS2D_TRY(render_views(ctx, vs, s, false, false, nullptr, false, !walk_orders));
   const int stride = loss_blocks(vs.max_hw);
   if (vs.items > 0) {
     BlendArgs ba = blend_args(ctx);
     ba.loss_part = ctx->part;
     ba.lambda_d = a->lambda_d;
     ba.use_masks = a->use_masks;
+    if (walk_orders) {
+      ba.order_ids = ctx->pval[ctx->pair_buf];
+      ba.order_scratch = ctx->pval[ctx->pair_buf ^ 1];
+      ba.dkey = ctx->dkey;
+    }
     ProfScope ps(ctx, kBlendTrack, s);
     launch_blend_track(ba, ctx->opt.tile_w, ctx->opt.tile_h, work_ptr(ctx, s), s);
   } else {
@@ -756,10 +763,10 @@ GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
   if (!ctx) return GS2D_OK;
   (void)set_device(ctx);
   invalidate_graph(ctx);
-  void* bufs[] = {ctx->rec,       ctx->rect,     ctx->count,      ctx->dkey,      ctx->parts,      ctx->hist,
-                  ctx->gacc,      ctx->pkey[0],  ctx->pkey[1],   ctx->pval[0],  ctx->pval[1],    ctx->pkey_keep, ctx->pval_keep,  ctx->ranges,
-                  ctx->t_final,   ctx->last,     ctx->lgrad,      ctx->limg,      ctx->part,       ctx->lpart,
-                  ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl};
+  void* bufs[] = {ctx->rec,       ctx->rect,       ctx->count,     ctx->dkey,      ctx->parts,     ctx->hist,
+                  ctx->gacc,      ctx->pkey[0],    ctx->pkey[1],   ctx->pval[0],   ctx->pval[1],   ctx->pkey_keep,
+                  ctx->pval_keep, ctx->ranges,     ctx->t_final,   ctx->last,      ctx->lgrad,     ctx->limg,
+                  ctx->part,      ctx->lpart,      ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);

@@ -26,7 +26,7 @@
 // registers and reduces them once per workgroup (no per-surfel atomics); the
 // full mode reduces the 16 per-surfel terms over each wave and adds them
 // atomically.
-#include "gs2d_internal.h"
+#include "tile_order.h"
 
 namespace gs2d {
 namespace {
@@ -587,6 +587,13 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   }
 }
 
+// float4 slots before the ordered list in the tracking walk's LDS: the staged records
+// and their cull data, or the ordering's scratch, whichever is larger (both are used
+// one after the other)
+__host__ __device__ constexpr int track_stage_f4(int batch) {
+  return batch * (kLdsRec + 3) > (kOrderScratchWords + 3) / 4 ? batch * (kLdsRec + 3) : (kOrderScratchWords + 3) / 4;
+}
+
 // Tracking: the forward blend, the tracking loss and the pose-only gradient in one
 // walk of each tile's list.  For pixel loss gradients g_ch (known only once the
 // pixel is composited) the pose gradient of eq:derivatives is
@@ -623,6 +630,15 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
+  // the tile's depth order, in LDS when the list fits (see tile_order.h); the staged
+  // records are then gathered through the ordered ids in LDS
+  uint32_t* const sid = reinterpret_cast<uint32_t*>(srec + track_stage_f4(a.batch));
+  bool lds_list = false;
+  if constexpr (NT == kBlockThreads) {
+    if (a.order_ids)
+      lds_list = order_list(a.order_ids, a.order_scratch, a.dkey, start, end - start,
+                            order_lds(reinterpret_cast<uint32_t*>(srec), sid), true);
+  }
   FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
   float Q[6], Ar[6], Ag[6], Ab[6], AD[6];
 #pragma unroll
@@ -709,7 +725,8 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
     const int nb = min(a.batch, end - b0);
     for (int k = t; k < nb * kRecF4; k += NT) {
       const int j = k / kRecF4, f = k - j * kRecF4;
-      const float4 v = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
+      const uint32_t id = lds_list ? sid[b0 - start + j] : a.pval[b0 + j];
+      const float4 v = a.rec[(size_t)id * kRecF4 + f];
       if (f < kLdsRec) srec[j * kLdsRec + f] = v;
       stage_cull(cull, j, f, v);
     }
@@ -826,7 +843,8 @@ void launch_blend_fwd(const BlendArgs& a, int tile_w, int tile_h, float* t_final
 
 template <int TW, int TH>
 void track_shape(const BlendArgs& a, unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * (kLdsRec + 3) * sizeof(float4);
+  // staging (or, before it, the ordering's scratch), then the ordered list
+  const size_t lds = (size_t)track_stage_f4(a.batch) * sizeof(float4) + kOrderMax * sizeof(uint32_t);
   if (work)
     blend_track_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, work);
   else

@@ -259,6 +259,12 @@ struct BlendArgs {
   float* loss_part = nullptr;
   float lambda_d = 0.f;
   int use_masks = 0;
+  // tracking walk with 256-thread tiles: with order_ids, each workgroup first orders
+  // its own tile's list (order_ids = the tile-sorted ids, order_scratch a buffer of the
+  // same size, dkey the per-item depth keys), so no separate depth-order kernel runs
+  uint32_t* order_ids = nullptr;
+  uint32_t* order_scratch = nullptr;
+  const uint32_t* dkey = nullptr;
 };
 // Tracking: forward blend, tracking loss and pose-only gradient in one walk; needs
 // a.loss_part (tile rows: pose gradient in slots 0-5, loss in slot 6), lambda_d,

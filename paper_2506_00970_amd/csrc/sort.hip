@@ -11,9 +11,8 @@
 //                   view's tiles follow the previous view's), so that each tile's
 //                   items stay in ascending item order;
 //   3. depth order  one workgroup per tile stably sorts the tile's items by depth key;
-//                   with the items ascending on entry, ties keep item order.
-// Lists are short (a tile holds a few hundred items), so step 3 runs in LDS; longer
-// lists take the same passes through global memory.
+//                   with the items ascending on entry, ties keep item order (see
+//                   tile_order.h; the tracking walk orders its own tile instead).
 //
 // Radix pass of the tile sort (digits of up to 11 bits: 256 or 2048 bins) over blocks
 // of kScanItems keys, with a digit-major histogram plane: cell (d, b) = the keys of
@@ -33,20 +32,18 @@
 // Up to 2048 tiles take one pass, whose digit bases and totals are the tile ranges.
 // Kernels whose item count lives on the device read it and exit early, so a
 // capacity-sized launch can be captured in a graph.
-#include "gs2d_internal.h"
+#include "tile_order.h"
 
 namespace gs2d {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kBlockThreads;
 constexpr int kRounds = kScanItems / kThreads;  // 8
-constexpr int kWaves = kThreads / 64;
+constexpr int kWaves = kBlockWaves;
 constexpr int kBlockShift = 11;  // log2(kScanItems)
 static_assert(kScanItems == 1 << kBlockShift, "block shift");
 static_assert(kPartItems == kThreads, "duplication blocks are preprocessing blocks");
 constexpr int kDirectParts = 4096;  // up to this many item blocks, each block sums the counts before it
-constexpr int kOrderMax = kScanItems;  // tile lists up to this length are ordered in LDS
-constexpr int kOrderBits = 8;          // digit of the depth order: 4 passes over 32-bit keys
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -61,73 +58,12 @@ __global__ void copy_u32_kernel(const uint32_t* __restrict__ src, uint32_t* __re
   if (i < n) dst[i] = src[i];
 }
 
-// Exclusive scan over the 256 threads of a block: a scan within each wave, then the
-// totals of the lower waves (sh: kWaves words of LDS).  *total = the block's sum.
-// Every thread of the block must call it.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wave] = x;
-  __syncthreads();
-  uint32_t below = 0, all = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const uint32_t sw = sh[w];
-    below += w < wave ? sw : 0u;
-    all += sw;
-  }
-  __syncthreads();
-  if (total) *total = all;
-  return below + x - v;
-}
-
 // Item count of a pass: the device count clamped to the buffer capacity
 // (`limit`), or `limit` itself when there is no device count.
 __device__ inline int64_t item_count(const uint32_t* n_dev, int64_t limit) {
   if (!n_dev) return limit;
   const int64_t n = (int64_t)(*n_dev);
   return n < limit ? n : limit;
-}
-
-// Rank of one round of up to 256 keys in a stable counting pass (every thread of the
-// block calls it).  digit: the key's digit; valid: the lane holds a key; doff[d]: the
-// next free slot of digit d (advanced here); wcnt: per-wave digit counts, stamped.
-// Returns the key's slot.
-template <int R>
-__device__ inline uint32_t rank_round(uint32_t digit, bool valid, int bits, uint32_t stamp,
-                                      uint32_t (*wcnt)[R], uint32_t* doff) {
-  const int t = threadIdx.x, wave = t / 64, lane = t % 64;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint64_t peers = __ballot(valid);
-  for (int b = 0; b < bits; ++b) {
-    const bool set = (digit >> b) & 1u;
-    const uint64_t bal = __ballot(valid && set);
-    peers &= set ? bal : ~bal;
-  }
-  const uint32_t rank = (uint32_t)__popcll(peers & lt);
-  const uint32_t cnt = (uint32_t)__popcll(peers);
-  const bool leader = valid && rank == 0;
-  if (leader) wcnt[wave][digit] = stamp | cnt;
-  __syncthreads();
-  // the group's first slot: the digit's running offset plus the same digit's keys
-  // in the lower waves of this round
-  uint32_t pb = 0;
-  if (leader) {
-    pb = doff[digit];
-    for (int w = 0; w < wave; ++w) {
-      const uint32_t e = wcnt[w][digit];
-      if ((e & 0xFFFF0000u) == stamp) pb += e & 0xFFFFu;
-    }
-  }
-  __syncthreads();
-  if (leader) atomicAdd(&doff[digit], cnt);
-  const int src = peers ? (int)__ffsll((long long)peers) - 1 : lane;
-  return (uint32_t)__shfl((int)pb, src, 64) + rank;
 }
 
 // One workgroup per digit d (grid = the pass's bins): exclusive scan, in place, of
@@ -229,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
     const bool valid = base + r * kThreads + t < n;
     const uint32_t key = kr[r];
     const uint32_t digit = valid ? (key >> a.shift) & ((1u << a.bits) - 1u) : 0u;
-    const uint32_t pos = rank_round<R>(digit, valid, a.bits, (uint32_t)(r + 1) << 16, wcnt, doff);
+    const uint32_t pos = rank_round<R>(digit, valid, a.bits, (uint32_t)(r + 1) << 16, &wcnt[0][0], doff);
     if (valid) {
       a.kout[pos] = key;
       a.vout[pos] = vr[r];
@@ -365,137 +301,17 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __rest
   if (i == np - 1 || skey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
-// Depth order of one tile's list (one workgroup per tile), stable in the list order.
-// Up to 256 entries (the common case): each entry's slot is counted directly against
-// the others in LDS.  Longer lists: a stable LSD radix sort by the 32-bit depth keys,
-// four passes of 8 bits, each a counting pass (histogram, digit bases, ranked rounds
-// of 256); up to kOrderMax entries stay in LDS and registers (8 per thread) and skip
-// passes whose digit is the same for every entry; longer lists alternate between
-// `ids` and `scratch` in global memory, which after four passes leaves them in `ids`.
-__global__ __launch_bounds__(kThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
-                                                              uint32_t* __restrict__ ids,
-                                                              uint32_t* __restrict__ scratch,
-                                                              const uint32_t* __restrict__ dkey) {
-  constexpr int RB = 1 << kOrderBits;
+// Depth order of one tile's list: one workgroup per tile (see tile_order.h).
+__global__ __launch_bounds__(kBlockThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
+                                                                   uint32_t* __restrict__ ids,
+                                                                   uint32_t* __restrict__ scratch,
+                                                                   const uint32_t* __restrict__ dkey) {
   const uint2 rg = ranges[blockIdx.x];
   const int64_t start = rg.x, L = (int64_t)rg.y - (int64_t)rg.x;
   if (L <= 1) return;
-  __shared__ uint32_t wcnt[kWaves][RB];
-  __shared__ uint32_t doff[RB];
-  __shared__ uint32_t hcnt[RB];
-  __shared__ uint32_t sh[kWaves];
-  __shared__ __align__(16) uint32_t skey[kOrderMax];
+  __shared__ __align__(16) uint32_t lds[kOrderScratchWords];
   __shared__ uint32_t sid[kOrderMax];
-  const int t = threadIdx.x;
-  if (L <= kThreads) {
-    // one entry per thread, ranked by counting: the entries with a smaller key, and
-    // those with the same key earlier in the list (keys past the end read as 2^32 - 1,
-    // above every depth key)
-    const bool valid = t < L;
-    const uint32_t id = valid ? ids[start + t] : 0u;
-    const uint32_t key = valid ? dkey[id] : 0xFFFFFFFFu;
-    skey[t] = key;
-    __syncthreads();
-    const int n4 = (int)((L + 3) & ~3);
-    uint32_t rank = 0;
-    for (int j = 0; j < n4; j += 4) {
-      const uint4 k4 = *reinterpret_cast<const uint4*>(&skey[j]);
-      rank += (k4.x < key) + (k4.x == key && j < t);
-      rank += (k4.y < key) + (k4.y == key && j + 1 < t);
-      rank += (k4.z < key) + (k4.z == key && j + 2 < t);
-      rank += (k4.w < key) + (k4.w == key && j + 3 < t);
-    }
-    if (valid) ids[start + rank] = id;
-    return;
-  }
-  for (int k = t; k < kWaves * RB; k += kThreads) (&wcnt[0][0])[k] = 0u;
-  uint32_t stamp = 0;  // round counter across the whole sort: stamps never repeat
-  if (L <= kOrderMax) {
-    const int nr = (int)((L + kThreads - 1) / kThreads);
-    uint32_t key[kRounds], id[kRounds];
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const int e = r * kThreads + t;
-      id[r] = e < L ? ids[start + e] : 0u;
-      key[r] = e < L ? dkey[id[r]] : 0u;
-    }
-    for (int p = 0; p < 32 / kOrderBits; ++p) {
-      const int shift = p * kOrderBits;
-      hcnt[t] = 0u;
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r)
-        if (r * kThreads + t < L) atomicAdd(&hcnt[(key[r] >> shift) & (RB - 1)], 1u);
-      __syncthreads();
-      const uint32_t h = hcnt[t];
-      // a digit that every entry shares leaves the order as it is
-      const bool uniform = __syncthreads_or(h == (uint32_t)L) != 0;
-      if (uniform) continue;
-      doff[t] = block_exclusive_scan(h, sh, nullptr);
-      __syncthreads();
-      uint32_t pos[kRounds];
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r) {
-        if (r < nr) {
-          const bool valid = r * kThreads + t < L;
-          const uint32_t digit = valid ? (key[r] >> shift) & (RB - 1) : 0u;
-          stamp += 1u << 16;
-          pos[r] = rank_round<RB>(digit, valid, kOrderBits, stamp, wcnt, doff);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r) {
-        if (r * kThreads + t < L) {
-          skey[pos[r]] = key[r];
-          sid[pos[r]] = id[r];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r) {
-        const int e = r * kThreads + t;
-        if (e < L) {
-          key[r] = skey[e];
-          id[r] = sid[e];
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const int e = r * kThreads + t;
-      if (e < L) ids[start + e] = id[r];
-    }
-    return;
-  }
-  // long lists: the same passes through global memory, chunk by chunk
-  for (int p = 0; p < 32 / kOrderBits; ++p) {
-    const int shift = p * kOrderBits;
-    const uint32_t* __restrict__ src = (p & 1) ? scratch : ids;
-    uint32_t* __restrict__ dst = (p & 1) ? ids : scratch;
-    hcnt[t] = 0u;
-    __syncthreads();
-    for (int64_t e = t; e < L; e += kThreads) atomicAdd(&hcnt[(dkey[src[start + e]] >> shift) & (RB - 1)], 1u);
-    __syncthreads();
-    doff[t] = block_exclusive_scan(hcnt[t], sh, nullptr);
-    __syncthreads();
-    for (int64_t e0 = 0; e0 < L; e0 += kThreads) {
-      if ((stamp >> 16) == 0xFFFFu) {  // stamps used up: clear the counts and start again
-        __syncthreads();
-        for (int k = t; k < kWaves * RB; k += kThreads) (&wcnt[0][0])[k] = 0u;
-        __syncthreads();
-        stamp = 0;
-      }
-      const int64_t e = e0 + t;
-      const bool valid = e < L;
-      const uint32_t v = valid ? src[start + e] : 0u;
-      const uint32_t digit = valid ? (dkey[v] >> shift) & (RB - 1) : 0u;
-      stamp += 1u << 16;
-      const uint32_t pos = rank_round<RB>(digit, valid, kOrderBits, stamp, wcnt, doff);
-      if (valid) dst[start + pos] = v;
-    }
-    __syncthreads();
-  }
+  (void)order_list(ids, scratch, dkey, start, L, order_lds(lds, sid), true);
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per) > 0 ? (int)((n + per - 1) / per) : 1; }
