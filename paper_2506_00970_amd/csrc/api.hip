@@ -259,9 +259,26 @@ int build_views(gs2d_ctx* ctx, const gs2d_view* in, int nv, ViewSet& vs) {
   return GS2D_OK;
 }
 
+// A stride near 97 that is coprime to n: the blend's workgroup -> tile map.
+int tile_stride(int64_t n) {
+  int s = 97;
+  auto gcd = [](int64_t a, int64_t b) {
+    while (b) {
+      const int64_t t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  while (n > 1 && gcd(s, n) != 1) ++s;
+  return s;
+}
+
 BlendArgs blend_args(gs2d_ctx* ctx) {
-  return BlendArgs{ctx->ranges, ctx->pval[ctx->pair_buf], ctx->rec, ctx->views, ctx->last_views.n_views,
-                   (int)ctx->last_views.tiles, ctx->opt.z_near, ctx->opt.filter, ctx->opt.batch};
+  BlendArgs a{ctx->ranges, ctx->pval[ctx->pair_buf], ctx->rec, ctx->views, ctx->last_views.n_views,
+              (int)ctx->last_views.tiles, ctx->opt.z_near, ctx->opt.filter, ctx->opt.batch};
+  a.tile_stride = tile_stride(ctx->last_views.tiles);
+  return a;
 }
 
 // Forward pass of a view set.  With allow_sync the pair count is read back after the
@@ -371,6 +388,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     }
     BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, ctx->views, nv, (int)vs.tiles, ctx->opt.z_near,
                  ctx->opt.filter, ctx->opt.batch};
+    ba.tile_stride = tile_stride(vs.tiles);
     if (tl) {
       ba.loss_part = ctx->part;
       ba.lambda_d = tl->lambda_d;

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
                      srec + (size_t)a.batch * (kLdsRec + 2)};
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
   // each XCD gets every 8th tile: an even share of the dense and sparse image regions
-  const int tile = blockIdx.x;
+  const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   __shared__ float s_red[NW][6];
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
   // each XCD gets every 8th tile: an even share of the dense and sparse image regions
-  const int tile = blockIdx.x;
+  const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const CamF cam = V.cam;
   const int lt = tile - V.tile_base;
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
                      srec + (size_t)a.batch * (kLdsRec + 2)};
   __shared__ float s_red[NW][7];
-  const int tile = blockIdx.x;
+  const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const CamF cam = V.cam;
   const int lt = tile - V.tile_base;

@@ -254,6 +254,10 @@ struct BlendArgs {
   float z_near;
   int filter;
   int batch;
+  // workgroup i blends tile (i * tile_stride) mod n_tiles (tile_stride coprime to
+  // n_tiles): neighbouring tiles, which have lists of similar length, start at
+  // different times and on different compute units
+  int tile_stride = 1;
   // tracking: views with targets also get the tracking loss and its image gradients
   // from the forward blend, each tile's loss sum in loss_part[tile * 8 + 6]
   float* loss_part = nullptr;
