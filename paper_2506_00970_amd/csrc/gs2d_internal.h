@@ -198,7 +198,7 @@ void launch_preprocess_bwd(const float* params, int n, const float* pose, const 
                            int accumulate, float* part, hipStream_t s);
 
 // sort.hip
-constexpr int kScanItems = 2048;   // items per block of the scans and radix passes
+constexpr int kScanItems = 1024;   // keys per block of the radix passes
 constexpr int kMaxDigitBits = 11;  // widest radix digit (2048 bins)
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);

@@ -24,7 +24,7 @@
 //   scatter per block: the digit bases (an LDS scan of the row totals) plus the
 //           block's column give each digit's first output slot, and the block then
 //           clears its column, so that a plane is all zero again once its pass is
-//           done; then 8 rounds of 256 keys: a wave-level multi-split (ballots over
+//           done; then 4 rounds of 256 keys: a wave-level multi-split (ballots over
 //           the digit bits give each lane the mask of lanes holding the same digit),
 //           the same digit's keys in the lower waves of the round (per-wave counts in
 //           LDS, stamped with the round so that they need no clearing), and the
@@ -38,9 +38,9 @@ namespace gs2d {
 namespace {
 
 constexpr int kThreads = kBlockThreads;
-constexpr int kRounds = kScanItems / kThreads;  // 8
+constexpr int kRounds = kScanItems / kThreads;  // 4
 constexpr int kWaves = kBlockWaves;
-constexpr int kBlockShift = 11;  // log2(kScanItems)
+constexpr int kBlockShift = 10;  // log2(kScanItems)
 static_assert(kScanItems == 1 << kBlockShift, "block shift");
 static_assert(kPartItems == kThreads, "duplication blocks are preprocessing blocks");
 constexpr int kDirectParts = 4096;  // up to this many item blocks, each block sums the counts before it
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
 }
 
 // With more item blocks than kDirectParts: exclusive scan, in place, of the per-block
-// pair counts (one workgroup, chunks of 2048), and the totals.
+// pair counts (one workgroup, chunks of kScanItems), and the totals.
 __global__ __launch_bounds__(kThreads) void scan_parts_kernel(uint32_t* __restrict__ part_pairs,
                                                               const uint32_t* __restrict__ part_vis, int n_parts,
                                                               Ctrl* __restrict__ ctrl) {
@@ -240,15 +240,41 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
   const int t = threadIdx.x;
   const int g = blockIdx.x;
   const int64_t j = (int64_t)g * kThreads + t;
+  // the loads that do not wait on the scan go first
+  const uint32_t c = j < a.items ? a.count[j] : 0u;
+  const uint2 rc = c ? a.rect[j] : make_uint2(1u, 0u);
   for (int64_t k = j; k < a.n_tiles; k += (int64_t)gridDim.x * kThreads) a.ranges[k] = make_uint2(0u, 0u);
   __shared__ uint32_t sh[kWaves];
-  uint32_t before;
+  __shared__ unsigned long long sh64[kWaves];
+  uint32_t before, off;
   if (a.scanned) {
     before = a.part_pairs[g];
+    off = before + block_exclusive_scan(c, sh, nullptr);
   } else {
+    // one scan of (earlier blocks' counts, this item's count) packed in 64 bits: the
+    // high half's total is the pair count before the block, the low half's exclusive
+    // prefix the item's place within it
     uint32_t s = 0;
     for (int k = t; k < g; k += kThreads) s += a.part_pairs[k];
-    (void)block_exclusive_scan(s, sh, &before);
+    const int lane = t & 63, wave = t >> 6;
+    const unsigned long long v = ((unsigned long long)s << 32) | c;
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) sh64[wave] = x;
+    __syncthreads();
+    unsigned long long below = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const unsigned long long sw = sh64[w];
+      below += w < wave ? sw : 0ull;
+      all += sw;
+    }
+    before = (uint32_t)(all >> 32);
+    off = before + (uint32_t)((below + x - v) & 0xFFFFFFFFull);
     if (g == 0) {
       uint32_t sp = 0, sv = 0;
       for (int k = t; k < a.n_parts; k += kThreads) {
@@ -264,8 +290,6 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
       }
     }
   }
-  const uint32_t c = j < a.items ? a.count[j] : 0u;
-  uint32_t off = before + block_exclusive_scan(c, sh, nullptr);
   if (c == 0) return;
   if ((int64_t)off + c > a.p_cap) {
     a.ctrl->overflow = 1u;
@@ -275,7 +299,6 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
   const int item = (int)j;
   const ViewDesc& V = a.views[view_of_item(a.views, a.n_views, item)];
   const uint32_t tbase = (uint32_t)V.tile_base, tiles_x = (uint32_t)V.tiles_x;
-  const uint2 rc = a.rect[item];
   const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
   const uint32_t dmask = (1u << a.bits) - 1u;
   for (uint32_t ty = ty0; ty <= ty1; ++ty)
