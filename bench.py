@@ -2,10 +2,10 @@
 """Benchmark: graph-captured 2DGS tracking iterations at 640x480 with 300k surfels on one MI355X.
 
 One step is one tracking iteration of the whole hot path: per-surfel preprocessing,
-the depth sort, scan and pair duplication, the tile sort and ranges, the forward
-blend of colour/depth/normal/opacity, the tracking loss with its masks, the
-pose-only backward blend with the se(3) pose reduction, and the AdamW + Exp pose
-step.  Inputs (a seeded synthetic 6x5x3 m room with 20 boxes, 300,000 surfels,
+the pair duplication, the tile sort with the tile ranges, and the tracking walk (each
+tile's list put in depth order, then the forward blend of colour/depth/normal/
+opacity, the tracking loss with its masks and the pose-only backward with the se(3)
+pose reduction in one walk), and the AdamW + Exp pose step.  Inputs (a seeded synthetic 6x5x3 m room with 20 boxes, 300,000 surfels,
 the target RGB-D frame rendered at the ground-truth pose, a start pose 5 cm / 3 deg
 away) are resident in HBM before timing starts.
 

@@ -67,6 +67,7 @@ def _load():
         _lib.orc_render.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 8
         _lib.orc_backward.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 10
         _lib.orc_preprocess.argtypes = [P, ctypes.c_int64, P, P, P] + [P] * 5
+        _lib.orc_contribution.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_double, P, P]
     return _lib
 
 
@@ -156,6 +157,25 @@ def backward(params, camera, pose, d_rgb=None, d_depth=None, d_normal=None, d_al
     if touched is not None:
         out["touched"] = touched.astype(bool)
     return out
+
+
+def contribution(params, camera, pose, filter: bool = True, margin: float = 1e-5, nthreads=None):
+    """Per-surfel contribution C_k^V = sum over pixels of w_k(p) (eq:contribution).
+
+    Returns {"contrib": [n] FP64, "touched": [n] bool}: touched marks surfels evaluated
+    at a pixel whose smallest decision margin is below `margin` (their pixel sets may
+    differ in float32).
+    """
+    lib = _load()
+    p, T = _prep(params, pose)
+    c = _cam(camera)
+    n = p.shape[1]
+    contrib = np.zeros(n)
+    touched = np.zeros(n, dtype=np.uint8)
+    k = _consts(filter, True)
+    lib.orc_contribution(_ptr(p), n, ctypes.byref(c), _ptr(T), ctypes.byref(k), _threads(nthreads),
+                         ctypes.c_double(margin), _ptr(contrib), _ptr(touched))
+    return {"contrib": contrib, "touched": touched.astype(bool)}
 
 
 def preprocess(params, camera, pose, filter: bool = True):

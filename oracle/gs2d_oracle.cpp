@@ -393,6 +393,50 @@ int orc_render(const double* params, int64_t n, const OrcCamera* c, const double
   return 0;
 }
 
+// Per-surfel contribution to the rendered frame (eq:weight, eq:contribution): the
+// sum over pixels of the surfel's blending weight w_k(p) = alpha_k T_k, over the same
+// composited pairs as the forward.  contrib[n]; touched[n] (may be null) is set for
+// every surfel evaluated at a pixel whose smallest decision margin (fmargin) is below
+// `margin`, where a float32 renderer may composite a different set.  Per-thread sums
+// are added in thread order.
+int orc_contribution(const double* params, int64_t n, const OrcCamera* c, const double* pose,
+                     const OrcConsts* k, int nthreads, double margin, double* contrib, uint8_t* touched) {
+  Cam cam; Consts kk;
+  unpack(c, k, cam, kk);
+  if (nthreads < 1) nthreads = 1;
+  Scene sc;
+  build_scene(params, n, cam, pose, kk, nthreads, sc);
+  std::vector<std::vector<double>> acc((size_t)nthreads, std::vector<double>((size_t)n, 0.0));
+  std::vector<std::vector<uint8_t>> tch((size_t)nthreads, std::vector<uint8_t>(touched ? (size_t)n : 0, 0));
+  parallel_rows(cam.height, nthreads, [&](int t, int y) {
+    std::vector<Entry> list;
+    for (int x = 0; x < cam.width; ++x) {
+      list.clear();
+      double out[8], tf, fm, gm;
+      int cnt;
+      composite_pixel(sc, x, y, out, tf, cnt, fm, gm, &list);
+      for (const Entry& e : list) acc[(size_t)t][(size_t)e.h.id] += e.h.alpha * e.T;
+      if (touched && fm < margin) {
+        for (int64_t i : sc.rows[(size_t)y]) {
+          const Surf& s = sc.surf[(size_t)i];
+          if (!kk.use_rect || (x >= s.rect[0] && x <= s.rect[1])) tch[(size_t)t][(size_t)i] = 1;
+        }
+      }
+    }
+  });
+  for (int64_t i = 0; i < n; ++i) {
+    double sum = 0.0;
+    uint8_t tt = 0;
+    for (int t = 0; t < nthreads; ++t) {
+      sum += acc[(size_t)t][(size_t)i];
+      if (touched) tt |= tch[(size_t)t][(size_t)i];
+    }
+    contrib[i] = sum;
+    if (touched) touched[i] = tt;
+  }
+  return 0;
+}
+
 // Reverse mode of the forward above for dL/d(images) given per pixel.
 //
 // d_params [15][n] (may be null): gradient to mu, t_u, t_v (world frame), s_u,
