@@ -102,6 +102,96 @@ def cpu_baseline(room_params, cam, start, tgt_rgb, tgt_depth, budget_s=20.0):
                       f"'{cpu_model()}' ({os.cpu_count()} logical CPUs)"}
 
 
+def map_bench(args):
+    """Map bookkeeping: the forward blend with and without per-surfel contributions
+    (eq:contribution) on the tracking workload, and each bookkeeping kernel at map sizes
+    against the HBM roofline.  One JSON line."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_00970_amd import Rasterizer, mapstate
+
+    dev = torch.device("cuda", 0)
+    cam = synth.Camera(640, 480, 525.0, 525.0, 320.0, 240.0)
+    log("building the synthetic room")
+    room = synth.make_room(args.n, seed=args.seed)
+    pose_np = synth.room_camera(room, seed=args.seed)
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    P, pose = to_dev(room.params), to_dev(pose_np.reshape(12))
+    blend = {}
+    for contrib in (False, True):
+        r = Rasterizer(device=0, profile=2)
+        for _ in range(3):
+            r.render_batch([(P, cam, pose)], contribution=contrib)
+        torch.cuda.synchronize()
+        r.profile(reset=True)
+        for _ in range(args.profile_steps):
+            r.render_batch([(P, cam, pose)], contribution=contrib)
+        fam = r.profile(reset=True)["families"]
+        blend["with_contribution" if contrib else "plain"] = {
+            k: fam[k]["ms"] / fam[k]["launches"] for k in fam if fam[k]["launches"]}
+        del r
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    kernels = {}
+    g = np.random.default_rng(args.seed)
+    for n in (1_000_000, 16_000_000):
+        log(f"map kernels at {n} splats")
+        params = torch.empty((15, n), dtype=torch.float32, device=dev)
+        params.normal_()
+        ca = torch.rand(n, device=dev)
+        cb = torch.rand(n, device=dev)
+        closest = torch.from_numpy(g.integers(0, 8, n).astype(np.int32)).to(dev)
+        delta = to_dev(np.tile(np.hstack([np.eye(3), np.full((3, 1), 0.01)]).reshape(1, 12), (8, 1)))
+        st = mapstate.MapState(n, dev)
+        rm = mapstate.prune_mask(ca, closest, 3)
+        kept = float(n - int(rm.sum().item()))
+        work = torch.empty(max(1, mapstate._lib.load().gs2d_compact_workspace(n)), dtype=torch.int32, device=dev)
+        out = torch.empty_like(params)
+        n_out = torch.empty(1, dtype=torch.int32, device=dev)
+        moved = float(int((closest < 8).sum().item()))
+        # algorithmic HBM bytes per call: every input read once, every output written once
+        cases = {
+            "covisibility": (lambda: mapstate.covisibility_counts(ca, cb), 8.0 * n),
+            "prune_mask": (lambda: mapstate.prune_mask(ca, closest, 3), 9.0 * n),
+            "compact_15_planes": (lambda: mapstate._lib.check(mapstate._lib.load().gs2d_compact(
+                params.data_ptr(), n, 15, n, rm.data_ptr(), out.data_ptr(), n, n_out.data_ptr(), work.data_ptr(),
+                mapstate._stream(dev))), 2.0 * n + 2 * 60.0 * kept),
+            "state_update": (lambda: st.update(params, ca, pose, 9, inactive_after=5), 48.0 * n),
+            "correct": (lambda: mapstate.correct(params, closest, delta), 4.0 * n + 72.0 * moved),
+        }
+        for name, (fn, nbytes) in cases.items():
+            ms = timed(fn, args.profile_steps)
+            kernels[f"{name}@{n}"] = {"ms": ms, "algorithmic_bytes": nbytes, "GB/s": nbytes / (ms * 1e-3) / 1e9,
+                                      "frac_hbm": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del params, ca, cb, closest, st, rm, work, out
+        torch.cuda.empty_cache()
+    top = kernels["state_update@16000000"]
+    out = {
+        "metric": "map bookkeeping: forward blend with per-surfel contribution, and map kernels",
+        "value": top["GB/s"], "unit": "GB/s", "n_gpus": 1, "steps": args.profile_steps, "warmup": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"forward render 640x480 f=525, {args.n}-surfel synthetic room; map kernels on "
+                               "1M and 16M random splats", "n_surfels": args.n},
+        "roofline": {"bound": "hbm", "kernel": "state_update@16M", "achieved": top["GB/s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": top["frac_hbm"], "traffic": None},
+        "blend_ms_per_launch": blend,
+        "map_kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,11 +207,15 @@ def main():
                          "when the file is absent")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 3 plain device copies of 256 MiB (reference for HBM traffic counters)")
+    ap.add_argument("--map", action="store_true",
+                    help="measure the map bookkeeping (contribution blend and map kernels) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path: "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.map:
+        return map_bench(args)
 
     import numpy as np
     import torch

@@ -113,6 +113,10 @@ typedef struct gs2d_view {
   float* depth;
   float* normal;
   float* alpha;
+  /* optional [n] out: each surfel's contribution to this view, the sum over pixels of
+   * its blending weight (Sec. "Tracking and Keyframe Selection", eq:contribution);
+   * float atomics, so the summation order varies between runs.  NULL: not wanted. */
+  float* contrib;
 } gs2d_view;
 
 /* Gradients of one view for gs2d_render_backward_batch: image gradients in (any may

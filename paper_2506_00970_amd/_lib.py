@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs2d.so")
 INCLUDE_DIR = os.path.join(os.path.dirname(HERE), "include")
 HEADER_PATH = os.path.join(INCLUDE_DIR, "gs2d.h")
-HEADERS = [os.path.join(INCLUDE_DIR, h) for h in ("gs2d.h", "gs2d_warm.h")]
+HEADERS = [os.path.join(INCLUDE_DIR, h) for h in ("gs2d.h", "gs2d_warm.h", "gs2d_map.h")]
 
 OK = 0
 ERR_INVALID_ARG = -1
@@ -66,7 +66,7 @@ class WsAdamW(ctypes.Structure):
 class View(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
-                ("alpha", ctypes.c_void_p)]
+                ("alpha", ctypes.c_void_p), ("contrib", ctypes.c_void_p)]
 
 
 class ViewGrad(ctypes.Structure):
@@ -135,6 +135,17 @@ _SIGS = {
     "gs2d_ws_adamw_step": ([_P, ctypes.POINTER(WsAdamW), _P], ctypes.c_int),
     "gs2d_warm_start": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, _P, _P, ctypes.c_float,
                          ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    # map bookkeeping (gs2d_map.h)
+    "gs2d_covisibility_workspace": ([ctypes.c_int64], ctypes.c_int64),
+    "gs2d_covisibility": ([_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, _P], ctypes.c_int),
+    "gs2d_keyframe_test": ([_P, _P, _P, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
+    "gs2d_prune_mask": ([_P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P], ctypes.c_int),
+    "gs2d_compact_workspace": ([ctypes.c_int64], ctypes.c_int64),
+    "gs2d_compact": ([_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, _P, ctypes.c_int64, _P, _P, _P],
+                     ctypes.c_int),
+    "gs2d_map_state_update": ([_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                               _P, _P, _P], ctypes.c_int),
+    "gs2d_map_correct": ([_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
 }
 
 

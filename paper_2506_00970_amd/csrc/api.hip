@@ -241,6 +241,7 @@ int build_views(gs2d_ctx* ctx, const gs2d_view* in, int nv, ViewSet& vs) {
     d.depth = g.depth;
     d.normal = g.normal;
     d.alpha = g.alpha;
+    d.contrib = g.contrib;
     d.cam = camf(g.camera);
     d.n = (int)g.n;
     d.tiles_x = (g.camera.width + tw - 1) / tw;
@@ -395,6 +396,8 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
       ba.use_masks = tl->use_masks;
     }
     if (blend) {
+      for (int k = 0; k < nv; ++k)
+        if (vs.v[k].contrib) launch_fill_f32(vs.v[k].contrib, 0.f, vs.v[k].n, s);
       ProfScope ps(ctx, kBlendFwd, s);
       launch_blend_fwd(ba, tw, th, ctx->t_final, ctx->last, work_ptr(ctx, s), s);
     }

@@ -196,13 +196,14 @@ struct FwdPix {
   bool done;
 };
 
-// Front-to-back compositing of one evaluated entry (list position pos).
-__device__ __forceinline__ void composite(FwdPix& s, int code, const Hit& h, const Rec& r, int pos) {
-  if (s.done || code != 2) return;
+// Front-to-back compositing of one evaluated entry (list position pos); returns the
+// entry's blending weight at this pixel (0 when it is not composited).
+__device__ __forceinline__ float composite(FwdPix& s, int code, const Hit& h, const Rec& r, int pos) {
+  if (s.done || code != 2) return 0.f;
   const float Tn = s.T * (1.0f - h.alpha);
   if (Tn < kTMin) {
     s.done = true;
-    return;
+    return 0.f;
   }
   const float w = h.alpha * s.T;
   s.cr = fmaf(w, r.c4.y, s.cr);
@@ -215,6 +216,36 @@ __device__ __forceinline__ void composite(FwdPix& s, int code, const Hit& h, con
   s.co += w;
   s.T = Tn;
   s.lastj = pos + 1;
+  return w;
+}
+
+// Sum over the wave, left in lane 63 (other lanes hold partial sums): an inclusive scan
+// inside each 16-lane row by DPP row shifts, then the row totals carried forward by the
+// row broadcasts of lanes 15 and 31.  Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_total_lane63(float x) {
+  x = dpp_add<0x111, 0xf>(x);  // row_shr:1
+  x = dpp_add<0x112, 0xf>(x);  // row_shr:2
+  x = dpp_add<0x114, 0xf>(x);  // row_shr:4
+  x = dpp_add<0x118, 0xf>(x);  // row_shr:8
+  x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x = dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+// eq:contribution: the wave's weights of one entry, added to the surfel's sum (one
+// atomic per wave and entry, none where the wave has no weight for it).  Every lane of
+// the wave calls it.
+__device__ __forceinline__ void add_contribution(float* contrib, uint32_t surfel, float w, int lane) {
+  if (__ballot(w != 0.f) == 0ull) return;
+  const float ws = wave_total_lane63(w);
+  // a global (not flat) atomic: flat ones also hold the LDS counter the walk waits on
+  using gfloat = __attribute__((address_space(1))) float;
+  if (lane == 63)
+    __hip_atomic_fetch_add((gfloat*)(contrib + surfel), ws, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int TW, int TH, bool PROF>
@@ -225,6 +256,7 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   extern __shared__ float4 srec[];
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
                      srec + (size_t)a.batch * (kLdsRec + 2)};
+  uint32_t* const sids = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * (kLdsRec + 3));
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
   // each XCD gets every 8th tile: an even share of the dense and sparse image regions
   const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
@@ -241,14 +273,19 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
   FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
+  // read once: the contribution atomics could alias the view table for the compiler
+  float* const contrib = V.contrib;
+  const uint32_t item_base = (uint32_t)V.item_base;
   int n_eval = 0, n_cov = 0;
   for (int b0 = start; b0 < end; b0 += a.batch) {
     if (__syncthreads_count(!s.done) == 0) break;
     const int nb = min(a.batch, end - b0);
     for (int k = t; k < nb * kRecF4; k += NT) {
       const int j = k / kRecF4, f = k - j * kRecF4;
-      const float4 v = a.rec[(size_t)a.pval[b0 + j] * kRecF4 + f];
+      const uint32_t id = a.pval[b0 + j];
+      const float4 v = a.rec[(size_t)id * kRecF4 + f];
       if (f < kLdsRec) srec[j * kLdsRec + f] = v;
+      if (f == 0) sids[j] = id;
       stage_cull(cull, j, f, v);
     }
     __syncthreads();
@@ -264,6 +301,7 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
         const bool two = m != 0ull;
         const int j2 = two ? c0 + __builtin_ctzll(m) : j1;
         if (two) m &= m - 1ull;
+        float w1 = 0.f, w2 = 0.f;
         if (!s.done) {
           const Rec r1 = load_rec(srec, j1), r2 = load_rec(srec, j2);
           Hit h1, h2;
@@ -273,14 +311,18 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
             n_eval += 1;
             n_cov += k1 > 0;
           }
-          composite(s, k1, h1, r1, pos0 + j1);
+          w1 = composite(s, k1, h1, r1, pos0 + j1);
           if (two && !s.done) {
             if (PROF) {
               n_eval += 1;
               n_cov += k2 > 0;
             }
-            composite(s, k2, h2, r2, pos0 + j2);
+            w2 = composite(s, k2, h2, r2, pos0 + j2);
           }
+        }
+        if (contrib) {  // the view, and so this branch, is uniform over the workgroup
+          add_contribution(contrib, sids[j1] - item_base, w1, lane);
+          if (two) add_contribution(contrib, sids[j2] - item_base, w2, lane);
         }
         if (__ballot(!s.done) == 0ull) break;
       }
@@ -794,7 +836,8 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
 
 template <int TW, int TH>
 void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * (kLdsRec + 3) * sizeof(float4);
+  // staged records and their cull data, then the staged surfel ids
+  const size_t lds = (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + sizeof(uint32_t));
   if (work)
     blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
   else

@@ -57,6 +57,7 @@ struct ViewDesc {
   const float* tgt_rgb;  // tracking targets
   const float* tgt_depth;
   float* d_pose;         // [6] pose gradient out (nullable)
+  float* contrib;        // [n] per-surfel contribution out (nullable; forward blend)
   CamF cam;
   int n;                 // surfels of this view
   int item_base;         // first (view, surfel) item

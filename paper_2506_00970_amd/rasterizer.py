@@ -48,6 +48,7 @@ class RenderOut:
     normal: torch.Tensor
     alpha: torch.Tensor
     generation: int
+    contrib: torch.Tensor | None = None  # [n] per-surfel contribution (render_batch(contribution=True))
 
 
 class Rasterizer:
@@ -115,11 +116,13 @@ class Rasterizer:
         self._last = (params, pose, cam)  # keep the inputs alive until the backward
         return RenderOut(rgb, depth, normal, alpha, int(gen.value))
 
-    def render_batch(self, views) -> list:
+    def render_batch(self, views, contribution: bool = False) -> list:
         """Render several views in one batched launch.
 
         ``views``: sequence of (params [15, N], camera, pose [12]); views may share a
-        params tensor.  Returns one RenderOut per view (all with the same generation).
+        params tensor.  Returns one RenderOut per view (all with the same generation);
+        with ``contribution`` each also carries every surfel's contribution to its view
+        (eq:contribution).
         """
         views = list(views)
         if not 1 <= len(views) <= _lib.MAX_VIEWS:
@@ -137,15 +140,16 @@ class Rasterizer:
                  torch.empty((H, W), dtype=torch.float32, device=self.device),
                  torch.empty((3, H, W), dtype=torch.float32, device=self.device),
                  torch.empty((H, W), dtype=torch.float32, device=self.device)]
+            c = torch.empty(n, dtype=torch.float32, device=self.device) if contribution else None
             arr[k] = _lib.View(params.data_ptr(), n, cam, pose.data_ptr(), o[0].data_ptr(), o[1].data_ptr(),
-                               o[2].data_ptr(), o[3].data_ptr())
-            outs.append(o)
+                               o[2].data_ptr(), o[3].data_ptr(), None if c is None else c.data_ptr())
+            outs.append(o + [c])
             keep.append((params, pose, cam))
         gen = ctypes.c_uint32(0)
         _lib.check(self._lib.gs2d_render_batch(self._ctx, arr, len(views), ctypes.byref(gen), self._stream()),
                    self._ctx)
         self._last = keep
-        return [RenderOut(o[0], o[1], o[2], o[3], int(gen.value)) for o in outs]
+        return [RenderOut(o[0], o[1], o[2], o[3], int(gen.value), o[4]) for o in outs]
 
     def backward_batch(self, generation: int, grads, params_grad=True, accumulate: bool = False):
         """Reverse mode of a batched render.
