@@ -78,9 +78,11 @@ def depth_normals(depth: torch.Tensor, camera) -> torch.Tensor:
     dx = X[:, 1:-1, 2:] - X[:, 1:-1, :-2]
     dy = X[:, 2:, 1:-1] - X[:, :-2, 1:-1]
     c = torch.linalg.cross(dx, dy, dim=0)
-    norm = torch.sqrt((c * c).sum(dim=0))
-    safe = torch.where(norm > 0, norm, torch.ones_like(norm))
-    inner = torch.where(norm > 0, c / safe, torch.zeros_like(c))
+    # N_D = 0 where the cross product vanishes; the square root is taken of a guarded
+    # value so that its derivative stays finite there (the gradient is then 0)
+    n2 = (c * c).sum(dim=0)
+    norm = torch.sqrt(torch.where(n2 > 0, n2, torch.ones_like(n2)))
+    inner = torch.where(n2 > 0, c / norm, torch.zeros_like(c))
     return torch.nn.functional.pad(inner, (1, 1, 1, 1))
 
 
@@ -104,5 +106,5 @@ def mapping_loss(rgb, depth, normal, tgt_rgb, tgt_depth, camera, w_l1=W_L1, w_ss
     loss = per_pixel.sum() / hw
     loss.backward()
     terms = tuple(float(t.detach().sum() / hw) for t in (l1, dssim, ld, ln))
-    return {"loss": float(loss), "terms": terms, "d_rgb": I.grad.numpy(), "d_depth": D.grad.numpy(),
+    return {"loss": float(loss.detach()), "terms": terms, "d_rgb": I.grad.numpy(), "d_depth": D.grad.numpy(),
             "d_normal": N.grad.numpy()}

@@ -176,3 +176,26 @@ def test_terms_of_constant_offsets():
     assert abs(l1 - 0.35) < 1e-12 and abs(ld - 0.3) < 1e-12
     assert abs(out["loss"] - (0.875 * 0.35 + 0.125 * dssim + 0.5 * 0.3 + 0.02 * ln)) < 1e-12
     assert 0.0 < dssim < 1.0
+
+
+def test_gradients_where_the_depth_normal_vanishes():
+    """Zero depth (no surface) around some pixels: N_D = 0 there with a zero, finite
+    gradient, and finite differences still agree everywhere else."""
+    g = np.random.default_rng(6)
+    H, W = 17, 23
+    D = _plane_depth(np.array([0.2, -0.1, 1.0]), 2.5, CAM)
+    D[5:11, 6:14] = 0.0
+    rgb, tgt = g.random((3, H, W)), g.random((3, H, W))
+    N = g.standard_normal((3, H, W))
+    out = ml.mapping_loss(rgb, D, N, tgt, D + 0.1, CAM)
+    assert all(np.all(np.isfinite(out[k])) for k in ("d_rgb", "d_depth", "d_normal"))
+    nd = ml.depth_normals(torch.tensor(D), CAM).numpy()
+    assert np.all(nd[:, 6:10, 7:13] == 0) and np.all(out["d_normal"][:, 6:10, 7:13] == 0)
+    h = 1e-6
+    for idx in [(4, 6), (8, 9), (11, 14), (2, 20)]:
+        Dp, Dm = D.copy(), D.copy()
+        Dp[idx] += h
+        Dm[idx] -= h
+        fd = (ml.mapping_loss(rgb, Dp, N, tgt, D + 0.1, CAM)["loss"] -
+              ml.mapping_loss(rgb, Dm, N, tgt, D + 0.1, CAM)["loss"]) / (2 * h)
+        assert abs(fd - out["d_depth"][idx]) < 1e-7, (idx, fd, out["d_depth"][idx])
