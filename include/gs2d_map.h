@@ -1,6 +1,7 @@
-/* Map bookkeeping around the rasterizer: covisibility and keyframe selection,
- * contribution pruning with stable compaction, the per-splat map state, and map
- * correction after pose-graph optimisation.
+/* The mapping side around the rasterizer: the mapping loss with its image
+ * gradients, covisibility and keyframe selection, contribution pruning with stable
+ * compaction, the per-splat map state, and map correction after pose-graph
+ * optimisation.
  *
  * Per-splat contributions come from the forward render (gs2d_view.contrib,
  * eq:contribution).  Every pointer is caller-owned device memory; every call is
@@ -19,6 +20,36 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Weights of the mapping loss's four terms.  The table of parameters gives 0.125 to
+ * the SSIM term (so 0.875 to the L1 term), w_d = 0.5 and w_n = 0.02: the defaults. */
+typedef struct gs2d_mapping_weights {
+  float w_l1, w_ssim, w_d, w_n;
+} gs2d_mapping_weights;
+
+/* Floats of workspace gs2d_mapping_loss needs for a width x height image. */
+GS2D_API int64_t gs2d_mapping_loss_workspace(int32_t width, int32_t height);
+
+/* Mapping loss of Sec. "Mapping" on one view's rendered images (planar float32:
+ * rgb [3][H][W], depth [H][W], normal [3][H][W]) against the observed tgt_rgb and
+ * tgt_depth:
+ *   L_m = (1/HW) sum_p [ w_l1 |rgb - tgt_rgb|_1 + w_ssim (1 - SSIM(p))
+ *                        + w_d |depth - tgt_depth| + w_n (1 - N_D(p) . normal(p)) ],
+ * with SSIM(p) the mean over RGB of the SSIM map (11 x 11 Gaussian window, sigma 1.5,
+ * zero outside the image, C1 = 0.01^2, C2 = 0.03^2) and N_D the normals of the
+ * rendered depth (eq:normal_fromD): the normalised cross product of the central
+ * differences X(x+1, y) - X(x-1, y) and X(x, y+1) - X(x, y-1) of the back-projected
+ * pixels X = depth ((x - cx)/fx, (y - cy)/fy, 1), x the column; 0 on the image border
+ * and where the cross product vanishes.  weights NULL: the defaults above.
+ * Writes loss (device float [5]) = {L_m, and the image means of |d rgb|_1,
+ * 1 - SSIM, |d depth| and 1 - N_D . N}, and the gradients of L_m to the three
+ * rendered images (d|x|/dx = 0 at 0) to d_rgb, d_depth, d_normal (overwritten).
+ * work: device float [gs2d_mapping_loss_workspace(W, H)].  Deterministic: fixed-order
+ * sums, no atomics. */
+GS2D_API int gs2d_mapping_loss(const gs2d_camera* camera, const float* rgb, const float* depth, const float* normal,
+                               const float* tgt_rgb, const float* tgt_depth, const gs2d_mapping_weights* weights,
+                               float* loss, float* d_rgb, float* d_depth, float* d_normal, float* work,
+                               hipStream_t stream);
 
 /* Words of workspace gs2d_covisibility needs for n splats (at most 2048). */
 GS2D_API int64_t gs2d_covisibility_workspace(int64_t n);

@@ -63,6 +63,11 @@ class WsAdamW(ctypes.Structure):
                 ("weight_decay", ctypes.c_float)]
 
 
+class MappingWeights(ctypes.Structure):
+    _fields_ = [("w_l1", ctypes.c_float), ("w_ssim", ctypes.c_float), ("w_d", ctypes.c_float),
+                ("w_n", ctypes.c_float)]
+
+
 class View(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
@@ -146,6 +151,9 @@ _SIGS = {
     "gs2d_map_state_update": ([_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
                                _P, _P, _P], ctypes.c_int),
     "gs2d_map_correct": ([_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "gs2d_mapping_loss_workspace": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
+    "gs2d_mapping_loss": ([ctypes.POINTER(Camera), _P, _P, _P, _P, _P, ctypes.POINTER(MappingWeights), _P, _P, _P,
+                           _P, _P, _P], ctypes.c_int),
 }
 
 

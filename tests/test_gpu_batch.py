@@ -58,11 +58,12 @@ def test_batch_backward_shared_params(pkg):
     views = [(P, cams[k], dev(poses[k].reshape(12))) for k in range(3)]
     outs = r.render_batch(views)
     g = np.random.default_rng(0)
-    grads = []
+    grads, grads_np = [], []
     for cam in cams:
         H, W = cam.height, cam.width
-        grads.append({"d_rgb": dev(g.normal(size=(3, H, W)) / (H * W)),
-                      "d_depth": dev(g.normal(size=(H, W)) / (H * W))})
+        grads_np.append({"d_rgb": (g.normal(size=(3, H, W)) / (H * W)).astype(np.float32),
+                         "d_depth": (g.normal(size=(H, W)) / (H * W)).astype(np.float32)})
+        grads.append({k: dev(v) for k, v in grads_np[-1].items()})
     res = r.backward_batch(outs[0].generation, grads, params_grad=True)
     torch.cuda.synchronize()
     dp_batch = host(res[0][0])
@@ -76,8 +77,8 @@ def test_batch_backward_shared_params(pkg):
         np.testing.assert_allclose(host(res[k][1]), host(d_pose), rtol=1e-4, atol=1e-6 * np.abs(host(d_pose)).max())
     check_grads(dp_batch, total, rel=1e-4, floor=1e-5)
     # and against the oracle's summed gradient
-    ref = sum(oracle.backward(room.params, cams[k], poses[k], d_rgb=host(grads[k]["d_rgb"]),
-                              d_depth=host(grads[k]["d_depth"]))["d_params"] for k in range(3))
+    ref = sum(oracle.backward(room.params, cams[k], poses[k], d_rgb=grads_np[k]["d_rgb"],
+                              d_depth=grads_np[k]["d_depth"])["d_params"] for k in range(3))
     check_grads(dp_batch, ref)
 
 

@@ -122,17 +122,18 @@ def test_gpu_backward_parity_random(gs, seed):
 
 
 def test_gpu_backward_frame_loss(gs):
-    """The single-frame workload: L1 on rgb, depth and normal against a second seeded render."""
+    """The single-frame workload: L1 on rgb, depth and normal against a second seeded
+    render; the image gradients come from the oracle's renders and feed both sides."""
     s = synth.random_surfels(2000, seed=0)
     t = synth.random_surfels(2000, seed=1)
     r = gs.Rasterizer()
-    _, tgt = _render(r, t.params, t.camera, t.pose)
-    out, img = _render(r, s.params, s.camera, s.pose)
-    _, d_rgb, d_depth, d_normal = oloss.frame_loss(img["rgb"], img["depth"], img["normal"], tgt["rgb"],
+    tgt = oracle.render(t.params, t.camera, t.pose)
+    ref = oracle.render(s.params, s.camera, s.pose)
+    _, d_rgb, d_depth, d_normal = oloss.frame_loss(ref["rgb"], ref["depth"], ref["normal"], tgt["rgb"],
                                                    tgt["depth"], tgt["normal"])
     grads = {"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": d_normal, "d_alpha": None}
+    out, _ = _render(r, s.params, s.camera, s.pose)
     dp, dpose = _gpu_backward(r, out.generation, grads)
-    ref = oracle.render(s.params, s.camera, s.pose)
     og = oracle.backward(s.params, s.camera, s.pose, **grads, watch=ref["gmargin"] < 1e-5)
     check_grads(dp, og["d_params"], skip=og["touched"])
     check_pose(dpose, og["pose_paper"])
@@ -323,20 +324,25 @@ def test_gpu_tile_batch_invariance(gs, tile, batch):
 
 
 def test_gpu_tracking_loss_parity(gs):
+    """The loss kernel on the oracle's renders (rounded to float32, the kernel's input
+    precision) against the oracle's loss of the same float32 images."""
     room, pose = room_scene(300_000, seed=2, cam_seed=2)
     start = synth.perturb_pose(pose, 0.05, 3.0, seed=5)
     r = gs.Rasterizer()
-    tgt_out, tgt = _render(r, room.params, ROOM_CAM, pose)
-    out, img = _render(r, room.params, ROOM_CAM, start)
-    loss, d_rgb, d_depth = r.tracking_loss(ROOM_CAM, out.rgb, out.depth, out.normal, out.alpha, tgt_out.rgb,
-                                           tgt_out.depth, lambda_d=0.7, use_masks=True)
+    f32 = lambda a: np.asarray(a, dtype=np.float32)
+    tgt = {k: f32(v) for k, v in oracle.render(room.params, ROOM_CAM, pose).items() if k in ("rgb", "depth")}
+    img = {k: f32(v) for k, v in oracle.render(room.params, ROOM_CAM, start).items()
+           if k in ("rgb", "depth", "normal", "alpha")}
+    g = {k: dev(v) for k, v in img.items()}
+    loss, d_rgb, d_depth = r.tracking_loss(ROOM_CAM, g["rgb"], g["depth"], g["normal"], g["alpha"], dev(tgt["rgb"]),
+                                           dev(tgt["depth"]), lambda_d=0.7, use_masks=True)
     torch.cuda.synchronize()
     L, e_rgb, e_depth, m = oloss.tracking_loss(img["rgb"], img["depth"], img["normal"], img["alpha"], tgt["rgb"],
                                                tgt["depth"], ROOM_CAM, lambda_d=0.7)
     assert float(loss) == pytest.approx(L, rel=1e-5)
     np.testing.assert_allclose(host(d_rgb), e_rgb, rtol=1e-6, atol=1e-12)
     np.testing.assert_allclose(host(d_depth), e_depth, rtol=1e-6, atol=1e-12)
-    loss2, _, _ = r.tracking_loss(ROOM_CAM, out.rgb, out.depth, None, None, tgt_out.rgb, tgt_out.depth,
+    loss2, _, _ = r.tracking_loss(ROOM_CAM, g["rgb"], g["depth"], None, None, dev(tgt["rgb"]), dev(tgt["depth"]),
                                   lambda_d=1.0, use_masks=False)
     L2 = oloss.tracking_loss(img["rgb"], img["depth"], img["normal"], img["alpha"], tgt["rgb"], tgt["depth"],
                              ROOM_CAM, use_masks=False)[0]
@@ -408,10 +414,13 @@ def test_gpu_track_first_step_matches_oracle(gs):
     room, pose = room_scene(300_000, seed=0, cam_seed=0)
     start = synth.perturb_pose(pose, 0.05, 3.0, seed=1)
     r = gs.Rasterizer()
-    tgt, timg = _render(r, room.params, ROOM_CAM, pose)
+    # the observed frame: the oracle's render at the true pose, in float32 on both sides
+    timg = {k: np.asarray(v, dtype=np.float32) for k, v in oracle.render(room.params, ROOM_CAM, pose).items()
+            if k in ("rgb", "depth")}
     p = dev(start.reshape(12))
     lr = (1e-3, 1e-3, 1e-3, 3e-3, 3e-3, 3e-3)
-    _, ph, lh = r.track(dev(room.params), ROOM_CAM, p, tgt.rgb, tgt.depth, n_iters=1, lr=lr, use_graph=False)
+    _, ph, lh = r.track(dev(room.params), ROOM_CAM, p, dev(timg["rgb"]), dev(timg["depth"]), n_iters=1, lr=lr,
+                        use_graph=False)
     torch.cuda.synchronize()
     ref = oracle.render(room.params, ROOM_CAM, start)
     L, d_rgb, d_depth, _ = oloss.tracking_loss(ref["rgb"], ref["depth"], ref["normal"], ref["alpha"], timg["rgb"],
