@@ -103,8 +103,10 @@ def cpu_baseline(room_params, cam, start, tgt_rgb, tgt_depth, budget_s=20.0):
 
 
 def map_bench(args):
-    """Map bookkeeping: the forward blend with and without per-surfel contributions
-    (eq:contribution) on the tracking workload, and each bookkeeping kernel at map sizes
+    """The mapping side: the forward blend with and without per-surfel contributions
+    (eq:contribution) on the tracking workload; the mapping loss of one view and a
+    mapping iteration over a 5-keyframe window (batched render, each view's loss, the
+    batched backward to all surfel parameters); each bookkeeping kernel at map sizes
     against the HBM roofline.  One JSON line."""
     import numpy as np
     import torch
@@ -119,6 +121,17 @@ def map_bench(args):
     pose_np = synth.room_camera(room, seed=args.seed)
     to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
     P, pose = to_dev(room.params), to_dev(pose_np.reshape(12))
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     blend = {}
     for contrib in (False, True):
         r = Rasterizer(device=0, profile=2)
@@ -133,16 +146,39 @@ def map_bench(args):
             k: fam[k]["ms"] / fam[k]["launches"] for k in fam if fam[k]["launches"]}
         del r
 
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+    # the mapping loss of one 640x480 view, and a mapping iteration over the window of
+    # N_a + N_i = 5 keyframes: batched render, each view's loss, batched full backward
+    from paper_2506_00970_amd import maploss
+
+    r = Rasterizer(device=0, profile=2)
+    poses = [to_dev(synth.room_camera(room, seed=args.seed + k).reshape(12)) for k in range(5)]
+    tposes = [to_dev(synth.perturb_pose(synth.room_camera(room, seed=args.seed + k), 0.02, 1.0, seed=k).reshape(12))
+              for k in range(5)]
+    targets = []
+    for tp in tposes:
+        o = r.render(P, cam, tp)
+        targets.append((o.rgb.clone(), o.depth.clone()))
+    o = r.render(P, cam, poses[0])
+    loss_ms = timed(lambda: maploss.mapping_loss(o.rgb, o.depth, o.normal, targets[0][0], targets[0][1], cam),
+                    args.profile_steps)
+
+    def mapping_iteration():
+        outs = r.render_batch([(P, cam, p) for p in poses])
+        grads = []
+        for k, out in enumerate(outs):
+            _, d_rgb, d_depth, d_normal = maploss.mapping_loss(out.rgb, out.depth, out.normal, targets[k][0],
+                                                               targets[k][1], cam)
+            grads.append({"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": d_normal})
+        r.backward_batch(outs[0].generation, grads, params_grad=True)
+
+    mapping_iteration()
+    torch.cuda.synchronize()
+    r.profile(reset=True)
+    iter_ms = timed(mapping_iteration, args.profile_steps)
+    fam = r.profile(reset=True)["families"]
+    mapping = {"loss_ms_640x480": loss_ms, "iteration_ms_5_views": iter_ms,
+               "iteration_families_ms": {k: fam[k]["ms"] / (args.profile_steps + 1) for k in fam if fam[k]["launches"]}}
+    del r
 
     kernels = {}
     g = np.random.default_rng(args.seed)
@@ -179,14 +215,17 @@ def map_bench(args):
         torch.cuda.empty_cache()
     top = kernels["state_update@16000000"]
     out = {
-        "metric": "map bookkeeping: forward blend with per-surfel contribution, and map kernels",
+        "metric": "mapping side: contribution render, mapping loss and iteration, map kernels",
         "value": top["GB/s"], "unit": "GB/s", "n_gpus": 1, "steps": args.profile_steps, "warmup": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"forward render 640x480 f=525, {args.n}-surfel synthetic room; map kernels on "
-                               "1M and 16M random splats", "n_surfels": args.n},
+        "config": {"workload": f"640x480 f=525 views of the {args.n}-surfel synthetic room (forward render with "
+                               "contributions; mapping loss; mapping iteration over 5 views: batched render, "
+                               "loss, full backward, no optimizer step); map kernels on 1M and 16M random "
+                               "splats", "n_surfels": args.n},
         "roofline": {"bound": "hbm", "kernel": "state_update@16M", "achieved": top["GB/s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": top["frac_hbm"], "traffic": None},
         "blend_ms_per_launch": blend,
+        "mapping": mapping,
         "map_kernels": kernels,
     }
     print(json.dumps(out), flush=True)

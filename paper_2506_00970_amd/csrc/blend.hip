@@ -497,16 +497,39 @@ __device__ __forceinline__ void reverse_entry(BwdPix& s, const Hit& h, const Rec
   }
 }
 
-// Full mode: the wave's sum of one entry's 16 terms, added to the surfel's row.
+// Keep the half of v (N values) selected by the lane bit `bit` and add the partner
+// lane's values of that half (the partner keeps the other half): N/2 shuffles.
+template <int N>
+__device__ __forceinline__ void fold_half(const float* v, float* out, int lane, int bit) {
+  const bool hi = (lane & bit) != 0;
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const float mine = hi ? v[N / 2 + i] : v[i], give = hi ? v[i] : v[N / 2 + i];
+    out[i] = mine + __shfl_xor(give, bit, 64);
+  }
+}
+
+// Full mode: the wave's sums of one entry's 16 terms, added to the surfel's row.  A
+// transposing butterfly halves the values per lane at each exchange (lane bits 5, 4,
+// 3, 2 pick the term), then sums the last four lanes: 17 shuffles instead of 16 full
+// wave sums, and lanes 4k hold term k, so the row takes one 16-lane atomic store.
 __device__ __forceinline__ void flush_entry(const float* acc, bool contrib, float* __restrict__ gacc, uint32_t id,
                                             int lane) {
   if (__ballot(contrib) == 0ull) return;
-  float* dst = gacc + (size_t)id * 16;
+  float v16[16], v8[8], v4[4], v2[2], v1[1];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const float v = wave_sum(contrib ? acc[k] : 0.f);
-    if (lane == 0) atomicAdd(dst + k, v);
-  }
+  for (int k = 0; k < 16; ++k) v16[k] = contrib ? acc[k] : 0.f;
+  fold_half<16>(v16, v8, lane, 32);
+  fold_half<8>(v8, v4, lane, 16);
+  fold_half<4>(v4, v2, lane, 8);
+  fold_half<2>(v2, v1, lane, 4);
+  float v = v1[0];
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 1, 64);
+  const int k = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+  using gfloat = __attribute__((address_space(1))) float;
+  if ((lane & 3) == 0)
+    __hip_atomic_fetch_add((gfloat*)(gacc + (size_t)id * 16 + k), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>

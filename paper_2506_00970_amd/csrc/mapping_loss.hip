@@ -6,15 +6,16 @@
 // (eq:normal_fromD): normalised cross product of the central differences of the
 // back-projected pixels, 0 on the image border and where the cross product vanishes.
 //
-// Two kernels over pixel tiles with a 5-pixel halo staged in LDS:
-//  * forward (16 x 8 tiles): the 15 windowed statistics of each pixel by a horizontal
-//    then a vertical pass, in FP64: the variances E[x^2] - mu^2 cancel in flat regions,
+// Two kernels over 16 x 16 pixel tiles with a 5-pixel halo staged in LDS, one colour
+// channel at a time:
+//  * forward: the 15 windowed statistics of each pixel by a horizontal then a
+//    vertical pass, in FP64: the variances E[x^2] - mu^2 cancel in flat regions,
 //    and the gradient that follows cancels again, so FP32 statistics leave it only a
 //    few bits; SSIM and its per-pixel adjoint coefficients A, B, C (so that
 //    dL/dI_r = W*A + 2 I_r (W*B) + I (W*C)); the depth normal, d_normal, and the
 //    gradients to the two neighbour differences; one partial of each loss term per
 //    workgroup.
-//  * backward (16 x 16 tiles): the window filter of A, B, C (the Gaussian is symmetric, so the adjoint
+//  * backward: the window filter of A, B, C (the Gaussian is symmetric, so the adjoint
 //    of the zero-padded filter is the same filter), d_rgb and, gathering the
 //    neighbour-difference gradients of the 4 neighbours, d_depth.  Workgroup 0 also
 //    adds the forward's partials in a fixed order.
@@ -29,13 +30,10 @@ namespace gs2d {
 namespace maploss {
 namespace {
 
-constexpr int kT = 16;              // tile width; backward tile height
-constexpr int kFH = 8;              // forward tile height
+constexpr int kT = 16;              // output tile side
 constexpr int kR = 5;               // window radius
-constexpr int kS = kT + 2 * kR;     // staged width (and backward staged height), 26
-constexpr int kFS = kFH + 2 * kR;   // forward staged height, 18
-constexpr int kThreads = kT * kT;   // backward: one thread per output pixel
-constexpr int kFThreads = kT * kFH; // forward: one thread per output pixel
+constexpr int kS = kT + 2 * kR;     // staged side, 26
+constexpr int kThreads = kT * kT;   // one thread per output pixel
 constexpr double kC1 = 0.01 * 0.01;
 constexpr double kC2 = 0.03 * 0.03;
 
@@ -55,9 +53,9 @@ struct Args {
   float* d_normal;
   float* coef;   // 9 planes: A (3 channels), B (3), C (3)
   float* gdiff;  // 6 planes: dL/d(dx) (3), dL/d(dy) (3)
-  float* part;   // [forward tiles][4] partial sums of the four loss terms
+  float* part;   // [tiles][4] partial sums of the four loss terms
   float* loss;   // [5]
-  int W, H, tiles_x, fwd_tiles, n_tiles;
+  int W, H, tiles_x, n_tiles;
   float fx, fy, cx, cy;
   float w_l1, w_ssim, w_d, w_n;
   Win win;
@@ -75,67 +73,66 @@ __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
   return make_float3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
 }
 
-__global__ __launch_bounds__(kFThreads) void maploss_fwd_kernel(Args a) {
-  __shared__ float sx[3][kFS][kS], sy[3][kFS][kS];
-  __shared__ double hs[5][3][kFS][kT];
-  __shared__ float red[4][kFThreads / 64];
+__global__ __launch_bounds__(kThreads) void maploss_fwd_kernel(Args a) {
+  __shared__ float sx[kS][kS], sy[kS][kS];
+  __shared__ double hs[5][kS][kT];
+  __shared__ float red[4][kThreads / 64];
   const int t = threadIdx.x;
-  const int tx0 = (blockIdx.x % a.tiles_x) * kT, ty0 = (blockIdx.x / a.tiles_x) * kFH;
+  const int tx0 = (blockIdx.x % a.tiles_x) * kT, ty0 = (blockIdx.x / a.tiles_x) * kT;
   const int HW = a.W * a.H;
-  for (int k = t; k < kFS * kS; k += kFThreads) {
-    const int r = k / kS, c = k - r * kS;
-    const int gy = ty0 - kR + r, gx = tx0 - kR + c;
-    const bool in = gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
-    const int p = gy * a.W + gx;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      sx[ch][r][c] = in ? a.rgb[ch * HW + p] : 0.f;
-      sy[ch][r][c] = in ? a.trgb[ch * HW + p] : 0.f;
-    }
-  }
-  __syncthreads();
-  // horizontal pass: x, y, x^2, y^2, xy along rows, for every staged row (FP64; the
-  // products of two floats are exact)
-  for (int k = t; k < 3 * kFS * kT; k += kFThreads) {
-    const int ch = k / (kFS * kT), rem = k - ch * (kFS * kT), r = rem / kT, c = rem - r * kT;
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
-#pragma unroll
-    for (int j = 0; j < 2 * kR + 1; ++j) {
-      const double x = sx[ch][r][c + j], y = sy[ch][r][c + j], g = a.win.gd[j];
-      m0 = fma(g, x, m0);
-      m1 = fma(g, y, m1);
-      m2 = fma(g, x * x, m2);
-      m3 = fma(g, y * y, m3);
-      m4 = fma(g, x * y, m4);
-    }
-    hs[0][ch][r][c] = m0;
-    hs[1][ch][r][c] = m1;
-    hs[2][ch][r][c] = m2;
-    hs[3][ch][r][c] = m3;
-    hs[4][ch][r][c] = m4;
-  }
-  __syncthreads();
   const int ly = t / kT, lx = t - ly * kT;
   const int gx = tx0 + lx, gy = ty0 + ly;
   const bool inside = gx < a.W && gy < a.H;
   const int p = gy * a.W + gx;
   const float inv = 1.0f / (float)HW;
+  const double gs = -(double)a.w_ssim / (3.0 * (double)HW);  // dL/dSSIM_ch(p)
   float l1 = 0.f, dssim = 0.f, ld = 0.f, ln = 0.f;
-  if (inside) {
-    // vertical pass and SSIM with its adjoint coefficients
-    const double gs = -(double)a.w_ssim / (3.0 * (double)HW);  // dL/dSSIM_ch(p)
-    double ssum = 0.0;
+  double ssum = 0.0;
+  // one colour channel at a time, so that the staging stays small enough for several
+  // workgroups per compute unit
+  for (int ch = 0; ch < 3; ++ch) {
+    if (ch) __syncthreads();
+    for (int k = t; k < kS * kS; k += kThreads) {
+      const int r = k / kS, c = k - r * kS;
+      const int yy = ty0 - kR + r, xx = tx0 - kR + c;
+      const bool in = xx >= 0 && xx < a.W && yy >= 0 && yy < a.H;
+      const int q = ch * HW + yy * a.W + xx;
+      sx[r][c] = in ? a.rgb[q] : 0.f;
+      sy[r][c] = in ? a.trgb[q] : 0.f;
+    }
+    __syncthreads();
+    // horizontal pass: x, y, x^2, y^2, xy along every staged row (FP64; the products of
+    // two floats are exact)
+    for (int k = t; k < kS * kT; k += kThreads) {
+      const int r = k / kT, c = k - r * kT;
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
+      for (int j = 0; j < 2 * kR + 1; ++j) {
+        const double x = sx[r][c + j], y = sy[r][c + j], g = a.win.gd[j];
+        m0 = fma(g, x, m0);
+        m1 = fma(g, y, m1);
+        m2 = fma(g, x * x, m2);
+        m3 = fma(g, y * y, m3);
+        m4 = fma(g, x * y, m4);
+      }
+      hs[0][r][c] = m0;
+      hs[1][r][c] = m1;
+      hs[2][r][c] = m2;
+      hs[3][r][c] = m3;
+      hs[4][r][c] = m4;
+    }
+    __syncthreads();
+    if (inside) {
+      // vertical pass, SSIM and its adjoint coefficients
       double mx = 0.0, my = 0.0, exx = 0.0, eyy = 0.0, exy = 0.0;
 #pragma unroll
       for (int i = 0; i < 2 * kR + 1; ++i) {
         const double g = a.win.gd[i];
-        mx = fma(g, hs[0][ch][ly + i][lx], mx);
-        my = fma(g, hs[1][ch][ly + i][lx], my);
-        exx = fma(g, hs[2][ch][ly + i][lx], exx);
-        eyy = fma(g, hs[3][ch][ly + i][lx], eyy);
-        exy = fma(g, hs[4][ch][ly + i][lx], exy);
+        mx = fma(g, hs[0][ly + i][lx], mx);
+        my = fma(g, hs[1][ly + i][lx], my);
+        exx = fma(g, hs[2][ly + i][lx], exx);
+        eyy = fma(g, hs[3][ly + i][lx], eyy);
+        exy = fma(g, hs[4][ly + i][lx], exy);
       }
       const double vx = fma(-mx, mx, exx), vy = fma(-my, my, eyy), cxy = fma(-mx, my, exy);
       const double n1 = fma(2.0 * mx, my, kC1), n2 = fma(2.0, cxy, kC2);
@@ -150,8 +147,10 @@ __global__ __launch_bounds__(kFThreads) void maploss_fwd_kernel(Args a) {
       a.coef[(0 + ch) * HW + p] = (float)(gs * ds_dm);
       a.coef[(3 + ch) * HW + p] = (float)(gs * ds_dxx);
       a.coef[(6 + ch) * HW + p] = (float)(gs * ds_dxy);
-      l1 += fabsf(sx[ch][ly + kR][lx + kR] - sy[ch][ly + kR][lx + kR]);
+      l1 += fabsf(sx[ly + kR][lx + kR] - sy[ly + kR][lx + kR]);
     }
+  }
+  if (inside) {
     dssim = (float)(1.0 - ssum * (1.0 / 3.0));
     ld = fabsf(a.depth[p] - a.tdepth[p]);
     // depth normal from the central differences of the back-projected neighbours,
@@ -198,53 +197,57 @@ __global__ __launch_bounds__(kFThreads) void maploss_fwd_kernel(Args a) {
   if (t < 4) {
     float s = 0.f;
 #pragma unroll
-    for (int w = 0; w < kFThreads / 64; ++w) s += red[t][w];
+    for (int w = 0; w < kThreads / 64; ++w) s += red[t][w];
     a.part[blockIdx.x * 4 + t] = s;
   }
 }
 
 __global__ __launch_bounds__(kThreads) void maploss_bwd_kernel(Args a) {
-  __shared__ float sc[9][kS][kS];
-  __shared__ float hc[9][kS][kT];
+  __shared__ float sc[3][kS][kS];
+  __shared__ float hc[3][kS][kT];
   __shared__ float red[4][kThreads / 64];
   const int t = threadIdx.x;
   const int tx0 = (blockIdx.x % a.tiles_x) * kT, ty0 = (blockIdx.x / a.tiles_x) * kT;
   const int HW = a.W * a.H;
-  for (int k = t; k < kS * kS; k += kThreads) {
-    const int r = k / kS, c = k - r * kS;
-    const int gy = ty0 - kR + r, gx = tx0 - kR + c;
-    const bool in = gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
-    const int p = gy * a.W + gx;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) sc[q][r][c] = in ? a.coef[q * HW + p] : 0.f;
-  }
-  __syncthreads();
-  for (int k = t; k < 9 * kS * kT; k += kThreads) {
-    const int q = k / (kS * kT), rem = k - q * (kS * kT), r = rem / kT, c = rem - r * kT;
-    float m = 0.f;
-#pragma unroll
-    for (int j = 0; j < 2 * kR + 1; ++j) m = fmaf(a.win.g[j], sc[q][r][c + j], m);
-    hc[q][r][c] = m;
-  }
-  __syncthreads();
   const int ly = t / kT, lx = t - ly * kT;
   const int gx = tx0 + lx, gy = ty0 + ly;
-  if (gx < a.W && gy < a.H) {
-    const int p = gy * a.W + gx;
-    const float inv = 1.0f / (float)HW;
-    float f[9];
+  const bool inside = gx < a.W && gy < a.H;
+  const int p = gy * a.W + gx;
+  const float inv = 1.0f / (float)HW;
+  // one colour channel at a time: its A, B, C planes filtered, then its d_rgb
+  for (int ch = 0; ch < 3; ++ch) {
+    if (ch) __syncthreads();
+    for (int k = t; k < kS * kS; k += kThreads) {
+      const int r = k / kS, c = k - r * kS;
+      const int yy = ty0 - kR + r, xx = tx0 - kR + c;
+      const bool in = xx >= 0 && xx < a.W && yy >= 0 && yy < a.H;
+      const int q = yy * a.W + xx;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      float m = 0.f;
-#pragma unroll
-      for (int i = 0; i < 2 * kR + 1; ++i) m = fmaf(a.win.g[i], hc[q][ly + i][lx], m);
-      f[q] = m;
+      for (int m = 0; m < 3; ++m) sc[m][r][c] = in ? a.coef[(3 * m + ch) * HW + q] : 0.f;
     }
+    __syncthreads();
+    for (int k = t; k < 3 * kS * kT; k += kThreads) {
+      const int m = k / (kS * kT), rem = k - m * (kS * kT), r = rem / kT, c = rem - r * kT;
+      float acc = 0.f;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
+      for (int j = 0; j < 2 * kR + 1; ++j) acc = fmaf(a.win.g[j], sc[m][r][c + j], acc);
+      hc[m][r][c] = acc;
+    }
+    __syncthreads();
+    if (inside) {
+      float f[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < 2 * kR + 1; ++i) acc = fmaf(a.win.g[i], hc[m][ly + i][lx], acc);
+        f[m] = acc;
+      }
       const float x = a.rgb[ch * HW + p], y = a.trgb[ch * HW + p];
-      a.d_rgb[ch * HW + p] = fmaf(a.w_l1 * inv, sgn(x - y), fmaf(2.f * x, f[3 + ch], fmaf(y, f[6 + ch], f[ch])));
+      a.d_rgb[ch * HW + p] = fmaf(a.w_l1 * inv, sgn(x - y), fmaf(2.f * x, f[1], fmaf(y, f[2], f[0])));
     }
+  }
+  if (inside) {
     // d_depth: the depth L1 term, and the gradients of the neighbour differences that
     // contain this pixel: +dx of the left neighbour, -dx of the right one, +dy of the one
     // above, -dy of the one below (zero outside the image)
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void maploss_bwd_kernel(Args a) {
     // the loss: wave q adds term q's partials in a fixed order
     const int wave = t >> 6, lane = t & 63;
     float s = 0.f;
-    for (int b = lane; b < a.fwd_tiles; b += 64) s += a.part[b * 4 + wave];
+    for (int b = lane; b < a.n_tiles; b += 64) s += a.part[b * 4 + wave];
     s = wave_sum(s);
     if (lane == 0) red[wave][0] = s;
     __syncthreads();
@@ -308,8 +311,8 @@ using namespace gs2d::maploss;
 
 GS2D_API int64_t gs2d_mapping_loss_workspace(int32_t width, int32_t height) {
   if (width <= 0 || height <= 0) return 0;
-  const int64_t fwd_tiles = (int64_t)((width + kT - 1) / kT) * ((height + kFH - 1) / kFH);
-  return 15 * (int64_t)width * height + 4 * fwd_tiles;
+  const int64_t tiles = (int64_t)((width + kT - 1) / kT) * ((height + kT - 1) / kT);
+  return 15 * (int64_t)width * height + 4 * tiles;
 }
 
 GS2D_API int gs2d_mapping_loss(const gs2d_camera* camera, const float* rgb, const float* depth, const float* normal,
@@ -337,7 +340,6 @@ GS2D_API int gs2d_mapping_loss(const gs2d_camera* camera, const float* rgb, cons
   a.part = work + 15 * HW;
   a.loss = loss;
   a.tiles_x = (a.W + kT - 1) / kT;
-  a.fwd_tiles = a.tiles_x * ((a.H + kFH - 1) / kFH);
   a.n_tiles = a.tiles_x * ((a.H + kT - 1) / kT);
   a.fx = camera->fx;
   a.fy = camera->fy;
@@ -349,7 +351,7 @@ GS2D_API int gs2d_mapping_loss(const gs2d_camera* camera, const float* rgb, cons
   a.w_d = w.w_d;
   a.w_n = w.w_n;
   a.win = make_window();
-  maploss_fwd_kernel<<<a.fwd_tiles, kFThreads, 0, stream>>>(a);
+  maploss_fwd_kernel<<<a.n_tiles, kThreads, 0, stream>>>(a);
   maploss_bwd_kernel<<<a.n_tiles, kThreads, 0, stream>>>(a);
   return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_ERR_HIP;
 }
