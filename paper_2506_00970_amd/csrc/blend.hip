@@ -497,35 +497,48 @@ __device__ __forceinline__ void reverse_entry(BwdPix& s, const Hit& h, const Rec
   }
 }
 
-// Keep the half of v (N values) selected by the lane bit `bit` and add the partner
-// lane's values of that half (the partner keeps the other half): N/2 shuffles.
-template <int N>
-__device__ __forceinline__ void fold_half(const float* v, float* out, int lane, int bit) {
-  const bool hi = (lane & bit) != 0;
-#pragma unroll
-  for (int i = 0; i < N / 2; ++i) {
-    const float mine = hi ? v[N / 2 + i] : v[i], give = hi ? v[i] : v[N / 2 + i];
-    out[i] = mine + __shfl_xor(give, bit, 64);
-  }
+// The value of x at the lane that DPP control CTRL selects (all rows and banks on).
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
 // Full mode: the wave's sums of one entry's 16 terms, added to the surfel's row.  A
-// transposing butterfly halves the values per lane at each exchange (lane bits 5, 4,
-// 3, 2 pick the term), then sums the last four lanes: 17 shuffles instead of 16 full
-// wave sums, and lanes 4k hold term k, so the row takes one 16-lane atomic store.
+// transposing butterfly halves the values per lane at each exchange, so that lane bits
+// 5, 4, 3, 2 pick the term, then sums the four lanes of each quad.  Every exchange is a
+// VALU lane move: v_permlane32_swap (lanes L, L^32), v_permlane16_swap (rows 0-1 and
+// 2-3), DPP row_ror:8 (L^8 within a row), DPP row_half_mirror (a lane of the other
+// half of its 8-lane group) and quad_perm.  Lanes 4k hold term k, so the row takes one
+// 16-lane atomic store.  Every lane of the wave must be active.
 __device__ __forceinline__ void flush_entry(const float* acc, bool contrib, float* __restrict__ gacc, uint32_t id,
                                             int lane) {
   if (__ballot(contrib) == 0ull) return;
-  float v16[16], v8[8], v4[4], v2[2], v1[1];
+  float v16[16], v8[8], v4[4], v2[2];
 #pragma unroll
   for (int k = 0; k < 16; ++k) v16[k] = contrib ? acc[k] : 0.f;
-  fold_half<16>(v16, v8, lane, 32);
-  fold_half<8>(v8, v4, lane, 16);
-  fold_half<4>(v4, v2, lane, 8);
-  fold_half<2>(v2, v1, lane, 4);
-  float v = v1[0];
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 1, 64);
+  // lanes 0-31 keep terms 0-7 and add lane L+32's; lanes 32-63 keep 8-15 and add L-32's
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v16[i]), __float_as_uint(v16[8 + i]), false,
+                                                    false);
+    v8[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // rows 0 and 2 keep the lower four, rows 1 and 3 the upper four
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v8[i]), __float_as_uint(v8[4 + i]), false,
+                                                    false);
+    v4[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool h8 = (lane & 8) != 0, h4 = (lane & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float mine = h8 ? v4[2 + i] : v4[i], give = h8 ? v4[i] : v4[2 + i];
+    v2[i] = mine + dpp_get<0x128>(give);  // row_ror:8
+  }
+  float v = (h4 ? v2[1] : v2[0]) + dpp_get<0x141>(h4 ? v2[0] : v2[1]);  // row_half_mirror
+  v += dpp_get<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+  v += dpp_get<0xB1>(v);  // quad_perm [1, 0, 3, 2]
   const int k = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
   using gfloat = __attribute__((address_space(1))) float;
   if ((lane & 3) == 0)

@@ -77,30 +77,48 @@ __global__ void reduce_loss_kernel(const float* __restrict__ part, int n, float 
   if (threadIdx.x == 0) *loss = (float)s;
 }
 
-__global__ void reduce_pose_kernel(const float* __restrict__ part, int row0, int rows, float* __restrict__ d_pose,
-                                   int accumulate) {
-  double g[6];
+constexpr int kReduceThreads = 256;
+
+// The six pose partials (the first six of each 8-float row) summed over `rows` rows in
+// FP64 by one workgroup: every thread adds its rows' six values in one pass, then the
+// waves and the workgroup in a fixed order.  d_pose (=, or += with accumulate).
+__device__ void reduce_pose_rows(const float* __restrict__ part, int rows, float* __restrict__ d_pose,
+                                 int accumulate) {
+  __shared__ double sh[kReduceThreads / 64][6];
+  double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < rows; i += kReduceThreads) {
+    const float4 a = reinterpret_cast<const float4*>(part + (size_t)i * 8)[0];
+    const float2 b = reinterpret_cast<const float2*>(part + (size_t)i * 8)[2];
+    g[0] += a.x, g[1] += a.y, g[2] += a.z, g[3] += a.w, g[4] += b.x, g[5] += b.y;
+  }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = sum_parts(part + (size_t)row0 * 8, rows, 8, k);
-  if (threadIdx.x == 0) {
+  for (int k = 0; k < 6; ++k) g[k] = wave_sum_d(g[k]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) d_pose[k] = accumulate ? d_pose[k] + (float)g[k] : (float)g[k];
+    for (int k = 0; k < 6; ++k) sh[threadIdx.x >> 6][k] = g[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kReduceThreads / 64; ++w) t += sh[w][threadIdx.x];
+    d_pose[threadIdx.x] = accumulate ? d_pose[threadIdx.x] + (float)t : (float)t;
   }
 }
 
-// one wave per view: d_pose of view blockIdx.x = sum of the rows of its tiles
-__global__ void reduce_pose_views_kernel(const ViewDesc* __restrict__ views, const float* __restrict__ part,
-                                         int accumulate) {
+__global__ __launch_bounds__(kReduceThreads) void reduce_pose_kernel(const float* __restrict__ part, int row0,
+                                                                     int rows, float* __restrict__ d_pose,
+                                                                     int accumulate) {
+  reduce_pose_rows(part + (size_t)row0 * 8, rows, d_pose, accumulate);
+}
+
+// one workgroup per view: d_pose of view blockIdx.x = sum of the rows of its tiles
+__global__ __launch_bounds__(kReduceThreads) void reduce_pose_views_kernel(const ViewDesc* __restrict__ views,
+                                                                           const float* __restrict__ part,
+                                                                           int accumulate) {
   const ViewDesc& V = views[blockIdx.x];
   float* d_pose = V.d_pose;
   if (!d_pose) return;
-  double g[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) g[k] = sum_parts(part + (size_t)V.tile_base * 8, V.tiles_x * V.tiles_y, 8, k);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) d_pose[k] = accumulate ? d_pose[k] + (float)g[k] : (float)g[k];
-  }
+  reduce_pose_rows(part + (size_t)V.tile_base * 8, V.tiles_x * V.tiles_y, d_pose, accumulate);
 }
 
 __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_views, Ctrl* __restrict__ ctrl,
@@ -243,12 +261,12 @@ void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* los
 }
 
 void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, int accumulate, hipStream_t s) {
-  reduce_pose_kernel<<<1, 64, 0, s>>>(part, row0, rows, d_pose, accumulate);
+  reduce_pose_kernel<<<1, kReduceThreads, 0, s>>>(part, row0, rows, d_pose, accumulate);
 }
 
 void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,
                               hipStream_t s) {
-  reduce_pose_views_kernel<<<n_views, 64, 0, s>>>(views, part, accumulate);
+  reduce_pose_views_kernel<<<n_views, kReduceThreads, 0, s>>>(views, part, accumulate);
 }
 
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
