@@ -68,6 +68,7 @@ def _load():
         _lib.orc_backward.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 10
         _lib.orc_preprocess.argtypes = [P, ctypes.c_int64, P, P, P] + [P] * 5
         _lib.orc_contribution.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_double, P, P]
+        _lib.orc_depth_variants.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int, P, P, P]
     return _lib
 
 
@@ -176,6 +177,24 @@ def contribution(params, camera, pose, filter: bool = True, margin: float = 1e-5
     lib.orc_contribution(_ptr(p), n, ctypes.byref(c), _ptr(T), ctypes.byref(k), _threads(nthreads),
                          ctypes.c_double(margin), _ptr(contrib), _ptr(touched))
     return {"contrib": contrib, "touched": touched.astype(bool)}
+
+
+def depth_variants(params, camera, pose, filter: bool = True, nthreads=None):
+    """The normalised depth D/O and the median depth (depth of the last composited
+    intersection whose incoming transmittance exceeds 1/2).
+
+    Returns {"depth_norm", "depth_median", "margin"} ([H,W] each, FP64); margin is the
+    pixel's smallest relative margin to any decision, the median's T > 1/2 included.
+    """
+    lib = _load()
+    p, T = _prep(params, pose)
+    c = _cam(camera)
+    H, W = c.height, c.width
+    out = {"depth_norm": np.zeros((H, W)), "depth_median": np.zeros((H, W)), "margin": np.zeros((H, W))}
+    k = _consts(filter, True)
+    lib.orc_depth_variants(_ptr(p), p.shape[1], ctypes.byref(c), _ptr(T), ctypes.byref(k), _threads(nthreads),
+                           _ptr(out["depth_norm"]), _ptr(out["depth_median"]), _ptr(out["margin"]))
+    return out
 
 
 def preprocess(params, camera, pose, filter: bool = True):

@@ -393,6 +393,43 @@ int orc_render(const double* params, int64_t n, const OrcCamera* c, const double
   return 0;
 }
 
+// Depth variants of the forward render (the depth channel's alternatives):
+//  * depth_norm = D / O, the blended depth over the opacity (0 where O = 0);
+//  * depth_median = the depth of the last composited intersection whose incoming
+//    transmittance exceeds 1/2, i.e. where the accumulated opacity reaches one half
+//    (the last composited one if it never does; 0 with none).
+// margin[H][W] is the pixel's smallest relative margin to any decision of the render
+// and to the median's T > 1/2 decisions.
+int orc_depth_variants(const double* params, int64_t n, const OrcCamera* c, const double* pose,
+                       const OrcConsts* k, int nthreads, double* depth_norm, double* depth_median,
+                       double* margin) {
+  Cam cam; Consts kk;
+  unpack(c, k, cam, kk);
+  if (nthreads < 1) nthreads = 1;
+  Scene sc;
+  build_scene(params, n, cam, pose, kk, nthreads, sc);
+  std::vector<std::vector<Entry>> lists((size_t)nthreads);
+  parallel_rows(cam.height, nthreads, [&](int t, int y) {
+    std::vector<Entry>& list = lists[(size_t)t];
+    for (int x = 0; x < cam.width; ++x) {
+      double out[8], tf, fm, gm;
+      int cnt;
+      list.clear();
+      composite_pixel(sc, x, y, out, tf, cnt, fm, gm, &list);
+      const int64_t p = (int64_t)y * cam.width + x;
+      depth_norm[p] = out[7] > 0.0 ? out[3] / out[7] : 0.0;
+      double med = 0.0;
+      for (const Entry& e : list) {
+        fm = std::min(fm, rel(e.T, 0.5));
+        if (e.T > 0.5) med = e.h.d;
+      }
+      depth_median[p] = med;
+      margin[p] = fm;
+    }
+  });
+  return 0;
+}
+
 // Per-surfel contribution to the rendered frame (eq:weight, eq:contribution): the
 // sum over pixels of the surfel's blending weight w_k(p) = alpha_k T_k, over the same
 // composited pairs as the forward.  contrib[n]; touched[n] (may be null) is set for

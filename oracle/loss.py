@@ -7,6 +7,8 @@
   M_n = [N_r . r > 0] (r the pixel's unit ray, camera frame) and
   M_o = [O > 0.95].  |Omega| is every pixel.  Masks are held constant in the
   gradient; the L1 derivative at zero is zero.
+* ``tracking_error``: the relocalisation check e_t (eq:tracking_error), the masked
+  depth L1 of the tracking loss on its own.
 * ``frame_loss``: unmasked L1 over colour, depth and normal, averaged over
   pixels (the single-frame random-surfel workload).
 * ``adamw_pose_step``: AdamW on the left-perturbation twist, which is reset to
@@ -62,6 +64,15 @@ def tracking_loss(rgb, depth, normal, alpha, tgt_rgb, tgt_depth, camera, lambda_
     d_rgb = m[None] * np.sign(dr) / hw
     d_depth = lambda_d * m * np.sign(dd) / hw
     return loss, d_rgb, d_depth, m.astype(bool)
+
+
+def tracking_error(depth, normal, alpha, tgt_depth, camera, decision_dtype=np.float32):
+    """e_t of eq:tracking_error: (1/|Omega|) sum_p M_n(p) M_o(p) |D_r(p) - D(p)|, the
+    masked depth L1 of the rendered depth against the observed one (the relocalisation
+    check), with the tracking loss's masks decided in ``decision_dtype``."""
+    m_n, m_o, _ = masks(normal, alpha, camera, decision_dtype)
+    dd = np.asarray(depth, dtype=np.float64) - np.asarray(tgt_depth, dtype=np.float64)
+    return float(np.sum((m_n & m_o) * np.abs(dd)) / dd.size)
 
 
 def frame_loss(rgb, depth, normal, tgt_rgb, tgt_depth, tgt_normal):
