@@ -117,6 +117,12 @@ typedef struct gs2d_view {
    * its blending weight (Sec. "Tracking and Keyframe Selection", eq:contribution);
    * float atomics, so the summation order varies between runs.  NULL: not wanted. */
   float* contrib;
+  /* optional [H][W] outs, the depth channel's variants: depth_norm = D / O (0 where
+   * O = 0); depth_median = the depth of the last composited intersection whose
+   * incoming transmittance exceeds 1/2, where the accumulated opacity reaches one half
+   * (the last composited one if it never does; 0 with none).  NULL: not wanted. */
+  float* depth_norm;
+  float* depth_median;
 } gs2d_view;
 
 /* Gradients of one view for gs2d_render_backward_batch: image gradients in (any may
@@ -228,6 +234,14 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
                                 const float* tgt_rgb, const float* tgt_depth, float lambda_d,
                                 int32_t use_masks, float* loss, float* d_rgb, float* d_depth,
                                 hipStream_t stream);
+
+/* Relocalisation error of Sec. "Loop Detection and Relocalization" (eq:tracking_error):
+ * e_t = (1/HW) sum_p M_n M_o |depth - tgt_depth|, the depth term of the tracking loss
+ * with its masks (M_n = [normal . ray > 0], M_o = [alpha > 0.95]), computed on the
+ * depth re-rendered at the optimised pose.  Inputs are images of `camera`'s size;
+ * writes *error (device scalar). */
+GS2D_API int gs2d_tracking_error(gs2d_ctx* ctx, const gs2d_camera* camera, const float* depth, const float* normal,
+                                 const float* alpha, const float* tgt_depth, float* error, hipStream_t stream);
 
 /* Run the tracking loop described at gs2d_track_args (the pose update of Sec.
  * "Tracking and Keyframe Selection": AdamW on the pose, surfels frozen).  The

@@ -71,7 +71,8 @@ class MappingWeights(ctypes.Structure):
 class View(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
-                ("alpha", ctypes.c_void_p), ("contrib", ctypes.c_void_p)]
+                ("alpha", ctypes.c_void_p), ("contrib", ctypes.c_void_p), ("depth_norm", ctypes.c_void_p),
+                ("depth_median", ctypes.c_void_p)]
 
 
 class ViewGrad(ctypes.Structure):
@@ -117,6 +118,7 @@ _SIGS = {
                          ctypes.c_int),
     "gs2d_tracking_loss": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
                             _P, _P, _P, _P], ctypes.c_int),
+    "gs2d_tracking_error": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),

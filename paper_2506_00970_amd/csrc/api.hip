@@ -242,6 +242,8 @@ int build_views(gs2d_ctx* ctx, const gs2d_view* in, int nv, ViewSet& vs) {
     d.normal = g.normal;
     d.alpha = g.alpha;
     d.contrib = g.contrib;
+    d.depth_norm = g.depth_norm;
+    d.depth_median = g.depth_median;
     d.cam = camf(g.camera);
     d.n = (int)g.n;
     d.tiles_x = (g.camera.width + tw - 1) / tw;
@@ -873,6 +875,38 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
   {
     ProfScope ps(ctx, kReduce, stream);
     launch_reduce_loss(ctx->lpart, loss_blocks(hw), 1.0f / (float)hw, loss, stream);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_tracking_error(gs2d_ctx* ctx, const gs2d_camera* camera, const float* depth, const float* normal,
+                                 const float* alpha, const float* tgt_depth, float* error, hipStream_t stream) {
+  if (!ctx || !valid_camera(camera) || !depth || !normal || !alpha || !tgt_depth || !error)
+    return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  const int hw = camera->width * camera->height;
+  bool capturing = false;
+  if (stream_capturing(stream, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+  if (loss_blocks(hw) > ctx->lpart_cap && capturing) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_lpart(ctx, loss_blocks(hw)));
+  ViewSet vs;
+  vs.n_views = 1;
+  ViewDesc& d = vs.v[0];
+  std::memset(&d, 0, sizeof(d));
+  d.cam = camf(*camera);
+  d.depth = const_cast<float*>(depth);
+  d.normal = const_cast<float*>(normal);
+  d.alpha = const_cast<float*>(alpha);
+  d.tgt_depth = tgt_depth;
+  launch_upload_views(vs, ctx->views, stream);
+  {
+    ProfScope ps(ctx, kLoss, stream);
+    launch_tracking_loss(ctx->views, 1, hw, 1.0f, 1, ctx->lpart, loss_blocks(hw), stream);
+  }
+  {
+    ProfScope ps(ctx, kReduce, stream);
+    launch_reduce_loss(ctx->lpart, loss_blocks(hw), 1.0f / (float)hw, error, stream);
   }
   GS2D_HIP(ctx, hipGetLastError());
   return GS2D_OK;

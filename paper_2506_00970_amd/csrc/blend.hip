@@ -192,6 +192,7 @@ __device__ __forceinline__ Rec load_rec(const float4* srec, int j) {
 
 struct FwdPix {
   float T, cr, cg, cb, cd, n0, n1, n2, co;
+  float dmed;  // median depth: of the last composited entry with incoming T > 1/2
   int lastj;
   bool done;
 };
@@ -214,6 +215,7 @@ __device__ __forceinline__ float composite(FwdPix& s, int code, const Hit& h, co
   s.n1 = fmaf(w, r.nv.y, s.n1);
   s.n2 = fmaf(w, r.nv.z, s.n2);
   s.co += w;
+  if (s.T > 0.5f) s.dmed = h.d;
   s.T = Tn;
   s.lastj = pos + 1;
   return w;
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
-  FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
+  FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
   // read once: the contribution atomics could alias the view table for the compiler
   float* const contrib = V.contrib;
   const uint32_t item_base = (uint32_t)V.item_base;
@@ -344,6 +346,8 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
       V.normal[2 * HW + p] = s.n2;
     }
     if (V.alpha) V.alpha[p] = s.co;
+    if (V.depth_norm) V.depth_norm[p] = s.co > 0.f ? s.cd / s.co : 0.f;
+    if (V.depth_median) V.depth_median[p] = s.dmed;
     t_final[V.pix_base + p] = s.T;
     last_out[V.pix_base + p] = (uint32_t)s.lastj;
   }
@@ -717,7 +721,7 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
       lds_list = order_list(a.order_ids, a.order_scratch, a.dkey, start, end - start,
                             order_lds(reinterpret_cast<uint32_t*>(srec), sid), true);
   }
-  FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
+  FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
   float Q[6], Ar[6], Ag[6], Ab[6], AD[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) Q[k] = Ar[k] = Ag[k] = Ab[k] = AD[k] = 0.f;

@@ -58,6 +58,8 @@ struct ViewDesc {
   const float* tgt_depth;
   float* d_pose;         // [6] pose gradient out (nullable)
   float* contrib;        // [n] per-surfel contribution out (nullable; forward blend)
+  float* depth_norm;     // [H][W] D / O out (nullable; forward blend)
+  float* depth_median;   // [H][W] median depth out (nullable; forward blend)
   CamF cam;
   int n;                 // surfels of this view
   int item_base;         // first (view, surfel) item

@@ -33,25 +33,21 @@ __global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(const ViewD
       m = (ndr > 0.0f) && (V.alpha[p] > kOpacityMask);
     }
     const float inv = 1.0f / (float)HW;
-    const float d0 = rgb[p] - tgt_rgb[p];
-    const float d1 = rgb[HW + p] - tgt_rgb[HW + p];
-    const float d2 = rgb[2 * HW + p] - tgt_rgb[2 * HW + p];
+    // no colour images: the depth term alone (the relocalisation error e_t)
+    const float d0 = rgb ? rgb[p] - tgt_rgb[p] : 0.f;
+    const float d1 = rgb ? rgb[HW + p] - tgt_rgb[HW + p] : 0.f;
+    const float d2 = rgb ? rgb[2 * HW + p] - tgt_rgb[2 * HW + p] : 0.f;
     const float dd = V.depth[p] - V.tgt_depth[p];
     auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
     float* d_rgb = V.g_rgb;
     float* d_depth = V.g_depth;
-    if (m) {
-      l = fabsf(d0) + fabsf(d1) + fabsf(d2) + lambda_d * fabsf(dd);
-      d_rgb[p] = sgn(d0) * inv;
-      d_rgb[HW + p] = sgn(d1) * inv;
-      d_rgb[2 * HW + p] = sgn(d2) * inv;
-      d_depth[p] = lambda_d * sgn(dd) * inv;
-    } else {
-      d_rgb[p] = 0.f;
-      d_rgb[HW + p] = 0.f;
-      d_rgb[2 * HW + p] = 0.f;
-      d_depth[p] = 0.f;
+    if (m) l = fabsf(d0) + fabsf(d1) + fabsf(d2) + lambda_d * fabsf(dd);
+    if (d_rgb) {
+      d_rgb[p] = m ? sgn(d0) * inv : 0.f;
+      d_rgb[HW + p] = m ? sgn(d1) * inv : 0.f;
+      d_rgb[2 * HW + p] = m ? sgn(d2) * inv : 0.f;
     }
+    if (d_depth) d_depth[p] = m ? lambda_d * sgn(dd) * inv : 0.f;
   }
   __shared__ float red[kLossThreads];
   red[threadIdx.x] = l;

@@ -49,6 +49,8 @@ class RenderOut:
     alpha: torch.Tensor
     generation: int
     contrib: torch.Tensor | None = None  # [n] per-surfel contribution (render_batch(contribution=True))
+    depth_norm: torch.Tensor | None = None    # [H, W] D / O (render_batch(depth_variants=True))
+    depth_median: torch.Tensor | None = None  # [H, W] median depth (render_batch(depth_variants=True))
 
 
 class Rasterizer:
@@ -116,13 +118,14 @@ class Rasterizer:
         self._last = (params, pose, cam)  # keep the inputs alive until the backward
         return RenderOut(rgb, depth, normal, alpha, int(gen.value))
 
-    def render_batch(self, views, contribution: bool = False) -> list:
+    def render_batch(self, views, contribution: bool = False, depth_variants: bool = False) -> list:
         """Render several views in one batched launch.
 
         ``views``: sequence of (params [15, N], camera, pose [12]); views may share a
         params tensor.  Returns one RenderOut per view (all with the same generation);
         with ``contribution`` each also carries every surfel's contribution to its view
-        (eq:contribution).
+        (eq:contribution); with ``depth_variants`` the normalised depth D/O and the
+        median depth.
         """
         views = list(views)
         if not 1 <= len(views) <= _lib.MAX_VIEWS:
@@ -141,15 +144,18 @@ class Rasterizer:
                  torch.empty((3, H, W), dtype=torch.float32, device=self.device),
                  torch.empty((H, W), dtype=torch.float32, device=self.device)]
             c = torch.empty(n, dtype=torch.float32, device=self.device) if contribution else None
+            dv = [torch.empty((H, W), dtype=torch.float32, device=self.device) for _ in range(2)] \
+                if depth_variants else [None, None]
+            ptr = lambda t: None if t is None else t.data_ptr()
             arr[k] = _lib.View(params.data_ptr(), n, cam, pose.data_ptr(), o[0].data_ptr(), o[1].data_ptr(),
-                               o[2].data_ptr(), o[3].data_ptr(), None if c is None else c.data_ptr())
-            outs.append(o + [c])
+                               o[2].data_ptr(), o[3].data_ptr(), ptr(c), ptr(dv[0]), ptr(dv[1]))
+            outs.append(o + [c] + dv)
             keep.append((params, pose, cam))
         gen = ctypes.c_uint32(0)
         _lib.check(self._lib.gs2d_render_batch(self._ctx, arr, len(views), ctypes.byref(gen), self._stream()),
                    self._ctx)
         self._last = keep
-        return [RenderOut(o[0], o[1], o[2], o[3], int(gen.value), o[4]) for o in outs]
+        return [RenderOut(o[0], o[1], o[2], o[3], int(gen.value), o[4], o[5], o[6]) for o in outs]
 
     def backward_batch(self, generation: int, grads, params_grad=True, accumulate: bool = False):
         """Reverse mode of a batched render.
@@ -269,6 +275,21 @@ class Rasterizer:
                                                 _dev_ptr(loss), _dev_ptr(d_rgb), _dev_ptr(d_depth),
                                                 self._stream()), self._ctx)
         return loss, d_rgb, d_depth
+
+    def tracking_error(self, camera, depth, normal, alpha, tgt_depth):
+        """The relocalisation error e_t (eq:tracking_error), a device scalar tensor."""
+        cam = _camera(camera)
+        H, W = cam.height, cam.width
+        for t, nm, shp in ((depth, "depth", (H, W)), (normal, "normal", (3, H, W)), (alpha, "alpha", (H, W)),
+                           (tgt_depth, "tgt_depth", (H, W))):
+            if t is None:
+                raise ValueError(f"{nm} is required")
+            _check_tensor(t, nm, shp, self.device)
+        err = torch.empty((), dtype=torch.float32, device=self.device)
+        _lib.check(self._lib.gs2d_tracking_error(self._ctx, ctypes.byref(cam), _dev_ptr(depth), _dev_ptr(normal),
+                                                 _dev_ptr(alpha), _dev_ptr(tgt_depth), _dev_ptr(err),
+                                                 self._stream()), self._ctx)
+        return err
 
     # ----------------------------------------------------------------- tracking
     def track(self, params, camera, pose, tgt_rgb, tgt_depth, n_iters: int, lr=(1e-3,) * 3 + (3e-3,) * 3,
