@@ -7,6 +7,9 @@
   M_n = [N_r . r > 0] (r the pixel's unit ray, camera frame) and
   M_o = [O > 0.95].  |Omega| is every pixel.  Masks are held constant in the
   gradient; the L1 derivative at zero is zero.
+* ``image_loss``: the masked, weighted L1 over colour, depth and normal that the
+  tracking loss, the single-frame workload's loss and the mapping window's loss are
+  instances of.
 * ``tracking_error``: the relocalisation check e_t (eq:tracking_error), the masked
   depth L1 of the tracking loss on its own.
 * ``frame_loss``: unmasked L1 over colour, depth and normal, averaged over
@@ -64,6 +67,35 @@ def tracking_loss(rgb, depth, normal, alpha, tgt_rgb, tgt_depth, camera, lambda_
     d_rgb = m[None] * np.sign(dr) / hw
     d_depth = lambda_d * m * np.sign(dd) / hw
     return loss, d_rgb, d_depth, m.astype(bool)
+
+
+def image_loss(rgb, depth, normal, alpha, tgt_rgb, tgt_depth, tgt_normal, camera, w_rgb=1.0, w_d=1.0, w_n=0.0,
+               normal_mask=True, opacity_mask=True, decision_dtype=np.float32):
+    """(1/|Omega|) sum_p M(p) (w_rgb |d rgb|_1 + w_d |d D| + w_n |d N|_1) with M the
+    product of the selected masks (M_n, M_o; none: 1), and its gradients to the three
+    rendered images (masks constant, d|x|/dx = 0 at 0).  The tracking loss is
+    (1, lambda_d, 0, both masks); the single-frame L1 (1, 1, 1, no masks); the mapping
+    window's (1, 0.5, 0, opacity mask only).  Returns (loss, d_rgb, d_depth, d_normal)."""
+    _, _, W, H = _rays(camera)
+    m = np.ones((H, W), dtype=bool)
+    if normal_mask or opacity_mask:
+        m_n, m_o, _ = masks(normal, alpha, camera, decision_dtype)
+        if normal_mask:
+            m &= m_n
+        if opacity_mask:
+            m &= m_o
+    mf = m.astype(np.float64)
+    hw = float(H * W)
+    dr = np.asarray(rgb, dtype=np.float64) - np.asarray(tgt_rgb, dtype=np.float64)
+    dd = np.asarray(depth, dtype=np.float64) - np.asarray(tgt_depth, dtype=np.float64)
+    terms = w_rgb * np.abs(dr).sum(axis=0) + w_d * np.abs(dd)
+    d_normal = np.zeros((3, H, W))
+    if w_n != 0.0:
+        dn = np.asarray(normal, dtype=np.float64) - np.asarray(tgt_normal, dtype=np.float64)
+        terms = terms + w_n * np.abs(dn).sum(axis=0)
+        d_normal = w_n * mf[None] * np.sign(dn) / hw
+    loss = float(np.sum(mf * terms) / hw)
+    return loss, w_rgb * mf[None] * np.sign(dr) / hw, w_d * mf * np.sign(dd) / hw, d_normal
 
 
 def tracking_error(depth, normal, alpha, tgt_depth, camera, decision_dtype=np.float32):

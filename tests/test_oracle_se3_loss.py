@@ -120,3 +120,40 @@ def test_adamw_first_step_closed_form():
     # second step with the same gradient: still -lr sign(g) up to eps
     T2, tau2 = loss.adamw_pose_step(T1, g, st, lr)
     np.testing.assert_allclose(tau2, -lr * g / (np.abs(g) + 1e-8), rtol=1e-9)
+
+
+def test_image_loss_instances():
+    """The general masked L1 against the tracking loss (both masks, no normal term), the
+    unmasked frame loss (all three terms), and a hand-worked opacity-mask-only case."""
+    import oracle
+
+    s = synth.random_surfels(2000, seed=0)
+    t = synth.random_surfels(2000, seed=1)
+    o = oracle.render(s.params, s.camera, s.pose)
+    g = oracle.render(t.params, t.camera, t.pose)
+    L, d_rgb, d_depth, _ = loss.tracking_loss(o["rgb"], o["depth"], o["normal"], o["alpha"], g["rgb"], g["depth"],
+                                              s.camera, lambda_d=0.7)
+    G = loss.image_loss(o["rgb"], o["depth"], o["normal"], o["alpha"], g["rgb"], g["depth"], g["normal"], s.camera,
+                        w_rgb=1.0, w_d=0.7, w_n=0.0)
+    assert G[0] == pytest.approx(L, rel=1e-14)
+    np.testing.assert_array_equal(G[1], d_rgb)
+    np.testing.assert_array_equal(G[2], d_depth)
+    assert not G[3].any()
+    F = loss.frame_loss(o["rgb"], o["depth"], o["normal"], g["rgb"], g["depth"], g["normal"])
+    G = loss.image_loss(o["rgb"], o["depth"], o["normal"], o["alpha"], g["rgb"], g["depth"], g["normal"], s.camera,
+                        w_rgb=1.0, w_d=1.0, w_n=1.0, normal_mask=False, opacity_mask=False)
+    assert G[0] == pytest.approx(F[0], rel=1e-14)
+    for a, b in zip(G[1:], F[1:]):
+        np.testing.assert_array_equal(a, b)
+    # 1 x 2 image: the opacity mask keeps pixel 0 only; the normal mask is not applied
+    cam = synth.Camera(2, 1, 1.0, 1.0, 0.5, 0.0)
+    rgb = np.array([[[0.5, 0.5]], [[0.2, 0.2]], [[0.9, 0.9]]])
+    tgt = np.zeros_like(rgb)
+    depth, tdepth = np.array([[2.0, 2.0]]), np.array([[1.0, 1.0]])
+    normal = np.zeros((3, 1, 2))
+    normal[2] = -1.0  # back faces: the normal mask would reject both pixels
+    alpha = np.array([[0.99, 0.9]])
+    G = loss.image_loss(rgb, depth, normal, alpha, tgt, tdepth, None, cam, w_rgb=1.0, w_d=0.5, w_n=0.0,
+                        normal_mask=False, opacity_mask=True)
+    assert G[0] == pytest.approx((0.5 + 0.2 + 0.9 + 0.5 * 1.0) / 2, rel=1e-15)
+    np.testing.assert_array_equal(G[2], [[0.5 / 2, 0.0]])
