@@ -231,6 +231,207 @@ def map_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _replay_times(graph, reps):
+    """Per-replay GPU times (ms) of a captured graph, each bracketed by its own events."""
+    import torch
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        graph.replay()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def config1_bench(args):
+    """Single frame: 2,000 random surfels at 64x48, forward render, the unmasked L1 over
+    colour, depth and normal against a second seeded render, and the backward to all
+    surfel parameters and the pose, captured into one graph after the autotuner has
+    picked the tile shape and LDS batch; median of 1,000 replays."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_00970_amd import Rasterizer
+
+    dev = torch.device("cuda", 0)
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    s, t = synth.random_surfels(2000, seed=0), synth.random_surfels(2000, seed=1)
+    cam = s.camera
+    r = Rasterizer(device=0)
+    tg = r.render(to_dev(t.params), cam, to_dev(t.pose.reshape(12)))
+    trgb, tdep, tnrm = tg.rgb.clone(), tg.depth.clone(), tg.normal.clone()
+    P, pose = to_dev(s.params), to_dev(s.pose.reshape(12))
+    # 12 tiles of 16 x 16: each blend is one tile's walk; the autotuner weighs smaller tiles
+    tuning = r.autotune(P, cam, pose)
+
+    def step():
+        out = r.render_batch([(P, cam, pose)])[0]
+        _, d_rgb, d_depth, d_normal = r.image_loss(cam, out.rgb, out.depth, out.normal, out.alpha, trgb, tdep, tnrm,
+                                                   w_rgb=1.0, w_depth=1.0, w_normal=1.0)
+        return r.backward_batch(out.generation, [{"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": d_normal}],
+                                params_grad=True)
+
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            step()
+    st.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=st):
+        step()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    times = _replay_times(graph, 1000)
+    med = float(np.median(times))
+    print(json.dumps({
+        "metric": "single-frame fwd+bwd (all surfel params + pose) wall time, graph replay, median of 1,000",
+        "value": med * 1e3, "unit": "us", "n_gpus": 1, "steps": 1000, "warmup": args.warmup,
+        "ms_per_step": med, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2,000 random surfels (seed 0), 64x48 f=60, L1 on colour, depth and normal against "
+                               "the render of seed 1; render + loss + backward in one HIP graph", "tuning": tuning},
+        "mean_us": float(np.mean(times)) * 1e3, "p90_us": float(np.percentile(times, 90)) * 1e3,
+        "counts": r.counts()}), flush=True)
+
+
+def config3_bench(args):
+    """Mapping window: 8 keyframes (4 at 640x480, 4 at 1200x680) over a 1M-surfel room;
+    the optimised state is the room with its centres jittered by 5 mm and colours by
+    0.05, the poses by 2 cm / 1 deg; targets are renders of the true room.  One
+    iteration renders the 8 views in one batched launch, forms each view's opacity-
+    masked colour + 0.5 depth L1, and runs the batched backward to all 15 surfel
+    parameters and the 8 poses; autotuned tile and batch, captured into one graph."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_00970_amd import Rasterizer
+
+    dev = torch.device("cuda", 0)
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    cam_s = synth.Camera(640, 480, 525.0, 525.0, 320.0, 240.0)
+    cam_l = synth.Camera(1200, 680, 600.0, 600.0, 600.0, 340.0)
+    cams = [cam_s] * 4 + [cam_l] * 4
+    log("building the 1M-surfel room")
+    room = synth.make_room(1_000_000, seed=100)
+    gt = [synth.room_camera(room, seed=100 + k) for k in range(8)]
+    g = np.random.default_rng(100)
+    state = room.params.astype(np.float32).copy()
+    state[0:3] += g.normal(0.0, 0.005, state[0:3].shape).astype(np.float32)
+    state[12:15] += g.normal(0.0, 0.05, state[12:15].shape).astype(np.float32)
+    poses = [synth.perturb_pose(gt[k], 0.02, 1.0, seed=200 + k) for k in range(8)]
+    r = Rasterizer(device=0)
+    Pgt = to_dev(room.params)
+    targets = []
+    for k in range(8):
+        o = r.render(Pgt, cams[k], to_dev(gt[k].reshape(12)))
+        targets.append((o.rgb.clone(), o.depth.clone()))
+    del Pgt
+    P = to_dev(state)
+    pose_t = [to_dev(p.reshape(12)) for p in poses]
+    tuning = r.autotune(P, cam_l, pose_t[4])
+    views = [(P, cams[k], pose_t[k]) for k in range(8)]
+
+    def step():
+        outs = r.render_batch(views)
+        grads = []
+        for k, o in enumerate(outs):
+            _, d_rgb, d_depth, _ = r.image_loss(cams[k], o.rgb, o.depth, o.normal, o.alpha, targets[k][0],
+                                                targets[k][1], None, w_rgb=1.0, w_depth=0.5, opacity_mask=True)
+            grads.append({"d_rgb": d_rgb, "d_depth": d_depth})
+        return r.backward_batch(outs[0].generation, grads, params_grad=True)
+
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(2):
+            step()
+    st.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=st):
+        step()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    steps = min(args.steps, 50)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    times = _replay_times(graph, 20)
+    print(json.dumps({
+        "metric": "mapping-window iterations/s (8 views fwd + bwd to all surfel params and poses), 1M surfels",
+        "value": steps / el, "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / steps, "higher_is_better": True, "scaling": "weak", "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "8 keyframes (4 x 640x480 f=525, 4 x 1200x680 f=600) of a 1M-surfel synthetic room "
+                               "(seed 100), state jittered 5 mm / 0.05 colour, poses 2 cm / 1 deg; opacity-masked "
+                               "colour + 0.5 depth L1 per view; one HIP graph per iteration", "tuning": tuning},
+        "median_replay_ms": float(np.median(times)), "counts": r.counts()}), flush=True)
+
+
+def config4_bench(args):
+    """Batched tracking: 32 independent problems (320x240 .. 1200x680, 50k .. 1M surfels,
+    2-8 cm / 1-5 deg starts), 50 graph-captured iterations of all 32 in one launch per
+    kernel per iteration; aggregate iterations/s and per-problem convergence."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_00970_amd import Rasterizer
+
+    dev = torch.device("cuda", 0)
+    to_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    res = [(320, 240), (640, 480), (848, 480), (1200, 680)]
+    r = Rasterizer(device=0)
+    batch, gts = [], []
+    log("building 32 rooms")
+    for j in range(32):
+        g = np.random.default_rng(1000 + j)
+        W, H = res[g.integers(0, 4)]
+        f = 525.0 * W / 640.0
+        cam = synth.Camera(W, H, f, f, W / 2.0, H / 2.0)
+        n = int(round(np.exp(g.uniform(np.log(5e4), np.log(1e6)))))
+        room = synth.make_room(n, seed=1000 + j)
+        gt = synth.room_camera(room, seed=1000 + j)
+        start = synth.perturb_pose(gt, g.uniform(0.02, 0.08), g.uniform(1.0, 5.0), seed=2000 + j)
+        P = to_dev(room.params)
+        tgt = r.render(P, cam, to_dev(gt.reshape(12)))
+        batch.append((P, cam, to_dev(start.reshape(12)), tgt.rgb.clone(), tgt.depth.clone()))
+        gts.append(gt)
+    starts = [b[2].clone() for b in batch]
+    r.track_batch(batch, n_iters=args.warmup)
+    for b, s0 in zip(batch, starts):
+        b[2].copy_(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ph, lh = r.track_batch(batch, n_iters=50)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hist = ph.cpu().numpy().astype(np.float64)
+    conv = []
+    for j in range(32):
+        it = None
+        for i in range(hist.shape[0]):
+            e_t, e_r = synth.pose_error(hist[i, j].reshape(3, 4), gts[j])
+            if e_t < 0.01 and e_r < 0.5:
+                it = i + 1
+                break
+        conv.append(it)
+    print(json.dumps({
+        "metric": "batched tracking: aggregate iterations/s of 32 independent problems, 50 iterations",
+        "value": 32 * 50 / el, "unit": "iters/s", "n_gpus": 1, "steps": 50, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / 50, "higher_is_better": True, "scaling": "weak", "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "32 seeded rooms (seeds 1000-1031), 320x240..1200x680, 50k..1M surfels, "
+                               "2-8 cm / 1-5 deg starts, tracking loss with masks, lambda_d = 1"},
+        "iters_to_converge": conv, "converged": sum(c is not None for c in conv),
+        "ms_to_converge_median": float(np.median([c for c in conv if c])) * 1e3 * el / 50 if any(conv) else None}),
+        flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,7 +448,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run 3 plain device copies of 256 MiB (reference for HBM traffic counters)")
     ap.add_argument("--map", action="store_true",
-                    help="measure the map bookkeeping (contribution blend and map kernels) instead")
+                    help="measure the mapping side (contribution render, mapping loss and iteration, map kernels)")
+    ap.add_argument("--config", type=int, choices=(1, 3, 4),
+                    help="measure another workload instead: 1 single frame, 3 mapping window, 4 batched tracking")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path: "
@@ -255,6 +458,8 @@ def main():
         sys.exit(2)
     if args.map:
         return map_bench(args)
+    if args.config:
+        return {1: config1_bench, 3: config3_bench, 4: config4_bench}[args.config](args)
 
     import numpy as np
     import torch

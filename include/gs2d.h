@@ -235,6 +235,28 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
                                 int32_t use_masks, float* loss, float* d_rgb, float* d_depth,
                                 hipStream_t stream);
 
+/* Weights and masks of gs2d_image_loss. */
+typedef struct gs2d_loss_weights {
+  float w_rgb, w_depth, w_normal;
+  int32_t normal_mask;   /* 1: M_n = [normal . ray > 0] (eq:normal_mask) */
+  int32_t opacity_mask;  /* 1: M_o = [alpha > 0.95] (eq:opacity_mask) */
+} gs2d_loss_weights;
+
+/* Masked L1 image loss: L = (1/HW) sum_p M (w_rgb |rgb - tgt_rgb|_1 + w_depth |depth -
+ * tgt_depth| + w_normal |normal - tgt_normal|_1), M the product of the selected masks
+ * (1 with none).  The tracking loss (eq:tracking_loss) is (1, lambda_d, 0) with both
+ * masks; the unmasked single-frame L1 over colour, depth and normal is (1, 1, 1); the
+ * mapping window's colour and depth terms (Sec. "Mapping", w_d = 0.5) under the opacity
+ * mask are (1, 0.5, 0) with opacity_mask only.  rgb/tgt_rgb may be NULL when w_rgb = 0
+ * and d_rgb is NULL, normal/tgt_normal when w_normal = 0, d_normal is NULL and the
+ * normal mask is off.  Writes *loss (device scalar) and, where not NULL, the gradients
+ * (masks constant, d|x|/dx = 0 at 0) to d_rgb [3][H][W], d_depth [H][W], d_normal
+ * [3][H][W]. */
+GS2D_API int gs2d_image_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const float* rgb, const float* depth,
+                             const float* normal, const float* alpha, const float* tgt_rgb, const float* tgt_depth,
+                             const float* tgt_normal, const gs2d_loss_weights* weights, float* loss, float* d_rgb,
+                             float* d_depth, float* d_normal, hipStream_t stream);
+
 /* Relocalisation error of Sec. "Loop Detection and Relocalization" (eq:tracking_error):
  * e_t = (1/HW) sum_p M_n M_o |depth - tgt_depth|, the depth term of the tracking loss
  * with its masks (M_n = [normal . ray > 0], M_o = [alpha > 0.95]), computed on the

@@ -68,6 +68,11 @@ class MappingWeights(ctypes.Structure):
                 ("w_n", ctypes.c_float)]
 
 
+class LossWeights(ctypes.Structure):
+    _fields_ = [("w_rgb", ctypes.c_float), ("w_depth", ctypes.c_float), ("w_normal", ctypes.c_float),
+                ("normal_mask", ctypes.c_int32), ("opacity_mask", ctypes.c_int32)]
+
+
 class View(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
@@ -119,6 +124,8 @@ _SIGS = {
     "gs2d_tracking_loss": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
                             _P, _P, _P, _P], ctypes.c_int),
     "gs2d_tracking_error": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "gs2d_image_loss": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(LossWeights), _P, _P,
+                         _P, _P, _P], ctypes.c_int),
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),

@@ -421,7 +421,7 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
     ViewDesc& d = vs.v[k];
     d.g_rgb = const_cast<float*>(grads[k].d_rgb);
     d.g_depth = const_cast<float*>(grads[k].d_depth);
-    d.g_normal = grads[k].d_normal;
+    d.g_normal = const_cast<float*>(grads[k].d_normal);
     d.g_alpha = grads[k].d_alpha;
     d.d_pose = grads[k].d_pose;
     full = full || grads[k].d_params != nullptr;
@@ -871,6 +871,52 @@ GS2D_API int gs2d_tracking_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const 
   {
     ProfScope ps(ctx, kLoss, stream);
     launch_tracking_loss(ctx->views, 1, hw, lambda_d, use_masks, ctx->lpart, loss_blocks(hw), stream);
+  }
+  {
+    ProfScope ps(ctx, kReduce, stream);
+    launch_reduce_loss(ctx->lpart, loss_blocks(hw), 1.0f / (float)hw, loss, stream);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_image_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const float* rgb, const float* depth,
+                             const float* normal, const float* alpha, const float* tgt_rgb, const float* tgt_depth,
+                             const float* tgt_normal, const gs2d_loss_weights* w, float* loss, float* d_rgb,
+                             float* d_depth, float* d_normal, hipStream_t stream) {
+  if (!ctx || !valid_camera(camera) || !w || !loss || !depth || !tgt_depth) return GS2D_ERR_INVALID_ARG;
+  if (!std::isfinite(w->w_rgb) || !std::isfinite(w->w_depth) || !std::isfinite(w->w_normal))
+    return GS2D_ERR_INVALID_ARG;
+  if ((w->w_rgb != 0.f || d_rgb) && (!rgb || !tgt_rgb)) return GS2D_ERR_INVALID_ARG;
+  if ((w->w_normal != 0.f || d_normal) && (!normal || !tgt_normal)) return GS2D_ERR_INVALID_ARG;
+  if ((w->normal_mask && !normal) || (w->opacity_mask && !alpha)) return GS2D_ERR_INVALID_ARG;
+  GS2D_TRY(set_device(ctx));
+  const int hw = camera->width * camera->height;
+  bool capturing = false;
+  if (stream_capturing(stream, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+  if (loss_blocks(hw) > ctx->lpart_cap && capturing) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_lpart(ctx, loss_blocks(hw)));
+  ViewSet vs;
+  vs.n_views = 1;
+  ViewDesc& d = vs.v[0];
+  std::memset(&d, 0, sizeof(d));
+  d.cam = camf(*camera);
+  const bool colour = w->w_rgb != 0.f || d_rgb, normals = w->w_normal != 0.f || d_normal;
+  d.rgb = colour ? const_cast<float*>(rgb) : nullptr;
+  d.tgt_rgb = colour ? tgt_rgb : nullptr;
+  d.depth = const_cast<float*>(depth);
+  d.tgt_depth = tgt_depth;
+  d.normal = const_cast<float*>(normal);
+  d.tgt_normal = normals ? tgt_normal : nullptr;
+  d.alpha = const_cast<float*>(alpha);
+  d.g_rgb = d_rgb;
+  d.g_depth = d_depth;
+  d.g_normal = d_normal;
+  launch_upload_views(vs, ctx->views, stream);
+  {
+    ProfScope ps(ctx, kLoss, stream);
+    launch_image_loss(ctx->views, 1, hw, LossW{w->w_rgb, w->w_depth, w->w_normal, w->normal_mask, w->opacity_mask},
+                      ctx->lpart, loss_blocks(hw), stream);
   }
   {
     ProfScope ps(ctx, kReduce, stream);

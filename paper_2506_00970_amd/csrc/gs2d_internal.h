@@ -52,10 +52,11 @@ struct ViewDesc {
   float* alpha;
   float* g_rgb;          // image gradients (backward inputs; tracking-loss outputs)
   float* g_depth;
-  const float* g_normal;
+  float* g_normal;       // (the image loss writes it when it has a normal term)
   const float* g_alpha;
   const float* tgt_rgb;  // tracking targets
   const float* tgt_depth;
+  const float* tgt_normal;  // image loss with a normal term
   float* d_pose;         // [6] pose gradient out (nullable)
   float* contrib;        // [n] per-surfel contribution out (nullable; forward blend)
   float* depth_norm;     // [H][W] D / O out (nullable; forward blend)
@@ -288,10 +289,22 @@ void launch_blend_bwd(const BlendArgs& a, int tile_w, int tile_h, const float* t
 
 // loss_pose.hip
 int loss_blocks(int hw);
-// Tracking loss of every view: images, targets and gradient outputs at the view
-// table's pointers; partial sums at part[v * part_stride + block].
-void launch_tracking_loss(const ViewDesc* views, int n_views, int max_hw, float lambda_d, int use_masks,
-                          float* part, int part_stride, hipStream_t s);
+// Weights and masks of the masked L1 image loss (the tracking loss is {1, lambda_d, 0,
+// masks, masks}).
+struct LossW {
+  float w_rgb, w_d, w_n;
+  int normal_mask, opacity_mask;
+};
+// Image loss of every view: images, targets and gradient outputs at the view table's
+// pointers (colour, normal and gradient pointers may be null: term or output skipped);
+// partial sums at part[v * part_stride + block].
+void launch_image_loss(const ViewDesc* views, int n_views, int max_hw, LossW w, float* part, int part_stride,
+                       hipStream_t s);
+inline void launch_tracking_loss(const ViewDesc* views, int n_views, int max_hw, float lambda_d, int use_masks,
+                                 float* part, int part_stride, hipStream_t s) {
+  launch_image_loss(views, n_views, max_hw, LossW{1.0f, lambda_d, 0.0f, use_masks, use_masks}, part, part_stride,
+                    s);
+}
 void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, hipStream_t s);
 // d_pose = sum of rows [row0, row0 + rows) of `part` (one launch).
 void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, int accumulate, hipStream_t s);

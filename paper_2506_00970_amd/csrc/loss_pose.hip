@@ -1,8 +1,11 @@
-// Tracking loss with its image gradients, partial-sum reductions, and the pose step.
+// Image losses with their image gradients, partial-sum reductions, and the pose step.
 //
-// Tracking loss (Sec. "Tracking and Keyframe Selection", eq:LD, eq:normal_mask,
-// eq:opacity_mask, eq:tracking_loss), one lane per pixel:
-//   L = (1/HW) sum_p M_n M_o (|rgb - I|_1 + lambda_d |D - D_obs|),
+// The masked L1 image loss, one lane per pixel:
+//   L = (1/HW) sum_p M (w_rgb |rgb - I|_1 + w_d |D - D_obs| + w_n |N - N_obs|_1),
+// M the product of the selected masks.  The tracking loss (Sec. "Tracking and Keyframe
+// Selection", eq:LD, eq:normal_mask, eq:opacity_mask, eq:tracking_loss) is w = (1,
+// lambda_d, 0) with both masks, the relocalisation error e_t (eq:tracking_error) its
+// depth term:
 //   M_n = [N . r > 0] (the sign does not depend on normalising the ray, so the
 //   ray (x - cx)/fx, (y - cy)/fy, 1 is used), M_o = [O > 0.95].
 // Gradients hold the masks fixed and take d|x|/dx = sign(x) (0 at 0).  Each
@@ -13,9 +16,8 @@
 namespace gs2d {
 namespace {
 
-__global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(const ViewDesc* __restrict__ views,
-                                                                     float lambda_d, int use_masks,
-                                                                     float* __restrict__ part, int part_stride) {
+__global__ __launch_bounds__(kLossThreads) void image_loss_kernel(const ViewDesc* __restrict__ views, LossW w,
+                                                                  float* __restrict__ part, int part_stride) {
   const ViewDesc& V = views[blockIdx.y];
   const CamF cam = V.cam;
   const int HW = cam.width * cam.height;
@@ -24,30 +26,41 @@ __global__ __launch_bounds__(kLossThreads) void tracking_loss_kernel(const ViewD
   if (p < HW) {
     const float* rgb = V.rgb;
     const float* tgt_rgb = V.tgt_rgb;
+    const float* normal = V.normal;
     const int y = p / cam.width, x = p - y * cam.width;
     bool m = true;
-    if (use_masks) {
-      const float* normal = V.normal;
+    if (w.normal_mask) {
       const float xh = ((float)x - cam.cx) / cam.fx, yh = ((float)y - cam.cy) / cam.fy;
       const float ndr = fmaf(normal[p], xh, fmaf(normal[HW + p], yh, normal[2 * HW + p]));
-      m = (ndr > 0.0f) && (V.alpha[p] > kOpacityMask);
+      m = ndr > 0.0f;
     }
+    if (w.opacity_mask) m = m && (V.alpha[p] > kOpacityMask);
     const float inv = 1.0f / (float)HW;
-    // no colour images: the depth term alone (the relocalisation error e_t)
+    // no colour images: no colour term (the relocalisation error e_t is the depth term)
     const float d0 = rgb ? rgb[p] - tgt_rgb[p] : 0.f;
     const float d1 = rgb ? rgb[HW + p] - tgt_rgb[HW + p] : 0.f;
     const float d2 = rgb ? rgb[2 * HW + p] - tgt_rgb[2 * HW + p] : 0.f;
     const float dd = V.depth[p] - V.tgt_depth[p];
+    const bool has_n = V.tgt_normal != nullptr;
+    const float n0 = has_n ? normal[p] - V.tgt_normal[p] : 0.f;
+    const float n1 = has_n ? normal[HW + p] - V.tgt_normal[HW + p] : 0.f;
+    const float n2 = has_n ? normal[2 * HW + p] - V.tgt_normal[2 * HW + p] : 0.f;
     auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
-    float* d_rgb = V.g_rgb;
-    float* d_depth = V.g_depth;
-    if (m) l = fabsf(d0) + fabsf(d1) + fabsf(d2) + lambda_d * fabsf(dd);
-    if (d_rgb) {
-      d_rgb[p] = m ? sgn(d0) * inv : 0.f;
-      d_rgb[HW + p] = m ? sgn(d1) * inv : 0.f;
-      d_rgb[2 * HW + p] = m ? sgn(d2) * inv : 0.f;
+    if (m) {
+      l = w.w_rgb * (fabsf(d0) + fabsf(d1) + fabsf(d2)) + w.w_d * fabsf(dd);
+      if (has_n) l += w.w_n * (fabsf(n0) + fabsf(n1) + fabsf(n2));
     }
-    if (d_depth) d_depth[p] = m ? lambda_d * sgn(dd) * inv : 0.f;
+    if (float* d_rgb = V.g_rgb) {
+      d_rgb[p] = m ? w.w_rgb * sgn(d0) * inv : 0.f;
+      d_rgb[HW + p] = m ? w.w_rgb * sgn(d1) * inv : 0.f;
+      d_rgb[2 * HW + p] = m ? w.w_rgb * sgn(d2) * inv : 0.f;
+    }
+    if (float* d_depth = V.g_depth) d_depth[p] = m ? w.w_d * sgn(dd) * inv : 0.f;
+    if (float* d_normal = V.g_normal) {
+      d_normal[p] = m ? w.w_n * sgn(n0) * inv : 0.f;
+      d_normal[HW + p] = m ? w.w_n * sgn(n1) * inv : 0.f;
+      d_normal[2 * HW + p] = m ? w.w_n * sgn(n2) * inv : 0.f;
+    }
   }
   __shared__ float red[kLossThreads];
   red[threadIdx.x] = l;
@@ -246,10 +259,10 @@ void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, h
 
 int loss_blocks(int hw) { return (hw + kLossThreads - 1) / kLossThreads; }
 
-void launch_tracking_loss(const ViewDesc* views, int n_views, int max_hw, float lambda_d, int use_masks,
-                          float* part, int part_stride, hipStream_t s) {
+void launch_image_loss(const ViewDesc* views, int n_views, int max_hw, LossW w, float* part, int part_stride,
+                       hipStream_t s) {
   const dim3 grid(loss_blocks(max_hw), n_views);
-  tracking_loss_kernel<<<grid, kLossThreads, 0, s>>>(views, lambda_d, use_masks, part, part_stride);
+  image_loss_kernel<<<grid, kLossThreads, 0, s>>>(views, w, part, part_stride);
 }
 
 void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, hipStream_t s) {

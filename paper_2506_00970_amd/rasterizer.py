@@ -276,6 +276,34 @@ class Rasterizer:
                                                 self._stream()), self._ctx)
         return loss, d_rgb, d_depth
 
+    def image_loss(self, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, tgt_normal, w_rgb=1.0, w_depth=1.0,
+                   w_normal=0.0, normal_mask=False, opacity_mask=False, grads=True):
+        """Masked L1 over colour, depth and normal (gs2d_image_loss).  Returns (loss scalar
+        tensor, d_rgb, d_depth, d_normal), the gradients None where not asked for (grads
+        False) or where their term has no weight and no images."""
+        cam = _camera(camera)
+        H, W = cam.height, cam.width
+        colour = w_rgb != 0.0
+        normals = w_normal != 0.0
+        for t, nm, shp, need in ((rgb, "rgb", (3, H, W), colour), (tgt_rgb, "tgt_rgb", (3, H, W), colour),
+                                 (depth, "depth", (H, W), True), (tgt_depth, "tgt_depth", (H, W), True),
+                                 (normal, "normal", (3, H, W), normals or normal_mask),
+                                 (tgt_normal, "tgt_normal", (3, H, W), normals), (alpha, "alpha", (H, W), opacity_mask)):
+            if need and t is None:
+                raise ValueError(f"{nm} is required")
+            _check_tensor(t, nm, shp, self.device)
+        mk = lambda c: torch.empty((c, H, W) if c > 1 else (H, W), dtype=torch.float32, device=self.device)
+        d_rgb = mk(3) if grads and colour else None
+        d_depth = mk(1) if grads else None
+        d_normal = mk(3) if grads and normals else None
+        loss = torch.empty((), dtype=torch.float32, device=self.device)
+        w = _lib.LossWeights(float(w_rgb), float(w_depth), float(w_normal), int(normal_mask), int(opacity_mask))
+        _lib.check(self._lib.gs2d_image_loss(self._ctx, ctypes.byref(cam), _dev_ptr(rgb), _dev_ptr(depth),
+                                             _dev_ptr(normal), _dev_ptr(alpha), _dev_ptr(tgt_rgb), _dev_ptr(tgt_depth),
+                                             _dev_ptr(tgt_normal), ctypes.byref(w), _dev_ptr(loss), _dev_ptr(d_rgb),
+                                             _dev_ptr(d_depth), _dev_ptr(d_normal), self._stream()), self._ctx)
+        return loss, d_rgb, d_depth, d_normal
+
     def tracking_error(self, camera, depth, normal, alpha, tgt_depth):
         """The relocalisation error e_t (eq:tracking_error), a device scalar tensor."""
         cam = _camera(camera)
