@@ -34,11 +34,14 @@ __global__ void upload_views_kernel(ViewChunk c, ViewDesc* __restrict__ dst) {
 }
 
 // One item (view, surfel); returns its tile count.
+template <bool ONE_VIEW>
 __device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, int n_views, int item, float z_near,
                                            int filter, int tile_w, int tile_h, float4* __restrict__ rec,
                                            uint2* __restrict__ rect, uint32_t* __restrict__ count,
                                            uint32_t* __restrict__ dkey, float* __restrict__ saved_pose) {
-  const int v = view_of_item(views, n_views, item);
+  // one view (tracking, single renders): a constant view index, so that its fields come
+  // in through scalar loads rather than a round trip of vector loads
+  const int v = ONE_VIEW ? 0 : view_of_item(views, n_views, item);
   const ViewDesc& V = views[v];
   const float* __restrict__ P = V.params;
   const float* __restrict__ pose = V.pose;
@@ -170,14 +173,15 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
 
 // One thread per item, kPartItems items per block; each block also stores its pair
 // count and visible-item count (the pair duplication places pairs from them).
+template <bool ONE_VIEW>
 __global__ __launch_bounds__(kPartItems) void preprocess_kernel(
     const ViewDesc* __restrict__ views, int n_views, int64_t items, float z_near, int filter, int tile_w,
     int tile_h, float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ count,
     uint32_t* __restrict__ dkey, float* __restrict__ saved_pose, uint32_t* __restrict__ part_pairs,
     uint32_t* __restrict__ part_vis, Ctrl* __restrict__ ctrl) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t cnt = gi < items ? preprocess_item(views, n_views, (int)gi, z_near, filter, tile_w, tile_h, rec,
-                                                    rect, count, dkey, saved_pose)
+  const uint32_t cnt = gi < items ? preprocess_item<ONE_VIEW>(views, n_views, (int)gi, z_near, filter, tile_w,
+                                                              tile_h, rec, rect, count, dkey, saved_pose)
                                   : 0u;
   __shared__ uint32_t sp[kPartItems / 64], sv[kPartItems / 64];
   const uint32_t wp = wave_sum_u32(cnt), wv = wave_sum_u32(cnt != 0u ? 1u : 0u);
@@ -318,8 +322,12 @@ void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float 
                        int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, float* saved_pose,
                        uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s) {
   const int grid = items > 0 ? (int)((items + kPartItems - 1) / kPartItems) : 1;
-  preprocess_kernel<<<grid, kPartItems, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec, rect,
-                                                count, dkey, saved_pose, part_pairs, part_vis, ctrl);
+  if (n_views == 1)
+    preprocess_kernel<true><<<grid, kPartItems, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec,
+                                                        rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl);
+  else
+    preprocess_kernel<false><<<grid, kPartItems, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec,
+                                                         rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl);
 }
 
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc,

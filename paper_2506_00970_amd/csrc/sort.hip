@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
   }
   // key = the view's first global tile + the tile's index within the view
   const int item = (int)j;
-  const ViewDesc& V = a.views[view_of_item(a.views, a.n_views, item)];
+  const ViewDesc& V = a.views[a.n_views == 1 ? 0 : view_of_item(a.views, a.n_views, item)];
   const uint32_t tbase = (uint32_t)V.tile_base, tiles_x = (uint32_t)V.tiles_x;
   const uint32_t tx0 = rc.x & 0xFFFFu, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFFu, ty1 = rc.y >> 16;
   const uint32_t dmask = (1u << a.bits) - 1u;
