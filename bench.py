@@ -176,8 +176,31 @@ def map_bench(args):
     r.profile(reset=True)
     iter_ms = timed(mapping_iteration, args.profile_steps)
     fam = r.profile(reset=True)["families"]
+    # with the Adam step over the surfel parameters: the whole iteration on the device.
+    # Tiny learning rates keep the timed workload (the map) the same from step to step;
+    # the step's cost does not depend on them.
+    Pm = P.clone()
+    opt = mapstate.ParamAdam(Pm, lr=(1e-7,) * 6)
+
+    def mapping_iteration_with_step():
+        outs = r.render_batch([(Pm, cam, p) for p in poses])
+        grads = []
+        for k, out in enumerate(outs):
+            _, d_rgb, d_depth, d_normal = maploss.mapping_loss(out.rgb, out.depth, out.normal, targets[k][0],
+                                                               targets[k][1], cam)
+            grads.append({"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": d_normal})
+        res = r.backward_batch(outs[0].generation, grads, params_grad=True)
+        opt.step(Pm, res[0][0])
+
+    Ps, Gs = P.clone(), torch.randn_like(P)
+    opt_s = mapstate.ParamAdam(Ps)
+    step_ms = timed(lambda: opt_s.step(Ps, Gs), args.profile_steps)
+    del Ps, Gs, opt_s
+    full_ms = timed(mapping_iteration_with_step, args.profile_steps)
     mapping = {"loss_ms_640x480": loss_ms, "iteration_ms_5_views": iter_ms,
-               "iteration_families_ms": {k: fam[k]["ms"] / (args.profile_steps + 1) for k in fam if fam[k]["launches"]}}
+               "iteration_families_ms": {k: fam[k]["ms"] / (args.profile_steps + 1) for k in fam if fam[k]["launches"]},
+               "adam_step_ms": step_ms, "adam_step_GB/s": 7 * 60.0 * args.n / (step_ms * 1e-3) / 1e9,
+               "iteration_with_adam_ms_5_views": full_ms}
     del r
 
     kernels = {}

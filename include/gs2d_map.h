@@ -114,6 +114,26 @@ GS2D_API int gs2d_map_state_update(const float* params, int64_t n, const float* 
 GS2D_API int gs2d_map_correct(float* params, int64_t n, const int32_t* closest_frame, const float* delta,
                               int32_t n_frames, hipStream_t stream);
 
+/* Arguments of gs2d_params_adam.  lr: one learning rate per parameter group, in the
+ * order mu, t_u, t_v, scales, opacity, colour; step: the 1-based step number t of the
+ * bias corrections. */
+typedef struct gs2d_adam_args {
+  float lr[6];
+  float beta1, beta2, eps, weight_decay;
+  int32_t step;
+  float s_min, o_min, o_max;
+} gs2d_adam_args;
+
+/* One Adam step over the surfel parameters params [15][n] with their gradient grad
+ * [15][n] and moments m, v [15][n] (all device float, updated in place): per entry
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^t) / (sqrt(v / (1 - b2^t)) + eps) + weight_decay p),
+ * then the scales (rows 9-10) clamped to >= s_min and the opacity (row 11) to
+ * [o_min, o_max].  The map's optimiser of Sec. "Mapping" (the paper does not state its
+ * constants; Adam is the optimiser of 2D Gaussian splatting maps).  Float32. */
+GS2D_API int gs2d_params_adam(float* params, const float* grad, float* m, float* v, int64_t n,
+                              const gs2d_adam_args* args, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -73,6 +73,12 @@ class LossWeights(ctypes.Structure):
                 ("normal_mask", ctypes.c_int32), ("opacity_mask", ctypes.c_int32)]
 
 
+class AdamArgs(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("step", ctypes.c_int32),
+                ("s_min", ctypes.c_float), ("o_min", ctypes.c_float), ("o_max", ctypes.c_float)]
+
+
 class View(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
                 ("rgb", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
@@ -160,6 +166,7 @@ _SIGS = {
     "gs2d_map_state_update": ([_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P,
                                _P, _P, _P], ctypes.c_int),
     "gs2d_map_correct": ([_P, ctypes.c_int64, _P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "gs2d_params_adam": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(AdamArgs), _P], ctypes.c_int),
     "gs2d_mapping_loss_workspace": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int64),
     "gs2d_mapping_loss": ([ctypes.POINTER(Camera), _P, _P, _P, _P, _P, ctypes.POINTER(MappingWeights), _P, _P, _P,
                            _P, _P, _P], ctypes.c_int),

@@ -3,11 +3,13 @@
 // state update (Sec. "Mapping", eq:map) and map correction (Sec. "Map Correction").
 //
 // All are HBM-bound streams over the splats: one thread per splat for the state update
-// and the correction, four for the covisibility counts and the prune mask, and for the
-// compaction 1024 splats per workgroup in four wave-contiguous rounds.  Decisions on distances and scores are taken in
+// and the correction, four for the covisibility counts, the prune mask and the Adam
+// step over the parameters, and for the compaction 1024 splats per workgroup in four
+// wave-contiguous rounds.  Decisions on distances and scores are taken in
 // double, as in their definitions.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "../../include/gs2d_map.h"
@@ -336,6 +338,55 @@ __global__ __launch_bounds__(kThreads) void correct_kernel(float* __restrict__ p
   }
 }
 
+// Adam over the surfel parameters [15][n]: row blockIdx.y, four surfels per thread
+// (16-byte accesses when n and the four arrays allow them).
+struct AdamP {
+  float lr[6];
+  float b1, b2, eps, wd;
+  float ic1, ic2;  // 1 / (1 - b1^t), 1 / (1 - b2^t)
+  float s_min, o_min, o_max;
+};
+
+__device__ __forceinline__ float adam_one(float p, float g, float& m, float& v, float lr, const AdamP& a, int row) {
+  m = fmaf(a.b1, m, (1.0f - a.b1) * g);
+  v = fmaf(a.b2, v, (1.0f - a.b2) * g * g);
+  const float step = (m * a.ic1) / (sqrtf(v * a.ic2) + a.eps);
+  p -= lr * fmaf(a.wd, p, step);
+  if (row == 9 || row == 10) p = fmaxf(p, a.s_min);
+  if (row == 11) p = fminf(fmaxf(p, a.o_min), a.o_max);
+  return p;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void params_adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                               float* __restrict__ m, float* __restrict__ v,
+                                                               int64_t n, AdamP a) {
+  const int row = blockIdx.y;
+  const int grp = row < 3 ? 0 : row < 6 ? 1 : row < 9 ? 2 : row < 11 ? 3 : row == 11 ? 4 : 5;
+  const float lr = a.lr[grp];
+  const int64_t k0 = 4 * ((int64_t)blockIdx.x * kThreads + threadIdx.x);
+  if (k0 >= n) return;
+  const size_t base = (size_t)row * (size_t)n;
+  if (VEC && k0 + 4 <= n) {
+    float4 pp = *reinterpret_cast<float4*>(p + base + k0), gg = *reinterpret_cast<const float4*>(g + base + k0);
+    float4 mm = *reinterpret_cast<float4*>(m + base + k0), vv = *reinterpret_cast<float4*>(v + base + k0);
+    pp.x = adam_one(pp.x, gg.x, mm.x, vv.x, lr, a, row);
+    pp.y = adam_one(pp.y, gg.y, mm.y, vv.y, lr, a, row);
+    pp.z = adam_one(pp.z, gg.z, mm.z, vv.z, lr, a, row);
+    pp.w = adam_one(pp.w, gg.w, mm.w, vv.w, lr, a, row);
+    *reinterpret_cast<float4*>(p + base + k0) = pp;
+    *reinterpret_cast<float4*>(m + base + k0) = mm;
+    *reinterpret_cast<float4*>(v + base + k0) = vv;
+    return;
+  }
+  for (int64_t k = k0; k < n && k < k0 + 4; ++k) {
+    float mk = m[base + k], vk = v[base + k];
+    p[base + k] = adam_one(p[base + k], g[base + k], mk, vk, lr, a, row);
+    m[base + k] = mk;
+    v[base + k] = vk;
+  }
+}
+
 }  // namespace
 }  // namespace map
 }  // namespace gs2d
@@ -414,5 +465,32 @@ GS2D_API int gs2d_map_correct(float* params, int64_t n, const int32_t* closest_f
     return GS2D_ERR_INVALID_ARG;
   if (n == 0 || n_frames == 0) return GS2D_OK;
   correct_kernel<<<blocks_for(n, kThreads), kThreads, 0, stream>>>(params, n, closest_frame, delta, n_frames);
+  return MAP_LAUNCHED();
+}
+
+GS2D_API int gs2d_params_adam(float* params, const float* grad, float* m, float* v, int64_t n,
+                              const gs2d_adam_args* args, hipStream_t stream) {
+  if (n < 0 || !args || args->step < 1 || (n > 0 && (!params || !grad || !m || !v))) return GS2D_ERR_INVALID_ARG;
+  if (!(args->beta1 >= 0.f && args->beta1 < 1.f) || !(args->beta2 >= 0.f && args->beta2 < 1.f) || !(args->eps >= 0.f))
+    return GS2D_ERR_INVALID_ARG;
+  if (n == 0) return GS2D_OK;
+  AdamP a;
+  for (int k = 0; k < 6; ++k) a.lr[k] = args->lr[k];
+  a.b1 = args->beta1;
+  a.b2 = args->beta2;
+  a.eps = args->eps;
+  a.wd = args->weight_decay;
+  a.ic1 = (float)(1.0 / (1.0 - std::pow((double)args->beta1, (double)args->step)));
+  a.ic2 = (float)(1.0 / (1.0 - std::pow((double)args->beta2, (double)args->step)));
+  a.s_min = args->s_min;
+  a.o_min = args->o_min;
+  a.o_max = args->o_max;
+  const dim3 grid((unsigned)blocks_for((n + 3) / 4, kThreads), 15);
+  const bool vec = (n % 4) == 0 && ((reinterpret_cast<uintptr_t>(params) | reinterpret_cast<uintptr_t>(grad) |
+                                      reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+  if (vec)
+    params_adam_kernel<true><<<grid, kThreads, 0, stream>>>(params, grad, m, v, n, a);
+  else
+    params_adam_kernel<false><<<grid, kThreads, 0, stream>>>(params, grad, m, v, n, a);
   return MAP_LAUNCHED();
 }

@@ -143,3 +143,32 @@ def correct(params: torch.Tensor, closest_frame: torch.Tensor, delta: torch.Tens
     _check(d, "delta", (d.shape[0], 12), torch.float32, dev)
     _lib.check(_lib.load().gs2d_map_correct(_dev_ptr(params), n, _dev_ptr(closest_frame), _dev_ptr(d), d.shape[0],
                                             _stream(dev)))
+
+
+class ParamAdam:
+    """Adam over a surfel parameter tensor [15, n] (gs2d_params_adam): one learning
+    rate per group (mu, t_u, t_v, scales, opacity, colour), moments kept here."""
+
+    def __init__(self, params: torch.Tensor, lr=(1.6e-4, 1e-3, 1e-3, 5e-3, 5e-2, 2.5e-3), betas=(0.9, 0.999),
+                 eps: float = 1e-15, weight_decay: float = 0.0, s_min: float = 1e-5, o_min: float = 0.0,
+                 o_max: float = 0.99):
+        n = params.shape[1]
+        _check(params, "params", (15, n), torch.float32, params.device)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.t = 0
+        self.lr, self.betas, self.eps, self.weight_decay = tuple(lr), betas, eps, weight_decay
+        self.s_min, self.o_min, self.o_max = s_min, o_min, o_max
+
+    def step(self, params: torch.Tensor, grad: torch.Tensor) -> None:
+        n = params.shape[1]
+        dev = params.device
+        _check(params, "params", (15, n), torch.float32, dev)
+        _check(grad, "grad", (15, n), torch.float32, dev)
+        if self.m.shape != params.shape:
+            raise ValueError("params changed shape; make a new ParamAdam")
+        self.t += 1
+        a = _lib.AdamArgs((ctypes.c_float * 6)(*self.lr), self.betas[0], self.betas[1], self.eps, self.weight_decay,
+                          self.t, self.s_min, self.o_min, self.o_max)
+        _lib.check(_lib.load().gs2d_params_adam(_dev_ptr(params), _dev_ptr(grad), _dev_ptr(self.m), _dev_ptr(self.v),
+                                                n, ctypes.byref(a), _stream(dev)))
