@@ -89,3 +89,36 @@ def test_warm_start_parameter_count(lib):
     from oracle import warmstart
 
     assert lib.gs2d_ws_param_count() == warmstart.param_count() == 900_326
+
+
+def test_map_entry_points_reject_invalid_arguments(lib):
+    """The mapping-side calls check their arguments before launching anything: invalid
+    ones return GS2D_ERR_INVALID_ARG (runs without a GPU), and empty inputs that need no
+    launch return GS2D_OK."""
+    P = ctypes.c_void_p
+    bad = _lib.ERR_INVALID_ARG
+    dummy = P(16)  # never dereferenced: every call below returns before launching
+    assert lib.gs2d_covisibility(dummy, dummy, -1, 0.5, dummy, dummy, None) == bad
+    assert lib.gs2d_covisibility(dummy, dummy, 10, 0.5, None, dummy, None) == bad
+    assert lib.gs2d_covisibility(dummy, dummy, 10, 0.5, dummy, None, None) == bad
+    assert lib.gs2d_keyframe_test(None, dummy, dummy, 0.9, 0.15, dummy, None) == bad
+    assert lib.gs2d_prune_mask(None, dummy, 0, 0.5, 10, dummy, None) == bad
+    assert lib.gs2d_prune_mask(None, None, 0, 0.5, 0, None, None) == _lib.OK
+    assert lib.gs2d_compact(dummy, 5, 15, 10, None, dummy, 10, dummy, dummy, None) == bad  # in_stride < n
+    assert lib.gs2d_compact(dummy, 10, 0, 10, None, dummy, 10, dummy, dummy, None) == bad  # no planes
+    assert lib.gs2d_compact_workspace(-1) == 0
+    assert lib.gs2d_map_state_update(None, 10, dummy, dummy, 1, 5, -1, dummy, dummy, dummy, dummy, None) == bad
+    assert lib.gs2d_map_state_update(None, 0, None, dummy, 1, 5, -1, None, None, None, None, None) == _lib.OK
+    assert lib.gs2d_map_correct(dummy, 10, None, dummy, 3, None) == bad
+    assert lib.gs2d_map_correct(None, 0, None, None, 0, None) == _lib.OK
+    cam = _lib.Camera(0, 48, 60.0, 60.0, 32.0, 24.0)
+    w = _lib.MappingWeights(0.875, 0.125, 0.5, 0.02)
+    assert lib.gs2d_mapping_loss(ctypes.byref(cam), dummy, dummy, dummy, dummy, dummy, ctypes.byref(w), dummy, dummy,
+                                 dummy, dummy, dummy, None) == bad  # zero width
+    assert lib.gs2d_mapping_loss_workspace(0, 48) == 0
+    a = _lib.AdamArgs((ctypes.c_float * 6)(*([1e-3] * 6)), 0.9, 0.999, 1e-8, 0.0, 0, 0.0, 0.0, 1.0)
+    assert lib.gs2d_params_adam(dummy, dummy, dummy, dummy, 10, ctypes.byref(a), None) == bad  # step 0
+    a.step, a.beta1 = 1, 1.0
+    assert lib.gs2d_params_adam(dummy, dummy, dummy, dummy, 10, ctypes.byref(a), None) == bad  # beta1 = 1
+    a.beta1 = 0.9
+    assert lib.gs2d_params_adam(None, None, None, None, 0, ctypes.byref(a), None) == _lib.OK
