@@ -29,7 +29,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd 2DGS iters/s @640x480, 300k surfels; ms to 1cm/0.5deg pose converge"
-LR = (1e-3, 1e-3, 1e-3, 3e-3, 3e-3, 3e-3)
+LR = (6e-3,) * 6  # the library's tracking default (rasterizer.TRACK_LR)
 HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per
 # lane per clock; transcendental ops occupy 4 issue slots).
