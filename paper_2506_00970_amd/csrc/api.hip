@@ -452,7 +452,7 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
     ProfScope ps(ctx, kReduce, s);
     launch_reduce_pose_views(ctx->views, nv, ctx->part, acc, s);
   } else {
-    launch_fill_f32(ctx->gacc, 0.f, vs.items * 16, s);
+    launch_clear_rows(ctx->count, ctx->gacc, vs.items, s);
     {
       ProfScope ps(ctx, kBlendBwd, s);
       launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, hn, ho, ctx->gacc,
@@ -470,7 +470,8 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
         if (grads[j].d_params == grads[k].d_params && vs.v[j].n > 0) acc_k = 1;
       {
         ProfScope ps(ctx, kPreBwd, s);
-        launch_preprocess_bwd(d.params, d.n, ctx->saved_pose + 12 * k, ctx->gacc + (size_t)16 * d.item_base,
+        launch_preprocess_bwd(d.params, d.n, ctx->saved_pose + 12 * k, ctx->count + d.item_base,
+                              ctx->gacc + (size_t)16 * d.item_base,
                               grads[k].d_params, acc_k, ctx->part, s);
       }
       if (grads[k].d_pose) {

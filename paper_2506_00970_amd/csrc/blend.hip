@@ -512,10 +512,11 @@ __device__ __forceinline__ float dpp_get(float x) {
 // 5, 4, 3, 2 pick the term, then sums the four lanes of each quad.  Every exchange is a
 // VALU lane move: v_permlane32_swap (lanes L, L^32), v_permlane16_swap (rows 0-1 and
 // 2-3), DPP row_ror:8 (L^8 within a row), DPP row_half_mirror (a lane of the other
-// half of its 8-lane group) and quad_perm.  Lanes 4k hold term k, so the row takes one
-// 16-lane atomic store.  Every lane of the wave must be active.
-__device__ __forceinline__ void flush_entry(const float* acc, bool contrib, float* __restrict__ gacc, uint32_t id,
-                                            int lane) {
+// half of its 8-lane group) and quad_perm.  Lanes 4k hold term k and add it into the
+// entry's 16-float slot of the workgroup's LDS accumulator (one 16-lane ds_add, 16
+// banks), which the block adds to the surfel's row in HBM once per batch.  Every lane
+// of the wave must be active.
+__device__ __forceinline__ void flush_entry(const float* acc, bool contrib, float* sacc, int j, int lane) {
   if (__ballot(contrib) == 0ull) return;
   float v16[16], v8[8], v4[4], v2[2];
 #pragma unroll
@@ -544,9 +545,9 @@ __device__ __forceinline__ void flush_entry(const float* acc, bool contrib, floa
   v += dpp_get<0x4E>(v);  // quad_perm [2, 3, 0, 1]
   v += dpp_get<0xB1>(v);  // quad_perm [1, 0, 3, 2]
   const int k = ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
-  using gfloat = __attribute__((address_space(1))) float;
+  using lfloat = __attribute__((address_space(3))) float;
   if ((lane & 3) == 0)
-    __hip_atomic_fetch_add((gfloat*)(gacc + (size_t)id * 16 + k), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add((lfloat*)(sacc + j * 16 + k), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>
@@ -559,6 +560,8 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
                      srec + (size_t)a.batch * (kLdsRec + 2)};
   uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * (kLdsRec + 3));
+  // full mode: per staged entry the block's sums of its 16 terms (zero between batches)
+  float* sacc = reinterpret_cast<float*>(sid + a.batch);
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
@@ -569,6 +572,8 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  if (!POSE_ONLY)
+    for (int k = t; k < a.batch * 16; k += NT) sacc[k] = 0.f;
   const int wx0 = tx * TW + (wave % WX) * 8, wy0 = ty * TH + (wave / WX) * 8;
   const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
   const bool inside = px < cam.width && py < cam.height;
@@ -645,9 +650,23 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
         float acc1[16], acc2[16];
         const bool c1on = live1 && k1 == 2, c2on = live2 && k2 == 2;
         if (c1on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h1, r1, cam, xh, yh, acc1);
-        if (!POSE_ONLY) flush_entry(acc1, c1on, gacc, sid[j1], lane);
+        if (!POSE_ONLY) flush_entry(acc1, c1on, sacc, j1, lane);
         if (c2on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h2, r2, cam, xh, yh, acc2);
-        if (!POSE_ONLY && two) flush_entry(acc2, c2on, gacc, sid[j2], lane);
+        if (!POSE_ONLY && two) flush_entry(acc2, c2on, sacc, j2, lane);
+      }
+    }
+    if (!POSE_ONLY) {
+      // the batch's sums into the surfel rows: one atomic per nonzero term, 16
+      // consecutive floats (one 64 B row) per entry; the slots are left zero
+      __syncthreads();
+      using gfloat = __attribute__((address_space(1))) float;
+      for (int k = t; k < nb * 16; k += NT) {
+        const float v = sacc[k];
+        if (v != 0.f) {
+          __hip_atomic_fetch_add((gfloat*)(gacc + (size_t)sid[k >> 4] * 16 + (k & 15)), v, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+          sacc[k] = 0.f;
+        }
       }
     }
   }
@@ -887,7 +906,9 @@ void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long
 template <int TW, int TH, bool PO, bool HN, bool HO>
 void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, float* gacc, float* part,
                  unsigned long long* work, hipStream_t s) {
-  const size_t lds = (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + sizeof(uint32_t));
+  // as the forward, and in full mode the per-entry term sums
+  const size_t lds =
+      (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + sizeof(uint32_t) + (PO ? 0 : 16 * sizeof(float)));
   if (work)
     blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
   else

@@ -198,8 +198,11 @@ constexpr int kPartItems = 256;  // items per preprocessing block (per-block pai
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
                        int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, float* saved_pose,
                        uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s);
-void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc, float* d_params,
-                           int accumulate, float* part, hipStream_t s);
+// Zero the 16-float accumulator rows of the items whose tile count is nonzero.
+void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStream_t s);
+// count: the items' tile counts (rows of items with none are not read)
+void launch_preprocess_bwd(const float* params, int n, const float* pose, const uint32_t* count, const float* gacc,
+                           float* d_params, int accumulate, float* part, hipStream_t s);
 
 // sort.hip
 constexpr int kScanItems = 1024;   // keys per block of the radix passes

@@ -210,13 +210,28 @@ __device__ inline void cross3(const float* a, const float* b, float* o) {
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Zero the accumulator rows (16 floats) of the items that touch a tile: the only rows
+// the backward blend adds into.  Four threads per row, one float4 each.
+__global__ __launch_bounds__(256) void clear_rows_kernel(const uint32_t* __restrict__ count,
+                                                          float4* __restrict__ gacc, int64_t items) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < items * 4 && count[q >> 2] != 0u) gacc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Per item the parameter gradient from its accumulator row, and the block sums of the
+// pose terms.  An item that touches no tile has a zero gradient and no row to read.
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
-    const float* __restrict__ P, int n, const float* __restrict__ pose,
+    const float* __restrict__ P, int n, const float* __restrict__ pose, const uint32_t* __restrict__ count,
     const float* __restrict__ gacc, float* __restrict__ d_params, int accumulate,
     float* __restrict__ part) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float pr[6] = {0, 0, 0, 0, 0, 0};
-  if (i < n) {
+  const bool hit = i < n && count[i] != 0u;
+  if (i < n && !hit && d_params && !accumulate) {
+#pragma unroll
+    for (int k = 0; k < 15; ++k) d_params[(size_t)k * n + i] = 0.f;
+  }
+  if (hit) {
     float R[9], t[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -330,10 +345,16 @@ void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float 
                                                          rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl);
 }
 
-void launch_preprocess_bwd(const float* params, int n, const float* pose, const float* gacc,
+void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStream_t s) {
+  if (items <= 0) return;
+  const int64_t grid = (items * 4 + 255) / 256;
+  clear_rows_kernel<<<(unsigned)grid, 256, 0, s>>>(count, reinterpret_cast<float4*>(gacc), items);
+}
+
+void launch_preprocess_bwd(const float* params, int n, const float* pose, const uint32_t* count, const float* gacc,
                            float* d_params, int accumulate, float* part, hipStream_t s) {
   const int grid = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
-  preprocess_bwd_kernel<<<grid, 256, 0, s>>>(params, n, pose, gacc, d_params, accumulate, part);
+  preprocess_bwd_kernel<<<grid, 256, 0, s>>>(params, n, pose, count, gacc, d_params, accumulate, part);
 }
 
 }  // namespace gs2d
