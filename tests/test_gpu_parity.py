@@ -121,6 +121,28 @@ def test_gpu_backward_parity_random(gs, seed):
     check_pose(dpose2, og["pose_paper"])
 
 
+_BWD_REF = {}
+
+
+@pytest.mark.parametrize("tile,batch", [((8, 8), 32), ((16, 8), 64), ((32, 16), 256), ((16, 16), 32)])
+def test_gpu_backward_parity_tiles_batches(gs, tile, batch):
+    """The full backward sums each entry's per-surfel terms over the workgroup's waves
+    in an LDS slot per staged entry, then adds them to the surfel rows once per batch:
+    every tile shape (1 to 8 waves per slot) and LDS batch gives the oracle's gradients."""
+    s = synth.random_surfels(2000, seed=0)
+    grads = _random_image_grads(48, 64, 0)
+    if not _BWD_REF:
+        ref = oracle.render(s.params, s.camera, s.pose)
+        _BWD_REF.update(oracle.backward(s.params, s.camera, s.pose, **grads, watch=ref["gmargin"] < 1e-5))
+    og = _BWD_REF
+    r = gs.Rasterizer(tile=tile, batch=batch)
+    out, _ = _render(r, s.params, s.camera, s.pose)
+    dp, dpose = _gpu_backward(r, out.generation, grads)
+    rep = check_grads(dp, og["d_params"], skip=og["touched"])
+    print("grads", tile, batch, rep)
+    check_pose(dpose, og["pose_paper"])
+
+
 def test_gpu_backward_frame_loss(gs):
     """The single-frame workload: L1 on rgb, depth and normal against a second seeded
     render; the image gradients come from the oracle's renders and feed both sides."""
