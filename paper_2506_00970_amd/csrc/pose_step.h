@@ -1,4 +1,4 @@
-// The pose step of tracking, shared by its own kernel and the fused tracking walk.
+// The pose step of tracking: the device side of the AdamW + Exp update of each view.
 //
 // Pose step (Sec. "Tracking and Keyframe Selection": AdamW on the camera pose with
 // the surfels frozen).  The step variable is the left-perturbation twist tau,
@@ -54,7 +54,8 @@ __device__ inline void se3_exp(const double tau[6], double R[9], double tt[3]) {
 
 // The AdamW + Exp step of view v, run by the 256 threads of one workgroup: a
 // fixed-order (deterministic) reduction of the view's pose and loss partials, then
-// the step on one thread.
+// the step on the first wave: lane k < 6 updates the moments of component k, every
+// lane forms the same Exp, and lane k < 12 writes pose entry k.
 __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __restrict__ views,
                                       const float* __restrict__ pose_part, int loss_in_part,
                                       const float* __restrict__ loss_part, int part_stride, const AdamArgs& adam,
@@ -64,68 +65,106 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
   const int HW = V.cam.width * V.cam.height;
   const int rows = V.tiles_x * V.tiles_y;
   const float* pp = pose_part + (size_t)V.tile_base * 8;
-  // the six pose sums and the loss in one pass and one block reduction (fixed order)
-  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < rows; i += blockDim.x)
-#pragma unroll
-    for (int k = 0; k < 6; ++k) acc[k] += (double)pp[(size_t)i * 8 + k];
-  if (loss_in_part) {
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) acc[6] += (double)pp[(size_t)i * 8 + 6];
-  } else {
-    const int nl = (HW + kLossThreads - 1) / kLossThreads;
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) acc[6] += (double)loss_part[(size_t)v * part_stride + i];
+  const int l = threadIdx.x;
+  // the step's state, loaded before the reduction so that its latency overlaps it
+  double m_old = 0.0, v_old = 0.0, T_old = 0.0;
+  if (l < 6) {
+    m_old = ctrl->adam_m[v][l];
+    v_old = ctrl->adam_v[v][l];
   }
-  const int w = threadIdx.x / 64;
+  if (l < 12) T_old = ctrl->master_pose[v][l];
+  const double b1t_old = ctrl->adam_b1t[v], b2t_old = ctrl->adam_b2t[v];
+  const uint32_t it = ctrl->iter_v[v];
+  float* const pose_out = V.pose;
+  // the six pose sums and the loss in one pass and one block reduction (fixed order)
+  // Rows are read kRowsInFlight per thread at a time (two 16-byte loads each), all
+  // issued before the first add; each thread adds its rows in ascending order.
+  constexpr int kRowsInFlight = 8;
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const float4* pp4 = reinterpret_cast<const float4*>(pp);
+  for (int i0 = l; i0 < rows; i0 += (int)blockDim.x * kRowsInFlight) {
+    float4 lo[kRowsInFlight], hi[kRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) {
+      const int i = i0 + u * (int)blockDim.x;
+      lo[u] = i < rows ? pp4[(size_t)i * 2] : make_float4(0.f, 0.f, 0.f, 0.f);
+      hi[u] = i < rows ? pp4[(size_t)i * 2 + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) {
+      if (i0 + u * (int)blockDim.x >= rows) break;
+      acc[0] += (double)lo[u].x;
+      acc[1] += (double)lo[u].y;
+      acc[2] += (double)lo[u].z;
+      acc[3] += (double)lo[u].w;
+      acc[4] += (double)hi[u].x;
+      acc[5] += (double)hi[u].y;
+      if (loss_in_part) acc[6] += (double)hi[u].z;
+    }
+  }
+  if (!loss_in_part) {
+    const int nl = (HW + kLossThreads - 1) / kLossThreads;
+    for (int i = l; i < nl; i += blockDim.x) acc[6] += (double)loss_part[(size_t)v * part_stride + i];
+  }
+  const int w = l / 64;
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
     const double s = wave_sum_d(acc[k]);
-    if (threadIdx.x % 64 == 0) sh[k][w] = s;
+    if (l % 64 == 0) sh[k][w] = s;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (l >= 64) return;
   double g[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
   const double loss = (sh[6][0] + sh[6][1] + sh[6][2] + sh[6][3]) / (double)HW;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) ctrl->last_grad[v][k] = g[k];
-  const uint32_t it = ctrl->iter_v[v];
   float* pose_history = ctrl->pose_history;
-  float* loss_history = ctrl->loss_history;
   const int max_hist = ctrl->max_hist;
-  ctrl->loss[v] = loss;
-  if (loss_history && (int)it < max_hist) loss_history[(size_t)it * n_views + v] = (float)loss;
   const double b1 = adam.beta1, b2 = adam.beta2;
   // bias corrections 1 - beta^t from running powers (t = it + 1)
-  const double b1t = ctrl->adam_b1t[v] * b1, b2t = ctrl->adam_b2t[v] * b2;
-  ctrl->adam_b1t[v] = b1t;
-  ctrl->adam_b2t[v] = b2t;
+  const double b1t = b1t_old * b1, b2t = b2t_old * b2;
   const double c1 = 1.0 - b1t, c2 = 1.0 - b2t;
-  double tau[6];
-  for (int k = 0; k < 6; ++k) {
-    const double m = b1 * ctrl->adam_m[v][k] + (1.0 - b1) * g[k];
-    const double vv = b2 * ctrl->adam_v[v][k] + (1.0 - b2) * g[k] * g[k];
-    ctrl->adam_m[v][k] = m;
-    ctrl->adam_v[v][k] = vv;
-    tau[k] = -(double)adam.lr[k] * (m / c1) / (sqrt(vv / c2) + (double)adam.eps);
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) ctrl->last_grad[v][k] = g[k];
+    ctrl->loss[v] = loss;
+    float* loss_history = ctrl->loss_history;
+    if (loss_history && (int)it < max_hist) loss_history[(size_t)it * n_views + v] = (float)loss;
+    ctrl->adam_b1t[v] = b1t;
+    ctrl->adam_b2t[v] = b2t;
+    ctrl->iter_v[v] = it + 1;
   }
+  double tau_l = 0.0;
+  if (l < 6) {
+    double gl = g[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) gl = l == k ? g[k] : gl;
+    const double m = b1 * m_old + (1.0 - b1) * gl;
+    const double vv = b2 * v_old + (1.0 - b2) * gl * gl;
+    ctrl->adam_m[v][l] = m;
+    ctrl->adam_v[v][l] = vv;
+    double lr = (double)adam.lr[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) lr = l == k ? (double)adam.lr[k] : lr;
+    tau_l = -lr * (m / c1) / (sqrt(vv / c2) + (double)adam.eps);
+  }
+  double tau[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) tau[k] = __shfl(tau_l, k, 64);
   double Re[9], te[3];
   se3_exp(tau, Re, te);
-  double* T = ctrl->master_pose[v];
-  double Tn[12];
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 4; ++c) {
-      double s = Re[r * 3 + 0] * T[0 * 4 + c] + Re[r * 3 + 1] * T[1 * 4 + c] + Re[r * 3 + 2] * T[2 * 4 + c];
-      if (c == 3) s += te[r];
-      Tn[r * 4 + c] = s;
-    }
+  // entry (r, c) of the new pose from column c of the old one
+  const int r = l / 4, c = l % 4;
+  double col[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) col[q] = __shfl(T_old, q * 4 + c, 64);
+  if (l < 12) {
+    double s = Re[r * 3 + 0] * col[0] + Re[r * 3 + 1] * col[1] + Re[r * 3 + 2] * col[2];
+    if (c == 3) s += te[r];
+    ctrl->master_pose[v][l] = s;
+    pose_out[l] = (float)s;
+    if (pose_history && (int)it < max_hist) pose_history[((size_t)it * n_views + v) * 12 + l] = (float)s;
   }
-  for (int k = 0; k < 12; ++k) {
-    T[k] = Tn[k];
-    V.pose[k] = (float)Tn[k];
-    if (pose_history && (int)it < max_hist) pose_history[((size_t)it * n_views + v) * 12 + k] = (float)Tn[k];
-  }
-  ctrl->iter_v[v] = it + 1;
 }
 
 }  // namespace gs2d
