@@ -203,7 +203,12 @@ GS2D_API int gs2d_render(gs2d_ctx* ctx, const float* params, int64_t n, const gs
  * selects the pose-only mode, in which no per-surfel gradient is formed.
  * d_pose [6] receives dL/dtau for a left perturbation of the pose, the paper's
  * eq:derivatives (dL/dmu_c [I, -mu_c^x] plus dL/dR_c against [0, -R_c[:,k]^x]).
- * flags: GS2D_ACCUMULATE adds to d_params and d_pose instead of overwriting. */
+ * flags: GS2D_ACCUMULATE adds to d_params and d_pose instead of overwriting.
+ * With d_params the per-surfel sums are added with float atomics, so d_params and
+ * d_pose can differ in their last bits between runs; the pose-only mode sums in a
+ * fixed order and is bitwise repeatable.  Needs the GPU to hold 64 B per (view,
+ * surfel) item of accumulator rows (grown on demand; GS2D_ERR_CAPACITY when
+ * that would happen under stream capture). */
 GS2D_API int gs2d_render_backward(gs2d_ctx* ctx, const float* d_rgb, const float* d_depth,
                                   const float* d_normal, const float* d_alpha, float* d_params,
                                   float* d_pose, uint32_t generation, int32_t flags,
