@@ -287,7 +287,8 @@ def config1_bench(args):
     trgb, tdep, tnrm = tg.rgb.clone(), tg.depth.clone(), tg.normal.clone()
     P, pose = to_dev(s.params), to_dev(s.pose.reshape(12))
     # 12 tiles of 16 x 16: each blend is one tile's walk; the autotuner weighs smaller tiles
-    tuning = r.autotune(P, cam, pose)
+    # on the step's own backward (to all surfel parameters)
+    tuning = r.autotune(P, cam, pose, full_backward=True)
 
     def step():
         out = r.render_batch([(P, cam, pose)])[0]
@@ -354,7 +355,7 @@ def config3_bench(args):
     del Pgt
     P = to_dev(state)
     pose_t = [to_dev(p.reshape(12)) for p in poses]
-    tuning = r.autotune(P, cam_l, pose_t[4])
+    tuning = r.autotune(P, cam_l, pose_t[4], full_backward=True)
     views = [(P, cams[k], pose_t[k]) for k in range(8)]
 
     def step():

@@ -304,7 +304,7 @@ GS2D_API int gs2d_pose_tau_grad(gs2d_ctx* ctx, const float* tau, const float* d_
 /* Result of gs2d_autotune. */
 typedef struct gs2d_tuning {
   int32_t tile_w, tile_h, batch;
-  float ms;                  /* best mean fwd + pose-only bwd time (ms) */
+  float ms;                  /* best mean fwd + bwd time (ms), the backward as flags select */
   int32_t n_candidates;
   int32_t from_cache;        /* 1: the choice came from the context's cache */
 } gs2d_tuning;
@@ -312,10 +312,15 @@ typedef struct gs2d_tuning {
 /* Autotuner: time forward + pose-only backward of (params, n, camera, pose) for every
  * tile shape {8x8, 16x8, 16x16, 32x16} x LDS batch {32, 64, 128, 256} (`reps` timed
  * repetitions each after one warm-up), keep the fastest in the context (its later
- * renders use it) and cache it for this (width, height, power-of-two class of n).
- * The images do not depend on the choice.  Synchronises `stream`; not capturable. */
+ * renders use it) and cache it for this (width, height, power-of-two class of n,
+ * flags).  flags: GS2D_TUNE_FULL_BACKWARD times the backward to all surfel
+ * parameters instead (the mapping side's workload; it needs 60 B per surfel of
+ * device memory while it runs).  The images do not depend on the choice.
+ * Synchronises `stream`; not capturable. */
+#define GS2D_TUNE_FULL_BACKWARD 1
+
 GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera,
-                           const float* pose, int32_t reps, gs2d_tuning* out, hipStream_t stream);
+                           const float* pose, int32_t reps, int32_t flags, gs2d_tuning* out, hipStream_t stream);
 
 /* Counters of the last render; synchronises `stream`. */
 GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream);

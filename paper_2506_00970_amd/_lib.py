@@ -23,6 +23,7 @@ ERR_CAPACITY = -4
 ERR_STATE = -5
 ERR_UNSUPPORTED = -6
 ACCUMULATE = 1
+TUNE_FULL_BACKWARD = 1
 
 
 class Camera(ctypes.Structure):
@@ -135,7 +136,7 @@ _SIGS = {
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),
-    "gs2d_autotune": ([_P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, ctypes.c_int32,
+    "gs2d_autotune": ([_P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, ctypes.c_int32, ctypes.c_int32,
                        ctypes.POINTER(Tuning), _P], ctypes.c_int),
     "gs2d_pose_exp": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "gs2d_pose_tau_grad": ([_P, _P, _P, _P, _P], ctypes.c_int),

@@ -1047,9 +1047,11 @@ GS2D_API int gs2d_pose_tau_grad(gs2d_ctx* ctx, const float* tau, const float* d_
 }
 
 GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera,
-                           const float* pose, int32_t reps, gs2d_tuning* out, hipStream_t stream) {
-  if (!ctx || !out || !valid_camera(camera) || n <= 0 || !params || !pose || reps < 1 || reps > 1000)
+                           const float* pose, int32_t reps, int32_t flags, gs2d_tuning* out, hipStream_t stream) {
+  if (!ctx || !out || !valid_camera(camera) || n <= 0 || !params || !pose || reps < 1 || reps > 1000 ||
+      (flags & ~GS2D_TUNE_FULL_BACKWARD) != 0 || n > INT32_MAX)
     return GS2D_ERR_INVALID_ARG;
+  const bool full = (flags & GS2D_TUNE_FULL_BACKWARD) != 0;
   GS2D_TRY(set_device(ctx));
   bool capturing = false;
   if (stream_capturing(stream, &capturing) != 0 || capturing) return GS2D_ERR_INVALID_ARG;
@@ -1058,7 +1060,7 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
   while ((1ll << ncls) < n) ++ncls;
   for (int i = 0; i < ctx->n_tune; ++i) {
     const auto& e = ctx->tune[i];
-    if (e.w == camera->width && e.h == camera->height && e.ncls == ncls) {
+    if (e.w == camera->width && e.h == camera->height && e.ncls == ncls && e.flags == flags) {
       if (ctx->opt.tile_w != e.tw || ctx->opt.tile_h != e.th || ctx->opt.batch != e.batch) invalidate_graph(ctx);
       ctx->opt.tile_w = e.tw;
       ctx->opt.tile_h = e.th;
@@ -1070,6 +1072,14 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
   const int64_t HW = (int64_t)camera->width * camera->height;
   float* img = nullptr;
   GS2D_HIP(ctx, hipMalloc((void**)&img, (size_t)(8 * HW + 8) * sizeof(float)));
+  float* dpar = nullptr;  // the timed full backward's parameter gradient
+  if (full) {
+    const hipError_t e = hipMalloc((void**)&dpar, (size_t)15 * n * sizeof(float));
+    if (e != hipSuccess) {
+      (void)hipFree(img);
+      return fail_hip(ctx, e);
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -1095,14 +1105,22 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
       vs.v[0].g_depth = img + 3 * HW;
       vs.v[0].d_pose = img + 8 * HW;
       ctx->pair_fixed = false;
-      // one synchronising warm-up sizes the pair buffers for this tile shape
+      // one synchronising warm-up sizes the pair buffers for this tile shape (and,
+      // for the full backward, its accumulator rows)
       r = render_views(ctx, vs, stream, true);
       if (r != GS2D_OK) break;
+      gs2d_view_grad g{img, img + 3 * HW, nullptr, nullptr, dpar, img + 8 * HW};
+      if (full) {
+        r = backward_views(ctx, &g, 1, 0, stream);
+        if (r != GS2D_OK) break;
+      }
       ctx->pair_fixed = true;
       (void)hipEventRecord(e0, stream);
       for (int k = 0; k < reps && r == GS2D_OK; ++k) {
         r = render_views(ctx, vs, stream, false);
-        if (r == GS2D_OK) {
+        if (r == GS2D_OK && full) {
+          r = backward_views(ctx, &g, 1, 0, stream);
+        } else if (r == GS2D_OK) {
           launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, false, false,
                            nullptr, ctx->part, nullptr, stream);
           launch_reduce_pose_views(ctx->views, 1, ctx->part, 0, stream);
@@ -1129,6 +1147,7 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(stream);
   (void)hipFree(img);
+  if (dpar) (void)hipFree(dpar);
   ctx->pair_fixed = saved_fixed;
   ctx->opt.profile = saved.profile;
   ctx->opt.tile_w = bt;
@@ -1140,7 +1159,7 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
     ctx->opt = saved;
     return r;
   }
-  if (ctx->n_tune < 32) ctx->tune[ctx->n_tune++] = {camera->width, camera->height, ncls, bt, bh, bb, best};
+  if (ctx->n_tune < 32) ctx->tune[ctx->n_tune++] = {camera->width, camera->height, ncls, flags, bt, bh, bb, best};
   *out = gs2d_tuning{bt, bh, bb, best, 16, 0};
   return GS2D_OK;
 }

@@ -627,14 +627,16 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
     }
     __syncthreads();
     // chunks of 64 from the back; within a chunk the overlapping entries below the
-    // wave's last position, highest first, two per step
+    // wave's last position, highest first (two per step in the pose-only mode)
     for (int c1 = nb; c1 > 0; c1 -= 64) {
       const int c0 = max(0, c1 - 64);
       uint64_t m = overlap_mask(cull, c0, c1, lane, bx0, by0, a.filter, bstart, wlast);
       while (m != 0ull) {
         const int b1 = 63 - __builtin_clzll(m);
         m &= ~(1ull << b1);
-        const bool two = m != 0ull;
+        // the full mode takes one entry per step: its 16 terms per entry then fit
+        // 70-80 VGPRs (about 110-120 with two), which doubles the waves per SIMD
+        const bool two = POSE_ONLY && m != 0ull;
         const int b2 = two ? 63 - __builtin_clzll(m) : b1;
         if (two) m &= ~(1ull << b2);
         const int j1 = c0 + b1, j2 = c0 + b2;

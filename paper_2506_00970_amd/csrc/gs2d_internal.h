@@ -176,7 +176,7 @@ struct gs2d_ctx {
   long long prof_launches[gs2d::kNumFamilies] = {0};
 
   // autotuner cache: (width, height, log2 n class) -> (tile_w, tile_h, batch, ms)
-  struct TuneEntry { int w, h, ncls, tw, th, batch; float ms; };
+  struct TuneEntry { int w, h, ncls, flags, tw, th, batch; float ms; };
   TuneEntry tune[32];
   int n_tune = 0;
 

@@ -227,16 +227,20 @@ class Rasterizer:
         return d_params, d_pose
 
     # ----------------------------------------------------------------- autotune
-    def autotune(self, params: torch.Tensor, camera, pose: torch.Tensor, reps: int = 3) -> dict:
-        """Pick the fastest tile shape and LDS batch for this workload; later renders use it."""
+    def autotune(self, params: torch.Tensor, camera, pose: torch.Tensor, reps: int = 3,
+                 full_backward: bool = False) -> dict:
+        """Pick the fastest tile shape and LDS batch for this workload; later renders use it.
+        The timed backward is the pose-only one (tracking), or with ``full_backward`` the one
+        to all surfel parameters (mapping)."""
         cam = _camera(camera)
         n = int(params.shape[1])
         _check_tensor(params, "params", (15, n), self.device)
         pose = pose.reshape(12)
         _check_tensor(pose, "pose", (12,), self.device)
         t = _lib.Tuning()
+        flags = _lib.TUNE_FULL_BACKWARD if full_backward else 0
         _lib.check(self._lib.gs2d_autotune(self._ctx, _dev_ptr(params), n, ctypes.byref(cam), _dev_ptr(pose),
-                                           int(reps), ctypes.byref(t), self._stream()), self._ctx)
+                                           int(reps), flags, ctypes.byref(t), self._stream()), self._ctx)
         self._last = None
         return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
 

@@ -469,3 +469,11 @@ def test_gpu_autotune(gs):
     for k in a:
         np.testing.assert_array_equal(a[k], host(getattr(after, k)), err_msg=k)
     print("autotune", t)
+    # the mapping side's tuning (forward + backward to all parameters) is cached apart
+    f = r.autotune(P, ROOM_CAM, T, reps=2, full_backward=True)
+    assert f["from_cache"] == 0 and f["ms"] > t["ms"] and f["batch"] in (32, 64, 128, 256)
+    assert r.autotune(P, ROOM_CAM, T, full_backward=True)["from_cache"] == 1
+    after = r.render(P, ROOM_CAM, T)
+    for k in a:
+        np.testing.assert_array_equal(a[k], host(getattr(after, k)), err_msg=k)
+    print("autotune, full backward", f)
