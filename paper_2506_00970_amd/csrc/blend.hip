@@ -109,7 +109,8 @@ __device__ __forceinline__ int wave_max(int v) {
 
 // Per staged entry, what the waves' cull reads: the footprint box, the 3-sigma
 // ellipse (centre relative to the box corner, support matrix Sxx, Sxy) and
-// (Syy, low-pass disc centre relative to the box corner, 0).
+// (Syy, low-pass disc centre relative to the box corner, free word; the backward
+// keeps the entry's surfel id there).
 constexpr int kLdsRec = 6;  // record float4 kept per staged entry ([6] feeds the cull only)
 
 struct CullLds {
@@ -559,9 +560,10 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   extern __shared__ float4 srec[];
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
                      srec + (size_t)a.batch * (kLdsRec + 2)};
-  uint32_t* sid = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * (kLdsRec + 3));
-  // full mode: per staged entry the block's sums of its 16 terms (zero between batches)
-  float* sacc = reinterpret_cast<float*>(sid + a.batch);
+  // full mode: per staged entry the block's sums of its 16 terms (zero between
+  // batches); the entry's surfel id rides in the unused last word of its cull data,
+  // which keeps a 256-entry batch within a third of the CU's LDS
+  float* sacc = reinterpret_cast<float*>(srec + (size_t)a.batch * (kLdsRec + 3));
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
   // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
       const float4 v = a.rec[(size_t)id * kRecF4 + f];
       if (f < kLdsRec) srec[j * kLdsRec + f] = v;
       stage_cull(cull, j, f, v);
-      if (f == 0) sid[j] = id;
+      if (f == 0) cull.ell2[j].w = __uint_as_float(id);
     }
     __syncthreads();
     // chunks of 64 from the back; within a chunk the overlapping entries below the
@@ -665,7 +667,8 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
       for (int k = t; k < nb * 16; k += NT) {
         const float v = sacc[k];
         if (v != 0.f) {
-          __hip_atomic_fetch_add((gfloat*)(gacc + (size_t)sid[k >> 4] * 16 + (k & 15)), v, __ATOMIC_RELAXED,
+          const uint32_t id = __float_as_uint(cull.ell2[k >> 4].w);
+          __hip_atomic_fetch_add((gfloat*)(gacc + (size_t)id * 16 + (k & 15)), v, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
           sacc[k] = 0.f;
         }
@@ -908,9 +911,8 @@ void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long
 template <int TW, int TH, bool PO, bool HN, bool HO>
 void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last, float* gacc, float* part,
                  unsigned long long* work, hipStream_t s) {
-  // as the forward, and in full mode the per-entry term sums
-  const size_t lds =
-      (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + sizeof(uint32_t) + (PO ? 0 : 16 * sizeof(float)));
+  // staged records and their cull data, and in full mode the per-entry term sums
+  const size_t lds = (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + (PO ? 0 : 16 * sizeof(float)));
   if (work)
     blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
   else
