@@ -477,3 +477,11 @@ def test_gpu_autotune(gs):
     for k in a:
         np.testing.assert_array_equal(a[k], host(getattr(after, k)), err_msg=k)
     print("autotune, full backward", f)
+    # unknown flags are rejected before any work
+    import ctypes
+    from paper_2506_00970_amd import _lib
+    cam = _lib.Camera(ROOM_CAM.width, ROOM_CAM.height, ROOM_CAM.fx, ROOM_CAM.fy, ROOM_CAM.cx, ROOM_CAM.cy)
+    t_out = _lib.Tuning()
+    code = r._lib.gs2d_autotune(r._ctx, ctypes.c_void_p(P.data_ptr()), P.shape[1], ctypes.byref(cam),
+                                ctypes.c_void_p(T.data_ptr()), 2, 2, ctypes.byref(t_out), None)
+    assert code == -1
