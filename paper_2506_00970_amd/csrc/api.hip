@@ -301,8 +301,11 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
   bool capturing = false;
   if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
   const bool grow_ok = !capturing;
-  int64_t rows = vs.tiles;
-  for (int k = 0; k < nv; ++k) rows = (vs.v[k].n + 255) / 256 > rows ? (vs.v[k].n + 255) / 256 : rows;
+  // partial rows: one per tile, or per block of 256 surfels of every view (the
+  // parameter backward of views that share their surfels writes them side by side)
+  int64_t rows = 0;
+  for (int k = 0; k < nv; ++k) rows += (vs.v[k].n + 255) / 256;
+  if (rows < vs.tiles) rows = vs.tiles;
   if ((items > ctx->n_cap || vs.pixels > ctx->hw_cap || vs.tiles > ctx->tile_cap || rows > ctx->part_cap ||
        ctx->p_cap == 0) &&
       !grow_ok)
@@ -457,6 +460,35 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
       ProfScope ps(ctx, kBlendBwd, s);
       launch_blend_bwd(ba, ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, hn, ho, ctx->gacc,
                        ctx->part, work_ptr(ctx, s), s);
+    }
+    // views that share the surfel set and d_params (the mapping window): one pass
+    bool group = nv <= GS2D_MAX_VIEWS && vs.v[0].n > 0 && grads[0].d_params != nullptr;
+    for (int k = 1; k < nv && group; ++k)
+      group = vs.v[k].params == vs.v[0].params && vs.v[k].n == vs.v[0].n && grads[k].d_params == grads[0].d_params;
+    if (group && nv > 1) {
+      const ViewDesc& d0 = vs.v[0];
+      const int blocks = (d0.n + 255) / 256;
+      const float* poses[GS2D_MAX_VIEWS];
+      const uint32_t* counts[GS2D_MAX_VIEWS];
+      const float* gaccs[GS2D_MAX_VIEWS];
+      for (int k = 0; k < nv; ++k) {
+        poses[k] = ctx->saved_pose + 12 * k;
+        counts[k] = ctx->count + vs.v[k].item_base;
+        gaccs[k] = ctx->gacc + (size_t)16 * vs.v[k].item_base;
+      }
+      {
+        ProfScope ps(ctx, kPreBwd, s);
+        if (launch_preprocess_bwd_group(d0.params, d0.n, nv, poses, counts, gaccs, grads[0].d_params, acc, ctx->part,
+                                        s) != 0)
+          return GS2D_ERR_INVALID_ARG;
+      }
+      for (int k = 0; k < nv; ++k)
+        if (grads[k].d_pose) {
+          ProfScope ps(ctx, kReduce, s);
+          launch_reduce_pose(ctx->part, k * blocks, blocks, grads[k].d_pose, acc, s);
+        }
+      GS2D_HIP(ctx, hipGetLastError());
+      return GS2D_OK;
     }
     for (int k = 0; k < nv; ++k) {
       const ViewDesc& d = vs.v[k];

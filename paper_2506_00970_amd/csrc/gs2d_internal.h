@@ -203,6 +203,12 @@ void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStr
 // count: the items' tile counts (rows of items with none are not read)
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const uint32_t* count, const float* gacc,
                            float* d_params, int accumulate, float* part, hipStream_t s);
+// The same for n_views (1..32) views that share params, n and d_params, in one pass:
+// view g's pose terms go to partial rows [g * blocks, (g + 1) * blocks), blocks =
+// ceil(n / 256).  Returns -1 (and launches nothing) for an unsupported n_views.
+int launch_preprocess_bwd_group(const float* params, int n, int n_views, const float* const* poses,
+                                const uint32_t* const* counts, const float* const* gaccs, float* d_params,
+                                int accumulate, float* part, hipStream_t s);
 
 // sort.hip
 constexpr int kScanItems = 1024;   // keys per block of the radix passes

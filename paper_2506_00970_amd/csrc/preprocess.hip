@@ -218,6 +218,76 @@ __global__ __launch_bounds__(256) void clear_rows_kernel(const uint32_t* __restr
   if (q < items * 4 && count[q >> 2] != 0u) gacc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// One item's parameter gradient o[15] (world frame) and pose terms pr[6] from its
+// accumulator row g, for the view pose (3x4, world to camera).
+__device__ __forceinline__ void item_grad(const float* __restrict__ P, int n, int i, const float* __restrict__ pose,
+                                          const float* __restrict__ gacc_row, float o[15], float pr[6]) {
+  float R[9], t[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    R[r * 3 + 0] = pose[r * 4 + 0];
+    R[r * 3 + 1] = pose[r * 4 + 1];
+    R[r * 3 + 2] = pose[r * 4 + 2];
+    t[r] = pose[r * 4 + 3];
+  }
+  float mu[3], tu[3], tv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = P[(size_t)(0 + c) * n + i];
+    tu[c] = P[(size_t)(3 + c) * n + i];
+    tv[c] = P[(size_t)(6 + c) * n + i];
+  }
+  const float su = P[(size_t)9 * n + i], sv = P[(size_t)10 * n + i];
+  float mc[3], uc[3], vc[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    mc[r] = R[r * 3 + 0] * mu[0] + R[r * 3 + 1] * mu[1] + R[r * 3 + 2] * mu[2] + t[r];
+    uc[r] = R[r * 3 + 0] * tu[0] + R[r * 3 + 1] * tu[1] + R[r * 3 + 2] * tu[2];
+    vc[r] = R[r * 3 + 0] * tv[0] + R[r * 3 + 1] * tv[1] + R[r * 3 + 2] * tv[2];
+  }
+  const float4* g4 = reinterpret_cast<const float4*>(gacc_row);
+  const float4 A = g4[0], B = g4[1], C = g4[2], D = g4[3];
+  const float gmu[3] = {A.x, A.y, A.z};
+  const float ga[3] = {A.w, B.x, B.y};
+  const float gb[3] = {B.z, B.w, C.x};
+  const float gn[3] = {C.y, C.z, C.w};
+  const float grgb[3] = {D.x, D.y, D.z};
+  const float go = D.w;
+  float tmp[3], gtu[3], gtv[3];
+  cross3(vc, gn, tmp);
+  for (int c = 0; c < 3; ++c) gtu[c] = su * ga[c] + tmp[c];
+  cross3(gn, uc, tmp);
+  for (int c = 0; c < 3; ++c) gtv[c] = sv * gb[c] + tmp[c];
+  const float gsu = uc[0] * ga[0] + uc[1] * ga[1] + uc[2] * ga[2];
+  const float gsv = vc[0] * gb[0] + vc[1] * gb[1] + vc[2] * gb[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o[0 + c] = R[0 * 3 + c] * gmu[0] + R[1 * 3 + c] * gmu[1] + R[2 * 3 + c] * gmu[2];
+    o[3 + c] = R[0 * 3 + c] * gtu[0] + R[1 * 3 + c] * gtu[1] + R[2 * 3 + c] * gtu[2];
+    o[6 + c] = R[0 * 3 + c] * gtv[0] + R[1 * 3 + c] * gtv[1] + R[2 * 3 + c] * gtv[2];
+    o[12 + c] = grgb[c];
+  }
+  o[9] = gsu;
+  o[10] = gsv;
+  o[11] = go;
+  // eq:derivatives, left perturbation: [I, -mu_c^x] and [0, -R_c[:,k]^x]
+  float gcu[3], gcv[3], c1[3], c2[3], c3[3], c4[3];
+  for (int c = 0; c < 3; ++c) {
+    gcu[c] = su * ga[c];
+    gcv[c] = sv * gb[c];
+  }
+  const float nn[3] = {uc[1] * vc[2] - uc[2] * vc[1], uc[2] * vc[0] - uc[0] * vc[2],
+                       uc[0] * vc[1] - uc[1] * vc[0]};
+  cross3(mc, gmu, c1);
+  cross3(uc, gcu, c2);
+  cross3(vc, gcv, c3);
+  cross3(nn, gn, c4);
+  for (int c = 0; c < 3; ++c) {
+    pr[c] = gmu[c];
+    pr[3 + c] = c1[c] + c2[c] + c3[c] + c4[c];
+  }
+}
+
 // Per item the parameter gradient from its accumulator row, and the block sums of the
 // pose terms.  An item that touches no tile has a zero gradient and no row to read.
 __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
@@ -232,77 +302,14 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
     for (int k = 0; k < 15; ++k) d_params[(size_t)k * n + i] = 0.f;
   }
   if (hit) {
-    float R[9], t[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      R[r * 3 + 0] = pose[r * 4 + 0];
-      R[r * 3 + 1] = pose[r * 4 + 1];
-      R[r * 3 + 2] = pose[r * 4 + 2];
-      t[r] = pose[r * 4 + 3];
-    }
-    float mu[3], tu[3], tv[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      mu[c] = P[(size_t)(0 + c) * n + i];
-      tu[c] = P[(size_t)(3 + c) * n + i];
-      tv[c] = P[(size_t)(6 + c) * n + i];
-    }
-    const float su = P[(size_t)9 * n + i], sv = P[(size_t)10 * n + i];
-    float mc[3], uc[3], vc[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      mc[r] = R[r * 3 + 0] * mu[0] + R[r * 3 + 1] * mu[1] + R[r * 3 + 2] * mu[2] + t[r];
-      uc[r] = R[r * 3 + 0] * tu[0] + R[r * 3 + 1] * tu[1] + R[r * 3 + 2] * tu[2];
-      vc[r] = R[r * 3 + 0] * tv[0] + R[r * 3 + 1] * tv[1] + R[r * 3 + 2] * tv[2];
-    }
-    const float4* g4 = reinterpret_cast<const float4*>(gacc + (size_t)i * 16);
-    const float4 A = g4[0], B = g4[1], C = g4[2], D = g4[3];
-    const float gmu[3] = {A.x, A.y, A.z};
-    const float ga[3] = {A.w, B.x, B.y};
-    const float gb[3] = {B.z, B.w, C.x};
-    const float gn[3] = {C.y, C.z, C.w};
-    const float grgb[3] = {D.x, D.y, D.z};
-    const float go = D.w;
-    float tmp[3], gtu[3], gtv[3];
-    cross3(vc, gn, tmp);
-    for (int c = 0; c < 3; ++c) gtu[c] = su * ga[c] + tmp[c];
-    cross3(gn, uc, tmp);
-    for (int c = 0; c < 3; ++c) gtv[c] = sv * gb[c] + tmp[c];
-    const float gsu = uc[0] * ga[0] + uc[1] * ga[1] + uc[2] * ga[2];
-    const float gsv = vc[0] * gb[0] + vc[1] * gb[1] + vc[2] * gb[2];
-    float out[15];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      out[0 + c] = R[0 * 3 + c] * gmu[0] + R[1 * 3 + c] * gmu[1] + R[2 * 3 + c] * gmu[2];
-      out[3 + c] = R[0 * 3 + c] * gtu[0] + R[1 * 3 + c] * gtu[1] + R[2 * 3 + c] * gtu[2];
-      out[6 + c] = R[0 * 3 + c] * gtv[0] + R[1 * 3 + c] * gtv[1] + R[2 * 3 + c] * gtv[2];
-      out[12 + c] = grgb[c];
-    }
-    out[9] = gsu;
-    out[10] = gsv;
-    out[11] = go;
+    float o[15];
+    item_grad(P, n, i, pose, gacc + (size_t)i * 16, o, pr);
     if (d_params) {
 #pragma unroll
       for (int k = 0; k < 15; ++k) {
         float* dst = d_params + (size_t)k * n + i;
-        *dst = accumulate ? *dst + out[k] : out[k];
+        *dst = accumulate ? *dst + o[k] : o[k];
       }
-    }
-    // eq:derivatives, left perturbation: [I, -mu_c^x] and [0, -R_c[:,k]^x]
-    float gcu[3], gcv[3], c1[3], c2[3], c3[3], c4[3];
-    for (int c = 0; c < 3; ++c) {
-      gcu[c] = su * ga[c];
-      gcv[c] = sv * gb[c];
-    }
-    const float nn[3] = {uc[1] * vc[2] - uc[2] * vc[1], uc[2] * vc[0] - uc[0] * vc[2],
-                         uc[0] * vc[1] - uc[1] * vc[0]};
-    cross3(mc, gmu, c1);
-    cross3(uc, gcu, c2);
-    cross3(vc, gcv, c3);
-    cross3(nn, gn, c4);
-    for (int c = 0; c < 3; ++c) {
-      pr[c] = gmu[c];
-      pr[3 + c] = c1[c] + c2[c] + c3[c] + c4[c];
     }
   }
   // block reduction of the six pose terms (fixed order: deterministic)
@@ -321,6 +328,62 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
   if (threadIdx.x == 6 || threadIdx.x == 7) part[(size_t)blockIdx.x * 8 + threadIdx.x] = 0.0f;
 }
 
+
+// The parameter backward of up to kMaxGroup views that share one surfel set and one
+// d_params buffer, in one pass over the surfels: each thread adds its surfel's
+// gradients of the views in view order in registers and writes d_params once; the
+// pose terms of view g go to rows [g * gridDim.x, (g + 1) * gridDim.x) of `part`.
+constexpr int kMaxGroup = 32;
+struct BwdGroup {
+  int n_views;
+  const float* pose[kMaxGroup];
+  const uint32_t* count[kMaxGroup];
+  const float* gacc[kMaxGroup];
+};
+__global__ __launch_bounds__(256) void preprocess_bwd_group_kernel(const float* __restrict__ P, int n, BwdGroup grp,
+                                                                   float* __restrict__ d_params, int accumulate,
+                                                                   float* __restrict__ part) {
+  __shared__ float red[4][6];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the running sum starts from d_params when accumulating, so the additions happen in
+  // the order the one-view kernel makes them through memory
+  float sum[15];
+  const bool live = i < n && d_params != nullptr;
+  bool have = live && accumulate, any = false;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) sum[k] = have ? d_params[(size_t)k * n + i] : 0.f;
+  for (int g = 0; g < grp.n_views; ++g) {
+    float pr[6] = {0, 0, 0, 0, 0, 0};
+    if (i < n && grp.count[g][i] != 0u) {
+      float o[15];
+      item_grad(P, n, i, grp.pose[g], grp.gacc[g] + (size_t)i * 16, o, pr);
+#pragma unroll
+      for (int k = 0; k < 15; ++k) sum[k] = have ? sum[k] + o[k] : o[k];
+      have = true;
+      any = true;
+    }
+    // block sums of the pose terms, fixed order: each wave's lanes, then the waves
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float v = pr[k];
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+      if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      const int k = threadIdx.x;
+      part[((size_t)g * gridDim.x + blockIdx.x) * 8 + k] =
+          k < 6 ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0f;
+    }
+    __syncthreads();
+  }
+  if (live && (any || !accumulate)) {
+#pragma unroll
+    for (int k = 0; k < 15; ++k) d_params[(size_t)k * n + i] = sum[k];
+  }
+}
 }  // namespace
 
 void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s) {
@@ -349,6 +412,22 @@ void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStr
   if (items <= 0) return;
   const int64_t grid = (items * 4 + 255) / 256;
   clear_rows_kernel<<<(unsigned)grid, 256, 0, s>>>(count, reinterpret_cast<float4*>(gacc), items);
+}
+
+int launch_preprocess_bwd_group(const float* params, int n, int n_views, const float* const* poses,
+                                const uint32_t* const* counts, const float* const* gaccs, float* d_params,
+                                int accumulate, float* part, hipStream_t s) {
+  if (n_views < 1 || n_views > kMaxGroup) return -1;
+  BwdGroup grp;
+  grp.n_views = n_views;
+  for (int g = 0; g < n_views; ++g) {
+    grp.pose[g] = poses[g];
+    grp.count[g] = counts[g];
+    grp.gacc[g] = gaccs[g];
+  }
+  const int grid = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
+  preprocess_bwd_group_kernel<<<grid, 256, 0, s>>>(params, n, grp, d_params, accumulate, part);
+  return 0;
 }
 
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const uint32_t* count, const float* gacc,
