@@ -301,10 +301,10 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
   bool capturing = false;
   if (stream_capturing(s, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
   const bool grow_ok = !capturing;
-  // partial rows: one per tile, or per block of 256 surfels of every view (the
+  // partial rows: one per tile, or per wave of 256-surfel blocks of every view (the
   // parameter backward of views that share their surfels writes them side by side)
   int64_t rows = 0;
-  for (int k = 0; k < nv; ++k) rows += (vs.v[k].n + 255) / 256;
+  for (int k = 0; k < nv; ++k) rows += (int64_t)kGroupRowsPerBlock * ((vs.v[k].n + 255) / 256);
   if (rows < vs.tiles) rows = vs.tiles;
   if ((items > ctx->n_cap || vs.pixels > ctx->hw_cap || vs.tiles > ctx->tile_cap || rows > ctx->part_cap ||
        ctx->p_cap == 0) &&
@@ -467,7 +467,7 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
       group = vs.v[k].params == vs.v[0].params && vs.v[k].n == vs.v[0].n && grads[k].d_params == grads[0].d_params;
     if (group && nv > 1) {
       const ViewDesc& d0 = vs.v[0];
-      const int blocks = (d0.n + 255) / 256;
+      const int rows = kGroupRowsPerBlock * ((d0.n + 255) / 256);
       const float* poses[GS2D_MAX_VIEWS];
       const uint32_t* counts[GS2D_MAX_VIEWS];
       const float* gaccs[GS2D_MAX_VIEWS];
@@ -482,11 +482,12 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
                                         s) != 0)
           return GS2D_ERR_INVALID_ARG;
       }
-      for (int k = 0; k < nv; ++k)
-        if (grads[k].d_pose) {
-          ProfScope ps(ctx, kReduce, s);
-          launch_reduce_pose(ctx->part, k * blocks, blocks, grads[k].d_pose, acc, s);
-        }
+      float* d_poses[GS2D_MAX_VIEWS];
+      for (int k = 0; k < nv; ++k) d_poses[k] = grads[k].d_pose;
+      {
+        ProfScope ps(ctx, kReduce, s);
+        launch_reduce_pose_group(ctx->part, rows, nv, d_poses, acc, s);
+      }
       GS2D_HIP(ctx, hipGetLastError());
       return GS2D_OK;
     }

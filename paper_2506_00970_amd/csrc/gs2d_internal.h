@@ -204,8 +204,10 @@ void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStr
 void launch_preprocess_bwd(const float* params, int n, const float* pose, const uint32_t* count, const float* gacc,
                            float* d_params, int accumulate, float* part, hipStream_t s);
 // The same for n_views (1..32) views that share params, n and d_params, in one pass:
-// view g's pose terms go to partial rows [g * blocks, (g + 1) * blocks), blocks =
-// ceil(n / 256).  Returns -1 (and launches nothing) for an unsupported n_views.
+// view g's pose terms go to partial rows [g * rows, (g + 1) * rows), rows =
+// 4 ceil(n / 256) (one per wave).  Returns -1 (and launches nothing) for an
+// unsupported n_views.
+constexpr int kGroupRowsPerBlock = 4;  // partial rows per 256-surfel block of the group backward
 int launch_preprocess_bwd_group(const float* params, int n, int n_views, const float* const* poses,
                                 const uint32_t* const* counts, const float* const* gaccs, float* d_params,
                                 int accumulate, float* part, hipStream_t s);
@@ -317,6 +319,10 @@ inline void launch_tracking_loss(const ViewDesc* views, int n_views, int max_hw,
 void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, hipStream_t s);
 // d_pose = sum of rows [row0, row0 + rows) of `part` (one launch).
 void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, int accumulate, hipStream_t s);
+// d_pose[g] (for g < n_views, skipped when NULL) = the sum of partial rows
+// [g * rows, (g + 1) * rows), one workgroup per view.
+void launch_reduce_pose_group(const float* part, int rows, int n_views, float* const* d_pose, int accumulate,
+                              hipStream_t s);
 // Per view: d_pose (from the view table) = sum of the rows of the view's tiles.
 void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,
                               hipStream_t s);

@@ -120,6 +120,17 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_pose_kernel(const float
   reduce_pose_rows(part + (size_t)row0 * 8, rows, d_pose, accumulate);
 }
 
+struct PoseOuts {
+  float* d_pose[kMaxViews];
+};
+// one workgroup per view of a group: d_pose[g] = sum of rows [g * rows, (g + 1) * rows)
+__global__ __launch_bounds__(kReduceThreads) void reduce_pose_group_kernel(const float* __restrict__ part, int rows,
+                                                                           PoseOuts out, int accumulate) {
+  float* d_pose = out.d_pose[blockIdx.x];
+  if (!d_pose) return;
+  reduce_pose_rows(part + (size_t)blockIdx.x * rows * 8, rows, d_pose, accumulate);
+}
+
 // one workgroup per view: d_pose of view blockIdx.x = sum of the rows of its tiles
 __global__ __launch_bounds__(kReduceThreads) void reduce_pose_views_kernel(const ViewDesc* __restrict__ views,
                                                                            const float* __restrict__ part,
@@ -271,6 +282,14 @@ void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* los
 
 void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, int accumulate, hipStream_t s) {
   reduce_pose_kernel<<<1, kReduceThreads, 0, s>>>(part, row0, rows, d_pose, accumulate);
+}
+
+void launch_reduce_pose_group(const float* part, int rows, int n_views, float* const* d_pose, int accumulate,
+                              hipStream_t s) {
+  if (n_views < 1 || n_views > kMaxViews) return;
+  PoseOuts out;
+  for (int g = 0; g < kMaxViews; ++g) out.d_pose[g] = g < n_views ? d_pose[g] : nullptr;
+  reduce_pose_group_kernel<<<n_views, kReduceThreads, 0, s>>>(part, rows, out, accumulate);
 }
 
 void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,

@@ -331,8 +331,9 @@ __global__ __launch_bounds__(256) void preprocess_bwd_kernel(
 
 // The parameter backward of up to kMaxGroup views that share one surfel set and one
 // d_params buffer, in one pass over the surfels: each thread adds its surfel's
-// gradients of the views in view order in registers and writes d_params once; the
-// pose terms of view g go to rows [g * gridDim.x, (g + 1) * gridDim.x) of `part`.
+// gradients of the views in view order in registers and writes d_params once.  The
+// pose terms of view g are summed per wave (no barrier) into rows
+// [g * 4 * gridDim.x, (g + 1) * 4 * gridDim.x) of `part`, one per wave.
 constexpr int kMaxGroup = 32;
 struct BwdGroup {
   int n_views;
@@ -343,7 +344,6 @@ struct BwdGroup {
 __global__ __launch_bounds__(256) void preprocess_bwd_group_kernel(const float* __restrict__ P, int n, BwdGroup grp,
                                                                    float* __restrict__ d_params, int accumulate,
                                                                    float* __restrict__ part) {
-  __shared__ float red[4][6];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // the running sum starts from d_params when accumulating, so the additions happen in
@@ -363,21 +363,16 @@ __global__ __launch_bounds__(256) void preprocess_bwd_group_kernel(const float* 
       have = true;
       any = true;
     }
-    // block sums of the pose terms, fixed order: each wave's lanes, then the waves
+    // the wave's sums of the pose terms (fixed order), lane k < 6 writing term k
+    float mine = 0.f;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       float v = pr[k];
 #pragma unroll
       for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-      if (lane == 0) red[wave][k] = v;
+      mine = lane == k ? v : mine;
     }
-    __syncthreads();
-    if (threadIdx.x < 8) {
-      const int k = threadIdx.x;
-      part[((size_t)g * gridDim.x + blockIdx.x) * 8 + k] =
-          k < 6 ? ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k] : 0.0f;
-    }
-    __syncthreads();
+    if (lane < 8) part[(((size_t)g * gridDim.x + blockIdx.x) * kGroupRowsPerBlock + wave) * 8 + lane] = mine;
   }
   if (live && (any || !accumulate)) {
 #pragma unroll
