@@ -360,11 +360,11 @@ def config3_bench(args):
 
     def step():
         outs = r.render_batch(views)
-        grads = []
-        for k, o in enumerate(outs):
-            _, d_rgb, d_depth, _ = r.image_loss(cams[k], o.rgb, o.depth, o.normal, o.alpha, targets[k][0],
-                                                targets[k][1], None, w_rgb=1.0, w_depth=0.5, opacity_mask=True)
-            grads.append({"d_rgb": d_rgb, "d_depth": d_depth})
+        # every view's loss and image gradients in one launch (and one for the reductions)
+        _, g = r.image_loss_batch([{"camera": cams[k], "rgb": o.rgb, "depth": o.depth, "normal": o.normal,
+                                    "alpha": o.alpha, "tgt_rgb": targets[k][0], "tgt_depth": targets[k][1]}
+                                   for k, o in enumerate(outs)], w_rgb=1.0, w_depth=0.5, opacity_mask=True)
+        grads = [{"d_rgb": d_rgb, "d_depth": d_depth} for d_rgb, d_depth, _ in g]
         return r.backward_batch(outs[0].generation, grads, params_grad=True)
 
     st = torch.cuda.Stream()

@@ -262,6 +262,22 @@ GS2D_API int gs2d_image_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const flo
                              const float* tgt_normal, const gs2d_loss_weights* weights, float* loss, float* d_rgb,
                              float* d_depth, float* d_normal, hipStream_t stream);
 
+/* One view of gs2d_image_loss_batch: its camera and the images, targets and gradient
+ * outputs of gs2d_image_loss (same NULL rules). */
+typedef struct gs2d_loss_view {
+  gs2d_camera camera;
+  const float *rgb, *depth, *normal, *alpha;
+  const float *tgt_rgb, *tgt_depth, *tgt_normal;
+  float *d_rgb, *d_depth, *d_normal;
+} gs2d_loss_view;
+
+/* gs2d_image_loss of n_views (1..GS2D_MAX_VIEWS) views with one set of weights, in one
+ * launch for all views and one for their reductions: losses [n_views] (device)
+ * receives each view's loss; each view's gradients as gs2d_image_loss writes them.
+ * Results equal n_views calls of gs2d_image_loss, bit for bit. */
+GS2D_API int gs2d_image_loss_batch(gs2d_ctx* ctx, const gs2d_loss_view* views, int32_t n_views,
+                                   const gs2d_loss_weights* weights, float* losses, hipStream_t stream);
+
 /* Relocalisation error of Sec. "Loop Detection and Relocalization" (eq:tracking_error):
  * e_t = (1/HW) sum_p M_n M_o |depth - tgt_depth|, the depth term of the tracking loss
  * with its masks (M_n = [normal . ray > 0], M_o = [alpha > 0.95]), computed on the

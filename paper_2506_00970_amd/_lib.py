@@ -74,6 +74,11 @@ class LossWeights(ctypes.Structure):
                 ("normal_mask", ctypes.c_int32), ("opacity_mask", ctypes.c_int32)]
 
 
+class LossView(ctypes.Structure):
+    _fields_ = [("camera", Camera)] + [(k, ctypes.c_void_p) for k in (
+        "rgb", "depth", "normal", "alpha", "tgt_rgb", "tgt_depth", "tgt_normal", "d_rgb", "d_depth", "d_normal")]
+
+
 class AdamArgs(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("step", ctypes.c_int32),
@@ -133,6 +138,8 @@ _SIGS = {
     "gs2d_tracking_error": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "gs2d_image_loss": ([_P, ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(LossWeights), _P, _P,
                          _P, _P, _P], ctypes.c_int),
+    "gs2d_image_loss_batch": ([_P, ctypes.POINTER(LossView), ctypes.c_int32, ctypes.POINTER(LossWeights), _P, _P],
+                              ctypes.c_int),
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),

@@ -960,6 +960,61 @@ GS2D_API int gs2d_image_loss(gs2d_ctx* ctx, const gs2d_camera* camera, const flo
   return GS2D_OK;
 }
 
+GS2D_API int gs2d_image_loss_batch(gs2d_ctx* ctx, const gs2d_loss_view* views, int32_t n_views,
+                                   const gs2d_loss_weights* w, float* losses, hipStream_t stream) {
+  if (!ctx || !views || !w || !losses || n_views < 1 || n_views > GS2D_MAX_VIEWS) return GS2D_ERR_INVALID_ARG;
+  if (!std::isfinite(w->w_rgb) || !std::isfinite(w->w_depth) || !std::isfinite(w->w_normal))
+    return GS2D_ERR_INVALID_ARG;
+  int max_hw = 0;
+  for (int k = 0; k < n_views; ++k) {
+    const gs2d_loss_view& v = views[k];
+    if (!valid_camera(&v.camera) || !v.depth || !v.tgt_depth) return GS2D_ERR_INVALID_ARG;
+    if ((w->w_rgb != 0.f || v.d_rgb) && (!v.rgb || !v.tgt_rgb)) return GS2D_ERR_INVALID_ARG;
+    if ((w->w_normal != 0.f || v.d_normal) && (!v.normal || !v.tgt_normal)) return GS2D_ERR_INVALID_ARG;
+    if ((w->normal_mask && !v.normal) || (w->opacity_mask && !v.alpha)) return GS2D_ERR_INVALID_ARG;
+    const int hw = v.camera.width * v.camera.height;
+    if (hw > max_hw) max_hw = hw;
+  }
+  GS2D_TRY(set_device(ctx));
+  const int stride = loss_blocks(max_hw);
+  bool capturing = false;
+  if (stream_capturing(stream, &capturing) != 0) return GS2D_ERR_INVALID_ARG;
+  if ((int64_t)n_views * stride > ctx->lpart_cap && capturing) return GS2D_ERR_CAPACITY;
+  GS2D_TRY(ensure_lpart(ctx, (int64_t)n_views * stride));
+  ViewSet vs;
+  vs.n_views = n_views;
+  for (int k = 0; k < n_views; ++k) {
+    const gs2d_loss_view& v = views[k];
+    ViewDesc& d = vs.v[k];
+    std::memset(&d, 0, sizeof(d));
+    d.cam = camf(v.camera);
+    const bool colour = w->w_rgb != 0.f || v.d_rgb, normals = w->w_normal != 0.f || v.d_normal;
+    d.rgb = colour ? const_cast<float*>(v.rgb) : nullptr;
+    d.tgt_rgb = colour ? v.tgt_rgb : nullptr;
+    d.depth = const_cast<float*>(v.depth);
+    d.tgt_depth = v.tgt_depth;
+    d.normal = const_cast<float*>(v.normal);
+    d.tgt_normal = normals ? v.tgt_normal : nullptr;
+    d.alpha = const_cast<float*>(v.alpha);
+    d.g_rgb = v.d_rgb;
+    d.g_depth = v.d_depth;
+    d.g_normal = v.d_normal;
+  }
+  launch_upload_views(vs, ctx->views, stream);
+  {
+    ProfScope ps(ctx, kLoss, stream);
+    launch_image_loss(ctx->views, n_views, max_hw,
+                      LossW{w->w_rgb, w->w_depth, w->w_normal, w->normal_mask, w->opacity_mask}, ctx->lpart, stride,
+                      stream);
+  }
+  {
+    ProfScope ps(ctx, kReduce, stream);
+    launch_reduce_loss_views(ctx->views, n_views, ctx->lpart, stride, losses, stream);
+  }
+  GS2D_HIP(ctx, hipGetLastError());
+  return GS2D_OK;
+}
+
 GS2D_API int gs2d_tracking_error(gs2d_ctx* ctx, const gs2d_camera* camera, const float* depth, const float* normal,
                                  const float* alpha, const float* tgt_depth, float* error, hipStream_t stream) {
   if (!ctx || !valid_camera(camera) || !depth || !normal || !alpha || !tgt_depth || !error)

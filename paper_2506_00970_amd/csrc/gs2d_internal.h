@@ -317,6 +317,9 @@ inline void launch_tracking_loss(const ViewDesc* views, int n_views, int max_hw,
                     s);
 }
 void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, hipStream_t s);
+// losses[v] = (sum of view v's partials, rows [v * part_stride, ...)) / HW_v, one wave per view.
+void launch_reduce_loss_views(const ViewDesc* views, int n_views, const float* part, int part_stride, float* losses,
+                              hipStream_t s);
 // d_pose = sum of rows [row0, row0 + rows) of `part` (one launch).
 void launch_reduce_pose(const float* part, int row0, int rows, float* d_pose, int accumulate, hipStream_t s);
 // d_pose[g] (for g < n_views, skipped when NULL) = the sum of partial rows

@@ -86,6 +86,17 @@ __global__ void reduce_loss_kernel(const float* __restrict__ part, int n, float 
   if (threadIdx.x == 0) *loss = (float)s;
 }
 
+// one wave per view: losses[v] = (sum of view v's partials) / HW_v
+__global__ void reduce_loss_views_kernel(const ViewDesc* __restrict__ views, const float* __restrict__ part,
+                                         int part_stride, float* __restrict__ losses) {
+  const CamF cam = views[blockIdx.x].cam;
+  const int hw = cam.width * cam.height;
+  // the same scaling as the one-view reduction: a float reciprocal of HW
+  const double s = sum_parts(part + (size_t)blockIdx.x * part_stride, loss_blocks_dev(hw), 1, 0) *
+                   (double)(1.0f / (float)hw);
+  if (threadIdx.x == 0) losses[blockIdx.x] = (float)s;
+}
+
 constexpr int kReduceThreads = 256;
 
 // The six pose partials (the first six of each 8-float row) summed over `rows` rows in
@@ -274,6 +285,11 @@ void launch_image_loss(const ViewDesc* views, int n_views, int max_hw, LossW w, 
                        hipStream_t s) {
   const dim3 grid(loss_blocks(max_hw), n_views);
   image_loss_kernel<<<grid, kLossThreads, 0, s>>>(views, w, part, part_stride);
+}
+
+void launch_reduce_loss_views(const ViewDesc* views, int n_views, const float* part, int part_stride, float* losses,
+                              hipStream_t s) {
+  reduce_loss_views_kernel<<<n_views, 64, 0, s>>>(views, part, part_stride, losses);
 }
 
 void launch_reduce_loss(const float* part, int n_parts, float inv_hw, float* loss, hipStream_t s) {

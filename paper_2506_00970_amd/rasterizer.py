@@ -316,6 +316,41 @@ class Rasterizer:
                                              _dev_ptr(d_depth), _dev_ptr(d_normal), self._stream()), self._ctx)
         return loss, d_rgb, d_depth, d_normal
 
+    def image_loss_batch(self, views, w_rgb=1.0, w_depth=1.0, w_normal=0.0, normal_mask=False, opacity_mask=False,
+                         grads=True):
+        """image_loss of several views with one set of weights, in one launch for all views
+        (gs2d_image_loss_batch).  views: a list of dicts with camera, rgb, depth, normal,
+        alpha, tgt_rgb, tgt_depth, tgt_normal (None where not needed).  Returns (losses
+        [n] tensor, a list of (d_rgb, d_depth, d_normal) per view)."""
+        if not 1 <= len(views) <= 32:
+            raise ValueError("1..32 views")
+        colour, normals = w_rgb != 0.0, w_normal != 0.0
+        arr = (_lib.LossView * len(views))()
+        outs = []
+        for k, v in enumerate(views):
+            cam = _camera(v["camera"])
+            H, W = cam.height, cam.width
+            for nm, shp, need in (("rgb", (3, H, W), colour), ("tgt_rgb", (3, H, W), colour),
+                                  ("depth", (H, W), True), ("tgt_depth", (H, W), True),
+                                  ("normal", (3, H, W), normals or normal_mask), ("tgt_normal", (3, H, W), normals),
+                                  ("alpha", (H, W), opacity_mask)):
+                t = v.get(nm)
+                if need and t is None:
+                    raise ValueError(f"view {k}: {nm} is required")
+                _check_tensor(t, nm, shp, self.device)
+            mk = lambda c: torch.empty((c, H, W) if c > 1 else (H, W), dtype=torch.float32, device=self.device)
+            g = (mk(3) if grads and colour else None, mk(1) if grads else None, mk(3) if grads and normals else None)
+            outs.append(g)
+            arr[k].camera = cam
+            for nm in ("rgb", "depth", "normal", "alpha", "tgt_rgb", "tgt_depth", "tgt_normal"):
+                setattr(arr[k], nm, v[nm].data_ptr() if v.get(nm) is not None else None)
+            arr[k].d_rgb, arr[k].d_depth, arr[k].d_normal = (t.data_ptr() if t is not None else None for t in g)
+        losses = torch.empty(len(views), dtype=torch.float32, device=self.device)
+        w = _lib.LossWeights(float(w_rgb), float(w_depth), float(w_normal), int(normal_mask), int(opacity_mask))
+        _lib.check(self._lib.gs2d_image_loss_batch(self._ctx, arr, len(views), ctypes.byref(w), _dev_ptr(losses),
+                                                   self._stream()), self._ctx)
+        return losses, outs
+
     def tracking_error(self, camera, depth, normal, alpha, tgt_depth):
         """The relocalisation error e_t (eq:tracking_error), a device scalar tensor."""
         cam = _camera(camera)

@@ -63,7 +63,7 @@ def test_struct_layouts_match_header(tmp_path):
                "gs2d_tuning": _lib.Tuning, "gs2d_view": _lib.View, "gs2d_view_grad": _lib.ViewGrad,
                "gs2d_track_problem": _lib.TrackProblem, "gs2d_ws_adamw": _lib.WsAdamW,
                "gs2d_mapping_weights": _lib.MappingWeights, "gs2d_loss_weights": _lib.LossWeights,
-               "gs2d_adam_args": _lib.AdamArgs}
+               "gs2d_adam_args": _lib.AdamArgs, "gs2d_loss_view": _lib.LossView}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs2d.h"', '#include "gs2d_warm.h"',
              '#include "gs2d_map.h"', "int main(void) {"]
     for cname, py in structs.items():

@@ -73,3 +73,33 @@ def test_tracking_loss_and_error_are_instances(r, frames):
     c = r.image_loss(ROOM_CAM, None, g["depth"], g["normal"], g["alpha"], None, t["depth"], None, w_rgb=0.0,
                      w_depth=1.0, normal_mask=True, opacity_mask=True, grads=False)
     assert torch.equal(e, c[0])
+
+
+def test_image_loss_batch_equals_single_calls(r):
+    """gs2d_image_loss_batch over views of two sizes equals one gs2d_image_loss call per
+    view, bit for bit (loss and gradients), with and without the masks and the normal term."""
+    cams = [synth.Camera(64, 48, 60.0, 60.0, 32.0, 24.0), synth.Camera(70, 45, 55.0, 55.0, 35.0, 22.5)]
+    g = np.random.default_rng(3)
+    views = []
+    for k in range(5):
+        c = cams[k % 2]
+        H, W = c.height, c.width
+        nrm = g.normal(size=(3, H, W))
+        nrm /= np.linalg.norm(nrm, axis=0, keepdims=True)
+        v = {"camera": c, "rgb": g.random((3, H, W)), "depth": g.random((H, W)) + 1.0, "normal": nrm,
+             "alpha": g.random((H, W)), "tgt_rgb": g.random((3, H, W)), "tgt_depth": g.random((H, W)) + 1.0,
+             "tgt_normal": nrm[::-1].copy()}
+        views.append({kk: (dev(vv) if isinstance(vv, np.ndarray) else vv) for kk, vv in v.items()})
+    for kw in (dict(w_rgb=1.0, w_depth=0.5, opacity_mask=True), dict(w_rgb=1.0, w_depth=1.0, w_normal=1.0),
+               dict(w_rgb=1.0, w_depth=0.7, normal_mask=True, opacity_mask=True)):
+        losses, grads = r.image_loss_batch(views, **kw)
+        torch.cuda.synchronize()
+        for k, v in enumerate(views):
+            loss, d_rgb, d_depth, d_normal = r.image_loss(v["camera"], v["rgb"], v["depth"], v["normal"], v["alpha"],
+                                                          v["tgt_rgb"], v["tgt_depth"], v["tgt_normal"], **kw)
+            torch.cuda.synchronize()
+            assert host(losses)[k] == host(loss), (kw, k)
+            for a, b in zip(grads[k], (d_rgb, d_depth, d_normal)):
+                assert (a is None) == (b is None)
+                if a is not None:
+                    np.testing.assert_array_equal(host(a), host(b))
