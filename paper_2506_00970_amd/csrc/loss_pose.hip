@@ -105,11 +105,24 @@ constexpr int kReduceThreads = 256;
 __device__ void reduce_pose_rows(const float* __restrict__ part, int rows, float* __restrict__ d_pose,
                                  int accumulate) {
   __shared__ double sh[kReduceThreads / 64][6];
+  // up to 8 rows per thread in flight before the first add; each thread adds its rows
+  // in ascending order
+  constexpr int kRowsInFlight = 8;
   double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < rows; i += kReduceThreads) {
-    const float4 a = reinterpret_cast<const float4*>(part + (size_t)i * 8)[0];
-    const float2 b = reinterpret_cast<const float2*>(part + (size_t)i * 8)[2];
-    g[0] += a.x, g[1] += a.y, g[2] += a.z, g[3] += a.w, g[4] += b.x, g[5] += b.y;
+  for (int i0 = threadIdx.x; i0 < rows; i0 += kReduceThreads * kRowsInFlight) {
+    float4 a[kRowsInFlight];
+    float2 b[kRowsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) {
+      const int i = i0 + u * kReduceThreads;
+      a[u] = i < rows ? reinterpret_cast<const float4*>(part + (size_t)i * 8)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+      b[u] = i < rows ? reinterpret_cast<const float2*>(part + (size_t)i * 8)[2] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsInFlight; ++u) {
+      if (i0 + u * kReduceThreads >= rows) break;
+      g[0] += a[u].x, g[1] += a[u].y, g[2] += a[u].z, g[3] += a[u].w, g[4] += b[u].x, g[5] += b[u].y;
+    }
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) g[k] = wave_sum_d(g[k]);
