@@ -65,7 +65,7 @@ def _load():
         _lib = ctypes.CDLL(build())
         P = ctypes.c_void_p
         _lib.orc_render.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 8
-        _lib.orc_backward.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 10
+        _lib.orc_backward.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 14
         _lib.orc_preprocess.argtypes = [P, ctypes.c_int64, P, P, P] + [P] * 5
         _lib.orc_contribution.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_double, P, P]
         _lib.orc_depth_variants.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int, P, P, P]
@@ -122,13 +122,20 @@ def render(params, camera, pose, filter: bool = True, use_rect: bool = True, nth
 
 
 def backward(params, camera, pose, d_rgb=None, d_depth=None, d_normal=None, d_alpha=None,
-             filter: bool = True, use_rect: bool = True, nthreads=None, watch=None):
+             filter: bool = True, use_rect: bool = True, nthreads=None, watch=None, scale: bool = False,
+             scale_mask=None):
     """Reverse mode for given image gradients.
 
     Returns a dict: d_params [15,N] (world frame), d_screen [16,N]
     (dL/dM row-major, dL/dn, dL/drgb, dL/do), pose_paper [6] and pose_identity
     [6] (rho, phi of a left perturbation), and, when ``watch`` (bool [H,W]) is
     given, touched [N] (surfels evaluated at a watched pixel).
+
+    With ``scale``: d_scale [15,N] and pose_scale [6], the magnitude scale of each
+    result, a bound on the sum over (pixel, surfel) pairs of |the pair's term|
+    (each result is a sum of such terms; its floating-point rounding is
+    proportional to this scale).  With ``scale_mask`` (bool [H,W]) also
+    pose_scale_masked [6], the same over the pairs at the masked pixels only.
     """
     lib = _load()
     p, T = _prep(params, pose)
@@ -151,10 +158,20 @@ def backward(params, camera, pose, d_rgb=None, d_depth=None, d_normal=None, d_al
     w = None if watch is None else np.ascontiguousarray(np.asarray(watch, dtype=np.uint8))
     touched = None if watch is None else np.zeros(n, dtype=np.uint8)
     k = _consts(filter, use_rect)
+    d_scale = np.zeros((15, n)) if scale else None
+    ps = np.zeros(6) if scale else None
+    sm = None if scale_mask is None else np.ascontiguousarray(np.asarray(scale_mask, dtype=np.uint8))
+    assert sm is None or sm.shape == (H, W)
+    psm = np.zeros(6) if (scale and sm is not None) else None
     lib.orc_backward(_ptr(p), n, ctypes.byref(c), _ptr(T), ctypes.byref(k), _threads(nthreads),
                      _ptr(gr), _ptr(gd), _ptr(gn), _ptr(ga), _ptr(d_params), _ptr(d_screen), _ptr(pp),
-                     _ptr(pi), _ptr(w), _ptr(touched))
+                     _ptr(pi), _ptr(w), _ptr(touched), _ptr(d_scale), _ptr(ps), _ptr(sm), _ptr(psm))
     out = {"d_params": d_params, "d_screen": d_screen, "pose_paper": pp, "pose_identity": pi}
+    if scale:
+        out["d_scale"] = d_scale
+        out["pose_scale"] = ps
+        if psm is not None:
+            out["pose_scale_masked"] = psm
     if touched is not None:
         out["touched"] = touched.astype(bool)
     return out

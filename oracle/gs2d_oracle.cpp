@@ -41,6 +41,7 @@
 #include <cstdint>
 #include <cstring>
 #include <thread>
+#include <array>
 #include <vector>
 
 namespace {
@@ -322,6 +323,61 @@ void parallel_rows(int height, int nthreads, F f) {
 
 }  // namespace
 
+// O6, per surfel: the chain from the 16 summed screen terms A (dL/dM row-major,
+// dL/dn, dL/drgb, dL/do) to the world-frame parameter gradient (15) and to the
+// paper-form pose gradient of eq:derivatives (6).  Linear in A, so it also maps one
+// pair's terms to that pair's share of every result.
+void surfel_chain(const Surf& s, const Cam& cam, const double* R, const double* A, double outp[15],
+                  double pose[6], double gmu_w[3], double gtu_w[3], double gtv_w[3]) {
+  // dL/d[a b mu_c] = K^T dL/dM   (the paper's W^T dL/dT)
+  double gA[3][3];
+  for (int j = 0; j < 3; ++j) {
+    double m0 = A[0 * 3 + j], m1 = A[1 * 3 + j], m2 = A[2 * 3 + j];
+    gA[0][j] = cam.fx * m0;
+    gA[1][j] = cam.fy * m1;
+    gA[2][j] = cam.cx * m0 + cam.cy * m1 + m2;
+  }
+  double ga[3] = {gA[0][0], gA[1][0], gA[2][0]};
+  double gb[3] = {gA[0][1], gA[1][1], gA[2][1]};
+  double gmu[3] = {gA[0][2], gA[1][2], gA[2][2]};
+  const double* gn = A + 9;
+  // camera-frame tangent gradients: scale chain plus normal chain n = t_uc x t_vc
+  double tmp[3], gtuc[3], gtvc[3];
+  cross(s.tvc, gn, tmp);
+  for (int cc = 0; cc < 3; ++cc) gtuc[cc] = s.su * ga[cc] + tmp[cc];
+  cross(gn, s.tuc, tmp);
+  for (int cc = 0; cc < 3; ++cc) gtvc[cc] = s.sv * gb[cc] + tmp[cc];
+  double gsu = dot(s.tuc, ga), gsv = dot(s.tvc, gb);
+  // world frame: g_world = R^T g_cam
+  for (int cc = 0; cc < 3; ++cc) {
+    gmu_w[cc] = R[0 * 4 + cc] * gmu[0] + R[1 * 4 + cc] * gmu[1] + R[2 * 4 + cc] * gmu[2];
+    gtu_w[cc] = R[0 * 4 + cc] * gtuc[0] + R[1 * 4 + cc] * gtuc[1] + R[2 * 4 + cc] * gtuc[2];
+    gtv_w[cc] = R[0 * 4 + cc] * gtvc[0] + R[1 * 4 + cc] * gtvc[1] + R[2 * 4 + cc] * gtvc[2];
+  }
+  for (int cc = 0; cc < 3; ++cc) {
+    outp[0 + cc] = gmu_w[cc];
+    outp[3 + cc] = gtu_w[cc];
+    outp[6 + cc] = gtv_w[cc];
+    outp[12 + cc] = A[12 + cc];
+  }
+  outp[9] = gsu;
+  outp[10] = gsv;
+  outp[11] = A[15];
+  // Pose, paper form: dmu_c/dT = [I, -mu_c^x], dR_c/dT = [0, -R_c[:,k]^x]
+  // with the columns of dL/dR_c = [dL/dt_uc (from H_c), dL/dt_vc, dL/dt_nc].
+  double gcol0[3], gcol1[3];
+  for (int cc = 0; cc < 3; ++cc) { gcol0[cc] = s.su * ga[cc]; gcol1[cc] = s.sv * gb[cc]; }
+  double c1[3], c2[3], c3[3], c4[3];
+  cross(s.mu_c, gmu, c1);
+  cross(s.tuc, gcol0, c2);
+  cross(s.tvc, gcol1, c3);
+  cross(s.n, gn, c4);
+  for (int cc = 0; cc < 3; ++cc) {
+    pose[cc] = gmu[cc];
+    pose[3 + cc] = c1[cc] + c2[cc] + c3[cc] + c4[cc];
+  }
+}
+
 extern "C" {
 
 struct OrcCamera {
@@ -490,7 +546,8 @@ int orc_backward(const double* params, int64_t n, const OrcCamera* c, const doub
                  const OrcConsts* k, int nthreads, const double* g_rgb, const double* g_depth,
                  const double* g_normal, const double* g_alpha, double* d_params, double* d_screen,
                  double* d_pose_paper, double* d_pose_identity, const uint8_t* watch,
-                 uint8_t* touched) {
+                 uint8_t* touched, double* d_scale, double* pose_scale, const uint8_t* scale_mask,
+                 double* pose_scale_masked) {
   Cam cam; Consts kk;
   unpack(c, k, cam, kk);
   if (nthreads < 1) nthreads = 1;
@@ -499,6 +556,17 @@ int orc_backward(const double* params, int64_t n, const OrcCamera* c, const doub
   const int64_t HW = (int64_t)cam.width * cam.height;
   const int NA = 16;  // per surfel: g_M (9), g_n (3), g_rgb (3), g_o (1)
   std::vector<std::vector<double>> acc((size_t)nthreads, std::vector<double>((size_t)(NA * n), 0.0));
+  // magnitude scales: the sums over pairs of |a pair's share of each result| (its
+  // world-frame parameter gradient and paper-form pose gradient), over all pixels and
+  // over the pixels of scale_mask
+  const double* R = pose;  // rows of R are pose[0..2], pose[4..6], pose[8..10]
+  const bool want_scale = d_scale || pose_scale || pose_scale_masked;
+  std::vector<std::vector<double>> acc_abs((size_t)nthreads);
+  std::vector<std::array<double, 12>> acc_pose_abs((size_t)nthreads);
+  for (int t = 0; t < nthreads; ++t) {
+    if (d_scale) acc_abs[(size_t)t].assign((size_t)(15 * n), 0.0);
+    acc_pose_abs[(size_t)t].fill(0.0);
+  }
   std::vector<std::vector<uint8_t>> tch((size_t)nthreads);
   if (touched)
     for (auto& v : tch) v.assign((size_t)n, 0);
@@ -587,6 +655,19 @@ int orc_backward(const double* params, int64_t n, const OrcCamera* c, const doub
           for (int cc = 0; cc < 3; ++cc) A[r * 3 + cc] += gM[r][cc];
         double* dst = ac + (size_t)(NA * h.id);
         for (int j = 0; j < NA; ++j) dst[j] += A[(size_t)j];
+        if (want_scale) {
+          double op[15], ps[6], w0[3], w1[3], w2[3];
+          surfel_chain(s, cam, R, A.data(), op, ps, w0, w1, w2);
+          if (d_scale) {
+            double* da = acc_abs[(size_t)t].data() + (size_t)(15 * h.id);
+            for (int j = 0; j < 15; ++j) da[j] += std::fabs(op[j]);
+          }
+          const bool masked = scale_mask && scale_mask[p];
+          for (int j = 0; j < 6; ++j) {
+            acc_pose_abs[(size_t)t][(size_t)j] += std::fabs(ps[j]);
+            if (masked) acc_pose_abs[(size_t)t][(size_t)(6 + j)] += std::fabs(ps[j]);
+          }
+        }
       }
     }
   });
@@ -603,7 +684,6 @@ int orc_backward(const double* params, int64_t n, const OrcCamera* c, const doub
     }
   }
 
-  const double* R = pose;  // rows of R are pose[0..2], pose[4..6], pose[8..10]
   double pp[6] = {0, 0, 0, 0, 0, 0}, pi[6] = {0, 0, 0, 0, 0, 0};
   for (int64_t i = 0; i < n; ++i) {
     const Surf& s = sc.surf[(size_t)i];
@@ -613,57 +693,12 @@ int orc_backward(const double* params, int64_t n, const OrcCamera* c, const doub
     double outp[15];
     for (int j = 0; j < 15; ++j) outp[j] = 0.0;
     if (!s.culled) {
-      // dL/d[a b mu_c] = K^T dL/dM   (the paper's W^T dL/dT)
-      double gA[3][3];
-      for (int j = 0; j < 3; ++j) {
-        double m0 = A[0 * 3 + j], m1 = A[1 * 3 + j], m2 = A[2 * 3 + j];
-        gA[0][j] = cam.fx * m0;
-        gA[1][j] = cam.fy * m1;
-        gA[2][j] = cam.cx * m0 + cam.cy * m1 + m2;
-      }
-      double ga[3] = {gA[0][0], gA[1][0], gA[2][0]};
-      double gb[3] = {gA[0][1], gA[1][1], gA[2][1]};
-      double gmu[3] = {gA[0][2], gA[1][2], gA[2][2]};
-      const double* gn = A + 9;
-      // camera-frame tangent gradients: scale chain plus normal chain n = t_uc x t_vc
-      double tmp[3], gtuc[3], gtvc[3];
-      cross(s.tvc, gn, tmp);
-      for (int cc = 0; cc < 3; ++cc) gtuc[cc] = s.su * ga[cc] + tmp[cc];
-      cross(gn, s.tuc, tmp);
-      for (int cc = 0; cc < 3; ++cc) gtvc[cc] = s.sv * gb[cc] + tmp[cc];
-      double gsu = dot(s.tuc, ga), gsv = dot(s.tvc, gb);
-      // world frame: g_world = R^T g_cam
-      double gmu_w[3], gtu_w[3], gtv_w[3];
-      for (int cc = 0; cc < 3; ++cc) {
-        gmu_w[cc] = R[0 * 4 + cc] * gmu[0] + R[1 * 4 + cc] * gmu[1] + R[2 * 4 + cc] * gmu[2];
-        gtu_w[cc] = R[0 * 4 + cc] * gtuc[0] + R[1 * 4 + cc] * gtuc[1] + R[2 * 4 + cc] * gtuc[2];
-        gtv_w[cc] = R[0 * 4 + cc] * gtvc[0] + R[1 * 4 + cc] * gtvc[1] + R[2 * 4 + cc] * gtvc[2];
-      }
-      for (int cc = 0; cc < 3; ++cc) {
-        outp[0 + cc] = gmu_w[cc];
-        outp[3 + cc] = gtu_w[cc];
-        outp[6 + cc] = gtv_w[cc];
-        outp[12 + cc] = A[12 + cc];
-      }
-      outp[9] = gsu;
-      outp[10] = gsv;
-      outp[11] = A[15];
+      double ps[6], gmu_w[3], gtu_w[3], gtv_w[3];
+      surfel_chain(s, cam, R, A, outp, ps, gmu_w, gtu_w, gtv_w);
+      for (int j = 0; j < 6; ++j) pp[j] += ps[j];
 
-      // Pose, paper form: dmu_c/dT = [I, -mu_c^x], dR_c/dT = [0, -R_c[:,k]^x]
-      // with the columns of dL/dR_c = [dL/dt_uc (from H_c), dL/dt_vc, dL/dt_nc].
-      double gcol0[3], gcol1[3];
-      for (int cc = 0; cc < 3; ++cc) { gcol0[cc] = s.su * ga[cc]; gcol1[cc] = s.sv * gb[cc]; }
-      double c1[3], c2[3], c3[3], c4[3];
-      cross(s.mu_c, gmu, c1);
-      cross(s.tuc, gcol0, c2);
-      cross(s.tvc, gcol1, c3);
-      cross(s.n, gn, c4);
-      for (int cc = 0; cc < 3; ++cc) {
-        pp[cc] += gmu[cc];
-        pp[3 + cc] += c1[cc] + c2[cc] + c3[cc] + c4[cc];
-      }
       // Pose through the world-frame gradients (independent route)
-      double Rg[3], Rtu[3], Rtv[3];
+      double Rg[3], Rtu[3], Rtv[3], c1[3], c2[3], c3[3];
       for (int r = 0; r < 3; ++r) {
         Rg[r] = R[r * 4 + 0] * gmu_w[0] + R[r * 4 + 1] * gmu_w[1] + R[r * 4 + 2] * gmu_w[2];
         Rtu[r] = R[r * 4 + 0] * gtu_w[0] + R[r * 4 + 1] * gtu_w[1] + R[r * 4 + 2] * gtu_w[2];
@@ -679,6 +714,22 @@ int orc_backward(const double* params, int64_t n, const OrcCamera* c, const doub
     }
     if (d_params)
       for (int j = 0; j < 15; ++j) d_params[j * n + i] = outp[j];
+  }
+  if (d_scale) {
+    std::vector<double> sc15((size_t)(15 * n), 0.0);
+    for (int t = 0; t < nthreads; ++t)
+      for (size_t j = 0; j < sc15.size(); ++j) sc15[j] += acc_abs[(size_t)t][j];
+    for (int64_t i = 0; i < n; ++i)
+      for (int j = 0; j < 15; ++j) d_scale[j * n + i] = sc15[(size_t)(15 * i + j)];
+  }
+  if (pose_scale || pose_scale_masked) {
+    double tot_abs[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < nthreads; ++t)
+      for (int j = 0; j < 12; ++j) tot_abs[j] += acc_pose_abs[(size_t)t][(size_t)j];
+    for (int j = 0; j < 6; ++j) {
+      if (pose_scale) pose_scale[j] = tot_abs[j];
+      if (pose_scale_masked) pose_scale_masked[j] = tot_abs[6 + j];
+    }
   }
   if (d_pose_paper)
     for (int j = 0; j < 6; ++j) d_pose_paper[j] = pp[j];
