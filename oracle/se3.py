@@ -17,14 +17,31 @@ def hat(w):
     return np.array([[0.0, -w[2], w[1]], [w[2], 0.0, -w[0]], [-w[1], w[0], 0.0]])
 
 
+def _coef_b(th):
+    """(1 - cos th)/th^2, written as 2 sin^2(th/2)/th^2 (no cancellation near 0)."""
+    if th == 0.0:
+        return 0.5
+    s = np.sin(0.5 * th)
+    return 2.0 * s * s / (th * th)
+
+
+def _coef_c(th):
+    """(th - sin th)/th^3; its Taylor series 1/6 - th^2/120 + th^4/5040 below 1e-2 rad,
+    where the difference th - sin th would lose digits (the next term, th^6/362880, is
+    below 3e-18 there)."""
+    if th < 1e-2:
+        t2 = th * th
+        return 1.0 / 6.0 - t2 / 120.0 + t2 * t2 / 5040.0
+    return (th - np.sin(th)) / th ** 3
+
+
 def so3_exp(phi):
-    """Rodrigues' formula; second-order series below 1e-8 rad."""
+    """Rodrigues' formula R = I + sin(th)/th K + (1 - cos th)/th^2 K^2."""
     phi = np.asarray(phi, dtype=np.float64)
     th = np.linalg.norm(phi)
     K = hat(phi)
-    if th < 1e-8:
-        return np.eye(3) + K + 0.5 * K @ K
-    return np.eye(3) + np.sin(th) / th * K + (1.0 - np.cos(th)) / th ** 2 * K @ K
+    a = 1.0 if th == 0.0 else np.sin(th) / th
+    return np.eye(3) + a * K + _coef_b(th) * K @ K
 
 
 def so3_left_jacobian(phi):
@@ -32,16 +49,16 @@ def so3_left_jacobian(phi):
     phi = np.asarray(phi, dtype=np.float64)
     th = np.linalg.norm(phi)
     K = hat(phi)
-    if th < 1e-6:
-        return np.eye(3) + 0.5 * K + K @ K / 6.0
-    return np.eye(3) + (1.0 - np.cos(th)) / th ** 2 * K + (th - np.sin(th)) / th ** 3 * K @ K
+    return np.eye(3) + _coef_b(th) * K + _coef_c(th) * K @ K
 
 
 def so3_log(R):
+    """The rotation vector of R: angle atan2(|v|/2, (tr R - 1)/2) with v the
+    antisymmetric part (|v| = 2 sin th), which keeps its digits at small angles."""
     R = np.asarray(R, dtype=np.float64)
     c = np.clip((np.trace(R) - 1.0) / 2.0, -1.0, 1.0)
-    th = np.arccos(c)
     v = np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    th = np.arctan2(0.5 * np.linalg.norm(v), c)
     if th < 1e-8:
         return 0.5 * v
     if np.pi - th < 1e-6:
