@@ -175,6 +175,8 @@ typedef struct gs2d_track_args {
   int32_t use_graph;         /* 1: capture one iteration into a HIP graph and replay it */
   float* pose_history;       /* [n_iters][12] pose after each step, or NULL */
   float* loss_history;       /* [n_iters] loss before each step, or NULL */
+  double* grad_history;      /* [n_iters][6] pose gradient (rho, phi) each step consumed, FP64
+                                as the step uses it, or NULL */
 } gs2d_track_args;
 
 /* Fill *opt with the defaults listed above. */
@@ -301,7 +303,8 @@ GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* args, hipStream_t 
  * each one's tracking loss, runs one batched pose-only backward and one AdamW + Exp
  * step per problem.  `common` supplies lambda_d, use_masks, n_iters, the optimizer
  * constants and use_graph (its params/n/camera/pose/target fields are ignored);
- * its pose_history is [n_iters][n_problems][12] and loss_history [n_iters][n_problems].
+ * its pose_history is [n_iters][n_problems][12], loss_history [n_iters][n_problems] and
+ * grad_history [n_iters][n_problems][6].
  * Same graph caching, synchronisation and restart rules as gs2d_track. */
 GS2D_API int gs2d_track_batch(gs2d_ctx* ctx, const gs2d_track_problem* problems, int32_t n_problems,
                               const gs2d_track_args* common, hipStream_t stream);
@@ -325,14 +328,17 @@ typedef struct gs2d_tuning {
   int32_t from_cache;        /* 1: the choice came from the context's cache */
 } gs2d_tuning;
 
-/* Autotuner: time forward + pose-only backward of (params, n, camera, pose) for every
- * tile shape {8x8, 16x8, 16x16, 32x16} x LDS batch {32, 64, 128, 256} (`reps` timed
- * repetitions each after one warm-up), keep the fastest in the context (its later
- * renders use it) and cache it for this (width, height, power-of-two class of n,
- * flags).  flags: GS2D_TUNE_FULL_BACKWARD times the backward to all surfel
- * parameters instead (the mapping side's workload; it needs 60 B per surfel of
- * device memory while it runs).  The images do not depend on the choice.
- * Synchronises `stream`; not capturable. */
+/* Autotuner: for every tile shape {8x8, 16x8, 16x16, 32x16} x LDS batch {32, 64, 128,
+ * 256}, time `reps` repetitions (after one warm-up) of the tracking iteration that
+ * gs2d_track runs on (params, n, camera, pose): the sorts, the fused walk (forward
+ * blend, tracking loss and pose-only backward) and the pose step, against the render
+ * at `pose` as target, on a copy of the pose (the caller's pose is only read).  Keep
+ * the fastest in the context (its later renders and tracking calls use it) and cache
+ * it for this (width, height, power-of-two class of n, flags).  flags:
+ * GS2D_TUNE_FULL_BACKWARD times the forward render and the backward to all surfel
+ * parameters instead (the mapping side's workload; it needs 60 B per surfel of device
+ * memory while it runs).  The images do not depend on the choice.  Synchronises
+ * `stream`; not capturable. */
 #define GS2D_TUNE_FULL_BACKWARD 1
 
 GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera,

@@ -108,7 +108,8 @@ class TrackArgs(ctypes.Structure):
                 ("lambda_d", ctypes.c_float), ("use_masks", ctypes.c_int32), ("n_iters", ctypes.c_int32),
                 ("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("use_graph", ctypes.c_int32),
-                ("pose_history", ctypes.c_void_p), ("loss_history", ctypes.c_void_p)]
+                ("pose_history", ctypes.c_void_p), ("loss_history", ctypes.c_void_p),
+                ("grad_history", ctypes.c_void_p)]
 
 
 class Gs2dError(RuntimeError):

@@ -701,7 +701,8 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
     }
     ctx->pair_fixed = true;
     launch_upload_views(vs, ctx->views, s);
-    launch_track_init(ctx->views, np, ctx->ctrl, a->pose_history, a->loss_history, a->n_iters, s);
+    launch_track_init(ctx->views, np, ctx->ctrl, a->pose_history, a->loss_history, a->grad_history, a->n_iters,
+                      s);
     int r = GS2D_OK;
     if (a->use_graph && a->n_iters > 0) {
       if (!reuse) {
@@ -1158,8 +1159,11 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
     }
   }
   const int64_t HW = (int64_t)camera->width * camera->height;
+  // images (also the tracking targets and image gradients of the timed passes), the
+  // timed backward's pose gradient, and a copy of the pose for the timed pose steps
   float* img = nullptr;
-  GS2D_HIP(ctx, hipMalloc((void**)&img, (size_t)(8 * HW + 8) * sizeof(float)));
+  GS2D_HIP(ctx, hipMalloc((void**)&img, (size_t)(8 * HW + 24) * sizeof(float)));
+  float* pose_copy = img + 8 * HW + 8;
   float* dpar = nullptr;  // the timed full backward's parameter gradient
   if (full) {
     const hipError_t e = hipMalloc((void**)&dpar, (size_t)15 * n * sizeof(float));
@@ -1179,7 +1183,17 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
   float best = 1e30f;
   int bt = saved.tile_w, bh = saved.tile_h, bb = saved.batch;
   int r = GS2D_OK;
-  gs2d_view v{params, n, *camera, pose, img, img + 3 * HW, img + 4 * HW, img + 7 * HW};
+  // pose-only mode: the timed work is the tracking iteration gs2d_track runs (sorts,
+  // the fused walk and the pose step), on a copy of the pose with zero learning rates
+  gs2d_track_args ta;
+  std::memset(&ta, 0, sizeof(ta));
+  ta.lambda_d = 1.0f;
+  ta.use_masks = 1;
+  ta.beta1 = 0.9f;
+  ta.beta2 = 0.999f;
+  ta.eps = 1e-8f;
+  GS2D_HIP(ctx, hipMemcpyAsync(pose_copy, pose, 12 * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  gs2d_view v{params, n, *camera, full ? pose : pose_copy, img, img + 3 * HW, img + 4 * HW, img + 7 * HW};
   for (int ti = 0; ti < 4 && r == GS2D_OK; ++ti)
     for (int bi = 0; bi < 4 && r == GS2D_OK; ++bi) {
       ctx->opt.tile_w = tiles[ti][0];
@@ -1188,10 +1202,13 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
       ViewSet vs;
       r = build_views(ctx, &v, 1, vs);
       if (r != GS2D_OK) break;
-      // the image buffer doubles as the image gradient of the timed backward
+      // the image buffer doubles as the image gradient of the timed backward, and as
+      // the tracking target of the timed walk
       vs.v[0].g_rgb = img;
       vs.v[0].g_depth = img + 3 * HW;
       vs.v[0].d_pose = img + 8 * HW;
+      vs.v[0].tgt_rgb = img;
+      vs.v[0].tgt_depth = img + 3 * HW;
       ctx->pair_fixed = false;
       // one synchronising warm-up sizes the pair buffers for this tile shape (and,
       // for the full backward, its accumulator rows)
@@ -1200,18 +1217,25 @@ GS2D_API int gs2d_autotune(gs2d_ctx* ctx, const float* params, int64_t n, const 
       gs2d_view_grad g{img, img + 3 * HW, nullptr, nullptr, dpar, img + 8 * HW};
       if (full) {
         r = backward_views(ctx, &g, 1, 0, stream);
-        if (r != GS2D_OK) break;
+      } else {
+        // the tracking loop's headroom for moving poses, and its state
+        const int64_t npairs = ctx->host_ctrl->n_pairs;
+        r = ensure_pairs(ctx, npairs + npairs / 2 + 1024);
+        if (r == GS2D_OK) {
+          launch_upload_views(vs, ctx->views, stream);
+          launch_track_init(ctx->views, 1, ctx->ctrl, nullptr, nullptr, nullptr, 0, stream);
+          r = track_iteration(ctx, vs, &ta, stream);
+        }
       }
+      if (r != GS2D_OK) break;
       ctx->pair_fixed = true;
       (void)hipEventRecord(e0, stream);
       for (int k = 0; k < reps && r == GS2D_OK; ++k) {
-        r = render_views(ctx, vs, stream, false);
-        if (r == GS2D_OK && full) {
-          r = backward_views(ctx, &g, 1, 0, stream);
-        } else if (r == GS2D_OK) {
-          launch_blend_bwd(blend_args(ctx), ctx->opt.tile_w, ctx->opt.tile_h, ctx->t_final, ctx->last, false, false,
-                           nullptr, ctx->part, nullptr, stream);
-          launch_reduce_pose_views(ctx->views, 1, ctx->part, 0, stream);
+        if (full) {
+          r = render_views(ctx, vs, stream, false);
+          if (r == GS2D_OK) r = backward_views(ctx, &g, 1, 0, stream);
+        } else {
+          r = track_iteration(ctx, vs, &ta, stream);
         }
       }
       (void)hipEventRecord(e1, stream);

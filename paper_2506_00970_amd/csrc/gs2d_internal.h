@@ -76,6 +76,7 @@ struct Ctrl {            // device-resident counters and tracking state
   uint32_t iter;         // unused (kept for layout); see iter_v
   float* pose_history;   // set per tracking call, read by the pose step
   float* loss_history;
+  double* grad_history;  // [max_hist][n_views][6] or null
   int32_t max_hist;
   int32_t n_views;
   unsigned long long work[4];  // profile counters: fwd evaluated, fwd covering, bwd evaluated, bwd covering
@@ -332,7 +333,7 @@ void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* p
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
-                       int max_hist, hipStream_t s);
+                       double* grad_history, int max_hist, hipStream_t s);
 // One AdamW + Exp step per view: pose partials are the rows of each view's tiles,
 // loss partials part[v * part_stride + block].
 // loss_in_part: each view's loss is the sum of its tiles' pose_part[tile * 8 + 6]

@@ -166,7 +166,8 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_pose_views_kernel(const
 }
 
 __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_views, Ctrl* __restrict__ ctrl,
-                                  float* pose_history, float* loss_history, int max_hist) {
+                                  float* pose_history, float* loss_history, double* grad_history,
+                                  int max_hist) {
   const int t = threadIdx.x;
   for (int k = t; k < n_views * 12; k += blockDim.x)
     ctrl->master_pose[k / 12][k % 12] = (double)views[k / 12].pose[k % 12];
@@ -184,6 +185,7 @@ __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_view
     ctrl->iter = 0;
     ctrl->pose_history = pose_history;
     ctrl->loss_history = loss_history;
+    ctrl->grad_history = grad_history;
     ctrl->max_hist = max_hist;
     ctrl->n_views = n_views;
   }
@@ -327,8 +329,8 @@ void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* p
 }
 
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
-                       int max_hist, hipStream_t s) {
-  track_init_kernel<<<1, 256, 0, s>>>(views, n_views, ctrl, pose_history, loss_history, max_hist);
+                       double* grad_history, int max_hist, hipStream_t s) {
+  track_init_kernel<<<1, 256, 0, s>>>(views, n_views, ctrl, pose_history, loss_history, grad_history, max_hist);
 }
 
 void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, bool loss_in_part,

@@ -130,6 +130,10 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
     ctrl->loss[v] = loss;
     float* loss_history = ctrl->loss_history;
     if (loss_history && (int)it < max_hist) loss_history[(size_t)it * n_views + v] = (float)loss;
+    double* grad_history = ctrl->grad_history;
+    if (grad_history && (int)it < max_hist)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) grad_history[((size_t)it * n_views + v) * 6 + k] = g[k];
     ctrl->adam_b1t[v] = b1t;
     ctrl->adam_b2t[v] = b2t;
     ctrl->iter_v[v] = it + 1;

@@ -369,8 +369,9 @@ class Rasterizer:
     # ----------------------------------------------------------------- tracking
     def track(self, params, camera, pose, tgt_rgb, tgt_depth, n_iters: int, lr=TRACK_LR,
               lambda_d: float = 1.0, use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8,
-              weight_decay: float = 0.0, use_graph: bool = True, history: bool = True):
-        """Run ``n_iters`` tracking iterations in place on ``pose`` [12]; returns (pose, pose_hist, loss_hist)."""
+              weight_decay: float = 0.0, use_graph: bool = True, history: bool = True, grads: bool = False):
+        """Run ``n_iters`` tracking iterations in place on ``pose`` [12]; returns (pose, pose_hist, loss_hist),
+        and with ``grads`` also the FP64 pose gradient each step consumed, [n_iters, 6]."""
         cam = _camera(camera)
         H, W = cam.height, cam.width
         n = int(params.shape[1])
@@ -380,6 +381,7 @@ class Rasterizer:
         _check_tensor(tgt_depth, "tgt_depth", (H, W), self.device)
         ph = torch.zeros((max(n_iters, 1), 12), dtype=torch.float32, device=self.device) if history else None
         lh = torch.zeros((max(n_iters, 1),), dtype=torch.float32, device=self.device) if history else None
+        gh = torch.zeros((max(n_iters, 1), 6), dtype=torch.float64, device=self.device) if grads else None
         a = _lib.TrackArgs()
         a.params = params.data_ptr()
         a.n = n
@@ -398,8 +400,9 @@ class Rasterizer:
         a.use_graph = 1 if use_graph else 0
         a.pose_history = ph.data_ptr() if ph is not None else None
         a.loss_history = lh.data_ptr() if lh is not None else None
+        a.grad_history = gh.data_ptr() if gh is not None else None
         _lib.check(self._lib.gs2d_track(self._ctx, ctypes.byref(a), self._stream()), self._ctx)
-        return pose, ph, lh
+        return (pose, ph, lh, gh) if grads else (pose, ph, lh)
 
     def track_batch(self, problems, n_iters: int, lr=TRACK_LR, lambda_d: float = 1.0,
                     use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8, weight_decay: float = 0.0,

@@ -44,8 +44,29 @@ def window():
     return room, cams, poses, grads
 
 
-def test_mapping_window_against_oracle(pkg, window):
+@pytest.fixture(scope="module")
+def window_oracle(window):
+    """The oracle's side of the window: each view's render, pose gradient with its
+    magnitude scale and the scale of its near-decision pixels, and the surfel gradient
+    summed over the 8 views."""
     room, cams, poses, grads = window
+    out = {"total": None, "touched": np.zeros(room.n, dtype=bool), "views": []}
+    for k in range(8):
+        ref = oracle.render(room.params, cams[k], poses[k])
+        near = ref["gmargin"] < 1e-5
+        ob = oracle.backward(room.params, cams[k], poses[k], d_rgb=grads[k]["d_rgb"].astype(np.float64),
+                             d_depth=grads[k]["d_depth"].astype(np.float64), watch=near, scale=True,
+                             scale_mask=near)
+        out["total"] = ob["d_params"] if out["total"] is None else out["total"] + ob["d_params"]
+        out["touched"] |= ob["touched"].astype(bool)
+        out["views"].append({"pose": ob["pose_paper"], "pose_scale": ob["pose_scale"],
+                             "flip": ob["pose_scale_masked"], "ref": ref if k in (0, 4) else None})
+    return out
+
+
+def test_mapping_window_against_oracle(pkg, window, window_oracle):
+    room, cams, poses, grads = window
+    wo = window_oracle
     r = pkg.Rasterizer()
     P = dev(room.params)
     views = [(P, cams[k], dev(poses[k].reshape(12))) for k in range(8)]
@@ -57,23 +78,17 @@ def test_mapping_window_against_oracle(pkg, window):
     print("mapping window counts", c)
     assert c["overflow"] == 0 and c["n_tiles"] == 4 * 1200 + 4 * 75 * 43
     d_params = host(res[0][0])
-    total = np.zeros_like(d_params, dtype=np.float64)
-    touched = np.zeros(room.n, dtype=bool)
     for k in range(8):
-        ref = oracle.render(room.params, cams[k], poses[k])
-        ob = oracle.backward(room.params, cams[k], poses[k], d_rgb=grads[k]["d_rgb"].astype(np.float64),
-                             d_depth=grads[k]["d_depth"].astype(np.float64), watch=ref["gmargin"] < 1e-5)
-        total += ob["d_params"]
-        touched |= ob["touched"].astype(bool)
-        # pixels near a decision change a few pair terms of the summed pose gradient
-        check_pose(host(res[k][1]), ob["pose_paper"], rel=1e-3, floor=1e-4)
-        if k in (0, 4):
+        v = wo["views"][k]
+        print("view", k, "pose", check_pose(host(res[k][1]), v["pose"], scale=v["pose_scale"], flip=v["flip"]))
+        if v["ref"] is not None:
             img = {n: host(getattr(outs[k], n)) for n in ("rgb", "depth", "normal", "alpha")}
-            print("view", k, check_images(img, ref, ref["fmargin"]))
-    print("surfel grads", check_grads(d_params, total, skip=touched), "skipped", int(touched.sum()))
+            print("view", k, check_images(img, v["ref"], v["ref"]["fmargin"]))
+    print("surfel grads", check_grads(d_params, wo["total"], skip=wo["touched"]), "skipped",
+          int(wo["touched"].sum()))
 
 
-def test_mapping_window_graph_replays(pkg, window):
+def test_mapping_window_graph_replays(pkg, window, window_oracle):
     """The batched forward + full backward captured into one graph; every replay, with
     unrelated eager work and synchronisations between replays, equals the eager pass
     (images bit for bit; gradients, which add float atomics, to the gradient bar)."""
@@ -102,8 +117,11 @@ def test_mapping_window_graph_replays(pkg, window):
         torch.cuda.synchronize()
         for k in range(8):
             np.testing.assert_array_equal(host(g_outs[k].rgb), ref_img[k], err_msg=f"replay {rep} view {k}")
-            check_pose(host(g_res[k][1]), ref_pose[k].astype(np.float64))
-        check_grads(host(g_res[0][0]), ref_d.astype(np.float64), rel=1e-3)
+            # both sides round: twice the oracle's magnitude scale
+            check_pose(host(g_res[k][1]), ref_pose[k].astype(np.float64),
+                       scale=2 * window_oracle["views"][k]["pose_scale"])
+        # each within the bar of the oracle's gradient: within twice the bar of each other
+        check_grads(host(g_res[0][0]), ref_d.astype(np.float64), rel=2e-3, floor=2e-6)
         other.render(dev(small.params), small.camera, dev(small.pose.reshape(12)))
         torch.cuda.synchronize()
 

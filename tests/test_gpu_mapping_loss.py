@@ -162,8 +162,9 @@ def test_mapping_gradient_end_to_end(ml):
     torch.cuda.synchronize()
     ref = oracle.render(s.params, cam, s.pose)
     oml_out = oml.mapping_loss(ref["rgb"], ref["depth"], ref["normal"], tgt["rgb"], tgt["depth"], cam)
+    near = ref["gmargin"] < 1e-5
     og = oracle.backward(s.params, cam, s.pose, d_rgb=oml_out["d_rgb"], d_depth=oml_out["d_depth"],
-                         d_normal=oml_out["d_normal"], watch=ref["gmargin"] < 1e-5)
+                         d_normal=oml_out["d_normal"], watch=near, scale=True, scale_mask=near)
     rep = check_grads(host(dp), og["d_params"], skip=og["touched"])
     print("mapping grads", rep, "skipped surfels", int(og["touched"].sum()))
-    check_pose(host(dpose), og["pose_paper"])
+    print("pose", check_pose(host(dpose), og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"]))

@@ -13,7 +13,8 @@ import torch
 import oracle
 import synth
 from oracle import loss as oloss
-from tests.gpu_common import ROOM_CAM, check_grads, check_images, check_pose, dev, host, room_scene
+from tests.gpu_common import (ROOM_CAM, check_grads, check_images, check_pose, dev, flip_scale, host, room_scene,
+                              tracking_ambiguous)
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +96,13 @@ def _random_image_grads(H, W, seed, normal=True, alpha=True):
     return out
 
 
+def _oracle_grads(params, cam, pose, grads, ref, filter=True):
+    """The oracle's gradients for given image gradients, with the magnitude scales of
+    every entry and of the pose, and the pose scale of the pixels near a decision."""
+    near = ref["gmargin"] < 1e-5
+    return oracle.backward(params, cam, pose, **grads, watch=near, scale=True, scale_mask=near, filter=filter)
+
+
 def _gpu_backward(r, gen, grads, params_grad=True):
     d = {k: (dev(v) if v is not None else None) for k, v in grads.items()}
     dp, dpose = r.backward(gen, d["d_rgb"], d["d_depth"], d["d_normal"], d["d_alpha"], params_grad=params_grad)
@@ -111,14 +119,14 @@ def test_gpu_backward_parity_random(gs, seed):
     ref = oracle.render(s.params, s.camera, s.pose)
     grads = _random_image_grads(48, 64, seed)
     dp, dpose = _gpu_backward(r, out.generation, grads)
-    og = oracle.backward(s.params, s.camera, s.pose, **grads, watch=ref["gmargin"] < 1e-5)
+    og = _oracle_grads(s.params, s.camera, s.pose, grads, ref)
     rep = check_grads(dp, og["d_params"], skip=og["touched"])
     print("grads", seed, rep, "skipped surfels", int(og["touched"].sum()))
-    check_pose(dpose, og["pose_paper"])
+    print("pose", check_pose(dpose, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"]))
     # the pose-only mode gives the same pose gradient without per-surfel terms
     out2, _ = _render(r, s.params, s.camera, s.pose)
     _, dpose2 = _gpu_backward(r, out2.generation, grads, params_grad=False)
-    check_pose(dpose2, og["pose_paper"])
+    check_pose(dpose2, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"])
 
 
 _BWD_REF = {}
@@ -133,14 +141,14 @@ def test_gpu_backward_parity_tiles_batches(gs, tile, batch):
     grads = _random_image_grads(48, 64, 0)
     if not _BWD_REF:
         ref = oracle.render(s.params, s.camera, s.pose)
-        _BWD_REF.update(oracle.backward(s.params, s.camera, s.pose, **grads, watch=ref["gmargin"] < 1e-5))
+        _BWD_REF.update(_oracle_grads(s.params, s.camera, s.pose, grads, ref))
     og = _BWD_REF
     r = gs.Rasterizer(tile=tile, batch=batch)
     out, _ = _render(r, s.params, s.camera, s.pose)
     dp, dpose = _gpu_backward(r, out.generation, grads)
     rep = check_grads(dp, og["d_params"], skip=og["touched"])
     print("grads", tile, batch, rep)
-    check_pose(dpose, og["pose_paper"])
+    check_pose(dpose, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"])
 
 
 def test_gpu_backward_frame_loss(gs):
@@ -156,9 +164,9 @@ def test_gpu_backward_frame_loss(gs):
     grads = {"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": d_normal, "d_alpha": None}
     out, _ = _render(r, s.params, s.camera, s.pose)
     dp, dpose = _gpu_backward(r, out.generation, grads)
-    og = oracle.backward(s.params, s.camera, s.pose, **grads, watch=ref["gmargin"] < 1e-5)
-    check_grads(dp, og["d_params"], skip=og["touched"])
-    check_pose(dpose, og["pose_paper"])
+    og = _oracle_grads(s.params, s.camera, s.pose, grads, ref)
+    print(check_grads(dp, og["d_params"], skip=og["touched"]))
+    check_pose(dpose, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"])
 
 
 def test_gpu_backward_parity_room_pose(gs):
@@ -174,14 +182,12 @@ def test_gpu_backward_parity_room_pose(gs):
     grads = {"d_rgb": d_rgb, "d_depth": d_depth, "d_normal": None, "d_alpha": None}
     out, _ = _render(r, room.params, ROOM_CAM, start)
     _, dpose = _gpu_backward(r, out.generation, grads, params_grad=False)
-    og = oracle.backward(room.params, ROOM_CAM, start, **grads)
-    # pixels near a decision change a few pair terms; the summed pose gradient stays within 1e-3
-    check_pose(dpose, og["pose_paper"], rel=1e-3, floor=1e-4)
+    og = _oracle_grads(room.params, ROOM_CAM, start, grads, ref)
+    print("pose-only", check_pose(dpose, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"]))
     out2, _ = _render(r, room.params, ROOM_CAM, start)
     dp, dpose_full = _gpu_backward(r, out2.generation, grads, params_grad=True)
-    check_pose(dpose_full, og["pose_paper"], rel=1e-3, floor=1e-4)
-    og2 = oracle.backward(room.params, ROOM_CAM, start, **grads, watch=ref["gmargin"] < 1e-5)
-    rep = check_grads(dp, og2["d_params"], skip=og2["touched"])
+    print("full", check_pose(dpose_full, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"]))
+    rep = check_grads(dp, og["d_params"], skip=og["touched"])
     print("room grads", rep, "loss", L)
 
 
@@ -282,53 +288,106 @@ def test_gpu_long_tile_lists(gs):
     memory: 3000 surfels stacked over one tile, in shuffled depth, with repeated depths
     (ties keep the surfel order), render as the oracle does and order as defined.  Their
     pairs also outgrow the default pair capacity, so the render grows it."""
-    s = synth.stacked_surfels(opacity=0.02)
-    base = s.params[:, :1]
-    n = 3000
-    g = np.random.default_rng(11)
-    P = np.repeat(base, n, axis=1).copy()
-    z = g.choice(np.linspace(1.0, 3.0, 1000), n)  # about three surfels per depth
-    P[2] = z
-    P[12] = g.uniform(0, 1, n)
-    cam = s.camera
+    P, cam, pose = _long_list_scene()
     r = gs.Rasterizer(keep_unsorted=True)
-    out, img = _render(r, P.astype(np.float32), cam, s.pose)
+    out, img = _render(r, P, cam, pose)
     c = r.counts()
     # more pairs than the default capacity: the render grew the pair buffers and ran again
-    assert c["overflow"] == 0 and c["n_pairs"] > 4 * n
+    assert c["overflow"] == 0 and c["n_pairs"] > 4 * P.shape[1]
     rng = r.debug("ranges").reshape(-1, 2)
     assert (rng[:, 1] - rng[:, 0]).max() > 2048
     keys, ids = r.debug("tile_keys"), r.debug("tile_ids")
     ek, ei = _expected_order(r.debug("unsorted_keys"), r.debug("unsorted_ids"), r.debug("depth_keys"))
     np.testing.assert_array_equal(keys, ek)
     np.testing.assert_array_equal(ids, ei)
-    ref = oracle.render(P.astype(np.float32), cam, s.pose)
-    # 3000 coincident footprints put many pixels near a cutoff decision of some pair
-    print("long lists", c, check_images(img, ref, ref["fmargin"], max_excluded=1e-2))
+    ref = oracle.render(P, cam, pose)
+    print("long lists", c, check_images(img, ref, ref["fmargin"]))
 
 
-def test_gpu_track_gradient_matches_oracle(gs):
+_TRACK_REF = {}
+
+
+def _track_reference(scene: str, filt: bool):
+    """A tracking problem and the oracle's side of its first iteration: the tracking
+    loss (eq:tracking_loss, both masks, lambda_d = 1) at the start pose against the
+    oracle's render at the true pose, its pose gradient (eq:derivatives, paper form),
+    the gradient's magnitude scale, and the pose scale of the pixels where the two
+    sides may decide differently (tracking_ambiguous)."""
+    key = (scene, filt)
+    if key in _TRACK_REF:
+        return _TRACK_REF[key]
+    if scene == "room":
+        room, pose = room_scene(300_000, seed=0, cam_seed=0)
+        params, cam = room.params, ROOM_CAM
+        start = synth.perturb_pose(pose, 0.05, 3.0, seed=1)
+    else:
+        params, cam, pose = _long_list_scene()
+        start = synth.perturb_pose(pose, 0.01, 0.5, seed=2)
+    ref = oracle.render(params, cam, start, filter=filt)
+    tgt = oracle.render(params, cam, pose, filter=filt)
+    L, d_rgb, d_depth, m = oloss.tracking_loss(ref["rgb"], ref["depth"], ref["normal"], ref["alpha"], tgt["rgb"],
+                                               tgt["depth"], cam)
+    og = oracle.backward(params, cam, start, d_rgb=d_rgb, d_depth=d_depth, filter=filt, scale=True)
+    amb = tracking_ambiguous(ref, tgt, cam, ref["gmargin"], tgt["fmargin"])
+    flip = flip_scale(params, cam, start, amb, filter=filt)
+    # the loss: rendering noise on every pixel (twice the parity bar: frame and
+    # target), plus the whole unmasked loss of pixels whose mask may flip
+    l_px = np.abs(ref["rgb"] - tgt["rgb"]).sum(axis=0) + np.abs(ref["depth"] - tgt["depth"])
+    noise = 3 * 2e-4 + 2e-4 * np.maximum(np.abs(tgt["depth"]), 1e-3)
+    l_tol = (noise.sum() + (l_px * amb).sum()) / (cam.width * cam.height)
+    out = {"params": params, "cam": cam, "pose": pose, "start": start, "L": L, "og": og, "flip": flip,
+           "l_tol": l_tol, "amb_frac": float(amb.mean())}
+    _TRACK_REF[key] = out
+    return out
+
+
+def _long_list_scene():
+    """3000 surfels stacked over the centre of a 64 x 48 image, at 50 distinct depths
+    (60 surfels per depth: ties keep surfel order), with opacity 0.02 so that about 450
+    of them composite: one 16 x 16 tile list holds 3000 entries."""
+    s = synth.stacked_surfels(opacity=0.02)
+    base = s.params[:, :1]
+    n = 3000
+    g = np.random.default_rng(11)
+    P = np.repeat(base, n, axis=1).copy()
+    P[2] = g.choice(np.linspace(1.0037, 2.9963, 50), n)
+    P[12] = g.uniform(0, 1, n)
+    P[13] = g.uniform(0, 1, n)
+    return P.astype(np.float32), s.camera, s.pose
+
+
+@pytest.mark.parametrize("tile,batch,filt,scene", [
+    ((16, 16), 128, True, "room"), ((16, 16), 32, True, "room"), ((16, 16), 256, True, "room"),
+    ((8, 8), 64, True, "room"), ((16, 8), 128, True, "room"), ((32, 16), 256, True, "room"),
+    ((32, 16), 32, True, "room"), ((16, 16), 128, False, "room"), ((8, 8), 32, False, "room"),
+    ((16, 16), 128, True, "long"), ((32, 16), 64, True, "long")])
+def test_gpu_track_gradient_matches_oracle(gs, tile, batch, filt, scene):
     """The tracking loop's fused walk (forward blend, tracking loss and pose gradient in
-    one pass) against the oracle's pose gradient of the tracking loss at the start pose.
-    Each side forms the loss from its own render and target, so only pixels whose
-    residual is within rendering noise of zero can differ in sign."""
-    room, pose = room_scene(300_000, seed=0, cam_seed=0)
-    start = synth.perturb_pose(pose, 0.05, 3.0, seed=1)
-    r = gs.Rasterizer()
-    P = dev(room.params)
-    t = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    one pass) against the oracle's loss and pose gradient at the start pose, for every
+    tile shape, LDS batches other than the default, the low-pass filter off, and a tile
+    list of 3000 entries (ordered through global memory).  Each side forms the loss
+    from its own render and target; the gradient bar is the method's (1e-3 relative,
+    1e-6 of the larger of rho and phi), plus float32 rounding of the entries' magnitude
+    scale and twice the scale of the pixels whose discrete decisions may differ."""
+    ref = _track_reference(scene, filt)
+    cam = ref["cam"]
+    r = gs.Rasterizer(tile=tile, batch=batch, filter=filt)
+    P = dev(ref["params"])
+    t = r.render(P, cam, dev(ref["pose"].reshape(12)))
     trgb, tdep = t.rgb.clone(), t.depth.clone()
-    ref = oracle.render(room.params, ROOM_CAM, start)
-    tgt = oracle.render(room.params, ROOM_CAM, pose)
-    L, d_rgb, d_depth, _ = oloss.tracking_loss(ref["rgb"], ref["depth"], ref["normal"], ref["alpha"], tgt["rgb"],
-                                               tgt["depth"], ROOM_CAM)
-    og = oracle.backward(room.params, ROOM_CAM, start, d_rgb=d_rgb, d_depth=d_depth)
+    if scene == "long":
+        rng = r.debug("ranges").reshape(-1, 2)
+        assert (rng[:, 1] - rng[:, 0]).max() > 2048
     for graph in (False, True):
-        p = dev(start.reshape(12))
-        r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=1, use_graph=graph)
-        g = r.debug("track_grad").reshape(-1, 6)[0]
-        print("fused tracking gradient", g, "oracle", og["pose_paper"])
-        check_pose(g, og["pose_paper"], rel=1e-3, floor=1e-4)
+        p = dev(ref["start"].reshape(12))
+        _, _, lh, gh = r.track(P, cam, p, trgb, tdep, n_iters=1, use_graph=graph, grads=True)
+        torch.cuda.synchronize()
+        g = host(gh)[0]
+        np.testing.assert_array_equal(g, r.debug("track_grad").reshape(-1, 6)[0])
+        rep = check_pose(g, ref["og"]["pose_paper"], scale=ref["og"]["pose_scale"], flip=ref["flip"])
+        assert abs(float(lh[0]) - ref["L"]) <= ref["l_tol"], (float(lh[0]), ref["L"], ref["l_tol"])
+        print(scene, tile, batch, filt, graph, "pose", rep, "loss", float(lh[0]), ref["L"],
+              "ambiguous", ref["amb_frac"])
 
 
 @pytest.mark.parametrize("tile,batch", [((8, 8), 64), ((16, 8), 128), ((32, 16), 32), ((16, 16), 256)])
@@ -485,3 +544,46 @@ def test_gpu_autotune(gs):
     code = r._lib.gs2d_autotune(r._ctx, ctypes.c_void_p(P.data_ptr()), P.shape[1], ctypes.byref(cam),
                                 ctypes.c_void_p(T.data_ptr()), 2, 2, ctypes.byref(t_out), None)
     assert code == -1
+
+
+def test_gpu_tuned_track_matches_oracle(gs):
+    """The pose-only autotuner times the tracking iteration gs2d_track runs (sorts,
+    fused walk, pose step); a tracking call on the tuned context still gives the
+    oracle's loss and pose gradient at the start pose."""
+    ref = _track_reference("room", True)
+    cam = ref["cam"]
+    r = gs.Rasterizer()
+    P = dev(ref["params"])
+    t = r.render(P, cam, dev(ref["pose"].reshape(12)))
+    trgb, tdep = t.rgb.clone(), t.depth.clone()
+    start = dev(ref["start"].reshape(12))
+    tune = r.autotune(P, cam, start, reps=3)
+    # the caller's pose is only read
+    np.testing.assert_array_equal(host(start), ref["start"].reshape(12).astype(np.float32))
+    p = start.clone()
+    _, _, lh, gh = r.track(P, cam, p, trgb, tdep, n_iters=1, grads=True)
+    torch.cuda.synchronize()
+    rep = check_pose(host(gh)[0], ref["og"]["pose_paper"], scale=ref["og"]["pose_scale"], flip=ref["flip"])
+    assert abs(float(lh[0]) - ref["L"]) <= ref["l_tol"]
+    print("tuned", tune, rep)
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_gpu_filter_off_render_and_backward(gs, seed):
+    """Option filter = 0 (no low-pass branch: a pair is included by the 3-sigma
+    footprint u^2 + v^2 <= 9 alone) on 2,000 random surfels, many of them below a
+    pixel: the four images and the gradients to all parameters and the pose against
+    the oracle run with the filter off."""
+    s = synth.random_surfels(2000, seed=seed)
+    r = gs.Rasterizer(filter=False)
+    out, img = _render(r, s.params, s.camera, s.pose)
+    ref = oracle.render(s.params, s.camera, s.pose, filter=False)
+    rep = check_images(img, ref, ref["fmargin"])
+    # the filter changes the images of this scene: the test exercises the option
+    with_filter = oracle.render(s.params, s.camera, s.pose)
+    assert np.abs(with_filter["alpha"] - ref["alpha"]).max() > 1e-2
+    grads = _random_image_grads(48, 64, seed)
+    dp, dpose = _gpu_backward(r, out.generation, grads)
+    og = _oracle_grads(s.params, s.camera, s.pose, grads, ref, filter=False)
+    print("filter off", rep, check_grads(dp, og["d_params"], skip=og["touched"]),
+          check_pose(dpose, og["pose_paper"], scale=og["pose_scale"], flip=og["pose_scale_masked"]))

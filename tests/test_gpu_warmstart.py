@@ -196,38 +196,47 @@ def test_warm_start_choice(wsmod):
 def held_out(wsmod):
     """Plain and warm-started tracking (100 iterations) on held-out rooms 0-19 with the
     tracking workload's 5 cm / 3 deg start, using the committed weights (trained on
-    rooms 2000-2199)."""
+    rooms 2000-2199), with the per-iteration and warm-start times measured on the
+    first room."""
     import os
 
     from paper_2506_00970_amd import Rasterizer
-    from paper_2506_00970_amd.eval_warmstart import run_case
+    from paper_2506_00970_amd.eval_warmstart import CAMERA, run_case, time_ms
 
     path = os.path.join(os.path.dirname(wsmod.__file__), "weights", "warm_start.npy")
     net = wsmod.WarmStartNet(max_batch=1)
     net.set_params(dev(np.load(path, allow_pickle=False).astype(np.float32)))
     r = Rasterizer()
-    out = []
+    out, ms_iter, ms_warm = [], None, None
     for seed in range(20):
         c = run_case(r, net, seed, 100)
+        if ms_iter is None:
+            pose = c["start"].clone()
+            ms_iter = time_ms(lambda: r.track(c["P"], CAMERA, pose.copy_(c["start"]), c["trgb"], c["tdep"], 100,
+                                              history=False)) / 100
+            ms_warm = time_ms(lambda: net.warm_start(r, c["P"], CAMERA, c["start"], c["trgb"], c["tdep"]))
         out.append((c["plain_iters"], c["warm_iters"]))
         print(seed, "plain", c["plain_iters"], "warm", c["warm_iters"], "after warm start", c["warm_err_cm_deg"])
-    return out
+    print("ms per iteration", ms_iter, "warm start ms", ms_warm)
+    return {"iters": out, "ms_iter": ms_iter, "ms_warm": ms_warm}
 
 
 def test_warm_start_gain_on_held_out_rooms(held_out):
-    """The warm-started tracking reaches 1 cm / 0.5 deg in fewer iterations in most rooms
-    (measured 16 of 20) and, with the warm start itself charged as 3 iterations (0.39 ms
-    against 0.15 ms per iteration), in at most 80 % of the plain iterations overall
-    (measured 433 against 651; unconverged runs count 101)."""
-    plain = [p or 101 for p, _ in held_out]
-    warm = [w or 101 for _, w in held_out]
-    assert sum(w + 3 for w in warm) <= 0.8 * sum(plain), (plain, warm)
+    """Time to 1 cm / 0.5 deg, from the measured per-iteration and warm-start times:
+    warm-started tracking (the warm start plus its iterations) is faster in most rooms
+    (measured 16 of 20), and its total over the 20 rooms is at most 80 % of plain
+    tracking's (unconverged runs count 101 iterations)."""
+    it, wm = held_out["ms_iter"], held_out["ms_warm"]
+    plain = [(p or 101) * it for p, _ in held_out["iters"]]
+    warm = [(w or 101) * it + wm for _, w in held_out["iters"]]
+    print("plain ms", np.median(plain), "warm ms", np.median(warm))
+    assert sum(warm) <= 0.8 * sum(plain), (plain, warm)
     assert sum(w < p for w, p in zip(warm, plain)) >= 14, (plain, warm)
 
 
 def test_tracking_converges_on_held_out_rooms(held_out):
-    """End to end: from a 5 cm / 3 deg start, plain tracking converges to 1 cm / 0.5 deg
-    within 100 iterations in at least 90 % of the rooms (measured 20 of 20, in at most 60
-    iterations) and the warm-started tracking in at least 95 % (measured 20 of 20)."""
-    assert sum(p is not None for p, _ in held_out) >= 18, held_out
-    assert sum(w is not None for _, w in held_out) >= 19, held_out
+    """End to end (P16): from a 5 cm / 3 deg start, plain tracking and warm-started
+    tracking each converge to 1 cm / 0.5 deg within 100 iterations in at least 95 % of
+    the rooms (measured 20 of 20 for both)."""
+    assert sum(p is not None for p, _ in held_out["iters"]) >= 19, held_out
+    assert sum(w is not None for _, w in held_out["iters"]) >= 19, held_out
