@@ -280,6 +280,27 @@ typedef struct gs2d_loss_view {
 GS2D_API int gs2d_image_loss_batch(gs2d_ctx* ctx, const gs2d_loss_view* views, int32_t n_views,
                                    const gs2d_loss_weights* weights, float* losses, hipStream_t stream);
 
+/* Largest image (width x height) gs2d_image_loss_noalloc takes. */
+#define GS2D_NOALLOC_MAX_PIXELS (1 << 24)
+
+/* gs2d_image_loss without a context, for callers that cannot allocate device memory:
+ * code under HIP graph capture, serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments (other than the context), NULL rules, results and launches as
+ * gs2d_image_loss, on the device that is current for the calling thread.  It calls no
+ * allocating routine: its scratch memory (a one-view descriptor table and one partial
+ * sum per 256 pixels, 257 KiB) is a fixed array in the library's device code, one copy
+ * per GPU, held until the process ends; the first call on a device looks up that
+ * copy's address.  Images of more than GS2D_NOALLOC_MAX_PIXELS pixels return
+ * GS2D_ERR_CAPACITY before any work.  Every call on one GPU shares that GPU's copy:
+ * calls that overlap on one GPU (on different streams, or from different threads)
+ * race and must be serialised by the caller.  GS2D_ERR_HIP if the address lookup or a
+ * launch fails. */
+GS2D_API int gs2d_image_loss_noalloc(const gs2d_camera* camera, const float* rgb, const float* depth,
+                                     const float* normal, const float* alpha, const float* tgt_rgb,
+                                     const float* tgt_depth, const float* tgt_normal,
+                                     const gs2d_loss_weights* weights, float* loss, float* d_rgb, float* d_depth,
+                                     float* d_normal, hipStream_t stream);
+
 /* Relocalisation error of Sec. "Loop Detection and Relocalization" (eq:tracking_error):
  * e_t = (1/HW) sum_p M_n M_o |depth - tgt_depth|, the depth term of the tracking loss
  * with its masks (M_n = [normal . ray > 0], M_o = [alpha > 0.95]), computed on the

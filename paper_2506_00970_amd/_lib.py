@@ -56,6 +56,7 @@ class Tuning(ctypes.Structure):
                 ("ms", ctypes.c_float), ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
+NOALLOC_MAX_PIXELS = 1 << 24
 MAX_VIEWS = 32
 
 
@@ -141,6 +142,8 @@ _SIGS = {
                          _P, _P, _P], ctypes.c_int),
     "gs2d_image_loss_batch": ([_P, ctypes.POINTER(LossView), ctypes.c_int32, ctypes.POINTER(LossWeights), _P, _P],
                               ctypes.c_int),
+    "gs2d_image_loss_noalloc": ([ctypes.POINTER(Camera), _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(LossWeights), _P,
+                                 _P, _P, _P, _P], ctypes.c_int),
     "gs2d_track": ([_P, ctypes.POINTER(TrackArgs), _P], ctypes.c_int),
     "gs2d_get_counts": ([_P, ctypes.POINTER(Counts), _P], ctypes.c_int),
     "gs2d_debug_copy": ([_P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_size_t), _P], ctypes.c_int),

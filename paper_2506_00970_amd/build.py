@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgs2d.so")
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "loss_pose.hip", "warmstart.hip", "mapstate.hip", "mapping_loss.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "blend.hip", "loss_pose.hip", "warmstart.hip", "mapstate.hip", "mapping_loss.hip",
+           "image_loss_noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -61,6 +61,32 @@ class RenderOut:
     depth_median: torch.Tensor | None = None  # [H, W] median depth (render_batch(depth_variants=True))
 
 
+def image_loss_noalloc(camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, tgt_normal, loss, d_rgb=None,
+                       d_depth=None, d_normal=None, w_rgb=1.0, w_depth=1.0, w_normal=0.0, normal_mask=False,
+                       opacity_mask=False):
+    """gs2d_image_loss_noalloc: the masked L1 image loss without a context and without
+    any allocation, on torch's current device and stream.  Every output (loss scalar,
+    optional image gradients) is a caller-owned tensor; nothing is allocated here
+    either, so the call can be captured into a graph.  Same NULL rules as
+    Rasterizer.image_loss; calls that overlap on one GPU race."""
+    cam = _camera(camera)
+    H, W = cam.height, cam.width
+    device = depth.device
+    for t, nm, shp in ((rgb, "rgb", (3, H, W)), (tgt_rgb, "tgt_rgb", (3, H, W)), (depth, "depth", (H, W)),
+                       (tgt_depth, "tgt_depth", (H, W)), (normal, "normal", (3, H, W)),
+                       (tgt_normal, "tgt_normal", (3, H, W)), (alpha, "alpha", (H, W)), (loss, "loss", ()),
+                       (d_rgb, "d_rgb", (3, H, W)), (d_depth, "d_depth", (H, W)), (d_normal, "d_normal", (3, H, W))):
+        _check_tensor(t, nm, shp, device)
+    lib = _lib.load()
+    w = _lib.LossWeights(float(w_rgb), float(w_depth), float(w_normal), int(normal_mask), int(opacity_mask))
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    _lib.check(lib.gs2d_image_loss_noalloc(ctypes.byref(cam), _dev_ptr(rgb), _dev_ptr(depth), _dev_ptr(normal),
+                                           _dev_ptr(alpha), _dev_ptr(tgt_rgb), _dev_ptr(tgt_depth),
+                                           _dev_ptr(tgt_normal), ctypes.byref(w), _dev_ptr(loss), _dev_ptr(d_rgb),
+                                           _dev_ptr(d_depth), _dev_ptr(d_normal), stream))
+    return loss
+
+
 class Rasterizer:
     """One libgs2d context on one device (one context per stream; not thread safe)."""
 
