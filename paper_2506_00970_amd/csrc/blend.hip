@@ -407,7 +407,7 @@ struct BwdPix {
 // pose sums (pose-only) or the entry's 16 per-surfel terms acc.
 template <bool POSE_ONLY, bool HAS_N, bool HAS_O>
 __device__ __forceinline__ void reverse_entry(BwdPix& s, const Hit& h, const Rec& r, const CamF& cam, float xh,
-                                              float yh, float* acc) {
+                                              float yh, float ifx, float ify, float* acc) {
   const float4 c4 = r.c4, nv = r.nv;
   const float al = h.alpha;
   const float Tj = s.T * __builtin_amdgcn_rcpf(1.0f - al);
@@ -458,10 +458,10 @@ __device__ __forceinline__ void reverse_entry(BwdPix& s, const Hit& h, const Rec
     // rho = 2 |p - c|^2 with c = (M02, M12) / m2; depth = m2
     const float gcx = -2.0f * kFilterScale * h.dx * dLdrho;
     const float gcy = -2.0f * kFilterScale * h.dy * dLdrho;
-    const float im2 = 1.0f / m2;
+    const float im2 = __builtin_amdgcn_rcpf(m2);
     Vx = cam.fx * gcx * im2;
     Vy = cam.fy * gcy * im2;
-    const float xc = ((r.ox + r.g1.x) - cam.cx) / cam.fx, yc = ((r.oy + r.g1.y) - cam.cy) / cam.fy;
+    const float xc = ((r.ox + r.g1.x) - cam.cx) * ifx, yc = ((r.oy + r.g1.y) - cam.cy) * ify;
     Vz = g_d - xc * Vx - yc * Vy;
     ue = 0.f;
     ve = 0.f;
@@ -603,6 +603,7 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
     if (HAS_O && V.g_alpha) s.go = V.g_alpha[p];
   }
   const float xh = (fpx - cam.cx) / cam.fx, yh = (fpy - cam.cy) / cam.fy;
+  const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
   int n_eval = 0, n_cov = 0;
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x;
@@ -653,9 +654,9 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
         }
         float acc1[16], acc2[16];
         const bool c1on = live1 && k1 == 2, c2on = live2 && k2 == 2;
-        if (c1on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h1, r1, cam, xh, yh, acc1);
+        if (c1on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h1, r1, cam, xh, yh, ifx, ify, acc1);
         if (!POSE_ONLY) flush_entry(acc1, c1on, sacc, j1, lane);
-        if (c2on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h2, r2, cam, xh, yh, acc2);
+        if (c2on) reverse_entry<POSE_ONLY, HAS_N, HAS_O>(s, h2, r2, cam, xh, yh, ifx, ify, acc2);
         if (!POSE_ONLY && two) flush_entry(acc2, c2on, sacc, j2, lane);
       }
     }
@@ -715,7 +716,7 @@ __host__ __device__ constexpr int track_stage_f4(int batch) {
 // walk's registers then allow five waves per SIMD, which hides more latency than
 // two independent evaluations per step at four.
 template <int TW, int TH, bool PROF>
-__global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsigned long long* __restrict__ work) {
+__global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(5))) void blend_track_kernel(BlendArgs a, unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
   extern __shared__ float4 srec[];
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
@@ -733,6 +734,7 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
   const float fpx = (float)px, fpy = (float)py;
   const float bx0 = (float)wx0, by0 = (float)wy0;
   const float xh = (fpx - cam.cx) / cam.fx, yh = (fpy - cam.cy) / cam.fy;
+  const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
   const uint2 rg = a.ranges[tile];
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
@@ -761,51 +763,57 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
     }
     const float T = s.T, w = al * T;
     const float m0 = r.g3.y, m1 = r.g3.z, m2 = r.g3.w;
-    // V = dLdrho V_rho + g_d V_d for the pair (see the backward kernel)
-    float Vr[3], Vd[3], X[3];
+    // V = dLdrho V_rho + g_d V_d for the pair (see the backward kernel); J and K are
+    // [V; X x V] with X = d (xr, yr, 1) the intersection point: X x V = d (r x V)
+    // with r = (xr, yr, 1) the ray through the pixel (or, in the filter branch, through
+    // the projected centre).
+    float Vr0, Vr1, Vd0, Vd1, Vd2, d;
     if (h.b3d) {
       const float hu0 = fmaf(-h.dx, m0, r.g2.y), hu1 = fmaf(-h.dx, m1, r.g2.z);
       const float hv0 = fmaf(-h.dy, m0, r.g2.w), hv1 = fmaf(-h.dy, m1, r.g3.x);
-      // gradient to (u, v): 2 (u, v) per unit dLdrho, (m0, m1) per unit g_d
-      const float ru0 = 2.0f * h.u * h.rq, rv0 = 2.0f * h.v * h.rq;
-      const float du0 = m0 * h.rq, dv0 = m1 * h.rq;
-      Vr[0] = cam.fx * (hv0 * rv0 - hv1 * ru0);
-      Vr[1] = cam.fy * (ru0 * hu1 - rv0 * hu0);
-      Vr[2] = -xh * Vr[0] - yh * Vr[1];
-      Vd[0] = cam.fx * (hv0 * dv0 - hv1 * du0);
-      Vd[1] = cam.fy * (du0 * hu1 - dv0 * hu0);
-      Vd[2] = 1.0f - xh * Vd[0] - yh * Vd[1];
-      X[0] = h.d * xh;
-      X[1] = h.d * yh;
-      X[2] = h.d;
+      // d(rho)/d(q-row entries) 2 (u, v) rq; d(depth) (m0, m1) rq, in which the pixel
+      // offsets cancel: h_v0 m1 - h_v1 m0 = Q0 m1 - Q1 m0, m0 h_u1 - m1 h_u0 = m0 P1 - m1 P0
+      const float r2 = 2.0f * h.rq;
+      Vr0 = (cam.fx * r2) * fmaf(hv0, h.v, -(hv1 * h.u));
+      Vr1 = (cam.fy * r2) * fmaf(hu1, h.u, -(hu0 * h.v));
+      Vd0 = (cam.fx * h.rq) * fmaf(r.g2.w, m1, -(r.g3.x * m0));
+      Vd1 = (cam.fy * h.rq) * fmaf(m0, r.g2.z, -(m1 * r.g2.y));
+      d = h.d;
     } else {
-      const float im2 = 1.0f / m2;
-      const float xc = ((r.ox + r.g1.x) - cam.cx) / cam.fx, yc = ((r.oy + r.g1.y) - cam.cy) / cam.fy;
-      Vr[0] = cam.fx * (-2.0f * kFilterScale * h.dx) * im2;
-      Vr[1] = cam.fy * (-2.0f * kFilterScale * h.dy) * im2;
-      Vr[2] = -xc * Vr[0] - yc * Vr[1];
-      Vd[0] = 0.f;
-      Vd[1] = 0.f;
-      Vd[2] = 1.0f;
-      X[0] = m2 * xc;
-      X[1] = m2 * yc;
-      X[2] = m2;
+      // filter branch: rho = 2 |p - c|^2 about the projected centre c, depth m2; its
+      // intersection point is the centre's ray at depth m2
+      const float im2 = __builtin_amdgcn_rcpf(m2);
+      Vr0 = cam.fx * (-2.0f * kFilterScale * h.dx) * im2;
+      Vr1 = cam.fy * (-2.0f * kFilterScale * h.dy) * im2;
+      Vd0 = 0.f;
+      Vd1 = 0.f;
+      d = m2;
     }
+    float xr = xh, yr = yh;
+    if (!h.b3d) {
+      xr = ((r.ox + r.g1.x) - cam.cx) * ifx;
+      yr = ((r.oy + r.g1.y) - cam.cy) * ify;
+    }
+    const float axy = xr * yr, bx = fmaf(xr, xr, 1.0f), by = fmaf(yr, yr, 1.0f);
+    const float Vr2 = fmaf(-xr, Vr0, -(yr * Vr1));
+    Vd2 = fmaf(-xr, Vd0, fmaf(-yr, Vd1, 1.0f));
     // J = dalpha/dtau = dLdrho-direction times drho/dalpha = -G o / 2 (unclamped)
     const float jc = h.clamped ? 0.f : -0.5f * h.G * r.c4.x;
+    const float jd = jc * d;
     float J[6], K[6];
-    J[0] = jc * Vr[0];
-    J[1] = jc * Vr[1];
-    J[2] = jc * Vr[2];
-    J[3] = jc * (X[1] * Vr[2] - X[2] * Vr[1]);
-    J[4] = jc * (X[2] * Vr[0] - X[0] * Vr[2]);
-    J[5] = jc * (X[0] * Vr[1] - X[1] * Vr[0]);
-    K[0] = Vd[0];
-    K[1] = Vd[1];
-    K[2] = Vd[2];
-    K[3] = X[1] * Vd[2] - X[2] * Vd[1];
-    K[4] = X[2] * Vd[0] - X[0] * Vd[2];
-    K[5] = X[0] * Vd[1] - X[1] * Vd[0];
+    J[0] = jc * Vr0;
+    J[1] = jc * Vr1;
+    J[2] = jc * Vr2;
+    // r x Vr with Vr2 = -xr Vr0 - yr Vr1: (-xr yr Vr0 - (1 + yr^2) Vr1, (1 + xr^2) Vr0 + xr yr Vr1, xr Vr1 - yr Vr0)
+    J[3] = jd * fmaf(-axy, Vr0, -(by * Vr1));
+    J[4] = jd * fmaf(bx, Vr0, axy * Vr1);
+    J[5] = jd * fmaf(xr, Vr1, -(yr * Vr0));
+    K[0] = Vd0;
+    K[1] = Vd1;
+    K[2] = Vd2;
+    K[3] = d * fmaf(yr, Vd2, -Vd1);
+    K[4] = d * fmaf(-xr, Vd2, Vd0);
+    K[5] = d * fmaf(xr, Vd1, -(yr * Vd0));
     const float ia = __builtin_amdgcn_rcpf(1.0f - al);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -820,9 +828,8 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
     s.cg = fmaf(w, r.c4.z, s.cg);
     s.cb = fmaf(w, r.c4.w, s.cb);
     s.cd = fmaf(w, h.d, s.cd);
-    s.n0 = fmaf(w, r.nv.x, s.n0);
-    s.n1 = fmaf(w, r.nv.y, s.n1);
-    s.n2 = fmaf(w, r.nv.z, s.n2);
+    // the normal mask needs only N . r: blended as the scalar n . r of each entry
+    s.n0 = fmaf(w, fmaf(r.nv.x, xh, fmaf(r.nv.y, yh, r.nv.z)), s.n0);
     s.co += w;
     s.T = Tn;
   };
@@ -866,7 +873,7 @@ __global__ __launch_bounds__(TW* TH) void blend_track_kernel(BlendArgs a, unsign
   if (inside) {
     bool mk = true;
     if (a.use_masks) {
-      const float ndr = fmaf(s.n0, xh, fmaf(s.n1, yh, s.n2));
+      const float ndr = s.n0;
       mk = (ndr > 0.0f) && (s.co > kOpacityMask);
     }
     if (mk) {
