@@ -34,11 +34,14 @@ HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (one lane-op per
 # lane per clock; transcendental ops occupy 4 issue slots).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic VALU lane-ops per (pixel, surfel) pair inside the footprint, reached
-# before termination: forward intersection + Gaussian + opacity + 8-channel blend;
-# backward recompute + blend reverse + intersection reverse + pose terms.
-OPS_FWD_PAIR = 44
-OPS_BWD_PAIR = 110
+# VALU lane-op slots per unit of work, counted in the gfx950 code of the blend kernels
+# (transcendentals at 4 slots): per evaluated (pixel, surfel) pair (the pairs each pixel
+# walks before it terminates, after the per-wave cull) and per composited pair (3D
+# branch).  blend_track: the evaluation, then the compositing with the pose-gradient
+# terms; blend_fwd: the evaluation, then the 8-channel compositing; blend_bwd (all
+# parameters): the evaluation, then the reverse step and the 16 per-surfel terms it
+# adds (the wave reduction that carries those additions is not counted).
+OPS_PER_UNIT = {"blend_track": (45, 129), "blend_fwd": (43, 20), "blend_bwd": (42, 86)}
 
 
 def log(msg):
@@ -56,22 +59,46 @@ def cpu_model():
     return platform.processor()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter runs, if the kernel is unchanged since."""
+def measured_counters(workload, kernel):
+    """Per-launch counters of `kernel` (rocprofv3 name) from the committed counter runs
+    (profiles/counters.json), if the blend kernels' source is unchanged since."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", "counters.json")
     src = os.path.join(ROOT, "paper_2506_00970_amd", "csrc", "blend.hip")
     try:
         with open(path) as f:
-            rec = json.load(f).get(kernel)
+            rec = json.load(f)
         with open(src, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_sha256") != sha:
+    if rec.get("source_sha256") != sha:
         return None
-    return rec["bytes_per_launch"]
+    return rec.get(workload, {}).get(kernel)
+
+
+def alu_roofline(kernel, evaluated, covering, ms, measured=None):
+    """The VALU roofline of a blend kernel: algorithmic lane-ops per launch (the per-unit
+    counts of OPS_PER_UNIT times the launch's evaluated and composited pairs) over its
+    average launch time, against the non-packed FP32 issue peak."""
+    pe, pc = OPS_PER_UNIT[kernel]
+    ops = pe * evaluated + pc * covering
+    achieved = ops / (ms * 1e-3) / 1e12
+    out = {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+           "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "units_per_launch": evaluated,
+           "ops_per_unit": ops / max(evaluated, 1.0), "avg_launch_ms": ms,
+           "ops_model": {"per_evaluated_pair": pe, "per_composited_pair": pc, "evaluated_pairs": evaluated,
+                         "covering_pairs": covering},
+           "measured": None}
+    if measured:
+        out["traffic"] = measured.get("fetch_bytes", 0.0) + measured.get("write_bytes", 0.0) or None
+        out["measured"] = {k: measured[k] for k in ("valu_busy", "valu_lane_utilisation", "valu_insts",
+                                                     "valu_lane_ops", "lds_insts", "lds_bank_conflict_frac",
+                                                     "l2_atomics") if k in measured}
+        # issued active-lane VALU work over the same launch time
+        out["measured"]["issued_frac"] = measured["valu_lane_ops"] / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+    return out
 
 
 def cpu_baseline(room_params, cam, start, tgt_rgb, tgt_depth, budget_s=20.0):
@@ -358,14 +385,14 @@ def config3_bench(args):
     tuning = r.autotune(P, cam_l, pose_t[4], full_backward=True)
     views = [(P, cams[k], pose_t[k]) for k in range(8)]
 
-    def step():
-        outs = r.render_batch(views)
+    def step(rr=r):
+        outs = rr.render_batch(views)
         # every view's loss and image gradients in one launch (and one for the reductions)
-        _, g = r.image_loss_batch([{"camera": cams[k], "rgb": o.rgb, "depth": o.depth, "normal": o.normal,
-                                    "alpha": o.alpha, "tgt_rgb": targets[k][0], "tgt_depth": targets[k][1]}
-                                   for k, o in enumerate(outs)], w_rgb=1.0, w_depth=0.5, opacity_mask=True)
+        _, g = rr.image_loss_batch([{"camera": cams[k], "rgb": o.rgb, "depth": o.depth, "normal": o.normal,
+                                     "alpha": o.alpha, "tgt_rgb": targets[k][0], "tgt_depth": targets[k][1]}
+                                    for k, o in enumerate(outs)], w_rgb=1.0, w_depth=0.5, opacity_mask=True)
         grads = [{"d_rgb": d_rgb, "d_depth": d_depth} for d_rgb, d_depth, _ in g]
-        return r.backward_batch(outs[0].generation, grads, params_grad=True)
+        return rr.backward_batch(outs[0].generation, grads, params_grad=True)
 
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
@@ -385,6 +412,28 @@ def config3_bench(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     times = _replay_times(graph, 20)
+    # eager passes of the same iteration with the tuned shape: one counting the blend
+    # work (its counting kernels are slower), one timing each kernel family with HIP
+    # events while running the same kernels as the graph
+    tw, th, tb = tuning["tile_w"], tuning["tile_h"], tuning["batch"]
+    rc = Rasterizer(device=0, tile=(tw, th), batch=tb, profile=1)
+    step(rc)
+    rc.profile(reset=True)
+    step(rc)
+    prof = rc.profile(reset=True)
+    rt = Rasterizer(device=0, tile=(tw, th), batch=tb, profile=2)
+    step(rt)
+    rt.profile(reset=True)
+    for _ in range(3):
+        step(rt)
+    fam = rt.profile(reset=True)["families"]
+    torch.cuda.synchronize()
+    per_launch = {k: (v["ms"] / v["launches"] if v["launches"] else 0.0) for k, v in fam.items()}
+    nf, nb = max(prof["families"]["blend_fwd"]["launches"], 1), max(prof["families"]["blend_bwd"]["launches"], 1)
+    roof_bwd = alu_roofline("blend_bwd", prof["bwd_evaluated"] / nb, prof["bwd_covering"] / nb, per_launch["blend_bwd"],
+                            measured_counters("map", f"blend_bwd_kernel<{tw}, {th}, false, false, false, false>"))
+    roof_fwd = alu_roofline("blend_fwd", prof["fwd_evaluated"] / nf, prof["fwd_covering"] / nf, per_launch["blend_fwd"],
+                            measured_counters("map", f"blend_fwd_kernel<{tw}, {th}, false>"))
     print(json.dumps({
         "metric": "mapping-window iterations/s (8 views fwd + bwd to all surfel params and poses), 1M surfels",
         "value": steps / el, "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -393,7 +442,8 @@ def config3_bench(args):
         "config": {"workload": "8 keyframes (4 x 640x480 f=525, 4 x 1200x680 f=600) of a 1M-surfel synthetic room "
                                "(seed 100), state jittered 5 mm / 0.05 colour, poses 2 cm / 1 deg; opacity-masked "
                                "colour + 0.5 depth L1 per view; one HIP graph per iteration", "tuning": tuning},
-        "median_replay_ms": float(np.median(times)), "counts": r.counts()}), flush=True)
+        "median_replay_ms": float(np.median(times)), "counts": r.counts(),
+        "roofline": roof_bwd, "roofline_forward": roof_fwd, "kernels_ms_per_launch": per_launch}), flush=True)
 
 
 def config4_bench(args):
@@ -599,23 +649,11 @@ def main():
     cfam = prof["families"]  # launches of the counting pass
     n_fwd = cfam["blend_fwd"]["launches"] + cfam["blend_track"]["launches"]
     n_bwd = cfam["blend_bwd"]["launches"]
-    if cfam["blend_track"]["launches"]:
-        # the tracking walk: forward blend, loss and pose gradient of each covering pair
-        dom = "blend_track"
-        units = prof["fwd_covering"] / max(n_fwd, 1)
-        ops_unit = OPS_FWD_PAIR + OPS_BWD_PAIR
-    else:
-        dom = max(("blend_fwd", "blend_bwd"), key=lambda k: per_launch[k])
-        if dom == "blend_bwd":
-            units, ops_unit = prof["bwd_covering"] / max(n_bwd, 1), OPS_BWD_PAIR
-        else:
-            units, ops_unit = prof["fwd_covering"] / max(n_fwd, 1), OPS_FWD_PAIR
-    ops = units * ops_unit
-    achieved = ops / (per_launch[dom] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(dom),
-                "units_per_launch": units, "ops_per_unit": ops_unit,
-                "avg_launch_ms": per_launch[dom]}
+    # the tracking walk: evaluated pairs, and the pairs it composites with their
+    # forward blend, loss and pose-gradient terms
+    roofline = alu_roofline("blend_track", prof["fwd_evaluated"] / max(n_fwd, 1), prof["fwd_covering"] / max(n_fwd, 1),
+                            per_launch["blend_track"],
+                            measured_counters("track", "blend_track_kernel<16, 16, false>"))
 
     out = {
         "metric": METRIC,
