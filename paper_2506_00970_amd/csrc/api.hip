@@ -177,6 +177,7 @@ int ensure_pixels(gs2d_ctx* ctx, int64_t hw) {
 int ensure_tiles(gs2d_ctx* ctx, int64_t tiles) {
   if (tiles <= ctx->tile_cap) return GS2D_OK;
   GS2D_TRY(realloc_dev(ctx, &ctx->ranges, tiles));
+  GS2D_TRY(realloc_dev(ctx, &ctx->queue, kQueueOrder + tiles));
   ctx->tile_cap = tiles;
   return GS2D_OK;
 }
@@ -281,6 +282,7 @@ BlendArgs blend_args(gs2d_ctx* ctx) {
   BlendArgs a{ctx->ranges, ctx->pval[ctx->pair_buf], ctx->rec, ctx->views, ctx->last_views.n_views,
               (int)ctx->last_views.tiles, ctx->opt.z_near, ctx->opt.filter, ctx->opt.batch};
   a.tile_stride = tile_stride(ctx->last_views.tiles);
+  a.queue = ctx->queue_on ? ctx->queue : nullptr;
   return a;
 }
 
@@ -332,6 +334,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     launch_fill_u32(ctx->last, 0u, vs.pixels, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ranges), 0u, 2 * vs.tiles, s);
     launch_fill_u32(reinterpret_cast<uint32_t*>(ctx->ctrl), 0u, 3, s);
+    ctx->queue_on = false;
   } else {
     clear_fresh_hist(ctx, s);
     SortPlanes ws = sort_planes(ctx);
@@ -392,9 +395,14 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
       ProfScope ps(ctx, kDepthSort, s);
       launch_tile_order(ctx->ranges, (int)vs.tiles, ctx->pval[pbuf], ctx->pval[pbuf ^ 1], ctx->dkey, s);
     }
+    // many more tiles than fit on the GPU at once: the blends pull tiles from a queue,
+    // longest lists first
+    ctx->queue_on = blend && vs.tiles > kQueueMinTiles;
+    if (ctx->queue_on) launch_queue_order(ctx->ranges, (int)vs.tiles, ctx->queue, s);
     BlendArgs ba{ctx->ranges, ctx->pval[pbuf], ctx->rec, ctx->views, nv, (int)vs.tiles, ctx->opt.z_near,
                  ctx->opt.filter, ctx->opt.batch};
     ba.tile_stride = tile_stride(vs.tiles);
+    ba.queue = ctx->queue_on ? ctx->queue : nullptr;
     if (tl) {
       ba.loss_part = ctx->part;
       ba.lambda_d = tl->lambda_d;
@@ -446,6 +454,7 @@ int backward_views(gs2d_ctx* ctx, const gs2d_view_grad* grads, int nv, int acc, 
   }
   launch_upload_views(vs, ctx->views, s);
   const BlendArgs ba = blend_args(ctx);
+  if (ba.queue) launch_fill_u32(ba.queue + kQueueHeadBwd, 0u, 1, s);
   if (!full) {
     {
       ProfScope ps(ctx, kBlendBwd, s);
@@ -824,7 +833,8 @@ GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
   void* bufs[] = {ctx->rec,       ctx->rect,       ctx->count,     ctx->dkey,      ctx->parts,     ctx->hist,
                   ctx->gacc,      ctx->pkey[0],    ctx->pkey[1],   ctx->pval[0],   ctx->pval[1],   ctx->pkey_keep,
                   ctx->pval_keep, ctx->ranges,     ctx->t_final,   ctx->last,      ctx->lgrad,     ctx->limg,
-                  ctx->part,      ctx->lpart,      ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl};
+                  ctx->part,      ctx->lpart,      ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl,
+                  ctx->queue};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);

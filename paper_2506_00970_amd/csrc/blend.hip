@@ -26,6 +26,9 @@
 // registers and reduces them once per workgroup (no per-surfel atomics); the
 // full mode reduces the 16 per-surfel terms over each wave and adds them
 // atomically.
+#include <mutex>
+#include <vector>
+
 #include "tile_order.h"
 
 namespace gs2d {
@@ -88,12 +91,30 @@ __device__ __forceinline__ float uniformf(float x) {
 // are resident at once, and a long list is the critical path of the launch, so its
 // waves take the SIMD before the short ones (which fill the remaining slots).
 __device__ __forceinline__ void prioritise(int len) {
+  __builtin_amdgcn_s_setprio(0);  // a persistent workgroup's next tile starts from 0
   if (len >= 192)
     __builtin_amdgcn_s_setprio(3);
   else if (len >= 128)
     __builtin_amdgcn_s_setprio(2);
   else if (len >= 64)
     __builtin_amdgcn_s_setprio(1);
+}
+
+// The tile of a workgroup of a direct (one workgroup per tile) launch: workgroups are
+// dealt round-robin to the 8 XCDs, so each XCD gets every 8th tile of the stride:
+// an even share of the dense and sparse image regions.
+__device__ __forceinline__ int grid_tile(const BlendArgs& a) {
+  return (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
+}
+
+// The next item of a persistent launch's queue for the whole workgroup (every thread
+// calls it; the previous item's LDS is free once everyone has passed the first barrier).
+__device__ __forceinline__ int next_queue_item(uint32_t* head) {
+  __shared__ int s_item;
+  __syncthreads();
+  if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
+  __syncthreads();
+  return s_item;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -252,17 +273,14 @@ __device__ __forceinline__ void add_contribution(float* contrib, uint32_t surfel
 }
 
 template <int TW, int TH, bool PROF>
-__global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ t_final,
-                                                           uint32_t* __restrict__ last_out,
-                                                           unsigned long long* __restrict__ work) {
+__device__ __forceinline__ void blend_fwd_tile(const BlendArgs& a, const int tile, float* __restrict__ t_final,
+                                               uint32_t* __restrict__ last_out,
+                                               unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8;
   extern __shared__ float4 srec[];
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
                      srec + (size_t)a.batch * (kLdsRec + 2)};
   uint32_t* const sids = reinterpret_cast<uint32_t*>(srec + (size_t)a.batch * (kLdsRec + 3));
-  // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
-  // each XCD gets every 8th tile: an even share of the dense and sparse image regions
-  const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const int lt = tile - V.tile_base;
   const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
@@ -392,6 +410,22 @@ __global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* _
       for (int w = 0; w < NT / 64; ++w) sum += s_loss[w];
       a.loss_part[(size_t)tile * 8 + 6] = sum;
     }
+  }
+}
+
+template <int TW, int TH, bool PROF>
+__global__ __launch_bounds__(TW* TH) void blend_fwd_kernel(BlendArgs a, float* __restrict__ t_final,
+                                                           uint32_t* __restrict__ last_out,
+                                                           unsigned long long* __restrict__ work) {
+  if (a.queue) {
+    // persistent: tiles in the queue's order (longest lists first) until it is empty
+    for (;;) {
+      const int item = next_queue_item(a.queue + kQueueHeadFwd);
+      if (item >= a.n_tiles) break;
+      blend_fwd_tile<TW, TH, PROF>(a, (int)a.queue[kQueueOrder + item], t_final, last_out, work);
+    }
+  } else {
+    blend_fwd_tile<TW, TH, PROF>(a, grid_tile(a), t_final, last_out, work);
   }
 }
 
@@ -552,10 +586,9 @@ __device__ __forceinline__ void flush_entry(const float* acc, bool contrib, floa
 }
 
 template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>
-__global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const float* __restrict__ t_final,
-                                                           const uint32_t* __restrict__ last_in,
-                                                           float* __restrict__ gacc, float* __restrict__ part,
-                                                           unsigned long long* __restrict__ work) {
+__device__ __forceinline__ void blend_bwd_tile(const BlendArgs& a, const int tile, const float* __restrict__ t_final,
+                                               const uint32_t* __restrict__ last_in, float* __restrict__ gacc,
+                                               float* __restrict__ part, unsigned long long* __restrict__ work) {
   constexpr int NT = TW * TH, WX = TW / 8, NW = NT / 64;
   extern __shared__ float4 srec[];
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
@@ -566,9 +599,6 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
   float* sacc = reinterpret_cast<float*>(srec + (size_t)a.batch * (kLdsRec + 3));
   __shared__ int s_wmax[NW];
   __shared__ float s_red[NW][6];
-  // global tile over all views; workgroups are dealt round-robin to the 8 XCDs, so
-  // each XCD gets every 8th tile: an even share of the dense and sparse image regions
-  const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const CamF cam = V.cam;
   const int lt = tile - V.tile_base;
@@ -691,6 +721,23 @@ __global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const fl
       for (int w = 0; w < NW; ++w) sum += s_red[w][t];
       part[(size_t)tile * 8 + t] = sum;
     }
+  }
+}
+
+template <int TW, int TH, bool POSE_ONLY, bool HAS_N, bool HAS_O, bool PROF>
+__global__ __launch_bounds__(TW* TH) void blend_bwd_kernel(BlendArgs a, const float* __restrict__ t_final,
+                                                           const uint32_t* __restrict__ last_in,
+                                                           float* __restrict__ gacc, float* __restrict__ part,
+                                                           unsigned long long* __restrict__ work) {
+  if (a.queue) {
+    for (;;) {
+      const int item = next_queue_item(a.queue + kQueueHeadBwd);
+      if (item >= a.n_tiles) break;
+      blend_bwd_tile<TW, TH, POSE_ONLY, HAS_N, HAS_O, PROF>(a, (int)a.queue[kQueueOrder + item], t_final, last_in,
+                                                            gacc, part, work);
+    }
+  } else {
+    blend_bwd_tile<TW, TH, POSE_ONLY, HAS_N, HAS_O, PROF>(a, grid_tile(a), t_final, last_in, gacc, part, work);
   }
 }
 
@@ -905,14 +952,52 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(5))) voi
   }
 }
 
+// Workgroups of `kernel` that fit on the current device at once (occupancy per CU
+// times the CUs), cached per kernel and LDS size: the grid of a persistent launch.
+template <typename K>
+int resident_workgroups(K kernel, int threads, size_t lds) {
+  struct Entry {
+    const void* k;
+    size_t lds;
+    int dev, n;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const Entry& e : cache)
+    if (e.k == reinterpret_cast<const void*>(kernel) && e.lds == lds && e.dev == dev) return e.n;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int n = per_cu * cus;
+  cache.push_back(Entry{reinterpret_cast<const void*>(kernel), lds, dev, n});
+  return n;
+}
+
+// Grid of a blend launch: one workgroup per tile, or with a queue the workgroups that
+// fit at once (each then pulls tiles until the queue is empty; never more than the
+// tiles).  A failed occupancy query falls back to one workgroup per tile.
+template <typename K>
+int blend_grid(const BlendArgs& a, K kernel, int threads, size_t lds) {
+  if (!a.queue) return a.n_tiles;
+  const int n = resident_workgroups(kernel, threads, lds);
+  return n > 0 && n < a.n_tiles ? n : a.n_tiles;
+}
+
 template <int TW, int TH>
 void fwd_shape(const BlendArgs& a, float* t_final, uint32_t* last, unsigned long long* work, hipStream_t s) {
   // staged records and their cull data, then the staged surfel ids
   const size_t lds = (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + sizeof(uint32_t));
-  if (work)
-    blend_fwd_kernel<TW, TH, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
-  else
-    blend_fwd_kernel<TW, TH, false><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, work);
+  if (work) {
+    auto k = blend_fwd_kernel<TW, TH, true>;
+    k<<<blend_grid(a, k, TW * TH, lds), TW * TH, lds, s>>>(a, t_final, last, work);
+  } else {
+    auto k = blend_fwd_kernel<TW, TH, false>;
+    k<<<blend_grid(a, k, TW * TH, lds), TW * TH, lds, s>>>(a, t_final, last, work);
+  }
 }
 
 template <int TW, int TH, bool PO, bool HN, bool HO>
@@ -920,11 +1005,13 @@ void bwd_variant(const BlendArgs& a, const float* t_final, const uint32_t* last,
                  unsigned long long* work, hipStream_t s) {
   // staged records and their cull data, and in full mode the per-entry term sums
   const size_t lds = (size_t)a.batch * ((kLdsRec + 3) * sizeof(float4) + (PO ? 0 : 16 * sizeof(float)));
-  if (work)
-    blend_bwd_kernel<TW, TH, PO, HN, HO, true><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
-  else
-    blend_bwd_kernel<TW, TH, PO, HN, HO, false><<<a.n_tiles, TW * TH, lds, s>>>(a, t_final, last, gacc, part,
-                                                                               work);
+  if (work) {
+    auto k = blend_bwd_kernel<TW, TH, PO, HN, HO, true>;
+    k<<<blend_grid(a, k, TW * TH, lds), TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
+  } else {
+    auto k = blend_bwd_kernel<TW, TH, PO, HN, HO, false>;
+    k<<<blend_grid(a, k, TW * TH, lds), TW * TH, lds, s>>>(a, t_final, last, gacc, part, work);
+  }
 }
 
 template <int TW, int TH>

@@ -149,6 +149,8 @@ struct gs2d_ctx {
 
   // tiles, pixels, partials, view tables
   uint2* ranges = nullptr;
+  uint32_t* queue = nullptr;   // [kQueueOrder + tile_cap]: the blends' work queue
+  bool queue_on = false;       // the last render built the queue (persistent blends)
   float* t_final = nullptr;
   uint32_t* last = nullptr;
   float* lgrad = nullptr;      // [4][pixels]: loss gradients of the tracking loop
@@ -252,6 +254,9 @@ void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t
                        hipStream_t s);
 void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s);
+// The blends' work queue of a view set: tiles by descending list length (counting
+// order over 64 buckets of 32 entries; within a bucket any order), both heads zero.
+void launch_queue_order(const uint2* ranges, int n_tiles, uint32_t* queue, hipStream_t s);
 void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s);
 
 struct AdamArgs {  // the tracking pose step's AdamW settings
@@ -285,7 +290,18 @@ struct BlendArgs {
   uint32_t* order_ids = nullptr;
   uint32_t* order_scratch = nullptr;
   const uint32_t* dkey = nullptr;
+  // persistent launch of the forward and backward blends (many more tiles than fit on
+  // the GPU at once): queue[kQueueHeadFwd], queue[kQueueHeadBwd] are the next items,
+  // queue[kQueueOrder + i] the tiles by descending list length; null: one workgroup
+  // per tile
+  uint32_t* queue = nullptr;
 };
+
+constexpr int kQueueHeadFwd = 0;
+constexpr int kQueueHeadBwd = 1;
+constexpr int kQueueOrder = 2;
+// Batched renders with more tiles than this use the persistent blends.
+constexpr int kQueueMinTiles = 4096;
 // Tracking: forward blend, tracking loss and pose-only gradient in one walk; needs
 // a.loss_part (tile rows: pose gradient in slots 0-5, loss in slot 6), lambda_d,
 // use_masks, and views with targets.  work: the forward's profile counters.

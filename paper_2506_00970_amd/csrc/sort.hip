@@ -350,6 +350,41 @@ void launch_pass(const PassArgs& a, int grid, hipStream_t s) {
   }
 }
 
+// The blends' work queue: tiles by descending list length.  One workgroup: a
+// histogram of the lengths over 64 buckets of 32 entries, bucket offsets from the
+// longest bucket down, then each tile's slot by an atomic on its bucket's offset.
+constexpr int kQueueThreads = 1024;
+constexpr int kQueueBuckets = 64;
+__device__ inline int queue_bucket(uint2 r) {
+  const uint32_t len = r.y - r.x;
+  return len >= (uint32_t)(32 * (kQueueBuckets - 1)) ? kQueueBuckets - 1 : (int)((len + 31u) >> 5);
+}
+__global__ __launch_bounds__(kQueueThreads) void queue_order_kernel(const uint2* __restrict__ ranges, int n_tiles,
+                                                                    uint32_t* __restrict__ queue) {
+  __shared__ uint32_t hist[kQueueBuckets], off[kQueueBuckets];
+  const int t = threadIdx.x;
+  if (t < kQueueBuckets) hist[t] = 0u;
+  if (t == 0) {
+    queue[kQueueHeadFwd] = 0u;
+    queue[kQueueHeadBwd] = 0u;
+  }
+  __syncthreads();
+  for (int i = t; i < n_tiles; i += kQueueThreads) atomicAdd(&hist[queue_bucket(ranges[i])], 1u);
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0u;
+    for (int b = kQueueBuckets - 1; b >= 0; --b) {
+      off[b] = run;
+      run += hist[b];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n_tiles; i += kQueueThreads) {
+    const uint32_t pos = atomicAdd(&off[queue_bucket(ranges[i])], 1u);
+    queue[kQueueOrder + pos] = (uint32_t)i;
+  }
+}
+
 }  // namespace
 
 int radix_pass_bits(int bits, int p) {
@@ -432,6 +467,10 @@ void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2*
                    hipStream_t s) {
   (void)n_tiles;  // cleared by the duplicate kernel
   ranges_kernel<<<blocks_for(p_cap, 256), 256, 0, s>>>(skey, ctrl, p_cap, ranges);
+}
+
+void launch_queue_order(const uint2* ranges, int n_tiles, uint32_t* queue, hipStream_t s) {
+  queue_order_kernel<<<1, kQueueThreads, 0, s>>>(ranges, n_tiles, queue);
 }
 
 void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* dkey,

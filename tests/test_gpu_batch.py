@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_common import check_grads, check_images, dev, host, room_scene
+from tests.gpu_common import check_grads, check_images, check_pose, dev, host, room_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -130,3 +130,37 @@ def test_batch_tracking_equals_single(pkg):
         np.testing.assert_array_equal(host(ph[:, k]), host(sph))
         np.testing.assert_array_equal(host(lh[:, k]), host(slh))
         assert host(lh[-1, k]) < host(lh[0, k])
+
+
+def test_persistent_blends_equal_direct_launches(pkg):
+    """A batch of more than 4096 tiles runs the forward and full backward blends as
+    persistent launches that pull tiles from a queue, longest lists first; every view's
+    images equal its own direct-launch render bit for bit, and the shared surfel
+    gradient and each pose gradient equal the single-view passes within twice the
+    gradient bar (both add float atomics, in different orders)."""
+    room, poses = _scene()
+    r = pkg.Rasterizer()
+    P = dev(room.params)
+    cams = [CAMS[2], CAMS[3], CAMS[2], CAMS[0]]  # 3225 + 1590 + 3225 + 1200 tiles of 16 x 16
+    views = [(P, cams[k], dev(poses[k].reshape(12))) for k in range(4)]
+    outs = r.render_batch(views)
+    assert r.counts()["n_tiles"] > 4096
+    g = np.random.default_rng(3)
+    grads = [{"d_rgb": dev(g.normal(size=(3, c.height, c.width)) / (c.height * c.width)),
+              "d_depth": dev(g.normal(size=(c.height, c.width)) / (c.height * c.width))} for c in cams]
+    res = r.backward_batch(outs[0].generation, grads, params_grad=True)
+    torch.cuda.synchronize()
+    imgs = [{n: host(getattr(o, n)) for n in ("rgb", "depth", "normal", "alpha")} for o in outs]
+    dp_batch = host(res[0][0])
+    poses_batch = [host(x[1]) for x in res]
+    total = np.zeros_like(dp_batch)
+    for k in range(4):
+        single = r.render(*views[k])
+        torch.cuda.synchronize()
+        for n in imgs[k]:
+            np.testing.assert_array_equal(imgs[k][n], host(getattr(single, n)), err_msg=f"view {k} {n}")
+        d_params, d_pose = r.backward(single.generation, grads[k]["d_rgb"], grads[k]["d_depth"], None, None)
+        torch.cuda.synchronize()
+        total += host(d_params)
+        check_pose(poses_batch[k], host(d_pose), rel=2e-3, floor=2e-6)
+    print(check_grads(dp_batch, total, rel=2e-3, floor=2e-6))
