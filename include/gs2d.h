@@ -64,6 +64,7 @@ extern "C" {
 #define GS2D_ERR_CAPACITY (-4)   /* tile-pair capacity exceeded on the device */
 #define GS2D_ERR_STATE (-5)      /* backward called without a matching forward */
 #define GS2D_ERR_UNSUPPORTED (-6)
+#define GS2D_ERR_NONFINITE (-7)    /* a surfel, pose, loss or gradient was not finite */
 
 /* Most views (or tracking problems) one batched call may take. */
 #define GS2D_MAX_VIEWS 32
@@ -99,6 +100,9 @@ typedef struct gs2d_counts {
   int64_t pair_capacity;     /* current pair capacity */
   int32_t overflow;          /* 1: the last render exceeded the capacity (outputs invalid) */
   int32_t n_tiles;
+  int32_t nonfinite;         /* 1: the last render met a surfel or pose with a value that is
+                                not finite; those surfels (all of a bad view) were culled */
+  int32_t pad;
 } gs2d_counts;
 
 /* One view of a batched render: its surfels [15][n], camera, pose [12] and outputs
@@ -177,6 +181,14 @@ typedef struct gs2d_track_args {
   float* loss_history;       /* [n_iters] loss before each step, or NULL */
   double* grad_history;      /* [n_iters][6] pose gradient (rho, phi) each step consumed, FP64
                                 as the step uses it, or NULL */
+  /* Divergence guard: after this many iterations in a row without a loss below the
+   * lowest one so far, the problem stops and its pose returns to the pose of that
+   * lowest loss; the remaining iterations leave it there (0: never stop). */
+  int32_t diverge_patience;
+  /* [n_problems] out (device, int32) or NULL: each problem's end state, 0 every
+   * iteration stepped, 1 stopped by the divergence guard, 2 stopped on a loss or
+   * pose gradient that is not finite (the pose is the last finite one). */
+  int32_t* status;
 } gs2d_track_args;
 
 /* Fill *opt with the defaults listed above. */
@@ -316,7 +328,10 @@ GS2D_API int gs2d_tracking_error(gs2d_ctx* ctx, const gs2d_camera* camera, const
  * replayed; the instantiated graph is kept and reused by later calls with the same
  * buffers and hyper-parameters.  Returns after the work has completed (the call
  * synchronises).  On a pair overflow the loop restarts from the start pose with
- * larger buffers (up to 3 attempts, then GS2D_ERR_CAPACITY). */
+ * larger buffers (up to 3 attempts, then GS2D_ERR_CAPACITY).  GS2D_ERR_NONFINITE
+ * when a surfel or the pose held a value that is not finite (such surfels are culled
+ * from every render) or a problem stopped on a non-finite loss or gradient; the poses
+ * and histories are still written (a stopped problem keeps its last finite pose). */
 GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* args, hipStream_t stream);
 
 /* n_problems (1..GS2D_MAX_VIEWS) independent tracking problems stepped together:

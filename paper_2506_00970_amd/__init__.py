@@ -6,7 +6,7 @@
 the library; the first ``Rasterizer`` does, and raises if it is missing.
 """
 
-from ._lib import Gs2dError  # noqa: F401
+from ._lib import ERR_NONFINITE, Gs2dError  # noqa: F401
 
 
 def __getattr__(name):

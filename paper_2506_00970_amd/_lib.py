@@ -22,6 +22,7 @@ ERR_HIP = -3
 ERR_CAPACITY = -4
 ERR_STATE = -5
 ERR_UNSUPPORTED = -6
+ERR_NONFINITE = -7
 ACCUMULATE = 1
 TUNE_FULL_BACKWARD = 1
 
@@ -39,7 +40,8 @@ class Options(ctypes.Structure):
 
 class Counts(ctypes.Structure):
     _fields_ = [("n_surfels", ctypes.c_int64), ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
-                ("pair_capacity", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
+                ("pair_capacity", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("nonfinite", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 PROFILE_FAMILIES = 13
@@ -110,7 +112,8 @@ class TrackArgs(ctypes.Structure):
                 ("lr", ctypes.c_float * 6), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("use_graph", ctypes.c_int32),
                 ("pose_history", ctypes.c_void_p), ("loss_history", ctypes.c_void_p),
-                ("grad_history", ctypes.c_void_p)]
+                ("grad_history", ctypes.c_void_p), ("diverge_patience", ctypes.c_int32),
+                ("status", ctypes.c_void_p)]
 
 
 class Gs2dError(RuntimeError):

@@ -318,7 +318,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
   GS2D_TRY(ensure_parts(ctx, rows));
   if (ctx->p_cap == 0)
     GS2D_TRY(ensure_pairs(ctx, ctx->opt.pair_capacity > 0 ? ctx->opt.pair_capacity : 4 * (items > 0 ? items : 1)));
-  if (upload) launch_upload_views(vs, ctx->views, s);
+  if (upload) launch_upload_views(vs, ctx->views, s, ctx->ctrl);
   const int tw = ctx->opt.tile_w, th = ctx->opt.tile_h;
   int pbuf = 0;
   if (items == 0) {
@@ -539,6 +539,7 @@ struct TrackKeyHead {
   int32_t use_masks;
   float lr[6];
   float beta1, beta2, eps, weight_decay;
+  int32_t patience, pad0;
   int64_t p_cap;
   int32_t tile_w, tile_h, batch, pad;
 };
@@ -554,6 +555,7 @@ std::vector<unsigned char> make_key(gs2d_ctx* ctx, const gs2d_track_problem* p, 
   h.beta2 = a->beta2;
   h.eps = a->eps;
   h.weight_decay = a->weight_decay;
+  h.patience = a->diverge_patience;
   h.p_cap = ctx->p_cap;
   h.tile_w = ctx->opt.tile_w;
   h.tile_h = ctx->opt.tile_h;
@@ -612,6 +614,7 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
   adam.beta2 = a->beta2;
   adam.eps = a->eps;
   adam.weight_decay = a->weight_decay;
+  adam.patience = a->diverge_patience;
   // sorts, then one walk per tile for the forward blend, the tracking loss and the
   // pose gradient; with no surfel there is no walk and the loss kernel forms the loss
   // with 256-pixel tiles each workgroup of the walk orders its own tile's list
@@ -653,7 +656,7 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.f) return GS2D_ERR_INVALID_ARG;
   if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f) ||
-      !std::isfinite(a->lambda_d))
+      !std::isfinite(a->lambda_d) || a->diverge_patience < 0)
     return GS2D_ERR_INVALID_ARG;
   GS2D_TRY(set_device(ctx));
   bool capturing = false;
@@ -709,7 +712,7 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
       }
     }
     ctx->pair_fixed = true;
-    launch_upload_views(vs, ctx->views, s);
+    launch_upload_views(vs, ctx->views, s, ctx->ctrl);
     launch_track_init(ctx->views, np, ctx->ctrl, a->pose_history, a->loss_history, a->grad_history, a->n_iters,
                       s);
     int r = GS2D_OK;
@@ -755,6 +758,14 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
     GS2D_HIP(ctx, hipStreamSynchronize(s));
     if (!ctx->host_ctrl->overflow) {
       result = GS2D_OK;
+      bool bad = ctx->host_ctrl->nonfinite != 0u;
+      for (int k = 0; k < np; ++k) bad = bad || ctx->host_ctrl->status[k] == kTrackNonFinite;
+      if (a->status) {
+        GS2D_HIP(ctx, hipMemcpyAsync(a->status, ctx->ctrl->status, (size_t)np * sizeof(int32_t),
+                                     hipMemcpyDeviceToDevice, s));
+        GS2D_HIP(ctx, hipStreamSynchronize(s));
+      }
+      if (bad) result = GS2D_ERR_NONFINITE;
       break;
     }
     invalidate_graph(ctx);
@@ -1081,6 +1092,8 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
   out->pair_capacity = ctx->p_cap;
   out->overflow = ctx->host_ctrl->overflow ? 1 : 0;
   out->n_tiles = (int32_t)ctx->last_views.tiles;
+  out->nonfinite = ctx->host_ctrl->nonfinite ? 1 : 0;
+  out->pad = 0;
   return GS2D_OK;
 }
 
@@ -1336,6 +1349,7 @@ GS2D_API const char* gs2d_error_string(int code) {
     case GS2D_ERR_CAPACITY: return "tile-pair capacity exceeded; outputs of the last render are invalid";
     case GS2D_ERR_STATE: return "backward without a matching forward (generation mismatch)";
     case GS2D_ERR_UNSUPPORTED: return "unsupported configuration";
+    case GS2D_ERR_NONFINITE: return "a surfel, pose, loss or gradient was not finite";
     default: return "unknown error code";
   }
 }

@@ -88,7 +88,20 @@ struct Ctrl {            // device-resident counters and tracking state
   double adam_b1t[kMaxViews];   // beta1^t, beta2^t of each view's AdamW step
   double adam_b2t[kMaxViews];
   double master_pose[kMaxViews][12];
+  // guards: nonzero when a render met a surfel or pose that is not finite (those items
+  // are culled; cleared when a render uploads its views); per tracking problem, the
+  // status (kTrackRan, kTrackDiverged, kTrackNonFinite), the iterations since the loss
+  // last fell, and the lowest loss with the pose it was measured at
+  uint32_t nonfinite;
+  int32_t status[kMaxViews];
+  int32_t rising[kMaxViews];
+  double best_loss[kMaxViews];
+  double best_pose[kMaxViews][12];
 };
+
+constexpr int32_t kTrackRan = 0;        // every iteration stepped
+constexpr int32_t kTrackDiverged = 1;   // stopped at the best pose after `patience` rising losses
+constexpr int32_t kTrackNonFinite = 2;  // stopped at the last finite pose on a non-finite loss or step
 
 // Kernel families timed by the profiler.
 enum Family { kPre, kDepthSort, kScan, kDup, kTileSort, kRanges, kBlendFwd, kLoss, kBlendBwd, kPreBwd, kPose,
@@ -193,7 +206,9 @@ struct gs2d_ctx {
 namespace gs2d {
 
 // preprocess.hip
-void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s);
+// Copies the view table to the device; with ctrl (a render's upload) also clears the
+// non-finite flag.
+void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s, Ctrl* ctrl = nullptr);
 constexpr int kPartItems = 256;  // items per preprocessing block (per-block pair counts)
 // Per item: record, tile rectangle, tile count and depth key (0xFFFFFFFF for items
 // that touch no tile); per block of kPartItems items: the pair count and the count of
@@ -259,9 +274,10 @@ void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2*
 void launch_queue_order(const uint2* ranges, int n_tiles, uint32_t* queue, hipStream_t s);
 void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t s);
 
-struct AdamArgs {  // the tracking pose step's AdamW settings
+struct AdamArgs {  // the tracking pose step's AdamW settings and divergence guard
   float lr[6];
   float beta1, beta2, eps, weight_decay;
+  int patience;     // stop after this many iterations without a lower loss (0: never)
 };
 
 // blend.hip

@@ -180,7 +180,11 @@ __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_view
     ctrl->iter_v[k] = 0;
     ctrl->adam_b1t[k] = 1.0;
     ctrl->adam_b2t[k] = 1.0;
+    ctrl->status[k] = kTrackRan;
+    ctrl->rising[k] = 0;
+    ctrl->best_loss[k] = __builtin_inf();
   }
+  for (int k = t; k < n_views * 12; k += blockDim.x) ctrl->best_pose[k / 12][k % 12] = (double)views[k / 12].pose[k % 12];
   if (t == 0) {
     ctrl->iter = 0;
     ctrl->pose_history = pose_history;

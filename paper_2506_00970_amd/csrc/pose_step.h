@@ -120,6 +120,51 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
   const double loss = (sh[6][0] + sh[6][1] + sh[6][2] + sh[6][3]) / (double)HW;
   float* pose_history = ctrl->pose_history;
   const int max_hist = ctrl->max_hist;
+  // guards: a problem that has stopped keeps its pose; a non-finite loss or gradient
+  // stops it at the pose it has (the last finite one); with a patience, `patience`
+  // iterations without a lower loss stop it at the pose of the lowest loss
+  const int32_t status_old = ctrl->status[v];
+  bool finite = isfinite(loss);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) finite = finite && isfinite(g[k]);
+  int32_t status = status_old;
+  const bool improved = finite && loss < ctrl->best_loss[v];
+  if (status == kTrackRan && !finite) status = kTrackNonFinite;
+  if (status == kTrackRan && !improved && adam.patience > 0 && ctrl->rising[v] + 1 >= adam.patience)
+    status = kTrackDiverged;
+  if (status != kTrackRan) {
+    // no step: the pose stays (or returns to the best one), the history repeats it
+    const bool to_best = status == kTrackDiverged && status_old == kTrackRan;
+    if (l == 0) {
+      ctrl->status[v] = status;
+      ctrl->loss[v] = loss;
+      float* loss_history = ctrl->loss_history;
+      if (loss_history && (int)it < max_hist) loss_history[(size_t)it * n_views + v] = (float)loss;
+      double* grad_history = ctrl->grad_history;
+      if (grad_history && (int)it < max_hist)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) grad_history[((size_t)it * n_views + v) * 6 + k] = g[k];
+      ctrl->iter_v[v] = it + 1;
+    }
+    if (l < 12) {
+      const double P = to_best ? ctrl->best_pose[v][l] : T_old;
+      if (to_best) {
+        ctrl->master_pose[v][l] = P;
+        pose_out[l] = (float)P;
+      }
+      if (pose_history && (int)it < max_hist) pose_history[((size_t)it * n_views + v) * 12 + l] = (float)P;
+    }
+    return;
+  }
+  if (l < 12 && improved) ctrl->best_pose[v][l] = T_old;
+  if (l == 0) {
+    if (improved) {
+      ctrl->best_loss[v] = loss;
+      ctrl->rising[v] = 0;
+    } else {
+      ctrl->rising[v] += 1;
+    }
+  }
   const double b1 = adam.beta1, b2 = adam.beta2;
   // bias corrections 1 - beta^t from running powers (t = it + 1)
   const double b1t = b1t_old * b1, b2t = b2t_old * b2;

@@ -28,9 +28,10 @@ struct ViewChunk {
   int first, count;
 };
 
-__global__ void upload_views_kernel(ViewChunk c, ViewDesc* __restrict__ dst) {
+__global__ void upload_views_kernel(ViewChunk c, ViewDesc* __restrict__ dst, Ctrl* __restrict__ ctrl) {
   const int i = threadIdx.x;
   if (i < c.count) dst[c.first + i] = c.v[i];
+  if (ctrl && i == 0) ctrl->nonfinite = 0u;
 }
 
 // One item (view, surfel); returns its tile count.
@@ -38,7 +39,8 @@ template <bool ONE_VIEW>
 __device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, int n_views, int item, float z_near,
                                            int filter, int tile_w, int tile_h, float4* __restrict__ rec,
                                            uint2* __restrict__ rect, uint32_t* __restrict__ count,
-                                           uint32_t* __restrict__ dkey, float* __restrict__ saved_pose) {
+                                           uint32_t* __restrict__ dkey, float* __restrict__ saved_pose,
+                                           Ctrl* __restrict__ ctrl) {
   // one view (tracking, single renders): a constant view index, so that its fields come
   // in through scalar loads rather than a round trip of vector loads
   const int v = ONE_VIEW ? 0 : view_of_item(views, n_views, item);
@@ -83,7 +85,11 @@ __device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, i
     M1[j] = (double)cam.fy * col[j][1] + (double)cam.cy * col[j][2];
     m[j] = col[j][2];
   }
-  bool vis = mc[2] > (double)z_near;
+  // an item whose geometry or pose is not finite is culled and flagged (NaN or an
+  // infinity in any input reaches one of these sums)
+  const double chk = mc[0] + mc[1] + mc[2] + uc[0] + uc[1] + uc[2] + vc[0] + vc[1] + vc[2] + su + sv;
+  bool finite = isfinite(chk);
+  bool vis = finite && mc[2] > (double)z_near;
   // C*_22 = 9 (m0^2 + m1^2) - m2^2 < 0  <=>  the 3-sigma disk is wholly in front of z = 0
   const double c22 = 9.0 * (m[0] * m[0] + m[1] * m[1]) - m[2] * m[2];
   vis = vis && (c22 < 0.0);
@@ -91,6 +97,15 @@ __device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, i
   uint2 rc = make_uint2(1u, 0u);
   double bx0 = 0, bx1 = -1, by0 = 0, by1 = -1, ux0 = 0, ux1 = -1, uy0 = 0, uy1 = -1;
   double ecx = 0, ecy = 0, sxx = 0, sxy = 0, syy = 0;  // the 3-sigma ellipse: centre, support matrix
+  float4 col4 = make_float4(0.f, 0.f, 0.f, 0.f);  // opacity and colour
+  if (vis) {
+    col4 = make_float4(P[(size_t)11 * n + i], P[(size_t)12 * n + i], P[(size_t)13 * n + i], P[(size_t)14 * n + i]);
+    if (!isfinite(col4.x + col4.y + col4.z + col4.w)) {
+      finite = false;
+      vis = false;
+    }
+  }
+  if (!finite) atomicOr(&ctrl->nonfinite, 1u);
   if (vis) {
     // dual conic entries needed for the box: C00, C11, C02, C12 (and C22)
     const double c00 = 9.0 * (M0[0] * M0[0] + M0[1] * M0[1]) - M0[2] * M0[2];
@@ -158,8 +173,7 @@ __device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, i
   r[1] = make_float4((float)(pcx - ux0), (float)(pcy - uy0), (float)Dt, (float)k0);
   r[2] = make_float4((float)k1, (float)P0, (float)P1, (float)Q0);
   r[3] = make_float4((float)Q1, (float)m[0], (float)m[1], (float)m[2]);
-  r[4] = make_float4(P[(size_t)11 * n + i], P[(size_t)12 * n + i], P[(size_t)13 * n + i],
-                     P[(size_t)14 * n + i]);
+  r[4] = col4;
   r[5] = make_float4((float)nn[0], (float)nn[1], (float)nn[2], (float)syy);
   r[6] = make_float4((float)(ecx - ux0), (float)(ecy - uy0), (float)sxx, (float)sxy);
   return cnt;
@@ -181,7 +195,7 @@ __global__ __launch_bounds__(kPartItems) void preprocess_kernel(
     uint32_t* __restrict__ part_vis, Ctrl* __restrict__ ctrl) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t cnt = gi < items ? preprocess_item<ONE_VIEW>(views, n_views, (int)gi, z_near, filter, tile_w,
-                                                              tile_h, rec, rect, count, dkey, saved_pose)
+                                                              tile_h, rec, rect, count, dkey, saved_pose, ctrl)
                                   : 0u;
   __shared__ uint32_t sp[kPartItems / 64], sv[kPartItems / 64];
   const uint32_t wp = wave_sum_u32(cnt), wv = wave_sum_u32(cnt != 0u ? 1u : 0u);
@@ -381,13 +395,13 @@ __global__ __launch_bounds__(256) void preprocess_bwd_group_kernel(const float* 
 }
 }  // namespace
 
-void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s) {
+void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s, Ctrl* ctrl) {
   for (int f = 0; f < vs.n_views; f += 8) {
     ViewChunk c;
     c.first = f;
     c.count = vs.n_views - f < 8 ? vs.n_views - f : 8;
     for (int k = 0; k < c.count; ++k) c.v[k] = vs.v[f + k];
-    upload_views_kernel<<<1, 64, 0, s>>>(c, dst);
+    upload_views_kernel<<<1, 64, 0, s>>>(c, dst, f == 0 ? ctrl : nullptr);
   }
 }
 

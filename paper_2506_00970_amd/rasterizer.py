@@ -115,6 +115,7 @@ class Rasterizer:
         self._ctx = ctx
         self._lib = lib
         self._last = None
+        self.track_status = None
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
@@ -395,9 +396,15 @@ class Rasterizer:
     # ----------------------------------------------------------------- tracking
     def track(self, params, camera, pose, tgt_rgb, tgt_depth, n_iters: int, lr=TRACK_LR,
               lambda_d: float = 1.0, use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8,
-              weight_decay: float = 0.0, use_graph: bool = True, history: bool = True, grads: bool = False):
+              weight_decay: float = 0.0, use_graph: bool = True, history: bool = True, grads: bool = False,
+              diverge_patience: int = 0):
         """Run ``n_iters`` tracking iterations in place on ``pose`` [12]; returns (pose, pose_hist, loss_hist),
-        and with ``grads`` also the FP64 pose gradient each step consumed, [n_iters, 6]."""
+        and with ``grads`` also the FP64 pose gradient each step consumed, [n_iters, 6].
+
+        ``diverge_patience`` > 0 stops the problem after that many iterations without a new lowest
+        loss and leaves the pose at the lowest-loss pose.  ``self.track_status`` then holds the end
+        state (0 ran, 1 stopped by that guard, 2 stopped on a non-finite loss or gradient); a
+        non-finite input or step raises Gs2dError with code ERR_NONFINITE after the pose is written."""
         cam = _camera(camera)
         H, W = cam.height, cam.width
         n = int(params.shape[1])
@@ -427,16 +434,26 @@ class Rasterizer:
         a.pose_history = ph.data_ptr() if ph is not None else None
         a.loss_history = lh.data_ptr() if lh is not None else None
         a.grad_history = gh.data_ptr() if gh is not None else None
-        _lib.check(self._lib.gs2d_track(self._ctx, ctypes.byref(a), self._stream()), self._ctx)
+        self._run_track(lambda: self._lib.gs2d_track(self._ctx, ctypes.byref(a), self._stream()), a, 1,
+                        diverge_patience)
         return (pose, ph, lh, gh) if grads else (pose, ph, lh)
+
+    def _run_track(self, call, a, n_problems: int, diverge_patience: int):
+        status = torch.full((n_problems,), -1, dtype=torch.int32, device=self.device)
+        a.diverge_patience = int(diverge_patience)
+        a.status = status.data_ptr()
+        code = call()
+        self.track_status = status.tolist() if code in (0, _lib.ERR_NONFINITE) else None
+        _lib.check(code, self._ctx)
 
     def track_batch(self, problems, n_iters: int, lr=TRACK_LR, lambda_d: float = 1.0,
                     use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8, weight_decay: float = 0.0,
-                    use_graph: bool = True, history: bool = True):
+                    use_graph: bool = True, history: bool = True, diverge_patience: int = 0):
         """Independent tracking problems stepped together in batched launches.
 
         ``problems``: sequence of (params, camera, pose [12] (updated in place), tgt_rgb, tgt_depth).
         Returns (pose_history [n_iters, P, 12], loss_history [n_iters, P]) or (None, None).
+        Guards and ``self.track_status`` (one entry per problem) as in :meth:`track`.
         """
         problems = list(problems)
         P = len(problems)
@@ -466,14 +483,15 @@ class Rasterizer:
         a.use_graph = 1 if use_graph else 0
         a.pose_history = ph.data_ptr() if ph is not None else None
         a.loss_history = lh.data_ptr() if lh is not None else None
-        _lib.check(self._lib.gs2d_track_batch(self._ctx, arr, P, ctypes.byref(a), self._stream()), self._ctx)
+        self._run_track(lambda: self._lib.gs2d_track_batch(self._ctx, arr, P, ctypes.byref(a), self._stream()),
+                        a, P, diverge_patience)
         return ph, lh
 
     # -------------------------------------------------------------- diagnostics
     def counts(self) -> dict:
         c = _lib.Counts()
         _lib.check(self._lib.gs2d_get_counts(self._ctx, ctypes.byref(c), self._stream()), self._ctx)
-        return {k: getattr(c, k) for k, _ in _lib.Counts._fields_}
+        return {k: getattr(c, k) for k, _ in _lib.Counts._fields_ if k != "pad"}
 
     def profile(self, reset: bool = False) -> dict:
         """Per-family kernel time (ms, summed) and launches, plus blend work counters."""

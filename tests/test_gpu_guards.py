@@ -1,0 +1,175 @@
+"""GPU: the guards against values that are not finite and against a diverging pose.
+
+A surfel or a pose holding NaN or an infinity is culled from the render and flagged
+(``counts()['nonfinite']``); the remaining surfels render exactly as they do without
+it.  The tracking loop stops a problem whose loss or pose gradient is not finite at
+its last finite pose (status 2, error ERR_NONFINITE), and, with a patience k, stops a
+problem after k iterations in a row without a new lowest loss and returns its pose to
+the pose of that lowest loss (status 1).  The expected stop of the divergence guard is
+derived on the host from the loss history the device recorded, by the rule itself.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_common import ROOM_CAM, dev, host, room_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gs():
+    import paper_2506_00970_amd as pkg
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def room():
+    room, pose = room_scene(100_000, seed=5, cam_seed=5)
+    return room, pose
+
+
+def _render(r, P, pose):
+    out = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    torch.cuda.synchronize()
+    return {k: host(getattr(out, k)) for k in ("rgb", "depth", "normal", "alpha")}
+
+
+def test_nonfinite_surfels_are_culled_and_flagged(gs, room):
+    scene, pose = room
+    params = scene.params.astype(np.float32).copy()
+    n = params.shape[1]
+    bad = np.array([7, 1234, n // 2, n - 1])
+    params[0, bad[0]] = np.nan          # a mean
+    params[4, bad[1]] = np.inf          # a tangent
+    params[9, bad[2]] = -np.inf         # a scale
+    params[12, bad[3]] = np.nan         # a colour
+    keep = np.setdiff1d(np.arange(n), bad)
+    r = gs.Rasterizer()
+    ref = _render(r, dev(params[:, keep]), pose)
+    assert r.counts()["nonfinite"] == 0
+    got = _render(r, dev(params), pose)
+    assert r.counts()["nonfinite"] == 1
+    for k in ref:
+        assert np.isfinite(got[k]).all(), k
+        np.testing.assert_array_equal(got[k], ref[k], err_msg=k)
+    # the backward gives the culled surfels a zero gradient and the others theirs
+    out = r.render(dev(params), ROOM_CAM, dev(pose.reshape(12)))
+    g = torch.ones_like(out.rgb)
+    d_params, d_pose = r.backward(out.generation, d_rgb=g)
+    torch.cuda.synchronize()
+    d = host(d_params)
+    assert np.isfinite(d).all() and np.isfinite(host(d_pose)).all()
+    assert (d[:, bad] == 0).all()
+    assert np.abs(d[:, keep]).sum() > 0
+    # a clean render clears the flag
+    _render(r, dev(params[:, keep]), pose)
+    assert r.counts()["nonfinite"] == 0
+
+
+def test_nonfinite_pose_culls_everything(gs, room):
+    scene, pose = room
+    r = gs.Rasterizer()
+    p = pose.reshape(12).astype(np.float32).copy()
+    p[3] = np.nan
+    got = _render(r, dev(scene.params), p)
+    assert r.counts()["nonfinite"] == 1
+    assert r.counts()["n_visible"] == 0
+    assert (got["alpha"] == 0).all() and (got["rgb"] == 0).all()
+
+
+def test_tracking_stops_on_nonfinite_loss(gs, room):
+    """A NaN target makes the first loss NaN: the problem stops at its start pose."""
+    scene, pose = room
+    r = gs.Rasterizer()
+    P = dev(scene.params)
+    t = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = t.rgb.clone(), t.depth.clone()
+    trgb.fill_(float("nan"))
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=6).reshape(12).astype(np.float32)
+    for graph in (False, True):
+        p = dev(start)
+        with pytest.raises(gs.Gs2dError) as e:
+            r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=6, use_graph=graph)
+        assert e.value.code == gs.ERR_NONFINITE
+        assert r.track_status == [2]
+        np.testing.assert_array_equal(host(p), start.astype(np.float64))
+
+
+def test_batch_tracking_flags_only_the_bad_problem(gs, room):
+    """Of two problems tracked together, the one with a NaN target stops; the other
+    runs as it does alone, bit for bit."""
+    scene, pose = room
+    r = gs.Rasterizer()
+    P = dev(scene.params)
+    t = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = t.rgb.clone(), t.depth.clone()
+    bad_rgb = torch.full_like(trgb, float("nan"))
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=7).reshape(12).astype(np.float32)
+    p0, p1 = dev(start), dev(start)
+    with pytest.raises(gs.Gs2dError) as e:
+        ph, lh = r.track_batch([(P, ROOM_CAM, p0, trgb, tdep), (P, ROOM_CAM, p1, bad_rgb, tdep)], n_iters=8)
+    assert e.value.code == gs.ERR_NONFINITE
+    assert r.track_status == [0, 2]
+    np.testing.assert_array_equal(host(p1), start.astype(np.float64))
+    p = dev(start)
+    r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=8)
+    assert r.track_status == [0]
+    np.testing.assert_array_equal(host(p0), host(p))
+
+
+def _expected_stop(loss, patience):
+    """The divergence rule on a loss history: the iteration at which the problem stops
+    (its loss is not below the lowest so far for the patience-th time in a row), and the
+    iteration whose loss is the lowest before it.  None if it never stops."""
+    best, best_it, rising = np.inf, -1, 0
+    for it, l in enumerate(loss):
+        if l < best:
+            best, best_it, rising = l, it, 0
+        else:
+            if rising + 1 >= patience:
+                return it, best_it
+            rising += 1
+    return None, best_it
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_divergence_guard_returns_to_best_pose(gs, room, graph):
+    """Learning rates far too large make the loss rise; with patience 3 the problem stops
+    and keeps the pose of its lowest loss.  The iterations before the stop are those of
+    the same run without the guard, bit for bit."""
+    scene, pose = room
+    r = gs.Rasterizer()
+    P = dev(scene.params)
+    t = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = t.rgb.clone(), t.depth.clone()
+    start = synth.perturb_pose(pose, 0.02, 1.0, seed=8).reshape(12).astype(np.float32)
+    lr = (0.3,) * 6
+    n_iters, patience = 12, 3
+    p_free = dev(start)
+    _, ph_free, lh_free = r.track(P, ROOM_CAM, p_free, trgb, tdep, n_iters=n_iters, lr=lr, use_graph=graph)
+    assert r.track_status == [0]
+    lh_free = host(lh_free)
+    ph_free = host(ph_free)
+    stop, best_it = _expected_stop(lh_free.astype(np.float32), patience)
+    assert stop is not None, f"the loss kept falling: {lh_free}"
+    p = dev(start)
+    _, ph, lh = r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=n_iters, lr=lr, use_graph=graph,
+                        diverge_patience=patience)
+    assert r.track_status == [1]
+    ph, lh = host(ph), host(lh)
+    # identical up to the stop (the loss at the stop is measured, the step is not taken)
+    np.testing.assert_array_equal(lh[: stop + 1], lh_free[: stop + 1])
+    np.testing.assert_array_equal(ph[:stop], ph_free[:stop])
+    # the pose of the lowest loss: the start pose, or the pose after step best_it - 1
+    best_pose = start.astype(np.float64) if best_it == 0 else ph_free[best_it - 1]
+    np.testing.assert_array_equal(host(p), best_pose)
+    for it in range(stop, n_iters):
+        np.testing.assert_array_equal(ph[it], best_pose)
+    # after the stop the loss is that of the best pose
+    if stop + 1 < n_iters:
+        np.testing.assert_array_equal(lh[stop + 1:], np.full(n_iters - stop - 1, lh_free[best_it]))
