@@ -65,6 +65,7 @@ extern "C" {
 #define GS2D_ERR_STATE (-5)      /* backward called without a matching forward */
 #define GS2D_ERR_UNSUPPORTED (-6)
 #define GS2D_ERR_NONFINITE (-7)    /* a surfel, pose, loss or gradient was not finite */
+#define GS2D_ERR_DEVICE_CHECK (-8) /* a device check of a GS2D_DEVICE_CHECKS build failed */
 
 /* Most views (or tracking problems) one batched call may take. */
 #define GS2D_MAX_VIEWS 32
@@ -102,7 +103,11 @@ typedef struct gs2d_counts {
   int32_t n_tiles;
   int32_t nonfinite;         /* 1: the last render met a surfel or pose with a value that is
                                 not finite; those surfels (all of a bad view) were culled */
-  int32_t pad;
+  int32_t device_checks;     /* bits of the device checks that failed since the context was
+                                created (always 0 unless built with GS2D_DEVICE_CHECKS):
+                                1 tile rectangle outside its view's grid, 2 pair tile key out
+                                of range, 4 pair slot past the capacity, 8 sorted key out of
+                                range, 16 blended tile or range invalid */
 } gs2d_counts;
 
 /* One view of a batched render: its surfels [15][n], camera, pose [12] and outputs
@@ -190,6 +195,13 @@ typedef struct gs2d_track_args {
    * pose gradient that is not finite (the pose is the last finite one). */
   int32_t* status;
 } gs2d_track_args;
+
+/* Build flags of the loaded library: GS2D_BUILD_DEVICE_CHECKS when it was compiled
+ * with GS2D_DEVICE_CHECKS (the debug build whose kernels check their indices and
+ * record failures in gs2d_counts.device_checks; gs2d_track then returns
+ * GS2D_ERR_DEVICE_CHECK). */
+#define GS2D_BUILD_DEVICE_CHECKS 1
+GS2D_API int gs2d_build_info(void);
 
 /* Fill *opt with the defaults listed above. */
 GS2D_API int gs2d_default_options(gs2d_options* opt);

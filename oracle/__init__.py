@@ -24,6 +24,11 @@ from . import loss, se3  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gs2d_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source, loaded instead
+# when GS2D_ORACLE_SANITIZED=1 (the process must preload gcc's libasan and libubsan)
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
 
 # The oracle's own copy of the method's constants.
 Z_NEAR = 0.2            # centre cull and per-pixel depth cut (metres)
@@ -34,14 +39,16 @@ T_MIN = 1e-4            # compositing stops before transmittance drops below thi
 FILTER_SCALE = 2.0      # low-pass filter term 2 |p - c|^2 (sigma^2 = 1/2 pixel^2)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with g++ into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
-                               "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle with g++ into ``oracle/liboracle.so`` (``sanitize``:
+    ``oracle/liboracle_san.so`` with ASan and UBSan)."""
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        flags = SANITIZE_FLAGS if sanitize else ["-O2"]
+        subprocess.check_call(["g++", *flags, "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Cam(ctypes.Structure):
@@ -62,7 +69,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        _lib = ctypes.CDLL(build(sanitize=os.environ.get("GS2D_ORACLE_SANITIZED") == "1"))
         P = ctypes.c_void_p
         _lib.orc_render.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 8
         _lib.orc_backward.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int] + [P] * 14

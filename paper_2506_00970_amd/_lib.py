@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgs2d.so")
+# GS2D_LIB selects another build of the library (the device-check or host-sanitizer
+# builds that build.py makes beside it)
+LIB_PATH = os.environ.get("GS2D_LIB") or os.path.join(HERE, "libgs2d.so")
 INCLUDE_DIR = os.path.join(os.path.dirname(HERE), "include")
 HEADER_PATH = os.path.join(INCLUDE_DIR, "gs2d.h")
 HEADERS = [os.path.join(INCLUDE_DIR, h) for h in ("gs2d.h", "gs2d_warm.h", "gs2d_map.h")]
@@ -23,6 +25,8 @@ ERR_CAPACITY = -4
 ERR_STATE = -5
 ERR_UNSUPPORTED = -6
 ERR_NONFINITE = -7
+ERR_DEVICE_CHECK = -8
+BUILD_DEVICE_CHECKS = 1
 ACCUMULATE = 1
 TUNE_FULL_BACKWARD = 1
 
@@ -41,7 +45,7 @@ class Options(ctypes.Structure):
 class Counts(ctypes.Structure):
     _fields_ = [("n_surfels", ctypes.c_int64), ("n_visible", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("pair_capacity", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
-                ("nonfinite", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("nonfinite", ctypes.c_int32), ("device_checks", ctypes.c_int32)]
 
 
 PROFILE_FAMILIES = 13
@@ -158,6 +162,7 @@ _SIGS = {
     "gs2d_get_profile": ([_P, ctypes.POINTER(Profile), ctypes.c_int32, _P], ctypes.c_int),
     "gs2d_last_hip_error": ([_P], ctypes.c_int),
     "gs2d_error_string": ([ctypes.c_int], ctypes.c_char_p),
+    "gs2d_build_info": ([], ctypes.c_int),
     # learned warm start (gs2d_warm.h)
     "gs2d_ws_param_count": ([], ctypes.c_int64),
     "gs2d_ws_create": ([ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int32], ctypes.c_int),

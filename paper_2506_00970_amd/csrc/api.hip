@@ -283,6 +283,7 @@ BlendArgs blend_args(gs2d_ctx* ctx) {
               (int)ctx->last_views.tiles, ctx->opt.z_near, ctx->opt.filter, ctx->opt.batch};
   a.tile_stride = tile_stride(ctx->last_views.tiles);
   a.queue = ctx->queue_on ? ctx->queue : nullptr;
+  a.check = &ctx->ctrl->check_bits;
   return a;
 }
 
@@ -403,6 +404,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
                  ctx->opt.filter, ctx->opt.batch};
     ba.tile_stride = tile_stride(vs.tiles);
     ba.queue = ctx->queue_on ? ctx->queue : nullptr;
+    ba.check = &ctx->ctrl->check_bits;
     if (tl) {
       ba.loss_part = ctx->part;
       ba.lambda_d = tl->lambda_d;
@@ -766,6 +768,7 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
         GS2D_HIP(ctx, hipStreamSynchronize(s));
       }
       if (bad) result = GS2D_ERR_NONFINITE;
+      if (ctx->host_ctrl->check_bits) result = GS2D_ERR_DEVICE_CHECK;
       break;
     }
     invalidate_graph(ctx);
@@ -1093,7 +1096,7 @@ GS2D_API int gs2d_get_counts(gs2d_ctx* ctx, gs2d_counts* out, hipStream_t stream
   out->overflow = ctx->host_ctrl->overflow ? 1 : 0;
   out->n_tiles = (int32_t)ctx->last_views.tiles;
   out->nonfinite = ctx->host_ctrl->nonfinite ? 1 : 0;
-  out->pad = 0;
+  out->device_checks = (int32_t)ctx->host_ctrl->check_bits;
   return GS2D_OK;
 }
 
@@ -1340,6 +1343,14 @@ GS2D_API int gs2d_get_profile(gs2d_ctx* ctx, gs2d_profile* out, int32_t reset, h
 
 GS2D_API int gs2d_last_hip_error(gs2d_ctx* ctx) { return ctx ? ctx->last_hip_error : 0; }
 
+GS2D_API int gs2d_build_info(void) {
+#ifdef GS2D_DEVICE_CHECKS
+  return GS2D_BUILD_DEVICE_CHECKS;
+#else
+  return 0;
+#endif
+}
+
 GS2D_API const char* gs2d_error_string(int code) {
   switch (code) {
     case GS2D_OK: return "ok";
@@ -1350,6 +1361,7 @@ GS2D_API const char* gs2d_error_string(int code) {
     case GS2D_ERR_STATE: return "backward without a matching forward (generation mismatch)";
     case GS2D_ERR_UNSUPPORTED: return "unsupported configuration";
     case GS2D_ERR_NONFINITE: return "a surfel, pose, loss or gradient was not finite";
+    case GS2D_ERR_DEVICE_CHECK: return "a device check failed (see gs2d_counts.device_checks)";
     default: return "unknown error code";
   }
 }

@@ -291,6 +291,7 @@ __device__ __forceinline__ void blend_fwd_tile(const BlendArgs& a, const int til
   const float fpx = (float)px, fpy = (float)py;
   const float bx0 = (float)wx0, by0 = (float)wy0;
   const uint2 rg = a.ranges[tile];
+  GS2D_DCHECK(a.check, tile < a.n_tiles && rg.x <= rg.y, kCheckBlendRange);
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
   FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
@@ -636,6 +637,7 @@ __device__ __forceinline__ void blend_bwd_tile(const BlendArgs& a, const int til
   const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
   int n_eval = 0, n_cov = 0;
   const uint2 rg = a.ranges[tile];
+  GS2D_DCHECK(a.check, tile < a.n_tiles && rg.x <= rg.y, kCheckBlendRange);
   const int start = (int)rg.x;
 
   const int wlast = wave_max(my_last);
@@ -783,6 +785,7 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(5))) voi
   const float xh = (fpx - cam.cx) / cam.fx, yh = (fpy - cam.cy) / cam.fy;
   const float ifx = 1.0f / cam.fx, ify = 1.0f / cam.fy;
   const uint2 rg = a.ranges[tile];
+  GS2D_DCHECK(a.check, tile < a.n_tiles && rg.x <= rg.y, kCheckBlendRange);
   const int start = (int)rg.x, end = (int)rg.y;
   prioritise(end - start);
   // the tile's depth order, in LDS when the list fits (see tile_order.h); the staged

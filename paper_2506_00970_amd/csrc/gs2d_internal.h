@@ -93,11 +93,30 @@ struct Ctrl {            // device-resident counters and tracking state
   // status (kTrackRan, kTrackDiverged, kTrackNonFinite), the iterations since the loss
   // last fell, and the lowest loss with the pose it was measured at
   uint32_t nonfinite;
+  uint32_t check_bits;   // device checks that failed (builds with GS2D_DEVICE_CHECKS; sticky)
   int32_t status[kMaxViews];
   int32_t rising[kMaxViews];
   double best_loss[kMaxViews];
   double best_pose[kMaxViews][12];
 };
+
+// Device checks of the debug build (GS2D_DEVICE_CHECKS): a failed check sets its bit
+// in Ctrl::check_bits instead of trapping; release builds compile them away.
+constexpr uint32_t kCheckRect = 1u;         // an item's tile rectangle lies inside its view's grid
+constexpr uint32_t kCheckPairKey = 2u;      // a pair's tile key is below the tile count
+constexpr uint32_t kCheckPairIndex = 4u;    // a pair's slot is below the pair capacity
+constexpr uint32_t kCheckRangeTile = 8u;    // a sorted key names a tile below the tile count
+constexpr uint32_t kCheckBlendRange = 16u;  // a blended tile exists and its range is ordered
+#ifdef GS2D_DEVICE_CHECKS
+#define GS2D_DCHECK(bits, cond, bit)                       \
+  do {                                                     \
+    if ((bits) != nullptr && !(cond)) atomicOr((bits), (bit)); \
+  } while (0)
+#else
+#define GS2D_DCHECK(bits, cond, bit) \
+  do {                               \
+  } while (0)
+#endif
 
 constexpr int32_t kTrackRan = 0;        // every iteration stepped
 constexpr int32_t kTrackDiverged = 1;   // stopped at the best pose after `patience` rising losses
@@ -267,7 +286,7 @@ int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_
 // of the same size as ids for lists longer than one workgroup's LDS.
 void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* dkey,
                        hipStream_t s);
-void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
+void launch_ranges(const uint32_t* skey, Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s);
 // The blends' work queue of a view set: tiles by descending list length (counting
 // order over 64 buckets of 32 entries; within a bucket any order), both heads zero.
@@ -311,6 +330,7 @@ struct BlendArgs {
   // queue[kQueueOrder + i] the tiles by descending list length; null: one workgroup
   // per tile
   uint32_t* queue = nullptr;
+  uint32_t* check = nullptr;  // Ctrl::check_bits (device checks)
 };
 
 constexpr int kQueueHeadFwd = 0;

@@ -147,6 +147,8 @@ __device__ inline uint32_t preprocess_item(const ViewDesc* __restrict__ views, i
       const int ty0 = (int)by0 / tile_h, ty1 = (int)by1 / tile_h;
       cnt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
       rc = make_uint2((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
+      GS2D_DCHECK(&ctrl->check_bits, 0 <= tx0 && tx0 <= tx1 && tx1 < V.tiles_x && 0 <= ty0 && ty0 <= ty1 &&
+                  ty1 < V.tiles_y, kCheckRect);
     }
   }
   count[item] = cnt;

@@ -115,6 +115,7 @@ struct PassArgs {
   uint2* ranges;          // a pass over every tile bit: block 0 writes each tile's [start, end)
   int n_tiles;            //   for tiles < n_tiles (empty ranges when *overflow != 0)
   const uint32_t* overflow;
+  uint32_t* check;        // Ctrl::check_bits (device checks)
 };
 
 template <int R>
@@ -147,6 +148,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
     if (c) *cell = 0u;  // only this block reads this column
     doff[d] = run + c;
     if (write_ranges && d < a.n_tiles) a.ranges[d] = empty ? make_uint2(0u, 0u) : make_uint2(run, run + tot[q]);
+    GS2D_DCHECK(a.check, !write_ranges || empty || d < a.n_tiles || tot[q] == 0u, kCheckRangeTile);
     run += tot[q];
   }
   __syncthreads();
@@ -304,6 +306,8 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
   for (uint32_t ty = ty0; ty <= ty1; ++ty)
     for (uint32_t tx = tx0; tx <= tx1; ++tx) {
       const uint32_t key = tbase + ty * tiles_x + tx;
+      GS2D_DCHECK(&a.ctrl->check_bits, key < (uint32_t)a.n_tiles, kCheckPairKey);
+      GS2D_DCHECK(&a.ctrl->check_bits, (int64_t)off < a.p_cap, kCheckPairIndex);
       a.pkey[off] = key;
       a.pval[off] = (uint32_t)item;
       atomicAdd(&a.hist[(size_t)(key & dmask) * a.stride + (off >> kBlockShift)], 1u);
@@ -311,15 +315,16 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
     }
 }
 
-__global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ skey,
-                                                          const Ctrl* __restrict__ ctrl, int64_t p_cap,
-                                                          uint2* __restrict__ ranges) {
+__global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __restrict__ skey, Ctrl* __restrict__ ctrl,
+                                                          int64_t p_cap, uint2* __restrict__ ranges, int n_tiles) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t np = ctrl->n_pairs;
   if (ctrl->overflow) np = 0;
   if (np > p_cap) np = p_cap;
   if (i >= np) return;
   const uint32_t t = skey[i];
+  GS2D_DCHECK(&ctrl->check_bits, t < (uint32_t)n_tiles, kCheckRangeTile);
+  (void)n_tiles;
   if (i == 0 || skey[i - 1] != t) ranges[t].x = (uint32_t)i;
   if (i == np - 1 || skey[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
@@ -455,6 +460,7 @@ int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_
       a.ranges = ranges;
       a.n_tiles = n_tiles;
       a.overflow = &ctrl->overflow;
+      a.check = &ctrl->check_bits;
     }
     launch_pass(a, grid, s);
     cur ^= 1;
@@ -463,10 +469,9 @@ int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_
   return cur;
 }
 
-void launch_ranges(const uint32_t* skey, const Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
-                   hipStream_t s) {
-  (void)n_tiles;  // cleared by the duplicate kernel
-  ranges_kernel<<<blocks_for(p_cap, 256), 256, 0, s>>>(skey, ctrl, p_cap, ranges);
+void launch_ranges(const uint32_t* skey, Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles, hipStream_t s) {
+  // the ranges were cleared by the duplicate kernel
+  ranges_kernel<<<blocks_for(p_cap, 256), 256, 0, s>>>(skey, ctrl, p_cap, ranges, n_tiles);
 }
 
 void launch_queue_order(const uint2* ranges, int n_tiles, uint32_t* queue, hipStream_t s) {

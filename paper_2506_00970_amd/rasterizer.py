@@ -8,6 +8,7 @@ device, contiguity).
 from __future__ import annotations
 
 import ctypes
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -87,6 +88,10 @@ def image_loss_noalloc(camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, tg
     return loss
 
 
+# the open rasterizers (a device-check build's test run reads their check bits)
+LIVE = weakref.WeakSet()
+
+
 class Rasterizer:
     """One libgs2d context on one device (one context per stream; not thread safe)."""
 
@@ -116,6 +121,7 @@ class Rasterizer:
         self._lib = lib
         self._last = None
         self.track_status = None
+        LIVE.add(self)
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
@@ -491,7 +497,7 @@ class Rasterizer:
     def counts(self) -> dict:
         c = _lib.Counts()
         _lib.check(self._lib.gs2d_get_counts(self._ctx, ctypes.byref(c), self._stream()), self._ctx)
-        return {k: getattr(c, k) for k, _ in _lib.Counts._fields_ if k != "pad"}
+        return {k: getattr(c, k) for k, _ in _lib.Counts._fields_}
 
     def profile(self, reset: bool = False) -> dict:
         """Per-family kernel time (ms, summed) and launches, plus blend work counters."""

@@ -20,9 +20,18 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_error_strings(lib):
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert len(_lib.error_string(code)) >= 2
+        assert _lib.error_string(code) != "unknown error code"
     assert _lib.error_string(-99) == "unknown error code"
+
+
+def test_build_info(lib):
+    """The release library has no device checks; its debug variant reports them."""
+    import os
+
+    expect = _lib.BUILD_DEVICE_CHECKS if _lib.LIB_PATH.endswith("libgs2d_checked.so") else 0
+    assert lib.gs2d_build_info() == expect, os.path.basename(_lib.LIB_PATH)
 
 
 def test_default_options(lib):
