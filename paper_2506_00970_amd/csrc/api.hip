@@ -297,8 +297,10 @@ struct TrackLoss {
   float lambda_d;
   int use_masks;
 };
+// tracking: a render of the tracking loop (the pair-overflow flag is kept from the
+// call's start, so that an overflow in any iteration restarts the call).
 int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync, bool upload = true,
-                 const TrackLoss* tl = nullptr, bool blend = true, bool order = true) {
+                 const TrackLoss* tl = nullptr, bool blend = true, bool order = true, bool tracking = false) {
   const int64_t items = vs.items;
   const int nv = vs.n_views;
   bool capturing = false;
@@ -344,7 +346,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     {
       ProfScope ps(ctx, kPre, s);
       launch_preprocess(ctx->views, nv, items, ctx->opt.z_near, ctx->opt.filter, tw, th, ctx->rec, ctx->rect,
-                        ctx->count, ctx->dkey, ctx->saved_pose, part_pairs, part_vis, ctx->ctrl, s);
+                        ctx->count, ctx->dkey, ctx->saved_pose, part_pairs, part_vis, ctx->ctrl, s, !tracking);
     }
     const bool scanned = part_scan_needed(items);
     if (scanned) {
@@ -621,7 +623,7 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
   // pose gradient; with no surfel there is no walk and the loss kernel forms the loss
   // with 256-pixel tiles each workgroup of the walk orders its own tile's list
   const bool walk_orders = ctx->opt.tile_w * ctx->opt.tile_h == 256;
-  GS2D_TRY(render_views(ctx, vs, s, false, false, nullptr, false, !walk_orders));
+  GS2D_TRY(render_views(ctx, vs, s, false, false, nullptr, false, !walk_orders, true));
   const int stride = loss_blocks(vs.max_hw);
   if (vs.items > 0) {
     BlendArgs ba = blend_args(ctx);

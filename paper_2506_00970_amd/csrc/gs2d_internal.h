@@ -231,10 +231,12 @@ void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s, Ctrl* 
 constexpr int kPartItems = 256;  // items per preprocessing block (per-block pair counts)
 // Per item: record, tile rectangle, tile count and depth key (0xFFFFFFFF for items
 // that touch no tile); per block of kPartItems items: the pair count and the count of
-// items that touch a tile.  Clears ctrl->overflow.
+// items that touch a tile.  clear_overflow: clears ctrl->overflow (a tracking loop
+// keeps it from the start of the call, so that an overflow in any iteration is seen).
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
                        int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, float* saved_pose,
-                       uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s);
+                       uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s,
+                       bool clear_overflow = true);
 // Zero the 16-float accumulator rows of the items whose tile count is nonzero.
 void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStream_t s);
 // count: the items' tile counts (rows of items with none are not read)
@@ -384,6 +386,7 @@ void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* p
                               hipStream_t s);
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
+// Resets the tracking state and the pair-overflow flag.
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
                        double* grad_history, int max_hist, hipStream_t s);
 // One AdamW + Exp step per view: pose partials are the rows of each view's tiles,
@@ -391,7 +394,6 @@ void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* po
 // loss_in_part: each view's loss is the sum of its tiles' pose_part[tile * 8 + 6]
 // (fused into the forward blend), else of its row of loss_part.
 void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, bool loss_in_part,
-                      const float* loss_part,
-                      int part_stride, AdamArgs adam, Ctrl* ctrl, hipStream_t s);
+                      const float* loss_part, int part_stride, AdamArgs adam, Ctrl* ctrl, hipStream_t s);
 
 }  // namespace gs2d

@@ -187,6 +187,7 @@ __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_view
   for (int k = t; k < n_views * 12; k += blockDim.x) ctrl->best_pose[k / 12][k % 12] = (double)views[k / 12].pose[k % 12];
   if (t == 0) {
     ctrl->iter = 0;
+    ctrl->overflow = 0u;  // kept for the whole call by the loop's renders
     ctrl->pose_history = pose_history;
     ctrl->loss_history = loss_history;
     ctrl->grad_history = grad_history;

@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kPartItems) void preprocess_kernel(
     const ViewDesc* __restrict__ views, int n_views, int64_t items, float z_near, int filter, int tile_w,
     int tile_h, float4* __restrict__ rec, uint2* __restrict__ rect, uint32_t* __restrict__ count,
     uint32_t* __restrict__ dkey, float* __restrict__ saved_pose, uint32_t* __restrict__ part_pairs,
-    uint32_t* __restrict__ part_vis, Ctrl* __restrict__ ctrl) {
+    uint32_t* __restrict__ part_vis, Ctrl* __restrict__ ctrl, int clear_overflow) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t cnt = gi < items ? preprocess_item<ONE_VIEW>(views, n_views, (int)gi, z_near, filter, tile_w,
                                                               tile_h, rec, rect, count, dkey, saved_pose, ctrl)
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kPartItems) void preprocess_kernel(
     }
     part_pairs[blockIdx.x] = bp;
     part_vis[blockIdx.x] = bv;
-    if (blockIdx.x == 0) ctrl->overflow = 0u;
+    if (blockIdx.x == 0 && clear_overflow) ctrl->overflow = 0u;
   }
 }
 
@@ -409,14 +409,15 @@ void launch_upload_views(const ViewSet& vs, ViewDesc* dst, hipStream_t s, Ctrl* 
 
 void launch_preprocess(const ViewDesc* views, int n_views, int64_t items, float z_near, int filter, int tile_w,
                        int tile_h, float4* rec, uint2* rect, uint32_t* count, uint32_t* dkey, float* saved_pose,
-                       uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s) {
+                       uint32_t* part_pairs, uint32_t* part_vis, Ctrl* ctrl, hipStream_t s, bool clear_overflow) {
   const int grid = items > 0 ? (int)((items + kPartItems - 1) / kPartItems) : 1;
+  const int co = clear_overflow ? 1 : 0;
   if (n_views == 1)
     preprocess_kernel<true><<<grid, kPartItems, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec,
-                                                        rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl);
+                                                        rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl, co);
   else
     preprocess_kernel<false><<<grid, kPartItems, 0, s>>>(views, n_views, items, z_near, filter, tile_w, tile_h, rec,
-                                                         rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl);
+                                                         rect, count, dkey, saved_pose, part_pairs, part_vis, ctrl, co);
 }
 
 void launch_clear_rows(const uint32_t* count, float* gacc, int64_t items, hipStream_t s) {

@@ -5,8 +5,8 @@
 // in ascending item order (the pairs are emitted in item order and sorted stably by
 // tile), so a stable sort by depth key alone gives that order.  One 256-thread
 // workgroup orders one list:
-//   up to 256 entries  each entry's slot is counted directly against the others
-//                      (smaller keys, and equal keys earlier in the list);
+//   up to 512 entries  each entry's slot is counted directly against the others: the
+//                      entries whose (depth key, item) is smaller, as one 64-bit key;
 //   up to kOrderMax    a stable LSD radix sort in LDS and registers, four passes of
 //                      8 bits, each a counting pass (histogram, digit offsets, ranked
 //                      rounds of 256); a digit that every entry shares is skipped;
@@ -24,6 +24,7 @@ constexpr int kBlockWaves = kBlockThreads / 64;
 constexpr int kOrderBits = 8;
 constexpr int kOrderBins = 1 << kOrderBits;
 constexpr int kOrderMax = 2048;  // lists up to this length are ordered in LDS
+constexpr int kOrderCounted = 2 * kBlockThreads;  // lists up to this length are ranked by counting
 constexpr int kOrderRounds = kOrderMax / kBlockThreads;
 // LDS words of the ordering's scratch, besides the ordered list itself: keys, per-wave
 // digit counts, digit offsets, histogram and the block scan's wave totals
@@ -112,37 +113,52 @@ __device__ inline OrderLds order_lds(uint32_t* scratch, uint32_t* sid) {
   return m;
 }
 
-// Orders ids[start .. start + L) (ascending on entry) stably by dkey[id]; every thread
-// of the 256-thread block calls it.  Lists of up to kOrderMax entries end in m.sid[0 ..
-// L) (and, with write_back, in ids as well) and the call returns true; longer lists
-// are ordered in ids (scratch: a buffer of the same size) and the call returns false.
-// Ends with a block barrier: the scratch may be reused at once.
+// Orders ids[start .. start + L) (ascending on entry) by (dkey[id], id), that is
+// stably by dkey[id]; every thread of the 256-thread block calls it.  Lists of up to
+// kOrderMax entries end in m.sid[0 .. L) (and, with write_back, in ids as well) and the
+// call returns true; longer lists are ordered in ids (scratch: a buffer of the same
+// size) and the call returns false.  Ends with a block barrier: the scratch may be
+// reused at once.
 __device__ inline bool order_list(uint32_t* __restrict__ ids, uint32_t* __restrict__ scratch,
                                   const uint32_t* __restrict__ dkey, int64_t start, int64_t L, const OrderLds& m,
                                   bool write_back) {
   constexpr int RB = kOrderBins;
   const int t = threadIdx.x;
-  if (L <= kBlockThreads) {
-    // one entry per thread, ranked by counting: the entries with a smaller key, and
-    // those with the same key earlier in the list (keys past the end read as 2^32 - 1,
-    // above every depth key)
-    const bool valid = t < L;
-    const uint32_t id = valid ? ids[start + t] : 0u;
-    const uint32_t key = valid ? dkey[id] : 0xFFFFFFFFu;
-    m.skey[t] = key;
+  if (L <= kOrderCounted) {
+    // up to two entries per thread, ranked by counting the entries whose (key, id),
+    // one 64-bit key, is smaller (ids within a list are distinct; slots past the end
+    // read as 2^64 - 1, above every entry)
+    static_assert(kOrderCounted * 2 <= kOrderMax, "the 64-bit keys fit the key scratch");
+    uint64_t* k64 = reinterpret_cast<uint64_t*>(m.skey);
+    const bool v0 = t < L, v1 = t + kBlockThreads < L;
+    const uint32_t id0 = v0 ? ids[start + t] : 0u;
+    const uint32_t id1 = v1 ? ids[start + t + kBlockThreads] : 0u;
+    const uint64_t key0 = v0 ? ((uint64_t)dkey[id0] << 32) | id0 : ~0ull;
+    const uint64_t key1 = v1 ? ((uint64_t)dkey[id1] << 32) | id1 : ~0ull;
+    k64[t] = key0;
+    k64[t + kBlockThreads] = key1;
     __syncthreads();
-    const int n4 = (int)((L + 3) & ~3);
-    uint32_t rank = 0;
-    for (int j = 0; j < n4; j += 4) {
-      const uint4 k4 = *reinterpret_cast<const uint4*>(&m.skey[j]);
-      rank += (k4.x < key) + (k4.x == key && j < t);
-      rank += (k4.y < key) + (k4.y == key && j + 1 < t);
-      rank += (k4.z < key) + (k4.z == key && j + 2 < t);
-      rank += (k4.w < key) + (k4.w == key && j + 3 < t);
+    const int n2 = (int)((L + 1) & ~1);
+    uint32_t r0 = 0, r1 = 0;
+    if (L <= kBlockThreads) {
+      for (int j = 0; j < n2; j += 2) {
+        const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(&k64[j]);
+        r0 += (q.x < key0) + (q.y < key0);
+      }
+    } else {
+      for (int j = 0; j < n2; j += 2) {
+        const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(&k64[j]);
+        r0 += (q.x < key0) + (q.y < key0);
+        r1 += (q.x < key1) + (q.y < key1);
+      }
     }
-    if (valid) {
-      m.sid[rank] = id;
-      if (write_back) ids[start + rank] = id;
+    if (v0) {
+      m.sid[r0] = id0;
+      if (write_back) ids[start + r0] = id0;
+    }
+    if (v1) {
+      m.sid[r1] = id1;
+      if (write_back) ids[start + r1] = id1;
     }
     __syncthreads();
     return true;
