@@ -580,9 +580,11 @@ def main():
         if conv_iter is None and e_t < 0.01 and e_r < 0.5:
             conv_iter = i + 1
 
-    # learned warm start: its own time, then the same iterations from the pose it chose
+    # learned warm start: the proposal's own time, then the same iterations from T_0, with
+    # the start pose as the fallback that the first iteration takes if T_0 is worse
     warm = None
     if os.path.exists(args.weights):
+        from paper_2506_00970_amd._lib import TRACK_FELL_BACK
         from paper_2506_00970_amd.warmstart import WarmStartNet
 
         log("warm-started convergence run")
@@ -591,17 +593,19 @@ def main():
         rw = Rasterizer(device=0)
         rw.track(P, cam, pose.copy_(start_dev), tgt_rgb, tgt_depth, n_iters=args.warmup, lr=LR, history=False)
         for _ in range(2):
-            net.warm_start(rw, P, cam, start_dev, tgt_rgb, tgt_depth)
+            net.propose(rw, P, cam, start_dev, tgt_rgb, tgt_depth)
         torch.cuda.synchronize()
         reps = 10
         t0 = time.perf_counter()
         for _ in range(reps):
-            w_pose, info = net.warm_start(rw, P, cam, start_dev, tgt_rgb, tgt_depth)
+            w_pose, start_loss = net.propose(rw, P, cam, start_dev, tgt_rgb, tgt_depth)
         torch.cuda.synchronize()
         warm_ms = 1e3 * (time.perf_counter() - t0) / reps
         w0 = w_pose.cpu().numpy().astype(np.float64).reshape(3, 4)
-        _, wph, _ = rw.track(P, cam, w_pose, tgt_rgb, tgt_depth, n_iters=100, lr=LR, use_graph=True)
+        _, wph, _ = rw.track(P, cam, w_pose, tgt_rgb, tgt_depth, n_iters=100, lr=LR, use_graph=True,
+                             fallback=(start_dev, start_loss))
         torch.cuda.synchronize()
+        kept = not (rw.track_status[0] & TRACK_FELL_BACK)
         whist = wph.cpu().numpy().astype(np.float64)
         wconv = None
         for i in range(whist.shape[0]):
@@ -610,7 +614,7 @@ def main():
                 wconv = i + 1
                 break
         e0 = synth.pose_error(w0, pose_gt)
-        warm = {"warm_start_ms": warm_ms, "iters_to_converge": wconv, "kept": bool(info[2].item() > 0.5),
+        warm = {"warm_start_ms": warm_ms, "iters_to_converge": wconv, "kept": kept,
                 "error_after_warm_start_cm_deg": [100 * e0[0], e0[1]]}
         del rw, net
 

@@ -153,6 +153,15 @@ typedef struct gs2d_track_problem {
   float* pose;               /* [12] in: start pose, out: final pose */
   const float* tgt_rgb;      /* [3][H][W] */
   const float* tgt_depth;    /* [H][W] */
+  /* Warm-start fallback (both device pointers, or both NULL for none): a pose [12] and
+   * its unmasked tracking loss [1] (use_masks = 0, the same lambda_d), as
+   * gs2d_warm_start_propose gives for the start pose.  The first iteration compares the
+   * unmasked loss at the problem's own start pose with it; if that is larger (or not
+   * finite), the pose becomes the fallback pose before the second iteration, with no
+   * step taken (the first entries of the histories record the rejected pose's loss and
+   * gradient, and the fallback pose); status then has GS2D_TRACK_FELL_BACK set. */
+  const float* fallback_pose;
+  const float* fallback_loss;
 } gs2d_track_problem;
 
 /* Kernel-family timings (options.profile = 1 or 2) and blend work counters (profile = 1). */
@@ -192,9 +201,15 @@ typedef struct gs2d_track_args {
   int32_t diverge_patience;
   /* [n_problems] out (device, int32) or NULL: each problem's end state, 0 every
    * iteration stepped, 1 stopped by the divergence guard, 2 stopped on a loss or
-   * pose gradient that is not finite (the pose is the last finite one). */
+   * pose gradient that is not finite (the pose is the last finite one); plus
+   * GS2D_TRACK_FELL_BACK (4) when the warm-start fallback replaced the start pose. */
   int32_t* status;
+  /* gs2d_track only: the warm-start fallback of its problem (see gs2d_track_problem);
+   * gs2d_track_batch reads each problem's own. */
+  const float* fallback_pose;
+  const float* fallback_loss;
 } gs2d_track_args;
+#define GS2D_TRACK_FELL_BACK 4
 
 /* Build flags of the loaded library: GS2D_BUILD_DEVICE_CHECKS when it was compiled
  * with GS2D_DEVICE_CHECKS (the debug build whose kernels check their indices and

@@ -109,6 +109,18 @@ GS2D_API int gs2d_warm_start(gs2d_ctx* ctx, gs2d_ws* net, const float* params, i
                              const float* tgt_depth, float lambda_d, int32_t use_masks, float* pose_out,
                              float* info, hipStream_t stream);
 
+/* The proposal half of gs2d_warm_start, for tracking that makes the fallback decision
+ * itself: render at pose_start, the residual, the network, and pose_out (device [12]) =
+ * T_0 = Exp(tau_hat) T_start; start_loss (device FP32 [1]) receives the unmasked
+ * tracking loss at T_start (lambda_d).  Pass (pose_start, start_loss) as the tracking
+ * problem's fallback (gs2d_track_problem.fallback_pose, .fallback_loss) and pose_out as
+ * its start pose: the first tracking iteration, which renders at T_0 anyway, rejects
+ * T_0 if its unmasked loss is larger, so no render at T_0 is spent here. */
+GS2D_API int gs2d_warm_start_propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n,
+                                     const gs2d_camera* camera, const float* pose_start, const float* tgt_rgb,
+                                     const float* tgt_depth, float lambda_d, float* pose_out, float* start_loss,
+                                     hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,7 @@ ERR_STATE = -5
 ERR_UNSUPPORTED = -6
 ERR_NONFINITE = -7
 ERR_DEVICE_CHECK = -8
+TRACK_FELL_BACK = 4
 BUILD_DEVICE_CHECKS = 1
 ACCUMULATE = 1
 TUNE_FULL_BACKWARD = 1
@@ -106,7 +107,8 @@ class ViewGrad(ctypes.Structure):
 
 class TrackProblem(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("n", ctypes.c_int64), ("camera", Camera), ("pose", ctypes.c_void_p),
-                ("tgt_rgb", ctypes.c_void_p), ("tgt_depth", ctypes.c_void_p)]
+                ("tgt_rgb", ctypes.c_void_p), ("tgt_depth", ctypes.c_void_p), ("fallback_pose", ctypes.c_void_p),
+                ("fallback_loss", ctypes.c_void_p)]
 
 
 class TrackArgs(ctypes.Structure):
@@ -117,7 +119,7 @@ class TrackArgs(ctypes.Structure):
                 ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float), ("use_graph", ctypes.c_int32),
                 ("pose_history", ctypes.c_void_p), ("loss_history", ctypes.c_void_p),
                 ("grad_history", ctypes.c_void_p), ("diverge_patience", ctypes.c_int32),
-                ("status", ctypes.c_void_p)]
+                ("status", ctypes.c_void_p), ("fallback_pose", ctypes.c_void_p), ("fallback_loss", ctypes.c_void_p)]
 
 
 class Gs2dError(RuntimeError):
@@ -175,6 +177,8 @@ _SIGS = {
     "gs2d_ws_adamw_step": ([_P, ctypes.POINTER(WsAdamW), _P], ctypes.c_int),
     "gs2d_warm_start": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, _P, _P, ctypes.c_float,
                          ctypes.c_int32, _P, _P, _P], ctypes.c_int),
+    "gs2d_warm_start_propose": ([_P, _P, _P, ctypes.c_int64, ctypes.POINTER(Camera), _P, _P, _P, ctypes.c_float,
+                                 _P, _P, _P], ctypes.c_int),
     # map bookkeeping (gs2d_map.h)
     "gs2d_covisibility_workspace": ([ctypes.c_int64], ctypes.c_int64),
     "gs2d_covisibility": ([_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, _P], ctypes.c_int),

@@ -653,10 +653,15 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
 int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2d_track_args* a,
                hipStream_t caller_stream) {
   if (!ctx || !probs || !a || np < 1 || np > kMaxViews || a->n_iters < 0) return GS2D_ERR_INVALID_ARG;
-  for (int k = 0; k < np; ++k)
+  Fallbacks fb{};
+  for (int k = 0; k < np; ++k) {
     if (!valid_camera(&probs[k].camera) || probs[k].n < 0 || (probs[k].n > 0 && !probs[k].params) ||
-        !probs[k].pose || !probs[k].tgt_rgb || !probs[k].tgt_depth)
+        !probs[k].pose || !probs[k].tgt_rgb || !probs[k].tgt_depth ||
+        (probs[k].fallback_pose == nullptr) != (probs[k].fallback_loss == nullptr))
       return GS2D_ERR_INVALID_ARG;
+    fb.pose[k] = probs[k].fallback_pose;
+    fb.loss[k] = probs[k].fallback_loss;
+  }
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(a->lr[k]) || a->lr[k] < 0.f) return GS2D_ERR_INVALID_ARG;
   if (!(a->beta1 >= 0.f && a->beta1 < 1.f && a->beta2 >= 0.f && a->beta2 < 1.f && a->eps > 0.f) ||
@@ -718,7 +723,7 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
     ctx->pair_fixed = true;
     launch_upload_views(vs, ctx->views, s, ctx->ctrl);
     launch_track_init(ctx->views, np, ctx->ctrl, a->pose_history, a->loss_history, a->grad_history, a->n_iters,
-                      s);
+                      s, &fb);
     int r = GS2D_OK;
     if (a->use_graph && a->n_iters > 0) {
       if (!reuse) {
@@ -765,8 +770,10 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
       bool bad = ctx->host_ctrl->nonfinite != 0u;
       for (int k = 0; k < np; ++k) bad = bad || ctx->host_ctrl->status[k] == kTrackNonFinite;
       if (a->status) {
-        GS2D_HIP(ctx, hipMemcpyAsync(a->status, ctx->ctrl->status, (size_t)np * sizeof(int32_t),
-                                     hipMemcpyDeviceToDevice, s));
+        int32_t st[kMaxViews];
+        for (int k = 0; k < np; ++k)
+          st[k] = ctx->host_ctrl->status[k] | (ctx->host_ctrl->fb_used[k] ? GS2D_TRACK_FELL_BACK : 0);
+        GS2D_HIP(ctx, hipMemcpyAsync(a->status, st, (size_t)np * sizeof(int32_t), hipMemcpyHostToDevice, s));
         GS2D_HIP(ctx, hipStreamSynchronize(s));
       }
       if (bad) result = GS2D_ERR_NONFINITE;
@@ -1076,7 +1083,8 @@ GS2D_API int gs2d_tracking_error(gs2d_ctx* ctx, const gs2d_camera* camera, const
 
 GS2D_API int gs2d_track(gs2d_ctx* ctx, const gs2d_track_args* a, hipStream_t caller_stream) {
   if (!ctx || !a) return GS2D_ERR_INVALID_ARG;
-  gs2d_track_problem p{a->params, a->n, a->camera, a->pose, a->tgt_rgb, a->tgt_depth};
+  gs2d_track_problem p{a->params,  a->n,         a->camera,        a->pose,
+                       a->tgt_rgb, a->tgt_depth, a->fallback_pose, a->fallback_loss};
   return track_impl(ctx, &p, 1, a, caller_stream);
 }
 

@@ -770,7 +770,7 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(5))) voi
   extern __shared__ float4 srec[];
   const CullLds cull{srec + (size_t)a.batch * kLdsRec, srec + (size_t)a.batch * (kLdsRec + 1),
                      srec + (size_t)a.batch * (kLdsRec + 2)};
-  __shared__ float s_red[NW][7];
+  __shared__ float s_red[NW][8];
   const int tile = (int)(((uint64_t)blockIdx.x * (uint64_t)a.tile_stride) % (uint64_t)a.n_tiles);
   const ViewDesc& V = a.views[view_of_tile(a.views, a.n_views, tile)];
   const CamF cam = V.cam;
@@ -919,35 +919,37 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(5))) voi
   // and eq:opacity_mask) and its gradient to the rendered colour and depth
   const int HW = cam.width * cam.height;
   const int p = py * cam.width + px;
-  float l = 0.f, pg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // (and the same sum without the masks, which the warm start's fallback compares)
+  float l = 0.f, lu = 0.f, pg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (inside) {
     bool mk = true;
     if (a.use_masks) {
       const float ndr = s.n0;
       mk = (ndr > 0.0f) && (s.co > kOpacityMask);
     }
+    const float d0 = s.cr - V.tgt_rgb[p];
+    const float d1 = s.cg - V.tgt_rgb[HW + p];
+    const float d2 = s.cb - V.tgt_rgb[2 * HW + p];
+    const float dd = s.cd - V.tgt_depth[p];
+    lu = fabsf(d0) + fabsf(d1) + fabsf(d2) + a.lambda_d * fabsf(dd);
     if (mk) {
       const float inv = 1.0f / (float)HW;
-      const float d0 = s.cr - V.tgt_rgb[p];
-      const float d1 = s.cg - V.tgt_rgb[HW + p];
-      const float d2 = s.cb - V.tgt_rgb[2 * HW + p];
-      const float dd = s.cd - V.tgt_depth[p];
       auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
-      l = fabsf(d0) + fabsf(d1) + fabsf(d2) + a.lambda_d * fabsf(dd);
+      l = lu;
       const float gr = sgn(d0) * inv, gg = sgn(d1) * inv, gb = sgn(d2) * inv, gd = a.lambda_d * sgn(dd) * inv;
 #pragma unroll
       for (int k = 0; k < 6; ++k) pg[k] = gr * Ar[k] + gg * Ag[k] + gb * Ab[k] + gd * AD[k];
     }
   }
-  // tile sums: pose gradient in slots 0-5, loss in slot 6
-  float v7[7] = {pg[0], pg[1], pg[2], pg[3], pg[4], pg[5], l};
+  // tile sums: pose gradient in slots 0-5, loss in slot 6, unmasked loss in slot 7
+  float v8[8] = {pg[0], pg[1], pg[2], pg[3], pg[4], pg[5], l, lu};
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const float sum = wave_sum(v7[k]);
+  for (int k = 0; k < 8; ++k) {
+    const float sum = wave_sum(v8[k]);
     if (lane == 0) s_red[wave][k] = sum;
   }
   __syncthreads();
-  if (t < 7) {
+  if (t < 8) {
     float sum = 0.f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) sum += s_red[w][t];

@@ -98,6 +98,12 @@ struct Ctrl {            // device-resident counters and tracking state
   int32_t rising[kMaxViews];
   double best_loss[kMaxViews];
   double best_pose[kMaxViews][12];
+  // warm-start fallback per tracking problem: armed, the pose and unmasked loss to fall
+  // back to, and whether the first iteration did
+  int32_t fb_armed[kMaxViews];
+  int32_t fb_used[kMaxViews];
+  double fb_loss[kMaxViews];
+  double fb_pose[kMaxViews][12];
 };
 
 // Device checks of the debug build (GS2D_DEVICE_CHECKS): a failed check sets its bit
@@ -386,9 +392,15 @@ void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* p
                               hipStream_t s);
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
-// Resets the tracking state and the pair-overflow flag.
+// Resets the tracking state and the pair-overflow flag.  fallback (nullable): per view
+// the device pose [12] and unmasked loss [1] of the warm start's fallback (either null:
+// none for that view).
+struct Fallbacks {
+  const float* pose[kMaxViews];
+  const float* loss[kMaxViews];
+};
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
-                       double* grad_history, int max_hist, hipStream_t s);
+                       double* grad_history, int max_hist, hipStream_t s, const Fallbacks* fallback = nullptr);
 // One AdamW + Exp step per view: pose partials are the rows of each view's tiles,
 // loss partials part[v * part_stride + block].
 // loss_in_part: each view's loss is the sum of its tiles' pose_part[tile * 8 + 6]

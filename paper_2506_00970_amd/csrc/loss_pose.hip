@@ -167,8 +167,18 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_pose_views_kernel(const
 
 __global__ void track_init_kernel(const ViewDesc* __restrict__ views, int n_views, Ctrl* __restrict__ ctrl,
                                   float* pose_history, float* loss_history, double* grad_history,
-                                  int max_hist) {
+                                  int max_hist, Fallbacks fb) {
   const int t = threadIdx.x;
+  for (int k = t; k < n_views; k += blockDim.x) {
+    const bool armed = fb.pose[k] != nullptr && fb.loss[k] != nullptr;
+    ctrl->fb_armed[k] = armed ? 1 : 0;
+    ctrl->fb_used[k] = 0;
+    ctrl->fb_loss[k] = armed ? (double)fb.loss[k][0] : 0.0;
+  }
+  for (int k = t; k < n_views * 12; k += blockDim.x) {
+    const float* fp = fb.pose[k / 12];
+    ctrl->fb_pose[k / 12][k % 12] = fp ? (double)fp[k % 12] : 0.0;
+  }
   for (int k = t; k < n_views * 12; k += blockDim.x)
     ctrl->master_pose[k / 12][k % 12] = (double)views[k / 12].pose[k % 12];
   for (int k = t; k < n_views * 6; k += blockDim.x) {
@@ -334,8 +344,10 @@ void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* p
 }
 
 void launch_track_init(const ViewDesc* views, int n_views, Ctrl* ctrl, float* pose_history, float* loss_history,
-                       double* grad_history, int max_hist, hipStream_t s) {
-  track_init_kernel<<<1, 256, 0, s>>>(views, n_views, ctrl, pose_history, loss_history, grad_history, max_hist);
+                       double* grad_history, int max_hist, hipStream_t s, const Fallbacks* fallback) {
+  Fallbacks fb{};
+  if (fallback) fb = *fallback;
+  track_init_kernel<<<1, 256, 0, s>>>(views, n_views, ctrl, pose_history, loss_history, grad_history, max_hist, fb);
 }
 
 void launch_pose_step(const ViewDesc* views, int n_views, const float* pose_part, bool loss_in_part,

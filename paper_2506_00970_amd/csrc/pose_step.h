@@ -60,7 +60,7 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
                                       const float* __restrict__ pose_part, int loss_in_part,
                                       const float* __restrict__ loss_part, int part_stride, const AdamArgs& adam,
                                       Ctrl* __restrict__ ctrl) {
-  __shared__ double sh[7][4];
+  __shared__ double sh[8][4];
   const ViewDesc& V = views[v];
   const int HW = V.cam.width * V.cam.height;
   const int rows = V.tiles_x * V.tiles_y;
@@ -76,11 +76,12 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
   const double b1t_old = ctrl->adam_b1t[v], b2t_old = ctrl->adam_b2t[v];
   const uint32_t it = ctrl->iter_v[v];
   float* const pose_out = V.pose;
-  // the six pose sums and the loss in one pass and one block reduction (fixed order)
+  // the six pose sums, the loss and the unmasked loss in one pass and one block
+  // reduction (fixed order)
   // Rows are read kRowsInFlight per thread at a time (two 16-byte loads each), all
   // issued before the first add; each thread adds its rows in ascending order.
   constexpr int kRowsInFlight = 8;
-  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const float4* pp4 = reinterpret_cast<const float4*>(pp);
   for (int i0 = l; i0 < rows; i0 += (int)blockDim.x * kRowsInFlight) {
     float4 lo[kRowsInFlight], hi[kRowsInFlight];
@@ -99,7 +100,10 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
       acc[3] += (double)lo[u].w;
       acc[4] += (double)hi[u].x;
       acc[5] += (double)hi[u].y;
-      if (loss_in_part) acc[6] += (double)hi[u].z;
+      if (loss_in_part) {
+        acc[6] += (double)hi[u].z;
+        acc[7] += (double)hi[u].w;
+      }
     }
   }
   if (!loss_in_part) {
@@ -108,7 +112,7 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
   }
   const int w = l / 64;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < 8; ++k) {
     const double s = wave_sum_d(acc[k]);
     if (l % 64 == 0) sh[k][w] = s;
   }
@@ -120,6 +124,32 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
   const double loss = (sh[6][0] + sh[6][1] + sh[6][2] + sh[6][3]) / (double)HW;
   float* pose_history = ctrl->pose_history;
   const int max_hist = ctrl->max_hist;
+  // warm-start fallback: at the first iteration, a start pose whose unmasked loss is
+  // above the fallback's (or not finite) gives way to the fallback pose, without a step;
+  // the histories record the rejected pose's loss and gradient and the fallback pose
+  if (it == 0 && loss_in_part && ctrl->fb_armed[v]) {
+    const double loss_un = (sh[7][0] + sh[7][1] + sh[7][2] + sh[7][3]) / (double)HW;
+    if (!(loss_un <= ctrl->fb_loss[v])) {
+      if (l == 0) {
+        ctrl->fb_used[v] = 1;
+        ctrl->loss[v] = loss;
+        float* loss_history = ctrl->loss_history;
+        if (loss_history && max_hist > 0) loss_history[v] = (float)loss;
+        double* grad_history = ctrl->grad_history;
+        if (grad_history && max_hist > 0)
+#pragma unroll
+          for (int k = 0; k < 6; ++k) grad_history[(size_t)v * 6 + k] = g[k];
+        ctrl->iter_v[v] = 1;
+      }
+      if (l < 12) {
+        const double P = ctrl->fb_pose[v][l];
+        ctrl->master_pose[v][l] = P;
+        pose_out[l] = (float)P;
+        if (pose_history && max_hist > 0) pose_history[(size_t)v * 12 + l] = (float)P;
+      }
+      return;
+    }
+  }
   // guards: a problem that has stopped keeps its pose; a non-finite loss or gradient
   // stops it at the pose it has (the last finite one); with a patience, `patience`
   // iterations without a lower loss stop it at the pose of the lowest loss

@@ -795,10 +795,17 @@ GS2D_API int gs2d_ws_adamw_step(gs2d_ws* net, const gs2d_ws_adamw* o, hipStream_
   return GS2D_OK;
 }
 
-GS2D_API int gs2d_warm_start(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const gs2d_camera* camera,
-                             const float* pose_start, const float* tgt_rgb, const float* tgt_depth, float lambda_d,
-                             int32_t use_masks, float* pose_out, float* info, hipStream_t s) {
-  if (!ctx || !net || !camera || !pose_start || !tgt_rgb || !tgt_depth || !pose_out || (n > 0 && !params))
+}  // extern "C"
+
+namespace {
+
+// The render at T_start, its tracking loss (into losses[0]), the residual, the network
+// and T_0 = Exp(tau_hat) T_start (into pose0).  rgb .. alpha: the network's image
+// workspace, sized here.
+int propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const gs2d_camera* camera,
+            const float* pose_start, const float* tgt_rgb, const float* tgt_depth, float lambda_d, int32_t use_masks,
+            float* pose0, float* losses, hipStream_t s) {
+  if (!ctx || !net || !camera || !pose_start || !tgt_rgb || !tgt_depth || !pose0 || !losses || (n > 0 && !params))
     return GS2D_ERR_INVALID_ARG;
   const int W = camera->width, H = camera->height;
   if (W <= 0 || H <= 0) return GS2D_ERR_INVALID_ARG;
@@ -821,8 +828,6 @@ GS2D_API int gs2d_warm_start(gs2d_ctx* ctx, gs2d_ws* net, const float* params, i
   float* input = net->wsf;
   float* out = input + act_size(-1);
   float* tau = out + 8;
-  float* pose0 = tau + 8;
-  float* losses = pose0 + 12;
   uint32_t gen = 0;
   // loss at the start pose and the network's input
   WS_TRY(gs2d_render(ctx, params, n, camera, pose_start, rgb, depth, normal, alpha, &gen, s));
@@ -832,6 +837,39 @@ GS2D_API int gs2d_warm_start(gs2d_ctx* ctx, gs2d_ws* net, const float* params, i
   WS_TRY(gs2d_ws_forward(net, input, 1, out, s));
   denormalise_kernel<<<1, 64, 0, s>>>(out, tau);
   WS_TRY(gs2d_pose_exp(ctx, tau, pose_start, pose0, s));
+  return GS2D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+GS2D_API int gs2d_warm_start_propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n,
+                                     const gs2d_camera* camera, const float* pose_start, const float* tgt_rgb,
+                                     const float* tgt_depth, float lambda_d, float* pose_out, float* start_loss,
+                                     hipStream_t s) {
+  if (!start_loss) return GS2D_ERR_INVALID_ARG;
+  WS_TRY(propose(ctx, net, params, n, camera, pose_start, tgt_rgb, tgt_depth, lambda_d, 0, pose_out, start_loss,
+                 s));
+  WS_HIP(hipGetLastError());
+  return GS2D_OK;
+}
+
+GS2D_API int gs2d_warm_start(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const gs2d_camera* camera,
+                             const float* pose_start, const float* tgt_rgb, const float* tgt_depth, float lambda_d,
+                             int32_t use_masks, float* pose_out, float* info, hipStream_t s) {
+  if (!net || !pose_out) return GS2D_ERR_INVALID_ARG;
+  float* pose0 = net->wsf + act_size(-1) + 16;
+  float* losses = pose0 + 12;
+  WS_TRY(propose(ctx, net, params, n, camera, pose_start, tgt_rgb, tgt_depth, lambda_d, use_masks, pose0, losses,
+                 s));
+  const int W = camera->width, H = camera->height;
+  const int64_t hw = (int64_t)W * H;
+  float* rgb = net->img;
+  float* depth = rgb + 3 * hw;
+  float* normal = rgb + 4 * hw;
+  float* alpha = rgb + 7 * hw;
+  uint32_t gen = 0;
   // loss at T_0, then the choice
   WS_TRY(gs2d_render(ctx, params, n, camera, pose0, rgb, depth, normal, alpha, &gen, s));
   WS_TRY(gs2d_tracking_loss(ctx, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks,

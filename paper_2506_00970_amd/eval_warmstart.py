@@ -21,6 +21,7 @@ import torch
 
 import synth
 
+from ._lib import TRACK_FELL_BACK
 from .rasterizer import Rasterizer
 from .warmstart import WarmStartNet
 
@@ -63,14 +64,15 @@ def run_case(rast: Rasterizer, net: WarmStartNet, seed: int, iters: int, n_surfe
     pose = s.clone()
     _, ph, _ = rast.track(P, CAMERA, pose, trgb, tdep, iters)
     plain = first_converged(ph.cpu().numpy(), gt)
-    # warm
-    w_pose, info = net.warm_start(rast, P, CAMERA, s, trgb, tdep)
+    # warm: the proposal, then tracking from T_0 with the start pose as its fallback
+    w_pose, start_loss = net.propose(rast, P, CAMERA, s, trgb, tdep)
     w0 = w_pose.clone()
-    _, wh, _ = rast.track(P, CAMERA, w_pose, trgb, tdep, iters)
+    _, wh, _ = rast.track(P, CAMERA, w_pose, trgb, tdep, iters, fallback=(s, start_loss))
+    kept = not (rast.track_status[0] & TRACK_FELL_BACK)
     warm = first_converged(wh.cpu().numpy(), gt)
     err0 = synth.pose_error(start, gt)
     errw = synth.pose_error(w0.cpu().numpy().reshape(3, 4), gt)
-    return {"seed": seed, "plain_iters": plain, "warm_iters": warm, "kept": bool(info[2].item() > 0.5),
+    return {"seed": seed, "plain_iters": plain, "warm_iters": warm, "kept": kept,
             "start_err_cm_deg": [err0[0] * 100, err0[1]], "warm_err_cm_deg": [errw[0] * 100, errw[1]],
             "P": P, "trgb": trgb, "tdep": tdep, "start": s}
 
@@ -94,7 +96,7 @@ def main(argv=None):
             pose = c["start"].clone()
             ms_iter = time_ms(lambda: rast.track(c["P"], CAMERA, pose.copy_(c["start"]), c["trgb"], c["tdep"],
                                                  a.iters, history=False)) / a.iters
-            ms_warm = time_ms(lambda: net.warm_start(rast, c["P"], CAMERA, c["start"], c["trgb"], c["tdep"]))
+            ms_warm = time_ms(lambda: net.propose(rast, c["P"], CAMERA, c["start"], c["trgb"], c["tdep"]))
         for k in ("P", "trgb", "tdep", "start"):
             del c[k]
         cases.append(c)

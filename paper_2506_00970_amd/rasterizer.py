@@ -403,14 +403,18 @@ class Rasterizer:
     def track(self, params, camera, pose, tgt_rgb, tgt_depth, n_iters: int, lr=TRACK_LR,
               lambda_d: float = 1.0, use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8,
               weight_decay: float = 0.0, use_graph: bool = True, history: bool = True, grads: bool = False,
-              diverge_patience: int = 0):
+              diverge_patience: int = 0, fallback=None):
         """Run ``n_iters`` tracking iterations in place on ``pose`` [12]; returns (pose, pose_hist, loss_hist),
         and with ``grads`` also the FP64 pose gradient each step consumed, [n_iters, 6].
 
         ``diverge_patience`` > 0 stops the problem after that many iterations without a new lowest
         loss and leaves the pose at the lowest-loss pose.  ``self.track_status`` then holds the end
         state (0 ran, 1 stopped by that guard, 2 stopped on a non-finite loss or gradient); a
-        non-finite input or step raises Gs2dError with code ERR_NONFINITE after the pose is written."""
+        non-finite input or step raises Gs2dError with code ERR_NONFINITE after the pose is written.
+
+        ``fallback`` = (pose [12], unmasked loss [1]) (device tensors, as WarmStartNet.propose gives
+        for the start pose): the first iteration replaces the start pose by that pose if its own
+        unmasked loss is larger; ``track_status`` then has TRACK_FELL_BACK (4) set."""
         cam = _camera(camera)
         H, W = cam.height, cam.width
         n = int(params.shape[1])
@@ -440,6 +444,11 @@ class Rasterizer:
         a.pose_history = ph.data_ptr() if ph is not None else None
         a.loss_history = lh.data_ptr() if lh is not None else None
         a.grad_history = gh.data_ptr() if gh is not None else None
+        if fallback is not None:
+            fp, fl = fallback
+            _check_tensor(fp, "fallback pose", (12,), self.device)
+            _check_tensor(fl, "fallback loss", (1,), self.device)
+            a.fallback_pose, a.fallback_loss = fp.data_ptr(), fl.data_ptr()
         self._run_track(lambda: self._lib.gs2d_track(self._ctx, ctypes.byref(a), self._stream()), a, 1,
                         diverge_patience)
         return (pose, ph, lh, gh) if grads else (pose, ph, lh)
@@ -454,12 +463,13 @@ class Rasterizer:
 
     def track_batch(self, problems, n_iters: int, lr=TRACK_LR, lambda_d: float = 1.0,
                     use_masks: bool = True, betas=(0.9, 0.999), eps: float = 1e-8, weight_decay: float = 0.0,
-                    use_graph: bool = True, history: bool = True, diverge_patience: int = 0):
+                    use_graph: bool = True, history: bool = True, diverge_patience: int = 0, fallbacks=None):
         """Independent tracking problems stepped together in batched launches.
 
         ``problems``: sequence of (params, camera, pose [12] (updated in place), tgt_rgb, tgt_depth).
         Returns (pose_history [n_iters, P, 12], loss_history [n_iters, P]) or (None, None).
-        Guards and ``self.track_status`` (one entry per problem) as in :meth:`track`.
+        Guards and ``self.track_status`` (one entry per problem) as in :meth:`track`; ``fallbacks``:
+        None or one (pose, loss) pair or None per problem, as ``fallback`` of :meth:`track`.
         """
         problems = list(problems)
         P = len(problems)
@@ -473,8 +483,13 @@ class Rasterizer:
             _check_tensor(pose, "pose", (12,), self.device)
             _check_tensor(tgt_rgb, "tgt_rgb", (3, cam.height, cam.width), self.device)
             _check_tensor(tgt_depth, "tgt_depth", (cam.height, cam.width), self.device)
+            fb = fallbacks[k] if fallbacks is not None else None
+            if fb is not None:
+                _check_tensor(fb[0], "fallback pose", (12,), self.device)
+                _check_tensor(fb[1], "fallback loss", (1,), self.device)
             arr[k] = _lib.TrackProblem(params.data_ptr(), n, cam, pose.data_ptr(), tgt_rgb.data_ptr(),
-                                       tgt_depth.data_ptr())
+                                       tgt_depth.data_ptr(), fb[0].data_ptr() if fb is not None else None,
+                                       fb[1].data_ptr() if fb is not None else None)
         ph = torch.zeros((max(n_iters, 1), P, 12), dtype=torch.float32, device=self.device) if history else None
         lh = torch.zeros((max(n_iters, 1), P), dtype=torch.float32, device=self.device) if history else None
         a = _lib.TrackArgs()

@@ -128,6 +128,26 @@ class WarmStartNet:
                                              _dev_ptr(info), self._stream()), rast._ctx)
         return pose, info
 
+    def propose(self, rast: Rasterizer, params, camera, pose_start, tgt_rgb, tgt_depth, lambda_d: float = 1.0):
+        """(T_0 [12], unmasked tracking loss at T_start [1]): the warm start without its
+        render at T_0.  Track from T_0 with ``fallback=(pose_start, loss)``; the first
+        tracking iteration then falls back to T_start if T_0 is worse."""
+        if rast.device != self.device:
+            raise ValueError("the rasterizer and the network must share a device")
+        cam = _camera(camera)
+        n = params.shape[1]
+        _check_tensor(params, "params", (15, n), self.device)
+        _check_tensor(pose_start, "pose_start", (12,), self.device)
+        _check_tensor(tgt_rgb, "tgt_rgb", (3, cam.height, cam.width), self.device)
+        _check_tensor(tgt_depth, "tgt_depth", (cam.height, cam.width), self.device)
+        pose = torch.empty(12, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _lib.check(self._lib.gs2d_warm_start_propose(rast._ctx, self._net, _dev_ptr(params), n, ctypes.byref(cam),
+                                                     _dev_ptr(pose_start), _dev_ptr(tgt_rgb), _dev_ptr(tgt_depth),
+                                                     float(lambda_d), _dev_ptr(pose), _dev_ptr(loss),
+                                                     self._stream()), rast._ctx)
+        return pose, loss
+
 
 def denormalise(out: torch.Tensor) -> torch.Tensor:
     """Network output -> twist (rho in metres, phi in radians)."""

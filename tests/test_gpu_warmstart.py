@@ -192,6 +192,86 @@ def test_warm_start_choice(wsmod):
     np.testing.assert_array_equal(host(chosen), start.reshape(12))
 
 
+def test_propose_matches_warm_start(wsmod):
+    """The proposal half gives the same T_0 as the full warm start and the same unmasked
+    loss at T_start (info[0] with use_masks = 0)."""
+    from paper_2506_00970_amd import Rasterizer
+    from tests.gpu_common import ROOM_CAM, room_scene
+
+    room, pose = room_scene(100_000, seed=3, cam_seed=3)
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=4)
+    r = Rasterizer()
+    P = dev(room.params)
+    tgt = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = tgt.rgb.clone(), tgt.depth.clone()
+    net = wsmod.WarmStartNet(max_batch=1)
+    net.set_params(dev(synth.init_params(5) * 0.3))
+    ps = dev(start.reshape(12))
+    t0, loss0 = net.propose(r, P, ROOM_CAM, ps, trgb, tdep)
+    chosen, info = net.warm_start(r, P, ROOM_CAM, ps, trgb, tdep)
+    info = host(info)
+    assert host(loss0)[0] == info[0]
+    if info[2] == 1.0:
+        np.testing.assert_array_equal(host(t0), host(chosen))
+
+
+def _fallback_case():
+    from paper_2506_00970_amd import Rasterizer
+    from tests.gpu_common import ROOM_CAM, room_scene
+
+    room, pose = room_scene(100_000, seed=6, cam_seed=6)
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=7).reshape(12).astype(np.float32)
+    r = Rasterizer()
+    P = dev(room.params)
+    tgt = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = tgt.rgb.clone(), tgt.depth.clone()
+    s = r.render(P, ROOM_CAM, dev(start))
+    loss_start, _, _ = r.tracking_loss(ROOM_CAM, s.rgb, s.depth, s.normal, s.alpha, trgb, tdep, use_masks=False)
+    return r, P, pose, start, trgb, tdep, loss_start.reshape(1).clone()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_tracking_fallback_rejects_a_worse_start(wsmod, graph):
+    """A start pose 20 deg off, with the 5 cm / 3 deg pose as its fallback: the first
+    iteration measures the worse unmasked loss and takes the fallback pose without a
+    step, and every later iteration is plain tracking from the fallback pose, bit for
+    bit, one iteration late."""
+    from paper_2506_00970_amd import _lib
+    from tests.gpu_common import ROOM_CAM
+
+    r, P, pose, start, trgb, tdep, loss_start = _fallback_case()
+    bad = synth.perturb_pose(start.reshape(3, 4).astype(np.float64), 0.3, 20.0, seed=8).reshape(12)
+    fb_pose = dev(start)
+    p = dev(bad)
+    _, ph, lh = r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=12, use_graph=graph, fallback=(fb_pose, loss_start))
+    assert r.track_status == [_lib.TRACK_FELL_BACK]
+    q = dev(start)
+    _, ph0, lh0 = r.track(P, ROOM_CAM, q, trgb, tdep, n_iters=11, use_graph=graph)
+    assert r.track_status == [0]
+    ph, lh, ph0, lh0 = host(ph), host(lh), host(ph0), host(lh0)
+    np.testing.assert_array_equal(ph[0], start.astype(np.float64))
+    np.testing.assert_array_equal(ph[1:], ph0)
+    np.testing.assert_array_equal(lh[1:], lh0)
+    np.testing.assert_array_equal(host(p), host(q))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_tracking_fallback_keeps_a_better_start(wsmod, graph):
+    """The ground-truth pose as the start, with the perturbed pose as the fallback: its
+    unmasked loss is lower, so the run is plain tracking from it, bit for bit."""
+    from tests.gpu_common import ROOM_CAM
+
+    r, P, pose, start, trgb, tdep, loss_start = _fallback_case()
+    good = pose.reshape(12).astype(np.float32)
+    p = dev(good)
+    _, ph, lh = r.track(P, ROOM_CAM, p, trgb, tdep, n_iters=8, use_graph=graph, fallback=(dev(start), loss_start))
+    assert r.track_status == [0]
+    q = dev(good)
+    _, ph0, lh0 = r.track(P, ROOM_CAM, q, trgb, tdep, n_iters=8, use_graph=graph)
+    np.testing.assert_array_equal(host(ph), host(ph0))
+    np.testing.assert_array_equal(host(lh), host(lh0))
+
+
 @pytest.fixture(scope="module")
 def held_out(wsmod):
     """Plain and warm-started tracking (100 iterations) on held-out rooms 0-19 with the
@@ -214,7 +294,7 @@ def held_out(wsmod):
             pose = c["start"].clone()
             ms_iter = time_ms(lambda: r.track(c["P"], CAMERA, pose.copy_(c["start"]), c["trgb"], c["tdep"], 100,
                                               history=False)) / 100
-            ms_warm = time_ms(lambda: net.warm_start(r, c["P"], CAMERA, c["start"], c["trgb"], c["tdep"]))
+            ms_warm = time_ms(lambda: net.propose(r, c["P"], CAMERA, c["start"], c["trgb"], c["tdep"]))
         out.append((c["plain_iters"], c["warm_iters"]))
         print(seed, "plain", c["plain_iters"], "warm", c["warm_iters"], "after warm start", c["warm_err_cm_deg"])
     print("ms per iteration", ms_iter, "warm start ms", ms_warm)
