@@ -136,9 +136,13 @@ def _ray_plane(s, x, y):
 
 @pytest.mark.parametrize("seed", range(4))
 def test_tilted_surfel_ray_plane(oracle_mod, seed):
-    """The homography intersection equals an explicit ray-plane intersection."""
+    """The homography intersection equals an explicit ray-plane intersection (odd
+    seeds with f_x != f_y and an off-centre principal point, so that the two focal
+    lengths and the two principal-point coordinates cannot stand in for each other)."""
     g = np.random.default_rng(100 + seed)
     s = synth.single_surfel(scale=0.25, opacity=0.9)
+    if seed % 2:
+        s.camera = synth.Camera(64, 48, 56.0, 71.0, 30.5, 25.25)
     rot = Rotation.from_rotvec(g.normal(size=3) * 0.6).as_matrix()
     s.params[3:6, 0] = (rot @ np.array([1.0, 0, 0])).astype(np.float32)
     s.params[6:9, 0] = (rot @ np.array([0, 1.0, 0])).astype(np.float32)
