@@ -138,18 +138,29 @@ __device__ inline bool order_list(uint32_t* __restrict__ ids, uint32_t* __restri
     k64[t] = key0;
     k64[t + kBlockThreads] = key1;
     __syncthreads();
-    const int n2 = (int)((L + 1) & ~1);
+    // 16 keys per trip (every slot below 512 holds a key or 2^64 - 1), the eight LDS
+    // reads of a trip issued before its compares: the loop is bound by LDS latency
+    constexpr int kTrip = 16;
+    const int n16 = (int)((L + kTrip - 1) & ~(int64_t)(kTrip - 1));
     uint32_t r0 = 0, r1 = 0;
     if (L <= kBlockThreads) {
-      for (int j = 0; j < n2; j += 2) {
-        const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(&k64[j]);
-        r0 += (q.x < key0) + (q.y < key0);
+      for (int j = 0; j < n16; j += kTrip) {
+        ulonglong2 q[kTrip / 2];
+#pragma unroll
+        for (int u = 0; u < kTrip / 2; ++u) q[u] = *reinterpret_cast<const ulonglong2*>(&k64[j + 2 * u]);
+#pragma unroll
+        for (int u = 0; u < kTrip / 2; ++u) r0 += (q[u].x < key0) + (q[u].y < key0);
       }
     } else {
-      for (int j = 0; j < n2; j += 2) {
-        const ulonglong2 q = *reinterpret_cast<const ulonglong2*>(&k64[j]);
-        r0 += (q.x < key0) + (q.y < key0);
-        r1 += (q.x < key1) + (q.y < key1);
+      for (int j = 0; j < n16; j += kTrip) {
+        ulonglong2 q[kTrip / 2];
+#pragma unroll
+        for (int u = 0; u < kTrip / 2; ++u) q[u] = *reinterpret_cast<const ulonglong2*>(&k64[j + 2 * u]);
+#pragma unroll
+        for (int u = 0; u < kTrip / 2; ++u) {
+          r0 += (q[u].x < key0) + (q[u].y < key0);
+          r1 += (q[u].x < key1) + (q[u].y < key1);
+        }
       }
     }
     if (v0) {
