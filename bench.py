@@ -48,6 +48,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def rooms_summary(warm, conv_iter, ms_step):
+    """Median ms to converge over the bench room and the extra rooms (unconverged runs
+    count 101 iterations), plain and warm-started (proposal time included)."""
+    import numpy as np
+
+    rooms = warm.get("more_rooms")
+    if not rooms:
+        return {}
+    plain = [conv_iter or 101] + [c["plain_iters"] or 101 for c in rooms]
+    warm_it = [warm["iters_to_converge"] or 101] + [c["warm_iters"] or 101 for c in rooms]
+    return {"rooms": len(plain), "median_ms_to_converge_plain": float(np.median(plain)) * ms_step,
+            "median_ms_to_converge_warm": warm["warm_start_ms"] + float(np.median(warm_it)) * ms_step,
+            "warm_faster_in": int(sum(warm["warm_start_ms"] + w * ms_step < p * ms_step
+                                      for p, w in zip(plain, warm_it)))}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -514,6 +530,8 @@ def main():
     ap.add_argument("--n", type=int, default=300_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--held-out-rooms", type=int, default=9,
+                    help="rooms after the bench room on which plain and warm-started convergence are also measured")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--weights", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                       "paper_2506_00970_amd", "weights", "warm_start.npy"),
@@ -616,6 +634,16 @@ def main():
         e0 = synth.pose_error(w0, pose_gt)
         warm = {"warm_start_ms": warm_ms, "iters_to_converge": wconv, "kept": kept,
                 "error_after_warm_start_cm_deg": [100 * e0[0], e0[1]]}
+        # one room says little about a learned proposal: iterations to converge on the
+        # next rooms of the same generator too (plain, and warm-started with fallback)
+        if args.held_out_rooms > 0:
+            from paper_2506_00970_amd.eval_warmstart import run_case
+
+            log(f"warm start on {args.held_out_rooms} more rooms")
+            warm["more_rooms"] = [
+                {k: c[k] for k in ("seed", "plain_iters", "warm_iters", "kept")}
+                for c in (run_case(rw, net, args.seed + k, 100, n_surfels=args.n)
+                          for k in range(1, args.held_out_rooms + 1))]
         del rw, net
 
     # warm-up and timed graph replays
@@ -681,7 +709,7 @@ def main():
         "final_error_cm_deg": [100 * errs[-1][0], errs[-1][1]],
         "warm_start": None if warm is None else dict(
             warm, ms_to_converge=(warm["warm_start_ms"] + warm["iters_to_converge"] * ms_step)
-            if warm["iters_to_converge"] else None),
+            if warm["iters_to_converge"] else None, **rooms_summary(warm, conv_iter, ms_step)),
         "roofline": roofline,
         "kernels_ms_per_launch": per_launch,
         "work": {"fwd_evaluated": prof["fwd_evaluated"] / max(n_fwd, 1),

@@ -304,7 +304,7 @@ def held_out(wsmod):
 def test_warm_start_gain_on_held_out_rooms(held_out):
     """Time to 1 cm / 0.5 deg, from the measured per-iteration and warm-start times:
     warm-started tracking (the warm start plus its iterations) is faster in most rooms
-    (measured 16 of 20), and its total over the 20 rooms is at most 80 % of plain
+    (measured 17 of 20), and its total over the 20 rooms is at most 80 % of plain
     tracking's (unconverged runs count 101 iterations)."""
     it, wm = held_out["ms_iter"], held_out["ms_warm"]
     plain = [(p or 101) * it for p, _ in held_out["iters"]]
