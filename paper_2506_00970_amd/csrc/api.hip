@@ -157,6 +157,7 @@ int ensure_pairs(gs2d_ctx* ctx, int64_t p) {
   for (int k = 0; k < 2; ++k) {
     GS2D_TRY(realloc_dev(ctx, &ctx->pkey[k], cap));
     GS2D_TRY(realloc_dev(ctx, &ctx->pval[k], cap));
+    GS2D_TRY(realloc_dev(ctx, &ctx->pdk[k], cap));
   }
   if (ctx->opt.keep_unsorted) {
     GS2D_TRY(realloc_dev(ctx, &ctx->pkey_keep, cap));
@@ -360,7 +361,8 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     auto duplicate = [&]() {
       ProfScope ps(ctx, kDup, s);
       launch_duplicate(ws, ctx->count, part_pairs, part_vis, scanned, ctx->rect, ctx->views, nv, items, ctx->p_cap,
-                       tbits, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
+                       tbits, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, ctx->dkey,
+                       ctx->pdk[0], s);
     };
     duplicate();
     if (allow_sync && !capturing && !ctx->pair_fixed) {
@@ -387,7 +389,8 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     }
     {
       ProfScope ps(ctx, kTileSort, s);
-      pbuf = tile_sort(ws, ctx->pkey, ctx->pval, ctx->p_cap, tbits, ctx->ctrl, ctx->ranges, (int)vs.tiles, s);
+      pbuf = tile_sort(ws, ctx->pkey, ctx->pval, ctx->pdk, ctx->p_cap, tbits, ctx->ctrl, ctx->ranges, (int)vs.tiles,
+                       s);
     }
     if (!fused_ranges) {
       ProfScope ps(ctx, kRanges, s);
@@ -396,7 +399,8 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     if (order) {
       // each tile's items, ascending on entry, stably into depth order
       ProfScope ps(ctx, kDepthSort, s);
-      launch_tile_order(ctx->ranges, (int)vs.tiles, ctx->pval[pbuf], ctx->pval[pbuf ^ 1], ctx->dkey, s);
+      launch_tile_order(ctx->ranges, (int)vs.tiles, ctx->pval[pbuf], ctx->pval[pbuf ^ 1], ctx->pdk[pbuf], ctx->dkey,
+                        s);
     }
     // many more tiles than fit on the GPU at once: the blends pull tiles from a queue,
     // longest lists first
@@ -634,6 +638,7 @@ int track_iteration(gs2d_ctx* ctx, const ViewSet& vs, const gs2d_track_args* a, 
       ba.order_ids = ctx->pval[ctx->pair_buf];
       ba.order_scratch = ctx->pval[ctx->pair_buf ^ 1];
       ba.dkey = ctx->dkey;
+      ba.order_keys = ctx->pdk[ctx->pair_buf];
     }
     ProfScope ps(ctx, kBlendTrack, s);
     launch_blend_track(ba, ctx->opt.tile_w, ctx->opt.tile_h, work_ptr(ctx, s), s);
@@ -857,7 +862,7 @@ GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
                   ctx->gacc,      ctx->pkey[0],    ctx->pkey[1],   ctx->pval[0],   ctx->pval[1],   ctx->pkey_keep,
                   ctx->pval_keep, ctx->ranges,     ctx->t_final,   ctx->last,      ctx->lgrad,     ctx->limg,
                   ctx->part,      ctx->lpart,      ctx->pose0,     ctx->saved_pose, ctx->views,    ctx->ctrl,
-                  ctx->queue};
+                  ctx->queue,     ctx->pdk[0],     ctx->pdk[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);

@@ -795,7 +795,7 @@ __global__ __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(5))) voi
   if constexpr (NT == kBlockThreads) {
     if (a.order_ids)
       lds_list = order_list(a.order_ids, a.order_scratch, a.dkey, start, end - start,
-                            order_lds(reinterpret_cast<uint32_t*>(srec), sid), false);
+                            order_lds(reinterpret_cast<uint32_t*>(srec), sid), false, a.order_keys);
   }
   FwdPix s{1.0f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, !inside};
   float Q[6], Ar[6], Ag[6], Ab[6], AD[6];

@@ -182,6 +182,7 @@ struct gs2d_ctx {
   // pairs [p_cap]
   uint32_t* pkey[2] = {nullptr, nullptr};
   uint32_t* pval[2] = {nullptr, nullptr};
+  uint32_t* pdk[2] = {nullptr, nullptr};  // each pair's depth key, moved with pval by the tile sort
   uint32_t* pkey_keep = nullptr;
   uint32_t* pval_keep = nullptr;
 
@@ -280,20 +281,23 @@ void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t it
 // The (tile, item) pairs of every item, in item order, placed by the per-block pair
 // counts of preprocessing (an exclusive prefix when `scanned`; otherwise the kernel
 // also stores ctrl->n_pairs and ctrl->n_visible); sets ctrl->overflow when the pairs
-// exceed p_cap.  Fills plane 1 with the first tile pass's histogram.
+// exceed p_cap.  Fills plane 1 with the first tile pass's histogram.  Each pair's
+// depth key (dkey of its item) goes to pdk beside pval.
 void launch_duplicate(const SortPlanes& ws, const uint32_t* count, const uint32_t* part_pairs,
                       const uint32_t* part_vis, bool scanned, const uint2* rect, const ViewDesc* views, int n_views,
                       int64_t items, int64_t p_cap, int tile_bits, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl,
-                      uint2* ranges, int n_tiles, hipStream_t s);
-// Stable sort of the min(n_pairs, p_cap) pairs by tile key over `bits` bits.  A single
-// pass also writes the tile ranges (empty after an overflow).  Returns the buffer index.
-int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_t p_cap, int bits, Ctrl* ctrl,
-              uint2* ranges, int n_tiles, hipStream_t s);
+                      uint2* ranges, int n_tiles, const uint32_t* dkey, uint32_t* pdk, hipStream_t s);
+// Stable sort of the min(n_pairs, p_cap) pairs by tile key over `bits` bits, moving
+// vals and dks with the keys.  A single pass also writes the tile ranges (empty after
+// an overflow).  Returns the buffer index.
+int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], uint32_t* dks[2], int64_t p_cap, int bits,
+              Ctrl* ctrl, uint2* ranges, int n_tiles, hipStream_t s);
 // Orders every tile's items (ids[ranges[t].x .. ranges[t].y), ascending on entry) by
-// depth key, stably: each list then ascends in (depth key, item).  scratch: a buffer
-// of the same size as ids for lists longer than one workgroup's LDS.
-void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* dkey,
-                       hipStream_t s);
+// depth key, stably: each list then ascends in (depth key, item).  pdk: the pairs'
+// depth keys beside ids; scratch: a buffer of the same size as ids for lists longer
+// than one workgroup's LDS (those read the keys through dkey[id]).
+void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* pdk,
+                       const uint32_t* dkey, hipStream_t s);
 void launch_ranges(const uint32_t* skey, Ctrl* ctrl, int64_t p_cap, uint2* ranges, int n_tiles,
                    hipStream_t s);
 // The blends' work queue of a view set: tiles by descending list length (counting
@@ -333,6 +337,7 @@ struct BlendArgs {
   uint32_t* order_ids = nullptr;
   uint32_t* order_scratch = nullptr;
   const uint32_t* dkey = nullptr;
+  const uint32_t* order_keys = nullptr;  // the pairs' depth keys beside order_ids
   // persistent launch of the forward and backward blends (many more tiles than fit on
   // the GPU at once): queue[kQueueHeadFwd], queue[kQueueHeadBwd] are the next items,
   // queue[kQueueOrder + i] the tiles by descending list length; null: one workgroup

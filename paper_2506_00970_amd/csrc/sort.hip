@@ -98,6 +98,44 @@ __global__ __launch_bounds__(kThreads) void radix_offsets_kernel(uint32_t* __res
   if (t == 0) dtot[blockIdx.x] = carry;
 }
 
+// The same for the 2048-bin passes, whose rows are short (the tile sorts of up to 2048
+// tiles: one entry per 1024 pairs): one wave per digit, four digits per workgroup,
+// each lane four consecutive entries per chunk of 256, a wave-level scan with a carry.
+__global__ __launch_bounds__(kThreads) void radix_offsets_wave_kernel(uint32_t* __restrict__ hist, int stride,
+                                                                      const uint32_t* __restrict__ n_dev,
+                                                                      int64_t n_host, uint32_t* __restrict__ dtot) {
+  const int64_t n = item_count(n_dev, n_host);
+  const int nb = (int)((n + kScanItems - 1) / kScanItems);
+  const int lane = threadIdx.x & 63;
+  const int d = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  uint32_t* __restrict__ row = hist + (size_t)d * stride;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nb; c0 += 4 * 64) {
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = c0 + 4 * lane + k;
+      v[k] = e < nb ? row[e] : 0u;
+    }
+    const uint32_t mine = v[0] + v[1] + v[2] + v[3];
+    uint32_t x = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+      if (lane >= o) x += y;
+    }
+    uint32_t run = carry + x - mine;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = c0 + 4 * lane + k;
+      if (e < nb) row[e] = run;
+      run += v[k];
+    }
+    carry += (uint32_t)__shfl((int)x, 63, 64);
+  }
+  if (lane == 0) dtot[d] = carry;
+}
+
 // One radix pass's scatter (see the top of the file).
 struct PassArgs {
   const uint32_t* kin;
@@ -116,6 +154,8 @@ struct PassArgs {
   int n_tiles;            //   for tiles < n_tiles (empty ranges when *overflow != 0)
   const uint32_t* overflow;
   uint32_t* check;        // Ctrl::check_bits (device checks)
+  const uint32_t* din;    // a second value moved with the keys (the pairs' depth keys), or null
+  uint32_t* dout;
 };
 
 template <int R>
@@ -155,12 +195,13 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
   const uint32_t nmask = (1u << a.nbits) - 1u;
   // all of the block's keys up front: the rounds' loads overlap instead of each
   // round waiting for its own
-  uint32_t kr[kRounds], vr[kRounds];
+  uint32_t kr[kRounds], vr[kRounds], dr[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const int64_t i = base + r * kThreads + t;
     kr[r] = i < n ? a.kin[i] : 0u;
     vr[r] = i < n ? a.vin[i] : 0u;
+    dr[r] = i < n && a.din ? a.din[i] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -171,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
     if (valid) {
       a.kout[pos] = key;
       a.vout[pos] = vr[r];
+      if (a.dout) a.dout[pos] = dr[r];
       if (a.hnext)
         atomicAdd(&a.hnext[(size_t)((key >> a.nshift) & nmask) * a.stride + (pos >> kBlockShift)], 1u);
     }
@@ -231,6 +273,8 @@ struct DupArgs {
   uint32_t* pkey;
   uint32_t* pval;
   Ctrl* ctrl;
+  const uint32_t* dkey;
+  uint32_t* pdk;
   uint2* ranges;  // cleared here for the ranges kernel (multi-pass tile sorts)
   int n_tiles;
   uint32_t* hist;  // the first tile pass's plane
@@ -245,6 +289,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
   // the loads that do not wait on the scan go first
   const uint32_t c = j < a.items ? a.count[j] : 0u;
   const uint2 rc = c ? a.rect[j] : make_uint2(1u, 0u);
+  const uint32_t dk = c ? a.dkey[j] : 0u;
   for (int64_t k = j; k < a.n_tiles; k += (int64_t)gridDim.x * kThreads) a.ranges[k] = make_uint2(0u, 0u);
   __shared__ uint32_t sh[kWaves];
   __shared__ unsigned long long sh64[kWaves];
@@ -310,6 +355,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
       GS2D_DCHECK(&a.ctrl->check_bits, (int64_t)off < a.p_cap, kCheckPairIndex);
       a.pkey[off] = key;
       a.pval[off] = (uint32_t)item;
+      a.pdk[off] = dk;
       atomicAdd(&a.hist[(size_t)(key & dmask) * a.stride + (off >> kBlockShift)], 1u);
       ++off;
     }
@@ -333,13 +379,14 @@ __global__ __launch_bounds__(kThreads) void ranges_kernel(const uint32_t* __rest
 __global__ __launch_bounds__(kBlockThreads) void tile_order_kernel(const uint2* __restrict__ ranges,
                                                                    uint32_t* __restrict__ ids,
                                                                    uint32_t* __restrict__ scratch,
+                                                                   const uint32_t* __restrict__ pdk,
                                                                    const uint32_t* __restrict__ dkey) {
   const uint2 rg = ranges[blockIdx.x];
   const int64_t start = rg.x, L = (int64_t)rg.y - (int64_t)rg.x;
   if (L <= 1) return;
   __shared__ __align__(16) uint32_t lds[kOrderScratchWords];
   __shared__ uint32_t sid[kOrderMax];
-  (void)order_list(ids, scratch, dkey, start, L, order_lds(lds, sid), true);
+  (void)order_list(ids, scratch, dkey, start, L, order_lds(lds, sid), true, pdk);
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per) > 0 ? (int)((n + per - 1) / per) : 1; }
@@ -349,8 +396,8 @@ void launch_pass(const PassArgs& a, int grid, hipStream_t s) {
     radix_offsets_kernel<<<256, kThreads, 0, s>>>(a.hist, a.stride, a.n_dev, a.n_host, const_cast<uint32_t*>(a.dtot));
     radix_scatter_kernel<256><<<grid, kThreads, 0, s>>>(a);
   } else {
-    radix_offsets_kernel<<<2048, kThreads, 0, s>>>(a.hist, a.stride, a.n_dev, a.n_host,
-                                                   const_cast<uint32_t*>(a.dtot));
+    radix_offsets_wave_kernel<<<2048 / kWaves, kThreads, 0, s>>>(a.hist, a.stride, a.n_dev, a.n_host,
+                                                                 const_cast<uint32_t*>(a.dtot));
     radix_scatter_kernel<2048><<<grid, kThreads, 0, s>>>(a);
   }
 }
@@ -424,16 +471,16 @@ void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t it
 void launch_duplicate(const SortPlanes& ws, const uint32_t* count, const uint32_t* part_pairs,
                       const uint32_t* part_vis, bool scanned, const uint2* rect, const ViewDesc* views, int n_views,
                       int64_t items, int64_t p_cap, int tile_bits, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl,
-                      uint2* ranges, int n_tiles, hipStream_t s) {
+                      uint2* ranges, int n_tiles, const uint32_t* dkey, uint32_t* pdk, hipStream_t s) {
   const int n_parts = blocks_for(items, kPartItems);
   DupArgs a{count,  part_pairs, part_vis, n_parts, scanned ? 1 : 0, rect,   views,   n_views,
-            items,  p_cap,      pkey,     pval,    ctrl,            ranges, n_tiles, ws.plane[1],
-            ws.stride, radix_pass_bits(tile_bits, 0)};
+            items,  p_cap,      pkey,     pval,    ctrl,            dkey,   pdk,     ranges,
+            n_tiles, ws.plane[1], ws.stride, radix_pass_bits(tile_bits, 0)};
   duplicate_kernel<<<n_parts, kThreads, 0, s>>>(a);
 }
 
-int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_t p_cap, int bits, Ctrl* ctrl,
-              uint2* ranges, int n_tiles, hipStream_t s) {
+int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], uint32_t* dks[2], int64_t p_cap, int bits,
+              Ctrl* ctrl, uint2* ranges, int n_tiles, hipStream_t s) {
   const int grid = blocks_for(p_cap, kScanItems);
   const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
   int cur = 0, shift = 0;
@@ -444,6 +491,8 @@ int tile_sort(const SortPlanes& ws, uint32_t* keys[2], uint32_t* vals[2], int64_
     a.vin = vals[cur];
     a.kout = keys[cur ^ 1];
     a.vout = vals[cur ^ 1];
+    a.din = dks[cur];
+    a.dout = dks[cur ^ 1];
     a.n_dev = &ctrl->n_pairs;
     a.n_host = p_cap;
     a.shift = shift;
@@ -478,10 +527,10 @@ void launch_queue_order(const uint2* ranges, int n_tiles, uint32_t* queue, hipSt
   queue_order_kernel<<<1, kQueueThreads, 0, s>>>(ranges, n_tiles, queue);
 }
 
-void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* dkey,
-                       hipStream_t s) {
+void launch_tile_order(const uint2* ranges, int n_tiles, uint32_t* ids, uint32_t* scratch, const uint32_t* pdk,
+                       const uint32_t* dkey, hipStream_t s) {
   if (n_tiles <= 0) return;
-  tile_order_kernel<<<n_tiles, kThreads, 0, s>>>(ranges, ids, scratch, dkey);
+  tile_order_kernel<<<n_tiles, kThreads, 0, s>>>(ranges, ids, scratch, pdk, dkey);
 }
 
 }  // namespace gs2d

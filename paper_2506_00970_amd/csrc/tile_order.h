@@ -114,14 +114,16 @@ __device__ inline OrderLds order_lds(uint32_t* scratch, uint32_t* sid) {
 }
 
 // Orders ids[start .. start + L) (ascending on entry) by (dkey[id], id), that is
-// stably by dkey[id]; every thread of the 256-thread block calls it.  Lists of up to
-// kOrderMax entries end in m.sid[0 .. L) (and, with write_back, in ids as well) and the
-// call returns true; longer lists are ordered in ids (scratch: a buffer of the same
-// size) and the call returns false.  Ends with a block barrier: the scratch may be
-// reused at once.
+// stably by dkey[id]; every thread of the 256-thread block calls it.  pkeys (nullable):
+// the same keys stored beside the ids, pkeys[start + e] = dkey[ids[start + e]], read
+// instead of gathering through the ids (not by the global-memory path, which permutes
+// the ids).  Lists of up to kOrderMax entries end in m.sid[0 .. L) (and, with
+// write_back, in ids as well) and the call returns true; longer lists are ordered in ids
+// (scratch: a buffer of the same size) and the call returns false.  Ends with a block
+// barrier: the scratch may be reused at once.
 __device__ inline bool order_list(uint32_t* __restrict__ ids, uint32_t* __restrict__ scratch,
                                   const uint32_t* __restrict__ dkey, int64_t start, int64_t L, const OrderLds& m,
-                                  bool write_back) {
+                                  bool write_back, const uint32_t* __restrict__ pkeys = nullptr) {
   constexpr int RB = kOrderBins;
   const int t = threadIdx.x;
   if (L <= kOrderCounted) {
@@ -133,8 +135,10 @@ __device__ inline bool order_list(uint32_t* __restrict__ ids, uint32_t* __restri
     const bool v0 = t < L, v1 = t + kBlockThreads < L;
     const uint32_t id0 = v0 ? ids[start + t] : 0u;
     const uint32_t id1 = v1 ? ids[start + t + kBlockThreads] : 0u;
-    const uint64_t key0 = v0 ? ((uint64_t)dkey[id0] << 32) | id0 : ~0ull;
-    const uint64_t key1 = v1 ? ((uint64_t)dkey[id1] << 32) | id1 : ~0ull;
+    const uint32_t dk0 = v0 ? (pkeys ? pkeys[start + t] : dkey[id0]) : 0u;
+    const uint32_t dk1 = v1 ? (pkeys ? pkeys[start + t + kBlockThreads] : dkey[id1]) : 0u;
+    const uint64_t key0 = v0 ? ((uint64_t)dk0 << 32) | id0 : ~0ull;
+    const uint64_t key1 = v1 ? ((uint64_t)dk1 << 32) | id1 : ~0ull;
     k64[t] = key0;
     k64[t + kBlockThreads] = key1;
     __syncthreads();
@@ -183,7 +187,7 @@ __device__ inline bool order_list(uint32_t* __restrict__ ids, uint32_t* __restri
     for (int r = 0; r < kOrderRounds; ++r) {
       const int e = r * kBlockThreads + t;
       id[r] = e < L ? ids[start + e] : 0u;
-      key[r] = e < L ? dkey[id[r]] : 0u;
+      key[r] = e < L ? (pkeys ? pkeys[start + e] : dkey[id[r]]) : 0u;
     }
     for (int p = 0; p < 32 / kOrderBits; ++p) {
       const int shift = p * kOrderBits;
