@@ -1,23 +1,33 @@
 // The learned pose warm start: a BF16 convolutional network on the matrix cores.
 //
 // Every layer, forward and backward, is one GEMM C[M][N] = sum_k A(m, k) B(k, n)
-// in a single kernel template: 256 threads, a 64 x 64 tile of C, K in steps of
-// 32.  Each step gathers the A and B sub-tiles (64 x 32 BF16 each) through the
-// layer's own index functions -- convolutions as implicit GEMMs, no im2col buffer
-// -- into LDS; each of the 4 waves then issues 2 x 2 v_mfma_f32_16x16x32_bf16 on
-// its 32 x 32 quarter, accumulating in FP32.  The layer's epilogue adds the bias,
-// applies ReLU (or, in the backward, the ReLU mask of the layer's input), rounds to
-// BF16 and stores; weight gradients go to FP32 partial sums over split-K slices
-// that a second kernel adds in a fixed order (deterministic), a constant-one
-// column of B giving the bias gradient in the same GEMM.
+// in a single kernel template: 256 threads (4 waves in a 2 x 2 grid), a BM x BN
+// tile of C chosen per layer, K in steps of 32.  Convolutions are implicit GEMMs
+// (no im2col buffer): activations are stored channels-last, [frame][y][x][c], and
+// the weights have BF16 copies permuted so that the reduction index runs along
+// channels, so every operand fetch is one aligned 16-byte load of 8 consecutive
+// BF16 values -- 8 consecutive k of one row ("k-chunks"), or, for the weight
+// gradients, whose reduction runs over pixels, 8 consecutive rows of one k
+// ("row chunks", read back from LDS with the transposing LDS read).  Operands are
+// fetched through buffer resources, whose range check supplies the zero padding.  The
+// chunks of the step after next are loaded into registers while the matrix cores
+// work on the current step from one of two LDS buffers (one barrier per step).  Each
+// wave issues (BM/32) x (BN/32) v_mfma_f32_16x16x32_bf16 per step on its quarter of
+// the tile, accumulating in FP32.  The layer's epilogue adds the bias, applies ReLU
+// (or, in the backward, the ReLU mask of the layer's input), rounds to BF16 and
+// stores 4 channels at once; weight gradients go to FP32 partial sums over split-K
+// slices that one kernel per backward pass adds in a fixed order (deterministic) and
+// maps back to the parameter layout, a constant-one column of B giving the bias
+// gradient in the same GEMM.
 //
 //   layer              M        N              K
-//   conv forward       Co       B OH OW        Ci k k
-//   conv input grad    Ci       B H W          Co k k   (stride-2 taps only)
-//   conv weight grad   Co       Ci k k + 1     B OH OW  (split-K)
+//   conv forward       Co       B OH OW        k k Ci'   (Ci' = Ci, or 8 for the 4-channel input)
+//   conv input grad    Ci       B H W / 4      taps Co   (one launch per output parity class:
+//                                                         only the stride-2 taps that reach it)
+//   conv weight grad   Co       k k Ci' + 1    B OH OW   (split-K)
 //   fc forward         O        B              I
-//   fc input grad      I        B              O
-//   fc weight grad     O        I + 1          B
+//   fc input grad      I        B              O'        (O' = O padded to 8)
+//   fc weight grad     O        I + 1          B         (split-K)
 //
 // MFMA operand layout used (16 x 16 x 32, wave64): lane l supplies row l % 16 of A
 // and column l % 16 of B, each with the 8 consecutive k of group l / 16; the FP32
@@ -40,8 +50,9 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8, kThreads = 256;
+constexpr int kBK = 32, kPad = 8, kThreads = 256, kStages = 2;
 constexpr uint16_t kOne = 0x3F80;  // bfloat16 1.0
+constexpr int kInCp = 8;           // input channels as stored (4 used, 4 zero)
 
 // Round to the nearest bfloat16, ties to even (finite inputs; NaN stays NaN).
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -50,297 +61,577 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // Post-ReLU activations are positive exactly when the sign bit is clear and they are not zero.
 __device__ __forceinline__ bool positive(uint16_t h) { return h != 0 && !(h & 0x8000u); }
+__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+__device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
+// 4 consecutive BF16 values: y[0..3] = bf16(relu(v + bias)) (8-byte aligned destination).
+__device__ __forceinline__ void store_relu4(uint16_t* y, const float* bias, f32x4 v) {
+  const float4 b = *reinterpret_cast<const float4*>(bias);
+  *reinterpret_cast<uint2*>(y) = uint2{pack2(to_bf16(relu(v[0] + b.x)), to_bf16(relu(v[1] + b.y))),
+                                       pack2(to_bf16(relu(v[2] + b.z)), to_bf16(relu(v[3] + b.w)))};
+}
+// 4 consecutive BF16 input gradients masked by the ReLU of the input x (8-byte aligned).
+__device__ __forceinline__ void store_masked4(uint16_t* gx, const uint16_t* x, f32x4 v) {
+  const uint2 xv = *reinterpret_cast<const uint2*>(x);
+  const uint16_t x0 = (uint16_t)xv.x, x1 = (uint16_t)(xv.x >> 16), x2 = (uint16_t)xv.y, x3 = (uint16_t)(xv.y >> 16);
+  *reinterpret_cast<uint2*>(gx) =
+      uint2{pack2(to_bf16(positive(x0) ? v[0] : 0.f), to_bf16(positive(x1) ? v[1] : 0.f)),
+            pack2(to_bf16(positive(x2) ? v[2] : 0.f), to_bf16(positive(x3) ? v[3] : 0.f))};
+}
 
-template <class Op>
-__global__ __launch_bounds__(kThreads) void gemm_kernel(Op op, int M, int N, int K, int k_split) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kBK + kPad];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kBK + kPad];
+// The workgroup's extent of a plain GEMM, blockIdx.z selecting a split-K slice of ks steps.
+struct Dims {
+  int M = 0, N = 0, K = 0, ks = 0;
+  __device__ void dims(int& m, int& n, int& kb, int& ke) const {
+    m = M;
+    n = N;
+    kb = blockIdx.z * ks;
+    ke = min(K, kb + ks);
+  }
+};
+
+// An operand op supplies, for its A and B, a per-chunk set-up and 16-byte chunks of 8
+// BF16 values, zero unless `ok` (the chunk lies inside the matrix).  A k-chunk operand
+// (kAk / kBk) gives the 8 consecutive k of one row: set-up a_prep(row), chunk
+// a(prep, k, ok) (K % 8 == 0).  A row-chunk operand gives 8 consecutive rows at one
+// k: set-up a_prep(first row), chunk a(prep, k, ok); the 8 rows may run past the last
+// row only where the source is padded to 8.
+//
+// k-chunks are stored in LDS row-major ([row][k]) and read as fragments with one
+// 16-byte read.  Row chunks are stored as loaded ([k][row]) and read with two
+// transposing reads (ds_read_b64_tr_b16): in each group of 16 lanes, lane q reads the
+// 4 rows (8 bytes) at row (kb + q / 4), column (m0 + 4 (q % 4)), and lane i receives
+// element i of each of the group's four 16-element rows -- (m0 + i, kb .. kb + 3),
+// the fragment's first or second 4 k.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+#define GS2D_LDS __attribute__((address_space(3)))
+__device__ __forceinline__ bf16x8 tr_fragment(const uint16_t* p0, const uint16_t* p1) {
+  const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((GS2D_LDS s16x4*)(p0));
+  const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((GS2D_LDS s16x4*)(p1));
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+template <class Op, int BM, int BN>
+__global__ __launch_bounds__(kThreads) void gemm_kernel(Op op) {
+  constexpr int FM = BM / 32, FN = BN / 32;  // 16 x 16 blocks per wave
+  constexpr int CA = BM * kBK / 8, CB = BN * kBK / 8;  // chunks per step
+  constexpr int NA = (CA + kThreads - 1) / kThreads, NB = (CB + kThreads - 1) / kThreads;
+  constexpr int RA = Op::kAk ? kBK / 8 : BM / 8, RB = Op::kBk ? kBK / 8 : BN / 8;
+  // LDS: k-chunk operands [rows][kBK + 8], row-chunk operands [kBK][rows + 16] (the
+  // row pitch puts the 4 rows of a transposing read in distinct banks)
+  constexpr int LA = Op::kAk ? BM : kBK, PA = Op::kAk ? kBK + kPad : BM + 16;
+  constexpr int LB = Op::kBk ? BN : kBK, PB = Op::kBk ? kBK + kPad : BN + 16;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][LA][PA];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][LB][PB];
+  int M, N, kb, ke;
+  op.dims(M, N, kb, ke);
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= M || n0 >= N) return;  // uniform over the workgroup
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-  const int kb = blockIdx.z * k_split, ke = min(K, kb + k_split);
-  const int r = t >> 2, kc = (t & 3) * 8;  // this thread's row (of A and of B^T) and k chunk
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const int li = lane & 15, g = lane >> 4;
-  const int m = m0 + r, n = n0 + r;
-  f32x4 acc[2][2];
+
+  // chunk c of a step: a k-chunk c -> (row c / R, k 8 (c % R)); a row chunk c -> (rows
+  // 8 (c % R) .., k c / R)
+  typename Op::APrep ap[NA];
+  typename Op::BPrep bp[NB];
+  int ar[NA], ak[NA], br[NB], bk[NB];
+  bool aon[NA], bon[NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += kBK) {
-    // each op gathers 8 consecutive k of one row (zero past ke): the index is
-    // decomposed once per chunk and stepped across the 8
-    uint16_t va[8], vb[8];
-    if (m < M)
-      op.a8(m, k0 + kc, ke, va);
-    else
-#pragma unroll
-      for (int i = 0; i < 8; ++i) va[i] = 0;
-    if (n < N)
-      op.b8(k0 + kc, n, ke, vb);
-    else
-#pragma unroll
-      for (int i = 0; i < 8; ++i) vb[i] = 0;
-    __syncthreads();  // the previous step's fragments have been read
-    uint4 pa, pb;
-    pa.x = va[0] | ((uint32_t)va[1] << 16);
-    pa.y = va[2] | ((uint32_t)va[3] << 16);
-    pa.z = va[4] | ((uint32_t)va[5] << 16);
-    pa.w = va[6] | ((uint32_t)va[7] << 16);
-    pb.x = vb[0] | ((uint32_t)vb[1] << 16);
-    pb.y = vb[2] | ((uint32_t)vb[3] << 16);
-    pb.z = vb[4] | ((uint32_t)vb[5] << 16);
-    pb.w = vb[6] | ((uint32_t)vb[7] << 16);
-    *reinterpret_cast<uint4*>(&As[r][kc]) = pa;
-    *reinterpret_cast<uint4*>(&Bs[r][kc]) = pb;
-    __syncthreads();
-    bf16x8 fa[2], fb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      fa[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 16 + li][g * 8]);
-      fb[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + i * 16 + li][g * 8]);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+  for (int i = 0; i < NA; ++i) {
+    const int c = t + i * kThreads;
+    ar[i] = Op::kAk ? c / RA : (c % RA) * 8;
+    ak[i] = Op::kAk ? (c % RA) * 8 : c / RA;
+    aon[i] = c < CA && m0 + ar[i] < M;
+    ap[i] = op.a_prep(aon[i] ? m0 + ar[i] : m0);
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NB; ++i) {
+    const int c = t + i * kThreads;
+    br[i] = Op::kBk ? c / RB : (c % RB) * 8;
+    bk[i] = Op::kBk ? (c % RB) * 8 : c / RB;
+    bon[i] = c < CB && n0 + br[i] < N;
+    bp[i] = op.b_prep(bon[i] ? n0 + br[i] : n0);
+  }
+  // a ring of kStages register stages: the chunks of step s + kStages are requested
+  // while step s is multiplied, so a step waits on memory only if kStages steps of
+  // products took less than one round trip
+  uint4 ra[kStages][NA], rb[kStages][NB];
+  auto fetch = [&](uint4* xa, uint4* xb, int k0) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < NA; ++i) xa[i] = op.a(ap[i], k0 + ak[i], aon[i] && k0 + ak[i] < ke);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int mm = m0 + wm + i * 16 + g * 4 + q, nn = n0 + wn + j * 16 + li;
-        if (mm < M && nn < N) op.store(mm, nn, acc[i][j][q]);
+    for (int i = 0; i < NB; ++i) xb[i] = op.b(bp[i], k0 + bk[i], bon[i] && k0 + bk[i] < ke);
+  };
+  auto stash = [&](const uint4* xa, const uint4* xb, int buf) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      if (t + i * kThreads >= CA) continue;
+      if constexpr (Op::kAk)
+        *reinterpret_cast<uint4*>(&As[buf][ar[i]][ak[i]]) = xa[i];
+      else
+        *reinterpret_cast<uint4*>(&As[buf][ak[i]][ar[i]]) = xa[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (t + i * kThreads >= CB) continue;
+      if constexpr (Op::kBk)
+        *reinterpret_cast<uint4*>(&Bs[buf][br[i]][bk[i]]) = xb[i];
+      else
+        *reinterpret_cast<uint4*>(&Bs[buf][bk[i]][br[i]]) = xb[i];
+    }
+  };
+
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto multiply = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += 32) {
+      bf16x8 fa[FM], fb[FN];
+      const int kq = kk + g * 8 + (li >> 2), mq = 4 * (li & 3);  // a transposing read's lane address
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        if constexpr (Op::kAk)
+          fa[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + i * 16 + li][kk + g * 8]);
+        else
+          fa[i] = tr_fragment(&As[buf][kq][wm + i * 16 + mq], &As[buf][kq + 4][wm + i * 16 + mq]);
       }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        if constexpr (Op::kBk)
+          fb[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + j * 16 + li][kk + g * 8]);
+        else
+          fb[j] = tr_fragment(&Bs[buf][kq][wn + j * 16 + mq], &Bs[buf][kq + 4][wn + j * 16 + mq]);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  const int steps = ke > kb ? (ke - kb + kBK - 1) / kBK : 0;
+#pragma unroll
+  for (int d = 0; d < kStages; ++d)
+    if (d < steps) fetch(ra[d], rb[d], kb + d * kBK);
+  for (int s0 = 0; s0 < steps; s0 += kStages) {
+#pragma unroll
+    for (int d = 0; d < kStages; ++d) {
+      const int s = s0 + d;
+      if (s >= steps) break;
+      // LDS buffer s & 1 was last read at step s - 2, before the previous barrier
+      stash(ra[d], rb[d], s & 1);
+      __syncthreads();
+      if (s + kStages < steps) fetch(ra[d], rb[d], kb + (s + kStages) * kBK);
+      multiply(s & 1);
+    }
+  }
+  // each lane holds rows mb .. mb + 3 of column n of every block: one 4-row store each
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int n = n0 + wn + j * 16 + li, mb = m0 + wm + i * 16 + g * 4;
+      if (n < N && mb < M) op.store4(mb, n, acc[i][j], min(4, M - mb));
+    }
 }
 
-// Shapes of one stride-2 convolution over a batch (kernel side KS fixed by the op).
-struct ConvShape {
-  int B, ci, co, k, H, W, OH, OW;
+// Operand sources are read through buffer resources with 32-bit byte offsets: a
+// chunk outside the matrix or in the zero padding gets the offset kOOB, which the
+// hardware's range check turns into zeros (no branch, no select).  Every source is
+// smaller than 2 GiB (the largest, an activation array at the largest batch, is
+// about 300 MiB).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr uint32_t kOOB = 0x80000000u;
+__device__ __forceinline__ Rsrc rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ uint4 bload(Rsrc r, uint32_t off) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+struct OffPrep {
+  uint32_t off;  // byte offset of the row (or of the first of 8 rows)
 };
 
-// 8 consecutive values of a contiguous row, zero past `end`.
-__device__ __forceinline__ void row8(const uint16_t* __restrict__ p, int k, int end, uint16_t* out) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) out[i] = k + i < end ? p[k + i] : (uint16_t)0;
-}
+// n / d for 0 <= n < 2^23 by a multiply and a shift: m = floor(2^(32 + l) / d) + 1 with
+// 2^l >= d, split as m = mh 2^32 + ml; n m / 2^(32 + l) exceeds n / d by less than
+// n / 2^(32 + l) < 1 / d, so its floor is floor(n / d).
+struct FastDiv {
+  uint32_t ml, mh;
+  int l;
+  __device__ int div(int n) const {
+    return (int)((__umulhi((uint32_t)n, ml) + (mh ? (uint32_t)n : 0u)) >> l);
+  }
+};
 
-// y = bf16(relu(conv(x, w) + bias)): M = co, N = B OH OW, K = ci KS KS.
+// y = bf16(relu(conv(x, w) + bias)), stride 2, zero padding KS / 2:
+// M = co, N = B OH OW, K = KS KS cp (k = (ky, kx, c), c fastest).
 template <int KS>
-struct ConvFwd {
-  ConvShape s;
-  const uint16_t* w;
+struct ConvFwd : Dims {
+  static constexpr bool kAk = true, kBk = true;
+  const uint16_t* w;  // [co][KS][KS][cp]
   const float* bias;
-  const uint16_t* x;
-  uint16_t* y;
-  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
-    row8(w + (size_t)m * (s.ci * KS * KS), k, ke, out);
+  const uint16_t* x;  // [B][H][W][cp]
+  uint16_t* y;        // [B][OH][OW][co]
+  int H, W, OH, OW, lc;  // lc = log2 cp
+  using APrep = OffPrep;
+  struct BPrep {
+    uint32_t off;  // the frame
+    int iy0, ix0;
+  };
+  __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const { return bload(rsrc(w), ok ? q.off + 2u * k : kOOB); }
+  __device__ BPrep b_prep(int n) const {
+    const int ohw = OH * OW, b = n / ohw, r = n - b * ohw, oy = r / OW, ox = r - oy * OW;
+    return {((uint32_t)(b * H * W) << lc) * 2u, 2 * oy - KS / 2, 2 * ox - KS / 2};
   }
-  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
-    const int ohw = s.OH * s.OW;
-    const int bi = n / ohw, rr = n - bi * ohw, oy = rr / s.OW, ox = rr - oy * s.OW;
-    const int iy0 = 2 * oy - KS / 2, ix0 = 2 * ox - KS / 2;
-    const uint16_t* __restrict__ xb = x + (size_t)bi * s.ci * s.H * s.W;
-    int c = k / (KS * KS), t = k - c * (KS * KS), ky = t / KS, kx = t - ky * KS;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int iy = iy0 + ky, ix = ix0 + kx;
-      out[i] = (k + i < ke && iy >= 0 && iy < s.H && ix >= 0 && ix < s.W) ? xb[((size_t)c * s.H + iy) * s.W + ix]
-                                                                           : (uint16_t)0;
-      if (++kx == KS) {
-        kx = 0;
-        if (++ky == KS) {
-          ky = 0;
-          ++c;
-        }
-      }
-    }
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const {
+    const int tap = k >> lc, c = k & ((1 << lc) - 1), ky = tap / KS, kx = tap - ky * KS;
+    const int iy = q.iy0 + ky, ix = q.ix0 + kx;
+    ok = ok && (unsigned)iy < (unsigned)H && (unsigned)ix < (unsigned)W;
+    return bload(rsrc(x), ok ? q.off + 2u * (((uint32_t)(iy * W + ix) << lc) + c) : kOOB);
   }
-  __device__ void store(int m, int n, float v) const {
-    const int ohw = s.OH * s.OW, bi = n / ohw, rr = n - bi * ohw;
-    v += bias[m];
-    y[((size_t)bi * s.co + m) * ohw + rr] = to_bf16(v > 0.f ? v : 0.f);
+  __device__ void store(int m, int n, float v) const { y[(size_t)n * M + m] = to_bf16(relu(v + bias[m])); }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {  // co % 4 == 0: rows == 4
+    store_relu4(y + (size_t)n * M + m, bias + m, v);
   }
 };
 
-// Input gradient of a convolution, masked by the ReLU of its input:
-// gx = bf16(conv^T(gy, w) [x > 0]): M = ci, N = B H W, K = co KS KS.
-template <int KS>
+// Input gradient of a 3 x 3 stride-2 convolution, masked by the ReLU of its input:
+// gx = bf16(conv^T(gy, w) [x > 0]).  Workgroup z = the parity class (iy % 2, ix % 2)
+// of the input pixels it computes: an even row is reached only by tap ky = 1 (from
+// output row iy / 2), an odd one by ky = 0 and 2 (output rows (iy + 1) / 2 and
+// (iy - 1) / 2), and likewise for columns.  M = ci, N = B Hc Wc (the class's pixels),
+// K = (taps in y) (taps in x) co (k = (tap, o), o fastest).
 struct ConvBwdData {
-  ConvShape s;
-  const uint16_t* w;
-  const uint16_t* gy;  // [B][co][OH][OW]
-  const uint16_t* x;   // the layer's input (post-ReLU)
-  uint16_t* gx;        // [B][ci][H][W]
-  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
-    constexpr int KK = KS * KS;
-    int o = k / KK, t = k - o * KK;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      out[i] = k + i < ke ? w[((size_t)o * s.ci + m) * KK + t] : (uint16_t)0;
-      if (++t == KK) {
-        t = 0;
-        ++o;
-      }
-    }
+  static constexpr bool kAk = true, kBk = true;
+  const uint16_t* wd;  // [ci][3][3][co]
+  const uint16_t* gy;  // [B][OH][OW][co]
+  const uint16_t* x;   // [B][H][W][ci], the layer's input (post-ReLU)
+  uint16_t* gx;        // [B][H][W][ci]
+  int Bn, ci, co, lco, H, W, OH, OW;
+  using APrep = OffPrep;
+  struct BPrep {
+    uint32_t off;  // the frame
+    int jy, jx;
+  };
+  __device__ int py() const { return blockIdx.z >> 1; }
+  __device__ int px() const { return blockIdx.z & 1; }
+  __device__ void dims(int& m, int& n, int& kb, int& ke) const {
+    m = ci;
+    n = Bn * ((H - py() + 1) >> 1) * ((W - px() + 1) >> 1);
+    kb = 0;
+    ke = ((1 + py()) * (1 + px())) << lco;
   }
-  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
-    const int hw = s.H * s.W;
-    const int bi = n / hw, rr = n - bi * hw, iy = rr / s.W, ix = rr - iy * s.W;
-    const uint16_t* __restrict__ gb = gy + (size_t)bi * s.co * s.OH * s.OW;
-    int o = k / (KS * KS), t = k - o * (KS * KS), ky = t / KS, kx = t - ky * KS;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int ty = iy + KS / 2 - ky, tx = ix + KS / 2 - kx;  // = 2 oy, 2 ox
-      const int oy = ty >> 1, ox = tx >> 1;
-      const bool ok = k + i < ke && ty >= 0 && tx >= 0 && !(ty & 1) && !(tx & 1) && oy < s.OH && ox < s.OW;
-      out[i] = ok ? gb[((size_t)o * s.OH + oy) * s.OW + ox] : (uint16_t)0;
-      if (++kx == KS) {
-        kx = 0;
-        if (++ky == KS) {
-          ky = 0;
-          ++o;
-        }
-      }
-    }
+  // tap t of the class -> (ty, tx); t = ty (taps in x) + tx
+  __device__ void tap(int t, int& ty, int& tx) const {
+    ty = px() ? t >> 1 : t;
+    tx = px() ? t & 1 : 0;
   }
-  __device__ void store(int m, int n, float v) const {
-    const int hw = s.H * s.W, bi = n / hw, rr = n - bi * hw;
-    const size_t idx = ((size_t)bi * s.ci + m) * hw + rr;
-    gx[idx] = to_bf16(positive(x[idx]) ? v : 0.f);
+  __device__ APrep a_prep(int m) const { return {(uint32_t)m * 9u * (uint32_t)co * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const {
+    int ty, tx;
+    tap(k >> lco, ty, tx);
+    const int ky = py() ? 2 * ty : 1, kx = px() ? 2 * tx : 1;
+    return bload(rsrc(wd), ok ? q.off + 2u * (uint32_t)((ky * 3 + kx) * co + (k & (co - 1))) : kOOB);
+  }
+  __device__ BPrep b_prep(int n) const {
+    const int Hc = (H - py() + 1) >> 1, Wc = (W - px() + 1) >> 1, per = Hc * Wc;
+    const int b = n / per, r = n - b * per, jy = r / Wc;
+    return {(uint32_t)(b * OH * OW * co) * 2u, jy, r - jy * Wc};
+  }
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const {
+    int ty, tx;
+    tap(k >> lco, ty, tx);
+    const int oy = py() ? q.jy + 1 - ty : q.jy, ox = px() ? q.jx + 1 - tx : q.jx;
+    ok = ok && oy < OH && ox < OW;
+    return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)((oy * OW + ox) * co + (k & (co - 1))) : kOOB);
+  }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {  // ci % 4 == 0: rows == 4
+    const int Hc = (H - py() + 1) >> 1, Wc = (W - px() + 1) >> 1, per = Hc * Wc;
+    const int b = n / per, r = n - b * per, jy = r / Wc, jx = r - jy * Wc;
+    const size_t idx = (((size_t)b * H + 2 * jy + py()) * W + 2 * jx + px()) * ci + m;
+    store_masked4(gx + idx, x + idx, v);
   }
 };
 
 // Weight and bias gradient of a convolution, one split-K slice per blockIdx.z:
-// part[z][co][ci KS KS + 1] = sum_n gy[co][n] [x patch | 1][n].
+// part[z][co][KS KS cp + 1] = sum over pixels n of gy[n][co] [x patch (ky, kx, c) | 1].
 template <int KS>
-struct ConvBwdWeight {
-  ConvShape s;
-  const uint16_t* gy;
-  const uint16_t* x;
+struct ConvBwdWeight : Dims {
+  static constexpr bool kAk = false, kBk = false;
+  const uint16_t* gy;  // [B][OH][OW][co]
+  const uint16_t* x;   // [B][H][W][cp]
   float* part;
-  int ncol;  // ci KS KS + 1
-  int M;
-  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
-    const int ohw = s.OH * s.OW;
-    int bi = k / ohw, rr = k - bi * ohw;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      out[i] = k + i < ke ? gy[((size_t)bi * s.co + m) * ohw + rr] : (uint16_t)0;
-      if (++rr == ohw) {
-        rr = 0;
-        ++bi;
-      }
-    }
+  int H, W, OH, OW, lc;
+  FastDiv by_ohw, by_ow;
+  using APrep = OffPrep;
+  struct BPrep {
+    int dy, dx, c;
+    bool bias;
+  };
+  __device__ APrep a_prep(int m8) const { return {(uint32_t)m8 * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const {
+    return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)(k * M) : kOOB);
   }
-  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
-    if (n == ncol - 1) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? kOne : (uint16_t)0;
-      return;
-    }
-    const int c = n / (KS * KS), t = n - c * (KS * KS), ky = t / KS, kx = t - ky * KS;
-    const int ohw = s.OH * s.OW;
-    int bi = k / ohw, rr = k - bi * ohw, oy = rr / s.OW, ox = rr - oy * s.OW;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int iy = 2 * oy + ky - KS / 2, ix = 2 * ox + kx - KS / 2;
-      const bool ok = k + i < ke && iy >= 0 && iy < s.H && ix >= 0 && ix < s.W;
-      out[i] = ok ? x[(((size_t)bi * s.ci + c) * s.H + iy) * s.W + ix] : (uint16_t)0;
-      if (++ox == s.OW) {
-        ox = 0;
-        if (++oy == s.OH) {
-          oy = 0;
-          ++bi;
-        }
-      }
-    }
+  __device__ BPrep b_prep(int n8) const {
+    const int tap = n8 >> lc, ky = tap / KS, kx = tap - ky * KS;
+    return {ky - KS / 2, kx - KS / 2, n8 & ((1 << lc) - 1), n8 == N - 1};
   }
-  __device__ void store(int m, int n, float v) const { part[((size_t)blockIdx.z * M + m) * ncol + n] = v; }
+  // pixel k = (frame, oy, ox)
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const {
+    if (q.bias) return ok ? uint4{kOne, 0u, 0u, 0u} : uint4{0u, 0u, 0u, 0u};
+    const int b = by_ohw.div(k), r = k - b * (OH * OW), oy = by_ow.div(r), ox = r - oy * OW;
+    const int iy = 2 * oy + q.dy, ix = 2 * ox + q.dx;
+    ok = ok && (unsigned)iy < (unsigned)H && (unsigned)ix < (unsigned)W;
+    return bload(rsrc(x), ok ? 2u * (((uint32_t)((b * H + iy) * W + ix) << lc) + q.c) : kOOB);
+  }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {
+    float* p = part + ((size_t)blockIdx.z * M + m) * N + n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < rows) p[(size_t)q * N] = v[q];
+  }
 };
 
 // Fully connected forward: y[b][o] = sum_i w[o][i] x[b][i] + bias[o]; M = O, N = B, K = I.
-struct FcFwd {
-  int I, O;
-  const uint16_t* w;
+struct FcFwd : Dims {
+  static constexpr bool kAk = true, kBk = true;
+  const uint16_t* w;  // [O][I]
   const float* bias;
-  const uint16_t* x;
-  uint16_t* y;   // ReLU + bf16 (hidden layer), or
-  float* yf;     // FP32, no ReLU (output layer)
-  __device__ void a8(int m, int k, int ke, uint16_t* out) const { row8(w + (size_t)m * I, k, ke, out); }
-  __device__ void b8(int k, int n, int ke, uint16_t* out) const { row8(x + (size_t)n * I, k, ke, out); }
+  const uint16_t* x;  // [B][I]
+  uint16_t* y;        // ReLU + bf16 (hidden layer), or
+  float* yf;          // FP32, no ReLU (output layer)
+  using APrep = OffPrep;
+  using BPrep = OffPrep;
+  __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const { return bload(rsrc(w), ok ? q.off + 2u * k : kOOB); }
+  __device__ BPrep b_prep(int n) const { return {(uint32_t)n * (uint32_t)K * 2u}; }
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const { return bload(rsrc(x), ok ? q.off + 2u * k : kOOB); }
   __device__ void store(int m, int n, float v) const {
     v += bias[m];
     if (yf)
-      yf[(size_t)n * O + m] = v;
+      yf[(size_t)n * M + m] = v;
     else
-      y[(size_t)n * O + m] = to_bf16(v > 0.f ? v : 0.f);
+      y[(size_t)n * M + m] = to_bf16(relu(v));
+  }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {
+    if (!yf && rows == 4) {
+      store_relu4(y + (size_t)n * M + m, bias + m, v);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < rows) store(m + q, n, v[q]);
+    }
   }
 };
 
 // Fully connected input gradient, masked by the ReLU of the input:
-// gx[b][i] = bf16(sum_o w[o][i] gy[b][o] [x > 0]); M = I, N = B, K = O.
-struct FcBwdData {
-  int I, O;
-  const uint16_t* w;
-  const uint16_t* gy;
-  const uint16_t* x;
+// gx[b][i] = bf16(sum_o w[o][i] gy[b][o] [x > 0]); M = I, N = B, K = O' (padded to 8).
+struct FcBwdData : Dims {
+  static constexpr bool kAk = true, kBk = true;
+  const uint16_t* wt;  // [I][O']
+  const uint16_t* gy;  // [B][O']
+  const uint16_t* x;   // [B][I]
   uint16_t* gx;
-  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? w[(size_t)(k + i) * I + m] : (uint16_t)0;
-  }
-  __device__ void b8(int k, int n, int ke, uint16_t* out) const { row8(gy + (size_t)n * O, k, ke, out); }
-  __device__ void store(int m, int n, float v) const {
-    const size_t idx = (size_t)n * I + m;
-    gx[idx] = to_bf16(positive(x[idx]) ? v : 0.f);
+  using APrep = OffPrep;
+  using BPrep = OffPrep;
+  __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const { return bload(rsrc(wt), ok ? q.off + 2u * k : kOOB); }
+  __device__ BPrep b_prep(int n) const { return {(uint32_t)n * (uint32_t)K * 2u}; }
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const { return bload(rsrc(gy), ok ? q.off + 2u * k : kOOB); }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {  // I % 4 == 0: rows == 4
+    const size_t idx = (size_t)n * M + m;
+    store_masked4(gx + idx, x + idx, v);
   }
 };
 
-// Fully connected weight and bias gradient: part[z][o][I + 1] = sum_b gy[b][o] [x[b] | 1].
-struct FcBwdWeight {
-  int I, O;
-  const uint16_t* gy;
-  const uint16_t* x;
+// Fully connected weight and bias gradient: part[z][o][I + 1] = sum_b gy[b][o] [x[b] | 1];
+// M = O, N = I + 1, K = B.
+struct FcBwdWeight : Dims {
+  static constexpr bool kAk = false, kBk = false;
+  const uint16_t* gy;  // [B][O'] (rows past O are zero)
+  const uint16_t* x;   // [B][I]
   float* part;
-  __device__ void a8(int m, int k, int ke, uint16_t* out) const {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? gy[(size_t)(k + i) * O + m] : (uint16_t)0;
+  int Op;  // O'
+  using APrep = OffPrep;
+  struct BPrep {
+    uint32_t off;
+    bool bias;
+  };
+  __device__ APrep a_prep(int m8) const { return {(uint32_t)m8 * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const {
+    return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)(k * Op) : kOOB);
   }
-  __device__ void b8(int k, int n, int ke, uint16_t* out) const {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) out[i] = k + i < ke ? (n == I ? kOne : x[(size_t)(k + i) * I + n]) : (uint16_t)0;
+  __device__ BPrep b_prep(int n8) const { return {(uint32_t)n8 * 2u, n8 == N - 1}; }
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const {
+    if (q.bias) return ok ? uint4{kOne, 0u, 0u, 0u} : uint4{0u, 0u, 0u, 0u};
+    return bload(rsrc(x), ok ? q.off + 2u * (uint32_t)(k * (N - 1)) : kOOB);
   }
-  __device__ void store(int m, int n, float v) const { part[((size_t)blockIdx.z * O + m) * (I + 1) + n] = v; }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {
+    float* p = part + ((size_t)blockIdx.z * M + m) * N + n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < rows) p[(size_t)q * N] = v[q];
+  }
 };
 
-// grad[w_off + m ncol' + j] (j < ncol - 1) and grad[b_off + m] (j = ncol - 1) = the sum
-// of the split-K partials in slice order.
-__global__ void reduce_parts_kernel(const float* __restrict__ part, int splits, int M, int ncol,
-                                    float* __restrict__ gw, float* __restrict__ gb) {
+// A forward layer with few output tiles (small batches) and a long reduction: each
+// split-K slice writes FP32 partial sums, and a second kernel adds them in slice
+// order and applies the layer's own epilogue (bias, ReLU, rounding) to the total.
+template <class Op>
+struct SplitPart : Op {
+  float* part;
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {
+    float* p = part + ((size_t)blockIdx.z * this->M + m) * this->N + n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < rows) p[(size_t)q * this->N] = v[q];
+  }
+};
+
+template <class Op>
+__global__ void split_finish_kernel(Op op, const float* __restrict__ part, int S) {
+  const int M = op.M, N = op.N;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M * ncol) return;
-  float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[(size_t)z * M * ncol + i];
-  const int m = i / ncol, j = i - m * ncol;
-  if (j == ncol - 1)
-    gb[m] = s;
-  else
-    gw[(size_t)m * (ncol - 1) + j] = s;
+  if (i >= M * N) return;
+  float v = 0.f;
+  for (int z = 0; z < S; ++z) v += part[(size_t)z * M * N + i];
+  op.store(i / N, i - (i / N) * N, v);
 }
 
-__global__ void to_bf16_kernel(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+// How a weight-gradient column j (of ncol - 1) maps to the parameter layout: conv
+// columns run (ky, kx, c) over cp >= ci channels (c >= ci: padding, dropped) into
+// [co][ci][ky][kx]; fc1 columns run (y, x, c) over the [128][4][5] feature map into
+// the flattened (c, y, x) order; fc2 columns map one to one.
+struct GradMap {
+  int kind;  // 0 conv, 1 fc1, 2 fc2
+  int ks, lc, ci;
+};
+
+// The weight-gradient GEMMs of one backward pass, for the one kernel that adds their
+// split-K partials: layer l's partials part[off + (z M + m) ncol + j], z < S, cover
+// workgroups block0 .. of the reduction grid.
+struct ReduceLayer {
+  int64_t off, w_off, b_off;
+  int S, M, ncol, block0;
+  GradMap map;
+};
+struct ReduceTable {
+  ReduceLayer L[6];
+  int n;
+};
+
+// grad[w][m][...] and grad[b][m] = the sum of the split-K partials: 64 outputs per
+// workgroup, wave w adding slices w, w + 4, w + 8, ... in order, then the four wave
+// sums in wave order (a fixed order: deterministic).
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restrict__ part, float* __restrict__ grad,
+                                                           ReduceTable tab) {
+  __shared__ float red[4][64];
+  int l = 0;
+  while (l + 1 < tab.n && (int)blockIdx.x >= tab.L[l + 1].block0) ++l;
+  const ReduceLayer& R = tab.L[l];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t MN = (int64_t)R.M * R.ncol;
+  const int64_t i = (int64_t)(blockIdx.x - R.block0) * 64 + lane;
+  float s = 0.f;
+  if (i < MN) {
+    const float* __restrict__ p = part + R.off + i;
+    int z = w;
+    for (; z + 12 < R.S; z += 16) {
+      const float v0 = p[z * MN], v1 = p[(z + 4) * MN], v2 = p[(z + 8) * MN], v3 = p[(z + 12) * MN];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; z < R.S; z += 4) s += p[z * MN];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || i >= MN) return;
+  s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  const int ncol = R.ncol, m = (int)(i / ncol), j = (int)(i - (int64_t)m * ncol);
+  if (j == ncol - 1) {
+    grad[R.b_off + m] = s;
+    return;
+  }
+  float* gw = grad + R.w_off;
+  const GradMap& map = R.map;
+  if (map.kind == 0) {
+    const int tap = j >> map.lc, c = j & ((1 << map.lc) - 1), ky = tap / map.ks, kx = tap - ky * map.ks;
+    if (c < map.ci) gw[(((size_t)m * map.ci + c) * map.ks + ky) * map.ks + kx] = s;
+  } else if (map.kind == 1) {
+    const int yx = j >> 7, c = j & 127;
+    gw[(size_t)m * (ncol - 1) + c * 20 + yx] = s;
+  } else {
+    gw[(size_t)m * (ncol - 1) + j] = s;
+  }
+}
+
+// The BF16 copies of the weights, in the layouts the GEMMs read:
+//   wf[l]: conv [co][k][k][cp]; fc1 [256][(y, x, c)]; fc2 [6][256]
+//   wd[l]: conv [ci][k][k][co] (layers 1-3); fc1 [(y, x, c)][256]; fc2 [256][8]
+// Entries no weight maps to (the input's padding channels, fc2's columns 6, 7) stay zero.
+struct Packed {
+  uint16_t* wf[6];
+  uint16_t* wd[6];
+  int64_t w_off[6], b_off[6];
+};
+
+__device__ void pack_weight(const Packed& pk, int64_t i, float v) {
+  int li = 0;
+  while (li < 5 && i >= pk.w_off[li + 1]) ++li;
+  if (i >= pk.b_off[li]) return;  // a bias: read in FP32
+  const int64_t r = i - pk.w_off[li];
+  const uint16_t h = to_bf16(v);
+  if (li < 4) {
+    const int ci = li == 0 ? 4 : (li == 1 ? 32 : (li == 2 ? 64 : 128));
+    const int co = li == 0 ? 32 : (li == 1 ? 64 : 128), k = li == 0 ? 5 : 3, kk = k * k;
+    const int cp = li == 0 ? kInCp : ci;
+    const int o = (int)(r / (ci * kk)), rem = (int)(r - (int64_t)o * ci * kk), c = rem / kk, tap = rem - c * kk;
+    pk.wf[li][((size_t)o * kk + tap) * cp + c] = h;
+    if (li > 0) pk.wd[li][((size_t)c * kk + tap) * co + o] = h;
+  } else if (li == 4) {
+    const int o = (int)(r / 2560), in = (int)(r - (int64_t)o * 2560), c = in / 20, yx = in - c * 20;
+    const int j = yx * 128 + c;
+    pk.wf[4][(size_t)o * 2560 + j] = h;
+    pk.wd[4][(size_t)j * 256 + o] = h;
+  } else {
+    const int o = (int)(r / 256), in = (int)(r - (int64_t)o * 256);
+    pk.wf[5][(size_t)o * 256 + in] = h;
+    pk.wd[5][(size_t)in * 8 + o] = h;
+  }
+}
+
+__global__ void pack_kernel(const float* __restrict__ theta, Packed pk, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = to_bf16(x[i]);
+  if (i < n) pack_weight(pk, i, theta[i]);
+}
+
+// FP32 input [B][4][60][80] -> BF16 [B][60][80][8], channels 4-7 zero.
+__global__ void load_input_kernel(const float* __restrict__ in, uint16_t* __restrict__ x, int64_t npix) {
+  constexpr int hw = GS2D_WS_IN_H * GS2D_WS_IN_W;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  const int64_t b = i / hw, q = i - b * hw;
+  const float* p = in + b * GS2D_WS_IN_C * hw + q;
+  uint4 v;
+  v.x = (uint32_t)to_bf16(p[0]) | ((uint32_t)to_bf16(p[hw]) << 16);
+  v.y = (uint32_t)to_bf16(p[2 * hw]) | ((uint32_t)to_bf16(p[3 * hw]) << 16);
+  v.z = v.w = 0u;
+  *reinterpret_cast<uint4*>(x + i * kInCp) = v;
 }
 
 // Mean squared error over n = B x 6 values (one workgroup, fixed-order sums), its
-// gradient 2 d / n rounded to bfloat16, and the FP32 loss.
+// gradient 2 d / n rounded to bfloat16 into rows of 8 (the last two zero), and the
+// FP32 loss.
 __global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ out, const float* __restrict__ target,
                                                   int n, uint16_t* __restrict__ gout, float* __restrict__ loss) {
   __shared__ float sh[256];
@@ -348,8 +639,9 @@ __global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ out,
   for (int i = threadIdx.x; i < n; i += 256) {
     const float d = out[i] - target[i];
     s = fmaf(d, d, s);
-    gout[i] = to_bf16(2.0f * d / (float)n);
+    gout[(i / 6) * 8 + i % 6] = to_bf16(2.0f * d / (float)n);
   }
+  for (int b = threadIdx.x; b < n / 6; b += 256) gout[b * 8 + 6] = gout[b * 8 + 7] = 0;
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -360,10 +652,9 @@ __global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ out,
 }
 
 // AdamW on the FP32 master vector (bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t from
-// the host), then the BF16 copy.
+// the host), then the BF16 copies.
 __global__ void adamw_kernel(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
-                             const float* __restrict__ g, uint16_t* __restrict__ wb, int n, gs2d_ws_adamw o,
-                             float c1, float c2) {
+                             const float* __restrict__ g, Packed pk, int n, gs2d_ws_adamw o, float c1, float c2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -374,7 +665,7 @@ __global__ void adamw_kernel(float* __restrict__ theta, float* __restrict__ m, f
   const float mh = mi / c1, vh = vi / c2;
   const float th = theta[i] * (1.f - o.lr * o.weight_decay) - o.lr * mh / (sqrtf(vh) + o.eps);
   theta[i] = th;
-  wb[i] = to_bf16(th);
+  pack_weight(pk, i, th);
 }
 
 // input[b][c][Y][X] = mean over the f x f block of (img - tgt), c < 3 colour, c = 3 depth.
@@ -430,62 +721,99 @@ int out_size(int n, int k) { return (n + 2 * (k / 2) - k) / 2 + 1; }
 int64_t layer_weights(const LayerDef& L) {
   return L.k ? (int64_t)L.co * L.ci * L.k * L.k : (int64_t)L.co * L.ci;
 }
-int64_t act_size(int li) {  // per frame, output of layer li (li = -1: the input)
-  if (li < 0) return (int64_t)GS2D_WS_IN_C * GS2D_WS_IN_H * GS2D_WS_IN_W;
+int cp_of(int li) { return li == 0 ? kInCp : kLayers[li].ci; }
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+FastDiv fast_div(int d) {
+  const int l = log2i(d);
+  const uint64_t m = ((uint64_t)1 << (32 + l)) / (uint64_t)d + 1;
+  return FastDiv{(uint32_t)m, (uint32_t)(m >> 32), l};
+}
+int64_t act_size(int li) {  // per frame, output of layer li (li = -1: the input as stored)
+  if (li < 0) return (int64_t)kInCp * GS2D_WS_IN_H * GS2D_WS_IN_W;
   const LayerDef& L = kLayers[li];
   if (L.k) return (int64_t)L.co * out_size(L.H, L.k) * out_size(L.W, L.k);
   return L.co;
 }
-
-template <class Op>
-void gemm(const Op& op, int M, int N, int K, int splits, hipStream_t s) {
-  const int ks = ((K + splits - 1) / splits + kBK - 1) / kBK * kBK;
-  dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM, splits);
-  gemm_kernel<Op><<<grid, kThreads, 0, s>>>(op, M, N, K, ks);
+// BF16 copies: forward and input-gradient layouts of each layer.
+int64_t wf_size(int li) {
+  const LayerDef& L = kLayers[li];
+  return L.k ? (int64_t)L.co * L.k * L.k * cp_of(li) : (int64_t)L.co * L.ci;
+}
+int64_t wd_size(int li) {
+  const LayerDef& L = kLayers[li];
+  if (L.k) return li == 0 ? 0 : (int64_t)L.ci * L.k * L.k * L.co;
+  return (int64_t)L.ci * (li == 5 ? 8 : L.co);
 }
 
-// A forward layer with few output tiles (small batches) and a long reduction: each
-// split-K slice writes FP32 partial sums, and a second kernel adds them in slice
-// order and applies the layer's own epilogue (bias, ReLU, rounding) to the total.
-template <class Op>
-struct SplitPart {
-  Op op;
-  float* part;
-  int M, N;
-  __device__ void a8(int m, int k, int ke, uint16_t* o) const { op.a8(m, k, ke, o); }
-  __device__ void b8(int k, int n, int ke, uint16_t* o) const { op.b8(k, n, ke, o); }
-  __device__ void store(int m, int n, float v) const { part[((size_t)blockIdx.z * M + m) * N + n] = v; }
-};
+int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-template <class Op>
-__global__ void split_finish_kernel(Op op, const float* __restrict__ part, int S, int M, int N) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M * N) return;
-  float v = 0.f;
-  for (int z = 0; z < S; ++z) v += part[(size_t)z * M * N + i];
-  op.store(i / N, i - (i / N) * N, v);
+template <int BM, int BN, class Op>
+void run(const Op& op, int M, int N, int gz, hipStream_t s) {
+  dim3 grid(cdiv(N, BN), cdiv(M, BM), gz);
+  gemm_kernel<Op, BM, BN><<<grid, kThreads, 0, s>>>(op);
 }
 
-template <class Op>
-void gemm_fwd(const Op& op, int M, int N, int K, float* part, int64_t part_cap, hipStream_t s) {
-  const int tiles = ((N + kBN - 1) / kBN) * ((M + kBM - 1) / kBM);
-  int S = 1;
-  if (tiles < 64 && K >= 256) {
-    S = K / 128;
-    const int want = (128 + tiles - 1) / tiles;  // about 128 workgroups in all
+// Tile columns: 128 while that still makes 512 workgroups, else 64 while that makes
+// 256, else 32 (groups: workgroups per tile, i.e. the parity classes).
+int pick_bn(int M, int N, int BM, int groups) {
+  if ((int64_t)cdiv(N, 128) * cdiv(M, BM) * groups >= 512) return 128;
+  if ((int64_t)cdiv(N, 64) * cdiv(M, BM) * groups >= 256) return 64;
+  return 32;
+}
+
+template <int BM, class Op>
+void run_bn(const Op& op, int M, int N, int gz, int bn, hipStream_t s) {
+  if (bn == 128)
+    run<BM, 128>(op, M, N, gz, s);
+  else if (bn == 64)
+    run<BM, 64>(op, M, N, gz, s);
+  else
+    run<BM, 32>(op, M, N, gz, s);
+}
+
+// A forward layer: large outputs as one GEMM (tile columns by pick_bn); few output
+// tiles with a long reduction split over about 128 workgroups.
+template <int BM, class Op>
+void gemm_fwd(Op op, float* part, int64_t part_cap, hipStream_t s) {
+  const int M = op.M, N = op.N, K = op.K;
+  const int tiles = cdiv(N, 64) * cdiv(M, BM);
+  if (tiles < 64 && K >= 512) {
+    int S = K / 128;
+    const int want = cdiv(128, tiles);
     S = S < want ? S : want;
+    const int ks = cdiv(cdiv(K, S), kBK) * kBK;
+    S = cdiv(K, ks);
+    if (S > 1 && (int64_t)S * M * N <= part_cap) {
+      SplitPart<Op> sp;
+      static_cast<Op&>(sp) = op;
+      sp.ks = ks;
+      sp.part = part;
+      run<BM, 64>(sp, M, N, S, s);
+      op.ks = ks;
+      split_finish_kernel<Op><<<cdiv((int64_t)M * N, 256), 256, 0, s>>>(op, part, S);
+      return;
+    }
   }
-  if (S > 1 && (int64_t)S * M * N <= part_cap) {
-    gemm(SplitPart<Op>{op, part, M, N}, M, N, K, S, s);
-    split_finish_kernel<Op><<<(M * N + 255) / 256, 256, 0, s>>>(op, part, S, M, N);
-  } else {
-    gemm(op, M, N, K, 1, s);
-  }
+  op.ks = cdiv(K, kBK) * kBK;
+  run_bn<BM>(op, M, N, 1, pick_bn(M, N, BM, 1), s);
 }
 
-int splits_for(int64_t K) {  // split-K slices of about 2048 reduction steps
-  int64_t s = (K + 2047) / 2048;
-  return (int)(s < 1 ? 1 : (s > 512 ? 512 : s));
+// Split-K slices of a weight-gradient GEMM: about 512 workgroups, at most 128 slices,
+// at least 512 reduction indices each.
+int wgrad_splits(int M, int N, int64_t K, int BM, int BN, int* ks_out) {
+  const int tiles = cdiv(N, BN) * cdiv(M, BM);
+  int64_t S = cdiv(512, tiles);
+  if (S > 128) S = 128;
+  const int64_t smax = K / 512 > 1 ? K / 512 : 1;
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  const int ks = cdiv(cdiv(K, S), kBK) * kBK;
+  if (ks_out) *ks_out = ks;
+  return cdiv(K, ks);
 }
 
 }  // namespace
@@ -499,9 +827,11 @@ struct gs2d_ws {
   float* m = nullptr;       // AdamW moments [P]
   float* v = nullptr;
   float* grad = nullptr;    // last gradient [P]
-  uint16_t* wb = nullptr;   // BF16 copy [P]
-  uint16_t* act[7] = {};    // BF16 activations: input, conv1..4, fc1 ([max_batch] frames each)
-  uint16_t* gact[7] = {};   // BF16 gradients of the same (pre-ReLU for layer outputs)
+  uint16_t* wp = nullptr;   // BF16 copies (pk's layouts)
+  int64_t wp_size = 0;
+  gs2d::ws::Packed pk = {};
+  uint16_t* act[7] = {};    // BF16 activations, channels last: input, conv1..4, fc1 ([max_batch] frames each)
+  uint16_t* gact[7] = {};   // BF16 gradients of the same (fc2's output gradient in rows of 8)
   float* out = nullptr;     // FP32 [max_batch][6]
   float* part = nullptr;    // split-K partials
   int64_t part_cap = 0;
@@ -512,12 +842,13 @@ struct gs2d_ws {
   float* igrad = nullptr;   // d_rgb, d_depth [4][hw]
   int64_t img_cap = 0;
   float* wsf = nullptr;     // input [4][60][80], out [6], tau [6], pose0 [12], loss [2]
-  int64_t w_off[6] = {}, b_off[6] = {};
 };
 
 namespace {
 
 using namespace gs2d::ws;
+
+constexpr int64_t kInPlanar = (int64_t)GS2D_WS_IN_C * GS2D_WS_IN_H * GS2D_WS_IN_W;  // FP32 input per frame
 
 int dev_alloc(void** p, size_t bytes) {
   if (hipMalloc(p, bytes) != hipSuccess) {
@@ -547,74 +878,191 @@ int ensure_part(gs2d_ws* net, int64_t n) {
   return GS2D_OK;
 }
 
-// Partial-sum floats of every weight-gradient GEMM of a batch (the largest one).
-int64_t part_need(int B) {
-  int64_t need = 0;
-  for (int li = 0; li < 6; ++li) {
-    const LayerDef& L = kLayers[li];
-    int64_t M, ncol, K;
-    if (L.k) {
-      M = L.co;
-      ncol = (int64_t)L.ci * L.k * L.k + 1;
-      K = (int64_t)B * out_size(L.H, L.k) * out_size(L.W, L.k);
-    } else {
-      M = L.co;
-      ncol = L.ci + 1;
-      K = B;
-    }
-    const int64_t sz = (int64_t)splits_for(K) * M * ncol;
-    need = sz > need ? sz : need;
-  }
-  return need;
-}
+// The tile of each layer's weight-gradient GEMM: rows (M = co or O) and columns (64:
+// wider tiles at small M halve the workgroups and were measured slower).
+int wgrad_bm(int li) { return kLayers[li].co >= 128 ? 128 : (kLayers[li].co >= 64 ? 64 : 32); }
+int wgrad_bn(int) { return 64; }
 
-ConvShape conv_shape(int li, int B) {
+// Weight-gradient GEMM of layer li over a batch of B: M, N (columns incl. bias), K.
+void wgrad_shape(int li, int B, int* M, int* N, int64_t* K) {
   const LayerDef& L = kLayers[li];
-  return ConvShape{B, L.ci, L.co, L.k, L.H, L.W, out_size(L.H, L.k), out_size(L.W, L.k)};
-}
-
-// Forward of `batch` frames whose BF16 input is in act[0]; FP32 output to net->out.
-void forward_layers(gs2d_ws* net, int B, hipStream_t s) {
-  for (int li = 0; li < 4; ++li) {
-    const ConvShape cs = conv_shape(li, B);
-    const uint16_t* w = net->wb + net->w_off[li];
-    const float* b = net->theta + net->b_off[li];
-    if (cs.k == 5)
-      gemm_fwd(ConvFwd<5>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 25,
-               net->part, net->part_cap, s);
-    else
-      gemm_fwd(ConvFwd<3>{cs, w, b, net->act[li], net->act[li + 1]}, cs.co, B * cs.OH * cs.OW, cs.ci * 9,
-               net->part, net->part_cap, s);
-  }
-  {
-    FcFwd op{2560, 256, net->wb + net->w_off[4], net->theta + net->b_off[4], net->act[4], net->act[5], nullptr};
-    gemm_fwd(op, 256, B, 2560, net->part, net->part_cap, s);
-  }
-  {
-    FcFwd op{256, 6, net->wb + net->w_off[5], net->theta + net->b_off[5], net->act[5], nullptr, net->out};
-    gemm_fwd(op, 6, B, 256, net->part, net->part_cap, s);
-  }
-}
-
-int weight_grad(gs2d_ws* net, int li, int B, hipStream_t s) {
-  const LayerDef& L = kLayers[li];
-  float* gw = net->grad + net->w_off[li];
-  float* gb = net->grad + net->b_off[li];
+  *M = L.co;
   if (L.k) {
-    const ConvShape cs = conv_shape(li, B);
-    const int ncol = cs.ci * cs.k * cs.k + 1, K = B * cs.OH * cs.OW, sp = splits_for(K);
-    if (cs.k == 5)
-      gemm(ConvBwdWeight<5>{cs, net->gact[li + 1], net->act[li], net->part, ncol, cs.co}, cs.co, ncol, K, sp, s);
-    else
-      gemm(ConvBwdWeight<3>{cs, net->gact[li + 1], net->act[li], net->part, ncol, cs.co}, cs.co, ncol, K, sp, s);
-    reduce_parts_kernel<<<(cs.co * ncol + 255) / 256, 256, 0, s>>>(net->part, sp, cs.co, ncol, gw, gb);
+    *N = L.k * L.k * cp_of(li) + 1;
+    *K = (int64_t)B * out_size(L.H, L.k) * out_size(L.W, L.k);
   } else {
-    const int sp = splits_for(B);
-    FcBwdWeight op{L.ci, L.co, net->gact[li + 1], net->act[li], net->part};
-    gemm(op, L.co, L.ci + 1, B, sp, s);
-    reduce_parts_kernel<<<(L.co * (L.ci + 1) + 255) / 256, 256, 0, s>>>(net->part, sp, L.co, L.ci + 1, gw, gb);
+    *N = L.ci + 1;
+    *K = B;
   }
-  return GS2D_OK;
+}
+
+// Partial-sum floats of the weight-gradient GEMMs of a batch, each layer in its own
+// region (offsets into off[6]; they are added by one kernel after the backward pass);
+// the split forward layers of small batches use the start of the buffer.
+int64_t part_layout(int B, int64_t* off) {
+  int64_t o = 0;
+  for (int li = 0; li < 6; ++li) {
+    int M, N;
+    int64_t K;
+    wgrad_shape(li, B, &M, &N, &K);
+    if (off) off[li] = o;
+    o += (int64_t)wgrad_splits(M, N, K, wgrad_bm(li), wgrad_bn(li), nullptr) * M * N;
+  }
+  return o > (1 << 20) ? o : (1 << 20);
+}
+
+// Forward of `batch` frames whose BF16 input is in act[0]; FP32 output to out [B][6].
+void forward_layers(gs2d_ws* net, int B, float* out, hipStream_t s) {
+  for (int li = 0; li < 4; ++li) {
+    const LayerDef& L = kLayers[li];
+    const int OH = out_size(L.H, L.k), OW = out_size(L.W, L.k), cp = cp_of(li);
+    auto fill = [&](auto& op) {
+      op.M = L.co;
+      op.N = B * OH * OW;
+      op.K = L.k * L.k * cp;
+      op.w = net->pk.wf[li];
+      op.bias = net->theta + net->pk.b_off[li];
+      op.x = net->act[li];
+      op.y = net->act[li + 1];
+      op.H = L.H;
+      op.W = L.W;
+      op.OH = OH;
+      op.OW = OW;
+      op.lc = log2i(cp);
+    };
+    if (li == 0) {
+      ConvFwd<5> op;
+      fill(op);
+      gemm_fwd<32>(op, net->part, net->part_cap, s);
+    } else {
+      ConvFwd<3> op;
+      fill(op);
+      if (li == 1)
+        gemm_fwd<64>(op, net->part, net->part_cap, s);
+      else
+        gemm_fwd<128>(op, net->part, net->part_cap, s);
+    }
+  }
+  {
+    FcFwd op;
+    op.M = 256;
+    op.N = B;
+    op.K = 2560;
+    op.w = net->pk.wf[4];
+    op.bias = net->theta + net->pk.b_off[4];
+    op.x = net->act[4];
+    op.y = net->act[5];
+    op.yf = nullptr;
+    gemm_fwd<128>(op, net->part, net->part_cap, s);
+  }
+  {
+    FcFwd op;
+    op.M = 6;
+    op.N = B;
+    op.K = 256;
+    op.w = net->pk.wf[5];
+    op.bias = net->theta + net->pk.b_off[5];
+    op.x = net->act[5];
+    op.y = nullptr;
+    op.yf = out;
+    gemm_fwd<32>(op, net->part, net->part_cap, s);
+  }
+}
+
+template <int BM, class Op>
+void wgrad_run(gs2d_ws* net, Op op, int li, int B, ReduceTable* tab, hipStream_t s) {
+  int M, N;
+  int64_t K;
+  wgrad_shape(li, B, &M, &N, &K);
+  int64_t off[6];
+  part_layout(B, off);
+  int ks = 0;
+  const int bn = wgrad_bn(li);
+  const int S = wgrad_splits(M, N, K, BM, bn, &ks);
+  op.M = M;
+  op.N = N;
+  op.K = (int)K;
+  op.ks = ks;
+  op.part = net->part + off[li];
+  if (bn == 128)
+    run<BM, 128>(op, M, N, S, s);
+  else
+    run<BM, 64>(op, M, N, S, s);
+  const LayerDef& L = kLayers[li];
+  ReduceLayer& R = tab->L[tab->n];
+  R.off = off[li];
+  R.w_off = net->pk.w_off[li];
+  R.b_off = net->pk.b_off[li];
+  R.S = S;
+  R.M = M;
+  R.ncol = N;
+  R.block0 = tab->n ? tab->L[tab->n - 1].block0 + cdiv((int64_t)tab->L[tab->n - 1].M * tab->L[tab->n - 1].ncol, 64)
+                    : 0;
+  R.map = GradMap{L.k ? 0 : (li == 4 ? 1 : 2), L.k, log2i(cp_of(li)), L.ci};
+  tab->n += 1;
+}
+
+void weight_grad(gs2d_ws* net, int li, int B, ReduceTable* tab, hipStream_t s) {
+  const LayerDef& L = kLayers[li];
+  if (L.k) {
+    auto fill = [&](auto& op) {
+      op.gy = net->gact[li + 1];
+      op.x = net->act[li];
+      op.H = L.H;
+      op.W = L.W;
+      op.OH = out_size(L.H, L.k);
+      op.OW = out_size(L.W, L.k);
+      op.lc = log2i(cp_of(li));
+      op.by_ohw = fast_div(op.OH * op.OW);
+      op.by_ow = fast_div(op.OW);
+    };
+    if (li == 0) {
+      ConvBwdWeight<5> op;
+      fill(op);
+      wgrad_run<32>(net, op, li, B, tab, s);
+    } else {
+      ConvBwdWeight<3> op;
+      fill(op);
+      if (li == 1)
+        wgrad_run<64>(net, op, li, B, tab, s);
+      else
+        wgrad_run<128>(net, op, li, B, tab, s);
+    }
+  } else {
+    FcBwdWeight op;
+    op.gy = net->gact[li + 1];
+    op.x = net->act[li];
+    op.Op = li == 5 ? 8 : L.co;
+    if (li == 4)
+      wgrad_run<128>(net, op, li, B, tab, s);
+    else
+      wgrad_run<32>(net, op, li, B, tab, s);
+  }
+}
+
+// Input gradient of conv layer li (1..3), masked by the ReLU of its input.
+void conv_data_grad(gs2d_ws* net, int li, int B, hipStream_t s) {
+  const LayerDef& L = kLayers[li];
+  ConvBwdData op;
+  op.wd = net->pk.wd[li];
+  op.gy = net->gact[li + 1];
+  op.x = net->act[li];
+  op.gx = net->gact[li];
+  op.Bn = B;
+  op.ci = L.ci;
+  op.co = L.co;
+  op.lco = log2i(L.co);
+  op.H = L.H;
+  op.W = L.W;
+  op.OH = out_size(L.H, 3);
+  op.OW = out_size(L.W, 3);
+  const int N = B * ((L.H + 1) >> 1) * ((L.W + 1) >> 1);  // the largest class
+  if (L.ci == 32)
+    run_bn<32>(op, L.ci, N, 4, pick_bn(L.ci, N, 32, 4), s);
+  else if (L.ci == 64)
+    run_bn<64>(op, L.ci, N, 4, pick_bn(L.ci, N, 64, 4), s);
+  else
+    run_bn<128>(op, L.ci, N, 4, pick_bn(L.ci, N, 128, 4), s);
 }
 
 int check_net(gs2d_ws* net, int batch) {
@@ -624,8 +1072,8 @@ int check_net(gs2d_ws* net, int batch) {
 }
 
 void load_input(gs2d_ws* net, const float* input, int B, hipStream_t s) {
-  const int64_t n = (int64_t)B * act_size(-1);
-  to_bf16_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(input, net->act[0], n);
+  const int64_t npix = (int64_t)B * GS2D_WS_IN_H * GS2D_WS_IN_W;
+  load_input_kernel<<<cdiv(npix, 256), 256, 0, s>>>(input, net->act[0], npix);
 }
 
 }  // namespace
@@ -646,35 +1094,47 @@ GS2D_API int gs2d_ws_create(gs2d_ws** out, int device, int32_t max_batch) {
   if (!net) return GS2D_ERR_OOM;
   net->device = device;
   net->max_batch = max_batch;
-  int64_t o = 0;
+  int64_t o = 0, wo = 0;
+  int64_t wf_off[6], wd_off[6];
   for (int li = 0; li < 6; ++li) {
-    net->w_off[li] = o;
+    net->pk.w_off[li] = o;
     o += layer_weights(kLayers[li]);
-    net->b_off[li] = o;
+    net->pk.b_off[li] = o;
     o += kLayers[li].co;
+    wf_off[li] = wo;
+    wo += wf_size(li);
+    wd_off[li] = wo;
+    wo += wd_size(li);
   }
   const int64_t P = o;
+  net->wp_size = wo;
   int r = GS2D_OK;
   if (r == GS2D_OK) r = dev_alloc((void**)&net->theta, P * sizeof(float));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->m, P * sizeof(float));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->v, P * sizeof(float));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->grad, P * sizeof(float));
-  if (r == GS2D_OK) r = dev_alloc((void**)&net->wb, P * sizeof(uint16_t));
+  if (r == GS2D_OK) r = dev_alloc((void**)&net->wp, wo * sizeof(uint16_t));
+  if (r == GS2D_OK)
+    for (int li = 0; li < 6; ++li) {
+      net->pk.wf[li] = net->wp + wf_off[li];
+      net->pk.wd[li] = wd_size(li) ? net->wp + wd_off[li] : nullptr;
+    }
   for (int i = 0; i < 6 && r == GS2D_OK; ++i) {
     const size_t bytes = (size_t)max_batch * act_size(i - 1) * sizeof(uint16_t);
     r = dev_alloc((void**)&net->act[i], bytes);
     if (r == GS2D_OK) r = dev_alloc((void**)&net->gact[i], bytes);
   }
-  if (r == GS2D_OK) r = dev_alloc((void**)&net->gact[6], (size_t)max_batch * 6 * sizeof(uint16_t));
+  if (r == GS2D_OK) r = dev_alloc((void**)&net->gact[6], (size_t)max_batch * 8 * sizeof(uint16_t));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->out, (size_t)max_batch * 6 * sizeof(float));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->lossbuf, 4 * sizeof(float));
   // warm-start scratch: input [4][60][80], out [8], tau [8], pose0 [12], losses [2]
-  if (r == GS2D_OK) r = dev_alloc((void**)&net->wsf, (act_size(-1) + 64) * sizeof(float));
-  if (r == GS2D_OK) r = ensure_part(net, part_need(max_batch));
+  if (r == GS2D_OK) r = dev_alloc((void**)&net->wsf, (kInPlanar + 64) * sizeof(float));
+  if (r == GS2D_OK) r = ensure_part(net, part_layout(max_batch, nullptr));
+
   if (r == GS2D_OK && (hipMemset(net->theta, 0, P * sizeof(float)) != hipSuccess ||
                        hipMemset(net->m, 0, P * sizeof(float)) != hipSuccess ||
                        hipMemset(net->v, 0, P * sizeof(float)) != hipSuccess ||
-                       hipMemset(net->wb, 0, P * sizeof(uint16_t)) != hipSuccess))
+                       hipMemset(net->wp, 0, wo * sizeof(uint16_t)) != hipSuccess))
     r = GS2D_ERR_HIP;
   if (r != GS2D_OK) {
     gs2d_ws_destroy(net);
@@ -691,7 +1151,7 @@ GS2D_API int gs2d_ws_destroy(gs2d_ws* net) {
                  net->wsf};
   for (float* p : fl)
     if (p) (void)hipFree(p);
-  if (net->wb) (void)hipFree(net->wb);
+  if (net->wp) (void)hipFree(net->wp);
   for (int i = 0; i < 7; ++i) {
     if (net->act[i]) (void)hipFree(net->act[i]);
     if (net->gact[i]) (void)hipFree(net->gact[i]);
@@ -707,7 +1167,7 @@ GS2D_API int gs2d_ws_set_params(gs2d_ws* net, const float* theta, hipStream_t s)
   WS_HIP(hipMemcpyAsync(net->theta, theta, P * sizeof(float), hipMemcpyDeviceToDevice, s));
   WS_HIP(hipMemsetAsync(net->m, 0, P * sizeof(float), s));
   WS_HIP(hipMemsetAsync(net->v, 0, P * sizeof(float), s));
-  to_bf16_kernel<<<(unsigned)((P + 255) / 256), 256, 0, s>>>(net->theta, net->wb, P);
+  pack_kernel<<<cdiv(P, 256), 256, 0, s>>>(net->theta, net->pk, P);
   net->step = 0;
   WS_HIP(hipGetLastError());
   return GS2D_OK;
@@ -727,7 +1187,7 @@ GS2D_API int gs2d_ws_residual(const float* rgb, const float* depth, const float*
   if (width % GS2D_WS_IN_W || height % GS2D_WS_IN_H || width / GS2D_WS_IN_W != height / GS2D_WS_IN_H)
     return GS2D_ERR_UNSUPPORTED;
   const int f = width / GS2D_WS_IN_W;
-  const int64_t n = (int64_t)batch * act_size(-1);
+  const int64_t n = (int64_t)batch * kInPlanar;
   residual_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, width, height, f,
                                                                batch, input);
   WS_HIP(hipGetLastError());
@@ -738,8 +1198,7 @@ GS2D_API int gs2d_ws_forward(gs2d_ws* net, const float* input, int32_t batch, fl
   WS_TRY(check_net(net, batch));
   if (!input || !out) return GS2D_ERR_INVALID_ARG;
   load_input(net, input, batch, s);
-  forward_layers(net, batch, s);
-  WS_HIP(hipMemcpyAsync(out, net->out, (size_t)batch * 6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  forward_layers(net, batch, out, s);
   WS_HIP(hipGetLastError());
   return GS2D_OK;
 }
@@ -749,31 +1208,47 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
   WS_TRY(check_net(net, batch));
   if (!input || !target) return GS2D_ERR_INVALID_ARG;
   const int B = batch;
+  float* outp = out ? out : net->out;
   load_input(net, input, B, s);
-  forward_layers(net, B, s);
-  mse_kernel<<<1, 256, 0, s>>>(net->out, target, B * 6, net->gact[6], net->lossbuf);
-  // fc2: weights, then the masked input gradient of h1
-  WS_TRY(weight_grad(net, 5, B, s));
-  {
-    FcBwdData op{256, 6, net->wb + net->w_off[5], net->gact[6], net->act[5], net->gact[5]};
-    gemm(op, 256, B, 6, 1, s);
+  forward_layers(net, B, outp, s);
+  mse_kernel<<<1, 256, 0, s>>>(outp, target, B * 6, net->gact[6], loss ? loss : net->lossbuf);
+  ReduceTable tab{};
+  // (running the weight gradients on a second stream beside the input-gradient chain
+  // was measured no faster: the GPU is already full)
+  weight_grad(net, 5, B, &tab, s);
+  {  // the masked input gradient of h1
+    FcBwdData op;
+    op.M = 256;
+    op.N = B;
+    op.K = 8;
+    op.ks = kBK;
+    op.wt = net->pk.wd[5];
+    op.gy = net->gact[6];
+    op.x = net->act[5];
+    op.gx = net->gact[5];
+    run_bn<128>(op, 256, B, 1, pick_bn(256, B, 128, 1), s);
   }
-  WS_TRY(weight_grad(net, 4, B, s));
+  weight_grad(net, 4, B, &tab, s);
   {
-    FcBwdData op{2560, 256, net->wb + net->w_off[4], net->gact[5], net->act[4], net->gact[4]};
-    gemm(op, 2560, B, 256, 1, s);
+    FcBwdData op;
+    op.M = 2560;
+    op.N = B;
+    op.K = 256;
+    op.ks = 256;
+    op.wt = net->pk.wd[4];
+    op.gy = net->gact[5];
+    op.x = net->act[4];
+    op.gx = net->gact[4];
+    run_bn<128>(op, 2560, B, 1, pick_bn(2560, B, 128, 1), s);
   }
   for (int li = 3; li >= 0; --li) {
-    WS_TRY(weight_grad(net, li, B, s));
-    if (li > 0) {
-      const ConvShape cs = conv_shape(li, B);
-      // layers 1-3 (the input gradient of layer 0 is not needed) are all 3 x 3
-      ConvBwdData<3> op{cs, net->wb + net->w_off[li], net->gact[li + 1], net->act[li], net->gact[li]};
-      gemm(op, cs.ci, B * cs.H * cs.W, cs.co * 9, 1, s);
-    }
+    weight_grad(net, li, B, &tab, s);
+    // layers 1-3 (the input gradient of layer 0 is not needed) are all 3 x 3
+    if (li > 0) conv_data_grad(net, li, B, s);
   }
-  if (loss) WS_HIP(hipMemcpyAsync(loss, net->lossbuf, sizeof(float), hipMemcpyDeviceToDevice, s));
-  if (out) WS_HIP(hipMemcpyAsync(out, net->out, (size_t)B * 6 * sizeof(float), hipMemcpyDeviceToDevice, s));
+  const ReduceLayer& last = tab.L[tab.n - 1];
+  reduce_parts_kernel<<<last.block0 + cdiv((int64_t)last.M * last.ncol, 64), 256, 0, s>>>(net->part, net->grad,
+                                                                                          tab);
   if (grad)
     WS_HIP(hipMemcpyAsync(grad, net->grad, (size_t)GS2D_WS_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s));
   WS_HIP(hipGetLastError());
@@ -790,7 +1265,7 @@ GS2D_API int gs2d_ws_adamw_step(gs2d_ws* net, const gs2d_ws_adamw* o, hipStream_
   const float c1 = (float)(1.0 - std::pow((double)o->beta1, (double)net->step));
   const float c2 = (float)(1.0 - std::pow((double)o->beta2, (double)net->step));
   const int P = GS2D_WS_PARAMS;
-  adamw_kernel<<<(P + 255) / 256, 256, 0, s>>>(net->theta, net->m, net->v, net->grad, net->wb, P, *o, c1, c2);
+  adamw_kernel<<<(P + 255) / 256, 256, 0, s>>>(net->theta, net->m, net->v, net->grad, net->pk, P, *o, c1, c2);
   WS_HIP(hipGetLastError());
   return GS2D_OK;
 }
@@ -826,7 +1301,7 @@ int propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const g
   float* normal = rgb + 4 * hw;
   float* alpha = rgb + 7 * hw;
   float* input = net->wsf;
-  float* out = input + act_size(-1);
+  float* out = input + kInPlanar;
   float* tau = out + 8;
   uint32_t gen = 0;
   // loss at the start pose and the network's input
@@ -859,7 +1334,7 @@ GS2D_API int gs2d_warm_start(gs2d_ctx* ctx, gs2d_ws* net, const float* params, i
                              const float* pose_start, const float* tgt_rgb, const float* tgt_depth, float lambda_d,
                              int32_t use_masks, float* pose_out, float* info, hipStream_t s) {
   if (!net || !pose_out) return GS2D_ERR_INVALID_ARG;
-  float* pose0 = net->wsf + act_size(-1) + 16;
+  float* pose0 = net->wsf + kInPlanar + 16;
   float* losses = pose0 + 12;
   WS_TRY(propose(ctx, net, params, n, camera, pose_start, tgt_rgb, tgt_depth, lambda_d, use_masks, pose0, losses,
                  s));
