@@ -408,6 +408,7 @@ struct FcFwd : Dims {
   const uint16_t* x;  // [B][I]
   uint16_t* y;        // ReLU + bf16 (hidden layer), or
   float* yf;          // FP32, no ReLU (output layer)
+  bool twist = false; // yf scaled from the normalised twist to (rho in m, phi in rad)
   using APrep = OffPrep;
   using BPrep = OffPrep;
   __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
@@ -417,7 +418,7 @@ struct FcFwd : Dims {
   __device__ void store(int m, int n, float v) const {
     v += bias[m];
     if (yf)
-      yf[(size_t)n * M + m] = v;
+      yf[(size_t)n * M + m] = twist ? v * (m < 3 ? 0.1f : (float)(8.0 * M_PI / 180.0)) : v;
     else
       y[(size_t)n * M + m] = to_bf16(relu(v));
   }
@@ -485,6 +486,8 @@ struct FcBwdWeight : Dims {
 // A forward layer with few output tiles (small batches) and a long reduction: each
 // split-K slice writes FP32 partial sums, and a second kernel adds them in slice
 // order and applies the layer's own epilogue (bias, ReLU, rounding) to the total.
+// (Letting the last of a tile's workgroups add them instead needs device-scope fences,
+// which write back the L2 and were measured several times slower.)
 template <class Op>
 struct SplitPart : Op {
   float* part;
@@ -689,10 +692,72 @@ __global__ void residual_kernel(const float* __restrict__ rgb, const float* __re
   input[i] = s / (float)(f * f);
 }
 
-// tau = denormalised network output (rho x 0.1 m, phi x 8 deg).
-__global__ void denormalise_kernel(const float* __restrict__ out, float* __restrict__ tau) {
-  const int i = threadIdx.x;
-  if (i < 6) tau[i] = out[i] * (i < 3 ? 0.1f : (float)(8.0 * M_PI / 180.0));
+// The proposal's two inputs from one rendered frame in one pass: the network input
+// x[Y][X][c] = bf16 of the block mean of (img - tgt) (channels 0-3 as residual_kernel,
+// 4-7 zero), and part[Y 80 + X] = the block's sum of |d r| + |d g| + |d b| + lambda_d
+// |d depth|, the terms of the unmasked tracking loss.  R8: 8 x 8 blocks (640 x 480
+// frames), one thread per block row (two float4 of each image), the 8 rows added by a
+// butterfly over the 8 lanes of a block; otherwise one thread per f x f block.
+template <bool R8>
+__global__ __launch_bounds__(64) void residual_loss_kernel(const float* __restrict__ rgb,
+                                                           const float* __restrict__ depth,
+                                                           const float* __restrict__ trgb,
+                                                           const float* __restrict__ tdepth, int W, int H, int f,
+                                                           float lambda_d, uint16_t* __restrict__ x,
+                                                           float* __restrict__ part) {
+  constexpr int nb = GS2D_WS_IN_H * GS2D_WS_IN_W;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = R8 ? g >> 3 : g;  // the block (every lane of a block row group is live)
+  if (i >= nb) return;
+  const int Y = i / GS2D_WS_IN_W, X = i - Y * GS2D_WS_IN_W;
+  const size_t hw = (size_t)W * H;
+  float s[4] = {0.f, 0.f, 0.f, 0.f}, a = 0.f;
+  for (int dy = R8 ? (g & 7) : 0; dy < (R8 ? (g & 7) + 1 : f); ++dy) {
+    const size_t row = (size_t)(Y * f + dy) * W + (size_t)X * f;
+    for (int dx = 0; dx < f; ++dx) {
+      float d[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float* img = c < 3 ? rgb + c * hw : depth;
+        const float* tgt = c < 3 ? trgb + c * hw : tdepth;
+        d[c] = img[row + dx] - tgt[row + dx];
+      }
+      a += fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]) + lambda_d * fabsf(d[3]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s[c] += d[c];
+    }
+  }
+  if constexpr (R8) {
+#pragma unroll
+    for (int w = 1; w < 8; w <<= 1) {
+      a += __shfl_xor(a, w, 8);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s[c] += __shfl_xor(s[c], w, 8);
+    }
+    if (g & 7) return;
+  }
+  const float ff = (float)(f * f);
+  uint4 v;
+  v.x = (uint32_t)to_bf16(s[0] / ff) | ((uint32_t)to_bf16(s[1] / ff) << 16);
+  v.y = (uint32_t)to_bf16(s[2] / ff) | ((uint32_t)to_bf16(s[3] / ff) << 16);
+  v.z = v.w = 0u;
+  *reinterpret_cast<uint4*>(x + (size_t)i * kInCp) = v;
+  part[i] = a;
+}
+
+// out = scale x the sum of part[0 .. n) (one workgroup, fixed order).
+__global__ __launch_bounds__(256) void sum_scaled_kernel(const float* __restrict__ part, int n, float scale,
+                                                         float* __restrict__ out) {
+  __shared__ float sh[256];
+  float v = 0.f;
+  for (int i = threadIdx.x; i < n; i += 256) v += part[i];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
 // Keep T_0 unless its loss exceeds the start pose's.
@@ -911,8 +976,9 @@ int64_t part_layout(int B, int64_t* off) {
   return o > (1 << 20) ? o : (1 << 20);
 }
 
-// Forward of `batch` frames whose BF16 input is in act[0]; FP32 output to out [B][6].
-void forward_layers(gs2d_ws* net, int B, float* out, hipStream_t s) {
+// Forward of `batch` frames whose BF16 input is in act[0]; FP32 output to out [B][6],
+// normalised, or (twist) as the twist itself.
+void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) {
   for (int li = 0; li < 4; ++li) {
     const LayerDef& L = kLayers[li];
     const int OH = out_size(L.H, L.k), OW = out_size(L.W, L.k), cp = cp_of(li);
@@ -965,6 +1031,7 @@ void forward_layers(gs2d_ws* net, int B, float* out, hipStream_t s) {
     op.x = net->act[5];
     op.y = nullptr;
     op.yf = out;
+    op.twist = twist;
     gemm_fwd<32>(op, net->part, net->part_cap, s);
   }
 }
@@ -1198,7 +1265,7 @@ GS2D_API int gs2d_ws_forward(gs2d_ws* net, const float* input, int32_t batch, fl
   WS_TRY(check_net(net, batch));
   if (!input || !out) return GS2D_ERR_INVALID_ARG;
   load_input(net, input, batch, s);
-  forward_layers(net, batch, out, s);
+  forward_layers(net, batch, out, false, s);
   WS_HIP(hipGetLastError());
   return GS2D_OK;
 }
@@ -1210,7 +1277,7 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
   const int B = batch;
   float* outp = out ? out : net->out;
   load_input(net, input, B, s);
-  forward_layers(net, B, outp, s);
+  forward_layers(net, B, outp, false, s);
   mse_kernel<<<1, 256, 0, s>>>(outp, target, B * 6, net->gact[6], loss ? loss : net->lossbuf);
   ReduceTable tab{};
   // (running the weight gradients on a second stream beside the input-gradient chain
@@ -1301,16 +1368,28 @@ int propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const g
   float* normal = rgb + 4 * hw;
   float* alpha = rgb + 7 * hw;
   float* input = net->wsf;
-  float* out = input + kInPlanar;
-  float* tau = out + 8;
+  float* tau = input + kInPlanar + 8;
   uint32_t gen = 0;
   // loss at the start pose and the network's input
   WS_TRY(gs2d_render(ctx, params, n, camera, pose_start, rgb, depth, normal, alpha, &gen, s));
-  WS_TRY(gs2d_tracking_loss(ctx, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks, losses,
-                            net->igrad, net->igrad + 3 * hw, s));
-  WS_TRY(gs2d_ws_residual(rgb, depth, tgt_rgb, tgt_depth, W, H, 1, input, s));
-  WS_TRY(gs2d_ws_forward(net, input, 1, out, s));
-  denormalise_kernel<<<1, 64, 0, s>>>(out, tau);
+  if (use_masks) {
+    WS_TRY(gs2d_tracking_loss(ctx, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks,
+                              losses, net->igrad, net->igrad + 3 * hw, s));
+    WS_TRY(gs2d_ws_residual(rgb, depth, tgt_rgb, tgt_depth, W, H, 1, input, s));
+    load_input(net, input, 1, s);
+  } else {  // the unmasked loss and the network's BF16 input in one pass over the frames
+    const int f = W / GS2D_WS_IN_W, nb = GS2D_WS_IN_H * GS2D_WS_IN_W;
+    float* part = net->igrad;  // per-block loss terms (the image-gradient workspace is free here)
+    const float scale = 1.f / (float)hw;
+    if (f == 8)
+      residual_loss_kernel<true><<<cdiv(8 * nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d,
+                                                                  net->act[0], part);
+    else
+      residual_loss_kernel<false><<<cdiv(nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d,
+                                                               net->act[0], part);
+    sum_scaled_kernel<<<1, 256, 0, s>>>(part, nb, scale, losses);
+  }
+  forward_layers(net, 1, tau, true, s);  // the twist itself
   WS_TRY(gs2d_pose_exp(ctx, tau, pose_start, pose0, s));
   return GS2D_OK;
 }
