@@ -21,10 +21,10 @@
 // gradient in the same GEMM.
 //
 //   layer              M        N              K
-//   conv forward       Co       B OH OW        k k Ci'   (Ci' = Ci, or 8 for the 4-channel input)
+//   conv forward       Co       B OH OW        k k Ci    (the 4-channel input: 5 x 3 pairs x 8)
 //   conv input grad    Ci       B H W / 4      taps Co   (one launch per output parity class:
 //                                                         only the stride-2 taps that reach it)
-//   conv weight grad   Co       k k Ci' + 1    B OH OW   (split-K)
+//   conv weight grad   Co       k k Ci + 1     B OH OW   (split-K; the input layer 120 + 1)
 //   fc forward         O        B              I
 //   fc input grad      I        B              O'        (O' = O padded to 8)
 //   fc weight grad     O        I + 1          B         (split-K)
@@ -52,32 +52,35 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBK = 32, kPad = 8, kThreads = 256, kStages = 2;
 constexpr uint16_t kOne = 0x3F80;  // bfloat16 1.0
-constexpr int kInCp = 8;           // input channels as stored (4 used, 4 zero)
+// The input layer's activations are stored with their 4 channels; its reduction index
+// runs (ky, kx pair, kx within the pair, c), so 8 consecutive k are 2 horizontally
+// adjacent pixels of one row (one 16-byte load), the 5 columns of a 5 x 5 kernel
+// taking 3 pairs (the sixth column has zero weights).
+constexpr int kInC = 4, kInPairs = 3, kInK = 5 * kInPairs * 2 * kInC;  // 120
 
-// Round to the nearest bfloat16, ties to even (finite inputs; NaN stays NaN).
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Round to the nearest bfloat16, ties to even (the hardware conversion,
+// v_cvt_pk_bf16_f32, in the default round-to-nearest-even mode with FP32 denormals
+// kept; NaN stays NaN).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t to_bf16x2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, bf16x2{(__bf16)lo, (__bf16)hi});
 }
 // Post-ReLU activations are positive exactly when the sign bit is clear and they are not zero.
 __device__ __forceinline__ bool positive(uint16_t h) { return h != 0 && !(h & 0x8000u); }
-__device__ __forceinline__ uint32_t pack2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
 __device__ __forceinline__ float relu(float v) { return v > 0.f ? v : 0.f; }
 // 4 consecutive BF16 values: y[0..3] = bf16(relu(v + bias)) (8-byte aligned destination).
 __device__ __forceinline__ void store_relu4(uint16_t* y, const float* bias, f32x4 v) {
   const float4 b = *reinterpret_cast<const float4*>(bias);
-  *reinterpret_cast<uint2*>(y) = uint2{pack2(to_bf16(relu(v[0] + b.x)), to_bf16(relu(v[1] + b.y))),
-                                       pack2(to_bf16(relu(v[2] + b.z)), to_bf16(relu(v[3] + b.w)))};
+  *reinterpret_cast<uint2*>(y) = uint2{to_bf16x2(relu(v[0] + b.x), relu(v[1] + b.y)),
+                                       to_bf16x2(relu(v[2] + b.z), relu(v[3] + b.w))};
 }
 // 4 consecutive BF16 input gradients masked by the ReLU of the input x (8-byte aligned).
 __device__ __forceinline__ void store_masked4(uint16_t* gx, const uint16_t* x, f32x4 v) {
   const uint2 xv = *reinterpret_cast<const uint2*>(x);
   const uint16_t x0 = (uint16_t)xv.x, x1 = (uint16_t)(xv.x >> 16), x2 = (uint16_t)xv.y, x3 = (uint16_t)(xv.y >> 16);
-  *reinterpret_cast<uint2*>(gx) =
-      uint2{pack2(to_bf16(positive(x0) ? v[0] : 0.f), to_bf16(positive(x1) ? v[1] : 0.f)),
-            pack2(to_bf16(positive(x2) ? v[2] : 0.f), to_bf16(positive(x3) ? v[3] : 0.f))};
+  *reinterpret_cast<uint2*>(gx) = uint2{to_bf16x2(positive(x0) ? v[0] : 0.f, positive(x1) ? v[1] : 0.f),
+                                        to_bf16x2(positive(x2) ? v[2] : 0.f, positive(x3) ? v[3] : 0.f)};
 }
 
 // The workgroup's extent of a plain GEMM, blockIdx.z selecting a split-K slice of ks steps.
@@ -279,7 +282,8 @@ struct ConvFwd : Dims {
   const float* bias;
   const uint16_t* x;  // [B][H][W][cp]
   uint16_t* y;        // [B][OH][OW][co]
-  int H, W, OH, OW, lc;  // lc = log2 cp
+  int H, W, OH, OW, lc;  // lc = log2 ci
+  FastDiv by_ohw, by_ow;
   using APrep = OffPrep;
   struct BPrep {
     uint32_t off;  // the frame
@@ -288,7 +292,7 @@ struct ConvFwd : Dims {
   __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
   __device__ uint4 a(const APrep& q, int k, bool ok) const { return bload(rsrc(w), ok ? q.off + 2u * k : kOOB); }
   __device__ BPrep b_prep(int n) const {
-    const int ohw = OH * OW, b = n / ohw, r = n - b * ohw, oy = r / OW, ox = r - oy * OW;
+    const int b = by_ohw.div(n), r = n - b * (OH * OW), oy = by_ow.div(r), ox = r - oy * OW;
     return {((uint32_t)(b * H * W) << lc) * 2u, 2 * oy - KS / 2, 2 * ox - KS / 2};
   }
   __device__ uint4 b(const BPrep& q, int k, bool ok) const {
@@ -300,6 +304,78 @@ struct ConvFwd : Dims {
   __device__ void store(int m, int n, float v) const { y[(size_t)n * M + m] = to_bf16(relu(v + bias[m])); }
   __device__ void store4(int m, int n, f32x4 v, int rows) const {  // co % 4 == 0: rows == 4
     store_relu4(y + (size_t)n * M + m, bias + m, v);
+  }
+};
+
+// The input layer, 5 x 5, stride 2, zero padding 2, over the 4-channel input:
+// y = bf16(relu(conv(x, w) + bias)); M = co, N = B OH OW, K = 120 (kInK).
+struct ConvFwdIn : Dims {
+  static constexpr bool kAk = true, kBk = true;
+  const uint16_t* w;  // [co][5][3][2][4]
+  const float* bias;
+  const uint16_t* x;  // [B][H][W][4]
+  uint16_t* y;        // [B][OH][OW][co]
+  int H, W, OH, OW;
+  FastDiv by_ohw, by_ow;
+  using APrep = OffPrep;
+  struct BPrep {
+    uint32_t off;  // the frame
+    int iy0, ix0;
+  };
+  __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const { return bload(rsrc(w), ok ? q.off + 2u * k : kOOB); }
+  __device__ BPrep b_prep(int n) const {
+    const int b = by_ohw.div(n), r = n - b * (OH * OW), oy = by_ow.div(r), ox = r - oy * OW;
+    return {(uint32_t)(b * H * W * kInC) * 2u, 2 * oy - 2, 2 * ox - 2};
+  }
+  // k = 8 (3 ky + pair): pixels (iy0 + ky, ix0 + 2 pair + 0, 1); ix is even and W
+  // even, so both lie inside or both outside
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const {
+    const int r = k >> 3, ky = r / kInPairs, pr = r - ky * kInPairs;
+    const int iy = q.iy0 + ky, ix = q.ix0 + 2 * pr;
+    ok = ok && (unsigned)iy < (unsigned)H && (unsigned)ix < (unsigned)W;
+    return bload(rsrc(x), ok ? q.off + 2u * (uint32_t)((iy * W + ix) * kInC) : kOOB);
+  }
+  __device__ void store(int m, int n, float v) const { y[(size_t)n * M + m] = to_bf16(relu(v + bias[m])); }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {  // co % 4 == 0: rows == 4
+    store_relu4(y + (size_t)n * M + m, bias + m, v);
+  }
+};
+
+// Weight and bias gradient of the input layer, one split-K slice per blockIdx.z:
+// part[z][co][120 + 1] = sum over pixels n of gy[n][co] [x pair patch | 1].
+struct ConvBwdWeightIn : Dims {
+  static constexpr bool kAk = false, kBk = false;
+  const uint16_t* gy;  // [B][OH][OW][co]
+  const uint16_t* x;   // [B][H][W][4]
+  float* part;
+  int H, W, OH, OW;
+  FastDiv by_ohw, by_ow;
+  using APrep = OffPrep;
+  struct BPrep {
+    int dy, dx;
+    bool bias;
+  };
+  __device__ APrep a_prep(int m8) const { return {(uint32_t)m8 * 2u}; }
+  __device__ uint4 a(const APrep& q, int k, bool ok) const {
+    return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)(k * M) : kOOB);
+  }
+  __device__ BPrep b_prep(int n8) const {
+    const int r = n8 >> 3, ky = r / kInPairs, pr = r - ky * kInPairs;
+    return {ky - 2, 2 * pr - 2, n8 == N - 1};
+  }
+  __device__ uint4 b(const BPrep& q, int k, bool ok) const {
+    if (q.bias) return ok ? uint4{kOne, 0u, 0u, 0u} : uint4{0u, 0u, 0u, 0u};
+    const int b = by_ohw.div(k), r = k - b * (OH * OW), oy = by_ow.div(r), ox = r - oy * OW;
+    const int iy = 2 * oy + q.dy, ix = 2 * ox + q.dx;
+    ok = ok && (unsigned)iy < (unsigned)H && (unsigned)ix < (unsigned)W;
+    return bload(rsrc(x), ok ? 2u * (uint32_t)(((b * H + iy) * W + ix) * kInC) : kOOB);
+  }
+  __device__ void store4(int m, int n, f32x4 v, int rows) const {
+    float* p = part + ((size_t)blockIdx.z * M + m) * N + n;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (q < rows) p[(size_t)q * N] = v[q];
   }
 };
 
@@ -316,6 +392,7 @@ struct ConvBwdData {
   const uint16_t* x;   // [B][H][W][ci], the layer's input (post-ReLU)
   uint16_t* gx;        // [B][H][W][ci]
   int Bn, ci, co, lco, H, W, OH, OW;
+  FastDiv by_per[4], by_wc[4];  // per class: its pixels per frame, its columns
   using APrep = OffPrep;
   struct BPrep {
     uint32_t off;  // the frame
@@ -341,10 +418,18 @@ struct ConvBwdData {
     const int ky = py() ? 2 * ty : 1, kx = px() ? 2 * tx : 1;
     return bload(rsrc(wd), ok ? q.off + 2u * (uint32_t)((ky * 3 + kx) * co + (k & (co - 1))) : kOOB);
   }
+  // n -> (frame, class row, class column)
+  __device__ void split(int n, int& b, int& jy, int& jx) const {
+    const int Hc = (H - py() + 1) >> 1, Wc = (W - px() + 1) >> 1;
+    b = by_per[blockIdx.z].div(n);
+    const int r = n - b * (Hc * Wc);
+    jy = by_wc[blockIdx.z].div(r);
+    jx = r - jy * Wc;
+  }
   __device__ BPrep b_prep(int n) const {
-    const int Hc = (H - py() + 1) >> 1, Wc = (W - px() + 1) >> 1, per = Hc * Wc;
-    const int b = n / per, r = n - b * per, jy = r / Wc;
-    return {(uint32_t)(b * OH * OW * co) * 2u, jy, r - jy * Wc};
+    int b, jy, jx;
+    split(n, b, jy, jx);
+    return {(uint32_t)(b * OH * OW * co) * 2u, jy, jx};
   }
   __device__ uint4 b(const BPrep& q, int k, bool ok) const {
     int ty, tx;
@@ -354,8 +439,8 @@ struct ConvBwdData {
     return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)((oy * OW + ox) * co + (k & (co - 1))) : kOOB);
   }
   __device__ void store4(int m, int n, f32x4 v, int rows) const {  // ci % 4 == 0: rows == 4
-    const int Hc = (H - py() + 1) >> 1, Wc = (W - px() + 1) >> 1, per = Hc * Wc;
-    const int b = n / per, r = n - b * per, jy = r / Wc, jx = r - jy * Wc;
+    int b, jy, jx;
+    split(n, b, jy, jx);
     const size_t idx = (((size_t)b * H + 2 * jy + py()) * W + 2 * jx + px()) * ci + m;
     store_masked4(gx + idx, x + idx, v);
   }
@@ -510,11 +595,12 @@ __global__ void split_finish_kernel(Op op, const float* __restrict__ part, int S
 }
 
 // How a weight-gradient column j (of ncol - 1) maps to the parameter layout: conv
-// columns run (ky, kx, c) over cp >= ci channels (c >= ci: padding, dropped) into
-// [co][ci][ky][kx]; fc1 columns run (y, x, c) over the [128][4][5] feature map into
-// the flattened (c, y, x) order; fc2 columns map one to one.
+// columns run (ky, kx, c) into [co][ci][ky][kx]; the input layer's run (ky, kx pair,
+// kx within the pair, c), the sixth column of the pairs dropped; fc1 columns run
+// (y, x, c) over the [128][4][5] feature map into the flattened (c, y, x) order; fc2
+// columns map one to one.
 struct GradMap {
-  int kind;  // 0 conv, 1 fc1, 2 fc2
+  int kind;  // 0 conv, 1 fc1, 2 fc2, 3 the input layer's pairs
   int ks, lc, ci;
 };
 
@@ -523,43 +609,51 @@ struct GradMap {
 // workgroups block0 .. of the reduction grid.
 struct ReduceLayer {
   int64_t off, w_off, b_off;
-  int S, M, ncol, block0;
+  int S, M, ncol, block0, zl;  // zl: lanes adding one output's slices (4, or 16 from 128 slices)
   GradMap map;
+  float* dst;   // not NULL: the sums (times scale) go to dst[0 .. M ncol) instead
+  float scale;
 };
 struct ReduceTable {
-  ReduceLayer L[6];
+  ReduceLayer L[7];  // the five GEMM layers, fc2 (from the head) and the loss
   int n;
 };
 
-// grad[w][m][...] and grad[b][m] = the sum of the split-K partials: 64 outputs per
-// workgroup, wave w adding slices w, w + 4, w + 8, ... in order, then the four wave
-// sums in wave order (a fixed order: deterministic).
+// grad[w][m][...] and grad[b][m] = the sum of the split-K partials: 256 / zl outputs per
+// workgroup, lane group g < zl adding slices g, g + zl, g + 2 zl, ... in order, then the
+// zl group sums in group order (a fixed order: deterministic).
 __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restrict__ part, float* __restrict__ grad,
                                                            ReduceTable tab) {
-  __shared__ float red[4][64];
+  __shared__ float red[256];
   int l = 0;
   while (l + 1 < tab.n && (int)blockIdx.x >= tab.L[l + 1].block0) ++l;
   const ReduceLayer& R = tab.L[l];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int opb = 256 / R.zl, ol = threadIdx.x % opb, zg = threadIdx.x / opb;
   const int64_t MN = (int64_t)R.M * R.ncol;
-  const int64_t i = (int64_t)(blockIdx.x - R.block0) * 64 + lane;
+  const int64_t i = (int64_t)(blockIdx.x - R.block0) * opb + ol;
   float s = 0.f;
   if (i < MN) {
     const float* __restrict__ p = part + R.off + i;
-    int z = w;
-    for (; z + 12 < R.S; z += 16) {
-      const float v0 = p[z * MN], v1 = p[(z + 4) * MN], v2 = p[(z + 8) * MN], v3 = p[(z + 12) * MN];
+    const int zl = R.zl;
+    int z = zg;
+    for (; z + 3 * zl < R.S; z += 4 * zl) {
+      const float v0 = p[z * MN], v1 = p[(z + zl) * MN], v2 = p[(z + 2 * zl) * MN], v3 = p[(z + 3 * zl) * MN];
       s += v0;
       s += v1;
       s += v2;
       s += v3;
     }
-    for (; z < R.S; z += 4) s += p[z * MN];
+    for (; z < R.S; z += zl) s += p[z * MN];
   }
-  red[w][lane] = s;
+  red[threadIdx.x] = s;
   __syncthreads();
-  if (w != 0 || i >= MN) return;
-  s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  if (zg != 0 || i >= MN) return;
+  s = red[ol];
+  for (int g = 1; g < R.zl; ++g) s += red[g * opb + ol];
+  if (R.dst) {
+    R.dst[i] = s * R.scale;
+    return;
+  }
   const int ncol = R.ncol, m = (int)(i / ncol), j = (int)(i - (int64_t)m * ncol);
   if (j == ncol - 1) {
     grad[R.b_off + m] = s;
@@ -569,7 +663,10 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restri
   const GradMap& map = R.map;
   if (map.kind == 0) {
     const int tap = j >> map.lc, c = j & ((1 << map.lc) - 1), ky = tap / map.ks, kx = tap - ky * map.ks;
-    if (c < map.ci) gw[(((size_t)m * map.ci + c) * map.ks + ky) * map.ks + kx] = s;
+    gw[(((size_t)m * map.ci + c) * map.ks + ky) * map.ks + kx] = s;
+  } else if (map.kind == 3) {
+    const int r = j >> 3, ky = r / kInPairs, kx = 2 * (r - ky * kInPairs) + ((j >> 2) & 1), c = j & 3;
+    if (kx < 5) gw[(((size_t)m * kInC + c) * 5 + ky) * 5 + kx] = s;
   } else if (map.kind == 1) {
     const int yx = j >> 7, c = j & 127;
     gw[(size_t)m * (ncol - 1) + c * 20 + yx] = s;
@@ -579,9 +676,10 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restri
 }
 
 // The BF16 copies of the weights, in the layouts the GEMMs read:
-//   wf[l]: conv [co][k][k][cp]; fc1 [256][(y, x, c)]; fc2 [6][256]
-//   wd[l]: conv [ci][k][k][co] (layers 1-3); fc1 [(y, x, c)][256]; fc2 [256][8]
-// Entries no weight maps to (the input's padding channels, fc2's columns 6, 7) stay zero.
+//   wf[l]: the input layer [co][5][3][2][4]; conv [co][k][k][ci]; fc1 [256][(y, x, c)];
+//          fc2 [6][256]
+//   wd[l]: conv [ci][k][k][co] (layers 1-3); fc1 [(y, x, c)][256]
+// Entries no weight maps to (the input layer's sixth column) stay zero.
 struct Packed {
   uint16_t* wf[6];
   uint16_t* wd[6];
@@ -594,13 +692,15 @@ __device__ void pack_weight(const Packed& pk, int64_t i, float v) {
   if (i >= pk.b_off[li]) return;  // a bias: read in FP32
   const int64_t r = i - pk.w_off[li];
   const uint16_t h = to_bf16(v);
-  if (li < 4) {
-    const int ci = li == 0 ? 4 : (li == 1 ? 32 : (li == 2 ? 64 : 128));
-    const int co = li == 0 ? 32 : (li == 1 ? 64 : 128), k = li == 0 ? 5 : 3, kk = k * k;
-    const int cp = li == 0 ? kInCp : ci;
-    const int o = (int)(r / (ci * kk)), rem = (int)(r - (int64_t)o * ci * kk), c = rem / kk, tap = rem - c * kk;
-    pk.wf[li][((size_t)o * kk + tap) * cp + c] = h;
-    if (li > 0) pk.wd[li][((size_t)c * kk + tap) * co + o] = h;
+  if (li == 0) {
+    const int o = (int)(r / 100), rem = (int)(r - (int64_t)o * 100), c = rem / 25, tap = rem - c * 25;
+    const int ky = tap / 5, kx = tap - ky * 5;
+    pk.wf[0][(size_t)o * kInK + ((ky * kInPairs + (kx >> 1)) * 2 + (kx & 1)) * kInC + c] = h;
+  } else if (li < 4) {
+    const int ci = li == 1 ? 32 : (li == 2 ? 64 : 128), co = li == 1 ? 64 : 128;
+    const int o = (int)(r / (ci * 9)), rem = (int)(r - (int64_t)o * ci * 9), c = rem / 9, tap = rem - c * 9;
+    pk.wf[li][((size_t)o * 9 + tap) * ci + c] = h;
+    pk.wd[li][((size_t)c * 9 + tap) * co + o] = h;
   } else if (li == 4) {
     const int o = (int)(r / 2560), in = (int)(r - (int64_t)o * 2560), c = in / 20, yx = in - c * 20;
     const int j = yx * 128 + c;
@@ -609,7 +709,6 @@ __device__ void pack_weight(const Packed& pk, int64_t i, float v) {
   } else {
     const int o = (int)(r / 256), in = (int)(r - (int64_t)o * 256);
     pk.wf[5][(size_t)o * 256 + in] = h;
-    pk.wd[5][(size_t)in * 8 + o] = h;
   }
 }
 
@@ -618,40 +717,92 @@ __global__ void pack_kernel(const float* __restrict__ theta, Packed pk, int64_t 
   if (i < n) pack_weight(pk, i, theta[i]);
 }
 
-// FP32 input [B][4][60][80] -> BF16 [B][60][80][8], channels 4-7 zero.
+// FP32 input [B][4][60][80] -> BF16 [B][60][80][4].
 __global__ void load_input_kernel(const float* __restrict__ in, uint16_t* __restrict__ x, int64_t npix) {
   constexpr int hw = GS2D_WS_IN_H * GS2D_WS_IN_W;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= npix) return;
   const int64_t b = i / hw, q = i - b * hw;
   const float* p = in + b * GS2D_WS_IN_C * hw + q;
-  uint4 v;
-  v.x = (uint32_t)to_bf16(p[0]) | ((uint32_t)to_bf16(p[hw]) << 16);
-  v.y = (uint32_t)to_bf16(p[2 * hw]) | ((uint32_t)to_bf16(p[3 * hw]) << 16);
-  v.z = v.w = 0u;
-  *reinterpret_cast<uint4*>(x + i * kInCp) = v;
+  *reinterpret_cast<uint2*>(x + i * kInC) = uint2{to_bf16x2(p[0], p[hw]), to_bf16x2(p[2 * hw], p[3 * hw])};
 }
 
-// Mean squared error over n = B x 6 values (one workgroup, fixed-order sums), its
-// gradient 2 d / n rounded to bfloat16 into rows of 8 (the last two zero), and the
-// FP32 loss.
-__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ out, const float* __restrict__ target,
-                                                  int n, uint16_t* __restrict__ gout, float* __restrict__ loss) {
-  __shared__ float sh[256];
-  float s = 0.f;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    const float d = out[i] - target[i];
-    s = fmaf(d, d, s);
-    gout[(i / 6) * 8 + i % 6] = to_bf16(2.0f * d / (float)n);
+// The network's output layer in training, for kHeadFrames frames per workgroup (two
+// per wave; lane l holds inputs 4l .. 4l + 3 of the 256): fc2's forward, out = w2 h1 +
+// b2; the squared error against the target; the loss gradient 2 d / n (n = 6 B)
+// rounded to bfloat16; fc2's input gradient, bf16(w2^T g [h1 > 0]); and fc2's weight
+// and bias gradient and the squared error summed over the workgroup's frames in a
+// fixed order (partials part[blk][6][257] and loss_part[blk], added with the other
+// layers' partials).
+constexpr int kHeadFrames = 8;
+__device__ __forceinline__ float bf16_at(uint32_t w, int hi) { return __uint_as_float(hi ? w & 0xFFFF0000u : w << 16); }
+
+__global__ __launch_bounds__(256) void head_kernel(const uint16_t* __restrict__ h1, const uint16_t* __restrict__ w2,
+                                                   const float* __restrict__ b2, const float* __restrict__ target,
+                                                   int B, float* __restrict__ out, uint16_t* __restrict__ gh1,
+                                                   float* __restrict__ part, float* __restrict__ loss_part) {
+  __shared__ float red[4][6][256];
+  __shared__ float redb[4][8];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const float n = (float)(6 * B);
+  float wv[6][4];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    const uint2 q = *reinterpret_cast<const uint2*>(w2 + o * 256 + 4 * l);
+    wv[o][0] = bf16_at(q.x, 0);
+    wv[o][1] = bf16_at(q.x, 1);
+    wv[o][2] = bf16_at(q.y, 0);
+    wv[o][3] = bf16_at(q.y, 1);
   }
-  for (int b = threadIdx.x; b < n / 6; b += 256) gout[b * 8 + 6] = gout[b * 8 + 7] = 0;
-  sh[threadIdx.x] = s;
+  float acc[6][4] = {}, db[6] = {}, lsum = 0.f;
+  for (int f = 0; f < 2; ++f) {
+    const int b = blockIdx.x * kHeadFrames + w * 2 + f;
+    if (b >= B) break;  // uniform over the wave
+    const uint2 hq = *reinterpret_cast<const uint2*>(h1 + (size_t)b * 256 + 4 * l);
+    const float h[4] = {bf16_at(hq.x, 0), bf16_at(hq.x, 1), bf16_at(hq.y, 0), bf16_at(hq.y, 1)};
+    float g[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+      float y = h[0] * wv[o][0];
+      y = fmaf(h[1], wv[o][1], y);
+      y = fmaf(h[2], wv[o][2], y);
+      y = fmaf(h[3], wv[o][3], y);
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) y += __shfl_xor(y, m, 64);
+      const float v = y + b2[o];
+      if (l == 0) out[(size_t)b * 6 + o] = v;
+      const float d = v - target[(size_t)b * 6 + o];
+      lsum = fmaf(d, d, lsum);
+      g[o] = __uint_as_float((uint32_t)to_bf16(2.0f * d / n) << 16);
+      db[o] += g[o];
+    }
+    float gi[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float v = wv[0][e] * g[0];
+#pragma unroll
+      for (int o = 1; o < 6; ++o) v = fmaf(wv[o][e], g[o], v);
+      gi[e] = h[e] > 0.f ? v : 0.f;
+#pragma unroll
+      for (int o = 0; o < 6; ++o) acc[o][e] = fmaf(g[o], h[e], acc[o][e]);
+    }
+    *reinterpret_cast<uint2*>(gh1 + (size_t)b * 256 + 4 * l) = uint2{to_bf16x2(gi[0], gi[1]), to_bf16x2(gi[2], gi[3])};
+  }
+#pragma unroll
+  for (int o = 0; o < 6; ++o)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[w][o][4 * l + e] = acc[o][e];
+  if (l == 0) {
+#pragma unroll
+    for (int o = 0; o < 6; ++o) redb[w][o] = db[o];
+    redb[w][6] = lsum;
+  }
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && loss) *loss = sh[0] / (float)n;
+  float* p = part + (size_t)blockIdx.x * 6 * 257;
+#pragma unroll
+  for (int o = 0; o < 6; ++o) p[o * 257 + t] = ((red[0][o][t] + red[1][o][t]) + red[2][o][t]) + red[3][o][t];
+  if (t < 6) p[t * 257 + 256] = ((redb[0][t] + redb[1][t]) + redb[2][t]) + redb[3][t];
+  if (t == 6) loss_part[blockIdx.x] = ((redb[0][6] + redb[1][6]) + redb[2][6]) + redb[3][6];
 }
 
 // AdamW on the FP32 master vector (bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t from
@@ -693,8 +844,8 @@ __global__ void residual_kernel(const float* __restrict__ rgb, const float* __re
 }
 
 // The proposal's two inputs from one rendered frame in one pass: the network input
-// x[Y][X][c] = bf16 of the block mean of (img - tgt) (channels 0-3 as residual_kernel,
-// 4-7 zero), and part[Y 80 + X] = the block's sum of |d r| + |d g| + |d b| + lambda_d
+// x[Y][X][c] = bf16 of the block mean of (img - tgt) (channels as residual_kernel),
+// and part[Y 80 + X] = the block's sum of |d r| + |d g| + |d b| + lambda_d
 // |d depth|, the terms of the unmasked tracking loss.  R8: 8 x 8 blocks (640 x 480
 // frames), one thread per block row (two float4 of each image), the 8 rows added by a
 // butterfly over the 8 lanes of a block; otherwise one thread per f x f block.
@@ -737,11 +888,8 @@ __global__ __launch_bounds__(64) void residual_loss_kernel(const float* __restri
     if (g & 7) return;
   }
   const float ff = (float)(f * f);
-  uint4 v;
-  v.x = (uint32_t)to_bf16(s[0] / ff) | ((uint32_t)to_bf16(s[1] / ff) << 16);
-  v.y = (uint32_t)to_bf16(s[2] / ff) | ((uint32_t)to_bf16(s[3] / ff) << 16);
-  v.z = v.w = 0u;
-  *reinterpret_cast<uint4*>(x + (size_t)i * kInCp) = v;
+  *reinterpret_cast<uint2*>(x + (size_t)i * kInC) = uint2{to_bf16x2(s[0] / ff, s[1] / ff),
+                                                          to_bf16x2(s[2] / ff, s[3] / ff)};
   part[i] = a;
 }
 
@@ -786,7 +934,6 @@ int out_size(int n, int k) { return (n + 2 * (k / 2) - k) / 2 + 1; }
 int64_t layer_weights(const LayerDef& L) {
   return L.k ? (int64_t)L.co * L.ci * L.k * L.k : (int64_t)L.co * L.ci;
 }
-int cp_of(int li) { return li == 0 ? kInCp : kLayers[li].ci; }
 int log2i(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -798,7 +945,7 @@ FastDiv fast_div(int d) {
   return FastDiv{(uint32_t)m, (uint32_t)(m >> 32), l};
 }
 int64_t act_size(int li) {  // per frame, output of layer li (li = -1: the input as stored)
-  if (li < 0) return (int64_t)kInCp * GS2D_WS_IN_H * GS2D_WS_IN_W;
+  if (li < 0) return (int64_t)kInC * GS2D_WS_IN_H * GS2D_WS_IN_W;
   const LayerDef& L = kLayers[li];
   if (L.k) return (int64_t)L.co * out_size(L.H, L.k) * out_size(L.W, L.k);
   return L.co;
@@ -806,12 +953,13 @@ int64_t act_size(int li) {  // per frame, output of layer li (li = -1: the input
 // BF16 copies: forward and input-gradient layouts of each layer.
 int64_t wf_size(int li) {
   const LayerDef& L = kLayers[li];
-  return L.k ? (int64_t)L.co * L.k * L.k * cp_of(li) : (int64_t)L.co * L.ci;
+  if (li == 0) return (int64_t)L.co * kInK;
+  return L.k ? (int64_t)L.co * L.k * L.k * L.ci : (int64_t)L.co * L.ci;
 }
 int64_t wd_size(int li) {
   const LayerDef& L = kLayers[li];
   if (L.k) return li == 0 ? 0 : (int64_t)L.ci * L.k * L.k * L.co;
-  return (int64_t)L.ci * (li == 5 ? 8 : L.co);
+  return li == 5 ? 0 : (int64_t)L.ci * L.co;
 }
 
 int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -841,14 +989,14 @@ void run_bn(const Op& op, int M, int N, int gz, int bn, hipStream_t s) {
 }
 
 // A forward layer: large outputs as one GEMM (tile columns by pick_bn); few output
-// tiles with a long reduction split over about 128 workgroups.
+// tiles with a long reduction split into slices whose sums a second kernel adds.
 template <int BM, class Op>
 void gemm_fwd(Op op, float* part, int64_t part_cap, hipStream_t s) {
   const int M = op.M, N = op.N, K = op.K;
   const int tiles = cdiv(N, 64) * cdiv(M, BM);
-  if (tiles < 64 && K >= 512) {
+  if (tiles < 64 && K >= 512) {  // (also splitting layers of 64-256 tiles was measured no faster)
     int S = K / 128;
-    const int want = cdiv(128, tiles);
+    const int want = cdiv(128, tiles);  // about 128 workgroups
     S = S < want ? S : want;
     const int ks = cdiv(cdiv(K, S), kBK) * kBK;
     S = cdiv(K, ks);
@@ -867,12 +1015,12 @@ void gemm_fwd(Op op, float* part, int64_t part_cap, hipStream_t s) {
   run_bn<BM>(op, M, N, 1, pick_bn(M, N, BM, 1), s);
 }
 
-// Split-K slices of a weight-gradient GEMM: about 512 workgroups, at most 128 slices,
+// Split-K slices of a weight-gradient GEMM: about 512 workgroups, at most 256 slices,
 // at least 512 reduction indices each.
 int wgrad_splits(int M, int N, int64_t K, int BM, int BN, int* ks_out) {
   const int tiles = cdiv(N, BN) * cdiv(M, BM);
   int64_t S = cdiv(512, tiles);
-  if (S > 128) S = 128;
+  if (S > 256) S = 256;
   const int64_t smax = K / 512 > 1 ? K / 512 : 1;
   if (S > smax) S = smax;
   if (S < 1) S = 1;
@@ -895,8 +1043,8 @@ struct gs2d_ws {
   uint16_t* wp = nullptr;   // BF16 copies (pk's layouts)
   int64_t wp_size = 0;
   gs2d::ws::Packed pk = {};
-  uint16_t* act[7] = {};    // BF16 activations, channels last: input, conv1..4, fc1 ([max_batch] frames each)
-  uint16_t* gact[7] = {};   // BF16 gradients of the same (fc2's output gradient in rows of 8)
+  uint16_t* act[6] = {};    // BF16 activations, channels last: input, conv1..4, fc1 ([max_batch] frames each)
+  uint16_t* gact[6] = {};   // BF16 gradients of the same (masked by the ReLU: the pre-ReLU gradient)
   float* out = nullptr;     // FP32 [max_batch][6]
   float* part = nullptr;    // split-K partials
   int64_t part_cap = 0;
@@ -953,7 +1101,7 @@ void wgrad_shape(int li, int B, int* M, int* N, int64_t* K) {
   const LayerDef& L = kLayers[li];
   *M = L.co;
   if (L.k) {
-    *N = L.k * L.k * cp_of(li) + 1;
+    *N = (li == 0 ? kInK : L.k * L.k * L.ci) + 1;
     *K = (int64_t)B * out_size(L.H, L.k) * out_size(L.W, L.k);
   } else {
     *N = L.ci + 1;
@@ -966,26 +1114,31 @@ void wgrad_shape(int li, int B, int* M, int* N, int64_t* K) {
 // the split forward layers of small batches use the start of the buffer.
 int64_t part_layout(int B, int64_t* off) {
   int64_t o = 0;
-  for (int li = 0; li < 6; ++li) {
+  for (int li = 0; li < 5; ++li) {
     int M, N;
     int64_t K;
     wgrad_shape(li, B, &M, &N, &K);
     if (off) off[li] = o;
     o += (int64_t)wgrad_splits(M, N, K, wgrad_bm(li), wgrad_bn(li), nullptr) * M * N;
   }
+  const int64_t hb = cdiv(B, kHeadFrames);  // fc2 and the loss: one partial per head workgroup
+  if (off) off[5] = o;
+  o += hb * 6 * 257;
+  if (off) off[6] = o;
+  o += hb;
   return o > (1 << 20) ? o : (1 << 20);
 }
 
-// Forward of `batch` frames whose BF16 input is in act[0]; FP32 output to out [B][6],
-// normalised, or (twist) as the twist itself.
+// Forward of `batch` frames whose BF16 input is in act[0] up to fc1, then (out not
+// NULL) fc2: FP32 output to out [B][6], normalised, or (twist) as the twist itself.
 void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) {
   for (int li = 0; li < 4; ++li) {
     const LayerDef& L = kLayers[li];
-    const int OH = out_size(L.H, L.k), OW = out_size(L.W, L.k), cp = cp_of(li);
+    const int OH = out_size(L.H, L.k), OW = out_size(L.W, L.k);
     auto fill = [&](auto& op) {
       op.M = L.co;
       op.N = B * OH * OW;
-      op.K = L.k * L.k * cp;
+      op.K = li == 0 ? kInK : L.k * L.k * L.ci;
       op.w = net->pk.wf[li];
       op.bias = net->theta + net->pk.b_off[li];
       op.x = net->act[li];
@@ -994,15 +1147,17 @@ void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) 
       op.W = L.W;
       op.OH = OH;
       op.OW = OW;
-      op.lc = log2i(cp);
+      op.by_ohw = fast_div(OH * OW);
+      op.by_ow = fast_div(OW);
     };
     if (li == 0) {
-      ConvFwd<5> op;
+      ConvFwdIn op;
       fill(op);
       gemm_fwd<32>(op, net->part, net->part_cap, s);
     } else {
       ConvFwd<3> op;
       fill(op);
+      op.lc = log2i(L.ci);
       if (li == 1)
         gemm_fwd<64>(op, net->part, net->part_cap, s);
       else
@@ -1021,7 +1176,7 @@ void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) 
     op.yf = nullptr;
     gemm_fwd<128>(op, net->part, net->part_cap, s);
   }
-  {
+  if (out) {
     FcFwd op;
     op.M = 6;
     op.N = B;
@@ -1036,12 +1191,35 @@ void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) 
   }
 }
 
+// Appends a GEMM's split-K partials (S slices of M x ncol at part + off) to the table.
+void add_reduce(ReduceTable* tab, int64_t off, int64_t w_off, int64_t b_off, int S, int M, int ncol, GradMap map,
+                float* dst, float scale) {
+  ReduceLayer& R = tab->L[tab->n];
+  R.off = off;
+  R.w_off = w_off;
+  R.b_off = b_off;
+  R.S = S;
+  R.M = M;
+  R.ncol = ncol;
+  R.zl = S >= 128 ? 16 : 4;
+  if (tab->n) {
+    const ReduceLayer& P = tab->L[tab->n - 1];
+    R.block0 = P.block0 + cdiv((int64_t)P.M * P.ncol, 256 / P.zl);
+  } else {
+    R.block0 = 0;
+  }
+  R.map = map;
+  R.dst = dst;
+  R.scale = scale;
+  tab->n += 1;
+}
+
 template <int BM, class Op>
 void wgrad_run(gs2d_ws* net, Op op, int li, int B, ReduceTable* tab, hipStream_t s) {
   int M, N;
   int64_t K;
   wgrad_shape(li, B, &M, &N, &K);
-  int64_t off[6];
+  int64_t off[7];
   part_layout(B, off);
   int ks = 0;
   const int bn = wgrad_bn(li);
@@ -1056,17 +1234,8 @@ void wgrad_run(gs2d_ws* net, Op op, int li, int B, ReduceTable* tab, hipStream_t
   else
     run<BM, 64>(op, M, N, S, s);
   const LayerDef& L = kLayers[li];
-  ReduceLayer& R = tab->L[tab->n];
-  R.off = off[li];
-  R.w_off = net->pk.w_off[li];
-  R.b_off = net->pk.b_off[li];
-  R.S = S;
-  R.M = M;
-  R.ncol = N;
-  R.block0 = tab->n ? tab->L[tab->n - 1].block0 + cdiv((int64_t)tab->L[tab->n - 1].M * tab->L[tab->n - 1].ncol, 64)
-                    : 0;
-  R.map = GradMap{L.k ? 0 : (li == 4 ? 1 : 2), L.k, log2i(cp_of(li)), L.ci};
-  tab->n += 1;
+  add_reduce(tab, off[li], net->pk.w_off[li], net->pk.b_off[li], S, M, N,
+             GradMap{li == 0 ? 3 : (L.k ? 0 : 1), L.k, log2i(L.ci), L.ci}, nullptr, 1.f);
 }
 
 void weight_grad(gs2d_ws* net, int li, int B, ReduceTable* tab, hipStream_t s) {
@@ -1079,31 +1248,28 @@ void weight_grad(gs2d_ws* net, int li, int B, ReduceTable* tab, hipStream_t s) {
       op.W = L.W;
       op.OH = out_size(L.H, L.k);
       op.OW = out_size(L.W, L.k);
-      op.lc = log2i(cp_of(li));
       op.by_ohw = fast_div(op.OH * op.OW);
       op.by_ow = fast_div(op.OW);
     };
     if (li == 0) {
-      ConvBwdWeight<5> op;
+      ConvBwdWeightIn op;
       fill(op);
       wgrad_run<32>(net, op, li, B, tab, s);
     } else {
       ConvBwdWeight<3> op;
       fill(op);
+      op.lc = log2i(L.ci);
       if (li == 1)
         wgrad_run<64>(net, op, li, B, tab, s);
       else
         wgrad_run<128>(net, op, li, B, tab, s);
     }
-  } else {
+  } else {  // fc1 (fc2's comes from the head kernel)
     FcBwdWeight op;
     op.gy = net->gact[li + 1];
     op.x = net->act[li];
-    op.Op = li == 5 ? 8 : L.co;
-    if (li == 4)
-      wgrad_run<128>(net, op, li, B, tab, s);
-    else
-      wgrad_run<32>(net, op, li, B, tab, s);
+    op.Op = L.co;
+    wgrad_run<128>(net, op, li, B, tab, s);
   }
 }
 
@@ -1123,6 +1289,11 @@ void conv_data_grad(gs2d_ws* net, int li, int B, hipStream_t s) {
   op.W = L.W;
   op.OH = out_size(L.H, 3);
   op.OW = out_size(L.W, 3);
+  for (int z = 0; z < 4; ++z) {
+    const int Hc = (L.H - (z >> 1) + 1) >> 1, Wc = (L.W - (z & 1) + 1) >> 1;
+    op.by_per[z] = fast_div(Hc * Wc);
+    op.by_wc[z] = fast_div(Wc);
+  }
   const int N = B * ((L.H + 1) >> 1) * ((L.W + 1) >> 1);  // the largest class
   if (L.ci == 32)
     run_bn<32>(op, L.ci, N, 4, pick_bn(L.ci, N, 32, 4), s);
@@ -1191,7 +1362,6 @@ GS2D_API int gs2d_ws_create(gs2d_ws** out, int device, int32_t max_batch) {
     r = dev_alloc((void**)&net->act[i], bytes);
     if (r == GS2D_OK) r = dev_alloc((void**)&net->gact[i], bytes);
   }
-  if (r == GS2D_OK) r = dev_alloc((void**)&net->gact[6], (size_t)max_batch * 8 * sizeof(uint16_t));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->out, (size_t)max_batch * 6 * sizeof(float));
   if (r == GS2D_OK) r = dev_alloc((void**)&net->lossbuf, 4 * sizeof(float));
   // warm-start scratch: input [4][60][80], out [8], tau [8], pose0 [12], losses [2]
@@ -1219,7 +1389,7 @@ GS2D_API int gs2d_ws_destroy(gs2d_ws* net) {
   for (float* p : fl)
     if (p) (void)hipFree(p);
   if (net->wp) (void)hipFree(net->wp);
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < 6; ++i) {
     if (net->act[i]) (void)hipFree(net->act[i]);
     if (net->gact[i]) (void)hipFree(net->gact[i]);
   }
@@ -1277,26 +1447,17 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
   const int B = batch;
   float* outp = out ? out : net->out;
   load_input(net, input, B, s);
-  forward_layers(net, B, outp, false, s);
-  mse_kernel<<<1, 256, 0, s>>>(outp, target, B * 6, net->gact[6], loss ? loss : net->lossbuf);
+  forward_layers(net, B, nullptr, false, s);  // up to fc1
+  int64_t off[7];
+  part_layout(B, off);
+  const int hb = cdiv(B, kHeadFrames);
+  head_kernel<<<hb, 256, 0, s>>>(net->act[5], net->pk.wf[5], net->theta + net->pk.b_off[5], target, B, outp,
+                                 net->gact[5], net->part + off[5], net->part + off[6]);
   ReduceTable tab{};
-  // (running the weight gradients on a second stream beside the input-gradient chain
-  // was measured no faster: the GPU is already full)
-  weight_grad(net, 5, B, &tab, s);
-  {  // the masked input gradient of h1
-    FcBwdData op;
-    op.M = 256;
-    op.N = B;
-    op.K = 8;
-    op.ks = kBK;
-    op.wt = net->pk.wd[5];
-    op.gy = net->gact[6];
-    op.x = net->act[5];
-    op.gx = net->gact[5];
-    run_bn<128>(op, 256, B, 1, pick_bn(256, B, 128, 1), s);
-  }
+  add_reduce(&tab, off[5], net->pk.w_off[5], net->pk.b_off[5], hb, 6, 257, GradMap{2, 0, 0, 256}, nullptr, 1.f);
+  add_reduce(&tab, off[6], 0, 0, hb, 1, 1, GradMap{2, 0, 0, 0}, loss ? loss : net->lossbuf, 1.f / (float)(6 * B));
   weight_grad(net, 4, B, &tab, s);
-  {
+  {  // the masked input gradient of the fc1 input (conv4's output)
     FcBwdData op;
     op.M = 2560;
     op.N = B;
@@ -1314,7 +1475,7 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
     if (li > 0) conv_data_grad(net, li, B, s);
   }
   const ReduceLayer& last = tab.L[tab.n - 1];
-  reduce_parts_kernel<<<last.block0 + cdiv((int64_t)last.M * last.ncol, 64), 256, 0, s>>>(net->part, net->grad,
+  reduce_parts_kernel<<<last.block0 + cdiv((int64_t)last.M * last.ncol, 256 / last.zl), 256, 0, s>>>(net->part, net->grad,
                                                                                           tab);
   if (grad)
     WS_HIP(hipMemcpyAsync(grad, net->grad, (size_t)GS2D_WS_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -38,8 +38,9 @@ def first_converged(hist: np.ndarray, gt: np.ndarray) -> int | None:
     return None
 
 
-def time_ms(fn, reps: int = 5) -> float:
-    fn()
+def time_ms(fn, reps: int = 20) -> float:
+    for _ in range(3):
+        fn()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
@@ -83,11 +84,19 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=20)
     ap.add_argument("--first-seed", type=int, default=0)
     ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--time-proposal", type=int, default=0, metavar="N",
+                    help="only time N back-to-back proposals on the first room, then exit")
     a = ap.parse_args(argv)
     rast = Rasterizer()
     net = WarmStartNet(max_batch=1)
     theta = np.load(a.weights, allow_pickle=False).astype(np.float32)
     net.set_params(torch.from_numpy(theta).cuda())
+    if a.time_proposal:
+        c = run_case(rast, net, a.first_seed, a.iters)
+        ms = time_ms(lambda: net.propose(rast, c["P"], CAMERA, c["start"], c["trgb"], c["tdep"]), a.time_proposal)
+        out = {"seed": a.first_seed, "proposal_ms": ms, "calls": a.time_proposal}
+        print(json.dumps(out), flush=True)
+        return out
     cases = []
     ms_iter = ms_warm = None
     for seed in range(a.first_seed, a.first_seed + a.seeds):
