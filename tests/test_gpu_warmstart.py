@@ -78,13 +78,15 @@ def test_ws_forward_exact(wsmod, seed):
     np.testing.assert_array_equal(host(net.params()), theta)
 
 
-@pytest.mark.parametrize("batch", [4, 37])
+@pytest.mark.parametrize("batch", [4, 37, 256])
 def test_ws_gradient_exact(wsmod, batch):
-    """Batch 37 spans several split-K slices and ragged GEMM tiles."""
+    """Batch 37 spans several split-K slices and ragged GEMM tiles; 256 is the training
+    batch, whose layers take the 128-column tiles, the split forward layer and the
+    split-K counts that the training step runs."""
     theta = synth.exact_params(2)
     x = synth.exact_inputs(batch, seed=22)
     tgt = synth.exact_targets(batch, seed=23)
-    net = wsmod.WarmStartNet(max_batch=64)
+    net = wsmod.WarmStartNet(max_batch=max(64, batch))
     net.set_params(dev(theta))
     loss, out, grad = net.gradient(dev(x), dev(tgt))
     loss, out, grad = float(host(loss)[0]), host(out), host(grad)
