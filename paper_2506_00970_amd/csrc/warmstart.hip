@@ -26,8 +26,11 @@
 //                                                         only the stride-2 taps that reach it)
 //   conv weight grad   Co       k k Ci + 1     B OH OW   (split-K; the input layer 120 + 1)
 //   fc forward         O        B              I
-//   fc input grad      I        B              O'        (O' = O padded to 8)
+//   fc input grad      I        B              O
 //   fc weight grad     O        I + 1          B         (split-K)
+//
+// In training, fc2 (256 -> 6) runs as one kernel of its own: forward, squared error,
+// loss gradient, input and weight gradients.
 //
 // MFMA operand layout used (16 x 16 x 32, wave64): lane l supplies row l % 16 of A
 // and column l % 16 of B, each with the 8 consecutive k of group l / 16; the FP32
@@ -98,15 +101,14 @@ struct Dims {
 // BF16 values, zero unless `ok` (the chunk lies inside the matrix).  A k-chunk operand
 // (kAk / kBk) gives the 8 consecutive k of one row: set-up a_prep(row), chunk
 // a(prep, k, ok) (K % 8 == 0).  A row-chunk operand gives 8 consecutive rows at one
-// k: set-up a_prep(first row), chunk a(prep, k, ok); the 8 rows may run past the last
-// row only where the source is padded to 8.
+// k: set-up a_prep(first row), chunk a(prep, k, ok) (M % 8 == 0).
 //
 // k-chunks are stored in LDS row-major ([row][k]) and read as fragments with one
 // 16-byte read.  Row chunks are stored as loaded ([k][row]) and read with two
-// transposing reads (ds_read_b64_tr_b16): in each group of 16 lanes, lane q reads the
-// 4 rows (8 bytes) at row (kb + q / 4), column (m0 + 4 (q % 4)), and lane i receives
-// element i of each of the group's four 16-element rows -- (m0 + i, kb .. kb + 3),
-// the fragment's first or second 4 k.
+// transposing reads (ds_read_b64_tr_b16): in each group of 16 lanes, lane q reads 8
+// bytes (4 elements) of LDS row kb + q / 4 from column m0 + 4 (q % 4), so the group
+// reads 16 columns of 4 rows, and lane i receives element i of each of the 4 rows --
+// operand row m0 + i at k = kb .. kb + 3, the fragment's first or second 4 k.
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 #define GS2D_LDS __attribute__((address_space(3)))
@@ -519,11 +521,11 @@ struct FcFwd : Dims {
 };
 
 // Fully connected input gradient, masked by the ReLU of the input:
-// gx[b][i] = bf16(sum_o w[o][i] gy[b][o] [x > 0]); M = I, N = B, K = O' (padded to 8).
+// gx[b][i] = bf16(sum_o w[o][i] gy[b][o] [x > 0]); M = I, N = B, K = O.
 struct FcBwdData : Dims {
   static constexpr bool kAk = true, kBk = true;
-  const uint16_t* wt;  // [I][O']
-  const uint16_t* gy;  // [B][O']
+  const uint16_t* wt;  // [I][O]
+  const uint16_t* gy;  // [B][O]
   const uint16_t* x;   // [B][I]
   uint16_t* gx;
   using APrep = OffPrep;
@@ -542,10 +544,9 @@ struct FcBwdData : Dims {
 // M = O, N = I + 1, K = B.
 struct FcBwdWeight : Dims {
   static constexpr bool kAk = false, kBk = false;
-  const uint16_t* gy;  // [B][O'] (rows past O are zero)
+  const uint16_t* gy;  // [B][O]
   const uint16_t* x;   // [B][I]
   float* part;
-  int Op;  // O'
   using APrep = OffPrep;
   struct BPrep {
     uint32_t off;
@@ -553,7 +554,7 @@ struct FcBwdWeight : Dims {
   };
   __device__ APrep a_prep(int m8) const { return {(uint32_t)m8 * 2u}; }
   __device__ uint4 a(const APrep& q, int k, bool ok) const {
-    return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)(k * Op) : kOOB);
+    return bload(rsrc(gy), ok ? q.off + 2u * (uint32_t)(k * M) : kOOB);
   }
   __device__ BPrep b_prep(int n8) const { return {(uint32_t)n8 * 2u, n8 == N - 1}; }
   __device__ uint4 b(const BPrep& q, int k, bool ok) const {
@@ -1268,7 +1269,6 @@ void weight_grad(gs2d_ws* net, int li, int B, ReduceTable* tab, hipStream_t s) {
     FcBwdWeight op;
     op.gy = net->gact[li + 1];
     op.x = net->act[li];
-    op.Op = L.co;
     wgrad_run<128>(net, op, li, B, tab, s);
   }
 }
