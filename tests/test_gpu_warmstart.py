@@ -78,9 +78,10 @@ def test_ws_forward_exact(wsmod, seed):
     np.testing.assert_array_equal(host(net.params()), theta)
 
 
-@pytest.mark.parametrize("batch", [4, 37, 256])
+@pytest.mark.parametrize("batch", [1, 4, 37, 256])
 def test_ws_gradient_exact(wsmod, batch):
-    """Batch 37 spans several split-K slices and ragged GEMM tiles; 256 is the training
+    """Batch 1 has one output-layer workgroup and one-slice weight gradients; batch 37
+    spans several split-K slices and ragged GEMM tiles; 256 is the training
     batch, whose layers take the 128-column tiles, the split forward layer and the
     split-K counts that the training step runs."""
     theta = synth.exact_params(2)
