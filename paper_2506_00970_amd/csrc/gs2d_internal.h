@@ -396,6 +396,9 @@ void launch_reduce_pose_group(const float* part, int rows, int n_views, float* c
 void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,
                               hipStream_t s);
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
+// launch_pose_exp after *sum = scale x the sum of part[0 .. n) (fixed order), one launch.
+void launch_pose_exp_sum(const float* tau, const float* pose_in, float* pose_out, const float* part, int n,
+                         float scale, float* sum, hipStream_t s);
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
 // Resets the tracking state and the pair-overflow flag.  fallback (nullable): per view
 // the device pose [12] and unmasked loss [1] of the warm start's fallback (either null:

@@ -45,6 +45,7 @@
 #include <new>
 
 #include "../../include/gs2d_warm.h"
+#include "gs2d_internal.h"
 
 namespace gs2d {
 namespace ws {
@@ -894,21 +895,6 @@ __global__ __launch_bounds__(64) void residual_loss_kernel(const float* __restri
   part[i] = a;
 }
 
-// out = scale x the sum of part[0 .. n) (one workgroup, fixed order).
-__global__ __launch_bounds__(256) void sum_scaled_kernel(const float* __restrict__ part, int n, float scale,
-                                                         float* __restrict__ out) {
-  __shared__ float sh[256];
-  float v = 0.f;
-  for (int i = threadIdx.x; i < n; i += 256) v += part[i];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = sh[0] * scale;
-}
-
 // Keep T_0 unless its loss exceeds the start pose's.
 __global__ void choose_pose_kernel(const float* __restrict__ loss, const float* __restrict__ p_start,
                                    const float* __restrict__ p0, float* __restrict__ out, float* __restrict__ info) {
@@ -1541,17 +1527,21 @@ int propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const g
   } else {  // the unmasked loss and the network's BF16 input in one pass over the frames
     const int f = W / GS2D_WS_IN_W, nb = GS2D_WS_IN_H * GS2D_WS_IN_W;
     float* part = net->igrad;  // per-block loss terms (the image-gradient workspace is free here)
-    const float scale = 1.f / (float)hw;
     if (f == 8)
       residual_loss_kernel<true><<<cdiv(8 * nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d,
                                                                   net->act[0], part);
     else
       residual_loss_kernel<false><<<cdiv(nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d,
                                                                net->act[0], part);
-    sum_scaled_kernel<<<1, 256, 0, s>>>(part, nb, scale, losses);
   }
   forward_layers(net, 1, tau, true, s);  // the twist itself
-  WS_TRY(gs2d_pose_exp(ctx, tau, pose_start, pose0, s));
+  if (use_masks) {
+    WS_TRY(gs2d_pose_exp(ctx, tau, pose_start, pose0, s));
+  } else {  // T_0, and the start loss from the residual pass's block sums, in one launch
+    gs2d::launch_pose_exp_sum(tau, pose_start, pose0, net->igrad, GS2D_WS_IN_H * GS2D_WS_IN_W,
+                              1.f / (float)hw, losses, s);
+    WS_HIP(hipGetLastError());
+  }
   return GS2D_OK;
 }
 
