@@ -292,16 +292,17 @@ BlendArgs blend_args(gs2d_ctx* ctx) {
 // scan and the pair buffers grow to fit; without it (graph capture, tracking loop) an
 // overflow only raises the device flag.
 // upload = false: the device view table already holds vs (the tracking loop uploads
-// it once, outside the captured iteration).  tl: the forward also forms the tracking
-// loss of the views that carry targets.
-struct TrackLoss {
+// it once, outside the captured iteration).  ro: the forward blend of a one-view set
+// with targets forms the learned warm start's input instead of the images.
+struct ResidualOut {
+  uint16_t* x;
+  float* part;
   float lambda_d;
-  int use_masks;
 };
 // tracking: a render of the tracking loop (the pair-overflow flag is kept from the
 // call's start, so that an overflow in any iteration restarts the call).
 int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_sync, bool upload = true,
-                 const TrackLoss* tl = nullptr, bool blend = true, bool order = true, bool tracking = false) {
+                 const ResidualOut* ro = nullptr, bool blend = true, bool order = true, bool tracking = false) {
   const int64_t items = vs.items;
   const int nv = vs.n_views;
   bool capturing = false;
@@ -349,10 +350,13 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
       launch_preprocess(ctx->views, nv, items, ctx->opt.z_near, ctx->opt.filter, tw, th, ctx->rec, ctx->rect,
                         ctx->count, ctx->dkey, ctx->saved_pose, part_pairs, part_vis, ctx->ctrl, s, !tracking);
     }
+    // the pair total is read back (and the pair buffers grown) unless capturing
+    const bool read_np = allow_sync && !capturing && !ctx->pair_fixed;
+    uint32_t* const np_out = read_np ? ctx->np_dev : nullptr;
     const bool scanned = part_scan_needed(items);
     if (scanned) {
       ProfScope ps(ctx, kScan, s);
-      launch_part_scan(part_pairs, part_vis, items, ctx->ctrl, s);
+      launch_part_scan(part_pairs, part_vis, items, ctx->ctrl, np_out, s);
     }
     // pairs in item order; a tile sort of one pass (up to 2048 tiles) writes the tile
     // ranges itself
@@ -362,13 +366,12 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
       ProfScope ps(ctx, kDup, s);
       launch_duplicate(ws, ctx->count, part_pairs, part_vis, scanned, ctx->rect, ctx->views, nv, items, ctx->p_cap,
                        tbits, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, ctx->dkey,
-                       ctx->pdk[0], s);
+                       ctx->pdk[0], np_out, s);
     };
     duplicate();
-    if (allow_sync && !capturing && !ctx->pair_fixed) {
-      GS2D_HIP(ctx, hipMemcpyAsync(ctx->host_ctrl, ctx->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    if (read_np) {
       GS2D_HIP(ctx, hipStreamSynchronize(s));
-      const int64_t np = ctx->host_ctrl->n_pairs;
+      const int64_t np = *ctx->np_host;
       if (np > ctx->p_cap) {
         // grow and duplicate again (the first pass counted part of its pairs into plane 1)
         GS2D_TRY(ensure_pairs(ctx, np + np / 4));
@@ -411,10 +414,10 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     ba.tile_stride = tile_stride(vs.tiles);
     ba.queue = ctx->queue_on ? ctx->queue : nullptr;
     ba.check = &ctx->ctrl->check_bits;
-    if (tl) {
-      ba.loss_part = ctx->part;
-      ba.lambda_d = tl->lambda_d;
-      ba.use_masks = tl->use_masks;
+    if (ro) {
+      ba.res_x = ro->x;
+      ba.res_part = ro->part;
+      ba.lambda_d = ro->lambda_d;
     }
     if (blend) {
       for (int k = 0; k < nv; ++k)
@@ -794,6 +797,26 @@ int track_impl(gs2d_ctx* ctx, const gs2d_track_problem* probs, int np, const gs2
 
 }  // namespace
 
+namespace gs2d {
+
+int render_residual(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera, const float* pose,
+                    const float* tgt_rgb, const float* tgt_depth, float lambda_d, uint16_t* x, float* part,
+                    hipStream_t s) {
+  if (!ctx || !valid_camera(camera) || n <= 0 || !params || !pose || !tgt_rgb || !tgt_depth || !x || !part)
+    return GS2D_ERR_INVALID_ARG;
+  if (camera->width % 8 || camera->height % 8) return GS2D_ERR_UNSUPPORTED;
+  gs2d_view v{params, n, *camera, pose, nullptr, nullptr, nullptr, nullptr};
+  ViewSet vs;
+  GS2D_TRY(build_views(ctx, &v, 1, vs));
+  vs.v[0].tgt_rgb = tgt_rgb;
+  vs.v[0].tgt_depth = tgt_depth;
+  GS2D_TRY(set_device(ctx));
+  const ResidualOut ro{x, part, lambda_d};
+  return render_views(ctx, vs, s, true, true, &ro);
+}
+
+}  // namespace gs2d
+
 extern "C" {
 
 GS2D_API int gs2d_default_options(gs2d_options* opt) {
@@ -838,6 +861,15 @@ GS2D_API int gs2d_create(gs2d_ctx** out, int device, const gs2d_options* opt) {
     hipError_t e = hipHostMalloc((void**)&ctx->host_ctrl, sizeof(Ctrl), hipHostMallocDefault);
     if (e != hipSuccess) r = fail_hip(ctx, e);
   }
+  if (r == GS2D_OK) {
+    uint32_t* p = nullptr;
+    hipError_t e = hipHostMalloc((void**)&p, 64, hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+      ctx->np_host = p;
+      e = hipHostGetDevicePointer((void**)&ctx->np_dev, p, 0);
+    }
+    if (e != hipSuccess) r = fail_hip(ctx, e);
+  }
   if (r == GS2D_OK && o.pair_capacity > 0) {
     r = ensure_pairs(ctx, o.pair_capacity);
     ctx->pair_fixed = true;
@@ -866,6 +898,7 @@ GS2D_API int gs2d_destroy(gs2d_ctx* ctx) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ctx->host_ctrl) (void)hipHostFree(ctx->host_ctrl);
+  if (ctx->np_host) (void)hipHostFree(const_cast<uint32_t*>(ctx->np_host));
   if (ctx->graph_stream) (void)hipStreamDestroy(ctx->graph_stream);
   for (int i = 0; i < ctx->ev_cap; ++i) {
     (void)hipEventDestroy(ctx->ev[i].a);

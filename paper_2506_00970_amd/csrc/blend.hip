@@ -371,45 +371,28 @@ __device__ __forceinline__ void blend_fwd_tile(const BlendArgs& a, const int til
     t_final[V.pix_base + p] = s.T;
     last_out[V.pix_base + p] = (uint32_t)s.lastj;
   }
-  if (a.loss_part && V.tgt_rgb) {  // tracking (uniform over the workgroup)
-    // eq:tracking_loss at this pixel, with the normal and opacity masks of
-    // eq:normal_mask and eq:opacity_mask, and its gradient to the rendered images
-    float l = 0.f;
-    if (inside) {
-      bool m = true;
-      if (a.use_masks) {
-        const float xh = (fpx - V.cam.cx) / V.cam.fx, yh = (fpy - V.cam.cy) / V.cam.fy;
-        const float ndr = fmaf(s.n0, xh, fmaf(s.n1, yh, s.n2));
-        m = (ndr > 0.0f) && (s.co > kOpacityMask);
-      }
-      const float inv = 1.0f / (float)HW;
-      const float d0 = s.cr - V.tgt_rgb[p];
-      const float d1 = s.cg - V.tgt_rgb[HW + p];
-      const float d2 = s.cb - V.tgt_rgb[2 * HW + p];
-      const float dd = s.cd - V.tgt_depth[p];
-      auto sgn = [](float v) { return v > 0.f ? 1.f : (v < 0.f ? -1.f : 0.f); };
-      if (m) {
-        l = fabsf(d0) + fabsf(d1) + fabsf(d2) + a.lambda_d * fabsf(dd);
-        V.g_rgb[p] = sgn(d0) * inv;
-        V.g_rgb[HW + p] = sgn(d1) * inv;
-        V.g_rgb[2 * HW + p] = sgn(d2) * inv;
-        V.g_depth[p] = a.lambda_d * sgn(dd) * inv;
-      } else {
-        V.g_rgb[p] = 0.f;
-        V.g_rgb[HW + p] = 0.f;
-        V.g_rgb[2 * HW + p] = 0.f;
-        V.g_depth[p] = 0.f;
-      }
-    }
-    __shared__ float s_loss[NT / 64];
+  if (a.res_x && wx0 < V.cam.width && wy0 < V.cam.height) {
+    // the learned warm start's input and the unmasked tracking loss's terms of this
+    // wave's 8 x 8 pixel block (the frame's sides are multiples of 8: every lane is
+    // inside), each a sum over the wave's lanes in butterfly order
+    float d[4];
+    d[0] = s.cr - V.tgt_rgb[p];
+    d[1] = s.cg - V.tgt_rgb[HW + p];
+    d[2] = s.cb - V.tgt_rgb[2 * HW + p];
+    d[3] = s.cd - V.tgt_depth[p];
+    float l = fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]) + a.lambda_d * fabsf(d[3]);
     l = wave_sum(l);
-    if (lane == 0) s_loss[wave] = l;
-    __syncthreads();
-    if (t == 0) {
-      float sum = 0.f;
 #pragma unroll
-      for (int w = 0; w < NT / 64; ++w) sum += s_loss[w];
-      a.loss_part[(size_t)tile * 8 + 6] = sum;
+    for (int c = 0; c < 4; ++c) d[c] = wave_sum(d[c]) * (1.0f / 64.0f);
+    if (lane == 0) {
+      const int blk = (wy0 >> 3) * (V.cam.width >> 3) + (wx0 >> 3);
+      uint2 q;
+      q.x = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)d[0]) |
+            ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)d[1]) << 16);
+      q.y = (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)d[2]) |
+            ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)d[3]) << 16);
+      *reinterpret_cast<uint2*>(a.res_x + (size_t)blk * 4) = q;
+      a.res_part[blk] = l;
     }
   }
 }

@@ -202,6 +202,10 @@ struct gs2d_ctx {
   gs2d::ViewDesc* views = nullptr;  // device view table [kMaxViews]
   gs2d::Ctrl* ctrl = nullptr;
   gs2d::Ctrl* host_ctrl = nullptr;  // pinned mirror for readbacks
+  // a pinned, device-mapped host word that the render's scan or duplication writes the
+  // pair total to: the render waits for it without a copy (np_dev: its device address)
+  volatile uint32_t* np_host = nullptr;
+  uint32_t* np_dev = nullptr;
   hipStream_t graph_stream = nullptr;  // capture stream of the tracking loop (default priority)
 
   // cached tracking graph (invalidated whenever a workspace buffer moves)
@@ -276,17 +280,20 @@ int radix_pass_bits(int bits, int p);
 // Whether `items` take the scan below (many preprocessing blocks); otherwise the
 // duplication sums the per-block counts itself.
 bool part_scan_needed(int64_t items);
-// Exclusive scan of the per-block pair counts in place, and ctrl->n_pairs / n_visible.
-void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t items, Ctrl* ctrl, hipStream_t s);
+// Exclusive scan of the per-block pair counts in place, and ctrl->n_pairs / n_visible
+// (n_pairs also to *np_host, a host-visible word, if not NULL).
+void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t items, Ctrl* ctrl, uint32_t* np_host,
+                      hipStream_t s);
 // The (tile, item) pairs of every item, in item order, placed by the per-block pair
 // counts of preprocessing (an exclusive prefix when `scanned`; otherwise the kernel
-// also stores ctrl->n_pairs and ctrl->n_visible); sets ctrl->overflow when the pairs
-// exceed p_cap.  Fills plane 1 with the first tile pass's histogram.  Each pair's
-// depth key (dkey of its item) goes to pdk beside pval.
+// also stores ctrl->n_pairs, and *np_host if not NULL, and ctrl->n_visible); sets
+// ctrl->overflow when the pairs exceed p_cap.  Fills plane 1 with the first tile
+// pass's histogram.  Each pair's depth key (dkey of its item) goes to pdk beside pval.
 void launch_duplicate(const SortPlanes& ws, const uint32_t* count, const uint32_t* part_pairs,
                       const uint32_t* part_vis, bool scanned, const uint2* rect, const ViewDesc* views, int n_views,
                       int64_t items, int64_t p_cap, int tile_bits, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl,
-                      uint2* ranges, int n_tiles, const uint32_t* dkey, uint32_t* pdk, hipStream_t s);
+                      uint2* ranges, int n_tiles, const uint32_t* dkey, uint32_t* pdk, uint32_t* np_host,
+                      hipStream_t s);
 // Stable sort of the min(n_pairs, p_cap) pairs by tile key over `bits` bits, moving
 // vals and dks with the keys.  A single pass also writes the tile ranges (empty after
 // an overflow).  Returns the buffer index.
@@ -326,11 +333,18 @@ struct BlendArgs {
   // n_tiles): neighbouring tiles, which have lists of similar length, start at
   // different times and on different compute units
   int tile_stride = 1;
-  // tracking: views with targets also get the tracking loss and its image gradients
-  // from the forward blend, each tile's loss sum in loss_part[tile * 8 + 6]
+  // the tracking walk's tile rows (pose gradient in slots 0-5, loss in slot 6), and
+  // the loss's depth weight and masks
   float* loss_part = nullptr;
   float lambda_d = 0.f;
   int use_masks = 0;
+  // the learned warm start's input from the forward blend of one view with targets
+  // (its sides multiples of 8; its images are not written): per 8 x 8 pixel block
+  // (row-major, width / 8 per row), the BF16 block means of (image - target) for R,
+  // G, B and depth in res_x[block][4], and |dR| + |dG| + |dB| + lambda_d |dD| summed
+  // over the block in res_part[block]
+  uint16_t* res_x = nullptr;
+  float* res_part = nullptr;
   // tracking walk with 256-thread tiles: with order_ids, each workgroup first orders
   // its own tile's list (order_ids = the tile-sorted ids, order_scratch a buffer of the
   // same size, dkey the per-item depth keys), so no separate depth-order kernel runs
@@ -396,9 +410,12 @@ void launch_reduce_pose_group(const float* part, int rows, int n_views, float* c
 void launch_reduce_pose_views(const ViewDesc* views, int n_views, const float* part, int accumulate,
                               hipStream_t s);
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s);
-// launch_pose_exp after *sum = scale x the sum of part[0 .. n) (fixed order), one launch.
-void launch_pose_exp_sum(const float* tau, const float* pose_in, float* pose_out, const float* part, int n,
-                         float scale, float* sum, hipStream_t s);
+// A render of one view (n > 0 surfels; its sides multiples of 8) whose forward blend
+// writes, instead of the images, the learned warm start's input against the targets:
+// x[block][4] and part[block] as BlendArgs::res_x and res_part describe.
+int render_residual(gs2d_ctx* ctx, const float* params, int64_t n, const gs2d_camera* camera, const float* pose,
+                    const float* tgt_rgb, const float* tgt_depth, float lambda_d, uint16_t* x, float* part,
+                    hipStream_t s);
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s);
 // Resets the tracking state and the pair-overflow flag.  fallback (nullable): per view
 // the device pose [12] and unmasked loss [1] of the warm start's fallback (either null:

@@ -270,9 +270,9 @@ __device__ void se3_left_jacobian(const double tau[6], double Jl[36]) {
     }
 }
 
-// T_out = Exp(tau) T_in in FP64, rounded to FP32 (one thread).
-__device__ void exp_times_pose(const float* __restrict__ tau, const float* __restrict__ pin,
-                               float* __restrict__ pout) {
+__global__ void pose_exp_kernel(const float* __restrict__ tau, const float* __restrict__ pin,
+                                float* __restrict__ pout) {
+  if (threadIdx.x != 0) return;
   double t[6], Re[9], te[3];
   for (int k = 0; k < 6; ++k) t[k] = tau[k];
   se3_exp(t, Re, te);
@@ -284,32 +284,6 @@ __device__ void exp_times_pose(const float* __restrict__ tau, const float* __res
       if (c == 3) s += te[r];
       pout[r * 4 + c] = (float)s;
     }
-}
-
-__global__ void pose_exp_kernel(const float* __restrict__ tau, const float* __restrict__ pin,
-                                float* __restrict__ pout) {
-  if (threadIdx.x == 0) exp_times_pose(tau, pin, pout);
-}
-
-// The same step, after out = scale x the sum of part[0 .. n) over one 256-thread
-// workgroup in a fixed order (the learned warm start's last launch: its loss at the
-// start pose and its proposed pose).
-__global__ __launch_bounds__(256) void pose_exp_sum_kernel(const float* __restrict__ tau,
-                                                           const float* __restrict__ pin, float* __restrict__ pout,
-                                                           const float* __restrict__ part, int n, float scale,
-                                                           float* __restrict__ out) {
-  __shared__ float sh[256];
-  float v = 0.f;
-  for (int i = threadIdx.x; i < n; i += 256) v += part[i];
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  *out = sh[0] * scale;
-  exp_times_pose(tau, pin, pout);
 }
 
 __global__ void pose_tau_grad_kernel(const float* __restrict__ tau, const float* __restrict__ g,
@@ -329,11 +303,6 @@ __global__ void pose_tau_grad_kernel(const float* __restrict__ tau, const float*
 
 void launch_pose_exp(const float* tau, const float* pose_in, float* pose_out, hipStream_t s) {
   pose_exp_kernel<<<1, 64, 0, s>>>(tau, pose_in, pose_out);
-}
-
-void launch_pose_exp_sum(const float* tau, const float* pose_in, float* pose_out, const float* part, int n,
-                         float scale, float* sum, hipStream_t s) {
-  pose_exp_sum_kernel<<<1, 256, 0, s>>>(tau, pose_in, pose_out, part, n, scale, sum);
 }
 
 void launch_pose_tau_grad(const float* tau, const float* d_pose, float* d_tau, hipStream_t s) {

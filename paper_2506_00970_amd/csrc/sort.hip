@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(PassArgs a) {
 // pair counts (one workgroup, chunks of kScanItems), and the totals.
 __global__ __launch_bounds__(kThreads) void scan_parts_kernel(uint32_t* __restrict__ part_pairs,
                                                               const uint32_t* __restrict__ part_vis, int n_parts,
-                                                              Ctrl* __restrict__ ctrl) {
+                                                              Ctrl* __restrict__ ctrl, uint32_t* __restrict__ np_host) {
   __shared__ uint32_t sh[kWaves];
   const int t = threadIdx.x;
   uint32_t carry = 0, vis = 0;
@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kThreads) void scan_parts_kernel(uint32_t* __restri
   if (t == 0) {
     ctrl->n_pairs = carry;
     ctrl->n_visible = vt;
+    if (np_host) *np_host = carry;
   }
 }
 
@@ -280,6 +281,7 @@ struct DupArgs {
   uint32_t* hist;  // the first tile pass's plane
   int stride;
   int bits;        // the first tile pass's digit: key mod 2^bits
+  uint32_t* np_host;  // nullable: the pair total also to this host-visible word
 };
 
 __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
@@ -334,6 +336,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
       if (t == 0) {
         a.ctrl->n_pairs = tp;
         a.ctrl->n_visible = tv;
+        if (a.np_host) *a.np_host = tp;
       }
     }
   }
@@ -464,18 +467,20 @@ void launch_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n, hipStream_t 
 
 bool part_scan_needed(int64_t items) { return blocks_for(items, kPartItems) > kDirectParts; }
 
-void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t items, Ctrl* ctrl, hipStream_t s) {
-  scan_parts_kernel<<<1, kThreads, 0, s>>>(part_pairs, part_vis, blocks_for(items, kPartItems), ctrl);
+void launch_part_scan(uint32_t* part_pairs, const uint32_t* part_vis, int64_t items, Ctrl* ctrl, uint32_t* np_host,
+                      hipStream_t s) {
+  scan_parts_kernel<<<1, kThreads, 0, s>>>(part_pairs, part_vis, blocks_for(items, kPartItems), ctrl, np_host);
 }
 
 void launch_duplicate(const SortPlanes& ws, const uint32_t* count, const uint32_t* part_pairs,
                       const uint32_t* part_vis, bool scanned, const uint2* rect, const ViewDesc* views, int n_views,
                       int64_t items, int64_t p_cap, int tile_bits, uint32_t* pkey, uint32_t* pval, Ctrl* ctrl,
-                      uint2* ranges, int n_tiles, const uint32_t* dkey, uint32_t* pdk, hipStream_t s) {
+                      uint2* ranges, int n_tiles, const uint32_t* dkey, uint32_t* pdk, uint32_t* np_host,
+                      hipStream_t s) {
   const int n_parts = blocks_for(items, kPartItems);
   DupArgs a{count,  part_pairs, part_vis, n_parts, scanned ? 1 : 0, rect,   views,   n_views,
             items,  p_cap,      pkey,     pval,    ctrl,            dkey,   pdk,     ranges,
-            n_tiles, ws.plane[1], ws.stride, radix_pass_bits(tile_bits, 0)};
+            n_tiles, ws.plane[1], ws.stride, radix_pass_bits(tile_bits, 0), np_host};
   duplicate_kernel<<<n_parts, kThreads, 0, s>>>(a);
 }
 

@@ -30,7 +30,8 @@
 //   fc weight grad     O        I + 1          B         (split-K)
 //
 // In training, fc2 (256 -> 6) runs as one kernel of its own: forward, squared error,
-// loss gradient, input and weight gradients.
+// loss gradient, input and weight gradients.  In the proposal (batch 1) it runs in
+// the closing launch, with the addition of fc1's split-K slices and T_0 = Exp(tau) T.
 //
 // MFMA operand layout used (16 x 16 x 32, wave64): lane l supplies row l % 16 of A
 // and column l % 16 of B, each with the 8 consecutive k of group l / 16; the FP32
@@ -46,6 +47,7 @@
 
 #include "../../include/gs2d_warm.h"
 #include "gs2d_internal.h"
+#include "pose_step.h"
 
 namespace gs2d {
 namespace ws {
@@ -496,7 +498,6 @@ struct FcFwd : Dims {
   const uint16_t* x;  // [B][I]
   uint16_t* y;        // ReLU + bf16 (hidden layer), or
   float* yf;          // FP32, no ReLU (output layer)
-  bool twist = false; // yf scaled from the normalised twist to (rho in m, phi in rad)
   using APrep = OffPrep;
   using BPrep = OffPrep;
   __device__ APrep a_prep(int m) const { return {(uint32_t)m * (uint32_t)K * 2u}; }
@@ -506,7 +507,7 @@ struct FcFwd : Dims {
   __device__ void store(int m, int n, float v) const {
     v += bias[m];
     if (yf)
-      yf[(size_t)n * M + m] = twist ? v * (m < 3 ? 0.1f : (float)(8.0 * M_PI / 180.0)) : v;
+      yf[(size_t)n * M + m] = v;
     else
       y[(size_t)n * M + m] = to_bf16(relu(v));
   }
@@ -586,13 +587,24 @@ struct SplitPart : Op {
   }
 };
 
+// The slices are loaded 16 at a time, all 16 loads issued before the first addition
+// (loads past the S M N floats of the partials return 0 and are not added).
 template <class Op>
 __global__ void split_finish_kernel(Op op, const float* __restrict__ part, int S) {
   const int M = op.M, N = op.N;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M * N) return;
+  const Rsrc r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(part), (short)0, 4 * S * M * N, 0x00020000);
   float v = 0.f;
-  for (int z = 0; z < S; ++z) v += part[(size_t)z * M * N + i];
+  for (int z0 = 0; z0 < S; z0 += 16) {
+    float q[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      q[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, 4u * (uint32_t)((z0 + u) * M * N + i), 0, 0));
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (z0 + u < S) v += q[u];
+  }
   op.store(i / N, i - (i / N) * N, v);
 }
 
@@ -845,13 +857,10 @@ __global__ void residual_kernel(const float* __restrict__ rgb, const float* __re
   input[i] = s / (float)(f * f);
 }
 
-// The proposal's two inputs from one rendered frame in one pass: the network input
-// x[Y][X][c] = bf16 of the block mean of (img - tgt) (channels as residual_kernel),
-// and part[Y 80 + X] = the block's sum of |d r| + |d g| + |d b| + lambda_d
-// |d depth|, the terms of the unmasked tracking loss.  R8: 8 x 8 blocks (640 x 480
-// frames), one thread per block row (two float4 of each image), the 8 rows added by a
-// butterfly over the 8 lanes of a block; otherwise one thread per f x f block.
-template <bool R8>
+// The proposal's two inputs from one rendered frame in one pass, one thread per f x f
+// block: the network input x[Y][X][c] = bf16 of the block mean of (img - tgt)
+// (channels as residual_kernel), and part[Y 80 + X] = the block's sum of |d r| +
+// |d g| + |d b| + lambda_d |d depth|, the terms of the unmasked tracking loss.
 __global__ __launch_bounds__(64) void residual_loss_kernel(const float* __restrict__ rgb,
                                                            const float* __restrict__ depth,
                                                            const float* __restrict__ trgb,
@@ -859,13 +868,12 @@ __global__ __launch_bounds__(64) void residual_loss_kernel(const float* __restri
                                                            float lambda_d, uint16_t* __restrict__ x,
                                                            float* __restrict__ part) {
   constexpr int nb = GS2D_WS_IN_H * GS2D_WS_IN_W;
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = R8 ? g >> 3 : g;  // the block (every lane of a block row group is live)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   const int Y = i / GS2D_WS_IN_W, X = i - Y * GS2D_WS_IN_W;
   const size_t hw = (size_t)W * H;
   float s[4] = {0.f, 0.f, 0.f, 0.f}, a = 0.f;
-  for (int dy = R8 ? (g & 7) : 0; dy < (R8 ? (g & 7) + 1 : f); ++dy) {
+  for (int dy = 0; dy < f; ++dy) {
     const size_t row = (size_t)(Y * f + dy) * W + (size_t)X * f;
     for (int dx = 0; dx < f; ++dx) {
       float d[4];
@@ -879,15 +887,6 @@ __global__ __launch_bounds__(64) void residual_loss_kernel(const float* __restri
 #pragma unroll
       for (int c = 0; c < 4; ++c) s[c] += d[c];
     }
-  }
-  if constexpr (R8) {
-#pragma unroll
-    for (int w = 1; w < 8; w <<= 1) {
-      a += __shfl_xor(a, w, 8);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) s[c] += __shfl_xor(s[c], w, 8);
-    }
-    if (g & 7) return;
   }
   const float ff = (float)(f * f);
   *reinterpret_cast<uint2*>(x + (size_t)i * kInC) = uint2{to_bf16x2(s[0] / ff, s[1] / ff),
@@ -906,6 +905,97 @@ __global__ void choose_pose_kernel(const float* __restrict__ loss, const float* 
     info[1] = loss[1];
     info[2] = keep ? 1.f : 0.f;
     info[3] = 0.f;
+  }
+}
+
+// The proposal's last launch, at batch 1 (one 256-thread workgroup).  Thread t forms
+// fc1's output h[t] = bf16(ReLU(b1[t] + the sum of fc1's S split-K slices, added in
+// slice order)), as the split finish does (S = 0: h1 holds it already).  The six
+// outputs are b2[o] + sum_t w2[o][t] h[t], each wave adding its 64 products by a
+// butterfly and the four wave sums in wave order, then scaled from the normalised
+// twist to (rho in m, phi in rad): tau.  Wave 0 then forms T_0 = Exp(tau) T_start in
+// FP64 and lane k < 12 writes entry k, rounded to FP32.  With loss_part, also
+// *loss = scale x the sum of loss_part[0 .. n), n <= 256 kLossPer (thread t adding
+// t, t + 256, ... in order, then a halving tree).  Every load is issued before the
+// first sum: the kernel is one memory latency, then arithmetic.
+constexpr int kLossPer = (GS2D_WS_IN_H * GS2D_WS_IN_W + 255) / 256;
+constexpr int kCloseSlices = 24;  // slices loaded at once (a batch-1 fc1 has 20)
+__global__ __launch_bounds__(256) void propose_close_kernel(
+    const float* __restrict__ part, int S, const uint16_t* __restrict__ h1, const float* __restrict__ b1,
+    const uint16_t* __restrict__ w2, const float* __restrict__ b2, const float* __restrict__ pin,
+    float* __restrict__ pout, float* __restrict__ tau_out, const float* __restrict__ loss_part, int n, float scale,
+    float* __restrict__ loss) {
+  __shared__ float red[4][6];
+  __shared__ float sh[256];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  // buffer loads past a resource's range return 0 (a NULL loss_part: an empty range)
+  const Rsrc rl = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(loss_part), (short)0,
+                                                    loss_part ? 4 * n : 0, 0x00020000);
+  const Rsrc rp = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(part), (short)0,
+                                                    S > 0 ? 4 * 256 * min(S, kCloseSlices) : 0, 0x00020000);
+  float lv[kLossPer], pv[kCloseSlices], wv[6];
+#pragma unroll
+  for (int j = 0; j < kLossPer; ++j)
+    lv[j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, 4u * (uint32_t)(t + 256 * j), 0, 0));
+#pragma unroll
+  for (int z = 0; z < kCloseSlices; ++z)
+    pv[z] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rp, 4u * (uint32_t)(z * 256 + t), 0, 0));
+#pragma unroll
+  for (int o = 0; o < 6; ++o) wv[o] = __uint_as_float((uint32_t)w2[o * 256 + t] << 16);
+  const float bias1 = b1[t];
+  const uint16_t hq = S > 0 ? 0 : h1[t];
+  float bo[6], col[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int o = 0; o < 6; ++o) bo[o] = b2[o];
+  if (t < 12)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) col[q] = pin[q * 4 + t % 4];
+  float a = 0.f;
+#pragma unroll
+  for (int j = 0; j < kLossPer; ++j) a += lv[j];
+  float h;
+  if (S > 0) {
+    float v = 0.f;
+#pragma unroll
+    for (int z = 0; z < kCloseSlices; ++z)
+      if (z < S) v += pv[z];
+    for (int z = kCloseSlices; z < S; ++z) v += part[(size_t)z * 256 + t];
+    h = __uint_as_float((uint32_t)to_bf16(relu(v + bias1)) << 16);
+  } else {
+    h = __uint_as_float((uint32_t)hq << 16);
+  }
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    float y = wv[o] * h;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) y += __shfl_xor(y, m, 64);
+    if (l == 0) red[w][o] = y;
+  }
+  sh[t] = a;
+  __syncthreads();
+  if (loss_part) {
+    for (int k = 128; k > 0; k >>= 1) {
+      if (t < k) sh[t] += sh[t + k];
+      __syncthreads();
+    }
+    if (t == 0) *loss = sh[0] * scale;
+  }
+  if (w != 0) return;
+  double tau[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) {
+    const float v = (((red[0][o] + red[1][o]) + red[2][o]) + red[3][o]) + bo[o];
+    const float f = v * (o < 3 ? 0.1f : (float)(8.0 * M_PI / 180.0));
+    tau[o] = f;
+    if (l == o) tau_out[o] = f;
+  }
+  double Re[9], te[3];
+  se3_exp(tau, Re, te);
+  if (l < 12) {
+    const int r = l / 4, c = l % 4;
+    double s = Re[r * 3 + 0] * (double)col[0] + Re[r * 3 + 1] * (double)col[1] + Re[r * 3 + 2] * (double)col[2];
+    if (c == 3) s += te[r];
+    pout[l] = (float)s;
   }
 }
 
@@ -977,8 +1067,10 @@ void run_bn(const Op& op, int M, int N, int gz, int bn, hipStream_t s) {
 
 // A forward layer: large outputs as one GEMM (tile columns by pick_bn); few output
 // tiles with a long reduction split into slices whose sums a second kernel adds.
+// Returns the number of split-K slices (0: one GEMM).  finish = false leaves a split
+// layer's slices in part for the caller to add.
 template <int BM, class Op>
-void gemm_fwd(Op op, float* part, int64_t part_cap, hipStream_t s) {
+int gemm_fwd(Op op, float* part, int64_t part_cap, hipStream_t s, bool finish = true) {
   const int M = op.M, N = op.N, K = op.K;
   const int tiles = cdiv(N, 64) * cdiv(M, BM);
   if (tiles < 64 && K >= 512) {  // (also splitting layers of 64-256 tiles was measured no faster)
@@ -987,19 +1079,20 @@ void gemm_fwd(Op op, float* part, int64_t part_cap, hipStream_t s) {
     S = S < want ? S : want;
     const int ks = cdiv(cdiv(K, S), kBK) * kBK;
     S = cdiv(K, ks);
-    if (S > 1 && (int64_t)S * M * N <= part_cap) {
+    if (S > 1 && (int64_t)S * M * N <= part_cap && (int64_t)(S + 16) * M * N < (1 << 29)) {
       SplitPart<Op> sp;
       static_cast<Op&>(sp) = op;
       sp.ks = ks;
       sp.part = part;
       run<BM, 64>(sp, M, N, S, s);
       op.ks = ks;
-      split_finish_kernel<Op><<<cdiv((int64_t)M * N, 256), 256, 0, s>>>(op, part, S);
-      return;
+      if (finish) split_finish_kernel<Op><<<cdiv((int64_t)M * N, 256), 256, 0, s>>>(op, part, S);
+      return S;
     }
   }
   op.ks = cdiv(K, kBK) * kBK;
   run_bn<BM>(op, M, N, 1, pick_bn(M, N, BM, 1), s);
+  return 0;
 }
 
 // Split-K slices of a weight-gradient GEMM: about 512 workgroups, at most 256 slices,
@@ -1116,9 +1209,11 @@ int64_t part_layout(int B, int64_t* off) {
   return o > (1 << 20) ? o : (1 << 20);
 }
 
-// Forward of `batch` frames whose BF16 input is in act[0] up to fc1, then (out not
-// NULL) fc2: FP32 output to out [B][6], normalised, or (twist) as the twist itself.
-void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) {
+// Forward of B frames whose BF16 input is in act[0] up to fc1, then (out not NULL)
+// fc2: the normalised FP32 output to out [B][6].  With fc1_slices, fc1 stops at its
+// split-K slices (their count in *fc1_slices; 0 if it ran as one GEMM into act[5])
+// and fc2 is left to the caller.
+void forward_layers(gs2d_ws* net, int B, float* out, hipStream_t s, int* fc1_slices = nullptr) {
   for (int li = 0; li < 4; ++li) {
     const LayerDef& L = kLayers[li];
     const int OH = out_size(L.H, L.k), OW = out_size(L.W, L.k);
@@ -1161,7 +1256,11 @@ void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) 
     op.x = net->act[4];
     op.y = net->act[5];
     op.yf = nullptr;
-    gemm_fwd<128>(op, net->part, net->part_cap, s);
+    const int S = gemm_fwd<128>(op, net->part, net->part_cap, s, fc1_slices == nullptr);
+    if (fc1_slices) {
+      *fc1_slices = S;
+      return;
+    }
   }
   if (out) {
     FcFwd op;
@@ -1173,7 +1272,6 @@ void forward_layers(gs2d_ws* net, int B, float* out, bool twist, hipStream_t s) 
     op.x = net->act[5];
     op.y = nullptr;
     op.yf = out;
-    op.twist = twist;
     gemm_fwd<32>(op, net->part, net->part_cap, s);
   }
 }
@@ -1421,7 +1519,7 @@ GS2D_API int gs2d_ws_forward(gs2d_ws* net, const float* input, int32_t batch, fl
   WS_TRY(check_net(net, batch));
   if (!input || !out) return GS2D_ERR_INVALID_ARG;
   load_input(net, input, batch, s);
-  forward_layers(net, batch, out, false, s);
+  forward_layers(net, batch, out, s);
   WS_HIP(hipGetLastError());
   return GS2D_OK;
 }
@@ -1433,7 +1531,7 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
   const int B = batch;
   float* outp = out ? out : net->out;
   load_input(net, input, B, s);
-  forward_layers(net, B, nullptr, false, s);  // up to fc1
+  forward_layers(net, B, nullptr, s);  // up to fc1
   int64_t off[7];
   part_layout(B, off);
   const int hb = cdiv(B, kHeadFrames);
@@ -1517,31 +1615,34 @@ int propose(gs2d_ctx* ctx, gs2d_ws* net, const float* params, int64_t n, const g
   float* input = net->wsf;
   float* tau = input + kInPlanar + 8;
   uint32_t gen = 0;
+  const int f = W / GS2D_WS_IN_W, nb = GS2D_WS_IN_H * GS2D_WS_IN_W;
+  float* part = net->igrad;  // per-block loss terms (the image-gradient workspace is free here)
   // loss at the start pose and the network's input
-  WS_TRY(gs2d_render(ctx, params, n, camera, pose_start, rgb, depth, normal, alpha, &gen, s));
   if (use_masks) {
+    WS_TRY(gs2d_render(ctx, params, n, camera, pose_start, rgb, depth, normal, alpha, &gen, s));
     WS_TRY(gs2d_tracking_loss(ctx, camera, rgb, depth, normal, alpha, tgt_rgb, tgt_depth, lambda_d, use_masks,
                               losses, net->igrad, net->igrad + 3 * hw, s));
     WS_TRY(gs2d_ws_residual(rgb, depth, tgt_rgb, tgt_depth, W, H, 1, input, s));
     load_input(net, input, 1, s);
-  } else {  // the unmasked loss and the network's BF16 input in one pass over the frames
-    const int f = W / GS2D_WS_IN_W, nb = GS2D_WS_IN_H * GS2D_WS_IN_W;
-    float* part = net->igrad;  // per-block loss terms (the image-gradient workspace is free here)
-    if (f == 8)
-      residual_loss_kernel<true><<<cdiv(8 * nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d,
-                                                                  net->act[0], part);
-    else
-      residual_loss_kernel<false><<<cdiv(nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d,
-                                                               net->act[0], part);
+  } else if (f == 8 && n > 0) {
+    // the unmasked loss's block terms and the network's BF16 input from the forward
+    // blend itself, each wave's 8 x 8 pixels being one block
+    WS_TRY(gs2d::render_residual(ctx, params, n, camera, pose_start, tgt_rgb, tgt_depth, lambda_d, net->act[0],
+                                 part, s));
+  } else {  // the same from the rendered frames, in one pass over them
+    WS_TRY(gs2d_render(ctx, params, n, camera, pose_start, rgb, depth, normal, alpha, &gen, s));
+    residual_loss_kernel<<<cdiv(nb, 64), 64, 0, s>>>(rgb, depth, tgt_rgb, tgt_depth, W, H, f, lambda_d, net->act[0],
+                                                     part);
   }
-  forward_layers(net, 1, tau, true, s);  // the twist itself
-  if (use_masks) {
-    WS_TRY(gs2d_pose_exp(ctx, tau, pose_start, pose0, s));
-  } else {  // T_0, and the start loss from the residual pass's block sums, in one launch
-    gs2d::launch_pose_exp_sum(tau, pose_start, pose0, net->igrad, GS2D_WS_IN_H * GS2D_WS_IN_W,
-                              1.f / (float)hw, losses, s);
-    WS_HIP(hipGetLastError());
-  }
+  // up to fc1's split-K slices; then its sum, fc2, the twist, T_0 = Exp(tau) T_start
+  // and (unmasked) the start loss from the residual pass's block sums in one launch
+  int S = 0;
+  forward_layers(net, 1, nullptr, s, &S);
+  propose_close_kernel<<<1, 256, 0, s>>>(net->part, S, net->act[5], net->theta + net->pk.b_off[4], net->pk.wf[5],
+                                         net->theta + net->pk.b_off[5], pose_start, pose0, tau,
+                                         use_masks ? nullptr : net->igrad, GS2D_WS_IN_H * GS2D_WS_IN_W,
+                                         1.f / (float)hw, losses);
+  WS_HIP(hipGetLastError());
   return GS2D_OK;
 }
 

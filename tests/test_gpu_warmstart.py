@@ -218,6 +218,72 @@ def test_propose_matches_warm_start(wsmod):
         np.testing.assert_array_equal(host(t0), host(chosen))
 
 
+def _check_proposal(r, net, theta, P, cam, start, trgb, tdep, block):
+    from oracle import se3
+
+    ps = dev(start)
+    t0, loss0 = net.propose(r, P, cam, ps, trgb, tdep)
+    t0, loss0 = host(t0), float(host(loss0)[0])
+    s = r.render(P, cam, ps)
+    res = np.concatenate([host(s.rgb).astype(np.float64) - host(trgb), (host(s.depth) - host(tdep))[None]])
+    out_ref, _ = ows.forward(theta.astype(np.float64), ows.downsample(res, block)[None])
+    out_ref = out_ref[0]
+    tau = se3.log(se3.as4(t0) @ np.linalg.inv(se3.as4(start)))
+    err = np.abs(ows.normalise(tau) - out_ref)
+    print(f"proposal ({block} px blocks): max |d out| {err.max():.3g} of {np.abs(out_ref).max():.3g}")
+    assert err.max() <= 1e-2 * np.abs(out_ref).max() + 1e-4, (err, out_ref)
+    ref_loss, _, _ = r.tracking_loss(cam, s.rgb, s.depth, s.normal, s.alpha, trgb, tdep, use_masks=False)
+    ref_loss = float(host(ref_loss).reshape(-1)[0])
+    assert abs(loss0 - ref_loss) <= 1e-5 * ref_loss, (loss0, ref_loss)
+
+
+def test_propose_against_oracle(wsmod):
+    """The proposal on the oracle's terms.  Its T_0 must be Exp(tau) T_start with tau
+    the oracle network's twist (FP64, denormalised) on the oracle's residual input: the
+    block means of (the frame rendered at T_start - the observed frame).  The twist
+    recovered from T_0 T_start^-1 meets the BF16-noise bar on the network output.  The
+    start loss is the unmasked tracking loss of that render (a sum in another order).
+    At 640 x 480 the forward blend forms both, one wave per 8 x 8 block."""
+    from paper_2506_00970_amd import Rasterizer
+    from tests.gpu_common import ROOM_CAM, room_scene
+
+    room, pose = room_scene(100_000, seed=3, cam_seed=3)
+    r = Rasterizer()
+    P = dev(room.params)
+    tgt = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    trgb, tdep = tgt.rgb.clone(), tgt.depth.clone()
+    net = wsmod.WarmStartNet(max_batch=1)
+    for seed in (5, 6):
+        start = synth.perturb_pose(pose, 0.05, 3.0, seed=seed + 10).reshape(12).astype(np.float32)
+        theta = (synth.init_params(seed, bias_std=0.05) * 0.3).astype(np.float32)
+        net.set_params(dev(theta))
+        _check_proposal(r, net, theta, P, ROOM_CAM, start, trgb, tdep, 8)
+
+
+def test_proposal_other_frames(wsmod):
+    """The proposal's other input path (a pass over the rendered frames): a 1280 x 960
+    frame, whose blocks are 16 x 16 pixels, and an empty map, whose render is zero."""
+    import dataclasses
+
+    from paper_2506_00970_amd import Rasterizer
+    from tests.gpu_common import ROOM_CAM, room_scene
+
+    room, pose = room_scene(100_000, seed=3, cam_seed=3)
+    cam2 = dataclasses.replace(ROOM_CAM, width=2 * ROOM_CAM.width, height=2 * ROOM_CAM.height, fx=2 * ROOM_CAM.fx,
+                               fy=2 * ROOM_CAM.fy, cx=2 * ROOM_CAM.cx, cy=2 * ROOM_CAM.cy)
+    r = Rasterizer()
+    P = dev(room.params)
+    net = wsmod.WarmStartNet(max_batch=1)
+    theta = (synth.init_params(7, bias_std=0.05) * 0.3).astype(np.float32)
+    net.set_params(dev(theta))
+    start = synth.perturb_pose(pose, 0.05, 3.0, seed=17).reshape(12).astype(np.float32)
+    tgt = r.render(P, cam2, dev(pose.reshape(12)))
+    _check_proposal(r, net, theta, P, cam2, start, tgt.rgb.clone(), tgt.depth.clone(), 16)
+    tgt = r.render(P, ROOM_CAM, dev(pose.reshape(12)))
+    empty = dev(np.zeros((room.params.shape[0], 0), np.float32))
+    _check_proposal(r, net, theta, empty, ROOM_CAM, start, tgt.rgb.clone(), tgt.depth.clone(), 8)
+
+
 def _fallback_case():
     from paper_2506_00970_amd import Rasterizer
     from tests.gpu_common import ROOM_CAM, room_scene
