@@ -623,11 +623,12 @@ struct GradMap {
 // workgroups block0 .. of the reduction grid.
 struct ReduceLayer {
   int64_t off, w_off, b_off;
-  int S, M, ncol, block0, zl;  // zl: lanes adding one output's slices (4, or 16 from 128 slices)
+  int S, M, ncol, block0, zl;  // zl: lanes adding one output's slices (S <= kReducePer zl, up to 64)
   GradMap map;
   float* dst;   // not NULL: the sums (times scale) go to dst[0 .. M ncol) instead
   float scale;
 };
+constexpr int kReducePer = 8;  // slices per lane of the split-K reduction
 struct ReduceTable {
   ReduceLayer L[7];  // the five GEMM layers, fc2 (from the head) and the loss
   int n;
@@ -647,17 +648,21 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const float* __restri
   const int64_t i = (int64_t)(blockIdx.x - R.block0) * opb + ol;
   float s = 0.f;
   if (i < MN) {
-    const float* __restrict__ p = part + R.off + i;
+    // slices zg, zg + zl, ... (at most kReducePer when S <= kReducePer zl): every load
+    // issued before the first addition; loads past the S slices return 0, unadded
     const int zl = R.zl;
-    int z = zg;
-    for (; z + 3 * zl < R.S; z += 4 * zl) {
-      const float v0 = p[z * MN], v1 = p[(z + zl) * MN], v2 = p[(z + 2 * zl) * MN], v3 = p[(z + 3 * zl) * MN];
-      s += v0;
-      s += v1;
-      s += v2;
-      s += v3;
+    const Rsrc r = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(part + R.off), (short)0,
+                                                     (int)(4 * R.S * MN), 0x00020000);
+    for (int z0 = zg; z0 < R.S; z0 += kReducePer * zl) {
+      float v[kReducePer];
+#pragma unroll
+      for (int u = 0; u < kReducePer; ++u)
+        v[u] = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(r, 4u * (uint32_t)((z0 + u * zl) * MN + i), 0, 0));
+#pragma unroll
+      for (int u = 0; u < kReducePer; ++u)
+        if (z0 + u * zl < R.S) s += v[u];
     }
-    for (; z < R.S; z += zl) s += p[z * MN];
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -1286,17 +1291,30 @@ void add_reduce(ReduceTable* tab, int64_t off, int64_t w_off, int64_t b_off, int
   R.S = S;
   R.M = M;
   R.ncol = ncol;
-  R.zl = S >= 128 ? 16 : 4;
-  if (tab->n) {
-    const ReduceLayer& P = tab->L[tab->n - 1];
-    R.block0 = P.block0 + cdiv((int64_t)P.M * P.ncol, 256 / P.zl);
-  } else {
-    R.block0 = 0;
-  }
+  R.zl = 1;
+  while (R.zl < 64 && R.S > kReducePer * R.zl) R.zl *= 2;
   R.map = map;
   R.dst = dst;
   R.scale = scale;
   tab->n += 1;
+}
+
+// Orders the table's layers by slice count, most first (their lanes' chains are the
+// longest: their workgroups start first), and assigns each its run of workgroups.
+// Returns the grid size.
+int finish_reduce(ReduceTable* tab) {
+  for (int a = 1; a < tab->n; ++a)
+    for (int b = a; b > 0 && tab->L[b].S > tab->L[b - 1].S; --b) {
+      const ReduceLayer t = tab->L[b];
+      tab->L[b] = tab->L[b - 1];
+      tab->L[b - 1] = t;
+    }
+  int blocks = 0;
+  for (int k = 0; k < tab->n; ++k) {
+    tab->L[k].block0 = blocks;
+    blocks += cdiv((int64_t)tab->L[k].M * tab->L[k].ncol, 256 / tab->L[k].zl);
+  }
+  return blocks;
 }
 
 template <int BM, class Op>
@@ -1558,9 +1576,8 @@ GS2D_API int gs2d_ws_gradient(gs2d_ws* net, const float* input, const float* tar
     // layers 1-3 (the input gradient of layer 0 is not needed) are all 3 x 3
     if (li > 0) conv_data_grad(net, li, B, s);
   }
-  const ReduceLayer& last = tab.L[tab.n - 1];
-  reduce_parts_kernel<<<last.block0 + cdiv((int64_t)last.M * last.ncol, 256 / last.zl), 256, 0, s>>>(net->part, net->grad,
-                                                                                          tab);
+  const int blocks = finish_reduce(&tab);
+  reduce_parts_kernel<<<blocks, 256, 0, s>>>(net->part, net->grad, tab);
   if (grad)
     WS_HIP(hipMemcpyAsync(grad, net->grad, (size_t)GS2D_WS_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s));
   WS_HIP(hipGetLastError());
