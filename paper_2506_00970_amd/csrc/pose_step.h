@@ -79,21 +79,24 @@ __device__ inline void pose_step_view(int v, int n_views, const ViewDesc* __rest
   // the six pose sums, the loss and the unmasked loss in one pass and one block
   // reduction (fixed order)
   // Rows are read kRowsInFlight per thread at a time (two 16-byte loads each), all
-  // issued before the first add; each thread adds its rows in ascending order.
+  // issued before the first add; each thread adds its rows in ascending order.  The
+  // loads go through a buffer resource over the view's rows: past its last row they
+  // return zeros, so no branch (and no wait) sits between them.
   constexpr int kRowsInFlight = 8;
   double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  const float4* pp4 = reinterpret_cast<const float4*>(pp);
+  const __amdgpu_buffer_rsrc_t prs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(pp), (short)0, rows * 32, 0x00020000);
   for (int i0 = l; i0 < rows; i0 += (int)blockDim.x * kRowsInFlight) {
     float4 lo[kRowsInFlight], hi[kRowsInFlight];
 #pragma unroll
     for (int u = 0; u < kRowsInFlight; ++u) {
-      const int i = i0 + u * (int)blockDim.x;
-      lo[u] = i < rows ? pp4[(size_t)i * 2] : make_float4(0.f, 0.f, 0.f, 0.f);
-      hi[u] = i < rows ? pp4[(size_t)i * 2 + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const uint32_t off = 32u * (uint32_t)(i0 + u * (int)blockDim.x);
+      lo[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(prs, off, 0, 0));
+      hi[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(prs, off + 16u, 0, 0));
     }
+    // (rows past the last read as zeros: adding them changes no sum)
 #pragma unroll
     for (int u = 0; u < kRowsInFlight; ++u) {
-      if (i0 + u * (int)blockDim.x >= rows) break;
       acc[0] += (double)lo[u].x;
       acc[1] += (double)lo[u].y;
       acc[2] += (double)lo[u].z;

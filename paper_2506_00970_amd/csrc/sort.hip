@@ -288,10 +288,15 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
   const int t = threadIdx.x;
   const int g = blockIdx.x;
   const int64_t j = (int64_t)g * kThreads + t;
-  // the loads that do not wait on the scan go first
-  const uint32_t c = j < a.items ? a.count[j] : 0u;
-  const uint2 rc = c ? a.rect[j] : make_uint2(1u, 0u);
-  const uint32_t dk = c ? a.dkey[j] : 0u;
+  // the loads that do not wait on the scan go first, all three at once
+  uint32_t c = 0u, dk = 0u;
+  uint2 rc = make_uint2(1u, 0u);
+  if (j < a.items) {
+    c = a.count[j];
+    rc = a.rect[j];
+    dk = a.dkey[j];
+  }
+  if (c == 0u) rc = make_uint2(1u, 0u);
   for (int64_t k = j; k < a.n_tiles; k += (int64_t)gridDim.x * kThreads) a.ranges[k] = make_uint2(0u, 0u);
   __shared__ uint32_t sh[kWaves];
   __shared__ unsigned long long sh64[kWaves];
@@ -303,8 +308,19 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
     // one scan of (earlier blocks' counts, this item's count) packed in 64 bits: the
     // high half's total is the pair count before the block, the low half's exclusive
     // prefix the item's place within it
+    // (the counts of blocks 0 .. g - 1, 8 per thread at a time, all loads issued before
+    // the first addition: reads past block g - 1 return 0)
     uint32_t s = 0;
-    for (int k = t; k < g; k += kThreads) s += a.part_pairs[k];
+    const __amdgpu_buffer_rsrc_t prs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(a.part_pairs), (short)0, 4 * g, 0x00020000);
+    for (int k0 = t; k0 < g; k0 += 8 * kThreads) {
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = __builtin_amdgcn_raw_buffer_load_b32(prs, 4u * (uint32_t)(k0 + u * kThreads), 0, 0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
     const int lane = t & 63, wave = t >> 6;
     const unsigned long long v = ((unsigned long long)s << 32) | c;
     unsigned long long x = v;
