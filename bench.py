@@ -659,15 +659,18 @@ def main():
         net.set_params(torch.from_numpy(np.load(args.weights, allow_pickle=False).astype(np.float32)).to(dev))
         rw = Rasterizer(device=0)
         rw.track(P, cam, pose.copy_(start_dev), tgt_rgb, tgt_depth, n_iters=args.warmup, lr=LR, history=False)
-        for _ in range(2):
+        for _ in range(3):
             net.propose(rw, P, cam, start_dev, tgt_rgb, tgt_depth)
         torch.cuda.synchronize()
-        reps = 10
-        t0 = time.perf_counter()
+        # back-to-back proposals, HIP events on the stream they run on
+        reps = 50
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
         for _ in range(reps):
             w_pose, start_loss = net.propose(rw, P, cam, start_dev, tgt_rgb, tgt_depth)
+        ev1.record()
         torch.cuda.synchronize()
-        warm_ms = 1e3 * (time.perf_counter() - t0) / reps
+        warm_ms = ev0.elapsed_time(ev1) / reps
         w0 = w_pose.cpu().numpy().astype(np.float64).reshape(3, 4)
         _, wph, _ = rw.track(P, cam, w_pose, tgt_rgb, tgt_depth, n_iters=100, lr=LR, use_graph=True,
                              fallback=(start_dev, start_loss))

@@ -294,6 +294,8 @@ BlendArgs blend_args(gs2d_ctx* ctx) {
 // upload = false: the device view table already holds vs (the tracking loop uploads
 // it once, outside the captured iteration).  ro: the forward blend of a one-view set
 // with targets forms the learned warm start's input instead of the images.
+constexpr uint32_t kNpPending = 0xFFFFFFFFu;  // the pair-total word before the device writes it
+
 struct ResidualOut {
   uint16_t* x;
   float* part;
@@ -353,6 +355,8 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     // the pair total is read back (and the pair buffers grown) unless capturing
     const bool read_np = allow_sync && !capturing && !ctx->pair_fixed;
     uint32_t* const np_out = read_np ? ctx->np_dev : nullptr;
+    // no render in flight writes the word (each one that does is waited for below)
+    if (read_np) *ctx->np_host = kNpPending;
     const bool scanned = part_scan_needed(items);
     if (scanned) {
       ProfScope ps(ctx, kScan, s);
@@ -362,17 +366,30 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
     // ranges itself
     const int tbits = tile_bits((int)vs.tiles);
     const bool fused_ranges = tbits <= kMaxDigitBits;
-    auto duplicate = [&]() {
+    auto duplicate = [&](uint32_t* np_dst) {
       ProfScope ps(ctx, kDup, s);
       launch_duplicate(ws, ctx->count, part_pairs, part_vis, scanned, ctx->rect, ctx->views, nv, items, ctx->p_cap,
                        tbits, ctx->pkey[0], ctx->pval[0], ctx->ctrl, ctx->ranges, (int)vs.tiles, ctx->dkey,
-                       ctx->pdk[0], np_out, s);
+                       ctx->pdk[0], np_dst, s);
     };
-    duplicate();
+    duplicate(np_out);
     if (read_np) {
-      GS2D_HIP(ctx, hipStreamSynchronize(s));
-      const int64_t np = *ctx->np_host;
+      // the total is written early (by the scan, or by the duplication's first
+      // workgroup): wait for the word itself rather than the whole stream, so that the
+      // launches below are queued before the duplication ends
+      uint32_t np32 = *ctx->np_host;
+      while (np32 == kNpPending) {
+        const hipError_t q = hipStreamQuery(s);
+        np32 = *ctx->np_host;
+        if (q == hipErrorNotReady || np32 != kNpPending) continue;
+        GS2D_HIP(ctx, q);
+        // the stream is idle and the word unwritten: read the device's copy
+        GS2D_HIP(ctx, hipMemcpy(&np32, &ctx->ctrl->n_pairs, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        break;
+      }
+      const int64_t np = np32;
       if (np > ctx->p_cap) {
+        GS2D_HIP(ctx, hipStreamSynchronize(s));
         // grow and duplicate again (the first pass counted part of its pairs into plane 1)
         GS2D_TRY(ensure_pairs(ctx, np + np / 4));
         if (ctx->hist_fresh) {
@@ -383,7 +400,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
         }
         ws = sort_planes(ctx);
         launch_fill_u32(&ctx->ctrl->overflow, 0u, 1, s);  // set by the first pass
-        duplicate();
+        duplicate(nullptr);
       }
     }
     if (ctx->opt.keep_unsorted && ctx->pkey_keep) {

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void scan_parts_kernel(uint32_t* __restri
   if (t == 0) {
     ctrl->n_pairs = carry;
     ctrl->n_visible = vt;
-    if (np_host) *np_host = carry;
+    if (np_host) __hip_atomic_store(np_host, carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void duplicate_kernel(DupArgs a) {
       if (t == 0) {
         a.ctrl->n_pairs = tp;
         a.ctrl->n_visible = tv;
-        if (a.np_host) *a.np_host = tp;
+        if (a.np_host) __hip_atomic_store(a.np_host, tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
   }
