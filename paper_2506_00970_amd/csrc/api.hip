@@ -388,6 +388,7 @@ int render_views(gs2d_ctx* ctx, const ViewSet& vs, hipStream_t s, bool allow_syn
         break;
       }
       const int64_t np = np32;
+      ctx->host_ctrl->n_pairs = np32;  // for callers that size buffers from this render
       if (np > ctx->p_cap) {
         GS2D_HIP(ctx, hipStreamSynchronize(s));
         // grow and duplicate again (the first pass counted part of its pairs into plane 1)
