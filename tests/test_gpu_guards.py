@@ -173,3 +173,25 @@ def test_divergence_guard_returns_to_best_pose(gs, room, graph):
     # after the stop the loss is that of the best pose
     if stop + 1 < n_iters:
         np.testing.assert_array_equal(lh[stop + 1:], np.full(n_iters - stop - 1, lh_free[best_it]))
+
+
+def test_tracking_pair_headroom_from_its_start_render(gs):
+    """The first tracking call sizes its pair buffers from the render at the start pose:
+    at least 1.5 times that render's pairs plus 1,024.  Large surfels (many tiles each)
+    make the pairs exceed the default capacity of 4 per surfel, so that render grows the
+    buffers itself first (to 1.25 times its pairs)."""
+    room, pose = room_scene(20_000, seed=7, cam_seed=7)
+    params = room.params.astype(np.float32).copy()
+    params[9:11] *= 12.0
+    P = dev(params)
+    start = dev(pose.reshape(12))
+    r0 = gs.Rasterizer()
+    t = r0.render(P, ROOM_CAM, start)
+    trgb, tdep = t.rgb.clone(), t.depth.clone()
+    torch.cuda.synchronize()
+    n0 = r0.counts()["n_pairs"]
+    assert n0 > 4 * params.shape[1], n0
+    r = gs.Rasterizer()
+    r.track(P, ROOM_CAM, dev(pose.reshape(12)), trgb, tdep, n_iters=2)
+    c = r.counts()
+    assert c["pair_capacity"] >= n0 + n0 // 2 + 1024, (c, n0)
